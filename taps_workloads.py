@@ -1,0 +1,153 @@
+"""Seeded synthetic inputs for the TAPS slab solve.
+
+This module is shared by the CPU oracle, the tests and the benchmark.  It holds
+only sizes, physical constants, grid coordinates and seeded random draws: no
+step of the method's arithmetic (basis, quadrature, assembly, contraction,
+solve) lives here, so both implementations build their own problem from these
+plain numbers.
+
+Workloads (shaped after the paper's additive-manufacturing heat problems):
+
+* ``poisson2d``   -- 2D steady Poisson, -lap u = f on [0,1]^2, homogeneous
+  Dirichlet on every side, manufactured f = 2 pi^2 sin(pi x) sin(pi y)
+  + 2x(1-x) + 2y(1-y) (exact u = sin sin + x(1-x)y(1-y)).
+* ``heat_slab``   -- one space-time slab of the transient heat equation
+  rho c_p du/dt - k lap u = f on 1 mm x 1 mm x 0.2 mm with a moving Gaussian
+  volumetric source (paper Sec. 2.4, moving-source equation), homogeneous
+  initial condition and u = 0 on the bottom face z = 0, other faces adiabatic.
+* ``heat_slab_batch`` -- uneven batch of heat slabs with random grid sizes and
+  random (P, r, k, y0) draws.
+
+Units: lengths in mm, time in ms, power in W, so k is W/(mm K), rho*c_p is
+J/(mm^3 K) and the source amplitude is W/mm^3; the time derivative carries the
+factor 1e3 (ms -> s) inside ``rho_cp_per_ms``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Tuple
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Axis:
+    """One tensor dimension: a uniform grid plus the C-HiDeNN hyperparameters."""
+
+    name: str
+    lo: float
+    hi: float
+    n: int
+    s: int = 2          # patch size
+    a: float = 20.0     # dilation
+    p: int = 2          # reproducing order
+    n_gauss: int = 5    # Gauss points per element
+    fixed: Tuple[int, ...] = ()  # node indices held at zero
+
+    def nodes(self) -> np.ndarray:
+        return np.linspace(self.lo, self.hi, self.n)
+
+
+@dataclass(frozen=True)
+class Poisson2D:
+    axes: Tuple[Axis, Axis]
+    M: int
+    seed: int
+    kind: str = "poisson2d"
+
+
+@dataclass(frozen=True)
+class HeatSlab:
+    """Parameters of one space-time slab (x, y, z, t)."""
+
+    axes: Tuple[Axis, Axis, Axis, Axis]
+    M: int
+    seed: int
+    k: float = 0.020          # W/(mm K)   (20 W/(m K))
+    rho_cp: float = 4.0e-3    # J/(mm^3 K) (8000 kg/m^3 * 500 J/(kg K))
+    eta: float = 0.4
+    power: float = 200.0      # W
+    radius: float = 0.050     # mm
+    depth: float = 0.050      # mm, penetration depth d_v
+    speed: float = 1.0        # mm/ms (1 m/s)
+    x_start: float = 0.1      # mm
+    y0: float = 0.5           # mm
+    kind: str = "heat_slab"
+
+    @property
+    def rho_cp_per_ms(self) -> float:
+        """rho*c_p in J/(mm^3 K) times d/dt in 1/ms -> W/(mm^3 K) scale."""
+        return self.rho_cp * 1.0e3
+
+    @property
+    def height(self) -> float:
+        return self.axes[2].hi
+
+
+def poisson2d(n_el: int = 64, M: int = 10, seed: int = 0, s: int = 2,
+              a: float = 20.0, p: int = 2, n_gauss: int = 5) -> Poisson2D:
+    n = n_el + 1
+    ax = lambda nm: Axis(nm, 0.0, 1.0, n, s, a, p, n_gauss, fixed=(0, n - 1))
+    return Poisson2D((ax("x"), ax("y")), M, seed)
+
+
+def heat_slab(nx: int = 512, ny: int = 512, nz: int = 128, nt: int = 257,
+              M: int = 40, seed: int = 2, s: int = 2, a: float = 20.0,
+              p: int = 2, n_gauss: int = 5, duration_ms: float = 0.8,
+              **phys) -> HeatSlab:
+    """The single-slab transient heat workload (default: 512x512x128 x 257)."""
+    ax = [
+        Axis("x", 0.0, 1.0, nx, s, a, p, n_gauss),
+        Axis("y", 0.0, 1.0, ny, s, a, p, n_gauss),
+        Axis("z", 0.0, 0.2, nz, s, a, p, n_gauss, fixed=(0,)),
+        Axis("t", 0.0, duration_ms, nt, s, a, p, n_gauss, fixed=(0,)),
+    ]
+    return HeatSlab(tuple(ax), M, seed, **phys)
+
+
+def heat_slab_batch(batch: int = 64, n_lo: int = 64, n_hi: int = 1024,
+                    M: int = 30, seed: int = 3, nt_hi: int | None = None):
+    """Uneven batch of heat slabs: every grid size drawn from U{n_lo..n_hi};
+    power, radius, conductivity and track offset drawn per problem."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(batch):
+        nx, ny, nz, nt = (int(v) for v in rng.integers(n_lo, n_hi + 1, size=4))
+        if nt_hi is not None:
+            nt = min(nt, nt_hi)
+        P = float(rng.uniform(100.0, 300.0))
+        r = float(rng.uniform(0.030, 0.080))
+        k = float(rng.uniform(0.010, 0.030))
+        y0 = float(rng.uniform(0.3, 0.7))
+        out.append(heat_slab(nx, ny, nz, nt, M=M, seed=seed * 100003 + b,
+                             power=P, radius=r, k=k, y0=y0))
+    return out
+
+
+def initial_factors(axes, M: int, seed: int):
+    """Random initial mode factors U_d ~ N(0,1) (n_d x M, float64, row-major),
+    one PCG64 stream per problem, dims drawn in order; rows of fixed nodes are 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Us = []
+    for ax in axes:
+        U = rng.standard_normal((ax.n, M))
+        if ax.fixed:
+            U[list(ax.fixed), :] = 0.0
+        Us.append(np.ascontiguousarray(U))
+    return Us
+
+
+def output_points(ax: Axis, n_pts: int) -> np.ndarray:
+    """Uniform evaluation points spanning an axis (end points included)."""
+    return np.linspace(ax.lo, ax.hi, n_pts)
+
+
+def shrink(case, factor: int):
+    """Same workload on a grid coarsened by ``factor`` along every axis
+    (fixed nodes remapped), for oracle-sized parity runs."""
+    axes = []
+    for ax in case.axes:
+        n = max(2 * ax.s + 2, (ax.n - 1) // factor + 1)
+        fixed = tuple(sorted({0 if f == 0 else n - 1 for f in ax.fixed}))
+        axes.append(replace(ax, n=n, fixed=fixed))
+    return replace(case, axes=tuple(axes))
