@@ -1,0 +1,255 @@
+/*
+ * taps.h -- C ABI of the TAPS slab-solve hot path on MI355X (gfx950).
+ *
+ * TAPS (Guo et al., tensor-decomposition-based a priori surrogate) solves the
+ * Galerkin form of a space-parameter-time PDE in CP-decomposed form
+ * u(x) = sum_m prod_d U_d[:, m]  (Sec. 2.2-2.3), one dimension at a time
+ * (Sec. 2.6, Algorithm 1).  This library holds every data-parallel step of
+ * that loop as HIP kernels:
+ *
+ *   taps_gauss_points / taps_shape1d     1D C-HiDeNN basis at points      (Sec. 2.1)
+ *   taps_source1d                        separable source factors           (Sec. 2.4)
+ *   taps_assemble1d                      1D quadrature matrices and loads  (Sec. 2.5)
+ *   taps_contract                        Grams, Hadamard couplings, force  (Sec. 2.5)
+ *   taps_solve_dim                       block-banded (n_d M) dim solve    (Sec. 2.6)
+ *   taps_residual / taps_balance         projected residual, mode balance  (Sec. 2.5-2.6)
+ *   taps_sweep / taps_als                Algorithm 1 driver                (Sec. 2.6)
+ *   taps_interp1d / taps_reconstruct     TD interpolation on grids         (Sec. 2.3)
+ *
+ * Conventions (every call):
+ *   - Pointers named d_* are device memory owned by the caller; everything else
+ *     is host memory read during the call only.
+ *   - Dense matrices are row-major.  Factors U_d are n_d x M, node-major
+ *     (U[i*M + m]).  1D banded matrices are stored as n x (2w+1) with
+ *     w = 2s+1 the half-bandwidth: band[i*(2w+1) + (j - i + w)] = A[i][j]
+ *     (test index i first, trial index j second).
+ *   - Work is enqueued on `stream` and is asynchronous to the host unless the
+ *     description says otherwise.  Arguments are validated on the host before
+ *     anything is enqueued: a bad argument returns TAPS_ERR_INVALID or
+ *     TAPS_ERR_UNSUPPORTED and enqueues nothing; taps_last_error() tells why.
+ *   - A handle owns a device workspace that grows on demand (hipMalloc after a
+ *     stream synchronisation).  Call taps_reserve() up front to keep later calls
+ *     allocation-free.  A handle is not thread-safe; use one per host thread.
+ *   - Numerical breakdown (zero or NaN pivot) never aborts: it is reported in a
+ *     device info word (LAPACK style) and the outputs are then unspecified.
+ *   - Everything is FP64 except the precision argument of taps_reconstruct.
+ */
+#ifndef TAPS_H
+#define TAPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TAPS_OK = 0,
+  TAPS_ERR_INVALID = -1,      /* bad argument (null pointer, size, range) */
+  TAPS_ERR_UNSUPPORTED = -2,  /* valid but outside what the kernels handle */
+  TAPS_ERR_ALLOC = -3,        /* device allocation failed */
+  TAPS_ERR_HIP = -4           /* a HIP runtime call or launch failed */
+} taps_status;
+
+typedef struct taps_handle* taps_handle_t;
+
+#define TAPS_MAX_DIMS 8
+#define TAPS_MAX_TERMS 16
+#define TAPS_MAX_KINDS 4
+#define TAPS_MAX_M 64
+#define TAPS_MAX_S 3
+#define TAPS_MAX_GAUSS 8
+
+/* Handle with an empty workspace.  Returns TAPS_ERR_INVALID for a null out-pointer. */
+taps_status taps_create(taps_handle_t* out);
+/* Frees the workspace (after synchronising the device).  Null is accepted. */
+taps_status taps_destroy(taps_handle_t h);
+/* Message of the last failed call on this handle ("" if none).  Owned by the handle. */
+const char* taps_last_error(taps_handle_t h);
+/* Grow the workspace to at least `bytes` now (synchronises the device). */
+taps_status taps_reserve(taps_handle_t h, size_t bytes);
+/* Bytes the workspace holds. */
+size_t taps_workspace_bytes(taps_handle_t h);
+
+/* ------------------------------------------------------------------------ */
+/* 1D C-HiDeNN basis (Sec. 2.1, the C-HiDeNN interpolation equation).
+ * Readings (the paper defers the patch function to its references):
+ *   patch of node i = nodes max(0,i-s)..min(n-1,i+s); W^i_j = cardinal
+ *   functions of radial-basis interpolation with degree-p polynomial
+ *   reproduction on that patch, kernel = cubic B-spline of |x-x_j|/(a h_i),
+ *   h_i = mean node spacing of the patch (for s = 0: of the adjacent elements),
+ *   polynomial basis in (x-x_i)/h_i.  Ntilde_k = sum over the element's two
+ *   nodes of (linear hat) * W.  A point on an interior node belongs to the
+ *   element on its right, the last node to the last element.             */
+typedef struct {
+  int32_t n_nodes;     /* >= max(2, 2s+2) */
+  const double* d_x;   /* device, n_nodes strictly increasing coordinates */
+  int32_t s;           /* patch size, 0..TAPS_MAX_S */
+  double a;            /* dilation, > 0 */
+  int32_t p;           /* reproducing order, 0 <= p <= s (p = 0 allowed for s = 0) */
+  int32_t n_gauss;     /* Gauss points per element, 1..TAPS_MAX_GAUSS */
+} taps_basis1d_t;
+
+/* Gauss-Legendre points and weights (Jacobian included) of every element,
+ * element-major: point g of element e at e*n_gauss+g.  d_xg, d_wg hold
+ * (n_nodes-1)*n_gauss doubles.  (Sec. 2.1: Gaussian integration.) */
+taps_status taps_gauss_points(taps_handle_t h, const taps_basis1d_t* b,
+                              double* d_xg, double* d_wg, hipStream_t stream);
+
+/* Shape values and derivatives at n_pts points (Sec. 2.5, the 1D shape
+ * functions Ntilde and their derivatives Btilde = dNtilde/dx).  Per point p:
+ * d_first[p] = first node of the window of L = 2s+2 nodes
+ * (clamped to [0, n-L]), d_N[p*L + l] = Ntilde_{first+l}(x_p), same for d_dN
+ * (nullable).  Points outside [x_0, x_{n-1}] are clamped onto the end elements
+ * (extrapolation). */
+taps_status taps_shape1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_pts,
+                         const double* d_pts, double* d_N, double* d_dN,
+                         int32_t* d_first, hipStream_t stream);
+
+/* Separable source factors evaluated at points (the forcing of Sec. 2.4 in
+ * separated form).  d_out[c*n_pts + p] = f_c(x_p) for c < n_cols.
+ *   TAPS_SRC_GAUSS:    params[0]*exp(-2 (x - d_centers[c])^2 / params[1]^2)
+ *                      (moving Gaussian beam profile, radius params[1])
+ *   TAPS_SRC_TOPLAYER: 1 if params[0] - x <= params[1] else 0 (top layer of
+ *                      depth params[1] below the surface x = params[0])
+ *   TAPS_SRC_POLY:     sum_q params[q] x^q, q < n_params (n_cols must be 1)
+ *   TAPS_SRC_SIN:      params[0]*sin(params[1]*x)      (n_cols must be 1)
+ *   TAPS_SRC_NODAL:    Ntilde_c(x) of `basis` (time interpolation of a
+ *                      non-separable source; n_cols = basis->n_nodes)
+ * d_centers is used by GAUSS only; basis by NODAL only. */
+typedef enum { TAPS_SRC_GAUSS = 0, TAPS_SRC_TOPLAYER = 1, TAPS_SRC_POLY = 2,
+               TAPS_SRC_SIN = 3, TAPS_SRC_NODAL = 4 } taps_source_kind;
+taps_status taps_source1d(taps_handle_t h, taps_source_kind kind, int32_t n_pts,
+                          const double* d_pts, int32_t n_cols, int32_t n_params,
+                          const double* params, const double* d_centers,
+                          const taps_basis1d_t* basis, double* d_out, hipStream_t stream);
+
+/* 1D matrices and load vectors by Gauss quadrature (Sec. 2.5, the 1D
+ * integrals of the spatial, parametric and temporal terms):
+ *   TAPS_MASS   int Ntilde_i Ntilde_j        TAPS_STIFF int Btilde_i Btilde_j
+ *   TAPS_DDT    int Ntilde_i Btilde_j        TAPS_WMASS int c(x) Ntilde_i Ntilde_j
+ *   TAPS_BMASS  e_b e_b^T (boundary point mass of node bnode[k])
+ * d_band: n_kinds bands of n_nodes*(4s+3) doubles, in the order of kinds[].
+ * d_coef_g: c at the Gauss points ((n_nodes-1)*n_gauss), WMASS only.
+ * Loads: d_F[i*n_loads + r] = int Ntilde_i f_r with f_r given at the Gauss
+ * points as d_f_g[r*n_gpts + g] (n_gpts = (n_nodes-1)*n_gauss).
+ * n_loads = 0 skips the loads. */
+typedef enum { TAPS_MASS = 0, TAPS_STIFF = 1, TAPS_DDT = 2, TAPS_WMASS = 3,
+               TAPS_BMASS = 4 } taps_kind;
+taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_kinds,
+                            const int32_t* kinds, const double* d_coef_g,
+                            const int32_t* bnode, double* d_band, int32_t n_loads,
+                            const double* d_f_g, double* d_F, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Separated problem (Sec. 2.5): operator sum_tau gamma_tau (x)_d A^{tau}_d
+ * with A^{tau}_d = band number term_kind[tau][d] of dim d, and load
+ * sum_r (x)_d F_d[:, col_d(r)].  Host struct, read during each call; the
+ * device arrays it points to must stay valid while work using them runs.  */
+typedef struct {
+  int32_t D;                                  /* dims, 1..TAPS_MAX_DIMS */
+  int32_t M;                                  /* modes, 1..TAPS_MAX_M */
+  int32_t T;                                  /* operator terms, 1..TAPS_MAX_TERMS */
+  int32_t R;                                  /* load terms, >= 1 */
+  int32_t n[TAPS_MAX_DIMS];                   /* nodes per dim */
+  int32_t s[TAPS_MAX_DIMS];                   /* patch size per dim (band half-width 2s+1) */
+  int32_t n_kinds[TAPS_MAX_DIMS];             /* bands per dim, 1..TAPS_MAX_KINDS */
+  int32_t term_kind[TAPS_MAX_TERMS][TAPS_MAX_DIMS];
+  double gamma[TAPS_MAX_TERMS];
+  const double* d_band[TAPS_MAX_DIMS];        /* n_kinds[d] * n[d] * (4s+3) */
+  int32_t R_cols[TAPS_MAX_DIMS];              /* columns of F_d */
+  const double* d_F[TAPS_MAX_DIMS];           /* n[d] * R_cols[d] */
+  /* load-term -> column map of dim d (R entries) and its inverse grouped by
+     column (CSR: d_load_ptr R_cols+1 entries, d_load_idx R entries).  All three
+     NULL means the identity map (R_cols[d] must equal R). */
+  const int32_t* d_load_col[TAPS_MAX_DIMS];
+  const int32_t* d_load_ptr[TAPS_MAX_DIMS];
+  const int32_t* d_load_idx[TAPS_MAX_DIMS];
+  const uint8_t* d_fixed[TAPS_MAX_DIMS];      /* n[d] bytes, 1 = node held at 0; NULL = none */
+} taps_problem_t;
+
+/* Couplings and force of dim d (Sec. 2.5: the coefficient matrices of the
+ * other dimensions multiplied entrywise, then the per-dim system).
+ *   Gram   G^k_e[m][n] = U_e[:,m]^T A^k_e U_e[:,n]   (test mode m first)
+ *   Lgram  L_e[c][m]   = F_e[:,c] . U_e[:,m]
+ *   d_C[k*M*M + m*M + n] = sum_{tau: term_kind[tau][d] = k} gamma_tau
+ *                           prod_{e != d} G^{term_kind[tau][e]}_e[m][n]
+ *   d_Q[i*M + m] = sum_r F_d[i][col_d(r)] prod_{e != d} L_e[col_e(r)][m]
+ * (all rows, fixed ones included).  Grams of dims whose bit is set in
+ * stale_mask are recomputed from d_U and cached in the handle; the others are
+ * taken from the cache, which belongs to the last problem contracted on the
+ * handle (pass all bits after changing the problem). */
+taps_status taps_contract(taps_handle_t h, const taps_problem_t* prob, int32_t d,
+                          uint32_t stale_mask, const double* const* d_U,
+                          double* d_C, double* d_Q, hipStream_t stream);
+
+/* Solve the dim-d system sum_k A^k_d X (C^k)^T = Q (Sec. 2.6, the linear
+ * system in the subspace iteration; node-major (n_d M) block-banded matrix
+ * with M x M blocks sum_k A^k_d[i][j] C^k and block half-bandwidth 2s+1).
+ * Rows of fixed nodes are X = 0.  Block LU without pivoting (valid when the
+ * symmetric part of the system is positive definite, which holds for the
+ * heat and Poisson operators with at least one Dirichlet or initial-condition
+ * row), pivot blocks inverted by Gauss-Jordan.  *d_info = 0 on success, or
+ * 1 + the block row of the first zero / non-finite pivot. */
+taps_status taps_solve_dim(taps_handle_t h, const taps_problem_t* prob, int32_t d,
+                           const double* d_C, const double* d_Q, double* d_X,
+                           int32_t* d_info, hipStream_t stream);
+
+/* Projected Galerkin residual of every dim (the block-diagonal system of
+ * Sec. 2.5; zero at a fixed point of Algorithm 1):
+ *   R_d = sum_k A^k_d U_d (C^k_d)^T - Q_d on free rows, Grams from d_U.
+ * d_out (D+2 doubles): [d] = ||R_d||_F^2, [D] = sum_d ||Q_d||_F^2 (free rows),
+ * [D+1] = rho = sqrt(sum_d ||R_d||^2 / sum_d ||Q_d||^2).  Refreshes the cache. */
+taps_status taps_residual(taps_handle_t h, const taps_problem_t* prob,
+                          const double* const* d_U, double* d_out, hipStream_t stream);
+
+/* Equalise the per-mode column norms across dims in place (the field is
+ * unchanged): U_e[:,m] *= g_m / ||U_e[:,m]||, g_m = geometric mean over e;
+ * skipped for a mode with any norm below 1e-300. */
+taps_status taps_balance(taps_handle_t h, const taps_problem_t* prob,
+                         double* const* d_U, hipStream_t stream);
+
+/* One sweep of Algorithm 1 (Sec. 2.6): for d = 0..D-1 contract, solve into
+ * d_U[d]; then balance.  d_info: one int32 (first failing block row + 1,
+ * from the first dim that failed; 0 = ok). */
+taps_status taps_sweep(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
+                       int32_t* d_info, hipStream_t stream);
+
+/* Algorithm 1 to tolerance: sweeps until rho <= tol or iter_max sweeps.
+ * Synchronises the stream once per sweep to read rho.  Host outputs:
+ * *sweeps, *rho (last), history[k] = rho after sweep k (nullable, iter_max
+ * entries).  Returns TAPS_OK even if not converged (compare *rho with tol);
+ * a breakdown in a dim solve ends the loop with *rho = NaN. */
+taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
+                     double tol, int32_t iter_max, int32_t* sweeps, double* rho,
+                     double* history, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* TD interpolation (Sec. 2.3): Phi = Ntilde(pts) U with the shape window of
+ * taps_shape1d (L values per point starting at d_first[p]):
+ * d_Phi[p*M + m] = sum_l d_N[p*L + l] * d_U[(d_first[p]+l)*M + m]. */
+taps_status taps_interp1d(taps_handle_t h, int32_t n_pts, int32_t L, const double* d_N,
+                          const int32_t* d_first, int32_t n_nodes, int32_t M,
+                          const double* d_U, double* d_Phi, hipStream_t stream);
+
+/* Rank-M field on a 3D grid (Sec. 2.3, TD interpolation):
+ *   u[i][j][k] = sum_m w_m Phi_0[i][m] Phi_1[j][m] Phi_2[k][m]
+ * (w = d_mode_w or all ones; e.g. Phi_t(t*) folds the time factor in).
+ * Precision: TAPS_FP64 (plain FP64), TAPS_FP32 (FP32 factors, FP32 MFMA
+ * accumulate), TAPS_BF16 (BF16 factors, FP32 MFMA accumulate).
+ * TAPS_STORE writes the field: d_out = n0*n1*n2 values (double for FP64,
+ * float otherwise), plane-major: u[i][j][k] at d_out[(k*n0 + i)*n1 + j].
+ * TAPS_REDUCE writes per z-plane k (n2 entries of 4 doubles):
+ *   {max_ij u, sum_ij u^2, count_ij(u > thr), 0}. */
+typedef enum { TAPS_FP64 = 0, TAPS_FP32 = 1, TAPS_BF16 = 2 } taps_prec;
+typedef enum { TAPS_STORE = 0, TAPS_REDUCE = 1 } taps_recon_mode;
+taps_status taps_reconstruct(taps_handle_t h, const int32_t* n_pts, const double* const* d_Phi,
+                             int32_t M, const double* d_mode_w, taps_prec prec,
+                             taps_recon_mode mode, void* d_out, double thr, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TAPS_H */

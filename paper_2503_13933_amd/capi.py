@@ -1,0 +1,214 @@
+"""ctypes binding of libtaps.so (the C ABI declared in include/taps.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Torch
+tensors provide device memory and the current stream.  Functions keep the C
+names; they raise TapsError on a non-OK status with the library's message.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtaps.so")
+
+MAX_DIMS, MAX_TERMS, MAX_KINDS, MAX_M, MAX_S, MAX_GAUSS = 8, 16, 4, 64, 3, 8
+
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = 0, -1, -2, -3, -4
+MASS, STIFF, DDT, WMASS, BMASS = 0, 1, 2, 3, 4
+SRC_GAUSS, SRC_TOPLAYER, SRC_POLY, SRC_SIN, SRC_NODAL = 0, 1, 2, 3, 4
+FP64, FP32, BF16 = 0, 1, 2
+STORE, REDUCE = 0, 1
+
+FUNCTIONS = (
+    "taps_create", "taps_destroy", "taps_last_error", "taps_reserve", "taps_workspace_bytes",
+    "taps_gauss_points", "taps_shape1d", "taps_source1d", "taps_assemble1d", "taps_contract",
+    "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
+    "taps_reconstruct",
+)
+
+
+class TapsError(RuntimeError):
+    pass
+
+
+class Basis1D(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("d_x", C.c_void_p), ("s", C.c_int32), ("a", C.c_double),
+                ("p", C.c_int32), ("n_gauss", C.c_int32)]
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("D", C.c_int32), ("M", C.c_int32), ("T", C.c_int32), ("R", C.c_int32),
+        ("n", C.c_int32 * MAX_DIMS), ("s", C.c_int32 * MAX_DIMS), ("n_kinds", C.c_int32 * MAX_DIMS),
+        ("term_kind", (C.c_int32 * MAX_DIMS) * MAX_TERMS), ("gamma", C.c_double * MAX_TERMS),
+        ("d_band", C.c_void_p * MAX_DIMS), ("R_cols", C.c_int32 * MAX_DIMS),
+        ("d_F", C.c_void_p * MAX_DIMS), ("d_load_col", C.c_void_p * MAX_DIMS),
+        ("d_load_ptr", C.c_void_p * MAX_DIMS), ("d_load_idx", C.c_void_p * MAX_DIMS),
+        ("d_fixed", C.c_void_p * MAX_DIMS),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TapsError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, dbl, sz = C.c_void_p, C.c_int32, C.c_uint32, C.c_double, C.c_size_t
+        P = C.POINTER
+        sig = {
+            "taps_create": (i32, [P(vp)]),
+            "taps_destroy": (i32, [vp]),
+            "taps_last_error": (C.c_char_p, [vp]),
+            "taps_reserve": (i32, [vp, sz]),
+            "taps_workspace_bytes": (sz, [vp]),
+            "taps_gauss_points": (i32, [vp, P(Basis1D), vp, vp, vp]),
+            "taps_shape1d": (i32, [vp, P(Basis1D), i32, vp, vp, vp, vp, vp]),
+            "taps_source1d": (i32, [vp, i32, i32, vp, i32, i32, P(dbl), vp, P(Basis1D), vp, vp]),
+            "taps_assemble1d": (i32, [vp, P(Basis1D), i32, P(i32), vp, P(i32), vp, i32, vp, vp, vp]),
+            "taps_contract": (i32, [vp, P(Problem), i32, u32, P(vp), vp, vp, vp]),
+            "taps_solve_dim": (i32, [vp, P(Problem), i32, vp, vp, vp, vp, vp]),
+            "taps_residual": (i32, [vp, P(Problem), P(vp), vp, vp]),
+            "taps_balance": (i32, [vp, P(Problem), P(vp), vp]),
+            "taps_sweep": (i32, [vp, P(Problem), P(vp), vp, vp]),
+            "taps_als": (i32, [vp, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), P(dbl), vp]),
+            "taps_interp1d": (i32, [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]),
+            "taps_reconstruct": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- helpers
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor, None for None."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise TapsError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+class Handle:
+    """Owning wrapper of a taps_handle_t."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        st = lib().taps_create(C.byref(h))
+        if st != OK:
+            raise TapsError(f"taps_create failed ({st})")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().taps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st, what):
+        if st != OK:
+            msg = lib().taps_last_error(self.h).decode()
+            raise TapsError(f"{what} -> {st}: {msg}")
+
+
+def _ptr_array(tensors):
+    arr = (C.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = _ptr(t)
+    return arr
+
+
+# ---------------------------------------------------------------- C names
+
+
+def taps_gauss_points(h: Handle, basis: Basis1D, xg, wg, stream=None):
+    h.check(lib().taps_gauss_points(h.h, C.byref(basis), _ptr(xg), _ptr(wg), _stream(stream)), "taps_gauss_points")
+
+
+def taps_shape1d(h: Handle, basis: Basis1D, pts, N, dN, first, stream=None):
+    h.check(lib().taps_shape1d(h.h, C.byref(basis), pts.numel(), _ptr(pts), _ptr(N), _ptr(dN), _ptr(first),
+                               _stream(stream)), "taps_shape1d")
+
+
+def taps_source1d(h: Handle, kind: int, pts, n_cols: int, params, out, centers=None, basis=None, stream=None):
+    prm = (C.c_double * max(1, len(params)))(*params)
+    bref = C.byref(basis) if basis is not None else None
+    h.check(lib().taps_source1d(h.h, kind, pts.numel(), _ptr(pts), n_cols, len(params), prm, _ptr(centers), bref,
+                                _ptr(out), _stream(stream)), "taps_source1d")
+
+
+def taps_assemble1d(h: Handle, basis: Basis1D, kinds, band, coef_g=None, bnode=None, f_g=None, F=None,
+                    n_loads: int = 0, stream=None):
+    k = (C.c_int32 * max(1, len(kinds)))(*kinds)
+    bn = (C.c_int32 * max(1, len(kinds)))(*(bnode or [-1] * len(kinds)))
+    h.check(lib().taps_assemble1d(h.h, C.byref(basis), len(kinds), k, _ptr(coef_g), bn, _ptr(band), n_loads,
+                                  _ptr(f_g), _ptr(F), _stream(stream)), "taps_assemble1d")
+
+
+def taps_contract(h: Handle, prob: Problem, d: int, stale_mask: int, U, Cout, Q, stream=None):
+    h.check(lib().taps_contract(h.h, C.byref(prob), d, stale_mask & 0xFFFFFFFF, _ptr_array(U), _ptr(Cout), _ptr(Q),
+                                _stream(stream)), "taps_contract")
+
+
+def taps_solve_dim(h: Handle, prob: Problem, d: int, Cin, Q, X, info, stream=None):
+    h.check(lib().taps_solve_dim(h.h, C.byref(prob), d, _ptr(Cin), _ptr(Q), _ptr(X), _ptr(info), _stream(stream)),
+            "taps_solve_dim")
+
+
+def taps_residual(h: Handle, prob: Problem, U, out, stream=None):
+    h.check(lib().taps_residual(h.h, C.byref(prob), _ptr_array(U), _ptr(out), _stream(stream)), "taps_residual")
+
+
+def taps_balance(h: Handle, prob: Problem, U, stream=None):
+    h.check(lib().taps_balance(h.h, C.byref(prob), _ptr_array(U), _stream(stream)), "taps_balance")
+
+
+def taps_sweep(h: Handle, prob: Problem, U, info=None, stream=None):
+    h.check(lib().taps_sweep(h.h, C.byref(prob), _ptr_array(U), _ptr(info), _stream(stream)), "taps_sweep")
+
+
+def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, stream=None):
+    """Returns (sweeps, rho, history list)."""
+    sweeps = C.c_int32()
+    rho = C.c_double()
+    hist = (C.c_double * iter_max)()
+    h.check(lib().taps_als(h.h, C.byref(prob), _ptr_array(U), tol, iter_max, C.byref(sweeps), C.byref(rho), hist,
+                           _stream(stream)), "taps_als")
+    return sweeps.value, rho.value, list(hist[: sweeps.value])
+
+
+def taps_interp1d(h: Handle, N, first, n_nodes: int, U, Phi, stream=None):
+    npts, L = N.shape
+    h.check(lib().taps_interp1d(h.h, npts, L, _ptr(N), _ptr(first), n_nodes, U.shape[1], _ptr(U), _ptr(Phi),
+                                _stream(stream)), "taps_interp1d")
+
+
+def taps_reconstruct(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int = STORE, mode_w=None,
+                     thr: float = 0.0, stream=None):
+    n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis])
+    h.check(lib().taps_reconstruct(h.h, n, _ptr_array(Phis), M, _ptr(mode_w), prec, mode, _ptr(out), thr,
+                                   _stream(stream)), "taps_reconstruct")

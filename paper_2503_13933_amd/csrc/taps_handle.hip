@@ -1,0 +1,137 @@
+// Handle lifetime, workspace, argument validation and the host Gauss rule.
+#include "taps_internal.hpp"
+
+#include <new>
+
+namespace taps {
+
+void gauss_legendre(int n, double* xi, double* w) {
+  // Roots of the Legendre polynomial P_n by Newton iteration from the
+  // Chebyshev-like initial guess cos(pi (k + 3/4) / (n + 1/2)); weights
+  // 2 / ((1 - x^2) P_n'(x)^2).  Symmetric pairs are filled from one root.
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < (n + 1) / 2; ++k) {
+    double x = std::cos(pi * (k + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? x : p1;
+      double pm = (n == 1) ? 1.0 : p0;
+      dp = n * (x * pn - pm) / (x * x - 1.0);
+      double dx = pn / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) {
+        // one more evaluation of the derivative at the converged root
+        p0 = 1.0;
+        p1 = x;
+        for (int j = 2; j <= n; ++j) {
+          double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+          p0 = p1;
+          p1 = p2;
+        }
+        pn = (n == 1) ? x : p1;
+        pm = (n == 1) ? 1.0 : p0;
+        dp = n * (x * pn - pm) / (x * x - 1.0);
+        break;
+      }
+    }
+    double wk = 2.0 / ((1.0 - x * x) * dp * dp);
+    // ascending order: the negative root first
+    xi[k] = -x;
+    w[k] = wk;
+    xi[n - 1 - k] = x;
+    w[n - 1 - k] = wk;
+  }
+  if (n % 2 == 1) xi[n / 2] = 0.0;
+}
+
+taps_status check_basis(taps_handle* h, const taps_basis1d_t* b) {
+  if (!b) return fail(h, TAPS_ERR_INVALID, "basis is null");
+  if (!b->d_x) return fail(h, TAPS_ERR_INVALID, "basis node pointer is null");
+  if (b->s < 0 || b->s > TAPS_MAX_S)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "patch size s=%d outside 0..%d", b->s, TAPS_MAX_S);
+  if (b->p < 0 || b->p > b->s)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "reproducing order p=%d needs 0 <= p <= s=%d", b->p, b->s);
+  if (!(b->a > 0.0)) return fail(h, TAPS_ERR_INVALID, "dilation a must be positive");
+  if (b->n_nodes < 2 || b->n_nodes < 2 * b->s + 2)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "n_nodes=%d below max(2, 2s+2)", b->n_nodes);
+  if (b->n_gauss < 1 || b->n_gauss > TAPS_MAX_GAUSS)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "n_gauss=%d outside 1..%d", b->n_gauss, TAPS_MAX_GAUSS);
+  return TAPS_OK;
+}
+
+taps_status check_problem(taps_handle* h, const taps_problem_t* p) {
+  if (!p) return fail(h, TAPS_ERR_INVALID, "problem is null");
+  if (p->D < 1 || p->D > TAPS_MAX_DIMS) return fail(h, TAPS_ERR_UNSUPPORTED, "D=%d", p->D);
+  if (p->M < 1 || p->M > TAPS_MAX_M) return fail(h, TAPS_ERR_UNSUPPORTED, "M=%d", p->M);
+  if (p->T < 1 || p->T > TAPS_MAX_TERMS) return fail(h, TAPS_ERR_UNSUPPORTED, "T=%d", p->T);
+  if (p->R < 1) return fail(h, TAPS_ERR_INVALID, "R=%d", p->R);
+  for (int d = 0; d < p->D; ++d) {
+    if (p->s[d] < 0 || p->s[d] > TAPS_MAX_S)
+      return fail(h, TAPS_ERR_UNSUPPORTED, "dim %d: s=%d", d, p->s[d]);
+    if (p->n[d] < 2 * p->s[d] + 2 || p->n[d] < 2)
+      return fail(h, TAPS_ERR_UNSUPPORTED, "dim %d: n=%d below 2s+2", d, p->n[d]);
+    if (p->n_kinds[d] < 1 || p->n_kinds[d] > TAPS_MAX_KINDS)
+      return fail(h, TAPS_ERR_UNSUPPORTED, "dim %d: n_kinds=%d", d, p->n_kinds[d]);
+    if (!p->d_band[d]) return fail(h, TAPS_ERR_INVALID, "dim %d: band pointer is null", d);
+    if (p->R_cols[d] < 1 || !p->d_F[d]) return fail(h, TAPS_ERR_INVALID, "dim %d: no load columns", d);
+    bool any = p->d_load_col[d] || p->d_load_ptr[d] || p->d_load_idx[d];
+    bool all = p->d_load_col[d] && p->d_load_ptr[d] && p->d_load_idx[d];
+    if (any && !all) return fail(h, TAPS_ERR_INVALID, "dim %d: load map needs col, ptr and idx", d);
+    if (!any && p->R_cols[d] != p->R)
+      return fail(h, TAPS_ERR_INVALID, "dim %d: identity load map needs R_cols == R", d);
+  }
+  for (int t = 0; t < p->T; ++t)
+    for (int d = 0; d < p->D; ++d)
+      if (p->term_kind[t][d] < 0 || p->term_kind[t][d] >= p->n_kinds[d])
+        return fail(h, TAPS_ERR_INVALID, "term %d dim %d: kind %d out of range", t, d, p->term_kind[t][d]);
+  return TAPS_OK;
+}
+
+}  // namespace taps
+
+extern "C" {
+
+taps_status taps_create(taps_handle_t* out) {
+  if (!out) return TAPS_ERR_INVALID;
+  *out = nullptr;
+  taps_handle* h = new (std::nothrow) taps_handle();
+  if (!h) return TAPS_ERR_ALLOC;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return TAPS_ERR_HIP;
+  }
+  if (hipMalloc(reinterpret_cast<void**>(&h->d_small), 1024) != hipSuccess) {
+    delete h;
+    return TAPS_ERR_ALLOC;
+  }
+  *out = h;
+  return TAPS_OK;
+}
+
+taps_status taps_destroy(taps_handle_t h) {
+  if (!h) return TAPS_OK;
+  (void)hipDeviceSynchronize();
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->cache) (void)hipFree(h->cache);
+  if (h->side) (void)hipFree(h->side);
+  if (h->d_small) (void)hipFree(h->d_small);
+  delete h;
+  return TAPS_OK;
+}
+
+const char* taps_last_error(taps_handle_t h) { return h ? h->err.c_str() : "null handle"; }
+
+taps_status taps_reserve(taps_handle_t h, size_t bytes) {
+  if (!h) return TAPS_ERR_INVALID;
+  return taps::need_ws(h, bytes, nullptr);
+}
+
+size_t taps_workspace_bytes(taps_handle_t h) { return h ? h->ws_bytes + h->cache_bytes : 0; }
+
+}  // extern "C"

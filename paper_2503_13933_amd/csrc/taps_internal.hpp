@@ -1,0 +1,128 @@
+// Internal plumbing of the TAPS HIP library: handle, workspace, argument
+// checks, launch helpers.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/taps.h"
+
+struct taps_handle {
+  // scratch: reused by every call (partial sums, solve factors, C/Q buffers)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // Gram cache: per dim e, n_kinds[e]*M*M Grams then R_cols[e]*M load Grams
+  double* cache = nullptr;
+  size_t cache_bytes = 0;
+  uint32_t cache_valid = 0;  // bit e: cache of dim e holds Grams of the current factors
+  // shape signature of the problem the cache belongs to
+  int32_t sig_D = -1, sig_M = -1;
+  int32_t sig_n[TAPS_MAX_DIMS] = {0}, sig_k[TAPS_MAX_DIMS] = {0}, sig_r[TAPS_MAX_DIMS] = {0};
+  // driver region: C and Q of the dim being solved, residual partials, info words
+  void* side = nullptr;
+  size_t side_bytes = 0;
+  // small fixed buffer: [0, 64) doubles residual output, then info words
+  double* d_small = nullptr;
+  std::string err;
+  int device = 0;
+};
+
+namespace taps {
+
+inline taps_status fail(taps_handle* h, taps_status st, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    h->err = buf;
+  }
+  return st;
+}
+
+#define TAPS_HIP(h, call)                                                               \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return taps::fail((h), TAPS_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TAPS_LAUNCHED(h, what)                                                          \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess)                                                              \
+      return taps::fail((h), TAPS_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TAPS_TRY(x)                    \
+  do {                                 \
+    taps_status st_ = (x);             \
+    if (st_ != TAPS_OK) return st_;    \
+  } while (0)
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Grow a device buffer (synchronising `stream` first, since old contents may be in use).
+inline taps_status grow(taps_handle* h, void** buf, size_t* have, size_t need, hipStream_t stream) {
+  if (need <= *have) return TAPS_OK;
+  TAPS_HIP(h, hipStreamSynchronize(stream));
+  if (*buf) TAPS_HIP(h, hipFree(*buf));
+  *buf = nullptr;
+  *have = 0;
+  size_t bytes = align256(need + need / 4);
+  if (hipMalloc(buf, bytes) != hipSuccess) {
+    *buf = nullptr;
+    (void)hipGetLastError();
+    return fail(h, TAPS_ERR_ALLOC, "hipMalloc of %zu bytes failed", bytes);
+  }
+  *have = bytes;
+  return TAPS_OK;
+}
+
+inline taps_status need_ws(taps_handle* h, size_t bytes, hipStream_t stream) {
+  return grow(h, &h->ws, &h->ws_bytes, bytes, stream);
+}
+
+// Bump allocator over the workspace (offsets only; 256-byte aligned).
+struct Bump {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  }
+};
+
+inline int band_width(int s) { return 4 * s + 3; }
+inline int half_band(int s) { return 2 * s + 1; }
+
+inline int cdiv(long a, long b) { return static_cast<int>((a + b - 1) / b); }
+
+// ---- shared argument checks ------------------------------------------------
+taps_status check_basis(taps_handle* h, const taps_basis1d_t* b);
+taps_status check_problem(taps_handle* h, const taps_problem_t* p);
+
+// ---- cross-file entry points (implemented in the .hip files) --------------
+// Gram cache refresh for the dims in `mask`, given factors d_U.
+taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask,
+                          const double* const* d_U, hipStream_t stream);
+// Offsets of dim e's Grams / load Grams inside h->cache.
+size_t cache_gram_off(const taps_problem_t* p, int e);
+size_t cache_lgram_off(const taps_problem_t* p, int e);
+size_t cache_total(const taps_problem_t* p);
+// Couplings + force of dim d from the cache (cache must be valid for e != d).
+taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, double* d_C,
+                             double* d_Q, hipStream_t stream);
+// Ensure the cache is sized and signed for problem p.
+taps_status prepare_cache(taps_handle* h, const taps_problem_t* p, hipStream_t stream);
+
+// Host Gauss-Legendre rule on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, double* xi, double* w);
+
+}  // namespace taps

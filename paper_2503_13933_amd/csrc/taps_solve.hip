@@ -1,0 +1,280 @@
+// Block-banded solve of the dim-d system (paper Sec. 2.6: with every factor
+// but U^[d] fixed, the Galerkin condition is the linear system
+// K^[d] U^[d] = Q^[d]; node-major it is block-banded with M x M blocks
+// B_ij = sum_k A^k_d[i][j] C^k and block half-bandwidth w = 2s+1).
+//
+// One workgroup walks the block chain i = 0..n-1 (block LU without pivoting,
+// right-looking, only the (w+1) x (w+1) active window is live):
+//   P = B_kk ; P^-1 by Gauss-Jordan in LDS ; y_k = P^-1 b_k
+//   Z_kj = P^-1 B_kj (j = k+1..k+w)        -- kept for back substitution
+//   B_ij -= B_ik Z_kj, b_i -= B_ik y_k     (i, j = k+1..k+w)
+// then x_k = y_k - sum_j Z_kj x_j from the last block row up.
+// The window lives in an L2-resident ring buffer indexed by (i mod (w+1),
+// j mod (w+1)); the pivot block, the column panel B_{k+1..k+w,k} and the
+// row panel Z_{k,k+1..k+w} live in LDS.  Rows of fixed nodes are identity
+// rows with zero right-hand side and their columns are zeroed, which keeps
+// X = 0 there.
+#include "taps_internal.hpp"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTI = 4;  // register tile of the trailing update (rows)
+constexpr int kTJ = 4;  // (cols)
+
+struct SolveArgs {
+  int n, M, s, K;
+  const double* band;   // K x n x (4s+3)
+  const double* C;      // K x M x M
+  const double* Q;      // n x M
+  const uint8_t* fixed; // n or null
+  double* X;            // n x M
+  double* Zst;          // n x M x (w M)
+  double* Yst;          // n x M
+  double* win;          // (w+1)^2 x M x M
+  double* rhs;          // (w+1) x M
+  int* info;
+};
+
+__device__ inline bool is_fixed(const SolveArgs& A, int i) { return A.fixed && A.fixed[i]; }
+
+// Write the original block B_ij (|i-j| <= w) into the window ring.
+__device__ void build_block(const SolveArgs& A, int i, int j, double* dst) {
+  const int M = A.M, MM = M * M, w = 2 * A.s + 1, BW = 2 * w + 1;
+  const bool fi = is_fixed(A, i), fj = is_fixed(A, j);
+  double coef[TAPS_MAX_KINDS];
+  for (int k = 0; k < A.K; ++k) coef[k] = A.band[(long(k) * A.n + i) * BW + (j - i + w)];
+  for (int t = threadIdx.x; t < MM; t += blockDim.x) {
+    double v;
+    if (fi) {
+      v = (i == j && (t / M) == (t % M)) ? 1.0 : 0.0;
+    } else if (fj) {
+      v = 0.0;
+    } else {
+      v = 0.0;
+      for (int k = 0; k < A.K; ++k) v += coef[k] * A.C[long(k) * MM + t];
+    }
+    dst[t] = v;
+  }
+}
+
+__device__ void build_rhs(const SolveArgs& A, int i, double* dst) {
+  const bool fi = is_fixed(A, i);
+  for (int m = threadIdx.x; m < A.M; m += blockDim.x) dst[m] = fi ? 0.0 : A.Q[long(i) * A.M + m];
+}
+
+__global__ __launch_bounds__(kThreads) void k_block_lu(SolveArgs A) {
+  extern __shared__ double lds[];
+  const int M = A.M, MM = M * M, w = 2 * A.s + 1, W1 = w + 1, n = A.n, wM = w * M;
+  double* sP = lds;            // M x M   pivot block -> its inverse
+  double* Lp = sP + MM;        // (w M) x M column panel  (also row-panel staging M x (w M))
+  double* Zp = Lp + w * MM;    // M x (w M)  Z row panel
+  double* sb = Zp + w * MM;    // M   b_k
+  double* sy = sb + M;         // M   y_k
+  __shared__ int s_info;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) s_info = 0;
+  auto WIN = [&](int i, int j) { return A.win + (long(i % W1) * W1 + (j % W1)) * MM; };
+  auto RHS = [&](int i) { return A.rhs + long(i % W1) * M; };
+
+  // initial window rows/cols 0..min(w, n-1)
+  const int init_hi = min(w, n - 1);
+  for (int i = 0; i <= init_hi; ++i) {
+    for (int j = 0; j <= init_hi; ++j) build_block(A, i, j, WIN(i, j));
+    build_rhs(A, i, RHS(i));
+  }
+  __syncthreads();
+
+  for (int k = 0; k < n; ++k) {
+    const int wa = min(w, n - 1 - k);  // active neighbours below / right
+    if (k > 0) {
+      const int t = k + w;
+      if (t < n) {
+        for (int j = k; j <= t; ++j) build_block(A, t, j, WIN(t, j));
+        for (int i = k; i < t; ++i) build_block(A, i, t, WIN(i, t));
+        build_rhs(A, t, RHS(t));
+      }
+      __syncthreads();
+    }
+    // ---- pivot block inverse (Gauss-Jordan, in place, no pivoting)
+    {
+      const double* P = WIN(k, k);
+      for (int t = tid; t < MM; t += nt) sP[t] = P[t];
+      const double* b = RHS(k);
+      for (int m = tid; m < M; m += nt) sb[m] = b[m];
+    }
+    __syncthreads();
+    for (int r = 0; r < M; ++r) {
+      const double piv = sP[r * M + r];
+      if (tid == 0 && s_info == 0 && (!(fabs(piv) > 0.0) || !isfinite(piv))) s_info = k + 1;
+      const double inv = 1.0 / piv;
+      for (int j = tid; j < M; j += nt)
+        if (j != r) sP[r * M + j] *= inv;
+      __syncthreads();
+      for (int t = tid; t < MM; t += nt) {
+        const int i = t / M, j = t % M;
+        if (i != r && j != r) sP[t] -= sP[i * M + r] * sP[r * M + j];
+      }
+      __syncthreads();
+      for (int i = tid; i < M; i += nt) {
+        if (i != r) sP[i * M + r] *= -inv;
+        else sP[r * M + r] = inv;
+      }
+      __syncthreads();
+    }
+    // y_k = P^-1 b_k ; stage the row panel B_{k, k+1..k+wa} (M x wa M) in Lp
+    for (int m = tid; m < M; m += nt) {
+      double v = 0.0;
+      for (int q = 0; q < M; ++q) v += sP[m * M + q] * sb[q];
+      sy[m] = v;
+      A.Yst[long(k) * M + m] = v;
+    }
+    const int waM = wa * M;
+    for (int t = tid; t < M * waM; t += nt) {
+      const int q = t / waM, J = t % waM;
+      const int jj = J / M, c = J % M;
+      Lp[q * waM + J] = WIN(k, k + 1 + jj)[q * M + c];
+    }
+    __syncthreads();
+    // Z = P^-1 (row panel), kept in LDS and stored for back substitution
+    for (int t = tid; t < M * waM; t += nt) {
+      const int q = t / waM, J = t % waM;
+      double v = 0.0;
+      for (int u = 0; u < M; ++u) v += sP[q * M + u] * Lp[u * waM + J];
+      Zp[q * waM + J] = v;
+      A.Zst[(long(k) * M + q) * wM + J] = v;
+    }
+    __syncthreads();
+    // column panel B_{k+1..k+wa, k} -> Lp ((wa M) x M)
+    for (int t = tid; t < waM * M; t += nt) {
+      const int I = t / M, q = t % M;
+      const int ii = I / M, r = I % M;
+      Lp[t] = WIN(k + 1 + ii, k)[r * M + q];
+    }
+    __syncthreads();
+    // trailing update of the window and the right-hand sides
+    const int nti = (waM + kTI - 1) / kTI, ntj = (waM + kTJ - 1) / kTJ;
+    for (int T = tid; T < nti * ntj; T += nt) {
+      const int I0 = (T / ntj) * kTI, J0 = (T % ntj) * kTJ;
+      double acc[kTI][kTJ];
+      for (int a = 0; a < kTI; ++a)
+        for (int b = 0; b < kTJ; ++b) acc[a][b] = 0.0;
+      for (int q = 0; q < M; ++q) {
+        double av[kTI], bv[kTJ];
+        for (int a = 0; a < kTI; ++a) av[a] = (I0 + a < waM) ? Lp[(I0 + a) * M + q] : 0.0;
+        for (int b = 0; b < kTJ; ++b) bv[b] = (J0 + b < waM) ? Zp[q * waM + J0 + b] : 0.0;
+        for (int a = 0; a < kTI; ++a)
+          for (int b = 0; b < kTJ; ++b) acc[a][b] += av[a] * bv[b];
+      }
+      for (int a = 0; a < kTI; ++a) {
+        const int I = I0 + a;
+        if (I >= waM) break;
+        const int bi = k + 1 + I / M, r = I % M;
+        for (int b = 0; b < kTJ; ++b) {
+          const int J = J0 + b;
+          if (J >= waM) break;
+          double* blk = WIN(bi, k + 1 + J / M);
+          blk[r * M + (J % M)] -= acc[a][b];
+        }
+      }
+    }
+    for (int I = tid; I < waM; I += nt) {
+      double v = 0.0;
+      for (int q = 0; q < M; ++q) v += Lp[I * M + q] * sy[q];
+      RHS(k + 1 + I / M)[I % M] -= v;
+    }
+    __syncthreads();
+  }
+
+  // ---- back substitution: x_k = y_k - sum_j Z_kj x_j
+  const int parts = max(1, nt / M);
+  double* sx = lds;                 // ring of (w+1) x M solved rows
+  double* spart = lds + W1 * M;     // parts x M partial sums
+  for (int k = n - 1; k >= 0; --k) {
+    const int wa = min(w, n - 1 - k);
+    const int waM = wa * M;
+    if (tid < parts * M) {
+      const int m = tid % M, part = tid / M;
+      const int per = (waM + parts - 1) / parts;
+      const int jb = part * per, je = min(waM, jb + per);
+      double v = 0.0;
+      const double* zrow = A.Zst + (long(k) * M + m) * wM;
+      for (int J = jb; J < je; ++J) v += zrow[J] * sx[((k + 1 + J / M) % W1) * M + (J % M)];
+      spart[part * M + m] = v;
+    }
+    __syncthreads();
+    for (int m = tid; m < M; m += nt) {
+      double v = A.Yst[long(k) * M + m];
+      for (int part = 0; part < parts; ++part) v -= spart[part * M + m];
+      sx[(k % W1) * M + m] = v;
+      A.X[long(k) * M + m] = v;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) A.info[0] = s_info;
+}
+
+bool lu_attr_set = false;
+
+}  // namespace
+
+namespace taps {
+
+size_t solve_lds_bytes(int M, int s) {
+  const int w = 2 * s + 1;
+  const size_t fwd = size_t(M) * M * (2 * w + 1) * 8 + 2 * size_t(M) * 8;
+  const size_t back = size_t(w + 1 + max(1, kThreads / M)) * M * 8;
+  return fwd > back ? fwd : back;
+}
+
+taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
+                           const double* d_Q, double* d_X, int* d_info, hipStream_t stream) {
+  const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
+  const size_t lds = solve_lds_bytes(M, s);
+  if (lds > 160 * 1024)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "M=%d with s=%d needs %zu bytes of LDS (max 163840)", M, s, lds);
+  Bump bump;
+  const size_t o_Z = bump.take(size_t(n) * M * w * M * 8);
+  const size_t o_Y = bump.take(size_t(n) * M * 8);
+  const size_t o_W = bump.take(size_t(w + 1) * (w + 1) * M * M * 8);
+  const size_t o_R = bump.take(size_t(w + 1) * M * 8);
+  TAPS_TRY(need_ws(h, bump.off, stream));
+  char* ws = static_cast<char*>(h->ws);
+  SolveArgs A;
+  A.n = n;
+  A.M = M;
+  A.s = s;
+  A.K = p->n_kinds[d];
+  A.band = p->d_band[d];
+  A.C = d_C;
+  A.Q = d_Q;
+  A.fixed = p->d_fixed[d];
+  A.X = d_X;
+  A.Zst = reinterpret_cast<double*>(ws + o_Z);
+  A.Yst = reinterpret_cast<double*>(ws + o_Y);
+  A.win = reinterpret_cast<double*>(ws + o_W);
+  A.rhs = reinterpret_cast<double*>(ws + o_R);
+  A.info = d_info;
+  if (!lu_attr_set) {
+    TAPS_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_lu),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    lu_attr_set = true;
+  }
+  k_block_lu<<<1, kThreads, lds, stream>>>(A);
+  TAPS_LAUNCHED(h, "k_block_lu");
+  return TAPS_OK;
+}
+
+}  // namespace taps
+
+using namespace taps;
+
+extern "C" taps_status taps_solve_dim(taps_handle_t h, const taps_problem_t* prob, int32_t d,
+                                      const double* d_C, const double* d_Q, double* d_X,
+                                      int32_t* d_info, hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  TAPS_TRY(check_problem(h, prob));
+  if (d < 0 || d >= prob->D) return fail(h, TAPS_ERR_INVALID, "dim %d out of range", d);
+  if (!d_C || !d_Q || !d_X || !d_info) return fail(h, TAPS_ERR_INVALID, "null pointer");
+  return solve_dim_impl(h, prob, d, d_C, d_Q, d_X, d_info, stream);
+}

@@ -1,0 +1,332 @@
+// Projected residual, mode balancing and the Algorithm 1 driver
+// (paper Sec. 2.5, the block-diagonal nonlinear system; Sec. 2.6, subspace
+// iteration).
+#include "taps_internal.hpp"
+
+#include <vector>
+
+namespace taps {
+size_t solve_lds_bytes(int M, int s);
+taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
+                           const double* d_Q, double* d_X, int* d_info, hipStream_t stream);
+}  // namespace taps
+
+namespace {
+
+constexpr int kResRows = 64;
+
+// Per chunk of kResRows rows: R = sum_k A^k U (C^k)^T - Q on the chunk, and the
+// chunk's sums of R^2 and Q^2 over free rows -> part[2*block], part[2*block+1].
+// V^k = U (C^k)^T is formed on the chunk plus a halo of w rows in LDS.
+__global__ void k_residual_part(int n, int M, int s, int K, const double* __restrict__ band,
+                                const double* __restrict__ C, const double* __restrict__ U,
+                                const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
+                                double* __restrict__ part) {
+  extern __shared__ double lds[];
+  const int w = 2 * s + 1, BW = 2 * w + 1, MM = M * M;
+  const int r0 = blockIdx.x * kResRows;
+  const int rows = min(kResRows, n - r0);
+  const int hr = rows + 2 * w;
+  double* sU = lds;              // hr x M
+  double* sV = sU + hr * M;      // hr x M
+  double* sC = sV + hr * M;      // M x M
+  double* sR = sC + MM;          // rows x M
+  __shared__ double red[2][256];
+  for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
+    const int rr = t / M, m = t % M;
+    const int g = r0 - w + rr;
+    sU[t] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
+  }
+  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) sR[t] = -Q[long(r0) * M + t];
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    for (int t = threadIdx.x; t < MM; t += blockDim.x) sC[t] = C[long(k) * MM + t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
+      const int rr = t / M, m = t % M;
+      double v = 0.0;
+      for (int q = 0; q < M; ++q) v += sU[rr * M + q] * sC[m * M + q];
+      sV[t] = v;
+    }
+    __syncthreads();
+    const double* bk = band + long(k) * n * BW;
+    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
+      const int i = t / M, m = t % M;
+      const double* brow = bk + long(r0 + i) * BW;
+      double v = 0.0;
+      for (int o = 0; o < BW; ++o) v += brow[o] * sV[(i + o) * M + m];
+      sR[t] += v;
+    }
+    __syncthreads();
+  }
+  double rr2 = 0.0, qq2 = 0.0;
+  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
+    const int i = t / M;
+    if (fixed && fixed[r0 + i]) continue;
+    const double q = Q[long(r0) * M + t];
+    rr2 += sR[t] * sR[t];
+    qq2 += q * q;
+  }
+  red[0][threadIdx.x] = rr2;
+  red[1][threadIdx.x] = qq2;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+struct ResFinal {
+  int D;
+  int nparts[TAPS_MAX_DIMS];
+  const double* part[TAPS_MAX_DIMS];
+};
+
+__global__ void k_residual_final(ResFinal A, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double rs = 0.0, qs = 0.0;
+  for (int d = 0; d < A.D; ++d) {
+    double r = 0.0, q = 0.0;
+    for (int b = 0; b < A.nparts[d]; ++b) {
+      r += A.part[d][2 * b];
+      q += A.part[d][2 * b + 1];
+    }
+    out[d] = r;
+    rs += r;
+    qs += q;
+  }
+  out[A.D] = qs;
+  out[A.D + 1] = (qs > 0.0) ? sqrt(rs / qs) : sqrt(rs);
+}
+
+struct BalanceArgs {
+  int D, M;
+  int n[TAPS_MAX_DIMS];
+  double* U[TAPS_MAX_DIMS];
+};
+
+// One block per mode: column norms of every dim, geometric mean, rescale.
+__global__ void k_balance(BalanceArgs A) {
+  __shared__ double red[256];
+  __shared__ double nrm[TAPS_MAX_DIMS];
+  const int m = blockIdx.x;
+  for (int e = 0; e < A.D; ++e) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < A.n[e]; i += blockDim.x) {
+      const double v = A.U[e][long(i) * A.M + m];
+      acc += v * v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) nrm[e] = sqrt(red[0]);
+    __syncthreads();
+  }
+  bool tiny = false;
+  double lg = 0.0;
+  for (int e = 0; e < A.D; ++e) {
+    tiny = tiny || !(nrm[e] >= 1e-300);
+    lg += log(nrm[e]);
+  }
+  if (tiny) return;
+  const double g = exp(lg / A.D);
+  for (int e = 0; e < A.D; ++e) {
+    const double f = g / nrm[e];
+    for (int i = threadIdx.x; i < A.n[e]; i += blockDim.x) A.U[e][long(i) * A.M + m] *= f;
+  }
+}
+
+__global__ void k_first_info(int D, const int* __restrict__ infos, int* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int v = 0;
+  for (int d = 0; d < D && v == 0; ++d) v = infos[d];
+  out[0] = v;
+}
+
+bool res_attr_set = false;
+
+}  // namespace
+
+namespace taps {
+size_t solve_lds_bytes(int M, int s);
+}
+
+using namespace taps;
+
+namespace {
+
+// Driver region of the handle: C and Q of the dim being solved, residual
+// partials of every dim, one info word per dim.
+struct DriverBufs {
+  double* C;
+  double* Q;
+  double* parts;
+  int* infos;
+};
+
+taps_status driver_bufs(taps_handle* h, const taps_problem_t* p, DriverBufs* out, hipStream_t stream) {
+  int Kmax = 1, nmax = 1, parts_total = 0;
+  for (int d = 0; d < p->D; ++d) {
+    Kmax = std::max(Kmax, p->n_kinds[d]);
+    nmax = std::max(nmax, p->n[d]);
+    parts_total += cdiv(p->n[d], kResRows);
+  }
+  Bump b;
+  const size_t oC = b.take(size_t(Kmax) * p->M * p->M * 8);
+  const size_t oQ = b.take(size_t(nmax) * p->M * 8);
+  const size_t oP = b.take(size_t(parts_total) * 2 * 8);
+  const size_t oI = b.take(TAPS_MAX_DIMS * 4);
+  TAPS_TRY(grow(h, &h->side, &h->side_bytes, b.off, stream));
+  char* base = static_cast<char*>(h->side);
+  out->C = reinterpret_cast<double*>(base + oC);
+  out->Q = reinterpret_cast<double*>(base + oQ);
+  out->parts = reinterpret_cast<double*>(base + oP);
+  out->infos = reinterpret_cast<int*>(base + oI);
+  return TAPS_OK;
+}
+
+taps_status residual_impl(taps_handle* h, const taps_problem_t* p, const double* const* d_U, double* d_out,
+                          hipStream_t stream) {
+  TAPS_TRY(prepare_cache(h, p, stream));
+  DriverBufs db;
+  TAPS_TRY(driver_bufs(h, p, &db, stream));
+  const uint32_t all = (1u << p->D) - 1u;
+  TAPS_TRY(refresh_grams(h, p, all, d_U, stream));
+  if (!res_attr_set) {
+    TAPS_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(k_residual_part),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    res_attr_set = true;
+  }
+  ResFinal rf{};
+  rf.D = p->D;
+  int off = 0;
+  for (int d = 0; d < p->D; ++d) {
+    const int nb = cdiv(p->n[d], kResRows);
+    const int w = 2 * p->s[d] + 1;
+    const int hr = kResRows + 2 * w;
+    const size_t lds = size_t(2 * hr * p->M + p->M * p->M + kResRows * p->M) * 8;
+    if (lds > 160 * 1024) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", lds);
+    TAPS_TRY(couple_and_force(h, p, d, db.C, db.Q, stream));
+    k_residual_part<<<nb, 256, lds, stream>>>(p->n[d], p->M, p->s[d], p->n_kinds[d], p->d_band[d], db.C,
+                                              d_U[d], db.Q, p->d_fixed[d], db.parts + 2 * off);
+    TAPS_LAUNCHED(h, "k_residual_part");
+    rf.nparts[d] = nb;
+    rf.part[d] = db.parts + 2 * off;
+    off += nb;
+  }
+  k_residual_final<<<1, 64, 0, stream>>>(rf, d_out);
+  TAPS_LAUNCHED(h, "k_residual_final");
+  return TAPS_OK;
+}
+
+taps_status balance_impl(taps_handle* h, const taps_problem_t* p, double* const* d_U, hipStream_t stream) {
+  BalanceArgs ba{};
+  ba.D = p->D;
+  ba.M = p->M;
+  for (int d = 0; d < p->D; ++d) {
+    ba.n[d] = p->n[d];
+    ba.U[d] = d_U[d];
+  }
+  k_balance<<<p->M, 256, 0, stream>>>(ba);
+  TAPS_LAUNCHED(h, "k_balance");
+  h->cache_valid = 0;  // every Gram changes scale
+  return TAPS_OK;
+}
+
+taps_status sweep_impl(taps_handle* h, const taps_problem_t* p, double* const* d_U, int* d_info,
+                       hipStream_t stream) {
+  TAPS_TRY(prepare_cache(h, p, stream));
+  DriverBufs db;
+  TAPS_TRY(driver_bufs(h, p, &db, stream));
+  const uint32_t all = (1u << p->D) - 1u;
+  h->cache_valid = 0;  // the factors passed in need not be those the cache was built from
+  for (int d = 0; d < p->D; ++d) {
+    const uint32_t need = all & ~(1u << d);
+    TAPS_TRY(refresh_grams(h, p, need & ~h->cache_valid, d_U, stream));
+    TAPS_TRY(couple_and_force(h, p, d, db.C, db.Q, stream));
+    TAPS_TRY(solve_dim_impl(h, p, d, db.C, db.Q, d_U[d], db.infos + d, stream));
+    h->cache_valid &= ~(1u << d);
+  }
+  TAPS_TRY(balance_impl(h, p, d_U, stream));
+  if (d_info) {
+    k_first_info<<<1, 64, 0, stream>>>(p->D, db.infos, d_info);
+    TAPS_LAUNCHED(h, "k_first_info");
+  }
+  return TAPS_OK;
+}
+
+taps_status check_factors(taps_handle* h, const taps_problem_t* p, const void* const* d_U) {
+  if (!d_U) return fail(h, TAPS_ERR_INVALID, "factor array is null");
+  for (int d = 0; d < p->D; ++d)
+    if (!d_U[d]) return fail(h, TAPS_ERR_INVALID, "factor %d is null", d);
+  return TAPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+taps_status taps_residual(taps_handle_t h, const taps_problem_t* prob, const double* const* d_U,
+                          double* d_out, hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  TAPS_TRY(check_problem(h, prob));
+  TAPS_TRY(check_factors(h, prob, reinterpret_cast<const void* const*>(d_U)));
+  if (!d_out) return fail(h, TAPS_ERR_INVALID, "null output");
+  return residual_impl(h, prob, d_U, d_out, stream);
+}
+
+taps_status taps_balance(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
+                         hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  TAPS_TRY(check_problem(h, prob));
+  TAPS_TRY(check_factors(h, prob, reinterpret_cast<const void* const*>(d_U)));
+  return balance_impl(h, prob, d_U, stream);
+}
+
+taps_status taps_sweep(taps_handle_t h, const taps_problem_t* prob, double* const* d_U, int32_t* d_info,
+                       hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  TAPS_TRY(check_problem(h, prob));
+  TAPS_TRY(check_factors(h, prob, reinterpret_cast<const void* const*>(d_U)));
+  return sweep_impl(h, prob, d_U, d_info, stream);
+}
+
+taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const* d_U, double tol,
+                     int32_t iter_max, int32_t* sweeps, double* rho, double* history, hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  TAPS_TRY(check_problem(h, prob));
+  TAPS_TRY(check_factors(h, prob, reinterpret_cast<const void* const*>(d_U)));
+  if (!sweeps || !rho) return fail(h, TAPS_ERR_INVALID, "null output");
+  if (iter_max < 1) return fail(h, TAPS_ERR_INVALID, "iter_max < 1");
+  const int D = prob->D;
+  double* d_res = h->d_small;                               // D+2 doubles
+  int* d_inf = reinterpret_cast<int*>(h->d_small + 64);    // one word
+  double res[TAPS_MAX_DIMS + 2];
+  int info = 0;
+  *sweeps = 0;
+  *rho = NAN;
+  for (int it = 0; it < iter_max; ++it) {
+    TAPS_TRY(sweep_impl(h, prob, d_U, d_inf, stream));
+    TAPS_TRY(residual_impl(h, prob, d_U, d_res, stream));
+    TAPS_HIP(h, hipMemcpyAsync(res, d_res, size_t(D + 2) * 8, hipMemcpyDeviceToHost, stream));
+    TAPS_HIP(h, hipMemcpyAsync(&info, d_inf, 4, hipMemcpyDeviceToHost, stream));
+    TAPS_HIP(h, hipStreamSynchronize(stream));
+    *sweeps = it + 1;
+    *rho = info ? NAN : res[D + 1];
+    if (history) history[it] = *rho;
+    if (info || !(*rho > tol)) break;
+  }
+  return TAPS_OK;
+}
+
+}  // extern "C"
