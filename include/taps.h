@@ -131,7 +131,7 @@ taps_status taps_source1d(taps_handle_t h, taps_source_kind kind, int32_t n_pts,
  *   TAPS_MASS   int Ntilde_i Ntilde_j        TAPS_STIFF int Btilde_i Btilde_j
  *   TAPS_DDT    int Ntilde_i Btilde_j        TAPS_WMASS int c(x) Ntilde_i Ntilde_j
  *   TAPS_BMASS  e_b e_b^T (boundary point mass of node bnode[k])
- * d_band: n_kinds bands of n_nodes*(4s+3) doubles, in the order of kinds[].
+ * d_band: n_kinds (<= 8) bands of n_nodes*(4s+3) doubles, in the order of kinds[].
  * d_coef_g: c at the Gauss points ((n_nodes-1)*n_gauss), WMASS only.
  * Loads: d_F[i*n_loads + r] = int Ntilde_i f_r with f_r given at the Gauss
  * points as d_f_g[r*n_gpts + g] (n_gpts = (n_nodes-1)*n_gauss).
@@ -185,6 +185,9 @@ taps_status taps_contract(taps_handle_t h, const taps_problem_t* prob, int32_t d
                           uint32_t stale_mask, const double* const* d_U,
                           double* d_C, double* d_Q, hipStream_t stream);
 
+/* Backward-error limit above which a dim solve counts as a breakdown. */
+#define TAPS_BERR_LIMIT 1e-8
+
 /* Solve the dim-d system sum_k A^k_d X (C^k)^T = Q (Sec. 2.6, the linear
  * system in the subspace iteration; node-major (n_d M) block-banded matrix
  * with M x M blocks sum_k A^k_d[i][j] C^k and block half-bandwidth 2s+1).
@@ -192,10 +195,15 @@ taps_status taps_contract(taps_handle_t h, const taps_problem_t* prob, int32_t d
  * symmetric part of the system is positive definite, which holds for the
  * heat and Poisson operators with at least one Dirichlet or initial-condition
  * row), pivot blocks inverted by Gauss-Jordan.  *d_info = 0 on success, or
- * 1 + the block row of the first zero / non-finite pivot. */
+ * 1 + the block row of the first zero / non-finite pivot.  Without pivoting
+ * the factorisation is not backward stable when the couplings are
+ * (near-)singular (more modes than the field's effective rank); d_berr
+ * (nullable, one double) receives the relative backward error
+ * ||sum_k A^k X C^k^T - Q||_F / ||Q||_F over free rows, computed after the
+ * solve, so callers can detect that case (TAPS_BERR_LIMIT). */
 taps_status taps_solve_dim(taps_handle_t h, const taps_problem_t* prob, int32_t d,
                            const double* d_C, const double* d_Q, double* d_X,
-                           int32_t* d_info, hipStream_t stream);
+                           int32_t* d_info, double* d_berr, hipStream_t stream);
 
 /* Projected Galerkin residual of every dim (the block-diagonal system of
  * Sec. 2.5; zero at a fixed point of Algorithm 1):
@@ -212,19 +220,41 @@ taps_status taps_balance(taps_handle_t h, const taps_problem_t* prob,
                          double* const* d_U, hipStream_t stream);
 
 /* One sweep of Algorithm 1 (Sec. 2.6): for d = 0..D-1 contract, solve into
- * d_U[d]; then balance.  d_info: one int32 (first failing block row + 1,
- * from the first dim that failed; 0 = ok). */
+ * d_U[d]; then balance.  d_info (nullable): one int32 (first failing block
+ * row + 1, from the first dim that failed; 0 = ok).  d_berr (nullable): D
+ * doubles, backward error of each dim solve. */
 taps_status taps_sweep(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
-                       int32_t* d_info, hipStream_t stream);
+                       int32_t* d_info, double* d_berr, hipStream_t stream);
 
 /* Algorithm 1 to tolerance: sweeps until rho <= tol or iter_max sweeps.
  * Synchronises the stream once per sweep to read rho.  Host outputs:
  * *sweeps, *rho (last), history[k] = rho after sweep k (nullable, iter_max
  * entries).  Returns TAPS_OK even if not converged (compare *rho with tol);
- * a breakdown in a dim solve ends the loop with *rho = NaN. */
+ * a breakdown in a dim solve (zero pivot, or backward error above
+ * TAPS_BERR_LIMIT) ends the loop with *rho = NaN and taps_last_error()
+ * naming the dim. */
 taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
                      double tol, int32_t iter_max, int32_t* sweeps, double* rho,
                      double* history, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing.  While enabled, each launch of a timed kernel family is
+ * bracketed by HIP events recorded on the stream it runs on, and the
+ * family's algorithmic work per launch is added up on the host:
+ *   TAPS_PROF_SOLVE    block LU of the dim system: flops = sum over block rows
+ *                      of 2/3 M^3 + 2 wa M^3 + 2 wa^2 M^3 + (2 + 4 wa) M^2,
+ *                      wa = min(w, n-1-k) (pivot factorisation, row panel,
+ *                      trailing update, right-hand side, back substitution);
+ *                      bytes = band + couplings + Q read, X written.
+ *   TAPS_PROF_CONTRACT Grams, load Grams, couplings and force: flops of the
+ *                      products, bytes = U, bands, F read once + outputs.
+ * taps_profile_enable(h, 1) clears the counters and starts recording,
+ * (h, 0) stops.  taps_profile_read synchronises on the recorded events and
+ * returns launches, summed kernel milliseconds, flops and bytes of one family. */
+typedef enum { TAPS_PROF_SOLVE = 0, TAPS_PROF_CONTRACT = 1 } taps_prof_family;
+taps_status taps_profile_enable(taps_handle_t h, int32_t enable);
+taps_status taps_profile_read(taps_handle_t h, taps_prof_family family, int32_t* launches,
+                              double* total_ms, double* flops, double* bytes);
 
 /* ------------------------------------------------------------------------ */
 /* TD interpolation (Sec. 2.3): Phi = Ntilde(pts) U with the shape window of

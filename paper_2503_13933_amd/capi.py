@@ -25,8 +25,9 @@ FUNCTIONS = (
     "taps_create", "taps_destroy", "taps_last_error", "taps_reserve", "taps_workspace_bytes",
     "taps_gauss_points", "taps_shape1d", "taps_source1d", "taps_assemble1d", "taps_contract",
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
-    "taps_reconstruct",
+    "taps_reconstruct", "taps_profile_enable", "taps_profile_read",
 )
+PROF_SOLVE, PROF_CONTRACT = 0, 1
 
 
 class TapsError(RuntimeError):
@@ -73,13 +74,15 @@ def lib():
             "taps_source1d": (i32, [vp, i32, i32, vp, i32, i32, P(dbl), vp, P(Basis1D), vp, vp]),
             "taps_assemble1d": (i32, [vp, P(Basis1D), i32, P(i32), vp, P(i32), vp, i32, vp, vp, vp]),
             "taps_contract": (i32, [vp, P(Problem), i32, u32, P(vp), vp, vp, vp]),
-            "taps_solve_dim": (i32, [vp, P(Problem), i32, vp, vp, vp, vp, vp]),
+            "taps_solve_dim": (i32, [vp, P(Problem), i32, vp, vp, vp, vp, vp, vp]),
             "taps_residual": (i32, [vp, P(Problem), P(vp), vp, vp]),
             "taps_balance": (i32, [vp, P(Problem), P(vp), vp]),
-            "taps_sweep": (i32, [vp, P(Problem), P(vp), vp, vp]),
+            "taps_sweep": (i32, [vp, P(Problem), P(vp), vp, vp, vp]),
             "taps_als": (i32, [vp, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), P(dbl), vp]),
             "taps_interp1d": (i32, [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]),
             "taps_reconstruct": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
+            "taps_profile_enable": (i32, [vp, i32]),
+            "taps_profile_read": (i32, [vp, i32, P(i32), P(dbl), P(dbl), P(dbl)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -174,9 +177,9 @@ def taps_contract(h: Handle, prob: Problem, d: int, stale_mask: int, U, Cout, Q,
                                 _stream(stream)), "taps_contract")
 
 
-def taps_solve_dim(h: Handle, prob: Problem, d: int, Cin, Q, X, info, stream=None):
-    h.check(lib().taps_solve_dim(h.h, C.byref(prob), d, _ptr(Cin), _ptr(Q), _ptr(X), _ptr(info), _stream(stream)),
-            "taps_solve_dim")
+def taps_solve_dim(h: Handle, prob: Problem, d: int, Cin, Q, X, info, berr=None, stream=None):
+    h.check(lib().taps_solve_dim(h.h, C.byref(prob), d, _ptr(Cin), _ptr(Q), _ptr(X), _ptr(info), _ptr(berr),
+                                 _stream(stream)), "taps_solve_dim")
 
 
 def taps_residual(h: Handle, prob: Problem, U, out, stream=None):
@@ -187,12 +190,14 @@ def taps_balance(h: Handle, prob: Problem, U, stream=None):
     h.check(lib().taps_balance(h.h, C.byref(prob), _ptr_array(U), _stream(stream)), "taps_balance")
 
 
-def taps_sweep(h: Handle, prob: Problem, U, info=None, stream=None):
-    h.check(lib().taps_sweep(h.h, C.byref(prob), _ptr_array(U), _ptr(info), _stream(stream)), "taps_sweep")
+def taps_sweep(h: Handle, prob: Problem, U, info=None, berr=None, stream=None):
+    h.check(lib().taps_sweep(h.h, C.byref(prob), _ptr_array(U), _ptr(info), _ptr(berr), _stream(stream)),
+            "taps_sweep")
 
 
 def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, stream=None):
-    """Returns (sweeps, rho, history list)."""
+    """Returns (sweeps, rho, history list); rho is NaN after a breakdown
+    (the reason is in last_error(h))."""
     sweeps = C.c_int32()
     rho = C.c_double()
     hist = (C.c_double * iter_max)()
@@ -212,3 +217,19 @@ def taps_reconstruct(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int =
     n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis])
     h.check(lib().taps_reconstruct(h.h, n, _ptr_array(Phis), M, _ptr(mode_w), prec, mode, _ptr(out), thr,
                                    _stream(stream)), "taps_reconstruct")
+
+
+def taps_profile_enable(h: Handle, enable: bool):
+    h.check(lib().taps_profile_enable(h.h, 1 if enable else 0), "taps_profile_enable")
+
+
+def taps_profile_read(h: Handle, family: int):
+    """(launches, total_ms, flops, bytes) of one kernel family since enable."""
+    n, ms, fl, by = C.c_int32(), C.c_double(), C.c_double(), C.c_double()
+    h.check(lib().taps_profile_read(h.h, family, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)),
+            "taps_profile_read")
+    return n.value, ms.value, fl.value, by.value
+
+
+def last_error(h: Handle) -> str:
+    return lib().taps_last_error(h.h).decode()

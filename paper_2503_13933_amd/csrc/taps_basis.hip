@@ -230,10 +230,12 @@ __global__ void k_source(SourceArgs S, const double* __restrict__ pts, const dou
   out[idx] = v;
 }
 
+constexpr int kMaxAssembleKinds = 8;
+
 struct BandArgs {
   int n, s, ng, K;
-  int kinds[TAPS_MAX_KINDS];
-  int bnode[TAPS_MAX_KINDS];
+  int kinds[kMaxAssembleKinds];
+  int bnode[kMaxAssembleKinds];
 };
 
 // Band entry (kind kk, row i, offset o): sum over the elements that contain
@@ -396,7 +398,8 @@ taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_
                             hipStream_t stream) {
   if (!h) return TAPS_ERR_INVALID;
   TAPS_TRY(check_basis(h, b));
-  if (n_kinds < 0 || n_kinds > TAPS_MAX_KINDS) return fail(h, TAPS_ERR_UNSUPPORTED, "n_kinds=%d", n_kinds);
+  if (n_kinds < 0 || n_kinds > kMaxAssembleKinds)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "n_kinds=%d outside 0..%d", n_kinds, kMaxAssembleKinds);
   if (n_kinds > 0 && (!kinds || !d_band)) return fail(h, TAPS_ERR_INVALID, "null kinds/band");
   if (n_loads < 0) return fail(h, TAPS_ERR_INVALID, "n_loads < 0");
   if (n_loads > 0 && (!d_f_g || !d_F)) return fail(h, TAPS_ERR_INVALID, "null load pointers");

@@ -204,7 +204,7 @@ __global__ void k_force(int n, int Rc, int M, const double* __restrict__ F, cons
   }
 }
 
-bool lds_attr_set = false;
+size_t gram_lds_allowed = 0;
 
 }  // namespace
 
@@ -250,11 +250,6 @@ taps_status prepare_cache(taps_handle* h, const taps_problem_t* p, hipStream_t s
 taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask, const double* const* d_U,
                           hipStream_t stream) {
   const int M = p->M;
-  if (!lds_attr_set) {
-    TAPS_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_partial),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    lds_attr_set = true;
-  }
   for (int e = 0; e < p->D; ++e) {
     if (!(mask & (1u << e))) continue;
     if (!d_U[e]) return fail(h, TAPS_ERR_INVALID, "factor of dim %d is null", e);
@@ -271,6 +266,9 @@ taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask
     double* gram = h->cache + cache_gram_off(p, e) / 8;
     double* lgram = h->cache + cache_lgram_off(p, e) / 8;
     const size_t lds = size_t(2 * kGramRows + 2 * w) * M * 8;
+    TAPS_TRY(allow_lds(h, k_gram_partial, lds, &gram_lds_allowed));
+    size_t slot;
+    TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
     k_gram_partial<<<chunks, 256, lds, stream>>>(n, M, p->s[e], K, p->d_band[e], d_U[e], pg);
     TAPS_LAUNCHED(h, "k_gram_partial");
     const long glen = long(K) * M * M;
@@ -283,6 +281,12 @@ taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask
     const long llen = long(Rc) * M;
     k_sum_parts<<<cdiv(llen, 256), 256, 0, stream>>>(splits, llen, pl, lgram);
     TAPS_LAUNCHED(h, "k_sum_parts(lgram)");
+    {
+      const double bw = 2 * w + 1;
+      const double fl = double(K) * (2.0 * bw * n * M + 2.0 * n * double(M) * M) + 2.0 * n * double(Rc) * M;
+      const double by = 8.0 * (double(n) * M + K * n * bw + double(n) * Rc + K * double(M) * M + double(Rc) * M);
+      TAPS_TRY(prof_end(h, slot, fl, by, stream));
+    }
     h->cache_valid |= (1u << e);
   }
   return TAPS_OK;
@@ -302,6 +306,8 @@ taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, dou
     for (int e = 0; e < p->D; ++e) ca.tk[t][e] = p->term_kind[t][e];
   }
   for (int e = 0; e < p->D; ++e) ca.gram[e] = h->cache + cache_gram_off(p, e) / 8;
+  size_t slot;
+  TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
   k_couple<<<cdiv(long(ca.Kd) * M * M, 256), 256, 0, stream>>>(ca, d_C);
   TAPS_LAUNCHED(h, "k_couple");
 
@@ -324,6 +330,10 @@ taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, dou
   TAPS_LAUNCHED(h, "k_load_weights");
   k_force<<<cdiv(p->n[d], kQRows), 256, 0, stream>>>(p->n[d], Rc, M, p->d_F[d], Wt, d_Q);
   TAPS_LAUNCHED(h, "k_force");
+  const double n = p->n[d];
+  const double fl = 2.0 * n * Rc * M + double(p->R) * (p->D - 1) * M + double(ca.Kd) * p->T * (p->D - 1) * M * M;
+  const double by = 8.0 * (n * Rc + double(Rc) * M + n * M + double(ca.Kd) * M * M);
+  TAPS_TRY(prof_end(h, slot, fl, by, stream));
   return TAPS_OK;
 }
 

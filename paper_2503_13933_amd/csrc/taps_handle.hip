@@ -93,9 +93,70 @@ taps_status check_problem(taps_handle* h, const taps_problem_t* p) {
   return TAPS_OK;
 }
 
+taps_status prof_begin(taps_handle* h, int family, hipStream_t stream, size_t* slot) {
+  *slot = size_t(-1);
+  if (!h->prof.on) return TAPS_OK;
+  auto& P = h->prof;
+  if (2 * (P.used + 1) > P.ev.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      TAPS_HIP(h, hipEventCreate(&e));
+      P.ev.push_back(e);
+    }
+    P.fam.push_back(family);
+  }
+  P.fam[P.used] = family;
+  TAPS_HIP(h, hipEventRecord(P.ev[2 * P.used], stream));
+  *slot = P.used++;
+  return TAPS_OK;
+}
+
+taps_status prof_end(taps_handle* h, size_t slot, double flops, double bytes, hipStream_t stream) {
+  if (slot == size_t(-1)) return TAPS_OK;
+  auto& P = h->prof;
+  TAPS_HIP(h, hipEventRecord(P.ev[2 * slot + 1], stream));
+  P.flops[P.fam[slot]] += flops;
+  P.bytes[P.fam[slot]] += bytes;
+  return TAPS_OK;
+}
+
 }  // namespace taps
 
 extern "C" {
+
+taps_status taps_profile_enable(taps_handle_t h, int32_t enable) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (enable) {
+    h->prof.used = 0;
+    h->prof.flops[0] = h->prof.flops[1] = 0.0;
+    h->prof.bytes[0] = h->prof.bytes[1] = 0.0;
+  }
+  h->prof.on = enable != 0;
+  return TAPS_OK;
+}
+
+taps_status taps_profile_read(taps_handle_t h, taps_prof_family family, int32_t* launches, double* total_ms,
+                              double* flops, double* bytes) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (family != TAPS_PROF_SOLVE && family != TAPS_PROF_CONTRACT)
+    return taps::fail(h, TAPS_ERR_INVALID, "unknown family %d", int(family));
+  auto& P = h->prof;
+  int cnt = 0;
+  double ms = 0.0;
+  for (size_t i = 0; i < P.used; ++i) {
+    if (P.fam[i] != family) continue;
+    TAPS_HIP(h, hipEventSynchronize(P.ev[2 * i + 1]));
+    float t = 0.0f;
+    TAPS_HIP(h, hipEventElapsedTime(&t, P.ev[2 * i], P.ev[2 * i + 1]));
+    ms += t;
+    ++cnt;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  if (flops) *flops = P.flops[family];
+  if (bytes) *bytes = P.bytes[family];
+  return TAPS_OK;
+}
 
 taps_status taps_create(taps_handle_t* out) {
   if (!out) return TAPS_ERR_INVALID;
@@ -119,6 +180,7 @@ taps_status taps_destroy(taps_handle_t h) {
   (void)hipDeviceSynchronize();
   if (h->ws) (void)hipFree(h->ws);
   if (h->cache) (void)hipFree(h->cache);
+  for (auto e : h->prof.ev) (void)hipEventDestroy(e);
   if (h->side) (void)hipFree(h->side);
   if (h->d_small) (void)hipFree(h->d_small);
   delete h;

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/taps.h"
 
@@ -30,6 +31,14 @@ struct taps_handle {
   double* d_small = nullptr;
   std::string err;
   int device = 0;
+  // kernel timing (taps_profile_*)
+  struct Prof {
+    std::vector<hipEvent_t> ev;    // start/stop pairs, reused
+    std::vector<int> fam;          // family of each recorded pair
+    size_t used = 0;               // pairs recorded since enable
+    double flops[2] = {0, 0}, bytes[2] = {0, 0};
+    bool on = false;
+  } prof;
 };
 
 namespace taps {
@@ -49,8 +58,10 @@ inline taps_status fail(taps_handle* h, taps_status st, const char* fmt, ...) {
 #define TAPS_HIP(h, call)                                                               \
   do {                                                                                 \
     hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
+    if (e_ != hipSuccess) {                                                            \
+      (void)hipGetLastError(); /* clear the sticky error for later launches */         \
       return taps::fail((h), TAPS_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    }                                                                                  \
   } while (0)
 
 #define TAPS_LAUNCHED(h, what)                                                          \
@@ -67,6 +78,17 @@ inline taps_status fail(taps_handle* h, taps_status st, const char* fmt, ...) {
   } while (0)
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Allow `bytes` of dynamic LDS for `kernel` (above 64 KB this must be opted in;
+// the limit counts static LDS too, so ask for what the launch needs).
+template <typename K>
+inline taps_status allow_lds(taps_handle* h, K kernel, size_t bytes, size_t* have) {
+  if (bytes <= *have || bytes <= 64 * 1024) return TAPS_OK;
+  TAPS_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  *have = bytes;
+  return TAPS_OK;
+}
 
 // Grow a device buffer (synchronising `stream` first, since old contents may be in use).
 inline taps_status grow(taps_handle* h, void** buf, size_t* have, size_t need, hipStream_t stream) {
@@ -121,6 +143,19 @@ taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, dou
                              double* d_Q, hipStream_t stream);
 // Ensure the cache is sized and signed for problem p.
 taps_status prepare_cache(taps_handle* h, const taps_problem_t* p, hipStream_t stream);
+
+// Dim solve (block LU) and the per-chunk sums of R^2 / Q^2 of the dim-d
+// system residual sum_k A^k U C^k^T - Q over free rows (2 doubles per chunk).
+taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
+                           const double* d_Q, double* d_X, int* d_info, double* d_berr, hipStream_t stream);
+int dim_residual_nparts(int n);
+taps_status dim_residual_parts(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
+                               const double* d_U, const double* d_Q, double* parts, int* nparts,
+                               hipStream_t stream);
+
+// Kernel timing helpers: bracket a launch with events when profiling is on.
+taps_status prof_begin(taps_handle* h, int family, hipStream_t stream, size_t* slot);
+taps_status prof_end(taps_handle* h, size_t slot, double flops, double bytes, hipStream_t stream);
 
 // Host Gauss-Legendre rule on [-1, 1] (Newton iteration on P_n).
 void gauss_legendre(int n, double* xi, double* w);

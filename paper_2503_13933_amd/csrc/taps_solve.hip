@@ -16,6 +16,8 @@
 // X = 0 there.
 #include "taps_internal.hpp"
 
+#include <algorithm>
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -214,11 +216,131 @@ __global__ __launch_bounds__(kThreads) void k_block_lu(SolveArgs A) {
   if (tid == 0) A.info[0] = s_info;
 }
 
-bool lu_attr_set = false;
+size_t lu_lds_allowed = 0;
+
+constexpr int kResRows = 64;
+
+
+// Per chunk of kResRows rows: R = sum_k A^k U (C^k)^T - Q on the chunk, and the
+// chunk's sums of R^2 and Q^2 over free rows -> part[2*block], part[2*block+1].
+// V^k = U (C^k)^T is formed on the chunk plus a halo of w rows in LDS.
+__global__ void k_residual_part(int n, int M, int s, int K, const double* __restrict__ band,
+                                const double* __restrict__ C, const double* __restrict__ U,
+                                const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
+                                double* __restrict__ part) {
+  extern __shared__ double lds[];
+  const int w = 2 * s + 1, BW = 2 * w + 1, MM = M * M;
+  const int r0 = blockIdx.x * kResRows;
+  const int rows = min(kResRows, n - r0);
+  const int hr = rows + 2 * w;
+  double* sU = lds;              // hr x M
+  double* sV = sU + hr * M;      // hr x M
+  double* sC = sV + hr * M;      // M x M
+  double* sR = sC + MM;          // rows x M
+  __shared__ double red[2][256];
+  for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
+    const int rr = t / M, m = t % M;
+    const int g = r0 - w + rr;
+    sU[t] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
+  }
+  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) sR[t] = -Q[long(r0) * M + t];
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    for (int t = threadIdx.x; t < MM; t += blockDim.x) sC[t] = C[long(k) * MM + t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
+      const int rr = t / M, m = t % M;
+      double v = 0.0;
+      for (int q = 0; q < M; ++q) v += sU[rr * M + q] * sC[m * M + q];
+      sV[t] = v;
+    }
+    __syncthreads();
+    const double* bk = band + long(k) * n * BW;
+    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
+      const int i = t / M, m = t % M;
+      const double* brow = bk + long(r0 + i) * BW;
+      double v = 0.0;
+      for (int o = 0; o < BW; ++o) v += brow[o] * sV[(i + o) * M + m];
+      sR[t] += v;
+    }
+    __syncthreads();
+  }
+  double rr2 = 0.0, qq2 = 0.0;
+  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
+    const int i = t / M;
+    if (fixed && fixed[r0 + i]) continue;
+    const double q = Q[long(r0) * M + t];
+    rr2 += sR[t] * sR[t];
+    qq2 += q * q;
+  }
+  red[0][threadIdx.x] = rr2;
+  red[1][threadIdx.x] = qq2;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+
+// Relative backward error of one dim solve from the per-chunk sums:
+// sqrt(sum R^2 / sum Q^2) over the free rows.
+__global__ void k_berr_final(int nparts, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double r = 0.0, q = 0.0;
+  for (int b = 0; b < nparts; ++b) {
+    r += part[2 * b];
+    q += part[2 * b + 1];
+  }
+  out[0] = q > 0.0 ? sqrt(r / q) : sqrt(r);
+}
+
+size_t res_lds_allowed = 0;
 
 }  // namespace
 
 namespace taps {
+
+int dim_residual_nparts(int n) { return cdiv(n, kResRows); }
+
+taps_status dim_residual_parts(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
+                               const double* d_U, const double* d_Q, double* parts, int* nparts,
+                               hipStream_t stream) {
+  const int nb = cdiv(p->n[d], kResRows);
+  const int w = 2 * p->s[d] + 1;
+  const int hr = kResRows + 2 * w;
+  const size_t lds = size_t(2 * hr * p->M + p->M * p->M + kResRows * p->M) * 8;
+  if (lds > 160 * 1024 - 4096) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", lds);
+  TAPS_TRY(allow_lds(h, k_residual_part, lds, &res_lds_allowed));
+  k_residual_part<<<nb, 256, lds, stream>>>(p->n[d], p->M, p->s[d], p->n_kinds[d], p->d_band[d], d_C, d_U, d_Q,
+                                            p->d_fixed[d], parts);
+  TAPS_LAUNCHED(h, "k_residual_part");
+  *nparts = nb;
+  return TAPS_OK;
+}
+
+// Algorithmic flops of the block LU solve (what the method needs, not what
+// the kernel spends: the pivot is counted as an LU, not an explicit inverse).
+double solve_flops(int n, int M, int w) {
+  const double m3 = double(M) * M * M, m2 = double(M) * M;
+  double f = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double wa = double(std::min(w, n - 1 - k));
+    f += (2.0 / 3.0) * m3 + 2.0 * wa * m3 + 2.0 * wa * wa * m3 + (2.0 + 4.0 * wa) * m2;
+  }
+  return f;
+}
+
+double solve_bytes(int n, int M, int w, int K) {
+  return 8.0 * (double(K) * n * (2 * w + 1) + double(K) * M * M + 2.0 * n * M);
+}
 
 size_t solve_lds_bytes(int M, int s) {
   const int w = 2 * s + 1;
@@ -228,16 +350,17 @@ size_t solve_lds_bytes(int M, int s) {
 }
 
 taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
-                           const double* d_Q, double* d_X, int* d_info, hipStream_t stream) {
+                           const double* d_Q, double* d_X, int* d_info, double* d_berr, hipStream_t stream) {
   const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
   const size_t lds = solve_lds_bytes(M, s);
-  if (lds > 160 * 1024)
+  if (lds > 160 * 1024 - 64)
     return fail(h, TAPS_ERR_UNSUPPORTED, "M=%d with s=%d needs %zu bytes of LDS (max 163840)", M, s, lds);
   Bump bump;
   const size_t o_Z = bump.take(size_t(n) * M * w * M * 8);
   const size_t o_Y = bump.take(size_t(n) * M * 8);
   const size_t o_W = bump.take(size_t(w + 1) * (w + 1) * M * M * 8);
   const size_t o_R = bump.take(size_t(w + 1) * M * 8);
+  const size_t o_P = bump.take(size_t(dim_residual_nparts(n)) * 2 * 8);
   TAPS_TRY(need_ws(h, bump.off, stream));
   char* ws = static_cast<char*>(h->ws);
   SolveArgs A;
@@ -255,13 +378,19 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
   A.win = reinterpret_cast<double*>(ws + o_W);
   A.rhs = reinterpret_cast<double*>(ws + o_R);
   A.info = d_info;
-  if (!lu_attr_set) {
-    TAPS_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_lu),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    lu_attr_set = true;
-  }
+  TAPS_TRY(allow_lds(h, k_block_lu, lds, &lu_lds_allowed));
+  size_t slot;
+  TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
   k_block_lu<<<1, kThreads, lds, stream>>>(A);
   TAPS_LAUNCHED(h, "k_block_lu");
+  TAPS_TRY(prof_end(h, slot, solve_flops(n, M, w), solve_bytes(n, M, w, A.K), stream));
+  if (d_berr) {
+    double* parts = reinterpret_cast<double*>(ws + o_P);
+    int nb = 0;
+    TAPS_TRY(dim_residual_parts(h, p, d, d_C, d_X, d_Q, parts, &nb, stream));
+    k_berr_final<<<1, 64, 0, stream>>>(nb, parts, d_berr);
+    TAPS_LAUNCHED(h, "k_berr_final");
+  }
   return TAPS_OK;
 }
 
@@ -271,10 +400,10 @@ using namespace taps;
 
 extern "C" taps_status taps_solve_dim(taps_handle_t h, const taps_problem_t* prob, int32_t d,
                                       const double* d_C, const double* d_Q, double* d_X,
-                                      int32_t* d_info, hipStream_t stream) {
+                                      int32_t* d_info, double* d_berr, hipStream_t stream) {
   if (!h) return TAPS_ERR_INVALID;
   TAPS_TRY(check_problem(h, prob));
   if (d < 0 || d >= prob->D) return fail(h, TAPS_ERR_INVALID, "dim %d out of range", d);
   if (!d_C || !d_Q || !d_X || !d_info) return fail(h, TAPS_ERR_INVALID, "null pointer");
-  return solve_dim_impl(h, prob, d, d_C, d_Q, d_X, d_info, stream);
+  return solve_dim_impl(h, prob, d, d_C, d_Q, d_X, d_info, d_berr, stream);
 }

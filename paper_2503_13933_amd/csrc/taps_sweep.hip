@@ -5,83 +5,8 @@
 
 #include <vector>
 
-namespace taps {
-size_t solve_lds_bytes(int M, int s);
-taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
-                           const double* d_Q, double* d_X, int* d_info, hipStream_t stream);
-}  // namespace taps
 
 namespace {
-
-constexpr int kResRows = 64;
-
-// Per chunk of kResRows rows: R = sum_k A^k U (C^k)^T - Q on the chunk, and the
-// chunk's sums of R^2 and Q^2 over free rows -> part[2*block], part[2*block+1].
-// V^k = U (C^k)^T is formed on the chunk plus a halo of w rows in LDS.
-__global__ void k_residual_part(int n, int M, int s, int K, const double* __restrict__ band,
-                                const double* __restrict__ C, const double* __restrict__ U,
-                                const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
-                                double* __restrict__ part) {
-  extern __shared__ double lds[];
-  const int w = 2 * s + 1, BW = 2 * w + 1, MM = M * M;
-  const int r0 = blockIdx.x * kResRows;
-  const int rows = min(kResRows, n - r0);
-  const int hr = rows + 2 * w;
-  double* sU = lds;              // hr x M
-  double* sV = sU + hr * M;      // hr x M
-  double* sC = sV + hr * M;      // M x M
-  double* sR = sC + MM;          // rows x M
-  __shared__ double red[2][256];
-  for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
-    const int rr = t / M, m = t % M;
-    const int g = r0 - w + rr;
-    sU[t] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
-  }
-  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) sR[t] = -Q[long(r0) * M + t];
-  __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    for (int t = threadIdx.x; t < MM; t += blockDim.x) sC[t] = C[long(k) * MM + t];
-    __syncthreads();
-    for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
-      const int rr = t / M, m = t % M;
-      double v = 0.0;
-      for (int q = 0; q < M; ++q) v += sU[rr * M + q] * sC[m * M + q];
-      sV[t] = v;
-    }
-    __syncthreads();
-    const double* bk = band + long(k) * n * BW;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-      const int i = t / M, m = t % M;
-      const double* brow = bk + long(r0 + i) * BW;
-      double v = 0.0;
-      for (int o = 0; o < BW; ++o) v += brow[o] * sV[(i + o) * M + m];
-      sR[t] += v;
-    }
-    __syncthreads();
-  }
-  double rr2 = 0.0, qq2 = 0.0;
-  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-    const int i = t / M;
-    if (fixed && fixed[r0 + i]) continue;
-    const double q = Q[long(r0) * M + t];
-    rr2 += sR[t] * sR[t];
-    qq2 += q * q;
-  }
-  red[0][threadIdx.x] = rr2;
-  red[1][threadIdx.x] = qq2;
-  __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + st];
-      red[1][threadIdx.x] += red[1][threadIdx.x + st];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = red[0][0];
-    part[2 * blockIdx.x + 1] = red[1][0];
-  }
-}
 
 struct ResFinal {
   int D;
@@ -153,13 +78,8 @@ __global__ void k_first_info(int D, const int* __restrict__ infos, int* __restri
   out[0] = v;
 }
 
-bool res_attr_set = false;
 
 }  // namespace
-
-namespace taps {
-size_t solve_lds_bytes(int M, int s);
-}
 
 using namespace taps;
 
@@ -171,6 +91,7 @@ struct DriverBufs {
   double* C;
   double* Q;
   double* parts;
+  double* berr;
   int* infos;
 };
 
@@ -179,18 +100,20 @@ taps_status driver_bufs(taps_handle* h, const taps_problem_t* p, DriverBufs* out
   for (int d = 0; d < p->D; ++d) {
     Kmax = std::max(Kmax, p->n_kinds[d]);
     nmax = std::max(nmax, p->n[d]);
-    parts_total += cdiv(p->n[d], kResRows);
+    parts_total += dim_residual_nparts(p->n[d]);
   }
   Bump b;
   const size_t oC = b.take(size_t(Kmax) * p->M * p->M * 8);
   const size_t oQ = b.take(size_t(nmax) * p->M * 8);
   const size_t oP = b.take(size_t(parts_total) * 2 * 8);
+  const size_t oB = b.take(TAPS_MAX_DIMS * 8);
   const size_t oI = b.take(TAPS_MAX_DIMS * 4);
   TAPS_TRY(grow(h, &h->side, &h->side_bytes, b.off, stream));
   char* base = static_cast<char*>(h->side);
   out->C = reinterpret_cast<double*>(base + oC);
   out->Q = reinterpret_cast<double*>(base + oQ);
   out->parts = reinterpret_cast<double*>(base + oP);
+  out->berr = reinterpret_cast<double*>(base + oB);
   out->infos = reinterpret_cast<int*>(base + oI);
   return TAPS_OK;
 }
@@ -202,24 +125,13 @@ taps_status residual_impl(taps_handle* h, const taps_problem_t* p, const double*
   TAPS_TRY(driver_bufs(h, p, &db, stream));
   const uint32_t all = (1u << p->D) - 1u;
   TAPS_TRY(refresh_grams(h, p, all, d_U, stream));
-  if (!res_attr_set) {
-    TAPS_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(k_residual_part),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    res_attr_set = true;
-  }
   ResFinal rf{};
   rf.D = p->D;
   int off = 0;
   for (int d = 0; d < p->D; ++d) {
-    const int nb = cdiv(p->n[d], kResRows);
-    const int w = 2 * p->s[d] + 1;
-    const int hr = kResRows + 2 * w;
-    const size_t lds = size_t(2 * hr * p->M + p->M * p->M + kResRows * p->M) * 8;
-    if (lds > 160 * 1024) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", lds);
     TAPS_TRY(couple_and_force(h, p, d, db.C, db.Q, stream));
-    k_residual_part<<<nb, 256, lds, stream>>>(p->n[d], p->M, p->s[d], p->n_kinds[d], p->d_band[d], db.C,
-                                              d_U[d], db.Q, p->d_fixed[d], db.parts + 2 * off);
-    TAPS_LAUNCHED(h, "k_residual_part");
+    int nb = 0;
+    TAPS_TRY(dim_residual_parts(h, p, d, db.C, d_U[d], db.Q, db.parts + 2 * off, &nb, stream));
     rf.nparts[d] = nb;
     rf.part[d] = db.parts + 2 * off;
     off += nb;
@@ -244,7 +156,7 @@ taps_status balance_impl(taps_handle* h, const taps_problem_t* p, double* const*
 }
 
 taps_status sweep_impl(taps_handle* h, const taps_problem_t* p, double* const* d_U, int* d_info,
-                       hipStream_t stream) {
+                       double* d_berr, hipStream_t stream) {
   TAPS_TRY(prepare_cache(h, p, stream));
   DriverBufs db;
   TAPS_TRY(driver_bufs(h, p, &db, stream));
@@ -254,7 +166,7 @@ taps_status sweep_impl(taps_handle* h, const taps_problem_t* p, double* const* d
     const uint32_t need = all & ~(1u << d);
     TAPS_TRY(refresh_grams(h, p, need & ~h->cache_valid, d_U, stream));
     TAPS_TRY(couple_and_force(h, p, d, db.C, db.Q, stream));
-    TAPS_TRY(solve_dim_impl(h, p, d, db.C, db.Q, d_U[d], db.infos + d, stream));
+    TAPS_TRY(solve_dim_impl(h, p, d, db.C, db.Q, d_U[d], db.infos + d, (d_berr ? d_berr : db.berr) + d, stream));
     h->cache_valid &= ~(1u << d);
   }
   TAPS_TRY(balance_impl(h, p, d_U, stream));
@@ -294,11 +206,11 @@ taps_status taps_balance(taps_handle_t h, const taps_problem_t* prob, double* co
 }
 
 taps_status taps_sweep(taps_handle_t h, const taps_problem_t* prob, double* const* d_U, int32_t* d_info,
-                       hipStream_t stream) {
+                       double* d_berr, hipStream_t stream) {
   if (!h) return TAPS_ERR_INVALID;
   TAPS_TRY(check_problem(h, prob));
   TAPS_TRY(check_factors(h, prob, reinterpret_cast<const void* const*>(d_U)));
-  return sweep_impl(h, prob, d_U, d_info, stream);
+  return sweep_impl(h, prob, d_U, d_info, d_berr, stream);
 }
 
 taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const* d_U, double tol,
@@ -310,21 +222,35 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
   if (iter_max < 1) return fail(h, TAPS_ERR_INVALID, "iter_max < 1");
   const int D = prob->D;
   double* d_res = h->d_small;                               // D+2 doubles
+  double* d_be = h->d_small + 32;                           // D doubles
   int* d_inf = reinterpret_cast<int*>(h->d_small + 64);    // one word
-  double res[TAPS_MAX_DIMS + 2];
+  double res[TAPS_MAX_DIMS + 2], be[TAPS_MAX_DIMS];
   int info = 0;
   *sweeps = 0;
   *rho = NAN;
   for (int it = 0; it < iter_max; ++it) {
-    TAPS_TRY(sweep_impl(h, prob, d_U, d_inf, stream));
+    TAPS_TRY(sweep_impl(h, prob, d_U, d_inf, d_be, stream));
     TAPS_TRY(residual_impl(h, prob, d_U, d_res, stream));
     TAPS_HIP(h, hipMemcpyAsync(res, d_res, size_t(D + 2) * 8, hipMemcpyDeviceToHost, stream));
+    TAPS_HIP(h, hipMemcpyAsync(be, d_be, size_t(D) * 8, hipMemcpyDeviceToHost, stream));
     TAPS_HIP(h, hipMemcpyAsync(&info, d_inf, 4, hipMemcpyDeviceToHost, stream));
     TAPS_HIP(h, hipStreamSynchronize(stream));
     *sweeps = it + 1;
-    *rho = info ? NAN : res[D + 1];
+    int bad = -1;
+    for (int d = 0; d < D && bad < 0; ++d)
+      if (!(be[d] <= TAPS_BERR_LIMIT)) bad = d;
+    *rho = (info || bad >= 0) ? NAN : res[D + 1];
     if (history) history[it] = *rho;
-    if (info || !(*rho > tol)) break;
+    if (info) {
+      fail(h, TAPS_OK, "sweep %d: zero or non-finite pivot (info %d)", it + 1, info);
+      break;
+    }
+    if (bad >= 0) {
+      fail(h, TAPS_OK, "sweep %d: dim %d solve backward error %.3e above %.0e", it + 1, bad, be[bad],
+           TAPS_BERR_LIMIT);
+      break;
+    }
+    if (!(*rho > tol)) break;
   }
   return TAPS_OK;
 }

@@ -73,7 +73,8 @@ class DeviceProblem:
         self.keep = []
         p = Problem()
         p.D, p.M, p.T = self.D, M, len(terms)
-        R = len(load_cols[0])
+        given = [len(c) for c in load_cols if c is not None]
+        R = given[0] if given else axes[0].F.shape[1]
         p.R = R
         for d, a in enumerate(axes):
             p.n[d] = a.n
