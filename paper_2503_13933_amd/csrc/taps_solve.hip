@@ -17,6 +17,7 @@
 #include "taps_internal.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace {
 
@@ -217,6 +218,196 @@ __global__ __launch_bounds__(kThreads) void k_block_lu(SolveArgs A) {
 }
 
 size_t lu_lds_allowed = 0;
+// ---------------------------------------------------------------------------
+// Matrix-core variant of the same block LU (same math, same window ring):
+// 512 threads, the pivot inverse by a double-buffered Gauss-Jordan (one
+// barrier per pivot), and both block products -- Z = P^-1 (row panel) and
+// the trailing update B_ij -= B_ik Z_kj -- on v_mfma_f64_16x16x4f64.
+// LDS holds the operands in fragment-friendly layouts (contiguous along the
+// 16-wide output index): LpT[q][I] = -B_{k+1+I/M, k}[I%M][q] and
+// Zp[q][J] = Z_{k, k+1+J/M}[q][J%M], inner index q padded to a multiple of 4
+// with zero rows.  MFMA f64 16x16x4 lane layout: A[l%16][l/16], B[l/16][l%16],
+// D[l/16 + 4i][l%16] (i = 0..3).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kThreadsMfma = 512;
+
+__device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma(SolveArgs A) {
+  extern __shared__ double lds[];
+  const int M = A.M, MM = M * M, w = 2 * A.s + 1, W1 = w + 1, n = A.n, wM = w * M;
+  const int M4 = (M + 3) & ~3;
+  const int P16 = ((wM + 15) / 16) * 16;
+  double* LpT = lds;              // M4 x P16
+  double* Zp = LpT + M4 * P16;    // M4 x P16
+  double* sPa = Zp + M4 * P16;    // M x M
+  double* sPb = sPa + MM;         // M x M
+  double* sb = sPb + MM;          // M
+  double* sy = sb + M;            // M
+  __shared__ int s_info;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+  if (tid == 0) s_info = 0;
+  auto WIN = [&](int i, int j) { return A.win + (long(i % W1) * W1 + (j % W1)) * MM; };
+  auto RHS = [&](int i) { return A.rhs + long(i % W1) * M; };
+  // zero the K-padding rows once; they are never written afterwards
+  for (int t = tid; t < (M4 - M) * P16; t += nt) {
+    LpT[M * P16 + t] = 0.0;
+    Zp[M * P16 + t] = 0.0;
+  }
+  const int init_hi = min(w, n - 1);
+  for (int i = 0; i <= init_hi; ++i) {
+    for (int j = 0; j <= init_hi; ++j) build_block(A, i, j, WIN(i, j));
+    build_rhs(A, i, RHS(i));
+  }
+  __syncthreads();
+
+  for (int k = 0; k < n; ++k) {
+    const int wa = min(w, n - 1 - k);
+    const int waM = wa * M;
+    if (k > 0) {
+      const int t = k + w;
+      if (t < n) {
+        for (int j = k; j <= t; ++j) build_block(A, t, j, WIN(t, j));
+        for (int i = k; i < t; ++i) build_block(A, i, t, WIN(i, t));
+        build_rhs(A, t, RHS(t));
+      }
+      __syncthreads();
+    }
+    // pivot block, right-hand side and the row panel B_{k, k+1..k+wa} (staged in LpT as [t][J])
+    {
+      const double* P = WIN(k, k);
+      for (int t = tid; t < MM; t += nt) sPa[t] = P[t];
+      const double* b = RHS(k);
+      for (int m = tid; m < M; m += nt) sb[m] = b[m];
+      for (int t = tid; t < M * waM; t += nt) {
+        const int q = t / waM, J = t % waM;
+        LpT[q * P16 + J] = WIN(k, k + 1 + J / M)[q * M + (J % M)];
+      }
+    }
+    __syncthreads();
+    // Gauss-Jordan inverse, double buffered: every entry of the next buffer
+    // depends on the current one only, so one barrier per pivot
+    double* cur = sPa;
+    double* nxt = sPb;
+    for (int r = 0; r < M; ++r) {
+      const double p = cur[r * M + r];
+      if (tid == 0 && s_info == 0 && (!(fabs(p) > 0.0) || !isfinite(p))) s_info = k + 1;
+      const double ip = 1.0 / p;
+      for (int t = tid; t < MM; t += nt) {
+        const int i = t / M, j = t % M;
+        double v;
+        if (i == r) v = (j == r) ? ip : cur[r * M + j] * ip;
+        else if (j == r) v = -cur[i * M + r] * ip;
+        else v = cur[t] - cur[i * M + r] * (cur[r * M + j] * ip);
+        nxt[t] = v;
+      }
+      __syncthreads();
+      double* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    }
+    // y_k = P^-1 b_k
+    for (int m = tid; m < M; m += nt) {
+      double v = 0.0;
+      for (int q = 0; q < M; ++q) v += cur[m * M + q] * sb[q];
+      sy[m] = v;
+      A.Yst[long(k) * M + m] = v;
+    }
+    // Z = P^-1 (row panel) on the matrix cores: tiles of 16 (rows q) x 16 (cols J)
+    {
+      const int tr = (M + 15) / 16, tc = (waM + 15) / 16;
+      for (int T = wave; T < tr * tc; T += nwaves) {
+        const int q0 = (T / tc) * 16, J0 = (T % tc) * 16;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        const int ar = q0 + (lane & 15);
+        const int bc = J0 + (lane & 15);
+        for (int kk = 0; kk < M4; kk += 4) {
+          const int kx = kk + (lane >> 4);
+          const double a = (ar < M && kx < M) ? cur[ar * M + kx] : 0.0;
+          const double b = (kx < M && bc < waM) ? LpT[kx * P16 + bc] : 0.0;
+          acc = mfma16x16x4(a, b, acc);
+        }
+        for (int i = 0; i < 4; ++i) {
+          const int q = q0 + (lane >> 4) + 4 * i;
+          if (q < M && bc < waM) {
+            Zp[q * P16 + bc] = acc[i];
+            A.Zst[(long(k) * M + q) * wM + bc] = acc[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // -(column panel)^T -> LpT[q][I]
+    for (int t = tid; t < waM * M; t += nt) {
+      const int I = t / M, q = t % M;
+      LpT[q * P16 + I] = -WIN(k + 1 + I / M, k)[(I % M) * M + q];
+    }
+    __syncthreads();
+    // trailing update B_ij += (-L) Z on the matrix cores, accumulating into the window
+    {
+      const int tt = (waM + 15) / 16;
+      for (int T = wave; T < tt * tt; T += nwaves) {
+        const int I0 = (T / tt) * 16, J0 = (T % tt) * 16;
+        const int col = J0 + (lane & 15);
+        double* cp[4];
+        v4d acc;
+        for (int i = 0; i < 4; ++i) {
+          const int row = I0 + (lane >> 4) + 4 * i;
+          cp[i] = (row < waM && col < waM)
+                      ? WIN(k + 1 + row / M, k + 1 + col / M) + (row % M) * M + (col % M)
+                      : nullptr;
+          acc[i] = cp[i] ? *cp[i] : 0.0;
+        }
+        const int ar = I0 + (lane & 15);
+        for (int kk = 0; kk < M4; kk += 4) {
+          const int kx = kk + (lane >> 4);
+          acc = mfma16x16x4(LpT[kx * P16 + ar], Zp[kx * P16 + col], acc);
+        }
+        for (int i = 0; i < 4; ++i)
+          if (cp[i]) *cp[i] = acc[i];
+      }
+    }
+    for (int I = tid; I < waM; I += nt) {
+      double v = 0.0;
+      for (int q = 0; q < M; ++q) v += LpT[q * P16 + I] * sy[q];
+      RHS(k + 1 + I / M)[I % M] += v;
+    }
+    __syncthreads();
+  }
+
+  // back substitution: x_k = y_k - sum_j Z_kj x_j
+  const int parts = max(1, nt / M);
+  double* sx = lds;
+  double* spart = lds + W1 * M;
+  for (int k = n - 1; k >= 0; --k) {
+    const int wa = min(w, n - 1 - k);
+    const int waM = wa * M;
+    if (tid < parts * M) {
+      const int m = tid % M, part = tid / M;
+      const int per = (waM + parts - 1) / parts;
+      const int jb = part * per, je = min(waM, jb + per);
+      double v = 0.0;
+      const double* zrow = A.Zst + (long(k) * M + m) * wM;
+      for (int J = jb; J < je; ++J) v += zrow[J] * sx[((k + 1 + J / M) % W1) * M + (J % M)];
+      spart[part * M + m] = v;
+    }
+    __syncthreads();
+    for (int m = tid; m < M; m += nt) {
+      double v = A.Yst[long(k) * M + m];
+      for (int part = 0; part < parts; ++part) v -= spart[part * M + m];
+      sx[(k % W1) * M + m] = v;
+      A.X[long(k) * M + m] = v;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) A.info[0] = s_info;
+}
+
+size_t lu_mfma_lds_allowed = 0;
+
 
 constexpr int kResRows = 64;
 
@@ -342,6 +533,14 @@ double solve_bytes(int n, int M, int w, int K) {
   return 8.0 * (double(K) * n * (2 * w + 1) + double(K) * M * M + 2.0 * n * M);
 }
 
+size_t solve_mfma_lds_bytes(int M, int s) {
+  const int w = 2 * s + 1;
+  const size_t M4 = (M + 3) & ~3, P16 = ((w * M + 15) / 16) * 16;
+  const size_t fwd = (2 * M4 * P16 + 2 * size_t(M) * M + 2 * size_t(M)) * 8;
+  const size_t back = size_t(w + 1 + max(1, kThreadsMfma / M)) * M * 8;
+  return fwd > back ? fwd : back;
+}
+
 size_t solve_lds_bytes(int M, int s) {
   const int w = 2 * s + 1;
   const size_t fwd = size_t(M) * M * (2 * w + 1) * 8 + 2 * size_t(M) * 8;
@@ -352,7 +551,9 @@ size_t solve_lds_bytes(int M, int s) {
 taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
                            const double* d_Q, double* d_X, int* d_info, double* d_berr, hipStream_t stream) {
   const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
-  const size_t lds = solve_lds_bytes(M, s);
+  const size_t lds_mfma = solve_mfma_lds_bytes(M, s);
+  const bool use_mfma = lds_mfma <= 160 * 1024 - 64 && !getenv("TAPS_SOLVE_VECTOR");
+  const size_t lds = use_mfma ? lds_mfma : solve_lds_bytes(M, s);
   if (lds > 160 * 1024 - 64)
     return fail(h, TAPS_ERR_UNSUPPORTED, "M=%d with s=%d needs %zu bytes of LDS (max 163840)", M, s, lds);
   Bump bump;
@@ -378,11 +579,18 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
   A.win = reinterpret_cast<double*>(ws + o_W);
   A.rhs = reinterpret_cast<double*>(ws + o_R);
   A.info = d_info;
-  TAPS_TRY(allow_lds(h, k_block_lu, lds, &lu_lds_allowed));
   size_t slot;
-  TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
-  k_block_lu<<<1, kThreads, lds, stream>>>(A);
-  TAPS_LAUNCHED(h, "k_block_lu");
+  if (use_mfma) {
+    TAPS_TRY(allow_lds(h, k_block_lu_mfma, lds, &lu_mfma_lds_allowed));
+    TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+    k_block_lu_mfma<<<1, kThreadsMfma, lds, stream>>>(A);
+    TAPS_LAUNCHED(h, "k_block_lu_mfma");
+  } else {
+    TAPS_TRY(allow_lds(h, k_block_lu, lds, &lu_lds_allowed));
+    TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+    k_block_lu<<<1, kThreads, lds, stream>>>(A);
+    TAPS_LAUNCHED(h, "k_block_lu");
+  }
   TAPS_TRY(prof_end(h, slot, solve_flops(n, M, w), solve_bytes(n, M, w, A.K), stream));
   if (d_berr) {
     double* parts = reinterpret_cast<double*>(ws + o_P);

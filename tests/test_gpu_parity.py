@@ -180,10 +180,15 @@ def _oracle_C_to_dev(ora, Co, d, M):
     return out
 
 
+@pytest.mark.parametrize("kernel", ["mfma", "vector"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_solve_dim(env, name):
+def test_solve_dim(env, name, kernel, monkeypatch):
     torch, capi, problem, h = env
-    _say(f"solve_dim {name}")
+    _say(f"solve_dim {name} ({kernel} kernel)")
+    if kernel == "vector":
+        monkeypatch.setenv("TAPS_SOLVE_VECTOR", "1")
+    else:
+        monkeypatch.delenv("TAPS_SOLVE_VECTOR", raising=False)
     case, dev, ora = _both(env, name)
     M = case.M
     Uh = _rand_U(ora, M, 23)
