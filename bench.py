@@ -1,12 +1,16 @@
 #!/usr/bin/env python
 """Benchmark: TAPS slab solves/s on one MI355X.
 
-A step is one slab solve: Algorithm 1 (subspace iteration) from the seeded
-initial factors until the projected residual reaches --tol or --sweeps sweeps
-have run, every kernel of the path (contractions, block-banded dim solves,
-balancing, residual) on the GPU through the C ABI.  Inputs are resident in
-HBM before timing starts.  The default workload is one space-time heat slab:
-512 x 512 x 128 nodes x 257 time nodes, M = 40 modes, moving Gaussian source.
+A step is one batch of slab solves: Algorithm 1 (subspace iteration) from the
+seeded initial factors until the projected residual reaches --tol or --sweeps
+sweeps have run, every kernel of the path (contractions, block-banded dim
+solves, balancing, residual) on the GPU through the C ABI.  Inputs are
+resident in HBM before timing starts.  The default workload is a batch of
+--batch independent space-time heat slabs on one grid, 512 x 512 x 128 nodes
+x 257 time nodes, M = 40 modes, moving Gaussian source with per-slab power,
+radius, conductivity and track offset; --batch 1 runs the plain
+one-slab-at-a-time form.  The plain form is also timed on one slab and
+reported beside the batched value.
 
 The JSON line carries the roofline of the dominant kernel (the block-banded
 dim solve, FP64 ALU-bound: algorithmic flops / event-timed kernel time over
@@ -14,6 +18,8 @@ the timed region) and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -81,6 +87,8 @@ def main():
     ap.add_argument("--M", type=int, default=40)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=10, help="sweep budget per slab solve")
+    ap.add_argument("--batch", type=int, default=128, help="slabs solved together (1 = plain form)")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside the batch")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-sweeps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,47 +101,71 @@ def main():
 
     import torch
     from paper_2503_13933_amd import capi, problem
+    import taps_workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     case = make_case(args)
     h = capi.Handle()
     t0 = time.perf_counter()
-    dp = problem.build(h, case)
-    import taps_workloads as W
-    U0 = dp.factors(W.initial_factors(case.axes, case.M, case.seed))
-    U = [u.clone() for u in U0]
+    if case.kind == "heat_slab" and args.batch > 1:
+        cases = W.heat_slab_family(args.batch, seed=args.seed, nx=args.nx, ny=args.nx, nz=args.nz,
+                                   nt=args.nt, M=args.M)
+    else:
+        cases = [case]
+    dps = [problem.build(h, c) for c in cases]
+    U0 = [dp.factors(W.initial_factors(c.axes, c.M, c.seed)) for dp, c in zip(dps, cases)]
+    U = [[u.clone() for u in us] for us in U0]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    log(f"setup {setup_s:.2f}s: {case.kind} n={[a.n for a in case.axes]} M={case.M}")
+    B = len(cases)
+    log(f"setup {setup_s:.2f}s: {B} x {case.kind} n={[a.n for a in case.axes]} M={case.M}")
 
-    def solve_once():
-        for u, u0 in zip(U, U0):
-            u.copy_(u0)
-        return capi.taps_als(h, dp.struct, U, args.tol, args.sweeps)
+    def reset(i=None):
+        for k in (range(B) if i is None else [i]):
+            for u, u0 in zip(U[k], U0[k]):
+                u.copy_(u0)
+
+    def solve_batch():
+        reset()
+        if B == 1:
+            sw, rho, _ = capi.taps_als(h, dps[0].struct, U[0], args.tol, args.sweeps)
+            return [sw], [rho]
+        return capi.taps_als_batched(h, [dp.struct for dp in dps], U, args.tol, args.sweeps)
 
     for w in range(args.warmup):
-        sw, rho, _ = solve_once()
+        sw, rho = solve_batch()
         torch.cuda.synchronize()
-        log(f"warmup {w + 1}/{args.warmup}: {sw} sweeps, rho={rho:.3e}")
+        log(f"warmup {w + 1}/{args.warmup}: sweeps {min(sw)}..{max(sw)}, rho {min(rho):.3e}..{max(rho):.3e}")
 
     capi.taps_profile_enable(h, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sweeps_total, rho = 0, float("nan")
+    sweeps_total, rhos = 0, []
     for k in range(args.steps):
-        sw, rho, hist = solve_once()
-        sweeps_total += sw
-        log(f"step {k + 1}/{args.steps}: {sw} sweeps, rho={rho:.3e}")
+        sw, rhos = solve_batch()
+        sweeps_total += sum(sw)
+        log(f"step {k + 1}/{args.steps}: sweeps {min(sw)}..{max(sw)}, rho {min(rhos):.3e}..{max(rhos):.3e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     capi.taps_profile_enable(h, False)
     n_solve, ms_solve, fl_solve, _ = capi.taps_profile_read(h, capi.PROF_SOLVE)
     n_con, ms_con, fl_con, by_con = capi.taps_profile_read(h, capi.PROF_CONTRACT)
 
-    value = args.steps / elapsed
+    plain = None
+    if B > 1 and not args.no_plain:
+        reset(0)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        sw, rho, _ = capi.taps_als(h, dps[0].struct, U[0], args.tol, args.sweeps)
+        torch.cuda.synchronize()
+        plain = {"value": 1.0 / (time.perf_counter() - tp), "sweeps": sw, "rho": rho}
+        log(f"plain form: one slab {1.0 / plain['value']:.3f} s, {sw} sweeps")
+
+    value = B * args.steps / elapsed
     achieved = (fl_solve / n_solve) / (ms_solve / n_solve * 1e-3) / 1e12 if n_solve else 0.0
-    sweeps_per_solve = sweeps_total / args.steps
+    sweeps_per_solve = sweeps_total / (B * args.steps)
+    rho = float(np.nanmax(rhos)) if rhos else float("nan")
     out = {
         "metric": "TAPS slab solves/s at rel. residual 1e-8; warm-start+batched vs plain",
         "value": value,
@@ -148,19 +180,22 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"{case.kind} {'x'.join(str(a.n) for a in case.axes)} M={case.M} "
-                         f"plain init, sweep budget {args.sweeps}, tol {args.tol:g}"),
-            "variant": "plain",
+            "workload": (f"{B} x {case.kind} {'x'.join(str(a.n) for a in case.axes)} M={case.M} "
+                         f"random init, sweep budget {args.sweeps}, tol {args.tol:g}"),
+            "variant": "batched" if B > 1 else "plain",
+            "batch": B,
             "sweeps_per_solve": sweeps_per_solve,
-            "rho_final": rho,
+            "rho_final_max": rho,
             "tol_reached": bool(rho <= args.tol),
             "setup_s": setup_s,
-            "solve_kernel_ms_per_sweep": ms_solve / max(1, sweeps_total),
-            "contract_kernel_ms_per_sweep": ms_con / max(1, sweeps_total),
+            "solve_kernel_ms_per_step": ms_solve / args.steps,
+            "contract_kernel_ms_per_step": ms_con / args.steps,
+            "plain": plain,
+            "batched_over_plain": (value / plain["value"]) if plain else None,
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_block_lu (block-banded FP64 dim solve)",
+            "kernel": "k_block_lu_mfma(_batched) (block-banded FP64 dim solve)",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
@@ -173,7 +208,7 @@ def main():
     }
     if not args.no_cpu_baseline and case.kind in ("heat_slab", "poisson2d"):
         log("cpu baseline: oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(case, sweeps_per_solve, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(cases[0], sweeps_per_solve, args.cpu_sweeps)
     h.close()
     print(json.dumps(out), flush=True)
 

@@ -237,6 +237,19 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
                      double tol, int32_t iter_max, int32_t* sweeps, double* rho,
                      double* history, hipStream_t stream);
 
+/* Algorithm 1 over a batch of B independent problems (slabs, parameter
+ * queries) sharing D, M and the patch size of each dim; grid sizes may
+ * differ.  d_U holds B*D factor pointers, problem-major (d_U[b*D + d]).
+ * Each dim step solves every active system in one launch (one workgroup
+ * per system, block LU on the matrix cores); after each sweep the host reads
+ * every problem's residual and backward errors and drops the problems that
+ * reached tol or broke down.  Host outputs: sweeps[b], rho[b] (NaN after a
+ * breakdown).  Synchronises the stream once per sweep.  Needs the matrix-core
+ * solve to fit LDS (TAPS_ERR_UNSUPPORTED otherwise). */
+taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* probs,
+                             double* const* d_U, double tol, int32_t iter_max, int32_t* sweeps,
+                             double* rho, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Kernel timing.  While enabled, each launch of a timed kernel family is
  * bracketed by HIP events recorded on the stream it runs on, and the

@@ -12,6 +12,7 @@ SOURCES = [
     "taps_contract.hip",
     "taps_solve.hip",
     "taps_sweep.hip",
+    "taps_batch.hip",
     "taps_reconstruct.hip",
     "taps_reconstruct_mfma.hip",
 ]

@@ -25,7 +25,7 @@ FUNCTIONS = (
     "taps_create", "taps_destroy", "taps_last_error", "taps_reserve", "taps_workspace_bytes",
     "taps_gauss_points", "taps_shape1d", "taps_source1d", "taps_assemble1d", "taps_contract",
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
-    "taps_reconstruct", "taps_profile_enable", "taps_profile_read",
+    "taps_reconstruct", "taps_profile_enable", "taps_profile_read", "taps_als_batched",
 )
 PROF_SOLVE, PROF_CONTRACT = 0, 1
 
@@ -82,6 +82,7 @@ def lib():
             "taps_interp1d": (i32, [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]),
             "taps_reconstruct": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
             "taps_profile_enable": (i32, [vp, i32]),
+            "taps_als_batched": (i32, [vp, i32, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), vp]),
             "taps_profile_read": (i32, [vp, i32, P(i32), P(dbl), P(dbl), P(dbl)]),
         }
         for name, (res, args) in sig.items():
@@ -233,3 +234,15 @@ def taps_profile_read(h: Handle, family: int):
 
 def last_error(h: Handle) -> str:
     return lib().taps_last_error(h.h).decode()
+
+
+def taps_als_batched(h: Handle, probs, Us, tol: float, iter_max: int, stream=None):
+    """Algorithm 1 over a batch.  probs: list of Problem; Us: list (per problem)
+    of factor tensor lists.  Returns (sweeps list, rho list)."""
+    B = len(probs)
+    arr = (Problem * B)(*probs)
+    ptrs = _ptr_array([u for U in Us for u in U])
+    sw = (C.c_int32 * B)()
+    rh = (C.c_double * B)()
+    h.check(lib().taps_als_batched(h.h, B, arr, ptrs, tol, iter_max, sw, rh, _stream(stream)), "taps_als_batched")
+    return list(sw), list(rh)

@@ -226,7 +226,7 @@ taps_status prepare_cache(taps_handle* h, const taps_problem_t* p, hipStream_t s
   for (int d = 0; same && d < p->D; ++d)
     same = h->sig_n[d] == p->n[d] && h->sig_k[d] == p->n_kinds[d] && h->sig_r[d] == p->R_cols[d];
   if (!same) {
-    h->cache_valid = 0;
+    h->gc.valid = 0;
     h->sig_D = p->D;
     h->sig_M = p->M;
     for (int d = 0; d < p->D; ++d) {
@@ -242,13 +242,14 @@ taps_status prepare_cache(taps_handle* h, const taps_problem_t* p, hipStream_t s
     TAPS_TRY(grow(h, &buf, &have, need, stream));
     h->cache = static_cast<double*>(buf);
     h->cache_bytes = have;
-    h->cache_valid = 0;
+    h->gc.valid = 0;
   }
+  h->gc.base = h->cache;
   return TAPS_OK;
 }
 
-taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask, const double* const* d_U,
-                          hipStream_t stream) {
+taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, taps_gram_cache* gc, uint32_t mask,
+                          const double* const* d_U, hipStream_t stream) {
   const int M = p->M;
   for (int e = 0; e < p->D; ++e) {
     if (!(mask & (1u << e))) continue;
@@ -263,8 +264,8 @@ taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask
     TAPS_TRY(need_ws(h, align256(part_g) + align256(part_l), stream));
     double* pg = static_cast<double*>(h->ws);
     double* pl = reinterpret_cast<double*>(static_cast<char*>(h->ws) + align256(part_g));
-    double* gram = h->cache + cache_gram_off(p, e) / 8;
-    double* lgram = h->cache + cache_lgram_off(p, e) / 8;
+    double* gram = gc->base + cache_gram_off(p, e) / 8;
+    double* lgram = gc->base + cache_lgram_off(p, e) / 8;
     const size_t lds = size_t(2 * kGramRows + 2 * w) * M * 8;
     TAPS_TRY(allow_lds(h, k_gram_partial, lds, &gram_lds_allowed));
     size_t slot;
@@ -287,13 +288,13 @@ taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask
       const double by = 8.0 * (double(n) * M + K * n * bw + double(n) * Rc + K * double(M) * M + double(Rc) * M);
       TAPS_TRY(prof_end(h, slot, fl, by, stream));
     }
-    h->cache_valid |= (1u << e);
+    gc->valid |= (1u << e);
   }
   return TAPS_OK;
 }
 
-taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, double* d_C, double* d_Q,
-                             hipStream_t stream) {
+taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, const taps_gram_cache* gc, int d,
+                             double* d_C, double* d_Q, hipStream_t stream) {
   const int M = p->M;
   CoupleArgs ca{};
   ca.D = p->D;
@@ -305,7 +306,7 @@ taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, dou
     ca.gamma[t] = p->gamma[t];
     for (int e = 0; e < p->D; ++e) ca.tk[t][e] = p->term_kind[t][e];
   }
-  for (int e = 0; e < p->D; ++e) ca.gram[e] = h->cache + cache_gram_off(p, e) / 8;
+  for (int e = 0; e < p->D; ++e) ca.gram[e] = gc->base + cache_gram_off(p, e) / 8;
   size_t slot;
   TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
   k_couple<<<cdiv(long(ca.Kd) * M * M, 256), 256, 0, stream>>>(ca, d_C);
@@ -321,7 +322,7 @@ taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, dou
   wa.d = d;
   wa.Rc = Rc;
   for (int e = 0; e < p->D; ++e) {
-    wa.lgram[e] = h->cache + cache_lgram_off(p, e) / 8;
+    wa.lgram[e] = gc->base + cache_lgram_off(p, e) / 8;
     wa.col[e] = p->d_load_col[e];
   }
   wa.ptr = p->d_load_ptr[d];
@@ -351,8 +352,8 @@ extern "C" taps_status taps_contract(taps_handle_t h, const taps_problem_t* prob
   TAPS_TRY(prepare_cache(h, prob, stream));
   const uint32_t all = (prob->D >= 32) ? 0xffffffffu : ((1u << prob->D) - 1u);
   const uint32_t need = all & ~(1u << d);
-  const uint32_t refresh = (stale_mask | ~h->cache_valid) & need;
-  TAPS_TRY(refresh_grams(h, prob, refresh, d_U, stream));
-  if (stale_mask & (1u << d)) h->cache_valid &= ~(1u << d);
-  return couple_and_force(h, prob, d, d_C, d_Q, stream);
+  const uint32_t refresh = (stale_mask | ~h->gc.valid) & need;
+  TAPS_TRY(refresh_grams(h, prob, &h->gc, refresh, d_U, stream));
+  if (stale_mask & (1u << d)) h->gc.valid &= ~(1u << d);
+  return couple_and_force(h, prob, &h->gc, d, d_C, d_Q, stream);
 }

@@ -182,6 +182,7 @@ taps_status taps_destroy(taps_handle_t h) {
   if (h->cache) (void)hipFree(h->cache);
   for (auto e : h->prof.ev) (void)hipEventDestroy(e);
   if (h->side) (void)hipFree(h->side);
+  if (h->batch) (void)hipFree(h->batch);
   if (h->d_small) (void)hipFree(h->d_small);
   delete h;
   return TAPS_OK;

@@ -13,14 +13,21 @@
 
 #include "../../include/taps.h"
 
+// Grams and load Grams of one problem (per dim e: n_kinds[e] M^2 Grams, then
+// R_cols[e] M load Grams) and which dims hold those of the current factors.
+struct taps_gram_cache {
+  double* base = nullptr;
+  uint32_t valid = 0;
+};
+
 struct taps_handle {
   // scratch: reused by every call (partial sums, solve factors, C/Q buffers)
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  // Gram cache: per dim e, n_kinds[e]*M*M Grams then R_cols[e]*M load Grams
+  // Gram cache of the single-problem calls
   double* cache = nullptr;
   size_t cache_bytes = 0;
-  uint32_t cache_valid = 0;  // bit e: cache of dim e holds Grams of the current factors
+  taps_gram_cache gc;
   // shape signature of the problem the cache belongs to
   int32_t sig_D = -1, sig_M = -1;
   int32_t sig_n[TAPS_MAX_DIMS] = {0}, sig_k[TAPS_MAX_DIMS] = {0}, sig_r[TAPS_MAX_DIMS] = {0};
@@ -29,6 +36,9 @@ struct taps_handle {
   size_t side_bytes = 0;
   // small fixed buffer: [0, 64) doubles residual output, then info words
   double* d_small = nullptr;
+  // batched driver region (per-problem caches, couplings, solve workspaces)
+  void* batch = nullptr;
+  size_t batch_bytes = 0;
   std::string err;
   int device = 0;
   // kernel timing (taps_profile_*)
@@ -132,15 +142,15 @@ taps_status check_problem(taps_handle* h, const taps_problem_t* p);
 
 // ---- cross-file entry points (implemented in the .hip files) --------------
 // Gram cache refresh for the dims in `mask`, given factors d_U.
-taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, uint32_t mask,
+taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, taps_gram_cache* gc, uint32_t mask,
                           const double* const* d_U, hipStream_t stream);
 // Offsets of dim e's Grams / load Grams inside h->cache.
 size_t cache_gram_off(const taps_problem_t* p, int e);
 size_t cache_lgram_off(const taps_problem_t* p, int e);
 size_t cache_total(const taps_problem_t* p);
 // Couplings + force of dim d from the cache (cache must be valid for e != d).
-taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, int d, double* d_C,
-                             double* d_Q, hipStream_t stream);
+taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, const taps_gram_cache* gc, int d,
+                             double* d_C, double* d_Q, hipStream_t stream);
 // Ensure the cache is sized and signed for problem p.
 taps_status prepare_cache(taps_handle* h, const taps_problem_t* p, hipStream_t stream);
 
@@ -152,6 +162,22 @@ int dim_residual_nparts(int n);
 taps_status dim_residual_parts(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
                                const double* d_U, const double* d_Q, double* parts, int* nparts,
                                hipStream_t stream);
+
+// Batched dim solve: one workgroup per system (all systems share M and s).
+size_t solve_args_bytes();
+size_t solve_ws_bytes(int n, int M, int s);
+void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_C, const double* d_Q,
+                     double* d_X, int* d_info, void* ws);
+bool solve_batched_supported(int M, int s);
+taps_status solve_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active,
+                                 int M, int s, double flops, double bytes, hipStream_t stream);
+taps_status berr_final_launch(taps_handle* h, int nparts, const double* parts, double* out, hipStream_t stream);
+double solve_flops(int n, int M, int w);
+double solve_bytes(int n, int M, int w, int K);
+
+taps_status balance_launch(taps_handle* h, const taps_problem_t* p, double* const* d_U, hipStream_t stream);
+taps_status residual_final_launch(taps_handle* h, int D, const int* nparts, double* const* parts, double* out,
+                                  hipStream_t stream);
 
 // Kernel timing helpers: bracket a launch with events when profiling is on.
 taps_status prof_begin(taps_handle* h, int family, hipStream_t stream, size_t* slot);

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 
 namespace {
 
@@ -235,7 +236,7 @@ __device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma(SolveArgs A) {
+__device__ void block_lu_mfma_body(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, w = 2 * A.s + 1, W1 = w + 1, n = A.n, wM = w * M;
   const int M4 = (M + 3) & ~3;
@@ -406,7 +407,17 @@ __global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma(SolveArgs A) {
   if (tid == 0) A.info[0] = s_info;
 }
 
+__global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma(SolveArgs A) { block_lu_mfma_body(A); }
+
+// Batched: one workgroup per (active) system; all share M and s, n may differ.
+__global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma_batched(const SolveArgs* __restrict__ args,
+                                                                        const int* __restrict__ active) {
+  const SolveArgs A = args[active[blockIdx.x]];
+  block_lu_mfma_body(A);
+}
+
 size_t lu_mfma_lds_allowed = 0;
+size_t lu_mfma_batched_lds_allowed = 0;
 
 
 constexpr int kResRows = 64;
@@ -599,6 +610,69 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
     k_berr_final<<<1, 64, 0, stream>>>(nb, parts, d_berr);
     TAPS_LAUNCHED(h, "k_berr_final");
   }
+  return TAPS_OK;
+}
+
+// ---- batched solve (used by the batched Algorithm-1 driver)
+size_t solve_args_bytes() { return sizeof(SolveArgs); }
+
+size_t solve_ws_bytes(int n, int M, int s) {
+  const int w = 2 * s + 1;
+  Bump bump;
+  bump.take(size_t(n) * M * w * M * 8);
+  bump.take(size_t(n) * M * 8);
+  bump.take(size_t(w + 1) * (w + 1) * M * M * 8);
+  bump.take(size_t(w + 1) * M * 8);
+  return bump.off;
+}
+
+// Fill the device argument record of one system into host memory `dst`
+// (sizeof(SolveArgs) bytes); `ws` is the system's own solve workspace.
+void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_C, const double* d_Q,
+                     double* d_X, int* d_info, void* ws) {
+  const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
+  Bump bump;
+  const size_t o_Z = bump.take(size_t(n) * M * w * M * 8);
+  const size_t o_Y = bump.take(size_t(n) * M * 8);
+  const size_t o_W = bump.take(size_t(w + 1) * (w + 1) * M * M * 8);
+  const size_t o_R = bump.take(size_t(w + 1) * M * 8);
+  char* base = static_cast<char*>(ws);
+  SolveArgs A;
+  A.n = n;
+  A.M = M;
+  A.s = s;
+  A.K = p->n_kinds[d];
+  A.band = p->d_band[d];
+  A.C = d_C;
+  A.Q = d_Q;
+  A.fixed = p->d_fixed[d];
+  A.X = d_X;
+  A.Zst = reinterpret_cast<double*>(base + o_Z);
+  A.Yst = reinterpret_cast<double*>(base + o_Y);
+  A.win = reinterpret_cast<double*>(base + o_W);
+  A.rhs = reinterpret_cast<double*>(base + o_R);
+  A.info = d_info;
+  memcpy(dst, &A, sizeof(A));
+}
+
+bool solve_batched_supported(int M, int s) { return solve_mfma_lds_bytes(M, s) <= 160 * 1024 - 64; }
+
+taps_status solve_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active,
+                                 int M, int s, double flops, double bytes, hipStream_t stream) {
+  const size_t lds = solve_mfma_lds_bytes(M, s);
+  TAPS_TRY(allow_lds(h, k_block_lu_mfma_batched, lds, &lu_mfma_batched_lds_allowed));
+  size_t slot;
+  TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+  k_block_lu_mfma_batched<<<n_active, kThreadsMfma, lds, stream>>>(static_cast<const SolveArgs*>(d_args),
+                                                                    d_active);
+  TAPS_LAUNCHED(h, "k_block_lu_mfma_batched");
+  TAPS_TRY(prof_end(h, slot, flops, bytes, stream));
+  return TAPS_OK;
+}
+
+taps_status berr_final_launch(taps_handle* h, int nparts, const double* parts, double* out, hipStream_t stream) {
+  k_berr_final<<<1, 64, 0, stream>>>(nparts, parts, out);
+  TAPS_LAUNCHED(h, "k_berr_final");
   return TAPS_OK;
 }
 

@@ -124,12 +124,12 @@ taps_status residual_impl(taps_handle* h, const taps_problem_t* p, const double*
   DriverBufs db;
   TAPS_TRY(driver_bufs(h, p, &db, stream));
   const uint32_t all = (1u << p->D) - 1u;
-  TAPS_TRY(refresh_grams(h, p, all, d_U, stream));
+  TAPS_TRY(refresh_grams(h, p, &h->gc, all, d_U, stream));
   ResFinal rf{};
   rf.D = p->D;
   int off = 0;
   for (int d = 0; d < p->D; ++d) {
-    TAPS_TRY(couple_and_force(h, p, d, db.C, db.Q, stream));
+    TAPS_TRY(couple_and_force(h, p, &h->gc, d, db.C, db.Q, stream));
     int nb = 0;
     TAPS_TRY(dim_residual_parts(h, p, d, db.C, d_U[d], db.Q, db.parts + 2 * off, &nb, stream));
     rf.nparts[d] = nb;
@@ -151,7 +151,7 @@ taps_status balance_impl(taps_handle* h, const taps_problem_t* p, double* const*
   }
   k_balance<<<p->M, 256, 0, stream>>>(ba);
   TAPS_LAUNCHED(h, "k_balance");
-  h->cache_valid = 0;  // every Gram changes scale
+  h->gc.valid = 0;  // every Gram changes scale
   return TAPS_OK;
 }
 
@@ -161,13 +161,13 @@ taps_status sweep_impl(taps_handle* h, const taps_problem_t* p, double* const* d
   DriverBufs db;
   TAPS_TRY(driver_bufs(h, p, &db, stream));
   const uint32_t all = (1u << p->D) - 1u;
-  h->cache_valid = 0;  // the factors passed in need not be those the cache was built from
+  h->gc.valid = 0;  // the factors passed in need not be those the cache was built from
   for (int d = 0; d < p->D; ++d) {
     const uint32_t need = all & ~(1u << d);
-    TAPS_TRY(refresh_grams(h, p, need & ~h->cache_valid, d_U, stream));
-    TAPS_TRY(couple_and_force(h, p, d, db.C, db.Q, stream));
+    TAPS_TRY(refresh_grams(h, p, &h->gc, need & ~h->gc.valid, d_U, stream));
+    TAPS_TRY(couple_and_force(h, p, &h->gc, d, db.C, db.Q, stream));
     TAPS_TRY(solve_dim_impl(h, p, d, db.C, db.Q, d_U[d], db.infos + d, (d_berr ? d_berr : db.berr) + d, stream));
-    h->cache_valid &= ~(1u << d);
+    h->gc.valid &= ~(1u << d);
   }
   TAPS_TRY(balance_impl(h, p, d_U, stream));
   if (d_info) {
@@ -176,6 +176,41 @@ taps_status sweep_impl(taps_handle* h, const taps_problem_t* p, double* const* d
   }
   return TAPS_OK;
 }
+
+}  // namespace
+
+namespace taps {
+
+// Launchers shared with the batched driver.
+taps_status balance_launch(taps_handle* h, const taps_problem_t* p, double* const* d_U, hipStream_t stream) {
+  BalanceArgs ba{};
+  ba.D = p->D;
+  ba.M = p->M;
+  for (int d = 0; d < p->D; ++d) {
+    ba.n[d] = p->n[d];
+    ba.U[d] = d_U[d];
+  }
+  k_balance<<<p->M, 256, 0, stream>>>(ba);
+  TAPS_LAUNCHED(h, "k_balance");
+  return TAPS_OK;
+}
+
+taps_status residual_final_launch(taps_handle* h, int D, const int* nparts, double* const* parts, double* out,
+                                  hipStream_t stream) {
+  ResFinal rf{};
+  rf.D = D;
+  for (int d = 0; d < D; ++d) {
+    rf.nparts[d] = nparts[d];
+    rf.part[d] = parts[d];
+  }
+  k_residual_final<<<1, 64, 0, stream>>>(rf, out);
+  TAPS_LAUNCHED(h, "k_residual_final");
+  return TAPS_OK;
+}
+
+}  // namespace taps
+
+namespace {
 
 taps_status check_factors(taps_handle* h, const taps_problem_t* p, const void* const* d_U) {
   if (!d_U) return fail(h, TAPS_ERR_INVALID, "factor array is null");

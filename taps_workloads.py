@@ -124,6 +124,21 @@ def heat_slab_batch(batch: int = 64, n_lo: int = 64, n_hi: int = 1024,
     return out
 
 
+def heat_slab_family(batch: int = 64, seed: int = 4, **grid):
+    """Independent heat slabs on one grid (default 512x512x128x257, M=40):
+    per slab power, radius, conductivity and track offset drawn like the uneven
+    batch, so the slabs stand for parameter queries or separate tracks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(batch):
+        P = float(rng.uniform(100.0, 300.0))
+        r = float(rng.uniform(0.030, 0.080))
+        k = float(rng.uniform(0.010, 0.030))
+        y0 = float(rng.uniform(0.3, 0.7))
+        out.append(heat_slab(seed=seed * 100003 + b, power=P, radius=r, k=k, y0=y0, **grid))
+    return out
+
+
 def initial_factors(axes, M: int, seed: int):
     """Random initial mode factors U_d ~ N(0,1) (n_d x M, float64, row-major),
     one PCG64 stream per problem, dims drawn in order; rows of fixed nodes are 0."""

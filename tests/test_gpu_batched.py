@@ -1,0 +1,94 @@
+"""Batched Algorithm 1: every problem of a batch must give what the
+single-problem path (and the oracle) gives on its own, including problems of
+different grid sizes and problems that converge at different sweeps."""
+import math
+
+import numpy as np
+import pytest
+
+import taps_workloads as W
+from oracle import als, problems, separated
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+@pytest.fixture(scope="module")
+def env(taps_lib):
+    import torch
+    from paper_2503_13933_amd import capi, problem
+    h = capi.Handle()
+    yield torch, capi, problem, h
+    h.close()
+
+
+def test_uneven_batch_matches_single_and_oracle(env):
+    torch, capi, problem, h = env
+    cases = [W.heat_slab(40, 33, 10, 21, M=6, seed=11),
+             W.heat_slab(67, 70, 13, 9, M=6, seed=12, power=120.0, radius=0.07),
+             W.heat_slab(24, 20, 12, 17, M=6, seed=13, k=0.012, y0=0.35)]
+    _say("batched: 3 uneven heat slabs, M=6, 2 sweeps")
+    devs = [problem.heat_slab(h, c) for c in cases]
+    U0 = [W.initial_factors(c.axes, c.M, c.seed) for c in cases]
+    Ub = [d.factors(u) for d, u in zip(devs, U0)]
+    sweeps, rhos = capi.taps_als_batched(h, [d.struct for d in devs], Ub, 0.0, 2)
+    torch.cuda.synchronize()
+    assert sweeps == [2, 2, 2]
+    for c, d, u0, ub, rb in zip(cases, devs, U0, Ub, rhos):
+        Us = d.factors(u0)
+        sw, rs, _ = capi.taps_als(h, d.struct, Us, 0.0, 2)
+        torch.cuda.synchronize()
+        ora = problems.heat_slab(c)
+        Uo = [u.copy() for u in u0]
+        for _ in range(2):
+            als.sweep(ora, Uo)
+            als.balance(Uo)
+        ro = separated.residual_norm(ora, Uo)
+        for a, b_, o in zip(ub, Us, Uo):
+            assert rel(a.cpu().numpy(), b_.cpu().numpy()) < 1e-12
+            assert rel(a.cpu().numpy(), o) < 1e-9
+        assert abs(rb - rs) <= 1e-12 * rs
+        assert abs(rb - ro) <= 1e-8 * ro
+        _say(f"  n={[a.n for a in c.axes]} rho batched {rb:.6e} single {rs:.6e} oracle {ro:.6e}")
+
+
+def test_batch_predicates_converged_problems(env):
+    # a rank-one manufactured heat field converges in a few sweeps; a Gaussian
+    # slab with M = 1 needs many: each must stop at its own sweep count and
+    # agree with its single-problem run
+    torch, capi, problem, h = env
+    cpoly = W.heat_slab(9, 8, 10, 7, M=1, seed=5)
+    cgauss = W.heat_slab(24, 20, 12, 17, M=1, seed=7)
+    _say("batched predication: polynomial + gaussian, M=1, tol 1e-10")
+    dpoly = problem.heat_polynomial(h, cpoly)
+    dg = problem.heat_slab(h, cgauss)
+    u0 = [W.initial_factors(cpoly.axes, 1, 5), W.initial_factors(cgauss.axes, 1, 7)]
+    Ub = [dpoly.factors(u0[0]), dg.factors(u0[1])]
+    sweeps, rhos = capi.taps_als_batched(h, [dpoly.struct, dg.struct], Ub, 1e-10, 60)
+    torch.cuda.synchronize()
+    singles = []
+    for d, u in zip([dpoly, dg], u0):
+        U = d.factors(u)
+        singles.append(capi.taps_als(h, d.struct, U, 1e-10, 60)[:2])
+    _say(f"  batched sweeps {sweeps} rho {rhos}; single {singles}")
+    assert sweeps[0] == singles[0][0] and sweeps[1] == singles[1][0]
+    assert sweeps[0] < sweeps[1]
+    for rb, (sw, rs) in zip(rhos, singles):
+        assert abs(rb - rs) <= 1e-9 * rs + 1e-15
+
+
+def test_batch_rejects_mismatched_modes(env):
+    torch, capi, problem, h = env
+    a = problem.heat_slab(h, W.heat_slab(8, 7, 6, 7, M=3))
+    b = problem.heat_slab(h, W.heat_slab(8, 7, 6, 7, M=4))
+    Ua = a.factors(W.initial_factors([x.ax for x in a.axes], 3, 1))
+    Ub = b.factors(W.initial_factors([x.ax for x in b.axes], 4, 1))
+    with pytest.raises(capi.TapsError):
+        capi.taps_als_batched(h, [a.struct, b.struct], [Ua, Ub], 0.0, 1)
