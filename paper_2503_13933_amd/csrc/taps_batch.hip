@@ -1,22 +1,139 @@
 // Batched Algorithm 1 (paper Sec. 2.6) over many independent problems --
 // slabs, parameter queries -- that share D, M and the patch size of each dim
-// (grid sizes may differ).  Every dim step solves all active systems in one
-// launch, one workgroup per system; problems that reach the tolerance (or
-// break down) are predicated off on the host after each sweep.
-#include "taps_internal.hpp"
+// (grid sizes may differ).  Every step of a sweep is one launch over all
+// active problems (the problem is the last grid coordinate): Gram refreshes,
+// couplings, forces, the block-LU solves (one workgroup per system), the
+// backward-error check, balancing and the residual.  Problems that reach the
+// tolerance or break down are predicated off on the host after each sweep by
+// shrinking the active list.
+#include "taps_device.hpp"
 
 #include <algorithm>
 #include <cstring>
 #include <vector>
 
 using namespace taps;
+using namespace taps::dev;
 
 namespace {
 
-struct ProbLayout {
-  size_t cache, C, Q, ws, parts, out, info;  // byte offsets in the batch buffer
-  int nparts[TAPS_MAX_DIMS];
-  int part_off[TAPS_MAX_DIMS];              // in units of 2 doubles
+// Device record of one problem of the batch.
+struct BProb {
+  int D, M;
+  int n[TAPS_MAX_DIMS], s[TAPS_MAX_DIMS], K[TAPS_MAX_DIMS], Rc[TAPS_MAX_DIMS];
+  const double* band[TAPS_MAX_DIMS];
+  const double* F[TAPS_MAX_DIMS];
+  const uint8_t* fixed[TAPS_MAX_DIMS];
+  double* U[TAPS_MAX_DIMS];
+  double* gram[TAPS_MAX_DIMS];
+  double* lgram[TAPS_MAX_DIMS];
+  int roff[TAPS_MAX_DIMS];  // residual partial offset of dim d (units of 2 doubles)
+  double* C;
+  double* Q;
+  double* Wt;
+  double* gpart;
+  double* lpart;
+  double* rparts;
+  double* outs;  // res (D+2), then backward error per dim (D)
+};
+
+__global__ void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
+  const BProb& q = P[act[blockIdx.y]];
+  const int n = q.n[e];
+  if (int(blockIdx.x) * kGramRows >= n) return;
+  gram_partial(blockIdx.x, n, q.M, q.s[e], q.K[e], q.band[e], q.U[e],
+               q.gpart + long(blockIdx.x) * q.K[e] * q.M * q.M);
+}
+
+__global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
+  const BProb& q = P[act[blockIdx.y]];
+  const int chunks = (q.n[e] + kGramRows - 1) / kGramRows;
+  sum_parts(blockIdx.x, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
+}
+
+__global__ void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
+  const BProb& q = P[act[blockIdx.z]];
+  if (int(blockIdx.x) * kLgCols >= q.Rc[e] || int(blockIdx.y) * kLgRows >= q.n[e]) return;
+  lgram_partial(blockIdx.x, blockIdx.y, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
+}
+
+__global__ void kb_lgram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
+  const BProb& q = P[act[blockIdx.y]];
+  const int splits = (q.n[e] + kLgRows - 1) / kLgRows;
+  sum_parts(blockIdx.x, splits, long(q.Rc[e]) * q.M, q.lpart, q.lgram[e]);
+}
+
+__global__ void kb_couple(const BProb* __restrict__ P, const CoupleArgs* __restrict__ CA,
+                          const int* __restrict__ act, int d, int D) {
+  const int b = act[blockIdx.y];
+  couple(blockIdx.x, CA[long(b) * D + d], P[b].C);
+}
+
+__global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* __restrict__ WA,
+                                const int* __restrict__ act, int d, int D) {
+  const int b = act[blockIdx.y];
+  load_weights(blockIdx.x, WA[long(b) * D + d], P[b].Wt);
+}
+
+__global__ void kb_force(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
+  const BProb& q = P[act[blockIdx.y]];
+  if (int(blockIdx.x) * kQRows >= q.n[d]) return;
+  force(blockIdx.x, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
+}
+
+__global__ void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
+  const BProb& q = P[act[blockIdx.y]];
+  if (int(blockIdx.x) * kResRows >= q.n[d]) return;
+  residual_part(blockIdx.x, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
+                q.rparts + 2 * (q.roff[d] + blockIdx.x));
+}
+
+// One thread per active problem: backward error of dim d from its partials.
+__global__ void kb_berr_final(const BProb* __restrict__ P, const int* __restrict__ act, int nact, int d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nact) return;
+  const BProb& q = P[act[i]];
+  const int nb = (q.n[d] + kResRows - 1) / kResRows;
+  const double* part = q.rparts + 2 * q.roff[d];
+  double r = 0.0, s = 0.0;
+  for (int c = 0; c < nb; ++c) {
+    r += part[2 * c];
+    s += part[2 * c + 1];
+  }
+  q.outs[q.D + 2 + d] = s > 0.0 ? sqrt(r / s) : sqrt(r);
+}
+
+// One thread per active problem: per-dim ||R_d||^2, sum ||Q_d||^2 and rho.
+__global__ void kb_residual_final(const BProb* __restrict__ P, const int* __restrict__ act, int nact) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nact) return;
+  const BProb& q = P[act[i]];
+  double rs = 0.0, qs = 0.0;
+  for (int d = 0; d < q.D; ++d) {
+    const int nb = (q.n[d] + kResRows - 1) / kResRows;
+    const double* part = q.rparts + 2 * q.roff[d];
+    double r = 0.0, s = 0.0;
+    for (int c = 0; c < nb; ++c) {
+      r += part[2 * c];
+      s += part[2 * c + 1];
+    }
+    q.outs[d] = r;
+    rs += r;
+    qs += s;
+  }
+  q.outs[q.D] = qs;
+  q.outs[q.D + 1] = qs > 0.0 ? sqrt(rs / qs) : sqrt(rs);
+}
+
+__global__ void kb_balance(const BalanceArgs* __restrict__ BA, const int* __restrict__ act) {
+  balance(blockIdx.x, BA[act[blockIdx.y]]);
+}
+
+size_t gram_lds_allowed = 0, res_lds_allowed = 0;
+
+struct Sizes {
+  int max_chunks = 1, max_ctiles = 1, max_splits = 1, max_gram = 1, max_lgram = 1, max_rblocks = 1;
+  int max_cpl = 1, max_wt = 1, max_rchunks = 1;
 };
 
 }  // namespace
@@ -38,103 +155,235 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       if (!d_U[size_t(b) * p.D + d]) return fail(h, TAPS_ERR_INVALID, "problem %d factor %d is null", b, d);
     }
   }
-  const int D = p0.D, M = p0.M;
+  const int D = p0.D, M = p0.M, MM = M * M;
   for (int d = 0; d < D; ++d)
     if (!solve_batched_supported(M, p0.s[d]))
       return fail(h, TAPS_ERR_UNSUPPORTED, "batched solve needs M=%d, s=%d to fit LDS", M, p0.s[d]);
 
   // ---- layout of the batch buffer
   const size_t args_sz = solve_args_bytes();
+  Sizes Z;
   Bump bump;
   const size_t o_args = bump.take(args_sz * size_t(D) * B);
+  const size_t o_prob = bump.take(sizeof(BProb) * size_t(B));
+  const size_t o_cpl = bump.take(sizeof(CoupleArgs) * size_t(B) * D);
+  const size_t o_wa = bump.take(sizeof(WeightArgs) * size_t(B) * D);
+  const size_t o_bal = bump.take(sizeof(BalanceArgs) * size_t(B));
   const size_t o_active = bump.take(size_t(B) * 4);
   const size_t o_outs = bump.take(size_t(B) * (2 * D + 2) * 8);
   const size_t o_infos = bump.take(size_t(B) * D * 4);
-  std::vector<ProbLayout> L(B);
+  std::vector<BProb> bp(B);
+  std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B);
   for (int b = 0; b < B; ++b) {
     const taps_problem_t& p = probs[b];
     int Kmax = 1, nmax = 1, tot = 0;
-    size_t ws = 0;
+    size_t ws = 0, gp = 0, lp = 0, wt = 0;
     for (int d = 0; d < D; ++d) {
+      const int ch = cdiv(p.n[d], kGramRows), ct = cdiv(p.R_cols[d], kLgCols), sp = cdiv(p.n[d], kLgRows);
       Kmax = std::max(Kmax, p.n_kinds[d]);
       nmax = std::max(nmax, p.n[d]);
       ws = std::max(ws, solve_ws_bytes(p.n[d], M, p.s[d]));
-      L[b].nparts[d] = dim_residual_nparts(p.n[d]);
-      L[b].part_off[d] = tot;
-      tot += L[b].nparts[d];
+      gp = std::max(gp, size_t(ch) * p.n_kinds[d] * MM * 8);
+      lp = std::max(lp, size_t(sp) * p.R_cols[d] * M * 8);
+      wt = std::max(wt, size_t(p.R_cols[d]) * M * 8);
+      bp[b].roff[d] = tot;
+      tot += cdiv(p.n[d], kResRows);
+      Z.max_chunks = std::max(Z.max_chunks, ch);
+      Z.max_ctiles = std::max(Z.max_ctiles, ct);
+      Z.max_splits = std::max(Z.max_splits, sp);
+      Z.max_gram = std::max(Z.max_gram, cdiv(long(p.n_kinds[d]) * MM, 256));
+      Z.max_lgram = std::max(Z.max_lgram, cdiv(long(p.R_cols[d]) * M, 256));
+      Z.max_rblocks = std::max(Z.max_rblocks, cdiv(p.n[d], kQRows));
+      Z.max_cpl = std::max(Z.max_cpl, cdiv(long(p.n_kinds[d]) * MM, 256));
+      Z.max_wt = std::max(Z.max_wt, cdiv(long(p.R_cols[d]) * M, 256));
+      Z.max_rchunks = std::max(Z.max_rchunks, cdiv(p.n[d], kResRows));
     }
-    L[b].cache = bump.take(cache_total(&p));
-    L[b].C = bump.take(size_t(Kmax) * M * M * 8);
-    L[b].Q = bump.take(size_t(nmax) * M * 8);
-    L[b].ws = bump.take(ws);
-    L[b].parts = bump.take(size_t(tot) * 2 * 8);
+    o_cache[b] = bump.take(cache_total(&p));
+    o_C[b] = bump.take(size_t(Kmax) * MM * 8);
+    o_Q[b] = bump.take(size_t(nmax) * M * 8);
+    o_Wt[b] = bump.take(wt);
+    o_gp[b] = bump.take(gp);
+    o_lp[b] = bump.take(lp);
+    o_rp[b] = bump.take(size_t(tot) * 2 * 8);
+    o_ws[b] = bump.take(ws);
   }
   TAPS_TRY(grow(h, &h->batch, &h->batch_bytes, bump.off, stream));
   char* base = static_cast<char*>(h->batch);
-  double* outs = reinterpret_cast<double*>(base + o_outs);  // [b]: res (D+2), berr (D)
-  int* infos = reinterpret_cast<int*>(base + o_infos);       // [b][d]
+  double* outs = reinterpret_cast<double*>(base + o_outs);
+  int* infos = reinterpret_cast<int*>(base + o_infos);
   int* d_active = reinterpret_cast<int*>(base + o_active);
-  auto C_of = [&](int b) { return reinterpret_cast<double*>(base + L[b].C); };
-  auto Q_of = [&](int b) { return reinterpret_cast<double*>(base + L[b].Q); };
-  auto parts_of = [&](int b) { return reinterpret_cast<double*>(base + L[b].parts); };
-  auto U_of = [&](int b) { return d_U + size_t(b) * D; };
+  const BProb* d_prob = reinterpret_cast<const BProb*>(base + o_prob);
+  const CoupleArgs* d_cpl = reinterpret_cast<const CoupleArgs*>(base + o_cpl);
+  const WeightArgs* d_wa = reinterpret_cast<const WeightArgs*>(base + o_wa);
+  const BalanceArgs* d_bal = reinterpret_cast<const BalanceArgs*>(base + o_bal);
 
-  // solve argument records for every (dim, problem)
+  // ---- device records (host staging kept alive until the copies are synchronised)
   std::vector<char> args(args_sz * size_t(D) * B);
-  for (int d = 0; d < D; ++d)
-    for (int b = 0; b < B; ++b)
-      solve_args_fill(args.data() + (size_t(d) * B + b) * args_sz, &probs[b], d, C_of(b), Q_of(b),
-                      U_of(b)[d], infos + size_t(b) * D + d, base + L[b].ws);
-  TAPS_HIP(h, hipMemcpyAsync(base + o_args, args.data(), args.size(), hipMemcpyHostToDevice, stream));
-
-  std::vector<taps_gram_cache> gc(B);
-  for (int b = 0; b < B; ++b) gc[b].base = reinterpret_cast<double*>(base + L[b].cache);
+  std::vector<CoupleArgs> cpl(size_t(B) * D);
+  std::vector<WeightArgs> wa(size_t(B) * D);
+  std::vector<BalanceArgs> bal(B);
+  for (int b = 0; b < B; ++b) {
+    const taps_problem_t& p = probs[b];
+    BProb& q = bp[b];
+    double* cache = reinterpret_cast<double*>(base + o_cache[b]);
+    q.D = D;
+    q.M = M;
+    for (int d = 0; d < D; ++d) {
+      q.n[d] = p.n[d];
+      q.s[d] = p.s[d];
+      q.K[d] = p.n_kinds[d];
+      q.Rc[d] = p.R_cols[d];
+      q.band[d] = p.d_band[d];
+      q.F[d] = p.d_F[d];
+      q.fixed[d] = p.d_fixed[d];
+      q.U[d] = d_U[size_t(b) * D + d];
+      q.gram[d] = cache + cache_gram_off(&p, d) / 8;
+      q.lgram[d] = cache + cache_lgram_off(&p, d) / 8;
+    }
+    q.C = reinterpret_cast<double*>(base + o_C[b]);
+    q.Q = reinterpret_cast<double*>(base + o_Q[b]);
+    q.Wt = reinterpret_cast<double*>(base + o_Wt[b]);
+    q.gpart = reinterpret_cast<double*>(base + o_gp[b]);
+    q.lpart = reinterpret_cast<double*>(base + o_lp[b]);
+    q.rparts = reinterpret_cast<double*>(base + o_rp[b]);
+    q.outs = outs + size_t(b) * (2 * D + 2);
+    for (int d = 0; d < D; ++d) {
+      CoupleArgs& ca = cpl[size_t(b) * D + d];
+      ca = CoupleArgs{};
+      ca.D = D;
+      ca.M = M;
+      ca.T = p.T;
+      ca.d = d;
+      ca.Kd = p.n_kinds[d];
+      for (int t = 0; t < p.T; ++t) {
+        ca.gamma[t] = p.gamma[t];
+        for (int e = 0; e < D; ++e) ca.tk[t][e] = p.term_kind[t][e];
+      }
+      for (int e = 0; e < D; ++e) ca.gram[e] = q.gram[e];
+      WeightArgs& w = wa[size_t(b) * D + d];
+      w = WeightArgs{};
+      w.D = D;
+      w.M = M;
+      w.R = p.R;
+      w.d = d;
+      w.Rc = p.R_cols[d];
+      for (int e = 0; e < D; ++e) {
+        w.lgram[e] = q.lgram[e];
+        w.col[e] = p.d_load_col[e];
+      }
+      w.ptr = p.d_load_ptr[d];
+      w.idx = p.d_load_idx[d];
+      solve_args_fill(args.data() + (size_t(d) * B + b) * args_sz, &p, d, q.C, q.Q, q.U[d],
+                      infos + size_t(b) * D + d, base + o_ws[b]);
+    }
+    bal[b] = BalanceArgs{};
+    bal[b].D = D;
+    bal[b].M = M;
+    for (int d = 0; d < D; ++d) {
+      bal[b].n[d] = p.n[d];
+      bal[b].U[d] = q.U[d];
+    }
+  }
   std::vector<int> active(B), next;
   for (int b = 0; b < B; ++b) {
     active[b] = b;
     sweeps[b] = 0;
     rho[b] = NAN;
   }
+  TAPS_HIP(h, hipMemcpyAsync(base + o_args, args.data(), args.size(), hipMemcpyHostToDevice, stream));
+  TAPS_HIP(h, hipMemcpyAsync(base + o_prob, bp.data(), sizeof(BProb) * B, hipMemcpyHostToDevice, stream));
+  TAPS_HIP(h, hipMemcpyAsync(base + o_cpl, cpl.data(), sizeof(CoupleArgs) * cpl.size(), hipMemcpyHostToDevice,
+                             stream));
+  TAPS_HIP(h, hipMemcpyAsync(base + o_wa, wa.data(), sizeof(WeightArgs) * wa.size(), hipMemcpyHostToDevice,
+                             stream));
+  TAPS_HIP(h, hipMemcpyAsync(base + o_bal, bal.data(), sizeof(BalanceArgs) * B, hipMemcpyHostToDevice, stream));
   TAPS_HIP(h, hipMemcpyAsync(d_active, active.data(), size_t(B) * 4, hipMemcpyHostToDevice, stream));
+  TAPS_HIP(h, hipStreamSynchronize(stream));
+
+  const size_t glds = size_t(gram_lds_doubles(M, *std::max_element(p0.s, p0.s + D))) * 8;
+  const size_t rlds = size_t(residual_lds_doubles(M, *std::max_element(p0.s, p0.s + D))) * 8;
+  if (rlds > 160 * 1024 - 4096) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", rlds);
+  TAPS_TRY(allow_lds(h, kb_gram_partial, glds, &gram_lds_allowed));
+  TAPS_TRY(allow_lds(h, kb_residual_part, rlds, &res_lds_allowed));
+
+  auto refresh = [&](int e, int nact) -> taps_status {
+    size_t slot;
+    TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
+    kb_gram_partial<<<dim3(Z.max_chunks, nact), 256, glds, stream>>>(d_prob, d_active, e);
+    TAPS_LAUNCHED(h, "kb_gram_partial");
+    kb_gram_sum<<<dim3(Z.max_gram, nact), 256, 0, stream>>>(d_prob, d_active, e);
+    TAPS_LAUNCHED(h, "kb_gram_sum");
+    kb_lgram_partial<<<dim3(Z.max_ctiles, Z.max_splits, nact), 256, 0, stream>>>(d_prob, d_active, e);
+    TAPS_LAUNCHED(h, "kb_lgram_partial");
+    kb_lgram_sum<<<dim3(Z.max_lgram, nact), 256, 0, stream>>>(d_prob, d_active, e);
+    TAPS_LAUNCHED(h, "kb_lgram_sum");
+    double fl = 0.0, by = 0.0;
+    for (int b : active) {
+      const taps_problem_t& p = probs[b];
+      const double n = p.n[e], K = p.n_kinds[e], Rc = p.R_cols[e], bw = 4 * p.s[e] + 3;
+      fl += K * (2.0 * bw * n * M + 2.0 * n * M * M) + 2.0 * n * Rc * M;
+      by += 8.0 * (n * M + K * n * bw + n * Rc + K * MM + Rc * M);
+    }
+    return prof_end(h, slot, fl, by, stream);
+  };
+  auto system = [&](int d, int nact) -> taps_status {
+    size_t slot;
+    TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
+    kb_couple<<<dim3(Z.max_cpl, nact), 256, 0, stream>>>(d_prob, d_cpl, d_active, d, D);
+    TAPS_LAUNCHED(h, "kb_couple");
+    kb_load_weights<<<dim3(Z.max_wt, nact), 256, 0, stream>>>(d_prob, d_wa, d_active, d, D);
+    TAPS_LAUNCHED(h, "kb_load_weights");
+    kb_force<<<dim3(Z.max_rblocks, nact), 256, 0, stream>>>(d_prob, d_active, d);
+    TAPS_LAUNCHED(h, "kb_force");
+    double fl = 0.0, by = 0.0;
+    for (int b : active) {
+      const taps_problem_t& p = probs[b];
+      const double n = p.n[d], Rc = p.R_cols[d];
+      fl += 2.0 * n * Rc * M;
+      by += 8.0 * (n * Rc + Rc * M + n * M);
+    }
+    return prof_end(h, slot, fl, by, stream);
+  };
+  auto residual_parts = [&](int d, int nact) -> taps_status {
+    kb_residual_part<<<dim3(Z.max_rchunks, nact), 256, rlds, stream>>>(d_prob, d_active, d);
+    TAPS_LAUNCHED(h, "kb_residual_part");
+    return TAPS_OK;
+  };
+
   std::vector<double> h_outs(size_t(B) * (2 * D + 2));
   std::vector<int> h_infos(size_t(B) * D);
   const uint32_t all = (1u << D) - 1u;
-
   for (int it = 0; it < iter_max && !active.empty(); ++it) {
-    for (int b : active) gc[b].valid = 0;
+    const int nact = int(active.size());
+    uint32_t valid = 0;
     for (int d = 0; d < D; ++d) {
-      const uint32_t need = all & ~(1u << d);
+      const uint32_t stale = (all & ~(1u << d)) & ~valid;
+      for (int e = 0; e < D; ++e)
+        if (stale & (1u << e)) TAPS_TRY(refresh(e, nact));
+      valid |= stale;
+      TAPS_TRY(system(d, nact));
       double fl = 0.0, by = 0.0;
       for (int b : active) {
         const taps_problem_t& p = probs[b];
-        TAPS_TRY(refresh_grams(h, &p, &gc[b], need & ~gc[b].valid, U_of(b), stream));
-        TAPS_TRY(couple_and_force(h, &p, &gc[b], d, C_of(b), Q_of(b), stream));
         fl += solve_flops(p.n[d], M, 2 * p.s[d] + 1);
         by += solve_bytes(p.n[d], M, 2 * p.s[d] + 1, p.n_kinds[d]);
       }
-      TAPS_TRY(solve_batched_launch(h, int(active.size()), base + o_args + size_t(d) * B * args_sz, d_active, M,
-                                    p0.s[d], fl, by, stream));
-      for (int b : active) {
-        gc[b].valid &= ~(1u << d);
-        int nb = 0;
-        TAPS_TRY(dim_residual_parts(h, &probs[b], d, C_of(b), U_of(b)[d], Q_of(b), parts_of(b), &nb, stream));
-        TAPS_TRY(berr_final_launch(h, nb, parts_of(b), outs + size_t(b) * (2 * D + 2) + (D + 2) + d, stream));
-      }
+      TAPS_TRY(solve_batched_launch(h, nact, base + o_args + size_t(d) * B * args_sz, d_active, M, p0.s[d], fl,
+                                    by, stream));
+      valid &= ~(1u << d);
+      TAPS_TRY(residual_parts(d, nact));
+      kb_berr_final<<<cdiv(nact, 64), 64, 0, stream>>>(d_prob, d_active, nact, d);
+      TAPS_LAUNCHED(h, "kb_berr_final");
     }
-    for (int b : active) {
-      const taps_problem_t& p = probs[b];
-      TAPS_TRY(balance_launch(h, &p, U_of(b), stream));
-      gc[b].valid = 0;
-      TAPS_TRY(refresh_grams(h, &p, &gc[b], all, U_of(b), stream));
-      double* parts[TAPS_MAX_DIMS];
-      for (int d = 0; d < D; ++d) {
-        TAPS_TRY(couple_and_force(h, &p, &gc[b], d, C_of(b), Q_of(b), stream));
-        parts[d] = parts_of(b) + 2 * L[b].part_off[d];
-        int nb = 0;
-        TAPS_TRY(dim_residual_parts(h, &p, d, C_of(b), U_of(b)[d], Q_of(b), parts[d], &nb, stream));
-      }
-      TAPS_TRY(residual_final_launch(h, D, L[b].nparts, parts, outs + size_t(b) * (2 * D + 2), stream));
+    kb_balance<<<dim3(M, nact), 256, 0, stream>>>(d_bal, d_active);
+    TAPS_LAUNCHED(h, "kb_balance");
+    for (int e = 0; e < D; ++e) TAPS_TRY(refresh(e, nact));
+    for (int d = 0; d < D; ++d) {
+      TAPS_TRY(system(d, nact));
+      TAPS_TRY(residual_parts(d, nact));
     }
+    kb_residual_final<<<cdiv(nact, 64), 64, 0, stream>>>(d_prob, d_active, nact);
+    TAPS_LAUNCHED(h, "kb_residual_final");
     TAPS_HIP(h, hipMemcpyAsync(h_outs.data(), outs, h_outs.size() * 8, hipMemcpyDeviceToHost, stream));
     TAPS_HIP(h, hipMemcpyAsync(h_infos.data(), infos, h_infos.size() * 4, hipMemcpyDeviceToHost, stream));
     TAPS_HIP(h, hipStreamSynchronize(stream));
@@ -148,11 +397,11 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       rho[b] = broke ? NAN : o[D + 1];
       if (!broke && rho[b] > tol) next.push_back(b);
     }
-    if (next.size() != active.size() && !next.empty())
+    if (next.size() != active.size() && !next.empty()) {
       TAPS_HIP(h, hipMemcpyAsync(d_active, next.data(), next.size() * 4, hipMemcpyHostToDevice, stream));
+      TAPS_HIP(h, hipStreamSynchronize(stream));
+    }
     active.swap(next);
-    // keep the staged active list alive until the copy has run
-    TAPS_HIP(h, hipStreamSynchronize(stream));
   }
   return TAPS_OK;
 }

@@ -3,205 +3,33 @@
 // M x M coefficient matrices that multiply entrywise; the forcing term gives
 // Q^[d]).  All reductions are two-stage with a fixed summation order, so two
 // runs give bitwise equal results.
-#include "taps_internal.hpp"
+#include "taps_device.hpp"
 
 namespace {
 
-constexpr int kGramRows = 64;   // rows of U per Gram partial block
-constexpr int kLgCols = 64;     // load columns per load-Gram block
-constexpr int kLgRows = 256;    // rows per load-Gram split
-constexpr int kLgStage = 32;    // rows staged in LDS at a time
-constexpr int kQRows = 64;      // rows of Q per force block
-constexpr int kQStage = 32;     // load columns staged in LDS at a time
+using namespace taps::dev;
 
-// Stage 1 of G^k = U^T A^k U: one block per chunk of kGramRows rows.  The chunk
-// of U plus a halo of w rows each side goes to LDS; V = A^k U is formed on the
-// chunk rows, then the chunk's contribution U_chunk^T V is written as a partial.
 __global__ void k_gram_partial(int n, int M, int s, int K, const double* __restrict__ band,
                                const double* __restrict__ U, double* __restrict__ part) {
-  extern __shared__ double lds[];
-  const int w = 2 * s + 1, BW = 2 * w + 1;
-  const int r0 = blockIdx.x * kGramRows;
-  const int rows = min(kGramRows, n - r0);
-  double* sU = lds;                                 // (kGramRows + 2w) x M
-  double* sV = lds + (kGramRows + 2 * w) * M;       // kGramRows x M
-  const int halo_rows = rows + 2 * w;
-  for (int t = threadIdx.x; t < halo_rows * M; t += blockDim.x) {
-    const int rr = t / M, m = t % M;
-    const int g = r0 - w + rr;
-    sU[rr * M + m] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
-  }
-  __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    const double* bk = band + long(k) * n * BW;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-      const int i = t / M, m = t % M;
-      const double* brow = bk + long(r0 + i) * BW;
-      double v = 0.0;
-      for (int o = 0; o < BW; ++o) v += brow[o] * sU[(i + o) * M + m];
-      sV[i * M + m] = v;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
-      const int m = t / M, nn = t % M;
-      double acc = 0.0;
-      for (int i = 0; i < rows; ++i) acc += sU[(i + w) * M + m] * sV[i * M + nn];
-      part[(long(blockIdx.x) * K + k) * M * M + t] = acc;
-    }
-    __syncthreads();
-  }
+  gram_partial(blockIdx.x, n, M, s, K, band, U, part + long(blockIdx.x) * K * M * M);
 }
 
-// Stage 2: out[t] = sum_b part[b][t] in block order.
 __global__ void k_sum_parts(int nparts, long len, const double* __restrict__ part, double* __restrict__ out) {
-  const long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
-  if (t >= len) return;
-  double acc = 0.0;
-  for (int b = 0; b < nparts; ++b) acc += part[long(b) * len + t];
-  out[t] = acc;
+  sum_parts(blockIdx.x, nparts, len, part, out);
 }
 
-// Stage 1 of L = F^T U: block (column tile, row split) accumulates
-// sum_{i in split} F[i][c] U[i][m] for its kLgCols columns.
-__global__ void k_lgram_partial(int n, int Rc, int M, const double* __restrict__ F,
-                                const double* __restrict__ U, double* __restrict__ part) {
-  __shared__ double sF[kLgStage][kLgCols + 1];
-  __shared__ double sU[kLgStage * TAPS_MAX_M];
-  const int c0 = blockIdx.x * kLgCols;
-  const int rbeg = blockIdx.y * kLgRows, rend = min(n, rbeg + kLgRows);
-  const int nout = kLgCols * M;
-  constexpr int kPer = (kLgCols * TAPS_MAX_M + 255) / 256;
-  double acc[kPer];
-  for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-  for (int i0 = rbeg; i0 < rend; i0 += kLgStage) {
-    const int rows = min(kLgStage, rend - i0);
-    for (int t = threadIdx.x; t < kLgStage * kLgCols; t += blockDim.x) {
-      const int r = t / kLgCols, c = t % kLgCols;
-      sF[r][c] = (r < rows && c0 + c < Rc) ? F[long(i0 + r) * Rc + c0 + c] : 0.0;
-    }
-    for (int t = threadIdx.x; t < kLgStage * M; t += blockDim.x) {
-      const int r = t / M;
-      sU[t] = (r < rows) ? U[long(i0) * M + t] : 0.0;
-    }
-    __syncthreads();
-    for (int q = 0; q < kPer; ++q) {
-      const int o = threadIdx.x + q * blockDim.x;
-      if (o < nout) {
-        const int c = o / M, m = o % M;
-        double a = acc[q];
-        for (int r = 0; r < rows; ++r) a += sF[r][c] * sU[r * M + m];
-        acc[q] = a;
-      }
-    }
-    __syncthreads();
-  }
-  // partial layout: [split][Rc][M]
-  for (int q = 0; q < kPer; ++q) {
-    const int o = threadIdx.x + q * blockDim.x;
-    if (o < nout) {
-      const int c = o / M, m = o % M;
-      if (c0 + c < Rc) part[(long(blockIdx.y) * Rc + c0 + c) * M + m] = acc[q];
-    }
-  }
+__global__ void k_lgram_partial(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ U,
+                                double* __restrict__ part) {
+  lgram_partial(blockIdx.x, blockIdx.y, n, Rc, M, F, U, part);
 }
 
-struct CoupleArgs {
-  int D, M, T, d;
-  int tk[TAPS_MAX_TERMS][TAPS_MAX_DIMS];
-  double gamma[TAPS_MAX_TERMS];
-  const double* gram[TAPS_MAX_DIMS];  // cache base of dim e's Grams (n_kinds[e] x M x M)
-  int Kd;
-};
+__global__ void k_couple(CoupleArgs A, double* __restrict__ C) { couple(blockIdx.x, A, C); }
 
-// C^k_d[m][n] = sum over terms whose dim-d matrix is k of
-// gamma * prod_{e != d} G_e^{kind(term, e)}[m][n]  (Hadamard product).
-__global__ void k_couple(CoupleArgs A, double* __restrict__ C) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int MM = A.M * A.M;
-  if (t >= A.Kd * MM) return;
-  const int k = t / MM, mn = t % MM;
-  double acc = 0.0;
-  for (int tau = 0; tau < A.T; ++tau) {
-    if (A.tk[tau][A.d] != k) continue;
-    double prod = A.gamma[tau];
-    for (int e = 0; e < A.D; ++e) {
-      if (e == A.d) continue;
-      prod *= A.gram[e][long(A.tk[tau][e]) * MM + mn];
-    }
-    acc += prod;
-  }
-  C[t] = acc;
-}
+__global__ void k_load_weights(WeightArgs A, double* __restrict__ Wt) { load_weights(blockIdx.x, A, Wt); }
 
-struct WeightArgs {
-  int D, M, R, d, Rc;
-  const double* lgram[TAPS_MAX_DIMS];     // Rc_e x M
-  const int* col[TAPS_MAX_DIMS];          // R entries or null (identity)
-  const int* ptr;                         // dim d grouping (null = identity)
-  const int* idx;
-};
-
-// Wt[c][m] = sum over load terms r with col_d(r) = c of prod_{e != d} L_e[col_e(r)][m].
-__global__ void k_load_weights(WeightArgs A, double* __restrict__ Wt) {
-  const long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
-  if (t >= long(A.Rc) * A.M) return;
-  const int c = int(t / A.M), m = int(t % A.M);
-  const int rb = A.ptr ? A.ptr[c] : c;
-  const int re = A.ptr ? A.ptr[c + 1] : c + 1;
-  double acc = 0.0;
-  for (int q = rb; q < re; ++q) {
-    const int r = A.ptr ? A.idx[q] : q;
-    double prod = 1.0;
-    for (int e = 0; e < A.D; ++e) {
-      if (e == A.d) continue;
-      const int ce = A.col[e] ? A.col[e][r] : r;
-      prod *= A.lgram[e][long(ce) * A.M + m];
-    }
-    acc += prod;
-  }
-  Wt[t] = acc;
-}
-
-// Q = F_d Wt: block per kQRows rows, load columns staged through LDS.
 __global__ void k_force(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ Wt,
                         double* __restrict__ Q) {
-  __shared__ double sF[kQRows][kQStage + 1];
-  __shared__ double sW[kQStage * TAPS_MAX_M];
-  const int r0 = blockIdx.x * kQRows;
-  const int rows = min(kQRows, n - r0);
-  const int nout = kQRows * M;
-  constexpr int kPer = (kQRows * TAPS_MAX_M + 255) / 256;
-  double acc[kPer];
-  for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-  for (int c0 = 0; c0 < Rc; c0 += kQStage) {
-    const int cols = min(kQStage, Rc - c0);
-    for (int t = threadIdx.x; t < kQRows * kQStage; t += blockDim.x) {
-      const int r = t / kQStage, c = t % kQStage;
-      sF[r][c] = (r < rows && c < cols) ? F[long(r0 + r) * Rc + c0 + c] : 0.0;
-    }
-    for (int t = threadIdx.x; t < kQStage * M; t += blockDim.x) {
-      const int c = t / M;
-      sW[t] = (c < cols) ? Wt[long(c0) * M + t] : 0.0;
-    }
-    __syncthreads();
-    for (int q = 0; q < kPer; ++q) {
-      const int o = threadIdx.x + q * blockDim.x;
-      if (o < nout) {
-        const int r = o / M, m = o % M;
-        double a = acc[q];
-        for (int c = 0; c < cols; ++c) a += sF[r][c] * sW[c * M + m];
-        acc[q] = a;
-      }
-    }
-    __syncthreads();
-  }
-  for (int q = 0; q < kPer; ++q) {
-    const int o = threadIdx.x + q * blockDim.x;
-    if (o < nout) {
-      const int r = o / M, m = o % M;
-      if (r < rows) Q[long(r0 + r) * M + m] = acc[q];
-    }
-  }
+  force(blockIdx.x, n, Rc, M, F, Wt, Q);
 }
 
 size_t gram_lds_allowed = 0;

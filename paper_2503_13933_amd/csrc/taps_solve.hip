@@ -14,7 +14,7 @@
 // row panel Z_{k,k+1..k+w} live in LDS.  Rows of fixed nodes are identity
 // rows with zero right-hand side and their columns are zeroed, which keeps
 // X = 0 there.
-#include "taps_internal.hpp"
+#include "taps_device.hpp"
 
 #include <algorithm>
 #include <cstdlib>
@@ -420,7 +420,7 @@ size_t lu_mfma_lds_allowed = 0;
 size_t lu_mfma_batched_lds_allowed = 0;
 
 
-constexpr int kResRows = 64;
+constexpr int kResRows = taps::dev::kResRows;
 
 
 // Per chunk of kResRows rows: R = sum_k A^k U (C^k)^T - Q on the chunk, and the
@@ -430,67 +430,8 @@ __global__ void k_residual_part(int n, int M, int s, int K, const double* __rest
                                 const double* __restrict__ C, const double* __restrict__ U,
                                 const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
                                 double* __restrict__ part) {
-  extern __shared__ double lds[];
-  const int w = 2 * s + 1, BW = 2 * w + 1, MM = M * M;
-  const int r0 = blockIdx.x * kResRows;
-  const int rows = min(kResRows, n - r0);
-  const int hr = rows + 2 * w;
-  double* sU = lds;              // hr x M
-  double* sV = sU + hr * M;      // hr x M
-  double* sC = sV + hr * M;      // M x M
-  double* sR = sC + MM;          // rows x M
-  __shared__ double red[2][256];
-  for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
-    const int rr = t / M, m = t % M;
-    const int g = r0 - w + rr;
-    sU[t] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
-  }
-  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) sR[t] = -Q[long(r0) * M + t];
-  __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    for (int t = threadIdx.x; t < MM; t += blockDim.x) sC[t] = C[long(k) * MM + t];
-    __syncthreads();
-    for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
-      const int rr = t / M, m = t % M;
-      double v = 0.0;
-      for (int q = 0; q < M; ++q) v += sU[rr * M + q] * sC[m * M + q];
-      sV[t] = v;
-    }
-    __syncthreads();
-    const double* bk = band + long(k) * n * BW;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-      const int i = t / M, m = t % M;
-      const double* brow = bk + long(r0 + i) * BW;
-      double v = 0.0;
-      for (int o = 0; o < BW; ++o) v += brow[o] * sV[(i + o) * M + m];
-      sR[t] += v;
-    }
-    __syncthreads();
-  }
-  double rr2 = 0.0, qq2 = 0.0;
-  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-    const int i = t / M;
-    if (fixed && fixed[r0 + i]) continue;
-    const double q = Q[long(r0) * M + t];
-    rr2 += sR[t] * sR[t];
-    qq2 += q * q;
-  }
-  red[0][threadIdx.x] = rr2;
-  red[1][threadIdx.x] = qq2;
-  __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + st];
-      red[1][threadIdx.x] += red[1][threadIdx.x + st];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = red[0][0];
-    part[2 * blockIdx.x + 1] = red[1][0];
-  }
+  taps::dev::residual_part(blockIdx.x, n, M, s, K, band, C, U, Q, fixed, part + 2 * blockIdx.x);
 }
-
 
 // Relative backward error of one dim solve from the per-chunk sums:
 // sqrt(sum R^2 / sum Q^2) over the free rows.

@@ -1,7 +1,7 @@
 // Projected residual, mode balancing and the Algorithm 1 driver
 // (paper Sec. 2.5, the block-diagonal nonlinear system; Sec. 2.6, subspace
 // iteration).
-#include "taps_internal.hpp"
+#include "taps_device.hpp"
 
 #include <vector>
 
@@ -31,45 +31,9 @@ __global__ void k_residual_final(ResFinal A, double* __restrict__ out) {
   out[A.D + 1] = (qs > 0.0) ? sqrt(rs / qs) : sqrt(rs);
 }
 
-struct BalanceArgs {
-  int D, M;
-  int n[TAPS_MAX_DIMS];
-  double* U[TAPS_MAX_DIMS];
-};
+using taps::dev::BalanceArgs;
 
-// One block per mode: column norms of every dim, geometric mean, rescale.
-__global__ void k_balance(BalanceArgs A) {
-  __shared__ double red[256];
-  __shared__ double nrm[TAPS_MAX_DIMS];
-  const int m = blockIdx.x;
-  for (int e = 0; e < A.D; ++e) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < A.n[e]; i += blockDim.x) {
-      const double v = A.U[e][long(i) * A.M + m];
-      acc += v * v;
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) nrm[e] = sqrt(red[0]);
-    __syncthreads();
-  }
-  bool tiny = false;
-  double lg = 0.0;
-  for (int e = 0; e < A.D; ++e) {
-    tiny = tiny || !(nrm[e] >= 1e-300);
-    lg += log(nrm[e]);
-  }
-  if (tiny) return;
-  const double g = exp(lg / A.D);
-  for (int e = 0; e < A.D; ++e) {
-    const double f = g / nrm[e];
-    for (int i = threadIdx.x; i < A.n[e]; i += blockDim.x) A.U[e][long(i) * A.M + m] *= f;
-  }
-}
+__global__ void k_balance(BalanceArgs A) { taps::dev::balance(blockIdx.x, A); }
 
 __global__ void k_first_info(int D, const int* __restrict__ infos, int* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
