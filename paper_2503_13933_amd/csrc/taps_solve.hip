@@ -220,161 +220,299 @@ __global__ __launch_bounds__(kThreads) void k_block_lu(SolveArgs A) {
 
 size_t lu_lds_allowed = 0;
 // ---------------------------------------------------------------------------
-// Matrix-core variant of the same block LU (same math, same window ring):
-// 512 threads, the pivot inverse by a double-buffered Gauss-Jordan (one
-// barrier per pivot), and both block products -- Z = P^-1 (row panel) and
-// the trailing update B_ij -= B_ik Z_kj -- on v_mfma_f64_16x16x4f64.
-// LDS holds the operands in fragment-friendly layouts (contiguous along the
-// 16-wide output index): LpT[q][I] = -B_{k+1+I/M, k}[I%M][q] and
-// Zp[q][J] = Z_{k, k+1+J/M}[q][J%M], inner index q padded to a multiple of 4
-// with zero rows.  MFMA f64 16x16x4 lane layout: A[l%16][l/16], B[l/16][l%16],
-// D[l/16 + 4i][l%16] (i = 0..3).
+// Matrix-core variant of the same block LU (same math, same window ring),
+// 512 threads = 8 waves, four barriers per block row:
+//  (A) build the entering row/column of blocks (couplings held in registers,
+//      band coefficients prefetched into LDS during the previous row);
+//  (B) wave 0 inverts the pivot block by Gauss-Jordan in registers (one row
+//      per lane, pivot row broadcast with readlane) while waves 1-7 stage the
+//      row panel [B_{k,k+1..k+wa} | b_k] and the negated, transposed column
+//      panel in LDS;
+//  (C) [Z | y] = P^-1 [row panel | b] in place on v_mfma_f64_16x16x4f64, one
+//      16-column strip per wave (its B fragments are read before any write);
+//  (D) window and right-hand sides += (-L) [Z | y] on the matrix cores, the
+//      window values loaded before the MFMA chain and added after it.
+// LDS layouts are contiguous along the 16-wide output index; the inner index
+// is padded to a multiple of 4 with zero rows.  MFMA f64 16x16x4 lane
+// layout: A[l%16][l/16], B[l/16][l%16], D[l/16 + 4i][l%16] (i = 0..3).
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kThreadsMfma = 512;
+constexpr int kMaxBlk = 2 * (2 * TAPS_MAX_S + 1) + 1;  // entering blocks per row
 
 __device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+__device__ inline double rdlane(double v, int src) {
+  const unsigned long long x = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(unsigned(x & 0xffffffffu), src);
+  const unsigned hi = __builtin_amdgcn_readlane(unsigned(x >> 32), src);
+  return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
+}
+
+// Quotient by a kernel-constant divisor through its float reciprocal: exact
+// for 0 <= a < 2^20 and divisors <= 64 (the error of (a + 1/2)/d stays below
+// 1/(2d)).
+__device__ inline int fdiv(int a, float inv) { return int((float(a) + 0.5f) * inv); }
+
+// Gauss-Jordan inverse of the M x M block held column-major in S0
+// (S0[j*M + i] = A[i][j]) by the whole workgroup: every pivot reads one buffer
+// and writes the other, so one barrier per pivot; each thread owns the
+// entries t = tid + u*nt (row i = t % M, column j = t / M), indices computed
+// once by the caller.  Leaves P^-1 column-major in S0 (M even) or S1 (M odd).
+template <int KE>
+__device__ bool gj_block(int M, double* S0, double* S1, const int* ei, const int* ej) {
+  const int MM = M * M, tid = threadIdx.x, nt = blockDim.x;
+  bool bad = false;
+  double* cur = S0;
+  double* nxt = S1;
+  for (int r = 0; r < M; ++r) {
+    const double p = cur[r * M + r];
+    bad = bad || !(fabs(p) > 0.0) || !isfinite(p);
+    const double ip = 1.0 / p;
+#pragma unroll
+    for (int u = 0; u < KE; ++u) {
+      const int t = tid + u * nt;
+      if (t < MM) {
+        const int i = ei[u], j = ej[u];
+        const double aij = cur[t], air = cur[r * M + i], arj = cur[j * M + r];
+        double v;
+        if (i == r) v = (j == r) ? ip : aij * ip;
+        else v = (j == r) ? -air * ip : aij - air * (arj * ip);
+        nxt[t] = v;
+      }
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  return bad;
+}
+
+template <int MP>
 __device__ void block_lu_mfma_body(const SolveArgs& A) {
   extern __shared__ double lds[];
-  const int M = A.M, MM = M * M, w = 2 * A.s + 1, W1 = w + 1, n = A.n, wM = w * M;
+  constexpr int kEnt = (MP * MP + kThreadsMfma - 1) / kThreadsMfma;
+  const int M = A.M, MM = M * M, w = 2 * A.s + 1, W1 = w + 1, n = A.n, wM = w * M, K = A.K;
+  const int BW = 2 * w + 1;
   const int M4 = (M + 3) & ~3;
-  const int P16 = ((wM + 15) / 16) * 16;
+  const int P16 = ((wM + 1 + 15) / 16) * 16;
   double* LpT = lds;              // M4 x P16
   double* Zp = LpT + M4 * P16;    // M4 x P16
-  double* sPa = Zp + M4 * P16;    // M x M
-  double* sPb = sPa + MM;         // M x M
-  double* sb = sPb + MM;          // M
-  double* sy = sb + M;            // M
+  double* sG0 = Zp + M4 * P16;    // M x M  Gauss-Jordan buffers
+  double* sG1 = sG0 + MM;         // M x M
+  const double* sPinv = (M % 2 == 0) ? sG0 : sG1;  // where M pivots leave the inverse
+  __shared__ double sCoef[kMaxBlk * TAPS_MAX_KINDS];
+  __shared__ int sFix[kMaxBlk];
   __shared__ int s_info;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+  const float invM = 1.0f / float(M), invW1 = 1.0f / float(W1);
+  auto slot = [&](int i) { return i - fdiv(i, invW1) * W1; };
+  auto WIN = [&](int i, int j) { return A.win + (long(slot(i)) * W1 + slot(j)) * MM; };
+  auto RHS = [&](int i) { return A.rhs + long(slot(i)) * M; };
   if (tid == 0) s_info = 0;
-  auto WIN = [&](int i, int j) { return A.win + (long(i % W1) * W1 + (j % W1)) * MM; };
-  auto RHS = [&](int i) { return A.rhs + long(i % W1) * M; };
+  // this thread's entries of an M x M block, column-major (t = j*M + i)
+  int ei[kEnt], ej[kEnt];
+#pragma unroll
+  for (int u = 0; u < kEnt; ++u) {
+    const int t = tid + u * nt;
+    ej[u] = fdiv(t, invM);
+    ei[u] = t - ej[u] * M;
+  }
+  // couplings at this thread's entries of an M x M block (for building blocks)
+  double creg[TAPS_MAX_KINDS][kEnt];
+#pragma unroll
+  for (int u = 0; u < kEnt; ++u) {
+    const int t = tid + u * nt;
+#pragma unroll
+    for (int k = 0; k < TAPS_MAX_KINDS; ++k) creg[k][u] = (t < MM && k < K) ? A.C[long(k) * MM + t] : 0.0;
+  }
   // zero the K-padding rows once; they are never written afterwards
   for (int t = tid; t < (M4 - M) * P16; t += nt) {
     LpT[M * P16 + t] = 0.0;
     Zp[M * P16 + t] = 0.0;
   }
-  const int init_hi = min(w, n - 1);
-  for (int i = 0; i <= init_hi; ++i) {
-    for (int j = 0; j <= init_hi; ++j) build_block(A, i, j, WIN(i, j));
-    build_rhs(A, i, RHS(i));
+  // block (i, j) of the original matrix from coefficients cf[K] and fixed flags
+  auto build = [&](const double* cf, int fix, int i, int j, double* dst) {
+#pragma unroll
+    for (int u = 0; u < kEnt; ++u) {
+      const int t = tid + u * nt;
+      if (t < MM) {
+        const int r = fdiv(t, invM), c = t - r * M;
+        double v;
+        if (fix & 1) v = (i == j && r == c) ? 1.0 : 0.0;
+        else if (fix & 2) v = 0.0;
+        else {
+          v = 0.0;
+#pragma unroll
+          for (int k = 0; k < TAPS_MAX_KINDS; ++k)
+            if (k < K) v += cf[k] * creg[k][u];
+        }
+        dst[t] = v;
+      }
+    }
+  };
+  auto fixed_of = [&](int i) { return A.fixed ? int(A.fixed[i]) : 0; };
+  auto build_rhs_row = [&](int i) {
+    const bool fi = fixed_of(i);
+    for (int m = tid; m < M; m += nt) RHS(i)[m] = fi ? 0.0 : A.Q[long(i) * M + m];
+  };
+  // initial window rows/cols 0..min(w, n-1)
+  {
+    const int hi = min(w, n - 1);
+    for (int i = 0; i <= hi; ++i) {
+      for (int j = 0; j <= hi; ++j) {
+        double cf[TAPS_MAX_KINDS];
+#pragma unroll
+        for (int k = 0; k < TAPS_MAX_KINDS; ++k)
+          cf[k] = (k < K) ? A.band[(long(k) * n + i) * BW + (j - i + w)] : 0.0;
+        build(cf, (fixed_of(i) ? 1 : 0) | (fixed_of(j) ? 2 : 0), i, j, WIN(i, j));
+      }
+      build_rhs_row(i);
+    }
   }
+  // coefficients of the blocks entering at block row 1
+  auto prefetch = [&](int kn) {
+    const int t = kn + w;
+    if (t >= n || kn < 1) return;
+    for (int idx = tid; idx < (2 * w + 1) * K; idx += nt) {
+      const int b = idx / K, kk = idx % K;
+      const int i = (b <= w) ? t : kn + (b - w - 1);
+      const int j = (b <= w) ? kn + b : t;
+      sCoef[b * TAPS_MAX_KINDS + kk] = A.band[(long(kk) * n + i) * BW + (j - i + w)];
+      if (kk == 0) sFix[b] = (fixed_of(i) ? 1 : 0) | (fixed_of(j) ? 2 : 0);
+    }
+  };
+  prefetch(1);
   __syncthreads();
 
   for (int k = 0; k < n; ++k) {
     const int wa = min(w, n - 1 - k);
     const int waM = wa * M;
-    if (k > 0) {
+    // (A) entering blocks: row t = k + w (cols k..t) and column t (rows k..t-1)
+    if (k > 0 && k + w < n) {
       const int t = k + w;
-      if (t < n) {
-        for (int j = k; j <= t; ++j) build_block(A, t, j, WIN(t, j));
-        for (int i = k; i < t; ++i) build_block(A, i, t, WIN(i, t));
-        build_rhs(A, t, RHS(t));
+      for (int b = 0; b < 2 * w + 1; ++b) {
+        const int i = (b <= w) ? t : k + (b - w - 1);
+        const int j = (b <= w) ? k + b : t;
+        build(sCoef + b * TAPS_MAX_KINDS, sFix[b], i, j, WIN(i, j));
       }
+      build_rhs_row(t);
       __syncthreads();
     }
-    // pivot block, right-hand side and the row panel B_{k, k+1..k+wa} (staged in LpT as [t][J])
+    // (B) stage the pivot block (column-major), the row panel [B_{k,k+1..} | b_k]
+    // and the negated, transposed column panel; then invert the pivot block
     {
       const double* P = WIN(k, k);
-      for (int t = tid; t < MM; t += nt) sPa[t] = P[t];
-      const double* b = RHS(k);
-      for (int m = tid; m < M; m += nt) sb[m] = b[m];
-      for (int t = tid; t < M * waM; t += nt) {
-        const int q = t / waM, J = t % waM;
-        LpT[q * P16 + J] = WIN(k, k + 1 + J / M)[q * M + (J % M)];
+#pragma unroll
+      for (int u = 0; u < kEnt; ++u) {
+        const int t = tid + u * nt;
+        if (t < MM) sG0[t] = P[ei[u] * M + ej[u]];
+      }
+      for (int jj = 0; jj < wa; ++jj) {
+        const double* src = WIN(k, k + 1 + jj);
+        for (int t = tid; t < MM; t += nt) {
+          const int q = fdiv(t, invM), c = t - q * M;
+          Zp[q * P16 + jj * M + c] = src[t];
+        }
+      }
+      for (int q = tid; q < M; q += nt) Zp[q * P16 + waM] = RHS(k)[q];
+      for (int ii = 0; ii < wa; ++ii) {
+        const double* src = WIN(k + 1 + ii, k);
+        for (int t = tid; t < MM; t += nt) {
+          const int r = fdiv(t, invM), q = t - r * M;
+          LpT[q * P16 + ii * M + r] = -src[t];
+        }
       }
     }
     __syncthreads();
-    // Gauss-Jordan inverse, double buffered: every entry of the next buffer
-    // depends on the current one only, so one barrier per pivot
-    double* cur = sPa;
-    double* nxt = sPb;
-    for (int r = 0; r < M; ++r) {
-      const double p = cur[r * M + r];
-      if (tid == 0 && s_info == 0 && (!(fabs(p) > 0.0) || !isfinite(p))) s_info = k + 1;
-      const double ip = 1.0 / p;
-      for (int t = tid; t < MM; t += nt) {
-        const int i = t / M, j = t % M;
-        double v;
-        if (i == r) v = (j == r) ? ip : cur[r * M + j] * ip;
-        else if (j == r) v = -cur[i * M + r] * ip;
-        else v = cur[t] - cur[i * M + r] * (cur[r * M + j] * ip);
-        nxt[t] = v;
-      }
-      __syncthreads();
-      double* tmp = cur;
-      cur = nxt;
-      nxt = tmp;
-    }
-    // y_k = P^-1 b_k
-    for (int m = tid; m < M; m += nt) {
-      double v = 0.0;
-      for (int q = 0; q < M; ++q) v += cur[m * M + q] * sb[q];
-      sy[m] = v;
-      A.Yst[long(k) * M + m] = v;
-    }
-    // Z = P^-1 (row panel) on the matrix cores: tiles of 16 (rows q) x 16 (cols J)
+    if (gj_block<kEnt>(M, sG0, sG1, ei, ej) && tid == 0 && s_info == 0) s_info = k + 1;
+    // (C) [Z | y] = P^-1 [row panel | b], in place, one 16-column strip per wave
     {
-      const int tr = (M + 15) / 16, tc = (waM + 15) / 16;
-      for (int T = wave; T < tr * tc; T += nwaves) {
-        const int q0 = (T / tc) * 16, J0 = (T % tc) * 16;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        const int ar = q0 + (lane & 15);
-        const int bc = J0 + (lane & 15);
-        for (int kk = 0; kk < M4; kk += 4) {
-          const int kx = kk + (lane >> 4);
-          const double a = (ar < M && kx < M) ? cur[ar * M + kx] : 0.0;
-          const double b = (kx < M && bc < waM) ? LpT[kx * P16 + bc] : 0.0;
-          acc = mfma16x16x4(a, b, acc);
-        }
-        for (int i = 0; i < 4; ++i) {
-          const int q = q0 + (lane >> 4) + 4 * i;
-          if (q < M && bc < waM) {
-            Zp[q * P16 + bc] = acc[i];
-            A.Zst[(long(k) * M + q) * wM + bc] = acc[i];
+      const int ncol = waM + 1;
+      const int strips = (ncol + 15) / 16, rtiles = (M + 15) / 16;
+      const int ksteps = M4 / 4;
+      for (int st = wave; st < strips; st += nwaves) {
+        const int col = st * 16 + (lane & 15);
+        double bf[MP / 4];
+#pragma unroll
+        for (int kk = 0; kk < MP / 4; ++kk)
+          bf[kk] = (kk < ksteps) ? Zp[(4 * kk + (lane >> 4)) * P16 + col] : 0.0;
+        // B fragments of this strip are in registers: rows of Zp may now be overwritten
+        for (int tr = 0; tr < rtiles; ++tr) {
+          const int ar = tr * 16 + (lane & 15);
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kk = 0; kk < MP / 4; ++kk) {
+            const int kx = 4 * kk + (lane >> 4);
+            const double a = (ar < M && kx < M) ? sPinv[kx * M + ar] : 0.0;
+            acc = mfma16x16x4(a, bf[kk], acc);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int q = tr * 16 + (lane >> 4) + 4 * i;
+            if (q < M && col < ncol) {
+              Zp[q * P16 + col] = acc[i];
+              if (col < waM) A.Zst[(long(k) * M + q) * wM + col] = acc[i];
+              else A.Yst[long(k) * M + q] = acc[i];
+            }
           }
         }
       }
     }
     __syncthreads();
-    // -(column panel)^T -> LpT[q][I]
-    for (int t = tid; t < waM * M; t += nt) {
-      const int I = t / M, q = t % M;
-      LpT[q * P16 + I] = -WIN(k + 1 + I / M, k)[(I % M) * M + q];
-    }
-    __syncthreads();
-    // trailing update B_ij += (-L) Z on the matrix cores, accumulating into the window
+    // (D) window and right-hand sides += (-L) [Z | y]; the window values of
+    // the wave's next tile are loaded while the current tile's MFMA chain runs
     {
-      const int tt = (waM + 15) / 16;
-      for (int T = wave; T < tt * tt; T += nwaves) {
-        const int I0 = (T / tt) * 16, J0 = (T % tt) * 16;
+      const int trows = (waM + 15) / 16, tcols = (waM + 1 + 15) / 16;
+      const int ntiles = trows * tcols;
+      const int ksteps = M4 / 4;
+      auto locate = [&](int T, double** cp, double* old) {
+        const int I0 = (T / tcols) * 16, J0 = (T % tcols) * 16;
         const int col = J0 + (lane & 15);
-        double* cp[4];
-        v4d acc;
+        const int jb = fdiv(col, invM), cc = col - jb * M;
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = I0 + (lane >> 4) + 4 * i;
-          cp[i] = (row < waM && col < waM)
-                      ? WIN(k + 1 + row / M, k + 1 + col / M) + (row % M) * M + (col % M)
-                      : nullptr;
-          acc[i] = cp[i] ? *cp[i] : 0.0;
+          cp[i] = nullptr;
+          if (T < ntiles && row < waM && col <= waM) {
+            const int bi = fdiv(row, invM), r = row - bi * M;
+            cp[i] = (col < waM) ? WIN(k + 1 + bi, k + 1 + jb) + r * M + cc : RHS(k + 1 + bi) + r;
+          }
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) old[i] = cp[i] ? *cp[i] : 0.0;
+      };
+      double* cp[4];
+      double old[4];
+      locate(wave, cp, old);
+      for (int T = wave; T < ntiles; T += nwaves) {
+        double* cpn[4];
+        double oldn[4];
+        locate(T + nwaves, cpn, oldn);
+        const int I0 = (T / tcols) * 16, J0 = (T % tcols) * 16;
+        const int col = J0 + (lane & 15);
         const int ar = I0 + (lane & 15);
-        for (int kk = 0; kk < M4; kk += 4) {
-          const int kx = kk + (lane >> 4);
-          acc = mfma16x16x4(LpT[kx * P16 + ar], Zp[kx * P16 + col], acc);
+        double af[MP / 4], bfr[MP / 4];
+#pragma unroll
+        for (int kk = 0; kk < MP / 4; ++kk) {
+          const int kx = 4 * kk + (lane >> 4);
+          af[kk] = (kk < ksteps) ? LpT[kx * P16 + ar] : 0.0;
+          bfr[kk] = (kk < ksteps) ? Zp[kx * P16 + col] : 0.0;
         }
-        for (int i = 0; i < 4; ++i)
-          if (cp[i]) *cp[i] = acc[i];
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < MP / 4; ++kk) acc = mfma16x16x4(af[kk], bfr[kk], acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (cp[i]) *cp[i] = old[i] + acc[i];
+          cp[i] = cpn[i];
+          old[i] = oldn[i];
+        }
       }
-    }
-    for (int I = tid; I < waM; I += nt) {
-      double v = 0.0;
-      for (int q = 0; q < M; ++q) v += LpT[q * P16 + I] * sy[q];
-      RHS(k + 1 + I / M)[I % M] += v;
+      prefetch(k + 1);
     }
     __syncthreads();
   }
@@ -392,14 +530,17 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
       const int jb = part * per, je = min(waM, jb + per);
       double v = 0.0;
       const double* zrow = A.Zst + (long(k) * M + m) * wM;
-      for (int J = jb; J < je; ++J) v += zrow[J] * sx[((k + 1 + J / M) % W1) * M + (J % M)];
+      for (int J = jb; J < je; ++J) {
+        const int bj = fdiv(J, invM);
+        v += zrow[J] * sx[slot(k + 1 + bj) * M + (J - bj * M)];
+      }
       spart[part * M + m] = v;
     }
     __syncthreads();
     for (int m = tid; m < M; m += nt) {
       double v = A.Yst[long(k) * M + m];
       for (int part = 0; part < parts; ++part) v -= spart[part * M + m];
-      sx[(k % W1) * M + m] = v;
+      sx[slot(k) * M + m] = v;
       A.X[long(k) * M + m] = v;
     }
     __syncthreads();
@@ -407,17 +548,44 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
   if (tid == 0) A.info[0] = s_info;
 }
 
-__global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma(SolveArgs A) { block_lu_mfma_body(A); }
+#define TAPS_FOR_MP(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64)
 
-// Batched: one workgroup per (active) system; all share M and s, n may differ.
-__global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma_batched(const SolveArgs* __restrict__ args,
-                                                                        const int* __restrict__ active) {
-  const SolveArgs A = args[active[blockIdx.x]];
-  block_lu_mfma_body(A);
+#define TAPS_LU_KERNELS(MP)                                                                          \
+  __global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma_##MP(SolveArgs A) {                \
+    block_lu_mfma_body<MP>(A);                                                                       \
+  }                                                                                                  \
+  __global__ __launch_bounds__(kThreadsMfma) void k_block_lu_mfma_batched_##MP(                      \
+      const SolveArgs* __restrict__ args, const int* __restrict__ active) {                          \
+    const SolveArgs A = args[active[blockIdx.x]];                                                    \
+    block_lu_mfma_body<MP>(A);                                                                       \
+  }
+TAPS_FOR_MP(TAPS_LU_KERNELS)
+
+inline int mp_of(int M) { return ((M + 7) / 8) * 8; }
+
+typedef void (*lu_single_fn)(SolveArgs);
+typedef void (*lu_batched_fn)(const SolveArgs*, const int*);
+
+lu_single_fn lu_single_for(int M) {
+  switch (mp_of(M)) {
+#define TAPS_CASE(MP) case MP: return k_block_lu_mfma_##MP;
+    TAPS_FOR_MP(TAPS_CASE)
+#undef TAPS_CASE
+  }
+  return nullptr;
 }
 
-size_t lu_mfma_lds_allowed = 0;
-size_t lu_mfma_batched_lds_allowed = 0;
+lu_batched_fn lu_batched_for(int M) {
+  switch (mp_of(M)) {
+#define TAPS_CASE(MP) case MP: return k_block_lu_mfma_batched_##MP;
+    TAPS_FOR_MP(TAPS_CASE)
+#undef TAPS_CASE
+  }
+  return nullptr;
+}
+
+size_t lu_mfma_lds_allowed[9] = {0};
+size_t lu_mfma_batched_lds_allowed[9] = {0};
 
 
 constexpr int kResRows = taps::dev::kResRows;
@@ -487,8 +655,8 @@ double solve_bytes(int n, int M, int w, int K) {
 
 size_t solve_mfma_lds_bytes(int M, int s) {
   const int w = 2 * s + 1;
-  const size_t M4 = (M + 3) & ~3, P16 = ((w * M + 15) / 16) * 16;
-  const size_t fwd = (2 * M4 * P16 + 2 * size_t(M) * M + 2 * size_t(M)) * 8;
+  const size_t M4 = (M + 3) & ~3, P16 = ((w * M + 1 + 15) / 16) * 16;
+  const size_t fwd = (2 * M4 * P16 + 2 * size_t(M) * M) * 8;
   const size_t back = size_t(w + 1 + max(1, kThreadsMfma / M)) * M * 8;
   return fwd > back ? fwd : back;
 }
@@ -533,9 +701,10 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
   A.info = d_info;
   size_t slot;
   if (use_mfma) {
-    TAPS_TRY(allow_lds(h, k_block_lu_mfma, lds, &lu_mfma_lds_allowed));
+    lu_single_fn fn = lu_single_for(M);
+    TAPS_TRY(allow_lds(h, fn, lds, &lu_mfma_lds_allowed[mp_of(M) / 8]));
     TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
-    k_block_lu_mfma<<<1, kThreadsMfma, lds, stream>>>(A);
+    fn<<<1, kThreadsMfma, lds, stream>>>(A);
     TAPS_LAUNCHED(h, "k_block_lu_mfma");
   } else {
     TAPS_TRY(allow_lds(h, k_block_lu, lds, &lu_lds_allowed));
@@ -601,11 +770,11 @@ bool solve_batched_supported(int M, int s) { return solve_mfma_lds_bytes(M, s) <
 taps_status solve_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active,
                                  int M, int s, double flops, double bytes, hipStream_t stream) {
   const size_t lds = solve_mfma_lds_bytes(M, s);
-  TAPS_TRY(allow_lds(h, k_block_lu_mfma_batched, lds, &lu_mfma_batched_lds_allowed));
+  lu_batched_fn fn = lu_batched_for(M);
+  TAPS_TRY(allow_lds(h, fn, lds, &lu_mfma_batched_lds_allowed[mp_of(M) / 8]));
   size_t slot;
   TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
-  k_block_lu_mfma_batched<<<n_active, kThreadsMfma, lds, stream>>>(static_cast<const SolveArgs*>(d_args),
-                                                                    d_active);
+  fn<<<n_active, kThreadsMfma, lds, stream>>>(static_cast<const SolveArgs*>(d_args), d_active);
   TAPS_LAUNCHED(h, "k_block_lu_mfma_batched");
   TAPS_TRY(prof_end(h, slot, flops, bytes, stream));
   return TAPS_OK;
