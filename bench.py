@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--M", type=int, default=40)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=10, help="sweep budget per slab solve")
-    ap.add_argument("--batch", type=int, default=128, help="slabs solved together (1 = plain form)")
+    ap.add_argument("--batch", type=int, default=256, help="slabs solved together, one workgroup each (1 = plain form)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside the batch")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-sweeps", type=int, default=1)

@@ -224,16 +224,17 @@ size_t lu_lds_allowed = 0;
 // 512 threads = 8 waves, four barriers per block row:
 //  (A) build the entering row/column of blocks (couplings held in registers,
 //      band coefficients prefetched into LDS during the previous row);
-//  (B) wave 0 inverts the pivot block by Gauss-Jordan in registers (one row
-//      per lane, pivot row broadcast with readlane) while waves 1-7 stage the
-//      row panel [B_{k,k+1..k+wa} | b_k] and the negated, transposed column
-//      panel in LDS;
+//  (B) stage the pivot block, the row panel [B_{k,k+1..k+wa} | b_k] and the
+//      negated column panel in LDS (contiguous copies of the ring), then
+//      invert the pivot block by Gauss-Jordan over all 512 threads (two LDS
+//      buffers, one barrier per pivot);
 //  (C) [Z | y] = P^-1 [row panel | b] in place on v_mfma_f64_16x16x4f64, one
 //      16-column strip per wave (its B fragments are read before any write);
 //  (D) window and right-hand sides += (-L) [Z | y] on the matrix cores, the
 //      window values loaded before the MFMA chain and added after it.
-// LDS layouts are contiguous along the 16-wide output index; the inner index
-// is padded to a multiple of 4 with zero rows.  MFMA f64 16x16x4 lane
+// The row panel is stored K-major (contiguous along the 16-wide output index),
+// the column panel row-major with an odd row stride; the inner index is padded
+// to a multiple of 4 with zeros.  MFMA f64 16x16x4 lane
 // layout: A[l%16][l/16], B[l/16][l%16], D[l/16 + 4i][l%16] (i = 0..3).
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kThreadsMfma = 512;
@@ -243,44 +244,63 @@ __device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ inline double rdlane(double v, int src) {
-  const unsigned long long x = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane(unsigned(x & 0xffffffffu), src);
-  const unsigned hi = __builtin_amdgcn_readlane(unsigned(x >> 32), src);
-  return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
-}
-
 // Quotient by a kernel-constant divisor through its float reciprocal: exact
 // for 0 <= a < 2^20 and divisors <= 64 (the error of (a + 1/2)/d stays below
 // 1/(2d)).
 __device__ inline int fdiv(int a, float inv) { return int((float(a) + 0.5f) * inv); }
 
-// Gauss-Jordan inverse of the M x M block held column-major in S0
-// (S0[j*M + i] = A[i][j]) by the whole workgroup: every pivot reads one buffer
-// and writes the other, so one barrier per pivot; each thread owns the
-// entries t = tid + u*nt (row i = t % M, column j = t / M), indices computed
-// once by the caller.  Leaves P^-1 column-major in S0 (M even) or S1 (M odd).
+// Raw buffer resource over [base, base + bytes).  The address unit returns 0
+// for loads and drops stores whose offset lies outside the range, so a lane
+// with nothing to do is given kOOB instead of a branch: every wave then issues
+// the same memory operations and the compiler waits on exact counts rather
+// than draining the queue (vector loads and stores share one counter).
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+constexpr int kOOB = 0x7ffffff0;
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
+}
+__device__ inline double bload(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, int off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+// Gauss-Jordan inverse of an M x M block P by the whole workgroup.  S0 holds
+// P row-major, which read column-major is P^T; the elimination runs on that
+// array (every pivot reads one buffer and writes the other, so one barrier per
+// pivot) and the last pivot stores its result transposed, which leaves P^-1
+// column-major (S[j*M + i] = P^-1[i][j]) in S0 (M even) or S1 (M odd).  Each
+// thread owns the entries t = tid + u*nt (i = t % M, j = t / M; indices of
+// t >= M*M are clamped by the caller and their results discarded).  A pivot
+// step is branch-free: all its reads are issued first, and every thread
+// stores every entry (discarded ones to a sink), so no read is deferred into
+// a predicated region.
 template <int KE>
 __device__ bool gj_block(int M, double* S0, double* S1, const int* ei, const int* ej) {
+  __shared__ double sink;  // target of the discarded entries t >= M*M
   const int MM = M * M, tid = threadIdx.x, nt = blockDim.x;
   bool bad = false;
   double* cur = S0;
   double* nxt = S1;
   for (int r = 0; r < M; ++r) {
     const double p = cur[r * M + r];
+    double aij[KE], air[KE], arj[KE];
+#pragma unroll
+    for (int u = 0; u < KE; ++u) {
+      aij[u] = cur[ej[u] * M + ei[u]];
+      air[u] = cur[r * M + ei[u]];
+      arj[u] = cur[ej[u] * M + r];
+    }
     bad = bad || !(fabs(p) > 0.0) || !isfinite(p);
     const double ip = 1.0 / p;
 #pragma unroll
     for (int u = 0; u < KE; ++u) {
-      const int t = tid + u * nt;
-      if (t < MM) {
-        const int i = ei[u], j = ej[u];
-        const double aij = cur[t], air = cur[r * M + i], arj = cur[j * M + r];
-        double v;
-        if (i == r) v = (j == r) ? ip : aij * ip;
-        else v = (j == r) ? -air * ip : aij - air * (arj * ip);
-        nxt[t] = v;
-      }
+      const int i = ei[u], j = ej[u];
+      double v = aij[u] - air[u] * (arj[u] * ip);
+      v = (j == r) ? -air[u] * ip : v;
+      v = (i == r) ? ((j == r) ? ip : aij[u] * ip) : v;
+      *((tid + u * nt < MM) ? &nxt[r == M - 1 ? i * M + j : j * M + i] : &sink) = v;
     }
     __syncthreads();
     double* tmp = cur;
@@ -294,73 +314,82 @@ template <int MP>
 __device__ void block_lu_mfma_body(const SolveArgs& A) {
   extern __shared__ double lds[];
   constexpr int kEnt = (MP * MP + kThreadsMfma - 1) / kThreadsMfma;
+  constexpr int kStage = kEnt <= 2 ? 4 : 2;  // blocks staged per round of loads
   const int M = A.M, MM = M * M, w = 2 * A.s + 1, W1 = w + 1, n = A.n, wM = w * M, K = A.K;
   const int BW = 2 * w + 1;
   const int M4 = (M + 3) & ~3;
   const int P16 = ((wM + 1 + 15) / 16) * 16;
-  double* LpT = lds;              // M4 x P16
-  double* Zp = LpT + M4 * P16;    // M4 x P16
+  const int R16 = ((wM + 15) / 16) * 16, LDL = M4 + 1;  // odd row stride: no bank conflicts
+  double* Lp = lds;               // R16 x LDL: -(column panel), row-major
+  double* Zp = Lp + R16 * LDL;    // M4 x P16: [row panel | b], K-major
   double* sG0 = Zp + M4 * P16;    // M x M  Gauss-Jordan buffers
   double* sG1 = sG0 + MM;         // M x M
   const double* sPinv = (M % 2 == 0) ? sG0 : sG1;  // where M pivots leave the inverse
   __shared__ double sCoef[kMaxBlk * TAPS_MAX_KINDS];
-  __shared__ int sFix[kMaxBlk];
+  __shared__ double sQ[TAPS_MAX_M];
+  __shared__ int sFixRow[2 * TAPS_MAX_S + 2];
   __shared__ int s_info;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
   const float invM = 1.0f / float(M), invW1 = 1.0f / float(W1);
   auto slot = [&](int i) { return i - fdiv(i, invW1) * W1; };
-  auto WIN = [&](int i, int j) { return A.win + (long(slot(i)) * W1 + slot(j)) * MM; };
-  auto RHS = [&](int i) { return A.rhs + long(slot(i)) * M; };
+  // the window ring and the right-hand-side ring (which follows it in memory)
+  // through one buffer resource, addressed by byte offsets
+  const int rhs0 = int(A.rhs - A.win) * 8;
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(A.win, long(rhs0) + long(W1) * M * 8);
+  const __amdgpu_buffer_rsrc_t rfix = make_rsrc(A.fixed, A.fixed ? n : 0);
+  auto woff = [&](int i, int j) { return (slot(i) * W1 + slot(j)) * MM * 8; };
+  auto roff = [&](int i) { return rhs0 + slot(i) * M * 8; };
+  auto fixed_at = [&](int i) { return int(__builtin_amdgcn_raw_buffer_load_b8(rfix, i, 0, 0)); };
   if (tid == 0) s_info = 0;
-  // this thread's entries of an M x M block, column-major (t = j*M + i)
+  // this thread's entries t = tid + u*nt of an M x M block: row-major row ej,
+  // column ei (clamped for t >= M*M)
   int ei[kEnt], ej[kEnt];
 #pragma unroll
   for (int u = 0; u < kEnt; ++u) {
-    const int t = tid + u * nt;
+    const int t = min(tid + u * nt, MM - 1);
     ej[u] = fdiv(t, invM);
     ei[u] = t - ej[u] * M;
   }
-  // couplings at this thread's entries of an M x M block (for building blocks)
-  double creg[TAPS_MAX_KINDS][kEnt];
-#pragma unroll
-  for (int u = 0; u < kEnt; ++u) {
-    const int t = tid + u * nt;
-#pragma unroll
-    for (int k = 0; k < TAPS_MAX_KINDS; ++k) creg[k][u] = (t < MM && k < K) ? A.C[long(k) * MM + t] : 0.0;
-  }
-  // zero the K-padding rows once; they are never written afterwards
-  for (int t = tid; t < (M4 - M) * P16; t += nt) {
-    LpT[M * P16 + t] = 0.0;
-    Zp[M * P16 + t] = 0.0;
-  }
-  // block (i, j) of the original matrix from coefficients cf[K] and fixed flags
-  auto build = [&](const double* cf, int fix, int i, int j, double* dst) {
+  // couplings at this thread's entries of an M x M block, zero for kinds
+  // k >= K; loaded where blocks are built rather than held for the whole
+  // kernel (the registers are needed by the update)
+  auto load_couplings = [&](double (&cr)[TAPS_MAX_KINDS][kEnt]) {
 #pragma unroll
     for (int u = 0; u < kEnt; ++u) {
-      const int t = tid + u * nt;
-      if (t < MM) {
-        const int r = fdiv(t, invM), c = t - r * M;
-        double v;
-        if (fix & 1) v = (i == j && r == c) ? 1.0 : 0.0;
-        else if (fix & 2) v = 0.0;
-        else {
-          v = 0.0;
 #pragma unroll
-          for (int k = 0; k < TAPS_MAX_KINDS; ++k)
-            if (k < K) v += cf[k] * creg[k][u];
-        }
-        dst[t] = v;
+      for (int k = 0; k < TAPS_MAX_KINDS; ++k) {
+        const double c = A.C[long(min(k, K - 1)) * MM + ej[u] * M + ei[u]];
+        cr[k][u] = (k < K) ? c : 0.0;
       }
     }
   };
-  auto fixed_of = [&](int i) { return A.fixed ? int(A.fixed[i]) : 0; };
-  auto build_rhs_row = [&](int i) {
-    const bool fi = fixed_of(i);
-    for (int m = tid; m < M; m += nt) RHS(i)[m] = fi ? 0.0 : A.Q[long(i) * M + m];
+  // zero the K-padding (columns M..M4-1 of Lp, rows M..M4-1 of Zp) and Lp's
+  // tail rows once; they are never written afterwards
+  for (int t = tid; t < R16 * LDL; t += nt) Lp[t] = 0.0;
+  for (int t = tid; t < (M4 - M) * P16; t += nt) Zp[M * P16 + t] = 0.0;
+  // block (i, j) of the original matrix, from coefficients cf[K] and the fixed
+  // flags (bit 0: row i fixed -> identity or zero block, bit 1: column j fixed)
+  // (cf holds TAPS_MAX_KINDS values, zero beyond K, read once per block)
+  auto build = [&](const double (&creg)[TAPS_MAX_KINDS][kEnt], const double* cf, int fix, bool diag, int off) {
+    double c[TAPS_MAX_KINDS];
+#pragma unroll
+    for (int k = 0; k < TAPS_MAX_KINDS; ++k) c[k] = cf[k];
+#pragma unroll
+    for (int u = 0; u < kEnt; ++u) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < TAPS_MAX_KINDS; ++k) v += c[k] * creg[k][u];
+      v = (fix & 2) ? 0.0 : v;
+      v = (fix & 1) ? ((diag && ei[u] == ej[u]) ? 1.0 : 0.0) : v;
+      const int t = tid + u * nt;
+      bstore(rw, t < MM ? off + t * 8 : kOOB, v);
+    }
   };
   // initial window rows/cols 0..min(w, n-1)
   {
+    double creg[TAPS_MAX_KINDS][kEnt];
+    load_couplings(creg);
     const int hi = min(w, n - 1);
     for (int i = 0; i <= hi; ++i) {
       for (int j = 0; j <= hi; ++j) {
@@ -368,24 +397,38 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
 #pragma unroll
         for (int k = 0; k < TAPS_MAX_KINDS; ++k)
           cf[k] = (k < K) ? A.band[(long(k) * n + i) * BW + (j - i + w)] : 0.0;
-        build(cf, (fixed_of(i) ? 1 : 0) | (fixed_of(j) ? 2 : 0), i, j, WIN(i, j));
+        build(creg, cf, (fixed_at(i) ? 1 : 0) | (fixed_at(j) ? 2 : 0), i == j, woff(i, j));
       }
-      build_rhs_row(i);
+      const double q = fixed_at(i) ? 0.0 : A.Q[long(i) * M + min(tid, M - 1)];
+      bstore(rw, tid < M ? roff(i) + tid * 8 : kOOB, q);
     }
   }
-  // coefficients of the blocks entering at block row 1
-  auto prefetch = [&](int kn) {
+  // band coefficients, fixed flags of rows kn..kn+w and the load row of the
+  // blocks entering at block row kn (row t = kn + w, columns kn..t, and column
+  // t, rows kn..t-1): loaded early into registers, stored to LDS late
+  // (thread tid loads coefficient kk = tid % TAPS_MAX_KINDS of block
+  // b = tid / TAPS_MAX_KINDS, zero for kk >= K)
+  struct Pre { double cf, q; int fx; };
+  auto pre_issue = [&](int kn) {
+    Pre pr{0.0, 0.0, 0};
     const int t = kn + w;
-    if (t >= n || kn < 1) return;
-    for (int idx = tid; idx < (2 * w + 1) * K; idx += nt) {
-      const int b = idx / K, kk = idx % K;
-      const int i = (b <= w) ? t : kn + (b - w - 1);
-      const int j = (b <= w) ? kn + b : t;
-      sCoef[b * TAPS_MAX_KINDS + kk] = A.band[(long(kk) * n + i) * BW + (j - i + w)];
-      if (kk == 0) sFix[b] = (fixed_of(i) ? 1 : 0) | (fixed_of(j) ? 2 : 0);
-    }
+    if (t >= n || kn < 1) return pr;
+    const int b = min(tid / TAPS_MAX_KINDS, 2 * w), kk = tid % TAPS_MAX_KINDS;
+    const int i = (b <= w) ? t : kn + (b - w - 1);
+    const int j = (b <= w) ? kn + b : t;
+    const double cf = A.band[(long(min(kk, K - 1)) * n + i) * BW + (j - i + w)];
+    pr.cf = (kk < K) ? cf : 0.0;
+    pr.q = A.Q[long(t) * M + min(tid, M - 1)];
+    pr.fx = fixed_at(kn + min(tid, w));
+    return pr;
   };
-  prefetch(1);
+  auto pre_commit = [&](int kn, const Pre& pr) {
+    if (kn + w >= n || kn < 1) return;
+    if (tid < (2 * w + 1) * TAPS_MAX_KINDS) sCoef[tid] = pr.cf;
+    if (tid < M) sQ[tid] = pr.q;
+    if (tid <= w) sFixRow[tid] = pr.fx;
+  };
+  pre_commit(1, pre_issue(1));
   __syncthreads();
 
   for (int k = 0; k < n; ++k) {
@@ -394,38 +437,51 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
     // (A) entering blocks: row t = k + w (cols k..t) and column t (rows k..t-1)
     if (k > 0 && k + w < n) {
       const int t = k + w;
+      double creg[TAPS_MAX_KINDS][kEnt];
+      load_couplings(creg);
       for (int b = 0; b < 2 * w + 1; ++b) {
         const int i = (b <= w) ? t : k + (b - w - 1);
         const int j = (b <= w) ? k + b : t;
-        build(sCoef + b * TAPS_MAX_KINDS, sFix[b], i, j, WIN(i, j));
+        build(creg, sCoef + b * TAPS_MAX_KINDS, (sFixRow[i - k] ? 1 : 0) | (sFixRow[j - k] ? 2 : 0), i == j,
+              woff(i, j));
       }
-      build_rhs_row(t);
+      bstore(rw, tid < M ? roff(t) + tid * 8 : kOOB, sFixRow[w] ? 0.0 : sQ[min(tid, M - 1)]);
       __syncthreads();
     }
-    // (B) stage the pivot block (column-major), the row panel [B_{k,k+1..} | b_k]
-    // and the negated, transposed column panel; then invert the pivot block
+    // (B) stage the pivot block, the row panel [B_{k,k+1..} | b_k] and the
+    // negated column panel (blocks b = 0 | 1..wa | wa+1..2wa), several
+    // blocks' loads in flight per thread; then invert the pivot block
     {
-      const double* P = WIN(k, k);
+      const int nb = 2 * wa + 1;
+      for (int b0 = 0; b0 < nb; b0 += kStage) {
+        double v[kStage][kEnt];
 #pragma unroll
-      for (int u = 0; u < kEnt; ++u) {
-        const int t = tid + u * nt;
-        if (t < MM) sG0[t] = P[ei[u] * M + ej[u]];
-      }
-      for (int jj = 0; jj < wa; ++jj) {
-        const double* src = WIN(k, k + 1 + jj);
-        for (int t = tid; t < MM; t += nt) {
-          const int q = fdiv(t, invM), c = t - q * M;
-          Zp[q * P16 + jj * M + c] = src[t];
+        for (int c = 0; c < kStage; ++c) {
+          const int b = min(b0 + c, nb - 1);
+          const int i = (b <= wa) ? k : k + b - wa;
+          const int j = (b <= wa) ? k + b : k;
+          const int off = woff(i, j);
+#pragma unroll
+          for (int u = 0; u < kEnt; ++u) v[c][u] = bload(rw, off + (ej[u] * M + ei[u]) * 8);
+        }
+#pragma unroll
+        for (int c = 0; c < kStage; ++c) {
+          const int b = b0 + c;
+          if (b < nb) {
+#pragma unroll
+            for (int u = 0; u < kEnt; ++u) {
+              if (tid + u * nt < MM) {
+                const int r = ej[u], q = ei[u];
+                if (b == 0) sG0[r * M + q] = v[c][u];
+                else if (b <= wa) Zp[r * P16 + (b - 1) * M + q] = v[c][u];
+                else Lp[((b - wa - 1) * M + r) * LDL + q] = -v[c][u];
+              }
+            }
+          }
         }
       }
-      for (int q = tid; q < M; q += nt) Zp[q * P16 + waM] = RHS(k)[q];
-      for (int ii = 0; ii < wa; ++ii) {
-        const double* src = WIN(k + 1 + ii, k);
-        for (int t = tid; t < MM; t += nt) {
-          const int r = fdiv(t, invM), q = t - r * M;
-          LpT[q * P16 + ii * M + r] = -src[t];
-        }
-      }
+      const double bv = bload(rw, roff(k) + min(tid, M - 1) * 8);
+      if (tid < M) Zp[tid * P16 + waM] = bv;
     }
     __syncthreads();
     if (gj_block<kEnt>(M, sG0, sG1, ei, ej) && tid == 0 && s_info == 0) s_info = k + 1;
@@ -434,6 +490,8 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
       const int ncol = waM + 1;
       const int strips = (ncol + 15) / 16, rtiles = (M + 15) / 16;
       const int ksteps = M4 / 4;
+      const __amdgpu_buffer_rsrc_t rz = make_rsrc(A.Zst + long(k) * M * wM, long(M) * wM * 8);
+      const __amdgpu_buffer_rsrc_t ry = make_rsrc(A.Yst + long(k) * M, long(M) * 8);
       for (int st = wave; st < strips; st += nwaves) {
         const int col = st * 16 + (lane & 15);
         double bf[MP / 4];
@@ -441,6 +499,7 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
         for (int kk = 0; kk < MP / 4; ++kk)
           bf[kk] = (kk < ksteps) ? Zp[(4 * kk + (lane >> 4)) * P16 + col] : 0.0;
         // B fragments of this strip are in registers: rows of Zp may now be overwritten
+#pragma unroll 1
         for (int tr = 0; tr < rtiles; ++tr) {
           const int ar = tr * 16 + (lane & 15);
           v4d acc = {0.0, 0.0, 0.0, 0.0};
@@ -453,66 +512,74 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int q = tr * 16 + (lane >> 4) + 4 * i;
-            if (q < M && col < ncol) {
-              Zp[q * P16 + col] = acc[i];
-              if (col < waM) A.Zst[(long(k) * M + q) * wM + col] = acc[i];
-              else A.Yst[long(k) * M + q] = acc[i];
-            }
+            if (q < M && col < ncol) Zp[q * P16 + col] = acc[i];
+            bstore(rz, (q < M && col < waM) ? (q * wM + col) * 8 : kOOB, acc[i]);
+            bstore(ry, (q < M && col == waM) ? q * 8 : kOOB, acc[i]);
           }
         }
       }
     }
     __syncthreads();
-    // (D) window and right-hand sides += (-L) [Z | y]; the window values of
-    // the wave's next tile are loaded while the current tile's MFMA chain runs
+    // (D) window and right-hand sides += (-L) [Z | y]; the next block row's
+    // coefficients and the window values of the wave's next tile are loaded
+    // while the current tile's MFMA chain runs
     {
+      const Pre pr = pre_issue(k + 1);
       const int trows = (waM + 15) / 16, tcols = (waM + 1 + 15) / 16;
       const int ntiles = trows * tcols;
       const int ksteps = M4 / 4;
-      auto locate = [&](int T, double** cp, double* old) {
-        const int I0 = (T / tcols) * 16, J0 = (T % tcols) * 16;
+      const float invTc = 1.0f / float(tcols);
+      auto locate = [&](int T, int* o) {
+        const int tr = fdiv(T, invTc);
+        const int I0 = tr * 16, J0 = (T - tr * tcols) * 16;
         const int col = J0 + (lane & 15);
         const int jb = fdiv(col, invM), cc = col - jb * M;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = I0 + (lane >> 4) + 4 * i;
-          cp[i] = nullptr;
-          if (T < ntiles && row < waM && col <= waM) {
-            const int bi = fdiv(row, invM), r = row - bi * M;
-            cp[i] = (col < waM) ? WIN(k + 1 + bi, k + 1 + jb) + r * M + cc : RHS(k + 1 + bi) + r;
-          }
+          const int bi = fdiv(row, invM), r = row - bi * M;
+          const int ow = (col < waM) ? woff(k + 1 + bi, k + 1 + jb) + (r * M + cc) * 8 : roff(k + 1 + bi) + r * 8;
+          o[i] = (T < ntiles && row < waM && col <= waM) ? ow : kOOB;
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) old[i] = cp[i] ? *cp[i] : 0.0;
       };
-      double* cp[4];
-      double old[4];
-      locate(wave, cp, old);
-      for (int T = wave; T < ntiles; T += nwaves) {
-        double* cpn[4];
-        double oldn[4];
-        locate(T + nwaves, cpn, oldn);
-        const int I0 = (T / tcols) * 16, J0 = (T % tcols) * 16;
+      // one tile: (-L)[Z | y] on the matrix cores, added to the window values
+      // loaded one tile earlier
+      auto tile = [&](int T, const int* o, const double* old) {
+        const int I0 = fdiv(T, invTc) * 16, J0 = (T - fdiv(T, invTc) * tcols) * 16;
         const int col = J0 + (lane & 15);
         const int ar = I0 + (lane & 15);
         double af[MP / 4], bfr[MP / 4];
 #pragma unroll
         for (int kk = 0; kk < MP / 4; ++kk) {
           const int kx = 4 * kk + (lane >> 4);
-          af[kk] = (kk < ksteps) ? LpT[kx * P16 + ar] : 0.0;
+          af[kk] = (kk < ksteps) ? Lp[ar * LDL + kx] : 0.0;
           bfr[kk] = (kk < ksteps) ? Zp[kx * P16 + col] : 0.0;
         }
         v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < MP / 4; ++kk) acc = mfma16x16x4(af[kk], bfr[kk], acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (cp[i]) *cp[i] = old[i] + acc[i];
-          cp[i] = cpn[i];
-          old[i] = oldn[i];
-        }
+        for (int i = 0; i < 4; ++i) bstore(rw, o[i], old[i] + acc[i]);
+      };
+      // two register sets used alternately, so a prefetched value is never
+      // copied (a copy would wait for the load)
+      int oA[4], oB[4];
+      double vA[4], vB[4];
+      locate(wave, oA);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) vA[i] = bload(rw, oA[i]);
+      for (int T = wave; T < ntiles; T += 2 * nwaves) {
+        locate(T + nwaves, oB);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vB[i] = bload(rw, oB[i]);
+        tile(T, oA, vA);
+        if (T + nwaves >= ntiles) break;
+        locate(T + 2 * nwaves, oA);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vA[i] = bload(rw, oA[i]);
+        tile(T + nwaves, oB, vB);
       }
-      prefetch(k + 1);
+      pre_commit(k + 1, pr);
     }
     __syncthreads();
   }
@@ -656,7 +723,8 @@ double solve_bytes(int n, int M, int w, int K) {
 size_t solve_mfma_lds_bytes(int M, int s) {
   const int w = 2 * s + 1;
   const size_t M4 = (M + 3) & ~3, P16 = ((w * M + 1 + 15) / 16) * 16;
-  const size_t fwd = (2 * M4 * P16 + 2 * size_t(M) * M) * 8;
+  const size_t R16 = ((w * M + 15) / 16) * 16;
+  const size_t fwd = (R16 * (M4 + 1) + M4 * P16 + 2 * size_t(M) * M) * 8;
   const size_t back = size_t(w + 1 + max(1, kThreadsMfma / M)) * M * 8;
   return fwd > back ? fwd : back;
 }
