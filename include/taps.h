@@ -261,10 +261,13 @@ taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* p
  *                      bytes = band + couplings + Q read, X written.
  *   TAPS_PROF_CONTRACT Grams, load Grams, couplings and force: flops of the
  *                      products, bytes = U, bands, F read once + outputs.
+ *   TAPS_PROF_RECON    FP32/BF16 reconstruction on the matrix cores: flops =
+ *                      2 n0 n1 n2 Mp (Mp = M padded to the MFMA inner size),
+ *                      bytes = field written (STORE) + factors read once.
  * taps_profile_enable(h, 1) clears the counters and starts recording,
  * (h, 0) stops.  taps_profile_read synchronises on the recorded events and
  * returns launches, summed kernel milliseconds, flops and bytes of one family. */
-typedef enum { TAPS_PROF_SOLVE = 0, TAPS_PROF_CONTRACT = 1 } taps_prof_family;
+typedef enum { TAPS_PROF_SOLVE = 0, TAPS_PROF_CONTRACT = 1, TAPS_PROF_RECON = 2 } taps_prof_family;
 taps_status taps_profile_enable(taps_handle_t h, int32_t enable);
 taps_status taps_profile_read(taps_handle_t h, taps_prof_family family, int32_t* launches,
                               double* total_ms, double* flops, double* bytes);

@@ -27,7 +27,7 @@ FUNCTIONS = (
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
     "taps_reconstruct", "taps_profile_enable", "taps_profile_read", "taps_als_batched",
 )
-PROF_SOLVE, PROF_CONTRACT = 0, 1
+PROF_SOLVE, PROF_CONTRACT, PROF_RECON = 0, 1, 2
 
 
 class TapsError(RuntimeError):

@@ -1,10 +1,408 @@
-// Reduced-precision reconstruction on the matrix cores (placeholder until the
-// MFMA kernels land): reports TAPS_ERR_UNSUPPORTED.
+// Reduced-precision reconstruction of the rank-M field on the matrix cores
+// (paper Sec. 2.3, TD interpolation):
+//   u[i][j][k] = sum_m Phi_0[i][m] s_k[m] Phi_1[j][m],   s_k[m] = w_m Phi_2[k][m].
+// Per plane k this is an (n0 x M) x (M x n1) product whose inner index carries
+// the diagonal s_k.  The scaling is folded into the left operand once per
+// (workgroup, plane), A'_k = Phi_0 diag(s_k), and the right operand Phi_1 is
+// streamed through every j tile, so the per-plane cost outside the MFMA chain
+// is 64 x M multiplies per wave.
+//
+// Rounding points (the error statement follows from them):
+//   BF16: Phi_0, Phi_1, w, Phi_2 rounded to FP32; s = fl32(w * Phi_2);
+//         a' = bf16(fl32(Phi_0 * s)); b = bf16(Phi_1); products exact in FP32,
+//         accumulated in FP32 by v_mfma_f32_16x16x32_bf16.
+//   FP32: the same in FP32 throughout (v_mfma_f32_16x16x4_f32).
+//
+// Workgroup = 4 waves = 256 rows of i for one plane; each wave owns 64 rows
+// (four 16-row tiles, scaled Phi_0 operands in registers) and walks the j
+// tiles of 16 columns, Phi_1 operands loaded one tile ahead.  Lanes with no row or
+// column load and store through buffer resources with out-of-range offsets,
+// which the address unit turns into zeros and dropped stores.
+//
+// MFMA lane layouts (checked on the device): A[l%16][kgroup l/16],
+// B[kgroup l/16][l%16], D[4*(l/16) + r][l%16] for r = 0..3.  Accumulator
+// elements are copied to a plain array before the buffer stores: storing
+// acc[q] straight from the accumulator registers made this compiler emit the
+// first element for every q, and indexing the 128-bit load result of a
+// generic vector type element by element made it load one word for all four;
+// whole-vector bit casts and named components avoid both.
 #include "taps_internal.hpp"
 
-namespace taps {
-taps_status reconstruct_mfma(taps_handle* h, const int32_t*, const double* const*, int32_t, const double*,
-                             taps_prec, taps_recon_mode, void*, double, hipStream_t) {
-  return fail(h, TAPS_ERR_UNSUPPORTED, "FP32/BF16 reconstruction not built yet");
+#include <cmath>
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((__vector_size__(16)));
+
+constexpr int kWaves = 4;
+constexpr int kRowsWave = 64;
+constexpr int kRowsWG = kWaves * kRowsWave;
+constexpr int kOOB = 0x7ffffff0;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
 }
+
+// FP64 factor (n x M) -> T (n x Mp), zero-padded columns (conversion through FP32).
+template <typename T>
+__global__ void k_recon_convert(int n, int M, int Mp, const double* __restrict__ P, T* __restrict__ out) {
+  const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= long(n) * Mp) return;
+  const int i = int(idx / Mp), m = int(idx - long(i) * Mp);
+  const float v = (m < M) ? float(P[long(i) * M + m]) : 0.0f;
+  out[idx] = T(v);
+}
+
+struct Reduce {
+  float mx;
+  double ss;
+  unsigned long long cnt;  // wave-uniform: counted with ballots
+};
+
+// Epilogue of one j tile.  The products are formed transposed (streamed
+// Phi_1 rows as the MFMA's first operand), so lane l holds, for row
+// i = ibase + 16 rt + l%16, the four consecutive columns j0 .. j0+3 with
+// j0 = 16 jt + 4 (l/16): one 16-byte store per lane and 16-row tile.  Store
+// the values, or fold them into the lane's {max, sum of squares,
+// count(u > thr)}; thrf is thr rounded down to FP32, so v > thrf exactly when
+// v > thr.  Tiles wholly inside the plane take the unpredicated path.
+template <int MODE>
+__device__ inline void epilogue(const f32x4 (&acc)[4], int ibase, int c16, int j0, int n0, int n1, bool jfull,
+                                bool full, float thrf, Reduce& r, __amdgpu_buffer_rsrc_t ro) {
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const float v[4] = {acc[rt].x, acc[rt].y, acc[rt].z, acc[rt].w};
+    const int i = ibase + 16 * rt + c16;
+    if (MODE == TAPS_STORE) {
+      if (jfull) {
+        const int off = (i < n0) ? (i * n1 + j0) * 4 : kOOB;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[rt]), ro, off, 0, 0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int off = (i < n0 && j0 + q < n1) ? (i * n1 + j0 + q) * 4 : kOOB;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), ro, off, 0, 0);
+        }
+      }
+    } else {
+      float ss = 0.0f;
+      if (full) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          r.mx = fmaxf(r.mx, v[q]);
+          ss = fmaf(v[q], v[q], ss);
+          r.cnt += __popcll(__ballot(v[q] > thrf));
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = i < n0 && j0 + q < n1;
+          r.mx = ok ? fmaxf(r.mx, v[q]) : r.mx;
+          ss = ok ? fmaf(v[q], v[q], ss) : ss;
+          r.cnt += __popcll(__ballot(ok && v[q] > thrf));
+        }
+      }
+      r.ss += double(ss);
+    }
+  }
+}
+
+// Workgroup reduction of {max, sum of squares, count} into one record.
+__device__ void reduce_store(Reduce r, double* rec) {
+  __shared__ double sred[kWaves][3];
+  for (int off = 32; off > 0; off >>= 1) {
+    r.mx = fmaxf(r.mx, __shfl_xor(r.mx, off));
+    r.ss += __shfl_xor(r.ss, off);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sred[wave][0] = r.mx;
+    sred[wave][1] = r.ss;
+    sred[wave][2] = double(r.cnt);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = -INFINITY, ss = 0.0, cnt = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+      mx = fmax(mx, sred[w][0]);
+      ss += sred[w][1];
+      cnt += sred[w][2];
+    }
+    rec[0] = mx;
+    rec[1] = ss;
+    rec[2] = cnt;
+    rec[3] = 0.0;
+  }
+}
+
+// Scale factors of plane k in LDS: s[m] = fl32(fl32(w_m) * fl32(Phi_2[k][m])).
+__device__ void plane_scale(float* s, int k, int M, int Mp, const double* P2, const double* mw) {
+  for (int m = threadIdx.x; m < Mp; m += blockDim.x)
+    s[m] = (m < M) ? float(mw ? mw[m] : 1.0) * float(P2[long(k) * M + m]) : 0.0f;
+  __syncthreads();
+}
+
+// BF16 x BF16 -> FP32.  KS = Mp / 32 inner steps of 32 modes; lane group
+// g = l/16 of step ks covers modes 32 ks + 8 g + (0..7).
+template <int KS, int MODE>
+__global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int nrb, int M, const float* __restrict__ P0f,
+                                                            const __bf16* __restrict__ P1b, const double* __restrict__ P2,
+                                                            const double* __restrict__ mw, float thrf, float* __restrict__ out,
+                                                            double* __restrict__ rec) {
+  constexpr int Mp = 32 * KS;
+  __shared__ __align__(16) float s[Mp];
+  const int k = blockIdx.x / nrb, rb = blockIdx.x - k * nrb;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile tests branch on the scalar unit
+  plane_scale(s, k, M, Mp, P2, mw);
+  const int ibase = rb * kRowsWG + wave * kRowsWave;
+  // scaled operands a'[i][m] = bf16(P0f[i][m] * s[m]), kept as packed words
+  // (held as eight separate halves they were re-packed at every use)
+  // (rows past n0 read row n0-1 and are zeroed: no load is predicated)
+  u32x4 a[4][KS];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const int i = ibase + 16 * rt + c16;
+    const f32x4* row = reinterpret_cast<const f32x4*>(P0f + long(min(i, n0 - 1)) * Mp);
+    const float keep = (i < n0) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int q4 = (32 * ks + 8 * g) / 4;
+      const f32x4 x0 = row[q4], x1 = row[q4 + 1];
+      const f32x4 s0 = reinterpret_cast<const f32x4*>(s)[q4], s1 = reinterpret_cast<const f32x4*>(s)[q4 + 1];
+      bf16x8 v;
+      v[0] = __bf16(x0.x * s0.x * keep);
+      v[1] = __bf16(x0.y * s0.y * keep);
+      v[2] = __bf16(x0.z * s0.z * keep);
+      v[3] = __bf16(x0.w * s0.w * keep);
+      v[4] = __bf16(x1.x * s1.x * keep);
+      v[5] = __bf16(x1.y * s1.y * keep);
+      v[6] = __bf16(x1.z * s1.z * keep);
+      v[7] = __bf16(x1.w * s1.w * keep);
+      a[rt][ks] = __builtin_bit_cast(u32x4, v);
+    }
+  }
+  const __amdgpu_buffer_rsrc_t rb1 = make_rsrc(P1b, long(n1) * Mp * 2);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + (MODE == TAPS_STORE ? long(k) * n0 * n1 : 0),
+                                              MODE == TAPS_STORE ? long(n0) * n1 * 4 : 0);
+  auto bload = [&](int jt, bf16x8* b) {
+    const int j = 16 * jt + c16;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int off = (j < n1) ? (j * Mp + 32 * ks + 8 * g) * 2 : kOOB;
+      b[ks] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb1, off, 0, 0));
+    }
+  };
+  Reduce red{-INFINITY, 0.0, 0ull};
+  const bool rows_full = ibase + kRowsWave <= n0;
+  auto tile = [&](int jt, const bf16x8* b) {
+    f32x4 acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      acc[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks], __builtin_bit_cast(bf16x8, a[rt][ks]), acc[rt], 0, 0, 0);
+    }
+    const bool jfull = 16 * jt + 16 <= n1;
+    epilogue<MODE>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, rows_full && jfull, thrf, red, ro);
+  };
+  // four register sets in rotation: tile jt's operands were requested three
+  // tiles earlier (an L2 round trip outlasts one tile's MFMA chain)
+  const int ntj = (n1 + 15) / 16;
+  bf16x8 b0[KS], b1[KS], b2[KS], b3[KS];
+  bload(0, b0);
+  bload(1, b1);
+  bload(2, b2);
+  for (int jt = 0; jt < ntj; jt += 4) {
+    bload(jt + 3, b3);
+    tile(jt, b0);
+    if (jt + 1 >= ntj) break;
+    bload(jt + 4, b0);
+    tile(jt + 1, b1);
+    if (jt + 2 >= ntj) break;
+    bload(jt + 5, b1);
+    tile(jt + 2, b2);
+    if (jt + 3 >= ntj) break;
+    bload(jt + 6, b2);
+    tile(jt + 3, b3);
+  }
+  if (MODE == TAPS_REDUCE) reduce_store(red, rec + (long(k) * nrb + rb) * 4);
+}
+
+// FP32 x FP32 -> FP32.  S = Mp / 4 instructions of K = 4; in instruction q
+// lane group g takes mode g*S + q, so each lane's modes are contiguous.
+template <int S, int MODE>
+__global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int nrb, int M, const float* __restrict__ P0f,
+                                                            const float* __restrict__ P1f, const double* __restrict__ P2,
+                                                            const double* __restrict__ mw, float thrf, float* __restrict__ out,
+                                                            double* __restrict__ rec) {
+  constexpr int Mp = 4 * S;
+  __shared__ __align__(16) float s[Mp];
+  const int k = blockIdx.x / nrb, rb = blockIdx.x - k * nrb;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile tests branch on the scalar unit
+  plane_scale(s, k, M, Mp, P2, mw);
+  const int ibase = rb * kRowsWG + wave * kRowsWave;
+  // (rows past n0 read row n0-1 and are zeroed: no load is predicated)
+  float a[4][S];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const int i = ibase + 16 * rt + c16;
+    const f32x4* row = reinterpret_cast<const f32x4*>(P0f + long(min(i, n0 - 1)) * Mp + g * S);
+    const f32x4* sv = reinterpret_cast<const f32x4*>(s + g * S);
+    const float keep = (i < n0) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int q4 = 0; q4 < S / 4; ++q4) {
+      const f32x4 x = row[q4], sc = sv[q4];
+      a[rt][4 * q4 + 0] = x.x * sc.x * keep;
+      a[rt][4 * q4 + 1] = x.y * sc.y * keep;
+      a[rt][4 * q4 + 2] = x.z * sc.z * keep;
+      a[rt][4 * q4 + 3] = x.w * sc.w * keep;
+    }
+  }
+  const __amdgpu_buffer_rsrc_t rb1 = make_rsrc(P1f, long(n1) * Mp * 4);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + (MODE == TAPS_STORE ? long(k) * n0 * n1 : 0),
+                                              MODE == TAPS_STORE ? long(n0) * n1 * 4 : 0);
+  auto bload = [&](int jt, float* b) {
+    const int j = 16 * jt + c16;
+#pragma unroll
+    for (int q4 = 0; q4 < S / 4; ++q4) {
+      const int off = (j < n1) ? (j * Mp + g * S + 4 * q4) * 4 : kOOB;
+      const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb1, off, 0, 0));
+      b[4 * q4 + 0] = v.x;
+      b[4 * q4 + 1] = v.y;
+      b[4 * q4 + 2] = v.z;
+      b[4 * q4 + 3] = v.w;
+    }
+  };
+  Reduce red{-INFINITY, 0.0, 0ull};
+  const bool rows_full = ibase + kRowsWave <= n0;
+  auto tile = [&](int jt, const float* b) {
+    f32x4 acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      acc[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < S; ++q) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[q], a[rt][q], acc[rt], 0, 0, 0);
+    }
+    const bool jfull = 16 * jt + 16 <= n1;
+    epilogue<MODE>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, rows_full && jfull, thrf, red, ro);
+  };
+  const int ntj = (n1 + 15) / 16;
+  float bA[S], bB[S];
+  bload(0, bA);
+  for (int jt = 0; jt < ntj; jt += 2) {
+    bload(jt + 1, bB);
+    tile(jt, bA);
+    if (jt + 1 >= ntj) break;
+    bload(jt + 2, bA);
+    tile(jt + 1, bB);
+  }
+  if (MODE == TAPS_REDUCE) reduce_store(red, rec + (long(k) * nrb + rb) * 4);
+}
+
+// Per-plane combination of the workgroup records (fixed order).
+__global__ void k_recon_plane_mfma(int nrb, int n2, const double* __restrict__ rec, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n2) return;
+  double mx = -INFINITY, ss = 0.0, cnt = 0.0;
+  for (int t = 0; t < nrb; ++t) {
+    const double* r = rec + (long(k) * nrb + t) * 4;
+    mx = fmax(mx, r[0]);
+    ss += r[1];
+    cnt += r[2];
+  }
+  out[long(k) * 4 + 0] = mx;
+  out[long(k) * 4 + 1] = ss;
+  out[long(k) * 4 + 2] = cnt;
+  out[long(k) * 4 + 3] = 0.0;
+}
+
+typedef void (*recon_fn)(dim3, hipStream_t, int, int, int, int, const float*, const void*, const double*,
+                         const double*, float, float*, double*);
+
+template <int KS, int MODE>
+void launch_bf16(dim3 grid, hipStream_t st, int n0, int n1, int nrb, int M, const float* P0f, const void* P1,
+                 const double* P2, const double* mw, float thr, float* out, double* rec) {
+  k_recon_bf16<KS, MODE><<<grid, kWaves * 64, 0, st>>>(n0, n1, nrb, M, P0f, static_cast<const __bf16*>(P1), P2, mw,
+                                                      thr, out, rec);
+}
+template <int S, int MODE>
+void launch_fp32(dim3 grid, hipStream_t st, int n0, int n1, int nrb, int M, const float* P0f, const void* P1,
+                 const double* P2, const double* mw, float thr, float* out, double* rec) {
+  k_recon_fp32<S, MODE><<<grid, kWaves * 64, 0, st>>>(n0, n1, nrb, M, P0f, static_cast<const float*>(P1), P2, mw,
+                                                     thr, out, rec);
+}
+
+}  // namespace
+
+namespace taps {
+
+// Accounting of one reconstruction call for the profiler family RECON:
+// flops = 2 n0 n1 n2 Mp (padded modes, as executed); bytes = stored field
+// (STORE) + factors read once.
+double recon_flops(int n0, int n1, int n2, int Mp) { return 2.0 * n0 * double(n1) * n2 * Mp; }
+
+taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double* const* d_Phi, int32_t M,
+                             const double* d_mode_w, taps_prec prec, taps_recon_mode mode, void* d_out, double thr,
+                             hipStream_t stream) {
+  const int n0 = n_pts[0], n1 = n_pts[1], n2 = n_pts[2];
+  const bool bf = (prec == TAPS_BF16);
+  const int Mp = bf ? 32 * cdiv(M, 32) : 16 * cdiv(M, 16);
+  if (long(n0) * n1 * 4 >= (1L << 31) || long(n1) * Mp * 4 >= (1L << 31))
+    return fail(h, TAPS_ERR_UNSUPPORTED, "plane %d x %d too large for 32-bit offsets", n0, n1);
+  const int nrb = cdiv(n0, kRowsWG);
+  if (long(nrb) * n2 >= (1L << 31)) return fail(h, TAPS_ERR_UNSUPPORTED, "grid too large");
+  Bump bump;
+  const size_t o_P0 = bump.take(size_t(n0) * Mp * 4);
+  const size_t o_P1 = bump.take(size_t(n1) * Mp * (bf ? 2 : 4));
+  const size_t o_R = bump.take(mode == TAPS_REDUCE ? size_t(n2) * nrb * 4 * 8 : 0);
+  TAPS_TRY(need_ws(h, bump.off, stream));
+  char* ws = static_cast<char*>(h->ws);
+  float* P0f = reinterpret_cast<float*>(ws + o_P0);
+  void* P1 = ws + o_P1;
+  double* rec = reinterpret_cast<double*>(ws + o_R);
+  k_recon_convert<float><<<cdiv(long(n0) * Mp, 256), 256, 0, stream>>>(n0, M, Mp, d_Phi[0], P0f);
+  TAPS_LAUNCHED(h, "k_recon_convert");
+  if (bf)
+    k_recon_convert<__bf16><<<cdiv(long(n1) * Mp, 256), 256, 0, stream>>>(n1, M, Mp, d_Phi[1],
+                                                                          static_cast<__bf16*>(P1));
+  else
+    k_recon_convert<float><<<cdiv(long(n1) * Mp, 256), 256, 0, stream>>>(n1, M, Mp, d_Phi[1],
+                                                                         static_cast<float*>(P1));
+  TAPS_LAUNCHED(h, "k_recon_convert");
+  const dim3 grid(unsigned(long(nrb) * n2));
+  float* out = mode == TAPS_STORE ? static_cast<float*>(d_out) : nullptr;
+  recon_fn fn = nullptr;
+  const bool st = (mode == TAPS_STORE);
+  if (bf) {
+    if (Mp == 32) fn = st ? launch_bf16<1, TAPS_STORE> : launch_bf16<1, TAPS_REDUCE>;
+    else fn = st ? launch_bf16<2, TAPS_STORE> : launch_bf16<2, TAPS_REDUCE>;
+  } else {
+    switch (Mp / 4) {
+      case 4: fn = st ? launch_fp32<4, TAPS_STORE> : launch_fp32<4, TAPS_REDUCE>; break;
+      case 8: fn = st ? launch_fp32<8, TAPS_STORE> : launch_fp32<8, TAPS_REDUCE>; break;
+      case 12: fn = st ? launch_fp32<12, TAPS_STORE> : launch_fp32<12, TAPS_REDUCE>; break;
+      default: fn = st ? launch_fp32<16, TAPS_STORE> : launch_fp32<16, TAPS_REDUCE>; break;
+    }
+  }
+  size_t slot;
+  TAPS_TRY(prof_begin(h, TAPS_PROF_RECON, stream, &slot));
+  // largest float <= thr (for u > thr decided in FP32 exactly as in FP64)
+  float thrf = float(thr);
+  if (double(thrf) > thr) thrf = std::nextafter(thrf, -INFINITY);
+  fn(grid, stream, n0, n1, nrb, M, P0f, P1, d_Phi[2], d_mode_w, thrf, out, rec);
+  TAPS_LAUNCHED(h, bf ? "k_recon_bf16" : "k_recon_fp32");
+  TAPS_TRY(prof_end(h, slot, recon_flops(n0, n1, n2, Mp),
+                    (st ? 4.0 * n0 * double(n1) * n2 : 0.0) + 4.0 * (double(n0) + n1) * Mp, stream));
+  if (mode == TAPS_REDUCE) {
+    k_recon_plane_mfma<<<cdiv(n2, 64), 64, 0, stream>>>(nrb, n2, rec, static_cast<double*>(d_out));
+    TAPS_LAUNCHED(h, "k_recon_plane_mfma");
+  }
+  return TAPS_OK;
+}
+
 }  // namespace taps

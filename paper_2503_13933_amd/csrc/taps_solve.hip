@@ -509,12 +509,15 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
             const double a = (ar < M && kx < M) ? sPinv[kx * M + ar] : 0.0;
             acc = mfma16x16x4(a, bf[kk], acc);
           }
+          // (elements copied out by name: indexing the accumulator vector in the
+          // store loop is not reliably compiled)
+          const double zv[4] = {acc.x, acc.y, acc.z, acc.w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int q = tr * 16 + (lane >> 4) + 4 * i;
-            if (q < M && col < ncol) Zp[q * P16 + col] = acc[i];
-            bstore(rz, (q < M && col < waM) ? (q * wM + col) * 8 : kOOB, acc[i]);
-            bstore(ry, (q < M && col == waM) ? q * 8 : kOOB, acc[i]);
+            if (q < M && col < ncol) Zp[q * P16 + col] = zv[i];
+            bstore(rz, (q < M && col < waM) ? (q * wM + col) * 8 : kOOB, zv[i]);
+            bstore(ry, (q < M && col == waM) ? q * 8 : kOOB, zv[i]);
           }
         }
       }
