@@ -10,6 +10,7 @@
  *   taps_gauss_points / taps_shape1d     1D C-HiDeNN basis at points      (Sec. 2.1)
  *   taps_source1d                        separable source factors           (Sec. 2.4)
  *   taps_assemble1d                      1D quadrature matrices and loads  (Sec. 2.5)
+ *   taps_band_apply                      banded 1D matrix x factor columns
  *   taps_contract                        Grams, Hadamard couplings, force  (Sec. 2.5)
  *   taps_solve_dim                       block-banded (n_d M) dim solve    (Sec. 2.6)
  *   taps_residual / taps_balance         projected residual, mode balance  (Sec. 2.5-2.6)
@@ -142,6 +143,19 @@ taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_
                             const int32_t* kinds, const double* d_coef_g,
                             const int32_t* bnode, double* d_band, int32_t n_loads,
                             const double* d_f_g, double* d_F, hipStream_t stream);
+
+/* Banded 1D matrix times a block of columns (Sec. 2.5: the 1D matrices act on
+ * factor columns; the slab chain builds its carried-field loads A_d V_d and the
+ * mode-compression loads M_d W_d this way):
+ *   d_Y[i*ldy + c] = alpha * scale[c] * sum_j A[i][j] d_X[j*ldx + c],
+ * i < n, c < n_cols, A one band of taps_assemble1d (n x (4s+3), half-bandwidth
+ * w = 2s+1), scale = d_scale (device, n_cols values) or all ones when NULL.
+ * ldx, ldy >= n_cols; X and Y must not overlap.  TAPS_ERR_INVALID for null
+ * pointers, n < 1, n_cols < 0, s outside 0..TAPS_MAX_S or short leading
+ * dimensions; n_cols = 0 enqueues nothing. */
+taps_status taps_band_apply(taps_handle_t h, int32_t n, int32_t s, const double* d_band,
+                            int32_t n_cols, const double* d_X, int32_t ldx, const double* d_scale,
+                            double alpha, double* d_Y, int32_t ldy, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Separated problem (Sec. 2.5): operator sum_tau gamma_tau (x)_d A^{tau}_d

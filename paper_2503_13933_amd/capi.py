@@ -25,7 +25,7 @@ FUNCTIONS = (
     "taps_create", "taps_destroy", "taps_last_error", "taps_reserve", "taps_workspace_bytes",
     "taps_gauss_points", "taps_shape1d", "taps_source1d", "taps_assemble1d", "taps_contract",
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
-    "taps_reconstruct", "taps_profile_enable", "taps_profile_read", "taps_als_batched",
+    "taps_reconstruct", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
 )
 PROF_SOLVE, PROF_CONTRACT, PROF_RECON = 0, 1, 2
 
@@ -84,6 +84,7 @@ def lib():
             "taps_profile_enable": (i32, [vp, i32]),
             "taps_als_batched": (i32, [vp, i32, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), vp]),
             "taps_profile_read": (i32, [vp, i32, P(i32), P(dbl), P(dbl), P(dbl)]),
+            "taps_band_apply": (i32, [vp, i32, i32, vp, i32, vp, i32, vp, dbl, vp, i32, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -205,6 +206,19 @@ def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, stream=None
     h.check(lib().taps_als(h.h, C.byref(prob), _ptr_array(U), tol, iter_max, C.byref(sweeps), C.byref(rho), hist,
                            _stream(stream)), "taps_als")
     return sweeps.value, rho.value, list(hist[: sweeps.value])
+
+
+def taps_band_apply(h: Handle, s: int, band, X, Y, alpha: float = 1.0, scale=None, stream=None):
+    """Y = alpha * (A X) * scale (per column), A = band (n x (4s+3)).  X and Y
+    may be column slices of wider row-major tensors (their row strides are
+    passed as leading dimensions)."""
+    n, ncols = X.shape
+    if X.stride(1) != 1 or Y.stride(1) != 1 or not band.is_contiguous():
+        raise TapsError("rows must be contiguous")
+    if Y.shape != X.shape:
+        raise TapsError("X and Y shapes differ")
+    h.check(lib().taps_band_apply(h.h, n, s, band.data_ptr(), ncols, X.data_ptr(), X.stride(0), _ptr(scale),
+                                  alpha, Y.data_ptr(), Y.stride(0), _stream(stream)), "taps_band_apply")
 
 
 def taps_interp1d(h: Handle, N, first, n_nodes: int, U, Phi, stream=None):

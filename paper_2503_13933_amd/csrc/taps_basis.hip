@@ -307,6 +307,20 @@ __global__ void k_interp(int npts, int L, const double* __restrict__ N, const in
   Phi[idx] = v;
 }
 
+// Y = alpha diag-scaled (A X): one thread per output entry (i, c); the band
+// row i is read once per column, X rows i-w..i+w stay in cache across c.
+__global__ void k_band_apply(int n, int w, const double* __restrict__ band, int ncols, const double* __restrict__ X,
+                             int ldx, const double* __restrict__ scale, double alpha, double* __restrict__ Y, int ldy) {
+  const long idx = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  if (idx >= long(n) * ncols) return;
+  const int i = int(idx / ncols), c = int(idx - long(i) * ncols);
+  const int BW = 2 * w + 1;
+  const int j0 = max(0, i - w), j1 = min(n - 1, i + w);
+  double v = 0.0;
+  for (int j = j0; j <= j1; ++j) v += band[long(i) * BW + (j - i + w)] * X[long(j) * ldx + c];
+  Y[long(i) * ldy + c] = alpha * (scale ? scale[c] : 1.0) * v;
+}
+
 BasisArgs basis_args(const taps_basis1d_t* b) {
   BasisArgs B;
   B.x = b->d_x;
@@ -445,6 +459,20 @@ taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_
                                                     d_f_g, d_F);
     TAPS_LAUNCHED(h, "k_load");
   }
+  return TAPS_OK;
+}
+
+taps_status taps_band_apply(taps_handle_t h, int32_t n, int32_t s, const double* d_band, int32_t n_cols,
+                            const double* d_X, int32_t ldx, const double* d_scale, double alpha, double* d_Y,
+                            int32_t ldy, hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (n < 1 || n_cols < 0 || s < 0 || s > TAPS_MAX_S) return fail(h, TAPS_ERR_INVALID, "n=%d n_cols=%d s=%d", n, n_cols, s);
+  if (ldx < n_cols || ldy < n_cols) return fail(h, TAPS_ERR_INVALID, "leading dimensions %d, %d < %d", ldx, ldy, n_cols);
+  if (n_cols == 0) return TAPS_OK;
+  if (!d_band || !d_X || !d_Y) return fail(h, TAPS_ERR_INVALID, "null pointer");
+  k_band_apply<<<grid_for(long(n) * n_cols, 256), 256, 0, stream>>>(n, 2 * s + 1, d_band, n_cols, d_X, ldx, d_scale,
+                                                                     alpha, d_Y, ldy);
+  TAPS_LAUNCHED(h, "k_band_apply");
   return TAPS_OK;
 }
 
