@@ -16,6 +16,8 @@
  *   taps_residual / taps_balance         projected residual, mode balance  (Sec. 2.5-2.6)
  *   taps_sweep / taps_als                Algorithm 1 driver                (Sec. 2.6)
  *   taps_interp1d / taps_reconstruct     TD interpolation on grids         (Sec. 2.3)
+ *   taps_canonicalize, taps_mlp_*,       learned warm start of a slab's factors
+ *   taps_adam_step
  *
  * Conventions (every call):
  *   - Pointers named d_* are device memory owned by the caller; everything else
@@ -308,6 +310,61 @@ typedef enum { TAPS_STORE = 0, TAPS_REDUCE = 1 } taps_recon_mode;
 taps_status taps_reconstruct(taps_handle_t h, const int32_t* n_pts, const double* const* d_Phi,
                              int32_t M, const double* d_mode_w, taps_prec prec,
                              taps_recon_mode mode, void* d_out, double thr, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned warm start.  A slab's converged factors are stored in a canonical
+ * form before a network learns them, and the network's coarse factors are
+ * prolongated with taps_shape1d + taps_interp1d.
+ *
+ * Canonical form of a CP field u = sum_m prod_d U_d[:, m] (the field is
+ * unchanged): modes ordered by lambda_m = prod_d ||U_d[:, m]||_2, largest
+ * first (ties keep the lower index first); for d >= 1 every column scaled to
+ * unit 2-norm with the sign that makes its largest-magnitude entry positive
+ * (the first such entry on ties); scale and sign go into U_0.  A mode with a
+ * zero column is left unscaled.  d_U[d] (n[d] x M) in, d_out[d] out (distinct
+ * buffers).  One workgroup; D <= TAPS_MAX_DIMS, M <= TAPS_MAX_M. */
+taps_status taps_canonicalize(taps_handle_t h, int32_t D, const int32_t* n, int32_t M,
+                              const double* const* d_U, double* const* d_out, hipStream_t stream);
+
+/* Multilayer perceptron x_{l+1} = GELU(W_l x_l + b_l), last layer linear,
+ * GELU(z) = z Phi(z).  Weights are BF16 (bit patterns, uint16), row-major
+ * width[l+1] x ldw(l) with ldw(l) = width[l] rounded up to a multiple of 32
+ * and zero padding; biases FP32.  Each layer's input is rounded to BF16
+ * (nearest, ties to even) and multiplied on the matrix cores with FP32
+ * accumulation (v_mfma_f32_16x16x32_bf16); the gradients are FP32 (FP32
+ * matrix-core products), the BF16 rounding passed through unchanged. */
+#define TAPS_MLP_MAX_LAYERS 8
+typedef struct {
+  int32_t n_layers;                              /* 1..TAPS_MLP_MAX_LAYERS */
+  int32_t width[TAPS_MLP_MAX_LAYERS + 1];        /* width[0] inputs .. width[L] outputs, <= 4096 */
+  const uint16_t* d_W[TAPS_MLP_MAX_LAYERS];      /* BF16 weights (device) */
+  const float* d_b[TAPS_MLP_MAX_LAYERS];         /* FP32 biases (device) */
+} taps_mlp_t;
+/* Bytes of the activation cache a forward pass leaves for the backward pass
+ * with batch B.  Layout, layer by layer, each block starting on a 256-byte
+ * boundary: the layer's BF16 input (B x ldw(l), zero padded), then its FP32
+ * pre-activation z (B x width[l+1]). */
+size_t taps_mlp_cache_bytes(const taps_mlp_t* net, int32_t B);
+/* Forward: d_X (B x width[0], FP32, row-major) -> d_Y (B x width[L], FP32);
+ * d_cache (taps_mlp_cache_bytes) receives what the backward pass needs. */
+taps_status taps_mlp_forward(taps_handle_t h, const taps_mlp_t* net, int32_t B, const float* d_X,
+                             void* d_cache, float* d_Y, hipStream_t stream);
+/* Backward from dL/dY (B x width[L], FP32): d_gW[l] (width[l+1] x ldw(l),
+ * FP32, padding written as 0) and d_gb[l] (width[l+1]) receive the gradients.
+ * Uses the handle's workspace for the intermediate input gradients. */
+taps_status taps_mlp_backward(taps_handle_t h, const taps_mlp_t* net, int32_t B, const void* d_cache,
+                              const float* d_dY, float* const* d_gW, float* const* d_gb, hipStream_t stream);
+/* Mean squared error over n entries: d_loss[0] = sum (Y-T)^2 / n (FP64),
+ * d_dY = 2 (Y - T) / n (FP32). */
+taps_status taps_mlp_mse(taps_handle_t h, int64_t n, const float* d_Y, const float* d_T, float* d_dY,
+                         double* d_loss, hipStream_t stream);
+/* One Adam step (bias-corrected, step number t >= 1) on n FP32 master values:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
+ * d_p16 (nullable) receives the updated values rounded to BF16. */
+taps_status taps_adam_step(taps_handle_t h, int64_t n, float* d_p, const float* d_g, float* d_m, float* d_v,
+                           double lr, double b1, double b2, double eps, int32_t t, uint16_t* d_p16,
+                           hipStream_t stream);
 
 #ifdef __cplusplus
 }

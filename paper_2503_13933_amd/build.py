@@ -15,6 +15,7 @@ SOURCES = [
     "taps_batch.hip",
     "taps_reconstruct.hip",
     "taps_reconstruct_mfma.hip",
+    "taps_mlp.hip",
 ]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

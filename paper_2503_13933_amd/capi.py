@@ -26,7 +26,10 @@ FUNCTIONS = (
     "taps_gauss_points", "taps_shape1d", "taps_source1d", "taps_assemble1d", "taps_contract",
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
     "taps_reconstruct", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
+    "taps_canonicalize", "taps_mlp_cache_bytes", "taps_mlp_forward", "taps_mlp_backward", "taps_mlp_mse",
+    "taps_adam_step",
 )
+MLP_MAX_LAYERS = 8
 PROF_SOLVE, PROF_CONTRACT, PROF_RECON = 0, 1, 2
 
 
@@ -49,6 +52,11 @@ class Problem(C.Structure):
         ("d_load_ptr", C.c_void_p * MAX_DIMS), ("d_load_idx", C.c_void_p * MAX_DIMS),
         ("d_fixed", C.c_void_p * MAX_DIMS),
     ]
+
+
+class MLP(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("width", C.c_int32 * (MLP_MAX_LAYERS + 1)),
+                ("d_W", C.c_void_p * MLP_MAX_LAYERS), ("d_b", C.c_void_p * MLP_MAX_LAYERS)]
 
 
 _lib = None
@@ -85,6 +93,12 @@ def lib():
             "taps_als_batched": (i32, [vp, i32, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), vp]),
             "taps_profile_read": (i32, [vp, i32, P(i32), P(dbl), P(dbl), P(dbl)]),
             "taps_band_apply": (i32, [vp, i32, i32, vp, i32, vp, i32, vp, dbl, vp, i32, vp]),
+            "taps_canonicalize": (i32, [vp, i32, P(i32), i32, P(vp), P(vp), vp]),
+            "taps_mlp_cache_bytes": (sz, [P(MLP), i32]),
+            "taps_mlp_forward": (i32, [vp, P(MLP), i32, vp, vp, vp, vp]),
+            "taps_mlp_backward": (i32, [vp, P(MLP), i32, vp, vp, P(vp), P(vp), vp]),
+            "taps_mlp_mse": (i32, [vp, C.c_int64, vp, vp, vp, vp, vp]),
+            "taps_adam_step": (i32, [vp, C.c_int64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -219,6 +233,48 @@ def taps_band_apply(h: Handle, s: int, band, X, Y, alpha: float = 1.0, scale=Non
         raise TapsError("X and Y shapes differ")
     h.check(lib().taps_band_apply(h.h, n, s, band.data_ptr(), ncols, X.data_ptr(), X.stride(0), _ptr(scale),
                                   alpha, Y.data_ptr(), Y.stride(0), _stream(stream)), "taps_band_apply")
+
+
+def taps_canonicalize(h: Handle, Us, outs, stream=None):
+    n = (C.c_int32 * len(Us))(*[int(u.shape[0]) for u in Us])
+    h.check(lib().taps_canonicalize(h.h, len(Us), n, int(Us[0].shape[1]), _ptr_array(Us), _ptr_array(outs),
+                                    _stream(stream)), "taps_canonicalize")
+
+
+def mlp_struct(widths, Ws, bs):
+    """taps_mlp_t over device tensors (Ws: uint16/bfloat16 width[l+1] x ldw, bs: float32)."""
+    m = MLP()
+    m.n_layers = len(widths) - 1
+    for l, w in enumerate(widths):
+        m.width[l] = int(w)
+    for l, (W, b) in enumerate(zip(Ws, bs)):
+        m.d_W[l] = _ptr(W)
+        m.d_b[l] = _ptr(b)
+    return m
+
+
+def taps_mlp_cache_bytes(net: MLP, B: int) -> int:
+    return int(lib().taps_mlp_cache_bytes(C.byref(net), B))
+
+
+def taps_mlp_forward(h: Handle, net: MLP, X, cache, Y, stream=None):
+    h.check(lib().taps_mlp_forward(h.h, C.byref(net), int(X.shape[0]), _ptr(X), _ptr(cache), _ptr(Y),
+                                   _stream(stream)), "taps_mlp_forward")
+
+
+def taps_mlp_backward(h: Handle, net: MLP, B: int, cache, dY, gWs, gbs, stream=None):
+    h.check(lib().taps_mlp_backward(h.h, C.byref(net), B, _ptr(cache), _ptr(dY), _ptr_array(gWs), _ptr_array(gbs),
+                                    _stream(stream)), "taps_mlp_backward")
+
+
+def taps_mlp_mse(h: Handle, Y, T, dY, loss, stream=None):
+    h.check(lib().taps_mlp_mse(h.h, int(Y.numel()), _ptr(Y), _ptr(T), _ptr(dY), _ptr(loss), _stream(stream)),
+            "taps_mlp_mse")
+
+
+def taps_adam_step(h: Handle, p, g, m, v, lr, t, p16=None, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    h.check(lib().taps_adam_step(h.h, int(p.numel()), _ptr(p), _ptr(g), _ptr(m), _ptr(v), lr, b1, b2, eps, t,
+                                 _ptr(p16), _stream(stream)), "taps_adam_step")
 
 
 def taps_interp1d(h: Handle, N, first, n_nodes: int, U, Phi, stream=None):

@@ -166,3 +166,12 @@ def shrink(case, factor: int):
         fixed = tuple(sorted({0 if f == 0 else n - 1 for f in ax.fixed}))
         axes.append(replace(ax, n=n, fixed=fixed))
     return replace(case, axes=tuple(axes))
+
+
+def mlp_init(widths, seed: int = 0):
+    """Seeded initial weights of the warm-start network: W_l ~ N(0, 2 / in)
+    (out x in), zero biases; float64 arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ws = [rng.standard_normal((o, i)) * np.sqrt(2.0 / i) for i, o in zip(widths[:-1], widths[1:])]
+    bs = [np.zeros(o) for o in widths[1:]]
+    return Ws, bs
