@@ -222,3 +222,55 @@ def train(h, net, X, T, steps, lr, batch, seed):
 
 def restart_plain(rho1, rho2, plain_median_rho1):
     return bool(rho1 > plain_median_rho1 or rho2 > rho1)
+
+
+# ------------------------------------------------------------- streaming
+
+
+def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, on_done=None):
+    """Continuous batching of Algorithm 1: up to ``slots`` slabs in flight,
+    one batched sweep (taps_als_batched) per round; a slab leaves as soon as
+    its projected residual reaches tol or it has run ``cap`` sweeps, and the
+    next waiting slab takes its place, so the matrix cores stay busy while
+    slabs converge at different speeds.
+
+    With U_plain and median_rho1 given, U holds warm starts and the fallback
+    rule is applied after sweep 2: a slab whose warm start lost (sweep-1
+    residual above median_rho1, or growing from sweep 1 to 2) restarts from
+    its U_plain factors with a fresh sweep count.
+    Returns (sweeps run per slab, final residual per slab, number of restarts)."""
+    from collections import deque
+    n = len(probs)
+    waiting = deque(range(n))
+    active = []
+    count = [0] * n          # sweeps since the (re)start
+    total = [0] * n          # sweeps run
+    rho = [float("nan")] * n
+    rho1 = [float("nan")] * n
+    restarted = set()
+    while waiting or active:
+        while len(active) < slots and waiting:
+            active.append(waiting.popleft())
+        _, r = capi.taps_als_batched(h, [probs[i].struct for i in active], [U[i] for i in active], 0.0, 1)
+        keep = []
+        for i, ri in zip(active, r):
+            count[i] += 1
+            total[i] += 1
+            rho[i] = ri
+            if U_plain is not None and i not in restarted:
+                if count[i] == 1:
+                    rho1[i] = ri
+                elif count[i] == 2 and restart_plain(rho1[i], ri, median_rho1):
+                    restarted.add(i)
+                    for u, u0 in zip(U[i], U_plain[i]):
+                        u.copy_(u0)
+                    count[i] = 0
+                    keep.append(i)
+                    continue
+            if ri <= tol or count[i] >= cap:
+                if on_done is not None:
+                    on_done(i)
+            else:
+                keep.append(i)
+        active = keep
+    return total, rho, len(restarted)
