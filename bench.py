@@ -44,6 +44,10 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix)
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
+# Memory traffic of the batched dim solve per algorithmic flop, from two
+# rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a
+# 1 GiB copy), valid for the solve source with this SHA-256 prefix only.
+SOLVE_TRAFFIC = {"bytes_per_flop": 0.2813, "source_sha256": "c9a856e7e0610480"}
 
 
 def log(msg):
@@ -200,6 +204,10 @@ def main():
         log(f"plain form: one slab {1.0 / plain['value']:.3f} s, {sw} sweeps")
 
     value = N * args.steps / el_w
+    import hashlib
+    src = os.path.join(ROOT, "paper_2503_13933_amd", "csrc", "taps_solve.hip")
+    same_kernel = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == SOLVE_TRAFFIC["source_sha256"]
+    traffic = SOLVE_TRAFFIC["bytes_per_flop"] * fl_solve / n_solve if (same_kernel and n_solve) else None
     achieved = (fl_solve / n_solve) / (ms_solve / n_solve * 1e-3) / 1e12 if n_solve else 0.0
     rec_tf = (fl_rec / n_rec) / (ms_rec / n_rec * 1e-3) / 1e12 if n_rec else 0.0
     out = {
@@ -246,7 +254,8 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM/MALL counters, calibrated)",
             "launches": n_solve,
             "avg_launch_ms": ms_solve / max(1, n_solve),
             "flops_per_launch": fl_solve / max(1, n_solve),
