@@ -14,8 +14,8 @@ interface the device code follows):
     fine nodes interpolates the coarse nodal values with the C-HiDeNN basis of
     the coarse grid.  By the Kronecker-delta property sampling after
     prolongation returns the coarse values.
-  * input features: (P, r, k) mapped linearly to [-1, 1] over their sampling
-    ranges, then the carried field sampled on a 4 x 4 x 4 coarse grid.
+  * input features: (P, r, k, y0) mapped linearly to [-1, 1] over their
+    sampling ranges, then the carried field sampled on a 4 x 4 x 4 coarse grid.
   * fallback: a warm start is dropped for the plain initialisation when its
     residual after sweep 1 exceeds the median of the plain initialisation's
     sweep-1 residuals, or when the residual grows from sweep 1 to sweep 2.
@@ -24,7 +24,7 @@ import numpy as np
 
 from . import basis, reconstruct
 
-PARAM_RANGES = {"power": (100.0, 300.0), "radius": (0.030, 0.080), "k": (0.010, 0.030)}
+PARAM_RANGES = {"power": (100.0, 300.0), "radius": (0.030, 0.080), "k": (0.010, 0.030), "y0": (0.3, 0.7)}
 
 
 def canonicalize(U):

@@ -1,6 +1,6 @@
 """Learned warm start of a slab's factors (driver above the C ABI).
 
-A network maps slab features -- (P, r, k) scaled to [-1, 1] and the carried
+A network maps slab features -- (P, r, k, y0) scaled to [-1, 1] and the carried
 initial condition sampled on a 4 x 4 x 4 coarse grid -- to the canonical
 factors of the converged slab solution in y, z and t, sampled at coarse nodes.
 Its prediction, prolongated to the fine grid by C-HiDeNN interpolation of the
@@ -24,7 +24,7 @@ import torch
 from . import capi
 
 F32, F64 = torch.float32, torch.float64
-PARAM_RANGES = {"power": (100.0, 300.0), "radius": (0.030, 0.080), "k": (0.010, 0.030)}
+PARAM_RANGES = {"power": (100.0, 300.0), "radius": (0.030, 0.080), "k": (0.010, 0.030), "y0": (0.3, 0.7)}
 
 
 def ldw(w: int) -> int:

@@ -71,8 +71,8 @@ def test_ic_features_of_separable_field():
 
 
 def test_param_features_and_fallback_rule():
-    lo = W.heat_slab(8, 8, 8, 8, power=100.0, radius=0.03, k=0.01)
-    hi = W.heat_slab(8, 8, 8, 8, power=300.0, radius=0.08, k=0.03)
+    lo = W.heat_slab(8, 8, 8, 8, power=100.0, radius=0.03, k=0.01, y0=0.3)
+    hi = W.heat_slab(8, 8, 8, 8, power=300.0, radius=0.08, k=0.03, y0=0.7)
     assert np.allclose(warmstart.param_features(lo), -1.0) and np.allclose(warmstart.param_features(hi), 1.0)
     assert warmstart.restart_plain(2.0, 1.0, 1.5)          # worse than the plain median
     assert warmstart.restart_plain(1.0, 1.2, 1.5)          # grows from sweep 1 to 2
