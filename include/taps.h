@@ -15,6 +15,7 @@
  *   taps_solve_dim                       block-banded (n_d M) dim solve    (Sec. 2.6)
  *   taps_residual / taps_balance         projected residual, mode balance  (Sec. 2.5-2.6)
  *   taps_sweep / taps_als                Algorithm 1 driver                (Sec. 2.6)
+ *   taps_als_batched, taps_autotune      many problems at once, HIP graphs
  *   taps_interp1d / taps_reconstruct     TD interpolation on grids         (Sec. 2.3)
  *   taps_canonicalize, taps_mlp_*,       learned warm start of a slab's factors
  *   taps_adam_step
@@ -265,6 +266,34 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
 taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* probs,
                              double* const* d_U, double tol, int32_t iter_max, int32_t* sweeps,
                              double* rho, hipStream_t stream);
+
+/* Tuning of the batched driver.  graph_sweeps = 0 launches every kernel of a
+ * sweep from the host; K > 0 captures K consecutive sweeps (every launch, no
+ * host work in between) into one HIP graph, replays it, and checks the
+ * residuals after each replay, so a slab that reaches tol mid-graph runs up
+ * to K-1 extra sweeps and sweeps[b] counts in steps of K.  The graph is
+ * re-captured when the set of unconverged slabs or the batch layout changes,
+ * and kept on the handle otherwise (across calls).  Graphs are not used while
+ * kernel timing is enabled.  Valid K: 0..16. */
+typedef struct {
+  int32_t graph_sweeps;
+} taps_tuning_t;
+taps_status taps_set_tuning(taps_handle_t h, const taps_tuning_t* t);
+taps_status taps_get_tuning(taps_handle_t h, taps_tuning_t* t);
+
+/* Timing autotuner of the batched driver.  For the candidates graph_sweeps =
+ * 0, 1, 2, 4 it times taps_als_batched on this batch (4 sweeps after one
+ * untimed run that also captures the graph; HIP events on `stream`), keeps the
+ * smallest K whose time per sweep is within 3 % of the fastest, applies it to
+ * the handle and returns it in *chosen; ms_per_sweep (nullable, 4 doubles)
+ * receives the measured times.  The factors d_U are saved first and restored
+ * before returning (device copies, allocated here).  With cache_path non-NULL
+ * the choice is looked up in, or appended to, a JSON file keyed by the batch
+ * shape (B, D, M, s, and per dim the largest n, R_cols and n_kinds); a key
+ * already there is applied without timing (ms_per_sweep then all -1). */
+taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* probs, double* const* d_U,
+                          const char* cache_path, taps_tuning_t* chosen, double* ms_per_sweep,
+                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing.  While enabled, each launch of a timed kernel family is

@@ -16,6 +16,7 @@ SOURCES = [
     "taps_reconstruct.hip",
     "taps_reconstruct_mfma.hip",
     "taps_mlp.hip",
+    "taps_tune.hip",
 ]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

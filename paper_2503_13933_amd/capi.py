@@ -27,7 +27,7 @@ FUNCTIONS = (
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
     "taps_reconstruct", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
     "taps_canonicalize", "taps_mlp_cache_bytes", "taps_mlp_forward", "taps_mlp_backward", "taps_mlp_mse",
-    "taps_adam_step",
+    "taps_adam_step", "taps_set_tuning", "taps_get_tuning", "taps_autotune",
 )
 MLP_MAX_LAYERS = 8
 PROF_SOLVE, PROF_CONTRACT, PROF_RECON = 0, 1, 2
@@ -52,6 +52,10 @@ class Problem(C.Structure):
         ("d_load_ptr", C.c_void_p * MAX_DIMS), ("d_load_idx", C.c_void_p * MAX_DIMS),
         ("d_fixed", C.c_void_p * MAX_DIMS),
     ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("graph_sweeps", C.c_int32)]
 
 
 class MLP(C.Structure):
@@ -99,6 +103,9 @@ def lib():
             "taps_mlp_backward": (i32, [vp, P(MLP), i32, vp, vp, P(vp), P(vp), vp]),
             "taps_mlp_mse": (i32, [vp, C.c_int64, vp, vp, vp, vp, vp]),
             "taps_adam_step": (i32, [vp, C.c_int64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i32, vp, vp]),
+            "taps_set_tuning": (i32, [vp, P(Tuning)]),
+            "taps_get_tuning": (i32, [vp, P(Tuning)]),
+            "taps_autotune": (i32, [vp, i32, P(Problem), P(vp), C.c_char_p, P(Tuning), P(dbl), vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -220,6 +227,29 @@ def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, stream=None
     h.check(lib().taps_als(h.h, C.byref(prob), _ptr_array(U), tol, iter_max, C.byref(sweeps), C.byref(rho), hist,
                            _stream(stream)), "taps_als")
     return sweeps.value, rho.value, list(hist[: sweeps.value])
+
+
+def taps_set_tuning(h: Handle, graph_sweeps: int):
+    t = Tuning(graph_sweeps)
+    h.check(lib().taps_set_tuning(h.h, C.byref(t)), "taps_set_tuning")
+
+
+def taps_get_tuning(h: Handle) -> int:
+    t = Tuning()
+    h.check(lib().taps_get_tuning(h.h, C.byref(t)), "taps_get_tuning")
+    return t.graph_sweeps
+
+
+def taps_autotune(h: Handle, probs, Us, cache_path=None, stream=None):
+    """Returns (chosen graph_sweeps, ms per sweep of candidates 0, 1, 2, 4)."""
+    B = len(probs)
+    arr = (Problem * B)(*probs)
+    t = Tuning()
+    ms = (C.c_double * 4)()
+    path = cache_path.encode() if cache_path else None
+    h.check(lib().taps_autotune(h.h, B, arr, _ptr_array([u for U in Us for u in U]), path, C.byref(t), ms,
+                                _stream(stream)), "taps_autotune")
+    return t.graph_sweeps, list(ms)
 
 
 def taps_band_apply(h: Handle, s: int, band, X, Y, alpha: float = 1.0, scale=None, stream=None):

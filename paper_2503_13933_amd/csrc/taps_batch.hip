@@ -305,17 +305,18 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   if (rlds > 160 * 1024 - 4096) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", rlds);
   TAPS_TRY(allow_lds(h, kb_gram_partial, glds, &gram_lds_allowed));
   TAPS_TRY(allow_lds(h, kb_residual_part, rlds, &res_lds_allowed));
+  for (int d = 0; d < D; ++d) TAPS_TRY(solve_batched_prepare(h, M, p0.s[d]));
 
-  auto refresh = [&](int e, int nact) -> taps_status {
+  auto refresh = [&](int e, int nact, hipStream_t st) -> taps_status {
     size_t slot;
-    TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
-    kb_gram_partial<<<dim3(Z.max_chunks, nact), 256, glds, stream>>>(d_prob, d_active, e);
+    TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
+    kb_gram_partial<<<dim3(Z.max_chunks, nact), 256, glds, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_partial");
-    kb_gram_sum<<<dim3(Z.max_gram, nact), 256, 0, stream>>>(d_prob, d_active, e);
+    kb_gram_sum<<<dim3(Z.max_gram, nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_sum");
-    kb_lgram_partial<<<dim3(Z.max_ctiles, Z.max_splits, nact), 256, 0, stream>>>(d_prob, d_active, e);
+    kb_lgram_partial<<<dim3(Z.max_ctiles, Z.max_splits, nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_lgram_partial");
-    kb_lgram_sum<<<dim3(Z.max_lgram, nact), 256, 0, stream>>>(d_prob, d_active, e);
+    kb_lgram_sum<<<dim3(Z.max_lgram, nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_lgram_sum");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -324,16 +325,16 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       fl += K * (2.0 * bw * n * M + 2.0 * n * M * M) + 2.0 * n * Rc * M;
       by += 8.0 * (n * M + K * n * bw + n * Rc + K * MM + Rc * M);
     }
-    return prof_end(h, slot, fl, by, stream);
+    return prof_end(h, slot, fl, by, st);
   };
-  auto system = [&](int d, int nact) -> taps_status {
+  auto system = [&](int d, int nact, hipStream_t st) -> taps_status {
     size_t slot;
-    TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
-    kb_couple<<<dim3(Z.max_cpl, nact), 256, 0, stream>>>(d_prob, d_cpl, d_active, d, D);
+    TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
+    kb_couple<<<dim3(Z.max_cpl, nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_couple");
-    kb_load_weights<<<dim3(Z.max_wt, nact), 256, 0, stream>>>(d_prob, d_wa, d_active, d, D);
+    kb_load_weights<<<dim3(Z.max_wt, nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_weights");
-    kb_force<<<dim3(Z.max_rblocks, nact), 256, 0, stream>>>(d_prob, d_active, d);
+    kb_force<<<dim3(Z.max_rblocks, nact), 256, 0, st>>>(d_prob, d_active, d);
     TAPS_LAUNCHED(h, "kb_force");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -342,26 +343,24 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       fl += 2.0 * n * Rc * M;
       by += 8.0 * (n * Rc + Rc * M + n * M);
     }
-    return prof_end(h, slot, fl, by, stream);
+    return prof_end(h, slot, fl, by, st);
   };
-  auto residual_parts = [&](int d, int nact) -> taps_status {
-    kb_residual_part<<<dim3(Z.max_rchunks, nact), 256, rlds, stream>>>(d_prob, d_active, d);
+  auto residual_parts = [&](int d, int nact, hipStream_t st) -> taps_status {
+    kb_residual_part<<<dim3(Z.max_rchunks, nact), 256, rlds, st>>>(d_prob, d_active, d);
     TAPS_LAUNCHED(h, "kb_residual_part");
     return TAPS_OK;
   };
 
-  std::vector<double> h_outs(size_t(B) * (2 * D + 2));
-  std::vector<int> h_infos(size_t(B) * D);
+  // every launch of one sweep over the nact active problems (no host work)
   const uint32_t all = (1u << D) - 1u;
-  for (int it = 0; it < iter_max && !active.empty(); ++it) {
-    const int nact = int(active.size());
+  auto one_sweep = [&](int nact, hipStream_t st) -> taps_status {
     uint32_t valid = 0;
     for (int d = 0; d < D; ++d) {
       const uint32_t stale = (all & ~(1u << d)) & ~valid;
       for (int e = 0; e < D; ++e)
-        if (stale & (1u << e)) TAPS_TRY(refresh(e, nact));
+        if (stale & (1u << e)) TAPS_TRY(refresh(e, nact, st));
       valid |= stale;
-      TAPS_TRY(system(d, nact));
+      TAPS_TRY(system(d, nact, st));
       double fl = 0.0, by = 0.0;
       for (int b : active) {
         const taps_problem_t& p = probs[b];
@@ -369,37 +368,96 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
         by += solve_bytes(p.n[d], M, 2 * p.s[d] + 1, p.n_kinds[d]);
       }
       TAPS_TRY(solve_batched_launch(h, nact, base + o_args + size_t(d) * B * args_sz, d_active, M, p0.s[d], fl,
-                                    by, stream));
+                                    by, st));
       valid &= ~(1u << d);
-      TAPS_TRY(residual_parts(d, nact));
-      kb_berr_final<<<cdiv(nact, 64), 64, 0, stream>>>(d_prob, d_active, nact, d);
+      TAPS_TRY(residual_parts(d, nact, st));
+      kb_berr_final<<<cdiv(nact, 64), 64, 0, st>>>(d_prob, d_active, nact, d);
       TAPS_LAUNCHED(h, "kb_berr_final");
     }
-    kb_balance<<<dim3(M, nact), 256, 0, stream>>>(d_bal, d_active);
+    kb_balance<<<dim3(M, nact), 256, 0, st>>>(d_bal, d_active);
     TAPS_LAUNCHED(h, "kb_balance");
-    for (int e = 0; e < D; ++e) TAPS_TRY(refresh(e, nact));
+    for (int e = 0; e < D; ++e) TAPS_TRY(refresh(e, nact, st));
     for (int d = 0; d < D; ++d) {
-      TAPS_TRY(system(d, nact));
-      TAPS_TRY(residual_parts(d, nact));
+      TAPS_TRY(system(d, nact, st));
+      TAPS_TRY(residual_parts(d, nact, st));
     }
-    kb_residual_final<<<cdiv(nact, 64), 64, 0, stream>>>(d_prob, d_active, nact);
+    kb_residual_final<<<cdiv(nact, 64), 64, 0, st>>>(d_prob, d_active, nact);
     TAPS_LAUNCHED(h, "kb_residual_final");
-    TAPS_HIP(h, hipMemcpyAsync(h_outs.data(), outs, h_outs.size() * 8, hipMemcpyDeviceToHost, stream));
-    TAPS_HIP(h, hipMemcpyAsync(h_infos.data(), infos, h_infos.size() * 4, hipMemcpyDeviceToHost, stream));
-    TAPS_HIP(h, hipStreamSynchronize(stream));
+    return TAPS_OK;
+  };
+
+  // graph mode: K sweeps captured once per launch layout, replayed on the
+  // handle's own stream (the caller's stream may be the legacy null stream,
+  // which cannot be captured); the uploads above were synchronised already
+  const int K = h->prof.on ? 0 : h->tune.graph_sweeps;
+  hipStream_t run = stream;
+  if (K > 0) {
+    if (!h->gstream) TAPS_HIP(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    run = h->gstream;
+  }
+  auto graph_for = [&](int nact, int k) -> taps_status {
+    std::vector<int64_t> sig = {int64_t(reinterpret_cast<intptr_t>(base)), B, D, M, nact, k, int64_t(glds),
+                                int64_t(rlds), Z.max_chunks, Z.max_ctiles, Z.max_splits, Z.max_gram, Z.max_lgram,
+                                Z.max_rblocks, Z.max_cpl, Z.max_wt, Z.max_rchunks};
+    for (int d = 0; d < D; ++d) sig.push_back(p0.s[d]);
+    if (h->graph_exec && sig == h->graph_sig) return TAPS_OK;
+    if (h->graph_exec) {
+      TAPS_HIP(h, hipGraphExecDestroy(h->graph_exec));
+      h->graph_exec = nullptr;
+    }
+    TAPS_HIP(h, hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
+    taps_status st = TAPS_OK;
+    for (int j = 0; j < k && st == TAPS_OK; ++j) st = one_sweep(nact, run);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(run, &graph);
+    if (st != TAPS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (ec != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, TAPS_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ec));
+    }
+    const hipError_t ei = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      (void)hipGetLastError();
+      h->graph_exec = nullptr;
+      return fail(h, TAPS_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    h->graph_sig = sig;
+    return TAPS_OK;
+  };
+
+  std::vector<double> h_outs(size_t(B) * (2 * D + 2));
+  std::vector<int> h_infos(size_t(B) * D);
+  for (int it = 0; it < iter_max && !active.empty();) {
+    const int nact = int(active.size());
+    int k = 1;
+    if (K > 0) {
+      k = std::min(K, iter_max - it);
+      TAPS_TRY(graph_for(nact, k));
+      TAPS_HIP(h, hipGraphLaunch(h->graph_exec, run));
+    } else {
+      TAPS_TRY(one_sweep(nact, run));
+    }
+    it += k;
+    TAPS_HIP(h, hipMemcpyAsync(h_outs.data(), outs, h_outs.size() * 8, hipMemcpyDeviceToHost, run));
+    TAPS_HIP(h, hipMemcpyAsync(h_infos.data(), infos, h_infos.size() * 4, hipMemcpyDeviceToHost, run));
+    TAPS_HIP(h, hipStreamSynchronize(run));
     next.clear();
     for (int b : active) {
       const double* o = h_outs.data() + size_t(b) * (2 * D + 2);
       bool broke = false;
       for (int d = 0; d < D; ++d)
         broke = broke || h_infos[size_t(b) * D + d] != 0 || !(o[D + 2 + d] <= TAPS_BERR_LIMIT);
-      sweeps[b] = it + 1;
+      sweeps[b] = it;
       rho[b] = broke ? NAN : o[D + 1];
       if (!broke && rho[b] > tol) next.push_back(b);
     }
     if (next.size() != active.size() && !next.empty()) {
-      TAPS_HIP(h, hipMemcpyAsync(d_active, next.data(), next.size() * 4, hipMemcpyHostToDevice, stream));
-      TAPS_HIP(h, hipStreamSynchronize(stream));
+      TAPS_HIP(h, hipMemcpyAsync(d_active, next.data(), next.size() * 4, hipMemcpyHostToDevice, run));
+      TAPS_HIP(h, hipStreamSynchronize(run));
     }
     active.swap(next);
   }

@@ -183,7 +183,24 @@ taps_status taps_destroy(taps_handle_t h) {
   if (h->side) (void)hipFree(h->side);
   if (h->batch) (void)hipFree(h->batch);
   if (h->d_small) (void)hipFree(h->d_small);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->gstream) (void)hipStreamDestroy(h->gstream);
   delete h;
+  return TAPS_OK;
+}
+
+taps_status taps_set_tuning(taps_handle_t h, const taps_tuning_t* t) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (!t || t->graph_sweeps < 0 || t->graph_sweeps > 16)
+    return taps::fail(h, TAPS_ERR_INVALID, "graph_sweeps must be 0..16");
+  h->tune = *t;
+  return TAPS_OK;
+}
+
+taps_status taps_get_tuning(taps_handle_t h, taps_tuning_t* t) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (!t) return taps::fail(h, TAPS_ERR_INVALID, "null pointer");
+  *t = h->tune;
   return TAPS_OK;
 }
 

@@ -41,6 +41,12 @@ struct taps_handle {
   size_t batch_bytes = 0;
   std::string err;
   int device = 0;
+  // tuning of the batched driver (taps_set_tuning / taps_autotune) and the
+  // instantiated graph of its sweeps, reused while the launch layout holds
+  taps_tuning_t tune{0};
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t gstream = nullptr;
+  std::vector<int64_t> graph_sig;
   // kernel timing (taps_profile_*)
   struct Prof {
     std::vector<hipEvent_t> ev;    // start/stop pairs, reused
@@ -169,6 +175,8 @@ size_t solve_ws_bytes(int n, int M, int s);
 void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_C, const double* d_Q,
                      double* d_X, int* d_info, void* ws);
 bool solve_batched_supported(int M, int s);
+// raises the kernel's LDS limit ahead of any launch (not allowed inside a capture)
+taps_status solve_batched_prepare(taps_handle* h, int M, int s);
 taps_status solve_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active,
                                  int M, int s, double flops, double bytes, hipStream_t stream);
 taps_status berr_final_launch(taps_handle* h, int nparts, const double* parts, double* out, hipStream_t stream);

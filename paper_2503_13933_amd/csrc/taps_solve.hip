@@ -838,6 +838,10 @@ void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_
 
 bool solve_batched_supported(int M, int s) { return solve_mfma_lds_bytes(M, s) <= 160 * 1024 - 64; }
 
+taps_status solve_batched_prepare(taps_handle* h, int M, int s) {
+  return allow_lds(h, lu_batched_for(M), solve_mfma_lds_bytes(M, s), &lu_mfma_batched_lds_allowed[mp_of(M) / 8]);
+}
+
 taps_status solve_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active,
                                  int M, int s, double flops, double bytes, hipStream_t stream) {
   const size_t lds = solve_mfma_lds_bytes(M, s);

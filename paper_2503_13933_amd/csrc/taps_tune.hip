@@ -1,0 +1,166 @@
+// Timing autotuner of the batched driver: how many sweeps one captured HIP
+// graph holds (0 = launches from the host).  Candidates are timed on the
+// caller's batch with HIP events; the factors are saved and restored around
+// the trials.  Choices are cached in a small JSON file keyed by the batch
+// shape, one entry per line:
+//   {
+//     "B=256;D=4;M=40;s=2,2,2,2;n=512,512,128,257;R=257,1,1,257;K=2,2,2,2": {"graph_sweeps": 1, "ms_per_sweep": 151.2},
+//     ...
+//   }
+#include "taps_internal.hpp"
+
+#include <algorithm>
+#include <fstream>
+#include <sstream>
+
+namespace {
+
+constexpr int kCandidates[4] = {0, 1, 2, 4};
+constexpr int kTimedSweeps = 4;
+
+std::string shape_key(int B, const taps_problem_t* probs) {
+  const taps_problem_t& p0 = probs[0];
+  std::ostringstream k;
+  k << "B=" << B << ";D=" << p0.D << ";M=" << p0.M << ";s=";
+  for (int d = 0; d < p0.D; ++d) k << (d ? "," : "") << p0.s[d];
+  const char* tags[3] = {";n=", ";R=", ";K="};
+  for (int f = 0; f < 3; ++f) {
+    k << tags[f];
+    for (int d = 0; d < p0.D; ++d) {
+      int mx = 0;
+      for (int b = 0; b < B; ++b)
+        mx = std::max(mx, f == 0 ? probs[b].n[d] : f == 1 ? probs[b].R_cols[d] : probs[b].n_kinds[d]);
+      k << (d ? "," : "") << mx;
+    }
+  }
+  return k.str();
+}
+
+// Entry lines of the cache file (everything between the outer braces).
+std::vector<std::string> read_entries(const char* path) {
+  std::vector<std::string> out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t q = line.find('"');
+    if (q == std::string::npos) continue;
+    out.push_back(line.substr(q));
+    if (!out.back().empty() && out.back().back() == ',') out.back().pop_back();
+  }
+  return out;
+}
+
+bool lookup(const std::vector<std::string>& entries, const std::string& key, int* graph_sweeps) {
+  const std::string head = "\"" + key + "\"";
+  for (const auto& e : entries) {
+    if (e.compare(0, head.size(), head) != 0) continue;
+    const size_t g = e.find("\"graph_sweeps\":");
+    if (g == std::string::npos) continue;
+    *graph_sweeps = std::atoi(e.c_str() + g + 15);
+    return true;
+  }
+  return false;
+}
+
+bool write_entries(const char* path, const std::vector<std::string>& entries) {
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return false;
+  f << "{\n";
+  for (size_t i = 0; i < entries.size(); ++i) f << "  " << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+  f << "}\n";
+  return bool(f);
+}
+
+}  // namespace
+
+using namespace taps;
+
+extern "C" taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* probs, double* const* d_U,
+                                     const char* cache_path, taps_tuning_t* chosen, double* ms_per_sweep,
+                                     hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (B < 1 || !probs || !d_U || !chosen) return fail(h, TAPS_ERR_INVALID, "bad autotune arguments");
+  for (int b = 0; b < B; ++b) TAPS_TRY(check_problem(h, &probs[b]));
+  const std::string key = shape_key(B, probs);
+  std::vector<std::string> entries;
+  if (cache_path) {
+    entries = read_entries(cache_path);
+    int K = 0;
+    if (lookup(entries, key, &K) && K >= 0 && K <= 16) {
+      h->tune.graph_sweeps = K;
+      *chosen = h->tune;
+      if (ms_per_sweep)
+        for (int c = 0; c < 4; ++c) ms_per_sweep[c] = -1.0;
+      return TAPS_OK;
+    }
+  }
+  if (h->prof.on) return fail(h, TAPS_ERR_INVALID, "autotune needs kernel timing disabled");
+  // save the factors
+  const int D = probs[0].D, M = probs[0].M;
+  size_t total = 0;
+  for (int b = 0; b < B; ++b)
+    for (int d = 0; d < D; ++d) total += size_t(probs[b].n[d]) * M;
+  double* saved = nullptr;
+  TAPS_HIP(h, hipMalloc(&saved, total * 8));
+  auto copy_all = [&](bool save) -> taps_status {
+    size_t off = 0;
+    for (int b = 0; b < B; ++b)
+      for (int d = 0; d < D; ++d) {
+        const size_t n = size_t(probs[b].n[d]) * M;
+        double* u = d_U[size_t(b) * D + d];
+        TAPS_HIP(h, hipMemcpyAsync(save ? saved + off : u, save ? u : saved + off, n * 8, hipMemcpyDeviceToDevice,
+                                   stream));
+        off += n;
+      }
+    return TAPS_OK;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<int32_t> sw(B);
+  std::vector<double> rho(B);
+  double ms[4] = {0, 0, 0, 0};
+  const taps_tuning_t before = h->tune;
+  taps_status st = copy_all(true);
+  if (st == TAPS_OK && hipEventCreate(&e0) != hipSuccess) st = fail(h, TAPS_ERR_HIP, "event creation failed");
+  if (st == TAPS_OK && hipEventCreate(&e1) != hipSuccess) st = fail(h, TAPS_ERR_HIP, "event creation failed");
+  for (int c = 0; c < 4 && st == TAPS_OK; ++c) {
+    h->tune.graph_sweeps = kCandidates[c];
+    // untimed run (captures the graph), then the timed one from the same factors
+    st = copy_all(false);
+    if (st == TAPS_OK) st = taps_als_batched(h, B, probs, d_U, 0.0, kTimedSweeps, sw.data(), rho.data(), stream);
+    if (st == TAPS_OK) st = copy_all(false);
+    if (st == TAPS_OK && hipEventRecord(e0, stream) != hipSuccess) st = fail(h, TAPS_ERR_HIP, "event record failed");
+    if (st == TAPS_OK) st = taps_als_batched(h, B, probs, d_U, 0.0, kTimedSweeps, sw.data(), rho.data(), stream);
+    if (st == TAPS_OK && hipEventRecord(e1, stream) != hipSuccess) st = fail(h, TAPS_ERR_HIP, "event record failed");
+    float t = 0.0f;
+    if (st == TAPS_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      st = fail(h, TAPS_ERR_HIP, "event timing failed");
+    ms[c] = double(t) / kTimedSweeps;
+  }
+  if (st == TAPS_OK) st = copy_all(false);
+  if (st == TAPS_OK && hipStreamSynchronize(stream) != hipSuccess) st = fail(h, TAPS_ERR_HIP, "synchronisation failed");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(saved);
+  if (st != TAPS_OK) {
+    h->tune = before;
+    return st;
+  }
+  const double best = *std::min_element(ms, ms + 4);
+  int pick = 3;
+  for (int c = 0; c < 4; ++c)
+    if (ms[c] <= 1.03 * best) {
+      pick = c;
+      break;
+    }
+  h->tune.graph_sweeps = kCandidates[pick];
+  *chosen = h->tune;
+  if (ms_per_sweep)
+    for (int c = 0; c < 4; ++c) ms_per_sweep[c] = ms[c];
+  if (cache_path) {
+    std::ostringstream e;
+    e << "\"" << key << "\": {\"graph_sweeps\": " << kCandidates[pick] << ", \"ms_per_sweep\": " << ms[pick] << "}";
+    entries.push_back(e.str());
+    if (!write_entries(cache_path, entries)) return fail(h, TAPS_ERR_INVALID, "cannot write %s", cache_path);
+  }
+  return TAPS_OK;
+}

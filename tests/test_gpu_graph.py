@@ -1,0 +1,90 @@
+"""Batched Algorithm 1 replayed through captured HIP graphs: every replay
+must give exactly what the host-launched sweeps give (same kernels, same
+order), across repeated calls with other work in between; the autotuner must
+restore the factors it times on and reuse its JSON cache."""
+import os
+
+import numpy as np
+import pytest
+
+import taps_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[graph]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env(taps_lib):
+    import torch
+    from paper_2503_13933_amd import capi, problem
+    h = capi.Handle()
+    yield torch, capi, problem, h
+    h.close()
+
+
+def batch(env, n=12, seed=31):
+    torch, capi, problem, h = env
+    cases = W.heat_slab_batch(batch=n, n_lo=12, n_hi=48, M=6, seed=seed)
+    devs = [problem.heat_slab(h, c) for c in cases]
+    U0 = [W.initial_factors(c.axes, c.M, c.seed) for c in cases]
+    return cases, devs, U0
+
+
+def run(env, devs, U0, sweeps, graph, tol=0.0):
+    torch, capi, problem, h = env
+    capi.taps_set_tuning(h, graph)
+    U = [d.factors(u) for d, u in zip(devs, U0)]
+    sw, rho = capi.taps_als_batched(h, [d.struct for d in devs], U, tol, sweeps)
+    torch.cuda.synchronize()
+    capi.taps_set_tuning(h, 0)
+    return [[u.cpu().numpy() for u in Ub] for Ub in U], sw, rho
+
+
+def test_graph_replays_equal_host_launches(env):
+    torch, capi, problem, h = env
+    cases, devs, U0 = batch(env)
+    _say("12 uneven slabs, M=6: host launches vs graphs of 1 and 3 sweeps")
+    ref, sw0, rho0 = run(env, devs, U0, 3, 0)
+    for K in (1, 3, 1, 3):               # the second pair reuses or re-captures across calls
+        got, sw, rho = run(env, devs, U0, 3, K)
+        x = torch.ones(1000, device="cuda").sum().item()   # eager work between the replays
+        assert x == 1000.0
+        assert sw == sw0 and np.array_equal(np.array(rho), np.array(rho0)), K
+        for a, b in zip(got, ref):
+            for u, v in zip(a, b):
+                assert np.array_equal(u, v), K
+
+
+def test_graph_with_tolerance_counts_in_steps_of_k(env):
+    torch, capi, problem, h = env
+    cases, devs, U0 = batch(env, n=6, seed=32)
+    _, sw1, rho1 = run(env, devs, U0, 8, 0, tol=5e-2)
+    _, sw2, rho2 = run(env, devs, U0, 8, 2, tol=5e-2)
+    for a, b, r in zip(sw1, sw2, rho2):
+        assert b % 2 == 0 and a <= b <= a + 1, (a, b)
+        assert (not r == r) or r <= 5e-2 or b == 8
+
+
+def test_autotune_restores_factors_and_uses_cache(env, tmp_path):
+    torch, capi, problem, h = env
+    cases, devs, U0 = batch(env, n=16, seed=33)
+    U = [d.factors(u) for d, u in zip(devs, U0)]
+    before = [[u.clone() for u in Ub] for Ub in U]
+    path = str(tmp_path / "tune.json")
+    K, ms = capi.taps_autotune(h, [d.struct for d in devs], U, path)
+    torch.cuda.synchronize()
+    _say(f"autotune: ms per sweep for graph_sweeps 0/1/2/4 = {[round(m, 3) for m in ms]} -> {K}")
+    assert K in (0, 1, 2, 4) and all(m > 0 for m in ms)
+    assert capi.taps_get_tuning(h) == K
+    for a, b in zip(U, before):
+        for u, v in zip(a, b):
+            assert torch.equal(u, v)
+    assert os.path.exists(path) and "graph_sweeps" in open(path).read()
+    K2, ms2 = capi.taps_autotune(h, [d.struct for d in devs], U, path)
+    assert K2 == K and all(m == -1.0 for m in ms2)
+    capi.taps_set_tuning(h, 0)
+    with pytest.raises(RuntimeError):
+        capi.taps_set_tuning(h, 17)
