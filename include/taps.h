@@ -267,16 +267,33 @@ taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* p
                              double* const* d_U, double tol, int32_t iter_max, int32_t* sweeps,
                              double* rho, hipStream_t stream);
 
-/* Tuning of the batched driver.  graph_sweeps = 0 launches every kernel of a
- * sweep from the host; K > 0 captures K consecutive sweeps (every launch, no
- * host work in between) into one HIP graph, replays it, and checks the
- * residuals after each replay, so a slab that reaches tol mid-graph runs up
- * to K-1 extra sweeps and sweeps[b] counts in steps of K.  The graph is
- * re-captured when the set of unconverged slabs or the batch layout changes,
- * and kept on the handle otherwise (across calls).  Graphs are not used while
- * kernel timing is enabled.  Valid K: 0..16. */
+/* Tuning of the dim solves and of the batched driver.
+ *
+ * graph_sweeps = 0 launches every kernel of a sweep from the host; K > 0
+ * captures K consecutive sweeps (every launch, no host work in between) into
+ * one HIP graph, replays it, and checks the residuals after each replay, so a
+ * slab that reaches tol mid-graph runs up to K-1 extra sweeps and sweeps[b]
+ * counts in steps of K.  The graph is re-captured when the set of unconverged
+ * slabs, the batch layout or the solver changes, and kept on the handle
+ * otherwise (across calls).  Graphs are not used while kernel timing is
+ * enabled.  Valid K: 0..16.
+ *
+ * solver selects how a dim system sum_k A^k X C^(k)T = Q (a Sylvester equation, Sec. 2.6) is
+ * solved, in taps_solve_dim, taps_als and taps_als_batched alike:
+ *   0  block LU over the block-banded operator (any number of kinds);
+ *   1  fast diagonalisation / complex Schur (Sec. 2.6): for a dim with two kinds,
+ *      E = C^(1)T C^(0)-T is brought to complex Schur form and its
+ *      eigenvectors P, and the system decouples into M banded complex
+ *      systems (A^0 + lambda_m A^1) y_m = (Q C^(0)-T P)_m, X = Re(Y P^-1).
+ *      Needs M <= 48; dims with another number of kinds, or larger M, use
+ *      the block LU.  Failure codes in the info word: -1 C^(0) singular,
+ *      -2 the QR iteration did not converge (40 M iterations), k > 0 a zero
+ *      pivot in row k-1 of a banded system.  Same backward-error check as
+ *      the block LU.
+ * Valid solver: 0, 1. */
 typedef struct {
   int32_t graph_sweeps;
+  int32_t solver;
 } taps_tuning_t;
 taps_status taps_set_tuning(taps_handle_t h, const taps_tuning_t* t);
 taps_status taps_get_tuning(taps_handle_t h, taps_tuning_t* t);

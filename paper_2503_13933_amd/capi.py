@@ -55,7 +55,7 @@ class Problem(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("graph_sweeps", C.c_int32)]
+    _fields_ = [("graph_sweeps", C.c_int32), ("solver", C.c_int32)]
 
 
 class MLP(C.Structure):
@@ -229,15 +229,23 @@ def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, stream=None
     return sweeps.value, rho.value, list(hist[: sweeps.value])
 
 
-def taps_set_tuning(h: Handle, graph_sweeps: int):
-    t = Tuning(graph_sweeps)
-    h.check(lib().taps_set_tuning(h.h, C.byref(t)), "taps_set_tuning")
+SOLVER_BLOCK_LU, SOLVER_FAST_DIAG = 0, 1
 
 
-def taps_get_tuning(h: Handle) -> int:
+def taps_get_tuning(h: Handle) -> Tuning:
     t = Tuning()
     h.check(lib().taps_get_tuning(h.h, C.byref(t)), "taps_get_tuning")
-    return t.graph_sweeps
+    return t
+
+
+def taps_set_tuning(h: Handle, graph_sweeps: int = None, solver: int = None):
+    """Fields left as None keep the handle's current value."""
+    t = taps_get_tuning(h)
+    if graph_sweeps is not None:
+        t.graph_sweeps = graph_sweeps
+    if solver is not None:
+        t.solver = solver
+    h.check(lib().taps_set_tuning(h.h, C.byref(t)), "taps_set_tuning")
 
 
 def taps_autotune(h: Handle, probs, Us, cache_path=None, stream=None):

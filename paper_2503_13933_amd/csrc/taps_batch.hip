@@ -156,9 +156,16 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     }
   }
   const int D = p0.D, M = p0.M, MM = M * M;
-  for (int d = 0; d < D; ++d)
-    if (!solve_batched_supported(M, p0.s[d]))
+  // per dim: fast diagonalisation when selected and every system of the
+  // batch has two kinds, block LU otherwise
+  std::vector<char> use_fd(D, 0);
+  for (int d = 0; d < D; ++d) {
+    bool fd = h->tune.solver == 1;
+    for (int b = 0; b < B && fd; ++b) fd = solve_fd_supported(M, p0.s[d], probs[b].n_kinds[d]);
+    use_fd[d] = fd;
+    if (!fd && !solve_batched_supported(M, p0.s[d]))
       return fail(h, TAPS_ERR_UNSUPPORTED, "batched solve needs M=%d, s=%d to fit LDS", M, p0.s[d]);
+  }
 
   // ---- layout of the batch buffer
   const size_t args_sz = solve_args_bytes();
@@ -305,7 +312,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   if (rlds > 160 * 1024 - 4096) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", rlds);
   TAPS_TRY(allow_lds(h, kb_gram_partial, glds, &gram_lds_allowed));
   TAPS_TRY(allow_lds(h, kb_residual_part, rlds, &res_lds_allowed));
-  for (int d = 0; d < D; ++d) TAPS_TRY(solve_batched_prepare(h, M, p0.s[d]));
+  for (int d = 0; d < D; ++d)
+    TAPS_TRY(use_fd[d] ? fd_prepare(h, M, p0.s[d]) : solve_batched_prepare(h, M, p0.s[d]));
 
   auto refresh = [&](int e, int nact, hipStream_t st) -> taps_status {
     size_t slot;
@@ -364,11 +372,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       double fl = 0.0, by = 0.0;
       for (int b : active) {
         const taps_problem_t& p = probs[b];
-        fl += solve_flops(p.n[d], M, 2 * p.s[d] + 1);
-        by += solve_bytes(p.n[d], M, 2 * p.s[d] + 1, p.n_kinds[d]);
+        fl += use_fd[d] ? solve_fd_flops(p.n[d], M, p.s[d]) : solve_flops(p.n[d], M, 2 * p.s[d] + 1);
+        by += use_fd[d] ? solve_fd_bytes(p.n[d], M, p.s[d]) : solve_bytes(p.n[d], M, 2 * p.s[d] + 1, p.n_kinds[d]);
       }
-      TAPS_TRY(solve_batched_launch(h, nact, base + o_args + size_t(d) * B * args_sz, d_active, M, p0.s[d], fl,
-                                    by, st));
+      const void* d_args = base + o_args + size_t(d) * B * args_sz;
+      TAPS_TRY(use_fd[d] ? fd_batched_launch(h, nact, d_args, d_active, M, p0.s[d], fl, by, st)
+                         : solve_batched_launch(h, nact, d_args, d_active, M, p0.s[d], fl, by, st));
       valid &= ~(1u << d);
       TAPS_TRY(residual_parts(d, nact, st));
       kb_berr_final<<<cdiv(nact, 64), 64, 0, st>>>(d_prob, d_active, nact, d);
@@ -399,7 +408,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     std::vector<int64_t> sig = {int64_t(reinterpret_cast<intptr_t>(base)), B, D, M, nact, k, int64_t(glds),
                                 int64_t(rlds), Z.max_chunks, Z.max_ctiles, Z.max_splits, Z.max_gram, Z.max_lgram,
                                 Z.max_rblocks, Z.max_cpl, Z.max_wt, Z.max_rchunks};
-    for (int d = 0; d < D; ++d) sig.push_back(p0.s[d]);
+    for (int d = 0; d < D; ++d) sig.push_back(p0.s[d] * 2 + use_fd[d]);
     if (h->graph_exec && sig == h->graph_sig) return TAPS_OK;
     if (h->graph_exec) {
       TAPS_HIP(h, hipGraphExecDestroy(h->graph_exec));

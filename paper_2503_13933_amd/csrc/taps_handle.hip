@@ -193,6 +193,7 @@ taps_status taps_set_tuning(taps_handle_t h, const taps_tuning_t* t) {
   if (!h) return TAPS_ERR_INVALID;
   if (!t || t->graph_sweeps < 0 || t->graph_sweeps > 16)
     return taps::fail(h, TAPS_ERR_INVALID, "graph_sweeps must be 0..16");
+  if (t->solver != 0 && t->solver != 1) return taps::fail(h, TAPS_ERR_INVALID, "solver must be 0 or 1");
   h->tune = *t;
   return TAPS_OK;
 }

@@ -177,6 +177,15 @@ void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_
 bool solve_batched_supported(int M, int s);
 // raises the kernel's LDS limit ahead of any launch (not allowed inside a capture)
 taps_status solve_batched_prepare(taps_handle* h, int M, int s);
+// Fast diagonalisation of two-kind dim systems (solver 1 of the tuning):
+// applicability, algorithmic work, LDS set-up and the batched launch (eigen
+// stage then banded stage, one workgroup per active system each).
+bool solve_fd_supported(int M, int s, int K);
+double solve_fd_flops(int n, int M, int s);
+double solve_fd_bytes(int n, int M, int s);
+taps_status fd_prepare(taps_handle* h, int M, int s);
+taps_status fd_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active, int M, int s,
+                              double flops, double bytes, hipStream_t stream);
 taps_status solve_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active,
                                  int M, int s, double flops, double bytes, hipStream_t stream);
 taps_status berr_final_launch(taps_handle* h, int nparts, const double* parts, double* out, hipStream_t stream);

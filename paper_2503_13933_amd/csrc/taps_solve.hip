@@ -685,6 +685,615 @@ __global__ void k_berr_final(int nparts, const double* __restrict__ part, double
 
 size_t res_lds_allowed = 0;
 
+// ---------------------------------------------------------------------------
+// Fast diagonalisation of a dim system with two 1D matrix kinds (the paper's
+// own solver, Sec. 2.6):  A1 X C1^T + A2 X C2^T = Q.  Right-multiplying by
+// C1^{-T} gives A1 X + A2 X E = Q C1^{-T} with E = C2^T C1^{-T}.  With the
+// complex Schur form E = Z T Z^H and the eigenvectors of T (T Wv = Wv diag(l),
+// Wv unit upper triangular), P = Z Wv diagonalises E, and Y = X P decouples
+// into M banded systems (A1 + l_m A2) y_m = (Q C1^{-T} P)_m; X = Re(Y P^{-1})
+// with P^{-1} = Wv^{-1} Z^H.
+//   k_fd_eig   (one wave per system): C1^{-1} by Gauss-Jordan with partial
+//              pivoting, E, Householder Hessenberg form, complex single-shift
+//              QR with Wilkinson shifts (Givens bulge chase, Z accumulated),
+//              Wv and Wv^{-1} by substitution; writes H2 = C1^{-T} Z Wv,
+//              H3 = Wv^{-1} Z^H and l to the workspace.
+//   k_fd_solve (one workgroup per system): R = Q H2, the M banded complex
+//              systems (one lane each; elimination without pivoting over a
+//              (w+1)-row window in LDS, U rows kept for back substitution),
+//              X = Re(Y H3).  Fixed rows are identity rows with zero right-hand
+//              side and zero columns.
+// Workspace (doubles, from A.Zst): H2 2M^2 | H3 2M^2 | l 2M | C1inv M^2 |
+// Y 2nM | U store 2 M n (w+1).
+struct cplx {
+  double r, i;
+};
+__device__ inline cplx cmk(double r, double i) { return cplx{r, i}; }
+__device__ inline cplx cadd(cplx a, cplx b) { return cplx{a.r + b.r, a.i + b.i}; }
+__device__ inline cplx csub(cplx a, cplx b) { return cplx{a.r - b.r, a.i - b.i}; }
+__device__ inline cplx cmul(cplx a, cplx b) { return cplx{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ inline cplx cconj(cplx a) { return cplx{a.r, -a.i}; }
+__device__ inline cplx cscale(cplx a, double s) { return cplx{a.r * s, a.i * s}; }
+__device__ inline double cabs2(cplx a) { return hypot(a.r, a.i); }
+__device__ inline cplx cdivz(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.r) >= fabs(b.i)) {
+    const double t = b.i / b.r, d = b.r + b.i * t;
+    return cplx{(a.r + a.i * t) / d, (a.i - a.r * t) / d};
+  }
+  const double t = b.r / b.i, d = b.i + b.r * t;
+  return cplx{(a.r * t + a.i) / d, (a.i * t - a.r) / d};
+}
+__device__ inline cplx csqrtz(cplx z) {
+  const double m = cabs2(z);
+  double r = sqrt(0.5 * (m + fabs(z.r)));
+  if (r == 0.0) return cplx{0.0, 0.0};
+  if (z.r >= 0.0) return cplx{r, z.i / (2.0 * r)};
+  return cplx{fabs(z.i) / (2.0 * r), z.i >= 0.0 ? r : -r};
+}
+
+constexpr int kFdMaxM = 48;
+
+// Workspace of one fast-diagonalisation solve (inside the first workspace
+// region): H2 = C1^{-T} P and H3 = P^{-1} (M x M complex), the eigenvalues
+// (M complex), the right-hand sides / solutions of the banded systems
+// (n x M complex, row-major) and their U rows (n x (w+1) x M complex).
+struct FdWs {
+  double *H2, *H3, *lam, *Y, *U;
+};
+__device__ inline FdWs fd_ws(const SolveArgs& A) {
+  const int M = A.M, MM = M * M;
+  FdWs f;
+  f.H2 = A.Zst;
+  f.H3 = f.H2 + 2 * MM;
+  f.lam = f.H3 + 2 * MM;
+  f.Y = f.lam + 2 * M;
+  f.U = f.Y + 2 * long(A.n) * M;
+  return f;
+}
+
+// |re| + |im|: the cheap modulus of the deflation and shift tests.
+__device__ inline double cabs1(cplx a) { return fabs(a.r) + fabs(a.i); }
+__device__ inline cplx crecip(cplx a) {
+  const double id = 1.0 / (a.r * a.r + a.i * a.i);
+  return cplx{a.r * id, -a.i * id};
+}
+
+// Complex Givens rotation [c s; -conj(s) c] [a; b] = [r; 0], c real:
+// c = |a| / r, s = (a / |a|) conj(b) / r, r = sqrt(|a|^2 + |b|^2).  The
+// operands are scaled by max(|a|_1, |b|_1) first so the squares stay in range.
+__device__ inline void cgivens(cplx a, cplx b, double& c, cplx& s) {
+  const double sc = fmax(cabs1(a), cabs1(b));
+  if (cabs1(b) == 0.0 || sc == 0.0) {
+    c = 1.0;
+    s = cmk(0.0, 0.0);
+    return;
+  }
+  const double is = 1.0 / sc;
+  const cplx as = cscale(a, is), bs = cscale(b, is);
+  const double a2 = as.r * as.r + as.i * as.i, b2 = bs.r * bs.r + bs.i * bs.i;
+  const double ir = 1.0 / sqrt(a2 + b2);
+  if (a2 == 0.0) {
+    c = 0.0;
+    s = cscale(cconj(bs), ir);
+    return;
+  }
+  const double na = sqrt(a2);
+  c = na * ir;
+  s = cscale(cmul(as, cconj(bs)), ir / na);
+}
+
+__device__ void fd_eig_body(const SolveArgs& A) {
+  extern __shared__ double lds[];
+  const int M = A.M, MM = M * M, lane = threadIdx.x;
+  cplx* H = reinterpret_cast<cplx*>(lds);          // M x M complex (row-major)
+  cplx* Z = H + MM;                                 // M x M complex
+  double* S0 = reinterpret_cast<double*>(Z + MM);   // M x M real (2 buffers), later Wv (complex)
+  double* S1 = S0 + MM;
+  double* Ci = S1 + MM;                             // C1^{-1}
+  double* C2s = Ci + MM;                            // C2, later the Householder vector
+  __shared__ int perm[64];
+  __shared__ int s_fail;
+  const FdWs f = fd_ws(A);
+  if (lane == 0) s_fail = 0;
+  // ---- C1^{-1}: Gauss-Jordan with partial pivoting (row swaps, undone as
+  // column swaps at the end)
+  for (int t = lane; t < MM; t += 64) {
+    S0[t] = A.C[t];
+    C2s[t] = A.C[MM + t];
+  }
+  __syncthreads();
+  double* cur = S0;
+  double* nxt = S1;
+  for (int r = 0; r < M; ++r) {
+    // pivot: largest |cur[i][r]|, i >= r (first on ties), by a wave reduction
+    double bv = (lane >= r && lane < M) ? fabs(cur[lane * M + r]) : -1.0;
+    int bi = lane;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    const int p = bi;
+    if (lane == 0) {
+      perm[r] = p;
+      if (!(bv > 0.0) || !isfinite(bv)) s_fail = 1;
+    }
+    if (p != r)
+      for (int j = lane; j < M; j += 64) {
+        const double t = cur[r * M + j];
+        cur[r * M + j] = cur[p * M + j];
+        cur[p * M + j] = t;
+      }
+    __syncthreads();
+    const double ip = 1.0 / cur[r * M + r];
+    for (int t = lane; t < MM; t += 64) {
+      const int i = t / M, j = t - (t / M) * M;
+      const double aij = cur[t], air = cur[i * M + r], arj = cur[r * M + j];
+      double v = aij - air * (arj * ip);
+      v = (j == r) ? -air * ip : v;
+      v = (i == r) ? ((j == r) ? ip : aij * ip) : v;
+      nxt[t] = v;
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  for (int r = M - 1; r >= 0; --r) {   // undo the row swaps as column swaps
+    const int p = perm[r];
+    if (p != r)
+      for (int i = lane; i < M; i += 64) {
+        const double t = cur[i * M + r];
+        cur[i * M + r] = cur[i * M + p];
+        cur[i * M + p] = t;
+      }
+    __syncthreads();
+  }
+  for (int t = lane; t < MM; t += 64) Ci[t] = cur[t];
+  __syncthreads();
+  // ---- E[i][j] = sum_q C2[q][i] C1inv[j][q] into H; Z = I
+  for (int t = lane; t < MM; t += 64) {
+    const int i = t / M, j = t - (t / M) * M;
+    double e = 0.0;
+    for (int q = 0; q < M; ++q) e += C2s[q * M + i] * Ci[j * M + q];
+    H[t] = cmk(e, 0.0);
+    Z[t] = cmk(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  // ---- Householder Hessenberg form (real), Z accumulated
+  double* v = C2s;   // length M
+  for (int k = 0; k + 2 < M; ++k) {
+    double x = (lane > k && lane < M) ? H[lane * M + k].r : 0.0;
+    double ss = x * x;
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+    const double x0 = __shfl(x, k + 1);
+    const double nx = sqrt(ss);
+    if (nx == 0.0) continue;
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    const double vi = (lane == k + 1) ? x - alpha : x;
+    double vv = vi * vi;
+    for (int o = 32; o > 0; o >>= 1) vv += __shfl_xor(vv, o);
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    if (lane < M) v[lane] = vi;
+    __syncthreads();
+    if (lane < M) {   // left: column lane, rows k+1..
+      double wj = 0.0;
+      for (int i = k + 1; i < M; ++i) wj += v[i] * H[i * M + lane].r;
+      for (int i = k + 1; i < M; ++i) H[i * M + lane].r -= beta * v[i] * wj;
+    }
+    __syncthreads();
+    if (lane < M) {   // right: row lane, columns k+1.. (H and Z)
+      double u = 0.0, uz = 0.0;
+      for (int j = k + 1; j < M; ++j) {
+        u += H[lane * M + j].r * v[j];
+        uz += Z[lane * M + j].r * v[j];
+      }
+      for (int j = k + 1; j < M; ++j) {
+        H[lane * M + j].r -= beta * u * v[j];
+        Z[lane * M + j].r -= beta * uz * v[j];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- complex single-shift QR
+  int hi = M - 1, it = 0, total = 0;
+  const int limit = 40 * M;
+  while (hi > 0 && total < limit) {
+    // lo: the largest i <= hi whose subdiagonal entry is negligible (0 if none)
+    bool neg = false;
+    if (lane >= 1 && lane <= hi)
+      neg = cabs1(H[lane * M + lane - 1]) <=
+            2.220446049250313e-16 * (cabs1(H[lane * M + lane]) + cabs1(H[(lane - 1) * M + lane - 1]));
+    const unsigned long long bal = __ballot(neg);
+    const int lo = bal ? 63 - __clzll(bal) : 0;
+    __syncthreads();
+    if (lo > 0 && lane == 0) H[lo * M + lo - 1] = cmk(0.0, 0.0);
+    if (lo == hi) {
+      --hi;
+      it = 0;
+      __syncthreads();
+      continue;
+    }
+    ++it;
+    ++total;
+    const cplx a = H[(hi - 1) * M + hi - 1], b = H[(hi - 1) * M + hi], c = H[hi * M + hi - 1], d = H[hi * M + hi];
+    const cplx tr = cadd(a, d), det = csub(cmul(a, d), cmul(b, c));
+    const cplx disc = csqrtz(csub(cscale(cmul(tr, tr), 0.25), det));
+    const cplx l1 = cadd(cscale(tr, 0.5), disc), l2 = csub(cscale(tr, 0.5), disc);
+    cplx mu = (cabs2(csub(l1, d)) < cabs2(csub(l2, d))) ? l1 : l2;
+    if (it % 11 == 0) mu = cadd(mu, cmk(cabs1(c), 0.0));   // exceptional shift
+    cplx x = csub(H[lo * M + lo], mu), y = H[(lo + 1) * M + lo];
+    for (int k = lo; k < hi; ++k) {
+      if (k > lo) {
+        x = H[k * M + k - 1];
+        y = H[(k + 1) * M + k - 1];
+      }
+      double cg;
+      cplx sg;
+      cgivens(x, y, cg, sg);
+      __syncthreads();
+      const int j0 = k > 0 ? k - 1 : 0;
+      if (lane >= j0 && lane < M) {   // rows k, k+1
+        const cplx hk = H[k * M + lane], hk1 = H[(k + 1) * M + lane];
+        H[k * M + lane] = cadd(cscale(hk, cg), cmul(sg, hk1));
+        H[(k + 1) * M + lane] = csub(cscale(hk1, cg), cmul(cconj(sg), hk));
+      }
+      __syncthreads();
+      const int i1 = min(k + 2, hi);
+      if (lane <= i1) {   // columns k, k+1 of H (times G^H)
+        const cplx hk = H[lane * M + k], hk1 = H[lane * M + k + 1];
+        H[lane * M + k] = cadd(cscale(hk, cg), cmul(cconj(sg), hk1));
+        H[lane * M + k + 1] = csub(cscale(hk1, cg), cmul(sg, hk));
+      }
+      if (lane < M) {
+        const cplx zk = Z[lane * M + k], zk1 = Z[lane * M + k + 1];
+        Z[lane * M + k] = cadd(cscale(zk, cg), cmul(cconj(sg), zk1));
+        Z[lane * M + k + 1] = csub(cscale(zk1, cg), cmul(sg, zk));
+      }
+      __syncthreads();
+    }
+  }
+  if (hi > 0 && lane == 0) s_fail = 2;
+  __syncthreads();
+  // ---- eigenvectors Wv of T (unit upper triangular), one column per lane
+  cplx* Wv = reinterpret_cast<cplx*>(S0);   // M x M complex in the S region
+  if (lane < M) {
+    const int k = lane;
+    const cplx tk = H[k * M + k];
+    double tn = 0.0;
+    for (int i = 0; i <= k; ++i) tn = fmax(tn, cabs2(H[i * M + i]));
+    const double small = 2.220446049250313e-16 * fmax(tn, 1e-300);
+    for (int i = 0; i < M; ++i) Wv[i * M + k] = cmk(i == k ? 1.0 : 0.0, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+      cplx sacc = cmk(0.0, 0.0);
+      for (int j = i + 1; j <= k; ++j) sacc = cadd(sacc, cmul(H[i * M + j], Wv[j * M + k]));
+      cplx den = csub(H[i * M + i], tk);
+      if (cabs2(den) < small) den = cmk(small, 0.0);
+      Wv[i * M + k] = cscale(cdivz(sacc, den), -1.0);
+    }
+    f.lam[2 * k] = tk.r;
+    f.lam[2 * k + 1] = tk.i;
+  }
+  __syncthreads();
+  // ---- Winv = Wv^{-1} (unit upper triangular) into H (T no longer needed)
+  if (lane < M) {
+    const int j = lane;
+    for (int i = 0; i < M; ++i) H[i * M + j] = cmk(i == j ? 1.0 : 0.0, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      cplx sacc = cmk(0.0, 0.0);
+      for (int k2 = i + 1; k2 <= j; ++k2) sacc = cadd(sacc, cmul(Wv[i * M + k2], H[k2 * M + j]));
+      H[i * M + j] = cscale(sacc, -1.0);
+    }
+  }
+  __syncthreads();
+  // ---- H3 = Winv Z^H  (H3[m][q] = sum_j Winv[m][j] conj(Z[q][j]))
+  for (int t = lane; t < MM; t += 64) {
+    const int m = t / M, q = t - (t / M) * M;
+    cplx sacc = cmk(0.0, 0.0);
+    for (int j = m; j < M; ++j) sacc = cadd(sacc, cmul(H[m * M + j], cconj(Z[q * M + j])));
+    f.H3[2 * t] = sacc.r;
+    f.H3[2 * t + 1] = sacc.i;
+  }
+  __syncthreads();
+  // ---- ZW = Z Wv into H, then H2 = C1inv^T ZW (H2[q][m] = sum_j C1inv[j][q] ZW[j][m])
+  for (int t = lane; t < MM; t += 64) {
+    const int i = t / M, m = t - (t / M) * M;
+    cplx sacc = cmk(0.0, 0.0);
+    for (int j = 0; j <= m; ++j) sacc = cadd(sacc, cmul(Z[i * M + j], Wv[j * M + m]));
+    H[t] = sacc;
+  }
+  __syncthreads();
+  for (int t = lane; t < MM; t += 64) {
+    const int q = t / M, m = t - (t / M) * M;
+    cplx sacc = cmk(0.0, 0.0);
+    for (int j = 0; j < M; ++j) sacc = cadd(sacc, cscale(H[j * M + m], Ci[j * M + q]));
+    f.H2[2 * t] = sacc.r;
+    f.H2[2 * t + 1] = sacc.i;
+  }
+  if (lane == 0) A.info[0] = s_fail ? -s_fail : 0;
+}
+
+constexpr int kFdThreads = 256;
+
+// Banded complex solves (A1 + lambda_m A2) y_m = r_m of the fast
+// diagonalisation with the elimination window in registers: lane m of wave 0
+// owns system m and keeps rows k..k+w, columns k..k+w of its partly reduced
+// matrix (a (w+1)^2 ring indexed by row and column modulo w+1, so the
+// unrolled steps address it statically) plus the right-hand sides of those
+// rows.  Band rows (A1, A2 pairs, shared by the M systems) are staged into a
+// three-chunk LDS ring by waves 1..3 while wave 0 eliminates; the right-hand
+// side entering at step k is loaded w+1 steps ahead.  Each step stores the
+// reciprocal pivot and the w upper entries of row k (the U row, layout
+// [row][entry][system] so stores and loads are coalesced over systems) and
+// the reduced right-hand side; back substitution walks the rows upwards with
+// the U rows loaded w+1 rows ahead.  Rows beyond n are identity rows, so the
+// last steps need no guards.  No pivoting: a zero pivot sets the info word.
+template <int W>
+__device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLam, double2* ring, int* s_info) {
+  constexpr int W1 = W + 1, BW = 2 * W + 1, CH = W1 * (32 / W1);
+  const int n = A.n, M = A.M, tid = threadIdx.x, wave = tid >> 6, m = tid & 63;
+  const double* b1 = A.band;
+  const double* b2 = A.band + long(n) * BW;
+  cplx* Yg = reinterpret_cast<cplx*>(f.Y);
+  cplx* Ug = reinterpret_cast<cplx*>(f.U);
+  // staged (a1, a2) of band row i, offset o (column i - W + o), with fixed
+  // rows (identity), fixed and out-of-range columns (zero) applied
+  auto stage = [&](int c, int t0, int nt) {
+    double2* dst = ring + (c % 3) * CH * BW;
+    for (int t = t0; t < CH * BW; t += nt) {
+      const int i = c * CH + t / BW, o = t % BW, j = i - W + o;
+      double2 v = make_double2(0.0, 0.0);
+      if (i >= n || is_fixed(A, i)) {
+        v.x = (o == W) ? 1.0 : 0.0;
+      } else if (j >= 0 && j < n && !is_fixed(A, j)) {
+        v = make_double2(b1[long(i) * BW + o], b2[long(i) * BW + o]);
+      }
+      dst[t] = v;
+    }
+  };
+  const int nchunks = (n + W) / CH + 1;   // rows up to n + W are read
+  stage(0, tid, blockDim.x);
+  if (nchunks > 1) stage(1, tid, blockDim.x);
+  __syncthreads();
+  const bool act = wave == 0 && m < M;
+  const cplx lam = act ? sLam[m] : cmk(0.0, 0.0);
+  auto E = [&](int i, int o) -> cplx {
+    const double2 v = ring[((i / CH) % 3 * CH + i % CH) * BW + o];
+    return cmk(v.x + lam.r * v.y, lam.i * v.y);
+  };
+  auto rhs_at = [&](int i) -> cplx { return i < n ? Yg[long(i) * M + m] : cmk(0.0, 0.0); };
+  cplx win[W1][W1], rhs[W1], rnext[W1];
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < W1; ++r) {
+#pragma unroll
+      for (int c = 0; c < W1; ++c) win[r][c] = E(r, c - r + W);
+      rhs[r] = rhs_at(r);
+      rnext[r] = rhs_at(r + W1);
+    }
+  }
+  int info = 0;
+  // ---- forward elimination, one chunk of CH rows per barrier
+  for (int c = 0; c * CH < n; ++c) {
+    if (act) {
+      for (int k0 = c * CH; k0 < (c + 1) * CH && k0 < n; k0 += W1) {
+#pragma unroll
+        for (int p = 0; p < W1; ++p) {
+          const int k = k0 + p;
+          if (k < n) {
+            const cplx piv = win[p][p];
+            const double d = piv.r * piv.r + piv.i * piv.i;
+            if (!(d > 0.0) || !(d < INFINITY)) info = info ? info : k + 1;
+            const cplx inv = cscale(cconj(piv), 1.0 / d);
+#pragma unroll
+            for (int r = 1; r < W1; ++r) {
+              const int rs = (p + r) % W1;
+              const cplx l = cmul(win[rs][p], inv);
+#pragma unroll
+              for (int cc = 1; cc < W1; ++cc) {
+                const int cs = (p + cc) % W1;
+                win[rs][cs] = csub(win[rs][cs], cmul(l, win[p][cs]));
+              }
+              rhs[rs] = csub(rhs[rs], cmul(l, rhs[p]));
+            }
+            cplx* u = Ug + long(k) * W1 * M + m;
+            u[0] = inv;
+#pragma unroll
+            for (int cc = 1; cc < W1; ++cc) u[long(cc) * M] = win[p][(p + cc) % W1];
+            Yg[long(k) * M + m] = rhs[p];
+            // slot p now takes row k + W1 (columns k+1 .. k+W1) and column
+            // k + W1 (rows k+1 .. k+W)
+            const int i = k + W1;
+#pragma unroll
+            for (int cc = 1; cc <= W1; ++cc) win[p][(p + cc) % W1] = E(i, cc - 1);
+#pragma unroll
+            for (int r = 1; r < W1; ++r) win[(p + r) % W1][p] = E(k + r, 2 * W + 1 - r);
+            rhs[p] = rnext[p];
+            rnext[p] = rhs_at(k + 2 * W1);
+          }
+        }
+      }
+    } else if (wave > 0) {
+      if (c + 2 < nchunks) stage(c + 2, tid - 64, blockDim.x - 64);
+    }
+    __syncthreads();
+  }
+  if (act && info) atomicCAS(s_info, 0, info);
+  // ---- back substitution: y_k = inv_k (yhat_k - sum_c U[k][c] y_{k+c})
+  if (act) {
+    cplx ub[W1][W1], yh[W1], yw[W1];
+    const int gtop = (n - 1) / W1;
+#pragma unroll
+    for (int p = 0; p < W1; ++p) {   // slot p: the highest row below n with k % W1 == p
+      yw[p] = cmk(0.0, 0.0);
+      const int k = gtop * W1 + p < n ? gtop * W1 + p : (gtop - 1) * W1 + p;
+      if (k >= 0) {
+#pragma unroll
+        for (int cc = 0; cc < W1; ++cc) ub[p][cc] = Ug[(long(k) * W1 + cc) * M + m];
+        yh[p] = Yg[long(k) * M + m];
+      }
+    }
+    for (int g = gtop; g >= 0; --g) {
+#pragma unroll
+      for (int p = W1 - 1; p >= 0; --p) {
+        const int k = g * W1 + p;
+        if (k < n) {
+          cplx acc = yh[p];
+#pragma unroll
+          for (int cc = 1; cc < W1; ++cc) acc = csub(acc, cmul(ub[p][cc], yw[(p + cc) % W1]));
+          const cplx y = cmul(acc, ub[p][0]);
+          yw[p] = y;
+          Yg[long(k) * M + m] = y;
+          if (k - W1 >= 0) {
+#pragma unroll
+            for (int cc = 0; cc < W1; ++cc) ub[p][cc] = Ug[(long(k - W1) * W1 + cc) * M + m];
+            yh[p] = Yg[long(k - W1) * M + m];
+          }
+        }
+      }
+    }
+  }
+}
+
+__device__ void fd_solve_body(const SolveArgs& A) {
+  extern __shared__ double lds[];
+  const int M = A.M, MM = M * M, n = A.n, w = 2 * A.s + 1, BW = 2 * w + 1, W1 = w + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  cplx* sH2 = reinterpret_cast<cplx*>(lds);    // M x M
+  cplx* sH3 = sH2 + MM;                          // M x M
+  cplx* sLam = sH3 + MM;                         // M
+  cplx* win = sLam + M;                          // M systems x (w+1) rows x (2w+1)
+  const FdWs f = fd_ws(A);
+  __shared__ int s_info;
+  if (tid == 0) s_info = 0;
+  if (A.info[0] != 0) return;   // the eigen stage failed: leave its code
+  for (int t = tid; t < MM; t += nt) {
+    sH2[t] = cmk(f.H2[2 * t], f.H2[2 * t + 1]);
+    sH3[t] = cmk(f.H3[2 * t], f.H3[2 * t + 1]);
+  }
+  for (int m = tid; m < M; m += nt) sLam[m] = cmk(f.lam[2 * m], f.lam[2 * m + 1]);
+  __syncthreads();
+  cplx* Y = reinterpret_cast<cplx*>(f.Y);      // n x M
+  cplx* U = reinterpret_cast<cplx*>(f.U);      // M x n x (w+1)
+  // ---- R = Q H2 (fixed rows zero)
+  for (long t = tid; t < long(n) * M; t += nt) {
+    const int i = int(t / M), m = int(t - (t / M) * M);
+    cplx sacc = cmk(0.0, 0.0);
+    if (!is_fixed(A, i))
+      for (int q = 0; q < M; ++q) sacc = cadd(sacc, cscale(sH2[q * M + m], A.Q[long(i) * M + q]));
+    Y[t] = sacc;
+  }
+  __syncthreads();
+  // ---- banded systems (A1 + l_m A2) y = r
+  if (w == 5 || w == 3 || w == 1) {
+    double2* ring = reinterpret_cast<double2*>(win);
+    if (w == 5) fd_banded_reg<5>(A, f, sLam, ring, &s_info);
+    if (w == 3) fd_banded_reg<3>(A, f, sLam, ring, &s_info);
+    if (w == 1) fd_banded_reg<1>(A, f, sLam, ring, &s_info);
+  } else if (tid < M) {   // any patch size: one lane per system, ring of rows in LDS
+    const double* b1 = A.band;
+    const double* b2 = A.band + long(n) * BW;
+    const int m = tid;
+    const cplx lam = sLam[m];
+    cplx* wr = win + long(m) * W1 * BW;   // ring of w+1 rows, entry c <-> column (row - w + c)
+    auto entry = [&](int i, int j) -> cplx {   // original matrix entry, fixed rows/cols applied
+      if (j < 0 || j >= n || j < i - w || j > i + w) return cmk(0.0, 0.0);
+      const bool fi = is_fixed(A, i), fj = is_fixed(A, j);
+      if (fi) return cmk(i == j ? 1.0 : 0.0, 0.0);
+      if (fj) return cmk(0.0, 0.0);
+      const double a1 = b1[long(i) * BW + (j - i + w)], a2 = b2[long(i) * BW + (j - i + w)];
+      return cmk(a1 + lam.r * a2, lam.i * a2);
+    };
+    auto load_row = [&](int i) {
+      cplx* row = wr + (i % W1) * BW;
+      for (int c = 0; c < BW; ++c) row[c] = entry(i, i - w + c);
+    };
+    for (int i = 0; i < min(W1, n); ++i) load_row(i);
+    for (int k = 0; k < n; ++k) {
+      cplx* rk = wr + (k % W1) * BW;          // row k: column k at c = w
+      const cplx piv = rk[w];
+      if (!(cabs2(piv) > 0.0) || !isfinite(piv.r) || !isfinite(piv.i)) {
+        atomicCAS(&s_info, 0, k + 1);
+      }
+      const cplx yk = Y[long(k) * M + m];
+      for (int i = k + 1; i <= min(k + w, n - 1); ++i) {
+        cplx* ri = wr + (i % W1) * BW;          // row i: column k at c = w - (i - k)
+        const int ci = w - (i - k);
+        const cplx l = cdivz(ri[ci], piv);
+        ri[ci] = cmk(0.0, 0.0);
+        for (int c = 1; c <= w; ++c) ri[ci + c] = csub(ri[ci + c], cmul(l, rk[w + c]));
+        Y[long(i) * M + m] = csub(Y[long(i) * M + m], cmul(l, yk));
+      }
+      // keep U row k (diagonal and w upper entries), then bring in row k+w+1
+      for (int c = 0; c <= w; ++c) U[(long(m) * n + k) * W1 + c] = rk[w + c];
+      if (k + W1 < n) load_row(k + W1);
+    }
+    for (int k = n - 1; k >= 0; --k) {
+      const cplx* uk = U + (long(m) * n + k) * W1;
+      cplx sacc = Y[long(k) * M + m];
+      for (int c = 1; c <= w && k + c < n; ++c) sacc = csub(sacc, cmul(uk[c], Y[long(k + c) * M + m]));
+      Y[long(k) * M + m] = cdivz(sacc, uk[0]);
+    }
+  }
+  __syncthreads();
+  // ---- X = Re(Y H3), fixed rows zero
+  for (long t = tid; t < long(n) * M; t += nt) {
+    const int i = int(t / M), q = int(t - (t / M) * M);
+    double x = 0.0;
+    if (!is_fixed(A, i))
+      for (int m = 0; m < M; ++m) {
+        const cplx y = Y[long(i) * M + m], h = sH3[m * M + q];
+        x += y.r * h.r - y.i * h.i;
+      }
+    A.X[t] = x;
+  }
+  if (tid == 0 && s_info) A.info[0] = s_info;
+}
+
+__global__ __launch_bounds__(64) void k_fd_eig(const SolveArgs* __restrict__ args, const int* __restrict__ active) {
+  const SolveArgs A = args[active[blockIdx.x]];
+  fd_eig_body(A);
+}
+__global__ __launch_bounds__(kFdThreads) void k_fd_solve(const SolveArgs* __restrict__ args,
+                                                         const int* __restrict__ active) {
+  const SolveArgs A = args[active[blockIdx.x]];
+  fd_solve_body(A);
+}
+__global__ __launch_bounds__(64) void k_fd_eig_one(SolveArgs A) { fd_eig_body(A); }
+__global__ __launch_bounds__(kFdThreads) void k_fd_solve_one(SolveArgs A) { fd_solve_body(A); }
+
+size_t fd_eig_lds(int M) { return size_t(8) * M * M * 8; }
+size_t fd_solve_lds(int M, int s) {
+  const int w = 2 * s + 1;
+  const size_t rows = size_t(M) * (w + 1) * (2 * w + 1);          // per-system row rings (any w)
+  const size_t ring = size_t(3) * ((w + 1) * (32 / (w + 1))) * (2 * w + 1);   // staged band chunks
+  return (size_t(2) * M * M + M + std::max(rows, ring)) * 16;
+}
+size_t fd_eig_allowed = 0, fd_solve_allowed = 0, fd_eig1_allowed = 0, fd_solve1_allowed = 0;
+
+bool fd_supported(int M, int s, int K) {
+  return K == 2 && M <= kFdMaxM && fd_eig_lds(M) <= 160 * 1024 - 2048 && fd_solve_lds(M, s) <= 160 * 1024 - 2048;
+}
+
+// Algorithmic flops of one fast-diagonalisation solve: the eigen stage
+// (nominal 30 M^3: inverse, E, Hessenberg form, QR, eigenvectors, H2, H3), the
+// two complex transforms (4 n M^2 each) and the M banded complex solves
+// (8 n w (w + 2) each).
+double fd_flops(int n, int M, int w) {
+  return 30.0 * M * double(M) * M + 8.0 * n * double(M) * M + 8.0 * M * double(n) * w * (w + 2);
+}
+
+// Algorithmic bytes: the two bands, Q and X once each, the couplings, and the
+// complex right-hand sides written and read back plus the U rows.
+double fd_bytes(int n, int M, int w) {
+  return 8.0 * (2.0 * n * (2 * w + 1) + 2.0 * n * M + 2.0 * M * M) + 16.0 * (2.0 * n * M + 2.0 * n * M * (w + 1));
+}
+
 }  // namespace
 
 namespace taps {
@@ -739,16 +1348,26 @@ size_t solve_lds_bytes(int M, int s) {
   return fwd > back ? fwd : back;
 }
 
+// Doubles of the first workspace region: the block LU's stored factors, or
+// the fast diagonalisation's transforms, eigenvalues, C1^{-1}, complex
+// right-hand sides and banded U rows, whichever is larger.
+size_t zst_doubles(int n, int M, int s) {
+  const size_t w = 2 * s + 1, lu = size_t(n) * M * w * M;
+  const size_t fd = size_t(5) * M * M + 2 * size_t(M) + 2 * size_t(n) * M * (w + 2);
+  return std::max(lu, fd);
+}
+
 taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
                            const double* d_Q, double* d_X, int* d_info, double* d_berr, hipStream_t stream) {
   const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
   const size_t lds_mfma = solve_mfma_lds_bytes(M, s);
   const bool use_mfma = lds_mfma <= 160 * 1024 - 64 && !getenv("TAPS_SOLVE_VECTOR");
   const size_t lds = use_mfma ? lds_mfma : solve_lds_bytes(M, s);
-  if (lds > 160 * 1024 - 64)
+  const bool use_fd = h->tune.solver == 1 && fd_supported(M, s, p->n_kinds[d]);
+  if (!use_fd && lds > 160 * 1024 - 64)
     return fail(h, TAPS_ERR_UNSUPPORTED, "M=%d with s=%d needs %zu bytes of LDS (max 163840)", M, s, lds);
   Bump bump;
-  const size_t o_Z = bump.take(size_t(n) * M * w * M * 8);
+  const size_t o_Z = bump.take(zst_doubles(n, M, s) * 8);
   const size_t o_Y = bump.take(size_t(n) * M * 8);
   const size_t o_W = bump.take(size_t(w + 1) * (w + 1) * M * M * 8);
   const size_t o_R = bump.take(size_t(w + 1) * M * 8);
@@ -771,7 +1390,16 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
   A.rhs = reinterpret_cast<double*>(ws + o_R);
   A.info = d_info;
   size_t slot;
-  if (use_mfma) {
+  if (use_fd) {
+    TAPS_TRY(allow_lds(h, k_fd_eig_one, fd_eig_lds(M), &fd_eig1_allowed));
+    TAPS_TRY(allow_lds(h, k_fd_solve_one, fd_solve_lds(M, s), &fd_solve1_allowed));
+    TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+    k_fd_eig_one<<<1, 64, fd_eig_lds(M), stream>>>(A);
+    TAPS_LAUNCHED(h, "k_fd_eig");
+    k_fd_solve_one<<<1, kFdThreads, fd_solve_lds(M, s), stream>>>(A);
+    TAPS_LAUNCHED(h, "k_fd_solve");
+    TAPS_TRY(prof_end(h, slot, fd_flops(n, M, w), fd_bytes(n, M, w), stream));
+  } else if (use_mfma) {
     lu_single_fn fn = lu_single_for(M);
     TAPS_TRY(allow_lds(h, fn, lds, &lu_mfma_lds_allowed[mp_of(M) / 8]));
     TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
@@ -800,7 +1428,7 @@ size_t solve_args_bytes() { return sizeof(SolveArgs); }
 size_t solve_ws_bytes(int n, int M, int s) {
   const int w = 2 * s + 1;
   Bump bump;
-  bump.take(size_t(n) * M * w * M * 8);
+  bump.take(zst_doubles(n, M, s) * 8);
   bump.take(size_t(n) * M * 8);
   bump.take(size_t(w + 1) * (w + 1) * M * M * 8);
   bump.take(size_t(w + 1) * M * 8);
@@ -813,7 +1441,7 @@ void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_
                      double* d_X, int* d_info, void* ws) {
   const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
   Bump bump;
-  const size_t o_Z = bump.take(size_t(n) * M * w * M * 8);
+  const size_t o_Z = bump.take(zst_doubles(n, M, s) * 8);
   const size_t o_Y = bump.take(size_t(n) * M * 8);
   const size_t o_W = bump.take(size_t(w + 1) * (w + 1) * M * M * 8);
   const size_t o_R = bump.take(size_t(w + 1) * M * 8);
@@ -837,6 +1465,28 @@ void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_
 }
 
 bool solve_batched_supported(int M, int s) { return solve_mfma_lds_bytes(M, s) <= 160 * 1024 - 64; }
+
+bool solve_fd_supported(int M, int s, int K) { return fd_supported(M, s, K); }
+double solve_fd_flops(int n, int M, int s) { return fd_flops(n, M, 2 * s + 1); }
+double solve_fd_bytes(int n, int M, int s) { return fd_bytes(n, M, 2 * s + 1); }
+
+taps_status fd_prepare(taps_handle* h, int M, int s) {
+  TAPS_TRY(allow_lds(h, k_fd_eig, fd_eig_lds(M), &fd_eig_allowed));
+  return allow_lds(h, k_fd_solve, fd_solve_lds(M, s), &fd_solve_allowed);
+}
+
+taps_status fd_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active, int M, int s,
+                              double flops, double bytes, hipStream_t stream) {
+  size_t slot;
+  TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+  const SolveArgs* args = static_cast<const SolveArgs*>(d_args);
+  k_fd_eig<<<n_active, 64, fd_eig_lds(M), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_eig");
+  k_fd_solve<<<n_active, kFdThreads, fd_solve_lds(M, s), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_solve");
+  TAPS_TRY(prof_end(h, slot, flops, bytes, stream));
+  return TAPS_OK;
+}
 
 taps_status solve_batched_prepare(taps_handle* h, int M, int s) {
   return allow_lds(h, lu_batched_for(M), solve_mfma_lds_bytes(M, s), &lu_mfma_batched_lds_allowed[mp_of(M) / 8]);

@@ -241,7 +241,10 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
     *rho = (info || bad >= 0) ? NAN : res[D + 1];
     if (history) history[it] = *rho;
     if (info) {
-      fail(h, TAPS_OK, "sweep %d: zero or non-finite pivot (info %d)", it + 1, info);
+      if (info < 0)
+        fail(h, TAPS_OK, "sweep %d: eigen stage of the fast diagonalisation failed (info %d)", it + 1, info);
+      else
+        fail(h, TAPS_OK, "sweep %d: zero or non-finite pivot (info %d)", it + 1, info);
       break;
     }
     if (bad >= 0) {

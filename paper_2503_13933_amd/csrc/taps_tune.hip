@@ -4,7 +4,7 @@
 // the trials.  Choices are cached in a small JSON file keyed by the batch
 // shape, one entry per line:
 //   {
-//     "B=256;D=4;M=40;s=2,2,2,2;n=512,512,128,257;R=257,1,1,257;K=2,2,2,2": {"graph_sweeps": 1, "ms_per_sweep": 151.2},
+//     "B=256;D=4;M=40;solver=1;s=2,2,2,2;n=512,512,128,257;R=257,1,1,257;K=2,2,2,2": {"graph_sweeps": 1, "ms_per_sweep": 151.2},
 //     ...
 //   }
 #include "taps_internal.hpp"
@@ -18,10 +18,10 @@ namespace {
 constexpr int kCandidates[4] = {0, 1, 2, 4};
 constexpr int kTimedSweeps = 4;
 
-std::string shape_key(int B, const taps_problem_t* probs) {
+std::string shape_key(int B, const taps_problem_t* probs, int solver) {
   const taps_problem_t& p0 = probs[0];
   std::ostringstream k;
-  k << "B=" << B << ";D=" << p0.D << ";M=" << p0.M << ";s=";
+  k << "B=" << B << ";D=" << p0.D << ";M=" << p0.M << ";solver=" << solver << ";s=";
   for (int d = 0; d < p0.D; ++d) k << (d ? "," : "") << p0.s[d];
   const char* tags[3] = {";n=", ";R=", ";K="};
   for (int f = 0; f < 3; ++f) {
@@ -81,7 +81,7 @@ extern "C" taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_prob
   if (!h) return TAPS_ERR_INVALID;
   if (B < 1 || !probs || !d_U || !chosen) return fail(h, TAPS_ERR_INVALID, "bad autotune arguments");
   for (int b = 0; b < B; ++b) TAPS_TRY(check_problem(h, &probs[b]));
-  const std::string key = shape_key(B, probs);
+  const std::string key = shape_key(B, probs, h->tune.solver);
   std::vector<std::string> entries;
   if (cache_path) {
     entries = read_entries(cache_path);

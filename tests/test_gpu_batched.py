@@ -29,12 +29,20 @@ def env(taps_lib):
     h.close()
 
 
-def test_uneven_batch_matches_single_and_oracle(env):
+@pytest.fixture(params=["blocklu", "fastdiag"])
+def solver(env, request):
+    torch, capi, problem, h = env
+    capi.taps_set_tuning(h, solver=capi.SOLVER_FAST_DIAG if request.param == "fastdiag" else capi.SOLVER_BLOCK_LU)
+    yield request.param
+    capi.taps_set_tuning(h, solver=capi.SOLVER_BLOCK_LU)
+
+
+def test_uneven_batch_matches_single_and_oracle(env, solver):
     torch, capi, problem, h = env
     cases = [W.heat_slab(40, 33, 10, 21, M=6, seed=11),
              W.heat_slab(67, 70, 13, 9, M=6, seed=12, power=120.0, radius=0.07),
              W.heat_slab(24, 20, 12, 17, M=6, seed=13, k=0.012, y0=0.35)]
-    _say("batched: 3 uneven heat slabs, M=6, 2 sweeps")
+    _say(f"batched: 3 uneven heat slabs, M=6, 2 sweeps ({solver})")
     devs = [problem.heat_slab(h, c) for c in cases]
     U0 = [W.initial_factors(c.axes, c.M, c.seed) for c in cases]
     Ub = [d.factors(u) for d, u in zip(devs, U0)]
@@ -59,14 +67,14 @@ def test_uneven_batch_matches_single_and_oracle(env):
         _say(f"  n={[a.n for a in c.axes]} rho batched {rb:.6e} single {rs:.6e} oracle {ro:.6e}")
 
 
-def test_batch_predicates_converged_problems(env):
+def test_batch_predicates_converged_problems(env, solver):
     # a rank-one manufactured heat field converges in a few sweeps; a Gaussian
     # slab with M = 1 needs many: each must stop at its own sweep count and
     # agree with its single-problem run
     torch, capi, problem, h = env
     cpoly = W.heat_slab(9, 8, 10, 7, M=1, seed=5)
     cgauss = W.heat_slab(24, 20, 12, 17, M=1, seed=7)
-    _say("batched predication: polynomial + gaussian, M=1, tol 1e-10")
+    _say(f"batched predication: polynomial + gaussian, M=1, tol 1e-10 ({solver})")
     dpoly = problem.heat_polynomial(h, cpoly)
     dg = problem.heat_slab(h, cgauss)
     u0 = [W.initial_factors(cpoly.axes, 1, 5), W.initial_factors(cgauss.axes, 1, 7)]

@@ -78,7 +78,7 @@ def test_autotune_restores_factors_and_uses_cache(env, tmp_path):
     torch.cuda.synchronize()
     _say(f"autotune: ms per sweep for graph_sweeps 0/1/2/4 = {[round(m, 3) for m in ms]} -> {K}")
     assert K in (0, 1, 2, 4) and all(m > 0 for m in ms)
-    assert capi.taps_get_tuning(h) == K
+    assert capi.taps_get_tuning(h).graph_sweeps == K
     for a, b in zip(U, before):
         for u, v in zip(a, b):
             assert torch.equal(u, v)

@@ -180,18 +180,35 @@ def _oracle_C_to_dev(ora, Co, d, M):
     return out
 
 
-@pytest.mark.parametrize("kernel", ["mfma", "vector"])
+@pytest.fixture
+def solver(env):
+    """Selects the dim solver for one test and restores block LU after it."""
+    torch, capi, problem, h = env
+
+    def use(which):
+        capi.taps_set_tuning(h, solver=which)
+    yield use
+    capi.taps_set_tuning(h, solver=capi.SOLVER_BLOCK_LU)
+
+
+@pytest.mark.parametrize("kernel", ["mfma", "vector", "fastdiag"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_solve_dim(env, name, kernel, monkeypatch):
+def test_solve_dim(env, name, kernel, monkeypatch, solver):
     torch, capi, problem, h = env
     _say(f"solve_dim {name} ({kernel} kernel)")
     if kernel == "vector":
         monkeypatch.setenv("TAPS_SOLVE_VECTOR", "1")
     else:
         monkeypatch.delenv("TAPS_SOLVE_VECTOR", raising=False)
+    solver(capi.SOLVER_FAST_DIAG if kernel == "fastdiag" else capi.SOLVER_BLOCK_LU)
     case, dev, ora = _both(env, name)
+    _check_solve_dim(env, case, dev, ora, seed=23)
+
+
+def _check_solve_dim(env, case, dev, ora, seed):
+    torch, capi, problem, h = env
     M = case.M
-    Uh = _rand_U(ora, M, 23)
+    Uh = _rand_U(ora, M, seed)
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     berr = torch.zeros(1, dtype=torch.float64, device="cuda")
     for d in range(ora.D):
@@ -212,6 +229,18 @@ def test_solve_dim(env, name, kernel, monkeypatch):
         # the library's own a-posteriori backward error is at rounding level too
         assert float(berr.item()) < 1e-12, float(berr.item())
         assert rel(X, Xo) < TOL, (d, rel(X, Xo))
+
+
+@pytest.mark.parametrize("M", [40, 48])
+def test_solve_dim_fast_diag_wide(env, M, solver):
+    # bench-sized mode counts (the eigen stage's largest M) on grids spanning
+    # several hundred rows with ragged ends
+    torch, capi, problem, h = env
+    _say(f"solve_dim fast diagonalisation, heat slab 130 x 70 x 20 x 33, M={M}")
+    solver(capi.SOLVER_FAST_DIAG)
+    case = W.heat_slab(130, 70, 20, 33, M=M, seed=4)
+    dev = problem.build(h, case)
+    _check_solve_dim(env, case, dev, problems.heat_slab(case), seed=41)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -242,10 +271,12 @@ def test_residual_and_balance(env, name):
 WELL_POSED = {"heat_tiny", "heat_ragged", "heat_M13", "heat_s1"}
 
 
+@pytest.mark.parametrize("which", ["blocklu", "fastdiag"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_sweeps(env, name):
+def test_sweeps(env, name, which, solver):
     torch, capi, problem, h = env
-    _say(f"sweeps {name}")
+    _say(f"sweeps {name} ({which})")
+    solver(capi.SOLVER_FAST_DIAG if which == "fastdiag" else capi.SOLVER_BLOCK_LU)
     case, dev, ora = _both(env, name)
     U0 = W.initial_factors(case.axes, case.M, case.seed)
     U = dev.factors(U0)
@@ -264,7 +295,7 @@ def test_sweeps(env, name):
         if math.isnan(rho):
             msg = capi.last_error(h)
             _say(f"  breakdown reported: {msg}")
-            assert "backward error" in msg or "pivot" in msg
+            assert "backward error" in msg or "pivot" in msg or "eigen stage" in msg
             return
     assert sweeps == 2
     Ug = [u.cpu().numpy() for u in U]
