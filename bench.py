@@ -47,7 +47,7 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 # Memory traffic of the batched dim solve per algorithmic flop, from two
 # rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a
 # 1 GiB copy), valid for the solve source with this SHA-256 prefix only.
-SOLVE_TRAFFIC = {"bytes_per_flop": 0.2813, "source_sha256": "c9a856e7e0610480"}
+SOLVE_TRAFFIC = {"bytes_per_flop": 0.2813, "source_sha256": "c9a856e7e0610480", "solver": "blocklu"}
 
 
 def log(msg):
@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--train-chains", type=int, default=512)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--Kc", type=int, default=8, help="modes of the carried initial condition")
+    ap.add_argument("--solver", choices=["fastdiag", "blocklu"], default="fastdiag",
+                    help="dim solver: fast diagonalisation (complex Schur) or block LU")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -123,13 +125,19 @@ def main():
     torch.cuda.set_device(0)
     grid = dict(nx=args.nx, ny=args.nx, nz=args.nz, nt=args.nt, M=args.M)
     h = capi.Handle()
+    capi.taps_set_tuning(h, solver=capi.SOLVER_FAST_DIAG if args.solver == "fastdiag" else capi.SOLVER_BLOCK_LU)
     M, B, N, cap = args.M, args.batch, args.slabs, 2 * args.sweeps
 
     # ---- set-up (untimed): benchmark slabs, training chains, network
     t0 = time.perf_counter()
     cases = family(N, args.seed, **grid)
     probs = [chain.slab_problem(h, c) for c in cases]
-    U_plain = [p.factors(W.initial_factors(c.axes, M, c.seed)) for p, c in zip(probs, cases)]
+    # random starts of all slabs, one (N, n_d, M) tensor per dim (a slab's factors are slices)
+    U0_host = [W.initial_factors(c.axes, M, c.seed) for c in cases]
+    U_plain_big = [torch.tensor(np.stack([u[d] for u in U0_host]), dtype=torch.float64, device="cuda")
+                   for d in range(4)]
+    del U0_host
+    U_plain = [[t[b] for t in U_plain_big] for b in range(N)]
     layout = ws.Layout(h, cases[0], M)
     n_tr = args.train_chains
     tr_a = family(n_tr, args.seed + 101, **grid)
@@ -158,12 +166,13 @@ def main():
 
     def step_warm():
         Y = net.forward(X_bench)
-        U = [layout.initial(Y[b], fixed) for b in range(N)]
+        U = layout.initial_batch(Y, fixed)
         return ws.solve_stream(h, probs, U, rho_star, cap, B, U_plain=U_plain, median_rho1=med1,
                                on_done=lambda i: reconstruct(U[i], i))
 
     def step_random_batched():
-        U = [[u.clone() for u in Ub] for Ub in U_plain]
+        big = [t.clone() for t in U_plain_big]
+        U = [[t[b] for t in big] for b in range(N)]
         return ws.solve_stream(h, probs, U, rho_star, cap, B, on_done=lambda i: reconstruct(U[i], i))
 
     def timed(fn, label, prof=False):
@@ -206,7 +215,8 @@ def main():
     value = N * args.steps / el_w
     import hashlib
     src = os.path.join(ROOT, "paper_2503_13933_amd", "csrc", "taps_solve.hip")
-    same_kernel = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == SOLVE_TRAFFIC["source_sha256"]
+    same_kernel = (args.solver == SOLVE_TRAFFIC["solver"] and
+                   hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == SOLVE_TRAFFIC["source_sha256"])
     traffic = SOLVE_TRAFFIC["bytes_per_flop"] * fl_solve / n_solve if (same_kernel and n_solve) else None
     achieved = (fl_solve / n_solve) / (ms_solve / n_solve * 1e-3) / 1e12 if n_solve else 0.0
     rec_tf = (fl_rec / n_rec) / (ms_rec / n_rec * 1e-3) / 1e12 if n_rec else 0.0
@@ -228,6 +238,7 @@ def main():
                          f"{B} in flight, to the plain {args.sweeps}-sweep median residual (cap {cap} sweeps), "
                          f"BF16 end-time reconstruction"),
             "variant": "warm-start+batched",
+            "solver": args.solver,
             "batch": B,
             "slabs_per_step": N,
             "target_rho": rho_star,
@@ -249,7 +260,8 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_block_lu_mfma_batched (block-banded FP64 dim solve)",
+            "kernel": ("k_fd_eig + k_fd_solve (fast-diagonalisation FP64 dim solve)" if args.solver == "fastdiag"
+                       else "k_block_lu_mfma_batched (block-banded FP64 dim solve)"),
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",

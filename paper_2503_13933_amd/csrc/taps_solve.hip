@@ -759,55 +759,93 @@ __device__ inline cplx crecip(cplx a) {
   return cplx{a.r * id, -a.i * id};
 }
 
-// Complex Givens rotation [c s; -conj(s) c] [a; b] = [r; 0], c real:
-// c = |a| / r, s = (a / |a|) conj(b) / r, r = sqrt(|a|^2 + |b|^2).  The
-// operands are scaled by max(|a|_1, |b|_1) first so the squares stay in range.
-__device__ inline void cgivens(cplx a, cplx b, double& c, cplx& s) {
-  const double sc = fmax(cabs1(a), cabs1(b));
-  if (cabs1(b) == 0.0 || sc == 0.0) {
+// Complex Givens rotation [c s; -conj(s) c] [f; g] = [r; 0], c real:
+// c = |f| / r, s = f conj(g) / (|f| r), r = sqrt(|f|^2 + |g|^2), from one
+// reciprocal square root of |f|^2 r^2.  Operands of extreme magnitude are
+// rescaled first.
+__device__ inline void cgivens(cplx f, cplx g, double& c, cplx& s) {
+  double f2 = f.r * f.r + f.i * f.i, g2 = g.r * g.r + g.i * g.i;
+  if (g2 == 0.0) {
     c = 1.0;
     s = cmk(0.0, 0.0);
     return;
   }
-  const double is = 1.0 / sc;
-  const cplx as = cscale(a, is), bs = cscale(b, is);
-  const double a2 = as.r * as.r + as.i * as.i, b2 = bs.r * bs.r + bs.i * bs.i;
-  const double ir = 1.0 / sqrt(a2 + b2);
-  if (a2 == 0.0) {
+  if (f2 == 0.0) {
     c = 0.0;
-    s = cscale(cconj(bs), ir);
+    s = cscale(cconj(g), rsqrt(g2));
     return;
   }
-  const double na = sqrt(a2);
-  c = na * ir;
-  s = cscale(cmul(as, cconj(bs)), ir / na);
+  double p = f2 * (f2 + g2);
+  if (!(p > 1e-280 && p < 1e280)) {
+    const double is = 1.0 / fmax(cabs1(f), cabs1(g));
+    f = cscale(f, is);
+    g = cscale(g, is);
+    f2 = f.r * f.r + f.i * f.i;
+    g2 = g.r * g.r + g.i * g.i;
+    p = f2 * (f2 + g2);
+  }
+  const double t = rsqrt(p);
+  c = f2 * t;
+  s = cscale(cmul(f, cconj(g)), t);
 }
 
+// Walk of the M x M index space by one lane of a 64-wide wave: t = lane,
+// lane + 64, ... as (row, column) without integer division in the loop.
+struct IjWalk {
+  int i, j, q, r;
+  __device__ IjWalk(int lane, int M, int stride = 64) : i(lane / M), j(lane % M), q(stride / M), r(stride % M) {}
+  __device__ void next(int M) {
+    i += q;
+    j += r;
+    if (j >= M) {
+      j -= M;
+      ++i;
+    }
+  }
+};
+
+// Eigen stage of the fast diagonalisation for one dim system with two kinds
+// (one 64-wide wave):
+//   C1^{-1} by Gauss-Jordan with partial pivoting,
+//   E = C2^T C1^{-T} (the system becomes A1 X + A2 X E = Q C1^{-T}),
+//   Householder reduction of E to Hessenberg form and complex single-shift
+//   QR to the Schur form E = Z T Z^H (Wilkinson shifts, an exceptional shift
+//   every 11 iterations, at most 40 M iterations),
+//   eigenvectors Wv of T (unit upper triangular), so P = Z Wv,
+//   H2 = C1^{-T} P and H3 = P^{-1} = Wv^{-1} Z^H to the workspace, with the
+//   eigenvalues.
+// LDS: six M x L arrays (L = M rounded up to odd, so that column walks over
+// the lanes hit distinct banks), H and Z complex, four real.
+// info word: 0, -1 (C1 singular) or -2 (no convergence).
 __device__ void fd_eig_body(const SolveArgs& A) {
   extern __shared__ double lds[];
-  const int M = A.M, MM = M * M, lane = threadIdx.x;
-  cplx* H = reinterpret_cast<cplx*>(lds);          // M x M complex (row-major)
-  cplx* Z = H + MM;                                 // M x M complex
-  double* S0 = reinterpret_cast<double*>(Z + MM);   // M x M real (2 buffers), later Wv (complex)
-  double* S1 = S0 + MM;
-  double* Ci = S1 + MM;                             // C1^{-1}
-  double* C2s = Ci + MM;                            // C2, later the Householder vector
+  const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
+  cplx* H = reinterpret_cast<cplx*>(lds);          // M x L complex
+  cplx* Z = H + LL;                                 // M x L complex
+  double* S0 = reinterpret_cast<double*>(Z + LL);   // M x L real (2 buffers), later Wv (complex)
+  double* S1 = S0 + LL;
+  double* Ci = S1 + LL;                             // C1^{-1}
+  double* C2s = Ci + LL;                            // C2, later the Householder vector
+  cplx* Wv = reinterpret_cast<cplx*>(S0);           // M x L complex over S0 and S1
   __shared__ int perm[64];
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
   if (lane == 0) s_fail = 0;
-  // ---- C1^{-1}: Gauss-Jordan with partial pivoting (row swaps, undone as
-  // column swaps at the end)
-  for (int t = lane; t < MM; t += 64) {
-    S0[t] = A.C[t];
-    C2s[t] = A.C[MM + t];
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      S0[w.i * L + w.j] = A.C[t];
+      C2s[w.i * L + w.j] = A.C[MM + t];
+    }
   }
   __syncthreads();
+  // ---- C1^{-1}: Gauss-Jordan with partial pivoting (row swaps, undone as
+  // column swaps at the end)
   double* cur = S0;
   double* nxt = S1;
   for (int r = 0; r < M; ++r) {
     // pivot: largest |cur[i][r]|, i >= r (first on ties), by a wave reduction
-    double bv = (lane >= r && lane < M) ? fabs(cur[lane * M + r]) : -1.0;
+    double bv = (lane >= r && lane < M) ? fabs(cur[lane * L + r]) : -1.0;
     int bi = lane;
     for (int o = 32; o > 0; o >>= 1) {
       const double ov = __shfl_xor(bv, o);
@@ -822,21 +860,24 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       perm[r] = p;
       if (!(bv > 0.0) || !isfinite(bv)) s_fail = 1;
     }
-    if (p != r)
-      for (int j = lane; j < M; j += 64) {
-        const double t = cur[r * M + j];
-        cur[r * M + j] = cur[p * M + j];
-        cur[p * M + j] = t;
-      }
+    if (p != r && lane < M) {
+      const double t = cur[r * L + lane];
+      cur[r * L + lane] = cur[p * L + lane];
+      cur[p * L + lane] = t;
+    }
     __syncthreads();
-    const double ip = 1.0 / cur[r * M + r];
-    for (int t = lane; t < MM; t += 64) {
-      const int i = t / M, j = t - (t / M) * M;
-      const double aij = cur[t], air = cur[i * M + r], arj = cur[r * M + j];
-      double v = aij - air * (arj * ip);
-      v = (j == r) ? -air * ip : v;
-      v = (i == r) ? ((j == r) ? ip : aij * ip) : v;
-      nxt[t] = v;
+    if (lane < M) {   // column lane of the next iterate
+      const int j = lane;
+      const double ip = 1.0 / cur[r * L + r];
+      const double arj = cur[r * L + j] * ip;
+#pragma unroll 4
+      for (int i = 0; i < M; ++i) {
+        const double aij = cur[i * L + j], air = cur[i * L + r];
+        double v = aij - air * arj;
+        v = (j == r) ? -air * ip : v;
+        v = (i == r) ? ((j == r) ? ip : arj) : v;
+        nxt[i * L + j] = v;
+      }
     }
     __syncthreads();
     double* tmp = cur;
@@ -845,29 +886,34 @@ __device__ void fd_eig_body(const SolveArgs& A) {
   }
   for (int r = M - 1; r >= 0; --r) {   // undo the row swaps as column swaps
     const int p = perm[r];
-    if (p != r)
-      for (int i = lane; i < M; i += 64) {
-        const double t = cur[i * M + r];
-        cur[i * M + r] = cur[i * M + p];
-        cur[i * M + p] = t;
-      }
+    if (p != r && lane < M) {
+      const double t = cur[lane * L + r];
+      cur[lane * L + r] = cur[lane * L + p];
+      cur[lane * L + p] = t;
+    }
     __syncthreads();
   }
-  for (int t = lane; t < MM; t += 64) Ci[t] = cur[t];
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) Ci[w.i * L + w.j] = cur[w.i * L + w.j];
+  }
   __syncthreads();
   // ---- E[i][j] = sum_q C2[q][i] C1inv[j][q] into H; Z = I
-  for (int t = lane; t < MM; t += 64) {
-    const int i = t / M, j = t - (t / M) * M;
-    double e = 0.0;
-    for (int q = 0; q < M; ++q) e += C2s[q * M + i] * Ci[j * M + q];
-    H[t] = cmk(e, 0.0);
-    Z[t] = cmk(i == j ? 1.0 : 0.0, 0.0);
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      const int i = w.i, j = w.j;
+      double e = 0.0;
+      for (int q = 0; q < M; ++q) e += C2s[q * L + i] * Ci[j * L + q];
+      H[i * L + j] = cmk(e, 0.0);
+      Z[i * L + j] = cmk(i == j ? 1.0 : 0.0, 0.0);
+    }
   }
   __syncthreads();
   // ---- Householder Hessenberg form (real), Z accumulated
   double* v = C2s;   // length M
   for (int k = 0; k + 2 < M; ++k) {
-    double x = (lane > k && lane < M) ? H[lane * M + k].r : 0.0;
+    const double x = (lane > k && lane < M) ? H[lane * L + k].r : 0.0;
     double ss = x * x;
     for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
     const double x0 = __shfl(x, k + 1);
@@ -882,20 +928,34 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     if (lane < M) v[lane] = vi;
     __syncthreads();
     if (lane < M) {   // left: column lane, rows k+1..
-      double wj = 0.0;
-      for (int i = k + 1; i < M; ++i) wj += v[i] * H[i * M + lane].r;
-      for (int i = k + 1; i < M; ++i) H[i * M + lane].r -= beta * v[i] * wj;
+      double w0 = 0.0, w1 = 0.0;
+      int i = k + 1;
+      for (; i + 1 < M; i += 2) {
+        w0 += v[i] * H[i * L + lane].r;
+        w1 += v[i + 1] * H[(i + 1) * L + lane].r;
+      }
+      if (i < M) w0 += v[i] * H[i * L + lane].r;
+      const double bw = beta * (w0 + w1);
+      for (i = k + 1; i < M; ++i) H[i * L + lane].r -= v[i] * bw;
     }
     __syncthreads();
     if (lane < M) {   // right: row lane, columns k+1.. (H and Z)
-      double u = 0.0, uz = 0.0;
-      for (int j = k + 1; j < M; ++j) {
-        u += H[lane * M + j].r * v[j];
-        uz += Z[lane * M + j].r * v[j];
+      double u0 = 0.0, u1 = 0.0, z0 = 0.0, z1 = 0.0;
+      int j = k + 1;
+      for (; j + 1 < M; j += 2) {
+        u0 += H[lane * L + j].r * v[j];
+        z0 += Z[lane * L + j].r * v[j];
+        u1 += H[lane * L + j + 1].r * v[j + 1];
+        z1 += Z[lane * L + j + 1].r * v[j + 1];
       }
+      if (j < M) {
+        u0 += H[lane * L + j].r * v[j];
+        z0 += Z[lane * L + j].r * v[j];
+      }
+      const double bu = beta * (u0 + u1), buz = beta * (z0 + z1);
       for (int j = k + 1; j < M; ++j) {
-        H[lane * M + j].r -= beta * u * v[j];
-        Z[lane * M + j].r -= beta * uz * v[j];
+        H[lane * L + j].r -= bu * v[j];
+        Z[lane * L + j].r -= buz * v[j];
       }
     }
     __syncthreads();
@@ -907,12 +967,12 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     // lo: the largest i <= hi whose subdiagonal entry is negligible (0 if none)
     bool neg = false;
     if (lane >= 1 && lane <= hi)
-      neg = cabs1(H[lane * M + lane - 1]) <=
-            2.220446049250313e-16 * (cabs1(H[lane * M + lane]) + cabs1(H[(lane - 1) * M + lane - 1]));
+      neg = cabs1(H[lane * L + lane - 1]) <=
+            2.220446049250313e-16 * (cabs1(H[lane * L + lane]) + cabs1(H[(lane - 1) * L + lane - 1]));
     const unsigned long long bal = __ballot(neg);
     const int lo = bal ? 63 - __clzll(bal) : 0;
     __syncthreads();
-    if (lo > 0 && lane == 0) H[lo * M + lo - 1] = cmk(0.0, 0.0);
+    if (lo > 0 && lane == 0) H[lo * L + lo - 1] = cmk(0.0, 0.0);
     if (lo == hi) {
       --hi;
       it = 0;
@@ -921,17 +981,20 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     }
     ++it;
     ++total;
-    const cplx a = H[(hi - 1) * M + hi - 1], b = H[(hi - 1) * M + hi], c = H[hi * M + hi - 1], d = H[hi * M + hi];
+    const cplx a = H[(hi - 1) * L + hi - 1], b = H[(hi - 1) * L + hi], c = H[hi * L + hi - 1], d = H[hi * L + hi];
     const cplx tr = cadd(a, d), det = csub(cmul(a, d), cmul(b, c));
     const cplx disc = csqrtz(csub(cscale(cmul(tr, tr), 0.25), det));
     const cplx l1 = cadd(cscale(tr, 0.5), disc), l2 = csub(cscale(tr, 0.5), disc);
-    cplx mu = (cabs2(csub(l1, d)) < cabs2(csub(l2, d))) ? l1 : l2;
+    cplx mu = (cabs1(csub(l1, d)) < cabs1(csub(l2, d))) ? l1 : l2;
     if (it % 11 == 0) mu = cadd(mu, cmk(cabs1(c), 0.0));   // exceptional shift
-    cplx x = csub(H[lo * M + lo], mu), y = H[(lo + 1) * M + lo];
+    // bulge chase: rotation k zeroes the bulge below the subdiagonal; it acts
+    // on rows k, k+1 (lane = column) and then on columns k, k+1 of H and Z
+    // (lane = row)
+    cplx x = csub(H[lo * L + lo], mu), y = H[(lo + 1) * L + lo];
     for (int k = lo; k < hi; ++k) {
       if (k > lo) {
-        x = H[k * M + k - 1];
-        y = H[(k + 1) * M + k - 1];
+        x = H[k * L + k - 1];
+        y = H[(k + 1) * L + k - 1];
       }
       double cg;
       cplx sg;
@@ -939,21 +1002,21 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       __syncthreads();
       const int j0 = k > 0 ? k - 1 : 0;
       if (lane >= j0 && lane < M) {   // rows k, k+1
-        const cplx hk = H[k * M + lane], hk1 = H[(k + 1) * M + lane];
-        H[k * M + lane] = cadd(cscale(hk, cg), cmul(sg, hk1));
-        H[(k + 1) * M + lane] = csub(cscale(hk1, cg), cmul(cconj(sg), hk));
+        const cplx hk = H[k * L + lane], hk1 = H[(k + 1) * L + lane];
+        H[k * L + lane] = cadd(cscale(hk, cg), cmul(sg, hk1));
+        H[(k + 1) * L + lane] = csub(cscale(hk1, cg), cmul(cconj(sg), hk));
       }
       __syncthreads();
       const int i1 = min(k + 2, hi);
       if (lane <= i1) {   // columns k, k+1 of H (times G^H)
-        const cplx hk = H[lane * M + k], hk1 = H[lane * M + k + 1];
-        H[lane * M + k] = cadd(cscale(hk, cg), cmul(cconj(sg), hk1));
-        H[lane * M + k + 1] = csub(cscale(hk1, cg), cmul(sg, hk));
+        const cplx hk = H[lane * L + k], hk1 = H[lane * L + k + 1];
+        H[lane * L + k] = cadd(cscale(hk, cg), cmul(cconj(sg), hk1));
+        H[lane * L + k + 1] = csub(cscale(hk1, cg), cmul(sg, hk));
       }
       if (lane < M) {
-        const cplx zk = Z[lane * M + k], zk1 = Z[lane * M + k + 1];
-        Z[lane * M + k] = cadd(cscale(zk, cg), cmul(cconj(sg), zk1));
-        Z[lane * M + k + 1] = csub(cscale(zk1, cg), cmul(sg, zk));
+        const cplx zk = Z[lane * L + k], zk1 = Z[lane * L + k + 1];
+        Z[lane * L + k] = cadd(cscale(zk, cg), cmul(cconj(sg), zk1));
+        Z[lane * L + k + 1] = csub(cscale(zk1, cg), cmul(sg, zk));
       }
       __syncthreads();
     }
@@ -961,20 +1024,19 @@ __device__ void fd_eig_body(const SolveArgs& A) {
   if (hi > 0 && lane == 0) s_fail = 2;
   __syncthreads();
   // ---- eigenvectors Wv of T (unit upper triangular), one column per lane
-  cplx* Wv = reinterpret_cast<cplx*>(S0);   // M x M complex in the S region
   if (lane < M) {
     const int k = lane;
-    const cplx tk = H[k * M + k];
+    const cplx tk = H[k * L + k];
     double tn = 0.0;
-    for (int i = 0; i <= k; ++i) tn = fmax(tn, cabs2(H[i * M + i]));
+    for (int i = 0; i <= k; ++i) tn = fmax(tn, cabs1(H[i * L + i]));
     const double small = 2.220446049250313e-16 * fmax(tn, 1e-300);
-    for (int i = 0; i < M; ++i) Wv[i * M + k] = cmk(i == k ? 1.0 : 0.0, 0.0);
+    for (int i = 0; i < M; ++i) Wv[i * L + k] = cmk(i == k ? 1.0 : 0.0, 0.0);
     for (int i = k - 1; i >= 0; --i) {
       cplx sacc = cmk(0.0, 0.0);
-      for (int j = i + 1; j <= k; ++j) sacc = cadd(sacc, cmul(H[i * M + j], Wv[j * M + k]));
-      cplx den = csub(H[i * M + i], tk);
-      if (cabs2(den) < small) den = cmk(small, 0.0);
-      Wv[i * M + k] = cscale(cdivz(sacc, den), -1.0);
+      for (int j = i + 1; j <= k; ++j) sacc = cadd(sacc, cmul(H[i * L + j], Wv[j * L + k]));
+      cplx den = csub(H[i * L + i], tk);
+      if (cabs1(den) < small) den = cmk(small, 0.0);
+      Wv[i * L + k] = cmul(sacc, cscale(crecip(den), -1.0));
     }
     f.lam[2 * k] = tk.r;
     f.lam[2 * k + 1] = tk.i;
@@ -983,37 +1045,46 @@ __device__ void fd_eig_body(const SolveArgs& A) {
   // ---- Winv = Wv^{-1} (unit upper triangular) into H (T no longer needed)
   if (lane < M) {
     const int j = lane;
-    for (int i = 0; i < M; ++i) H[i * M + j] = cmk(i == j ? 1.0 : 0.0, 0.0);
+    for (int i = 0; i < M; ++i) H[i * L + j] = cmk(i == j ? 1.0 : 0.0, 0.0);
     for (int i = j - 1; i >= 0; --i) {
       cplx sacc = cmk(0.0, 0.0);
-      for (int k2 = i + 1; k2 <= j; ++k2) sacc = cadd(sacc, cmul(Wv[i * M + k2], H[k2 * M + j]));
-      H[i * M + j] = cscale(sacc, -1.0);
+      for (int k2 = i + 1; k2 <= j; ++k2) sacc = cadd(sacc, cmul(Wv[i * L + k2], H[k2 * L + j]));
+      H[i * L + j] = cscale(sacc, -1.0);
     }
   }
   __syncthreads();
   // ---- H3 = Winv Z^H  (H3[m][q] = sum_j Winv[m][j] conj(Z[q][j]))
-  for (int t = lane; t < MM; t += 64) {
-    const int m = t / M, q = t - (t / M) * M;
-    cplx sacc = cmk(0.0, 0.0);
-    for (int j = m; j < M; ++j) sacc = cadd(sacc, cmul(H[m * M + j], cconj(Z[q * M + j])));
-    f.H3[2 * t] = sacc.r;
-    f.H3[2 * t + 1] = sacc.i;
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      const int m = w.i, q = w.j;
+      cplx sacc = cmk(0.0, 0.0);
+      for (int j = m; j < M; ++j) sacc = cadd(sacc, cmul(H[m * L + j], cconj(Z[q * L + j])));
+      f.H3[2 * t] = sacc.r;
+      f.H3[2 * t + 1] = sacc.i;
+    }
   }
   __syncthreads();
   // ---- ZW = Z Wv into H, then H2 = C1inv^T ZW (H2[q][m] = sum_j C1inv[j][q] ZW[j][m])
-  for (int t = lane; t < MM; t += 64) {
-    const int i = t / M, m = t - (t / M) * M;
-    cplx sacc = cmk(0.0, 0.0);
-    for (int j = 0; j <= m; ++j) sacc = cadd(sacc, cmul(Z[i * M + j], Wv[j * M + m]));
-    H[t] = sacc;
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      const int i = w.i, m = w.j;
+      cplx sacc = cmk(0.0, 0.0);
+      for (int j = 0; j <= m; ++j) sacc = cadd(sacc, cmul(Z[i * L + j], Wv[j * L + m]));
+      H[i * L + m] = sacc;
+    }
   }
   __syncthreads();
-  for (int t = lane; t < MM; t += 64) {
-    const int q = t / M, m = t - (t / M) * M;
-    cplx sacc = cmk(0.0, 0.0);
-    for (int j = 0; j < M; ++j) sacc = cadd(sacc, cscale(H[j * M + m], Ci[j * M + q]));
-    f.H2[2 * t] = sacc.r;
-    f.H2[2 * t + 1] = sacc.i;
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      const int q = w.i, m = w.j;
+      cplx sacc = cmk(0.0, 0.0);
+      for (int j = 0; j < M; ++j) sacc = cadd(sacc, cscale(H[j * L + m], Ci[j * L + q]));
+      f.H2[2 * t] = sacc.r;
+      f.H2[2 * t + 1] = sacc.i;
+    }
   }
   if (lane == 0) A.info[0] = s_fail ? -s_fail : 0;
 }
@@ -1181,12 +1252,15 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   cplx* Y = reinterpret_cast<cplx*>(f.Y);      // n x M
   cplx* U = reinterpret_cast<cplx*>(f.U);      // M x n x (w+1)
   // ---- R = Q H2 (fixed rows zero)
-  for (long t = tid; t < long(n) * M; t += nt) {
-    const int i = int(t / M), m = int(t - (t / M) * M);
-    cplx sacc = cmk(0.0, 0.0);
-    if (!is_fixed(A, i))
-      for (int q = 0; q < M; ++q) sacc = cadd(sacc, cscale(sH2[q * M + m], A.Q[long(i) * M + q]));
-    Y[t] = sacc;
+  {
+    IjWalk wk(tid, M, nt);
+    for (long t = tid; t < long(n) * M; t += nt, wk.next(M)) {
+      const int i = wk.i, m = wk.j;
+      cplx sacc = cmk(0.0, 0.0);
+      if (!is_fixed(A, i))
+        for (int q = 0; q < M; ++q) sacc = cadd(sacc, cscale(sH2[q * M + m], A.Q[long(i) * M + q]));
+      Y[t] = sacc;
+    }
   }
   __syncthreads();
   // ---- banded systems (A1 + l_m A2) y = r
@@ -1242,8 +1316,9 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   }
   __syncthreads();
   // ---- X = Re(Y H3), fixed rows zero
-  for (long t = tid; t < long(n) * M; t += nt) {
-    const int i = int(t / M), q = int(t - (t / M) * M);
+  IjWalk wk(tid, M, nt);
+  for (long t = tid; t < long(n) * M; t += nt, wk.next(M)) {
+    const int i = wk.i, q = wk.j;
     double x = 0.0;
     if (!is_fixed(A, i))
       for (int m = 0; m < M; ++m) {
@@ -1267,7 +1342,7 @@ __global__ __launch_bounds__(kFdThreads) void k_fd_solve(const SolveArgs* __rest
 __global__ __launch_bounds__(64) void k_fd_eig_one(SolveArgs A) { fd_eig_body(A); }
 __global__ __launch_bounds__(kFdThreads) void k_fd_solve_one(SolveArgs A) { fd_solve_body(A); }
 
-size_t fd_eig_lds(int M) { return size_t(8) * M * M * 8; }
+size_t fd_eig_lds(int M) { return size_t(8) * M * (M | 1) * 8; }
 size_t fd_solve_lds(int M, int s) {
   const int w = 2 * s + 1;
   const size_t rows = size_t(M) * (w + 1) * (2 * w + 1);          // per-system row rings (any w)

@@ -152,16 +152,24 @@ class Layout:
     def initial(self, y, fixed):
         """Network output (n_out,) -> fine initial factors [0, U_y, U_z, U_t];
         rows of fixed nodes set to zero."""
-        out, off = [], 0
+        return self.initial_batch(y.unsqueeze(0), fixed)[0]
+
+    def initial_batch(self, Y, fixed):
+        """Network outputs (N, n_out) -> per slab [0, U_y, U_z, U_t], the
+        slabs' factors being contiguous (n_d x M) slices of one (N, n_d, M)
+        tensor per dim: one prolongation call per dim for the whole batch
+        (the N coarse factors side by side as N*M columns)."""
+        N, M = Y.shape[0], self.M
+        dims, off = [], 0
         for d, (c, s, size) in enumerate(zip(self.coarse, self.scale, self.sizes)):
-            Uc = (y[off: off + size].to(F64) / s).reshape(c.nc, self.M).contiguous()
+            Uc = (Y[:, off: off + size].to(F64) / s).reshape(N, c.nc, M).permute(1, 0, 2).reshape(c.nc, N * M)
             off += size
-            Uf = c.prolong(Uc)
+            Uf = c.prolong(Uc.contiguous()).reshape(c.ax.n, N, M).permute(1, 0, 2).contiguous()
             if fixed[d + 1]:
-                Uf[list(fixed[d + 1])] = 0.0
-            out.append(Uf)
-        n0 = self.axes[0].n
-        return [torch.zeros((n0, self.M), dtype=F64, device=y.device)] + out
+                Uf[:, torch.tensor(sorted(fixed[d + 1]), device=Y.device)] = 0.0
+            dims.append(Uf)
+        U0 = torch.zeros((N, self.axes[0].n, M), dtype=F64, device=Y.device)
+        return [[U0[b]] + [Ud[b] for Ud in dims] for b in range(N)]
 
     def features(self, case, V):
         f = torch.tensor(param_features(case), dtype=F64, device=self.coarse[0].keep[0].device)

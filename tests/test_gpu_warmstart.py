@@ -63,6 +63,12 @@ def test_trained_network_beats_plain_initialisation(env):
         p = chain.slab_problem(h, c, V)
         probs.append(p)
         U0.append(layout.initial(Y[j], [ax.fixed for ax in c.axes]))
+    # the batched prolongation gives every slab exactly its single-slab start
+    fixed0 = [ax.fixed for ax in data["cases"][te[0]].axes]
+    Ub = layout.initial_batch(Y, fixed0)
+    for j in range(len(te)):
+        for u, v in zip(Ub[j], layout.initial(Y[j], fixed0)):
+            assert u.is_contiguous() and torch.equal(u, v)
     warm = ws.sweep_history(h, probs, U0, sweeps)
     plain = hist[:, te]
     for s in range(sweeps):
