@@ -69,6 +69,10 @@ __global__ void kb_couple(const BProb* __restrict__ P, const CoupleArgs* __restr
   couple(blockIdx.x, CA[long(b) * D + d], P[b].C);
 }
 
+__global__ void kb_load_terms(const WeightArgs* __restrict__ WA, const int* __restrict__ act, int d, int D) {
+  load_terms(blockIdx.x, WA[long(act[blockIdx.y]) * D + d]);
+}
+
 __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* __restrict__ WA,
                                 const int* __restrict__ act, int d, int D) {
   const int b = act[blockIdx.y];
@@ -81,7 +85,7 @@ __global__ void kb_force(const BProb* __restrict__ P, const int* __restrict__ ac
   force(blockIdx.x, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
 }
 
-__global__ void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
+__global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
   const BProb& q = P[act[blockIdx.y]];
   if (int(blockIdx.x) * kResRows >= q.n[d]) return;
   residual_part(blockIdx.x, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
@@ -133,7 +137,7 @@ size_t gram_lds_allowed = 0, res_lds_allowed = 0;
 
 struct Sizes {
   int max_chunks = 1, max_ctiles = 1, max_splits = 1, max_gram = 1, max_lgram = 1, max_rblocks = 1;
-  int max_cpl = 1, max_wt = 1, max_rchunks = 1;
+  int max_cpl = 1, max_wt = 1, max_rchunks = 1, max_terms = 1;
 };
 
 }  // namespace
@@ -180,7 +184,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const size_t o_outs = bump.take(size_t(B) * (2 * D + 2) * 8);
   const size_t o_infos = bump.take(size_t(B) * D * 4);
   std::vector<BProb> bp(B);
-  std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B);
+  std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B), wt_doubles(B);
   for (int b = 0; b < B; ++b) {
     const taps_problem_t& p = probs[b];
     int Kmax = 1, nmax = 1, tot = 0;
@@ -193,6 +197,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       gp = std::max(gp, size_t(ch) * p.n_kinds[d] * MM * 8);
       lp = std::max(lp, size_t(sp) * p.R_cols[d] * M * 8);
       wt = std::max(wt, size_t(p.R_cols[d]) * M * 8);
+      Z.max_terms = std::max(Z.max_terms, cdiv(long(p.R) * M, 256));
       bp[b].roff[d] = tot;
       tot += cdiv(p.n[d], kResRows);
       Z.max_chunks = std::max(Z.max_chunks, ch);
@@ -208,7 +213,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     o_cache[b] = bump.take(cache_total(&p));
     o_C[b] = bump.take(size_t(Kmax) * MM * 8);
     o_Q[b] = bump.take(size_t(nmax) * M * 8);
-    o_Wt[b] = bump.take(wt);
+    o_Wt[b] = bump.take(wt + size_t(p.R) * M * 8);   // Wt, then the per-term products
+    wt_doubles[b] = wt / 8;
     o_gp[b] = bump.take(gp);
     o_lp[b] = bump.take(lp);
     o_rp[b] = bump.take(size_t(tot) * 2 * 8);
@@ -280,6 +286,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       }
       w.ptr = p.d_load_ptr[d];
       w.idx = p.d_load_idx[d];
+      w.P = q.Wt + wt_doubles[b];
       solve_args_fill(args.data() + (size_t(d) * B + b) * args_sz, &p, d, q.C, q.Q, q.U[d],
                       infos + size_t(b) * D + d, base + o_ws[b]);
     }
@@ -340,6 +347,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
     kb_couple<<<dim3(Z.max_cpl, nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_couple");
+    kb_load_terms<<<dim3(Z.max_terms, nact), 256, 0, st>>>(d_wa, d_active, d, D);
+    TAPS_LAUNCHED(h, "kb_load_terms");
     kb_load_weights<<<dim3(Z.max_wt, nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_weights");
     kb_force<<<dim3(Z.max_rblocks, nact), 256, 0, st>>>(d_prob, d_active, d);

@@ -25,6 +25,7 @@ __global__ void k_lgram_partial(int n, int Rc, int M, const double* __restrict__
 
 __global__ void k_couple(CoupleArgs A, double* __restrict__ C) { couple(blockIdx.x, A, C); }
 
+__global__ void k_load_terms(WeightArgs A) { load_terms(blockIdx.x, A); }
 __global__ void k_load_weights(WeightArgs A, double* __restrict__ Wt) { load_weights(blockIdx.x, A, Wt); }
 
 __global__ void k_force(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ Wt,
@@ -94,7 +95,7 @@ taps_status refresh_grams(taps_handle* h, const taps_problem_t* p, taps_gram_cac
     double* pl = reinterpret_cast<double*>(static_cast<char*>(h->ws) + align256(part_g));
     double* gram = gc->base + cache_gram_off(p, e) / 8;
     double* lgram = gc->base + cache_lgram_off(p, e) / 8;
-    const size_t lds = size_t(2 * kGramRows + 2 * w) * M * 8;
+    const size_t lds = size_t(gram_lds_doubles(M, p->s[e])) * 8;
     TAPS_TRY(allow_lds(h, k_gram_partial, lds, &gram_lds_allowed));
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, stream, &slot));
@@ -141,7 +142,7 @@ taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, const taps
   TAPS_LAUNCHED(h, "k_couple");
 
   const int Rc = p->R_cols[d];
-  TAPS_TRY(need_ws(h, size_t(Rc) * M * 8, stream));
+  TAPS_TRY(need_ws(h, size_t(Rc + p->R) * M * 8, stream));
   double* Wt = static_cast<double*>(h->ws);
   WeightArgs wa{};
   wa.D = p->D;
@@ -155,6 +156,9 @@ taps_status couple_and_force(taps_handle* h, const taps_problem_t* p, const taps
   }
   wa.ptr = p->d_load_ptr[d];
   wa.idx = p->d_load_idx[d];
+  wa.P = Wt + size_t(Rc) * M;
+  k_load_terms<<<cdiv(long(p->R) * M, 256), 256, 0, stream>>>(wa);
+  TAPS_LAUNCHED(h, "k_load_terms");
   k_load_weights<<<cdiv(long(Rc) * M, 256), 256, 0, stream>>>(wa, Wt);
   TAPS_LAUNCHED(h, "k_load_weights");
   k_force<<<cdiv(p->n[d], kQRows), 256, 0, stream>>>(p->n[d], Rc, M, p->d_F[d], Wt, d_Q);

@@ -12,52 +12,70 @@ namespace dev {
 constexpr int kGramRows = 64;   // rows of U per Gram partial block
 constexpr int kLgCols = 64;     // load columns per load-Gram block
 constexpr int kLgRows = 256;    // rows per load-Gram split
-constexpr int kLgStage = 32;    // rows staged in LDS at a time
 constexpr int kQRows = 64;      // rows of Q per force block
-constexpr int kQStage = 32;     // load columns staged in LDS at a time
 constexpr int kResRows = 64;    // rows per residual partial block
 
-inline int gram_lds_doubles(int M, int s) { return (2 * kGramRows + 2 * (2 * s + 1)) * M; }
-inline int residual_lds_doubles(int M, int s) {
-  const int hr = kResRows + 2 * (2 * s + 1);
-  return 2 * hr * M + M * M + kResRows * M;
+inline int gram_lds_doubles(int M, int s) { return (2 * kGramRows + 2 * (2 * s + 1)) * (M | 1); }
+
+// v_mfma_f64_16x16x4f64 operands of lane l: A[l%16][l/16], B[l/16][l%16];
+// result D[l/16 + 4j][l%16], j = 0..3.
+typedef double rv4d __attribute__((ext_vector_type(4)));
+__device__ inline rv4d mfma_f64(double a, double b, rv4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+inline int residual_lds_doubles(int M, int s) { return (kResRows + 2 * (2 * s + 1) + M) * (M | 1); }
 
 // Partial of G^k = U^T A^k U over rows [chunk*kGramRows, +kGramRows): the
-// chunk of U plus a halo of w rows goes to LDS, V = A^k U on the chunk rows,
-// then U_chunk^T V.  part: K x M x M for this chunk.
+// chunk of U plus a halo of w rows goes to LDS, V = A^k U on the chunk rows
+// (vector FMAs), then U_chunk^T V on the matrix cores, the rows of the chunk
+// being the contracted index (16 steps of 4); the 16 x 16 tiles of the M x M
+// result are dealt to the 4 waves.  part: K x M x M for this chunk.
 __device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const double* __restrict__ band,
                                     const double* __restrict__ U, double* __restrict__ part) {
   extern __shared__ double lds[];
-  const int w = 2 * s + 1, BW = 2 * w + 1;
+  const int w = 2 * s + 1, BW = 2 * w + 1, L = M | 1, MM = M * M;
   const int r0 = chunk * kGramRows;
   const int rows = min(kGramRows, n - r0);
-  double* sU = lds;                            // (kGramRows + 2w) x M
-  double* sV = lds + (kGramRows + 2 * w) * M;  // kGramRows x M
-  const int halo_rows = rows + 2 * w;
-  for (int t = threadIdx.x; t < halo_rows * M; t += blockDim.x) {
-    const int rr = t / M, m = t % M;
+  double* sU = lds;                            // (kGramRows + 2w) x L
+  double* sV = lds + (kGramRows + 2 * w) * L;  // kGramRows x L
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int halo_rows = kGramRows + 2 * w;
+  for (int t = tid; t < halo_rows * M; t += blockDim.x) {
+    const int rr = t / M, m = t - (t / M) * M;
     const int g = r0 - w + rr;
-    sU[rr * M + m] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
+    sU[rr * L + m] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
   }
-  __syncthreads();
+  const int nt = (M + 15) / 16;
   for (int k = 0; k < K; ++k) {
+    __syncthreads();
     const double* bk = band + long(k) * n * BW;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-      const int i = t / M, m = t % M;
-      const double* brow = bk + long(r0 + i) * BW;
+    for (int t = tid; t < kGramRows * M; t += blockDim.x) {
+      const int i = t / M, m = t - (t / M) * M;
       double v = 0.0;
-      for (int o = 0; o < BW; ++o) v += brow[o] * sU[(i + o) * M + m];
-      sV[i * M + m] = v;
+      if (i < rows) {
+        const double* brow = bk + long(r0 + i) * BW;
+        for (int o = 0; o < BW; ++o) v += brow[o] * sU[(i + o) * L + m];
+      }
+      sV[i * L + m] = v;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
-      const int m = t / M, nn = t % M;
-      double acc = 0.0;
-      for (int i = 0; i < rows; ++i) acc += sU[(i + w) * M + m] * sV[i * M + nn];
-      part[long(k) * M * M + t] = acc;
+    for (int tile = wv; tile < nt * nt; tile += 4) {
+      const int tr = tile / nt, tc = tile - (tile / nt) * nt;
+      const int ma = tr * 16 + (lane & 15), nb = tc * 16 + (lane & 15);
+      rv4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int kk = 0; kk < kGramRows / 4; ++kk) {
+        const int i = 4 * kk + (lane >> 4);
+        const double a = ma < M ? sU[(i + w) * L + ma] : 0.0;
+        const double b = nb < M ? sV[i * L + nb] : 0.0;
+        acc = mfma_f64(a, b, acc);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = tr * 16 + (lane >> 4) + 4 * j;
+        if (m < M && nb < M) part[long(k) * MM + m * M + nb] = acc[j];
+      }
     }
-    __syncthreads();
   }
 }
 
@@ -72,44 +90,45 @@ __device__ inline void sum_parts(int tblock, int nparts, long len, const double*
 }
 
 // Partial of L = F^T U for load columns [ctile*kLgCols, +kLgCols) over rows of
-// split `split`.  part layout: [split][Rc][M].
+// split `split`, on the matrix cores: wave v owns load columns
+// [16v, 16v+16) of the tile, the rows are the contracted index, and the
+// M columns of U are covered in passes of up to four 16-wide tiles.  Operands
+// are read from global memory (16 consecutive doubles per row and step).
+// part layout: [split][Rc][M].
 __device__ inline void lgram_partial(int ctile, int split, int n, int Rc, int M, const double* __restrict__ F,
                                      const double* __restrict__ U, double* __restrict__ part) {
-  __shared__ double sF[kLgStage][kLgCols + 1];
-  __shared__ double sU[kLgStage * TAPS_MAX_M];
-  const int c0 = ctile * kLgCols;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cw = ctile * kLgCols + wv * 16;
+  if (cw >= Rc) return;
   const int rbeg = split * kLgRows, rend = min(n, rbeg + kLgRows);
-  const int nout = kLgCols * M;
-  constexpr int kPer = (kLgCols * TAPS_MAX_M + 255) / 256;
-  double acc[kPer];
-  for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-  for (int i0 = rbeg; i0 < rend; i0 += kLgStage) {
-    const int rows = min(kLgStage, rend - i0);
-    for (int t = threadIdx.x; t < kLgStage * kLgCols; t += blockDim.x) {
-      const int r = t / kLgCols, c = t % kLgCols;
-      sF[r][c] = (r < rows && c0 + c < Rc) ? F[long(i0 + r) * Rc + c0 + c] : 0.0;
-    }
-    for (int t = threadIdx.x; t < kLgStage * M; t += blockDim.x) {
-      const int r = t / M;
-      sU[t] = (r < rows) ? U[long(i0) * M + t] : 0.0;
-    }
-    __syncthreads();
-    for (int q = 0; q < kPer; ++q) {
-      const int o = threadIdx.x + q * blockDim.x;
-      if (o < nout) {
-        const int c = o / M, m = o % M;
-        double a = acc[q];
-        for (int r = 0; r < rows; ++r) a += sF[r][c] * sU[r * M + m];
-        acc[q] = a;
+  const int ca = cw + (lane & 15);
+  const int nct = (M + 15) / 16;
+  for (int ct0 = 0; ct0 < nct; ct0 += 4) {
+    rv4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int i0 = rbeg; i0 < rend; i0 += 4) {
+      const int i = i0 + (lane >> 4);
+      const bool ok = i < rend;
+      const double a = (ok && ca < Rc) ? F[long(i) * Rc + ca] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (ct0 + c >= nct) break;
+        const int m = (ct0 + c) * 16 + (lane & 15);
+        const double b = (ok && m < M) ? U[long(i) * M + m] : 0.0;
+        acc[c] = mfma_f64(a, b, acc[c]);
       }
     }
-    __syncthreads();
-  }
-  for (int q = 0; q < kPer; ++q) {
-    const int o = threadIdx.x + q * blockDim.x;
-    if (o < nout) {
-      const int c = o / M, m = o % M;
-      if (c0 + c < Rc) part[(long(split) * Rc + c0 + c) * M + m] = acc[q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int m = (ct0 + c) * 16 + (lane & 15);
+      if (ct0 + c >= nct || m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int cc = cw + (lane >> 4) + 4 * j;
+        if (cc < Rc) part[(long(split) * Rc + cc) * M + m] = acc[c][j];
+      }
     }
   }
 }
@@ -147,136 +166,177 @@ struct WeightArgs {
   const int* col[TAPS_MAX_DIMS];       // R entries or null (identity)
   const int* ptr;                      // dim d grouping (null = identity)
   const int* idx;
+  double* P;                           // R x M per-term products (ptr order)
 };
 
-// Wt[c][m] = sum over load terms r with col_d(r) = c of prod_{e != d} L_e[col_e(r)][m].
+// Per-term products, one thread per (term, mode), terms in the grouping order
+// of dim d: P[q][m] = prod_{e != d} L_e[col_e(r)][m], r = idx[q].  Every
+// thread's loads depend only on its own term, so the whole table fills in a
+// few memory latencies.
+__device__ inline void load_terms(int tblock, const WeightArgs& A) {
+  const long t = tblock * long(blockDim.x) + threadIdx.x;
+  if (t >= long(A.R) * A.M) return;
+  const int q = int(t / A.M), m = int(t - (t / A.M) * A.M);
+  const int r = A.ptr ? A.idx[q] : q;
+  double prod = 1.0;
+  for (int e = 0; e < A.D; ++e) {
+    if (e == A.d) continue;
+    const int ce = A.col[e] ? A.col[e][r] : r;
+    prod *= A.lgram[e][long(ce) * A.M + m];
+  }
+  A.P[t] = prod;
+}
+
+// Wt[c][m] = sum of P[q][m] over the terms q of group c (ptr[c] .. ptr[c+1]),
+// in term order; independent contiguous loads.
 __device__ inline void load_weights(int tblock, const WeightArgs& A, double* __restrict__ Wt) {
   const long t = tblock * long(blockDim.x) + threadIdx.x;
   if (t >= long(A.Rc) * A.M) return;
-  const int c = int(t / A.M), m = int(t % A.M);
+  const int c = int(t / A.M), m = int(t - (t / A.M) * A.M);
   const int rb = A.ptr ? A.ptr[c] : c;
   const int re = A.ptr ? A.ptr[c + 1] : c + 1;
+  const double* P = A.P + m;
   double acc = 0.0;
-  for (int q = rb; q < re; ++q) {
-    const int r = A.ptr ? A.idx[q] : q;
-    double prod = 1.0;
-    for (int e = 0; e < A.D; ++e) {
-      if (e == A.d) continue;
-      const int ce = A.col[e] ? A.col[e][r] : r;
-      prod *= A.lgram[e][long(ce) * A.M + m];
-    }
-    acc += prod;
+  int q = rb;
+  for (; q + 4 <= re; q += 4) {
+    const double p0 = P[long(q) * A.M], p1 = P[long(q + 1) * A.M], p2 = P[long(q + 2) * A.M],
+                 p3 = P[long(q + 3) * A.M];
+    acc = (((acc + p0) + p1) + p2) + p3;
   }
+  for (; q < re; ++q) acc += P[long(q) * A.M];
   Wt[t] = acc;
 }
 
-// Q = F_d Wt for rows [rblock*kQRows, +kQRows), load columns staged in LDS.
+// Q = F_d Wt for rows [rblock*kQRows, +kQRows) on the matrix cores: wave v
+// owns rows [16v, 16v+16) of the block, the load columns are the contracted
+// index (steps of 4), and the M columns are covered in passes of up to four
+// 16-wide tiles.
 __device__ inline void force(int rblock, int n, int Rc, int M, const double* __restrict__ F,
                              const double* __restrict__ Wt, double* __restrict__ Q) {
-  __shared__ double sF[kQRows][kQStage + 1];
-  __shared__ double sW[kQStage * TAPS_MAX_M];
-  const int r0 = rblock * kQRows;
-  const int rows = min(kQRows, n - r0);
-  const int nout = kQRows * M;
-  constexpr int kPer = (kQRows * TAPS_MAX_M + 255) / 256;
-  double acc[kPer];
-  for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-  for (int c0 = 0; c0 < Rc; c0 += kQStage) {
-    const int cols = min(kQStage, Rc - c0);
-    for (int t = threadIdx.x; t < kQRows * kQStage; t += blockDim.x) {
-      const int r = t / kQStage, c = t % kQStage;
-      sF[r][c] = (r < rows && c < cols) ? F[long(r0 + r) * Rc + c0 + c] : 0.0;
-    }
-    for (int t = threadIdx.x; t < kQStage * M; t += blockDim.x) {
-      const int c = t / M;
-      sW[t] = (c < cols) ? Wt[long(c0) * M + t] : 0.0;
-    }
-    __syncthreads();
-    for (int q = 0; q < kPer; ++q) {
-      const int o = threadIdx.x + q * blockDim.x;
-      if (o < nout) {
-        const int r = o / M, m = o % M;
-        double a = acc[q];
-        for (int c = 0; c < cols; ++c) a += sF[r][c] * sW[c * M + m];
-        acc[q] = a;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rw = rblock * kQRows + wv * 16;
+  if (rw >= n) return;
+  const int ia = rw + (lane & 15);
+  const int nct = (M + 15) / 16;
+  for (int ct0 = 0; ct0 < nct; ct0 += 4) {
+    rv4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int c0 = 0; c0 < Rc; c0 += 4) {
+      const int kc = c0 + (lane >> 4);
+      const bool ok = kc < Rc;
+      const double a = (ok && ia < n) ? F[long(ia) * Rc + kc] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (ct0 + c >= nct) break;
+        const int m = (ct0 + c) * 16 + (lane & 15);
+        const double b = (ok && m < M) ? Wt[long(kc) * M + m] : 0.0;
+        acc[c] = mfma_f64(a, b, acc[c]);
       }
     }
-    __syncthreads();
-  }
-  for (int q = 0; q < kPer; ++q) {
-    const int o = threadIdx.x + q * blockDim.x;
-    if (o < nout) {
-      const int r = o / M, m = o % M;
-      if (r < rows) Q[long(r0 + r) * M + m] = acc[q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int m = (ct0 + c) * 16 + (lane & 15);
+      if (ct0 + c >= nct || m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = rw + (lane >> 4) + 4 * j;
+        if (i < n) Q[long(i) * M + m] = acc[c][j];
+      }
     }
   }
 }
 
-// Per chunk of kResRows rows: R = sum_k A^k U (C^k)^T - Q and the chunk's
-// sums of R^2 and Q^2 over free rows -> part[0], part[1].  V^k = U (C^k)^T is
-// formed on the chunk plus a halo of w rows in LDS.
+// Per chunk of kResRows rows: R = sum_k (A^k U) (C^k)^T - Q and the chunk's
+// sums of R^2 and Q^2 over free rows -> part[0], part[1].  256 threads: wave
+// v owns rows [16v, 16v+16) of the chunk.  The chunk of U with a halo of w
+// rows and C^k sit in LDS (odd row stride L); the banded product W^k = A^k U
+// is formed directly as the A operands of v_mfma_f64_16x16x4f64 (lane l:
+// row l%16, column 4kk + l/16) and multiplied by (C^k)^T on the matrix cores,
+// up to four 16-column tiles of R per pass.
 __device__ inline void residual_part(int chunk, int n, int M, int s, int K, const double* __restrict__ band,
                                      const double* __restrict__ C, const double* __restrict__ U,
                                      const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
                                      double* __restrict__ part) {
   extern __shared__ double lds[];
-  const int w = 2 * s + 1, BW = 2 * w + 1, MM = M * M;
+  constexpr int kMaxBW = 2 * (2 * TAPS_MAX_S + 1) + 1;
+  const int w = 2 * s + 1, BW = 2 * w + 1, L = M | 1;
   const int r0 = chunk * kResRows;
   const int rows = min(kResRows, n - r0);
-  const int hr = rows + 2 * w;
-  double* sU = lds;          // hr x M
-  double* sV = sU + hr * M;  // hr x M
-  double* sC = sV + hr * M;  // M x M
-  double* sR = sC + MM;      // rows x M
-  __shared__ double red[2][256];
-  for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
-    const int rr = t / M, m = t % M;
+  const int hr = kResRows + 2 * w;
+  double* sU = lds;            // hr x L (halo rows r0-w ..)
+  double* sC = sU + hr * L;    // M x L
+  __shared__ double red[4][2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int t = tid; t < hr * M; t += blockDim.x) {
+    const int rr = t / M, m = t - (t / M) * M;
     const int g = r0 - w + rr;
-    sU[t] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
+    sU[rr * L + m] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
   }
-  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) sR[t] = -Q[long(r0) * M + t];
-  __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    for (int t = threadIdx.x; t < MM; t += blockDim.x) sC[t] = C[long(k) * MM + t];
-    __syncthreads();
-    for (int t = threadIdx.x; t < hr * M; t += blockDim.x) {
-      const int rr = t / M, m = t % M;
-      double v = 0.0;
-      for (int q = 0; q < M; ++q) v += sU[rr * M + q] * sC[m * M + q];
-      sV[t] = v;
-    }
-    __syncthreads();
-    const double* bk = band + long(k) * n * BW;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-      const int i = t / M, m = t % M;
-      const double* brow = bk + long(r0 + i) * BW;
-      double v = 0.0;
-      for (int o = 0; o < BW; ++o) v += brow[o] * sV[(i + o) * M + m];
-      sR[t] += v;
-    }
-    __syncthreads();
-  }
+  const int i_a = wv * 16 + (lane & 15);    // chunk row of this lane's A operands
+  const int ksteps = (M + 3) / 4, nct = (M + 15) / 16;
   double rr2 = 0.0, qq2 = 0.0;
-  for (int t = threadIdx.x; t < rows * M; t += blockDim.x) {
-    const int i = t / M;
-    if (fixed && fixed[r0 + i]) continue;
-    const double q = Q[long(r0) * M + t];
-    rr2 += sR[t] * sR[t];
-    qq2 += q * q;
-  }
-  red[0][threadIdx.x] = rr2;
-  red[1][threadIdx.x] = qq2;
-  __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + st];
-      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+  for (int ct0 = 0; ct0 < nct; ct0 += 4) {
+    rv4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < K; ++k) {
+      __syncthreads();   // sU staged / sC free
+      for (int t = tid; t < M * M; t += blockDim.x) {
+        const int r = t / M, c = t - (t / M) * M;
+        sC[r * L + c] = C[long(k) * M * M + t];
+      }
+      double bc[kMaxBW];
+      const double* brow = band + (long(k) * n + r0 + i_a) * BW;
+#pragma unroll
+      for (int o = 0; o < kMaxBW; ++o) bc[o] = (o < BW && i_a < rows) ? brow[o] : 0.0;
+      __syncthreads();
+      for (int kk = 0; kk < ksteps; ++kk) {
+        const int q = 4 * kk + (lane >> 4);
+        double a = 0.0;
+        if (q < M) {
+#pragma unroll
+          for (int o = 0; o < kMaxBW; ++o)
+            if (o < BW) a += bc[o] * sU[(i_a + o) * L + q];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (ct0 + c >= nct) break;
+          const int m = (ct0 + c) * 16 + (lane & 15);
+          const double b = (m < M && q < M) ? sC[m * L + q] : 0.0;
+          acc[c] = mfma_f64(a, b, acc[c]);
+        }
+      }
     }
-    __syncthreads();
+    // R = acc - Q on this pass's tiles; lane holds rows l/16 + 4j, column l%16
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int m = (ct0 + c) * 16 + (lane & 15);
+      if (ct0 + c >= nct || m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = wv * 16 + (lane >> 4) + 4 * j;
+        if (i >= rows || (fixed && fixed[r0 + i])) continue;
+        const double qv = Q[long(r0 + i) * M + m];
+        const double r = acc[c][j] - qv;
+        rr2 += r * r;
+        qq2 += qv * qv;
+      }
+    }
   }
-  if (threadIdx.x == 0) {
-    part[0] = red[0][0];
-    part[1] = red[1][0];
+  for (int o = 32; o > 0; o >>= 1) {
+    rr2 += __shfl_xor(rr2, o);
+    qq2 += __shfl_xor(qq2, o);
+  }
+  if (lane == 0) {
+    red[wv][0] = rr2;
+    red[wv][1] = qq2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[0] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    part[1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
   }
 }
 

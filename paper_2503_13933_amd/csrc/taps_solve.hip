@@ -662,9 +662,9 @@ constexpr int kResRows = taps::dev::kResRows;
 
 
 // Per chunk of kResRows rows: R = sum_k A^k U (C^k)^T - Q on the chunk, and the
-// chunk's sums of R^2 and Q^2 over free rows -> part[2*block], part[2*block+1].
-// V^k = U (C^k)^T is formed on the chunk plus a halo of w rows in LDS.
-__global__ void k_residual_part(int n, int M, int s, int K, const double* __restrict__ band,
+// chunk's sums of R^2 and Q^2 over free rows -> part[2*block], part[2*block+1]
+// (matrix-core body shared with the batched driver).
+__global__ __launch_bounds__(256) void k_residual_part(int n, int M, int s, int K, const double* __restrict__ band,
                                 const double* __restrict__ C, const double* __restrict__ U,
                                 const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
                                 double* __restrict__ part) {
@@ -1379,9 +1379,7 @@ taps_status dim_residual_parts(taps_handle* h, const taps_problem_t* p, int d, c
                                const double* d_U, const double* d_Q, double* parts, int* nparts,
                                hipStream_t stream) {
   const int nb = cdiv(p->n[d], kResRows);
-  const int w = 2 * p->s[d] + 1;
-  const int hr = kResRows + 2 * w;
-  const size_t lds = size_t(2 * hr * p->M + p->M * p->M + kResRows * p->M) * 8;
+  const size_t lds = size_t(taps::dev::residual_lds_doubles(p->M, p->s[d])) * 8;
   if (lds > 160 * 1024 - 4096) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", lds);
   TAPS_TRY(allow_lds(h, k_residual_part, lds, &res_lds_allowed));
   k_residual_part<<<nb, 256, lds, stream>>>(p->n[d], p->M, p->s[d], p->n_kinds[d], p->d_band[d], d_C, d_U, d_Q,
