@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--M", type=int, default=40)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=3, help="plain sweep budget that sets the target residual")
-    ap.add_argument("--batch", type=int, default=256, help="slabs in flight, one workgroup each")
+    ap.add_argument("--batch", type=int, default=512, help="slabs in flight, one workgroup each")
     ap.add_argument("--slabs", type=int, default=1024, help="slabs solved per step")
     ap.add_argument("--train-chains", type=int, default=512)
     ap.add_argument("--train-steps", type=int, default=3000)

@@ -193,7 +193,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       const int ch = cdiv(p.n[d], kGramRows), ct = cdiv(p.R_cols[d], kLgCols), sp = cdiv(p.n[d], kLgRows);
       Kmax = std::max(Kmax, p.n_kinds[d]);
       nmax = std::max(nmax, p.n[d]);
-      ws = std::max(ws, solve_ws_bytes(p.n[d], M, p.s[d]));
+      ws = std::max(ws, solve_ws_bytes(p.n[d], M, p.s[d], use_fd[d]));
       gp = std::max(gp, size_t(ch) * p.n_kinds[d] * MM * 8);
       lp = std::max(lp, size_t(sp) * p.R_cols[d] * M * 8);
       wt = std::max(wt, size_t(p.R_cols[d]) * M * 8);
@@ -288,7 +288,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       w.idx = p.d_load_idx[d];
       w.P = q.Wt + wt_doubles[b];
       solve_args_fill(args.data() + (size_t(d) * B + b) * args_sz, &p, d, q.C, q.Q, q.U[d],
-                      infos + size_t(b) * D + d, base + o_ws[b]);
+                      infos + size_t(b) * D + d, base + o_ws[b], use_fd[d]);
     }
     bal[b] = BalanceArgs{};
     bal[b].D = D;

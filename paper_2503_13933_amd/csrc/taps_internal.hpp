@@ -171,9 +171,11 @@ taps_status dim_residual_parts(taps_handle* h, const taps_problem_t* p, int d, c
 
 // Batched dim solve: one workgroup per system (all systems share M and s).
 size_t solve_args_bytes();
-size_t solve_ws_bytes(int n, int M, int s);
+// Workspace of one batched dim solve (fd: fast diagonalisation, else block
+// LU) and its device argument record.
+size_t solve_ws_bytes(int n, int M, int s, bool fd);
 void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_C, const double* d_Q,
-                     double* d_X, int* d_info, void* ws);
+                     double* d_X, int* d_info, void* ws, bool fd);
 bool solve_batched_supported(int M, int s);
 // raises the kernel's LDS limit ahead of any launch (not allowed inside a capture)
 taps_status solve_batched_prepare(taps_handle* h, int M, int s);

@@ -736,10 +736,11 @@ constexpr int kFdMaxM = 48;
 
 // Workspace of one fast-diagonalisation solve (inside the first workspace
 // region): H2 = C1^{-T} P and H3 = P^{-1} (M x M complex), the eigenvalues
-// (M complex), the right-hand sides / solutions of the banded systems
-// (n x M complex, row-major) and their U rows (n x (w+1) x M complex).
+// (M complex), C1^{-1} (M x M), the right-hand sides / solutions of the
+// banded systems (n x M complex, row-major) and their U rows
+// (n x (w+1) x M complex).
 struct FdWs {
-  double *H2, *H3, *lam, *Y, *U;
+  double *H2, *H3, *lam, *C1inv, *Y, *U;
 };
 __device__ inline FdWs fd_ws(const SolveArgs& A) {
   const int M = A.M, MM = M * M;
@@ -747,7 +748,8 @@ __device__ inline FdWs fd_ws(const SolveArgs& A) {
   f.H2 = A.Zst;
   f.H3 = f.H2 + 2 * MM;
   f.lam = f.H3 + 2 * MM;
-  f.Y = f.lam + 2 * M;
+  f.C1inv = f.lam + 2 * M;
+  f.Y = f.C1inv + MM;
   f.U = f.Y + 2 * long(A.n) * M;
   return f;
 }
@@ -808,25 +810,33 @@ struct IjWalk {
 // (one 64-wide wave):
 //   C1^{-1} by Gauss-Jordan with partial pivoting,
 //   E = C2^T C1^{-T} (the system becomes A1 X + A2 X E = Q C1^{-T}),
-//   Householder reduction of E to Hessenberg form and complex single-shift
-//   QR to the Schur form E = Z T Z^H (Wilkinson shifts, an exceptional shift
-//   every 11 iterations, at most 40 M iterations),
+//   Householder reduction of E to Hessenberg form, Francis double-shift QR
+//   in real arithmetic to the real Schur form (at most 40 M iterations), and
+//   unitary 2 x 2 rotations of its complex-pair blocks to the complex Schur
+//   form E = Z T Z^H,
 //   eigenvectors Wv of T (unit upper triangular), so P = Z Wv,
 //   H2 = C1^{-T} P and H3 = P^{-1} = Wv^{-1} Z^H to the workspace, with the
 //   eigenvalues.
-// LDS: six M x L arrays (L = M rounded up to odd, so that column walks over
-// the lanes hit distinct banks), H and Z complex, four real.
+// LDS: six M x L real units (L = M rounded up to odd, so that column walks
+// over the lanes hit distinct banks), reused by phase:
+//   units 0-1: C2 (unit 0) | complex H (T, then Wv^{-1}, then Z Wv)
+//   units 2-3: real Hessenberg / Schur Hr, Zr | complex Wv | C1^{-1} (unit 2)
+//   units 4-5: Gauss-Jordan buffers | complex Z
+// so that two workgroups share a compute unit at M = 40; C1^{-1} waits in
+// the workspace between its two uses.
 // info word: 0, -1 (C1 singular) or -2 (no convergence).
 __device__ void fd_eig_body(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
-  cplx* H = reinterpret_cast<cplx*>(lds);          // M x L complex
-  cplx* Z = H + LL;                                 // M x L complex
-  double* S0 = reinterpret_cast<double*>(Z + LL);   // M x L real (2 buffers), later Wv (complex)
-  double* S1 = S0 + LL;
-  double* Ci = S1 + LL;                             // C1^{-1}
-  double* C2s = Ci + LL;                            // C2, later the Householder vector
-  cplx* Wv = reinterpret_cast<cplx*>(S0);           // M x L complex over S0 and S1
+  cplx* H = reinterpret_cast<cplx*>(lds);            // units 0-1
+  double* C2s = lds;                                  // unit 0
+  double* Hr = lds + 2 * LL;                          // unit 2
+  double* Zr = lds + 3 * LL;                          // unit 3
+  cplx* Wv = reinterpret_cast<cplx*>(lds + 2 * LL);   // units 2-3
+  double* S0 = lds + 4 * LL;                          // unit 4
+  double* S1 = lds + 5 * LL;                          // unit 5
+  cplx* Z = reinterpret_cast<cplx*>(S0);              // units 4-5
+  __shared__ double v[64];                            // Householder vector
   __shared__ int perm[64];
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
@@ -893,27 +903,26 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     }
     __syncthreads();
   }
+  const double* Ci = cur;   // C1^{-1}, kept for E and saved for H2
   {
     IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) Ci[w.i * L + w.j] = cur[w.i * L + w.j];
+    for (int t = lane; t < MM; t += 64, w.next(M)) f.C1inv[t] = Ci[w.i * L + w.j];
   }
-  __syncthreads();
-  // ---- E[i][j] = sum_q C2[q][i] C1inv[j][q] into H; Z = I
+  // ---- E[i][j] = sum_q C2[q][i] C1inv[j][q] into Hr; Zr = I
   {
     IjWalk w(lane, M);
     for (int t = lane; t < MM; t += 64, w.next(M)) {
       const int i = w.i, j = w.j;
       double e = 0.0;
       for (int q = 0; q < M; ++q) e += C2s[q * L + i] * Ci[j * L + q];
-      H[i * L + j] = cmk(e, 0.0);
-      Z[i * L + j] = cmk(i == j ? 1.0 : 0.0, 0.0);
+      Hr[i * L + j] = e;
+      Zr[i * L + j] = (i == j) ? 1.0 : 0.0;
     }
   }
   __syncthreads();
-  // ---- Householder Hessenberg form (real), Z accumulated
-  double* v = C2s;   // length M
+  // ---- Householder Hessenberg form, Zr accumulated
   for (int k = 0; k + 2 < M; ++k) {
-    const double x = (lane > k && lane < M) ? H[lane * L + k].r : 0.0;
+    const double x = (lane > k && lane < M) ? Hr[lane * L + k] : 0.0;
     double ss = x * x;
     for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
     const double x0 = __shfl(x, k + 1);
@@ -931,98 +940,238 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       double w0 = 0.0, w1 = 0.0;
       int i = k + 1;
       for (; i + 1 < M; i += 2) {
-        w0 += v[i] * H[i * L + lane].r;
-        w1 += v[i + 1] * H[(i + 1) * L + lane].r;
+        w0 += v[i] * Hr[i * L + lane];
+        w1 += v[i + 1] * Hr[(i + 1) * L + lane];
       }
-      if (i < M) w0 += v[i] * H[i * L + lane].r;
+      if (i < M) w0 += v[i] * Hr[i * L + lane];
       const double bw = beta * (w0 + w1);
-      for (i = k + 1; i < M; ++i) H[i * L + lane].r -= v[i] * bw;
+      for (i = k + 1; i < M; ++i) Hr[i * L + lane] -= v[i] * bw;
     }
     __syncthreads();
-    if (lane < M) {   // right: row lane, columns k+1.. (H and Z)
+    if (lane < M) {   // right: row lane, columns k+1.. (Hr and Zr)
       double u0 = 0.0, u1 = 0.0, z0 = 0.0, z1 = 0.0;
       int j = k + 1;
       for (; j + 1 < M; j += 2) {
-        u0 += H[lane * L + j].r * v[j];
-        z0 += Z[lane * L + j].r * v[j];
-        u1 += H[lane * L + j + 1].r * v[j + 1];
-        z1 += Z[lane * L + j + 1].r * v[j + 1];
+        u0 += Hr[lane * L + j] * v[j];
+        z0 += Zr[lane * L + j] * v[j];
+        u1 += Hr[lane * L + j + 1] * v[j + 1];
+        z1 += Zr[lane * L + j + 1] * v[j + 1];
       }
       if (j < M) {
-        u0 += H[lane * L + j].r * v[j];
-        z0 += Z[lane * L + j].r * v[j];
+        u0 += Hr[lane * L + j] * v[j];
+        z0 += Zr[lane * L + j] * v[j];
       }
       const double bu = beta * (u0 + u1), buz = beta * (z0 + z1);
-      for (int j = k + 1; j < M; ++j) {
-        H[lane * L + j].r -= bu * v[j];
-        Z[lane * L + j].r -= buz * v[j];
+      for (j = k + 1; j < M; ++j) {
+        Hr[lane * L + j] -= bu * v[j];
+        Zr[lane * L + j] -= buz * v[j];
       }
     }
     __syncthreads();
   }
-  // ---- complex single-shift QR
+  // ---- real Schur form by Francis double-shift QR (two shifts per sweep,
+  // the eigenvalues of the trailing 2 x 2 block, or an exceptional pair every
+  // 10 iterations on one eigenvalue); 3-element Householder reflectors chase
+  // the bulge, rows on the column lanes and columns (of Hr and Zr) on the row
+  // lanes.  A deflated 2 x 2 block with real eigenvalues is rotated to upper
+  // triangular form; one with complex eigenvalues stays.
+  // reflector (I - tau u u^T), u = (1, u1, u2), applied to rows k.. of Hr
+  // (columns c0..M-1) and to columns k.. of Hr (rows 0..r1) and of Zr
+  auto reflect = [&](int k, int len, double tau, double u1, double u2, int c0, int r1) {
+    if (lane >= c0 && lane < M) {
+      const double h0 = Hr[k * L + lane], h1 = Hr[(k + 1) * L + lane];
+      const double h2 = len == 3 ? Hr[(k + 2) * L + lane] : 0.0;
+      const double w = tau * (h0 + u1 * h1 + u2 * h2);
+      Hr[k * L + lane] = h0 - w;
+      Hr[(k + 1) * L + lane] = h1 - w * u1;
+      if (len == 3) Hr[(k + 2) * L + lane] = h2 - w * u2;
+    }
+    __syncthreads();
+    if (lane <= r1) {
+      const double h0 = Hr[lane * L + k], h1 = Hr[lane * L + k + 1];
+      const double h2 = len == 3 ? Hr[lane * L + k + 2] : 0.0;
+      const double w = tau * (h0 + u1 * h1 + u2 * h2);
+      Hr[lane * L + k] = h0 - w;
+      Hr[lane * L + k + 1] = h1 - w * u1;
+      if (len == 3) Hr[lane * L + k + 2] = h2 - w * u2;
+    }
+    if (lane < M) {
+      const double z0 = Zr[lane * L + k], z1 = Zr[lane * L + k + 1];
+      const double z2 = len == 3 ? Zr[lane * L + k + 2] : 0.0;
+      const double w = tau * (z0 + u1 * z1 + u2 * z2);
+      Zr[lane * L + k] = z0 - w;
+      Zr[lane * L + k + 1] = z1 - w * u1;
+      if (len == 3) Zr[lane * L + k + 2] = z2 - w * u2;
+    }
+    __syncthreads();
+  };
+  // Householder vector of (x, y, z): (I - tau u u^T)(x, y, z)^T = (beta, 0, 0)^T
+  auto house = [](double x, double y, double z, double& tau, double& u1, double& u2) {
+    const double nrm = sqrt(x * x + y * y + z * z);
+    if (y == 0.0 && z == 0.0) {
+      tau = 0.0;
+      u1 = u2 = 0.0;
+      return;
+    }
+    const double beta = x >= 0.0 ? -nrm : nrm;
+    tau = (beta - x) / beta;
+    const double sc = 1.0 / (x - beta);
+    u1 = y * sc;
+    u2 = z * sc;
+  };
   int hi = M - 1, it = 0, total = 0;
   const int limit = 40 * M;
-  while (hi > 0 && total < limit) {
+  while (hi >= 0 && total < limit) {
     // lo: the largest i <= hi whose subdiagonal entry is negligible (0 if none)
     bool neg = false;
     if (lane >= 1 && lane <= hi)
-      neg = cabs1(H[lane * L + lane - 1]) <=
-            2.220446049250313e-16 * (cabs1(H[lane * L + lane]) + cabs1(H[(lane - 1) * L + lane - 1]));
+      neg = fabs(Hr[lane * L + lane - 1]) <=
+            2.220446049250313e-16 * (fabs(Hr[lane * L + lane]) + fabs(Hr[(lane - 1) * L + lane - 1]));
     const unsigned long long bal = __ballot(neg);
     const int lo = bal ? 63 - __clzll(bal) : 0;
     __syncthreads();
-    if (lo > 0 && lane == 0) H[lo * L + lo - 1] = cmk(0.0, 0.0);
+    if (lo > 0 && lane == 0) Hr[lo * L + lo - 1] = 0.0;
     if (lo == hi) {
       --hi;
       it = 0;
       __syncthreads();
       continue;
     }
+    if (lo == hi - 1) {
+      // 2 x 2 block: rotate to triangular form when its eigenvalues are real
+      const double a = Hr[(hi - 1) * L + hi - 1], b = Hr[(hi - 1) * L + hi], c = Hr[hi * L + hi - 1],
+                   d = Hr[hi * L + hi];
+      const double p = 0.5 * (a - d), disc = p * p + b * c;
+      __syncthreads();
+      if (disc >= 0.0) {
+        const double sq = sqrt(disc);
+        const double lam = 0.5 * (a + d) + (p >= 0.0 ? sq : -sq);
+        double e0 = b, e1 = lam - a;   // eigenvector of lam, the better conditioned form
+        const double f0 = lam - d, f1 = c;
+        if (e0 * e0 + e1 * e1 < f0 * f0 + f1 * f1) {
+          e0 = f0;
+          e1 = f1;
+        }
+        const double en = sqrt(e0 * e0 + e1 * e1);
+        if (en > 0.0) {
+          const double cs = e0 / en, sn = e1 / en;   // G = [cs -sn; sn cs]: H <- G^T H G
+          const int k = hi - 1;
+          if (lane >= k && lane < M) {
+            const double h0 = Hr[k * L + lane], h1 = Hr[(k + 1) * L + lane];
+            Hr[k * L + lane] = cs * h0 + sn * h1;
+            Hr[(k + 1) * L + lane] = cs * h1 - sn * h0;
+          }
+          __syncthreads();
+          if (lane <= hi) {
+            const double h0 = Hr[lane * L + k], h1 = Hr[lane * L + k + 1];
+            Hr[lane * L + k] = cs * h0 + sn * h1;
+            Hr[lane * L + k + 1] = cs * h1 - sn * h0;
+          }
+          if (lane < M) {
+            const double z0 = Zr[lane * L + k], z1 = Zr[lane * L + k + 1];
+            Zr[lane * L + k] = cs * z0 + sn * z1;
+            Zr[lane * L + k + 1] = cs * z1 - sn * z0;
+          }
+          __syncthreads();
+          if (lane == 0) Hr[hi * L + hi - 1] = 0.0;
+        }
+      }
+      hi -= 2;
+      it = 0;
+      __syncthreads();
+      continue;
+    }
     ++it;
     ++total;
-    const cplx a = H[(hi - 1) * L + hi - 1], b = H[(hi - 1) * L + hi], c = H[hi * L + hi - 1], d = H[hi * L + hi];
-    const cplx tr = cadd(a, d), det = csub(cmul(a, d), cmul(b, c));
-    const cplx disc = csqrtz(csub(cscale(cmul(tr, tr), 0.25), det));
-    const cplx l1 = cadd(cscale(tr, 0.5), disc), l2 = csub(cscale(tr, 0.5), disc);
-    cplx mu = (cabs1(csub(l1, d)) < cabs1(csub(l2, d))) ? l1 : l2;
-    if (it % 11 == 0) mu = cadd(mu, cmk(cabs1(c), 0.0));   // exceptional shift
-    // bulge chase: rotation k zeroes the bulge below the subdiagonal; it acts
-    // on rows k, k+1 (lane = column) and then on columns k, k+1 of H and Z
-    // (lane = row)
-    cplx x = csub(H[lo * L + lo], mu), y = H[(lo + 1) * L + lo];
-    for (int k = lo; k < hi; ++k) {
+    double h11, h12, h21, h22;
+    if (it % 10 == 0) {   // exceptional shifts
+      const double sx = fabs(Hr[hi * L + hi - 1]) + fabs(Hr[(hi - 1) * L + hi - 2]);
+      h11 = 0.75 * sx + Hr[hi * L + hi];
+      h12 = -0.4375 * sx;
+      h21 = sx;
+      h22 = h11;
+    } else {
+      h11 = Hr[(hi - 1) * L + hi - 1];
+      h12 = Hr[(hi - 1) * L + hi];
+      h21 = Hr[hi * L + hi - 1];
+      h22 = Hr[hi * L + hi];
+    }
+    const double s = h11 + h22, t = h11 * h22 - h12 * h21;
+    const double a00 = Hr[lo * L + lo], a01 = Hr[lo * L + lo + 1], a10 = Hr[(lo + 1) * L + lo],
+                 a11 = Hr[(lo + 1) * L + lo + 1], a21 = Hr[(lo + 2) * L + lo + 1];
+    double x = a00 * a00 + a01 * a10 - s * a00 + t;
+    double y = a10 * (a00 + a11 - s);
+    double z = a10 * a21;
+    for (int k = lo; k + 1 < hi; ++k) {
       if (k > lo) {
-        x = H[k * L + k - 1];
-        y = H[(k + 1) * L + k - 1];
+        x = Hr[k * L + k - 1];
+        y = Hr[(k + 1) * L + k - 1];
+        z = (k + 2 <= hi) ? Hr[(k + 2) * L + k - 1] : 0.0;
       }
-      double cg;
-      cplx sg;
-      cgivens(x, y, cg, sg);
+      double tau, u1, u2;
+      house(x, y, z, tau, u1, u2);
       __syncthreads();
-      const int j0 = k > 0 ? k - 1 : 0;
-      if (lane >= j0 && lane < M) {   // rows k, k+1
-        const cplx hk = H[k * L + lane], hk1 = H[(k + 1) * L + lane];
-        H[k * L + lane] = cadd(cscale(hk, cg), cmul(sg, hk1));
-        H[(k + 1) * L + lane] = csub(cscale(hk1, cg), cmul(cconj(sg), hk));
-      }
+      if (tau != 0.0) reflect(k, 3, tau, u1, u2, max(lo, k - 1), min(k + 3, hi));
+    }
+    {
+      const int k = hi - 1;
+      x = Hr[k * L + k - 1];
+      y = Hr[(k + 1) * L + k - 1];
+      double tau, u1, u2;
+      house(x, y, 0.0, tau, u1, u2);
       __syncthreads();
-      const int i1 = min(k + 2, hi);
-      if (lane <= i1) {   // columns k, k+1 of H (times G^H)
-        const cplx hk = H[lane * L + k], hk1 = H[lane * L + k + 1];
-        H[lane * L + k] = cadd(cscale(hk, cg), cmul(cconj(sg), hk1));
-        H[lane * L + k + 1] = csub(cscale(hk1, cg), cmul(sg, hk));
-      }
-      if (lane < M) {
-        const cplx zk = Z[lane * L + k], zk1 = Z[lane * L + k + 1];
-        Z[lane * L + k] = cadd(cscale(zk, cg), cmul(cconj(sg), zk1));
-        Z[lane * L + k + 1] = csub(cscale(zk1, cg), cmul(sg, zk));
-      }
-      __syncthreads();
+      if (tau != 0.0) reflect(k, 2, tau, u1, 0.0, max(lo, k - 1), hi);
     }
   }
-  if (hi > 0 && lane == 0) s_fail = 2;
+  if (hi >= 0 && lane == 0) s_fail = 2;
   __syncthreads();
+  // ---- complex Schur form: H = Hr, Z = Zr, then each remaining 2 x 2 block
+  // (complex eigenvalue pair) is triangularised by a unitary rotation whose
+  // first column is the block's eigenvector for mu
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      H[w.i * L + w.j] = cmk(Hr[w.i * L + w.j], 0.0);
+      Z[w.i * L + w.j] = cmk(Zr[w.i * L + w.j], 0.0);
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < M; ++k) {
+    const cplx c = H[(k + 1) * L + k];
+    if (c.r == 0.0 && c.i == 0.0) continue;
+    const cplx a = H[k * L + k], b = H[k * L + k + 1], d = H[(k + 1) * L + k + 1];
+    const cplx tr = cadd(a, d), det = csub(cmul(a, d), cmul(b, c));
+    const cplx mu = cadd(cscale(tr, 0.5), csqrtz(csub(cscale(cmul(tr, tr), 0.25), det)));
+    cplx e0 = b, e1 = csub(mu, a);
+    const cplx f0 = csub(mu, d), f1 = c;
+    if (cabs1(e0) + cabs1(e1) < cabs1(f0) + cabs1(f1)) {
+      e0 = f0;
+      e1 = f1;
+    }
+    const double en = rsqrt(e0.r * e0.r + e0.i * e0.i + e1.r * e1.r + e1.i * e1.i);
+    const cplx g0 = cscale(e0, en), g1 = cscale(e1, en);   // G = [g0 -conj(g1); g1 conj(g0)]
+    __syncthreads();
+    if (lane >= k && lane < M) {   // rows k, k+1 <- G^H rows
+      const cplx h0 = H[k * L + lane], h1 = H[(k + 1) * L + lane];
+      H[k * L + lane] = cadd(cmul(cconj(g0), h0), cmul(cconj(g1), h1));
+      H[(k + 1) * L + lane] = csub(cmul(g0, h1), cmul(g1, h0));
+    }
+    __syncthreads();
+    if (lane <= k + 1) {           // columns k, k+1 <- columns G
+      const cplx h0 = H[lane * L + k], h1 = H[lane * L + k + 1];
+      H[lane * L + k] = cadd(cmul(h0, g0), cmul(h1, g1));
+      H[lane * L + k + 1] = csub(cmul(h1, cconj(g0)), cmul(h0, cconj(g1)));
+    }
+    if (lane < M) {
+      const cplx z0 = Z[lane * L + k], z1 = Z[lane * L + k + 1];
+      Z[lane * L + k] = cadd(cmul(z0, g0), cmul(z1, g1));
+      Z[lane * L + k + 1] = csub(cmul(z1, cconj(g0)), cmul(z0, cconj(g1)));
+    }
+    __syncthreads();
+    if (lane == 0) H[(k + 1) * L + k] = cmk(0.0, 0.0);
+    __syncthreads();
+    ++k;   // the next subdiagonal entry is zero
+  }
   // ---- eigenvectors Wv of T (unit upper triangular), one column per lane
   if (lane < M) {
     const int k = lane;
@@ -1076,12 +1225,18 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     }
   }
   __syncthreads();
+  double* Ci2 = lds + 2 * LL;   // C1^{-1} back from the workspace (Wv is dead)
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) Ci2[w.i * L + w.j] = f.C1inv[t];
+  }
+  __syncthreads();
   {
     IjWalk w(lane, M);
     for (int t = lane; t < MM; t += 64, w.next(M)) {
       const int q = w.i, m = w.j;
       cplx sacc = cmk(0.0, 0.0);
-      for (int j = 0; j < M; ++j) sacc = cadd(sacc, cscale(H[j * L + m], Ci[j * L + q]));
+      for (int j = 0; j < M; ++j) sacc = cadd(sacc, cscale(H[j * L + m], Ci2[j * L + q]));
       f.H2[2 * t] = sacc.r;
       f.H2[2 * t + 1] = sacc.i;
     }
@@ -1342,7 +1497,7 @@ __global__ __launch_bounds__(kFdThreads) void k_fd_solve(const SolveArgs* __rest
 __global__ __launch_bounds__(64) void k_fd_eig_one(SolveArgs A) { fd_eig_body(A); }
 __global__ __launch_bounds__(kFdThreads) void k_fd_solve_one(SolveArgs A) { fd_solve_body(A); }
 
-size_t fd_eig_lds(int M) { return size_t(8) * M * (M | 1) * 8; }
+size_t fd_eig_lds(int M) { return size_t(6) * M * (M | 1) * 8; }
 size_t fd_solve_lds(int M, int s) {
   const int w = 2 * s + 1;
   const size_t rows = size_t(M) * (w + 1) * (2 * w + 1);          // per-system row rings (any w)
@@ -1424,10 +1579,13 @@ size_t solve_lds_bytes(int M, int s) {
 // Doubles of the first workspace region: the block LU's stored factors, or
 // the fast diagonalisation's transforms, eigenvalues, C1^{-1}, complex
 // right-hand sides and banded U rows, whichever is larger.
+size_t fd_doubles(int n, int M, int s) {
+  return size_t(5) * M * M + 2 * size_t(M) + 2 * size_t(n) * M * (2 * s + 3);
+}
+
 size_t zst_doubles(int n, int M, int s) {
   const size_t w = 2 * s + 1, lu = size_t(n) * M * w * M;
-  const size_t fd = size_t(5) * M * M + 2 * size_t(M) + 2 * size_t(n) * M * (w + 2);
-  return std::max(lu, fd);
+  return std::max(lu, fd_doubles(n, M, s));
 }
 
 taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const double* d_C,
@@ -1498,7 +1656,8 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
 // ---- batched solve (used by the batched Algorithm-1 driver)
 size_t solve_args_bytes() { return sizeof(SolveArgs); }
 
-size_t solve_ws_bytes(int n, int M, int s) {
+size_t solve_ws_bytes(int n, int M, int s, bool fd) {
+  if (fd) return fd_doubles(n, M, s) * 8;
   const int w = 2 * s + 1;
   Bump bump;
   bump.take(zst_doubles(n, M, s) * 8);
@@ -1511,7 +1670,7 @@ size_t solve_ws_bytes(int n, int M, int s) {
 // Fill the device argument record of one system into host memory `dst`
 // (sizeof(SolveArgs) bytes); `ws` is the system's own solve workspace.
 void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_C, const double* d_Q,
-                     double* d_X, int* d_info, void* ws) {
+                     double* d_X, int* d_info, void* ws, bool fd) {
   const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
   Bump bump;
   const size_t o_Z = bump.take(zst_doubles(n, M, s) * 8);
@@ -1530,9 +1689,9 @@ void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_
   A.fixed = p->d_fixed[d];
   A.X = d_X;
   A.Zst = reinterpret_cast<double*>(base + o_Z);
-  A.Yst = reinterpret_cast<double*>(base + o_Y);
-  A.win = reinterpret_cast<double*>(base + o_W);
-  A.rhs = reinterpret_cast<double*>(base + o_R);
+  A.Yst = fd ? nullptr : reinterpret_cast<double*>(base + o_Y);   // the fast diagonalisation
+  A.win = fd ? nullptr : reinterpret_cast<double*>(base + o_W);   // uses the first region only
+  A.rhs = fd ? nullptr : reinterpret_cast<double*>(base + o_R);
   A.info = d_info;
   memcpy(dst, &A, sizeof(A));
 }
