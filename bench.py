@@ -160,20 +160,21 @@ def main():
 
     stats = torch.empty((N, args.nz, 4), dtype=torch.float64, device="cuda")
 
-    def reconstruct(U, b):
-        capi.taps_reconstruct(h, U[:3], M, stats[b], prec=capi.BF16, mode=capi.REDUCE, mode_w=U[3][-1],
-                              thr=1000.0)
+    def reconstruct(U, done):
+        # end-time fields of the slabs that left this round, in one call
+        capi.taps_reconstruct_batched(h, [U[b][:3] for b in done], M, [stats[b] for b in done], prec=capi.BF16,
+                                      mode=capi.REDUCE, mode_ws=[U[b][3][-1] for b in done], thr=1000.0)
 
     def step_warm():
         Y = net.forward(X_bench)
         U = layout.initial_batch(Y, fixed)
         return ws.solve_stream(h, probs, U, rho_star, cap, B, U_plain=U_plain, median_rho1=med1,
-                               on_done=lambda i: reconstruct(U[i], i))
+                               on_done_batch=lambda done: reconstruct(U, done))
 
     def step_random_batched():
         big = [t.clone() for t in U_plain_big]
         U = [[t[b] for t in big] for b in range(N)]
-        return ws.solve_stream(h, probs, U, rho_star, cap, B, on_done=lambda i: reconstruct(U[i], i))
+        return ws.solve_stream(h, probs, U, rho_star, cap, B, on_done_batch=lambda done: reconstruct(U, done))
 
     def timed(fn, label, prof=False):
         for w in range(args.warmup):
@@ -207,7 +208,7 @@ def main():
         torch.cuda.synchronize()
         tp = time.perf_counter()
         sw, rho, _ = capi.taps_als(h, probs[0].struct, U, rho_star, cap)
-        reconstruct(U, 0)
+        capi.taps_reconstruct(h, U[:3], M, stats[0], prec=capi.BF16, mode=capi.REDUCE, mode_w=U[3][-1], thr=1000.0)
         torch.cuda.synchronize()
         plain = {"value": 1.0 / (time.perf_counter() - tp), "sweeps": sw, "rho": rho}
         log(f"plain form: one slab {1.0 / plain['value']:.3f} s, {sw} sweeps")

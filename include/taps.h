@@ -357,6 +357,19 @@ taps_status taps_reconstruct(taps_handle_t h, const int32_t* n_pts, const double
                              int32_t M, const double* d_mode_w, taps_prec prec,
                              taps_recon_mode mode, void* d_out, double thr, hipStream_t stream);
 
+/* B fields of one grid shape in one call (the same kernels as
+ * taps_reconstruct, with a field index in the launch grid, so every field's
+ * output is bit-identical to its own taps_reconstruct call).  d_Phi: 3*B
+ * device pointers, field b's factors at d_Phi[3b .. 3b+2]; d_mode_w: B
+ * pointers (entries may be null) or null; d_out: B outputs, each laid out as
+ * for taps_reconstruct.  The pointer arrays are host arrays; FP32 and BF16
+ * upload per-field tables to the handle workspace (one host-to-device copy),
+ * FP64 runs the fields one after the other.  B <= 65535. */
+taps_status taps_reconstruct_batched(taps_handle_t h, int32_t B, const int32_t* n_pts,
+                                     const double* const* d_Phi, int32_t M, const double* const* d_mode_w,
+                                     taps_prec prec, taps_recon_mode mode, void* const* d_out, double thr,
+                                     hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Learned warm start.  A slab's converged factors are stored in a canonical
  * form before a network learns them, and the network's coarse factors are

@@ -25,7 +25,7 @@ FUNCTIONS = (
     "taps_create", "taps_destroy", "taps_last_error", "taps_reserve", "taps_workspace_bytes",
     "taps_gauss_points", "taps_shape1d", "taps_source1d", "taps_assemble1d", "taps_contract",
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
-    "taps_reconstruct", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
+    "taps_reconstruct", "taps_reconstruct_batched", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
     "taps_canonicalize", "taps_mlp_cache_bytes", "taps_mlp_forward", "taps_mlp_backward", "taps_mlp_mse",
     "taps_adam_step", "taps_set_tuning", "taps_get_tuning", "taps_autotune",
 )
@@ -93,6 +93,7 @@ def lib():
             "taps_als": (i32, [vp, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), P(dbl), vp]),
             "taps_interp1d": (i32, [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]),
             "taps_reconstruct": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
+            "taps_reconstruct_batched": (i32, [vp, i32, P(i32), P(vp), i32, P(vp), i32, i32, P(vp), dbl, vp]),
             "taps_profile_enable": (i32, [vp, i32]),
             "taps_als_batched": (i32, [vp, i32, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), vp]),
             "taps_profile_read": (i32, [vp, i32, P(i32), P(dbl), P(dbl), P(dbl)]),
@@ -326,6 +327,17 @@ def taps_reconstruct(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int =
     n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis])
     h.check(lib().taps_reconstruct(h.h, n, _ptr_array(Phis), M, _ptr(mode_w), prec, mode, _ptr(out), thr,
                                    _stream(stream)), "taps_reconstruct")
+
+
+def taps_reconstruct_batched(h: Handle, Phis, M: int, outs, prec: int = BF16, mode: int = REDUCE, mode_ws=None,
+                             thr: float = 0.0, stream=None):
+    """Phis: B lists of 3 factor tensors (one grid shape); outs: B outputs;
+    mode_ws: B weight tensors (entries may be None) or None."""
+    B = len(Phis)
+    n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis[0]])
+    mw = _ptr_array(mode_ws) if mode_ws is not None else None
+    h.check(lib().taps_reconstruct_batched(h.h, B, n, _ptr_array([P for F in Phis for P in F]), M, mw, prec, mode,
+                                           _ptr_array(outs), thr, _stream(stream)), "taps_reconstruct_batched")
 
 
 def taps_profile_enable(h: Handle, enable: bool):

@@ -129,8 +129,8 @@ __global__ void kb_residual_final(const BProb* __restrict__ P, const int* __rest
   q.outs[q.D + 1] = qs > 0.0 ? sqrt(rs / qs) : sqrt(rs);
 }
 
-__global__ void kb_balance(const BalanceArgs* __restrict__ BA, const int* __restrict__ act) {
-  balance(blockIdx.x, BA[act[blockIdx.y]]);
+__global__ __launch_bounds__(256) void kb_balance(const BalanceArgs* __restrict__ BA, const int* __restrict__ act) {
+  balance(BA[act[blockIdx.x]]);
 }
 
 size_t gram_lds_allowed = 0, res_lds_allowed = 0;
@@ -392,7 +392,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       kb_berr_final<<<cdiv(nact, 64), 64, 0, st>>>(d_prob, d_active, nact, d);
       TAPS_LAUNCHED(h, "kb_berr_final");
     }
-    kb_balance<<<dim3(M, nact), 256, 0, st>>>(d_bal, d_active);
+    kb_balance<<<nact, 256, 0, st>>>(d_bal, d_active);
     TAPS_LAUNCHED(h, "kb_balance");
     for (int e = 0; e < D; ++e) TAPS_TRY(refresh(e, nact, st));
     for (int d = 0; d < D; ++d) {

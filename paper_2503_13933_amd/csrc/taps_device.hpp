@@ -346,38 +346,43 @@ struct BalanceArgs {
   double* U[TAPS_MAX_DIMS];
 };
 
-// Mode m: column norms of every dim, geometric mean, rescale (skipped when a
-// norm is below 1e-300).  Block of 256 threads.
-__device__ inline void balance(int m, const BalanceArgs& A) {
-  __shared__ double red[256];
-  __shared__ double nrm[TAPS_MAX_DIMS];
+// Every mode m of one problem: column norms of every dim, their geometric
+// mean g, U_e[:, m] *= g / ||U_e[:, m]|| (skipped for a mode with a norm below
+// 1e-300).  Block of 256 threads as 4 row phases x 64 mode lanes, so each row
+// of a factor is read and written as one contiguous segment; the row phases
+// are summed in a fixed order.
+__device__ inline void balance(const BalanceArgs& A) {
+  __shared__ double part[4][64];
+  __shared__ double fac[TAPS_MAX_DIMS][64];
+  const int m = threadIdx.x & 63, ph = threadIdx.x >> 6, M = A.M;
   for (int e = 0; e < A.D; ++e) {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < A.n[e]; i += blockDim.x) {
-      const double v = A.U[e][long(i) * A.M + m];
-      acc += v * v;
-    }
-    red[threadIdx.x] = acc;
+    if (m < M)
+      for (int i = ph; i < A.n[e]; i += 4) {
+        const double v = A.U[e][long(i) * M + m];
+        acc += v * v;
+      }
+    part[ph][m] = acc;
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) nrm[e] = sqrt(red[0]);
+    if (ph == 0) fac[e][m] = sqrt(((part[0][m] + part[1][m]) + part[2][m]) + part[3][m]);
     __syncthreads();
   }
-  bool tiny = false;
-  double lg = 0.0;
-  for (int e = 0; e < A.D; ++e) {
-    tiny = tiny || !(nrm[e] >= 1e-300);
-    lg += log(nrm[e]);
+  if (ph == 0 && m < M) {
+    bool tiny = false;
+    double lg = 0.0;
+    for (int e = 0; e < A.D; ++e) {
+      tiny = tiny || !(fac[e][m] >= 1e-300);
+      lg += log(fac[e][m]);
+    }
+    const double g = exp(lg / A.D);
+    for (int e = 0; e < A.D; ++e) fac[e][m] = tiny ? 1.0 : g / fac[e][m];
   }
-  if (tiny) return;
-  const double g = exp(lg / A.D);
-  for (int e = 0; e < A.D; ++e) {
-    const double f = g / nrm[e];
-    for (int i = threadIdx.x; i < A.n[e]; i += blockDim.x) A.U[e][long(i) * A.M + m] *= f;
-  }
+  __syncthreads();
+  if (m < M)
+    for (int e = 0; e < A.D; ++e) {
+      const double f = fac[e][m];
+      for (int i = ph; i < A.n[e]; i += 4) A.U[e][long(i) * M + m] *= f;
+    }
 }
 
 }  // namespace dev

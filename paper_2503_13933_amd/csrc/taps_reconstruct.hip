@@ -11,6 +11,9 @@ namespace taps {
 taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double* const* d_Phi, int32_t M,
                              const double* d_mode_w, taps_prec prec, taps_recon_mode mode, void* d_out,
                              double thr, hipStream_t stream);
+taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts, const double* const* d_Phi,
+                                    int32_t M, const double* const* d_mode_w, taps_prec prec, taps_recon_mode mode,
+                                    void* const* d_out, double thr, hipStream_t stream);
 }
 
 namespace {
@@ -117,5 +120,30 @@ extern "C" taps_status taps_reconstruct(taps_handle_t h, const int32_t* n_pts, c
   TAPS_LAUNCHED(h, "k_recon_fp64");
   k_recon_plane<<<cdiv(n2, 64), 64, 0, stream>>>(int(grid.x * grid.y), n2, t, static_cast<double*>(d_out));
   TAPS_LAUNCHED(h, "k_recon_plane");
+  return TAPS_OK;
+}
+
+extern "C" taps_status taps_reconstruct_batched(taps_handle_t h, int32_t B, const int32_t* n_pts,
+                                                const double* const* d_Phi, int32_t M,
+                                                const double* const* d_mode_w, taps_prec prec,
+                                                taps_recon_mode mode, void* const* d_out, double thr,
+                                                hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (B < 1 || !n_pts || !d_Phi || !d_out) return fail(h, TAPS_ERR_INVALID, "bad batched reconstruction arguments");
+  if (M < 1 || M > TAPS_MAX_M) return fail(h, TAPS_ERR_UNSUPPORTED, "M=%d", M);
+  for (int d = 0; d < 3; ++d)
+    if (n_pts[d] < 1) return fail(h, TAPS_ERR_INVALID, "n_pts[%d]=%d", d, n_pts[d]);
+  for (int b = 0; b < B; ++b) {
+    if (!d_out[b]) return fail(h, TAPS_ERR_INVALID, "output %d is null", b);
+    for (int d = 0; d < 3; ++d)
+      if (!d_Phi[3 * b + d]) return fail(h, TAPS_ERR_INVALID, "field %d: Phi[%d] is null", b, d);
+  }
+  if (mode != TAPS_STORE && mode != TAPS_REDUCE) return fail(h, TAPS_ERR_INVALID, "mode %d", int(mode));
+  if (prec == TAPS_FP32 || prec == TAPS_BF16)
+    return reconstruct_mfma_fields(h, B, n_pts, d_Phi, M, d_mode_w, prec, mode, d_out, thr, stream);
+  if (prec != TAPS_FP64) return fail(h, TAPS_ERR_INVALID, "precision %d", int(prec));
+  for (int b = 0; b < B; ++b)   // FP64: one field after the other
+    TAPS_TRY(taps_reconstruct(h, n_pts, d_Phi + 3 * b, M, d_mode_w ? d_mode_w[b] : nullptr, prec, mode, d_out[b],
+                              thr, stream));
   return TAPS_OK;
 }

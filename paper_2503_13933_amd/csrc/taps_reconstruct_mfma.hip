@@ -29,6 +29,7 @@
 #include "taps_internal.hpp"
 
 #include <cmath>
+#include <vector>
 
 namespace {
 
@@ -45,9 +46,33 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, long bytes)
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
 }
 
+// Per-field operands of a batched call (row blockIdx.y of a device table);
+// a single call passes its pointers directly and a null table.
+struct ConvJob {
+  const double* P;
+  void* out;
+};
+struct ReconJob {
+  const float* P0f;
+  const void* P1;
+  const double* P2;
+  const double* mw;
+  float* out;
+  double* rec;
+};
+struct PlaneJob {
+  const double* rec;
+  double* out;
+};
+
 // FP64 factor (n x M) -> T (n x Mp), zero-padded columns (conversion through FP32).
 template <typename T>
-__global__ void k_recon_convert(int n, int M, int Mp, const double* __restrict__ P, T* __restrict__ out) {
+__global__ void k_recon_convert(int n, int M, int Mp, const double* __restrict__ P, T* __restrict__ out,
+                                const ConvJob* __restrict__ tab) {
+  if (tab) {
+    P = tab[blockIdx.y].P;
+    out = static_cast<T*>(tab[blockIdx.y].out);
+  }
   const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= long(n) * Mp) return;
   const int i = int(idx / Mp), m = int(idx - long(i) * Mp);
@@ -150,7 +175,16 @@ template <int KS, int MODE>
 __global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int nrb, int M, const float* __restrict__ P0f,
                                                             const __bf16* __restrict__ P1b, const double* __restrict__ P2,
                                                             const double* __restrict__ mw, float thrf, float* __restrict__ out,
-                                                            double* __restrict__ rec) {
+                                                            double* __restrict__ rec, const ReconJob* __restrict__ tab) {
+  if (tab) {
+    const ReconJob& J = tab[blockIdx.y];
+    P0f = J.P0f;
+    P1b = static_cast<const __bf16*>(J.P1);
+    P2 = J.P2;
+    mw = J.mw;
+    out = J.out;
+    rec = J.rec;
+  }
   constexpr int Mp = 32 * KS;
   __shared__ __align__(16) float s[Mp];
   const int k = blockIdx.x / nrb, rb = blockIdx.x - k * nrb;
@@ -238,7 +272,16 @@ template <int S, int MODE>
 __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int nrb, int M, const float* __restrict__ P0f,
                                                             const float* __restrict__ P1f, const double* __restrict__ P2,
                                                             const double* __restrict__ mw, float thrf, float* __restrict__ out,
-                                                            double* __restrict__ rec) {
+                                                            double* __restrict__ rec, const ReconJob* __restrict__ tab) {
+  if (tab) {
+    const ReconJob& J = tab[blockIdx.y];
+    P0f = J.P0f;
+    P1f = static_cast<const float*>(J.P1);
+    P2 = J.P2;
+    mw = J.mw;
+    out = J.out;
+    rec = J.rec;
+  }
   constexpr int Mp = 4 * S;
   __shared__ __align__(16) float s[Mp];
   const int k = blockIdx.x / nrb, rb = blockIdx.x - k * nrb;
@@ -305,7 +348,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int 
 }
 
 // Per-plane combination of the workgroup records (fixed order).
-__global__ void k_recon_plane_mfma(int nrb, int n2, const double* __restrict__ rec, double* __restrict__ out) {
+__global__ void k_recon_plane_mfma(int nrb, int n2, const double* __restrict__ rec, double* __restrict__ out,
+                                   const PlaneJob* __restrict__ tab) {
+  if (tab) {
+    rec = tab[blockIdx.y].rec;
+    out = tab[blockIdx.y].out;
+  }
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n2) return;
   double mx = -INFINITY, ss = 0.0, cnt = 0.0;
@@ -322,19 +370,19 @@ __global__ void k_recon_plane_mfma(int nrb, int n2, const double* __restrict__ r
 }
 
 typedef void (*recon_fn)(dim3, hipStream_t, int, int, int, int, const float*, const void*, const double*,
-                         const double*, float, float*, double*);
+                         const double*, float, float*, double*, const ReconJob*);
 
 template <int KS, int MODE>
 void launch_bf16(dim3 grid, hipStream_t st, int n0, int n1, int nrb, int M, const float* P0f, const void* P1,
-                 const double* P2, const double* mw, float thr, float* out, double* rec) {
+                 const double* P2, const double* mw, float thr, float* out, double* rec, const ReconJob* tab) {
   k_recon_bf16<KS, MODE><<<grid, kWaves * 64, 0, st>>>(n0, n1, nrb, M, P0f, static_cast<const __bf16*>(P1), P2, mw,
-                                                      thr, out, rec);
+                                                      thr, out, rec, tab);
 }
 template <int S, int MODE>
 void launch_fp32(dim3 grid, hipStream_t st, int n0, int n1, int nrb, int M, const float* P0f, const void* P1,
-                 const double* P2, const double* mw, float thr, float* out, double* rec) {
+                 const double* P2, const double* mw, float thr, float* out, double* rec, const ReconJob* tab) {
   k_recon_fp32<S, MODE><<<grid, kWaves * 64, 0, st>>>(n0, n1, nrb, M, P0f, static_cast<const float*>(P1), P2, mw,
-                                                     thr, out, rec);
+                                                     thr, out, rec, tab);
 }
 
 }  // namespace
@@ -346,9 +394,13 @@ namespace taps {
 // (STORE) + factors read once.
 double recon_flops(int n0, int n1, int n2, int Mp) { return 2.0 * n0 * double(n1) * n2 * Mp; }
 
-taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double* const* d_Phi, int32_t M,
-                             const double* d_mode_w, taps_prec prec, taps_recon_mode mode, void* d_out, double thr,
-                             hipStream_t stream) {
+// B fields of one shape: d_Phi holds 3 factor pointers per field, d_mode_w
+// one pointer per field (or is null), d_out one output per field.  B = 1
+// passes the pointers to the kernels directly; B > 1 uploads per-field tables
+// (grid.y = field) into the workspace behind the staged factors.
+taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts, const double* const* d_Phi,
+                                    int32_t M, const double* const* d_mode_w, taps_prec prec, taps_recon_mode mode,
+                                    void* const* d_out, double thr, hipStream_t stream) {
   const int n0 = n_pts[0], n1 = n_pts[1], n2 = n_pts[2];
   const bool bf = (prec == TAPS_BF16);
   const int Mp = bf ? 32 * cdiv(M, 32) : 16 * cdiv(M, 16);
@@ -356,28 +408,58 @@ taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double*
     return fail(h, TAPS_ERR_UNSUPPORTED, "plane %d x %d too large for 32-bit offsets", n0, n1);
   const int nrb = cdiv(n0, kRowsWG);
   if (long(nrb) * n2 >= (1L << 31)) return fail(h, TAPS_ERR_UNSUPPORTED, "grid too large");
+  if (B > 65535) return fail(h, TAPS_ERR_UNSUPPORTED, "%d fields in one call (max 65535)", B);
+  const bool st = (mode == TAPS_STORE);
   Bump bump;
-  const size_t o_P0 = bump.take(size_t(n0) * Mp * 4);
-  const size_t o_P1 = bump.take(size_t(n1) * Mp * (bf ? 2 : 4));
-  const size_t o_R = bump.take(mode == TAPS_REDUCE ? size_t(n2) * nrb * 4 * 8 : 0);
+  const size_t s_P0 = size_t(n0) * Mp * 4, s_P1 = size_t(n1) * Mp * (bf ? 2 : 4);
+  const size_t s_R = st ? 0 : size_t(n2) * nrb * 4 * 8;
+  std::vector<size_t> o_P0(B), o_P1(B), o_R(B);
+  for (int b = 0; b < B; ++b) {
+    o_P0[b] = bump.take(s_P0);
+    o_P1[b] = bump.take(s_P1);
+    o_R[b] = bump.take(s_R);
+  }
+  const size_t o_tab = bump.take(B > 1 ? size_t(B) * (2 * sizeof(ConvJob) + sizeof(ReconJob) + sizeof(PlaneJob)) : 0);
   TAPS_TRY(need_ws(h, bump.off, stream));
   char* ws = static_cast<char*>(h->ws);
-  float* P0f = reinterpret_cast<float*>(ws + o_P0);
-  void* P1 = ws + o_P1;
-  double* rec = reinterpret_cast<double*>(ws + o_R);
-  k_recon_convert<float><<<cdiv(long(n0) * Mp, 256), 256, 0, stream>>>(n0, M, Mp, d_Phi[0], P0f);
+  auto P0f = [&](int b) { return reinterpret_cast<float*>(ws + o_P0[b]); };
+  auto P1 = [&](int b) { return static_cast<void*>(ws + o_P1[b]); };
+  auto rec = [&](int b) { return reinterpret_cast<double*>(ws + o_R[b]); };
+  const ConvJob* t_c0 = nullptr;
+  const ConvJob* t_c1 = nullptr;
+  const ReconJob* t_r = nullptr;
+  const PlaneJob* t_p = nullptr;
+  if (B > 1) {
+    std::vector<char> tab(size_t(B) * (2 * sizeof(ConvJob) + sizeof(ReconJob) + sizeof(PlaneJob)));
+    ConvJob* c0 = reinterpret_cast<ConvJob*>(tab.data());
+    ConvJob* c1 = c0 + B;
+    ReconJob* rj = reinterpret_cast<ReconJob*>(c1 + B);
+    PlaneJob* pj = reinterpret_cast<PlaneJob*>(rj + B);
+    for (int b = 0; b < B; ++b) {
+      c0[b] = ConvJob{d_Phi[3 * b], P0f(b)};
+      c1[b] = ConvJob{d_Phi[3 * b + 1], P1(b)};
+      rj[b] = ReconJob{P0f(b), P1(b), d_Phi[3 * b + 2], d_mode_w ? d_mode_w[b] : nullptr,
+                       st ? static_cast<float*>(d_out[b]) : nullptr, rec(b)};
+      pj[b] = PlaneJob{rec(b), static_cast<double*>(d_out[b])};
+    }
+    // pageable source: the runtime stages it before returning
+    TAPS_HIP(h, hipMemcpyAsync(ws + o_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, stream));
+    t_c0 = reinterpret_cast<const ConvJob*>(ws + o_tab);
+    t_c1 = t_c0 + B;
+    t_r = reinterpret_cast<const ReconJob*>(t_c1 + B);
+    t_p = reinterpret_cast<const PlaneJob*>(t_r + B);
+  }
+  const dim3 g0(cdiv(long(n0) * Mp, 256), B), g1(cdiv(long(n1) * Mp, 256), B);
+  k_recon_convert<float><<<g0, 256, 0, stream>>>(n0, M, Mp, d_Phi[0], P0f(0), t_c0);
   TAPS_LAUNCHED(h, "k_recon_convert");
   if (bf)
-    k_recon_convert<__bf16><<<cdiv(long(n1) * Mp, 256), 256, 0, stream>>>(n1, M, Mp, d_Phi[1],
-                                                                          static_cast<__bf16*>(P1));
+    k_recon_convert<__bf16><<<g1, 256, 0, stream>>>(n1, M, Mp, d_Phi[1], static_cast<__bf16*>(P1(0)), t_c1);
   else
-    k_recon_convert<float><<<cdiv(long(n1) * Mp, 256), 256, 0, stream>>>(n1, M, Mp, d_Phi[1],
-                                                                         static_cast<float*>(P1));
+    k_recon_convert<float><<<g1, 256, 0, stream>>>(n1, M, Mp, d_Phi[1], static_cast<float*>(P1(0)), t_c1);
   TAPS_LAUNCHED(h, "k_recon_convert");
-  const dim3 grid(unsigned(long(nrb) * n2));
-  float* out = mode == TAPS_STORE ? static_cast<float*>(d_out) : nullptr;
+  const dim3 grid(unsigned(long(nrb) * n2), B);
+  float* out0 = st ? static_cast<float*>(d_out[0]) : nullptr;
   recon_fn fn = nullptr;
-  const bool st = (mode == TAPS_STORE);
   if (bf) {
     if (Mp == 32) fn = st ? launch_bf16<1, TAPS_STORE> : launch_bf16<1, TAPS_REDUCE>;
     else fn = st ? launch_bf16<2, TAPS_STORE> : launch_bf16<2, TAPS_REDUCE>;
@@ -394,15 +476,25 @@ taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double*
   // largest float <= thr (for u > thr decided in FP32 exactly as in FP64)
   float thrf = float(thr);
   if (double(thrf) > thr) thrf = std::nextafter(thrf, -INFINITY);
-  fn(grid, stream, n0, n1, nrb, M, P0f, P1, d_Phi[2], d_mode_w, thrf, out, rec);
+  fn(grid, stream, n0, n1, nrb, M, P0f(0), P1(0), d_Phi[2], d_mode_w ? d_mode_w[0] : nullptr, thrf, out0, rec(0),
+     t_r);
   TAPS_LAUNCHED(h, bf ? "k_recon_bf16" : "k_recon_fp32");
-  TAPS_TRY(prof_end(h, slot, recon_flops(n0, n1, n2, Mp),
-                    (st ? 4.0 * n0 * double(n1) * n2 : 0.0) + 4.0 * (double(n0) + n1) * Mp, stream));
-  if (mode == TAPS_REDUCE) {
-    k_recon_plane_mfma<<<cdiv(n2, 64), 64, 0, stream>>>(nrb, n2, rec, static_cast<double*>(d_out));
+  TAPS_TRY(prof_end(h, slot, B * recon_flops(n0, n1, n2, Mp),
+                    B * ((st ? 4.0 * n0 * double(n1) * n2 : 0.0) + 4.0 * (double(n0) + n1) * Mp), stream));
+  if (!st) {
+    k_recon_plane_mfma<<<dim3(cdiv(n2, 64), B), 64, 0, stream>>>(nrb, n2, rec(0), static_cast<double*>(d_out[0]),
+                                                               t_p);
     TAPS_LAUNCHED(h, "k_recon_plane_mfma");
   }
   return TAPS_OK;
+}
+
+taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double* const* d_Phi, int32_t M,
+                             const double* d_mode_w, taps_prec prec, taps_recon_mode mode, void* d_out, double thr,
+                             hipStream_t stream) {
+  const double* const mw[1] = {d_mode_w};
+  void* const out[1] = {d_out};
+  return reconstruct_mfma_fields(h, 1, n_pts, d_Phi, M, d_mode_w ? mw : nullptr, prec, mode, out, thr, stream);
 }
 
 }  // namespace taps

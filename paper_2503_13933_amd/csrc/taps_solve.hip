@@ -876,17 +876,30 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       cur[p * L + lane] = t;
     }
     __syncthreads();
-    if (lane < M) {   // column lane of the next iterate
+    if (lane < M) {   // column lane of the next iterate, rows in batches of 8
       const int j = lane;
       const double ip = 1.0 / cur[r * L + r];
       const double arj = cur[r * L + j] * ip;
-#pragma unroll 4
-      for (int i = 0; i < M; ++i) {
-        const double aij = cur[i * L + j], air = cur[i * L + r];
-        double v = aij - air * arj;
-        v = (j == r) ? -air * ip : v;
-        v = (i == r) ? ((j == r) ? ip : arj) : v;
-        nxt[i * L + j] = v;
+      // new entry = alpha a_ij + beta a_ir off the pivot row, rowv on it
+      // (column r: -a_ir / p and 1 / p; other columns: a_ij - a_ir a_rj / p
+      // and a_rj / p), with per-lane coefficients so the loop has no branches
+      const double alpha = (j == r) ? 0.0 : 1.0;
+      const double beta = (j == r) ? -ip : -arj;
+      const double rowv = (j == r) ? ip : arj;
+      for (int i0 = 0; i0 < M; i0 += 8) {
+        double aa[8], ar[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {   // clamped rows: every load in bounds, issued together
+          const int i = min(i0 + u, M - 1);
+          aa[u] = cur[i * L + j];
+          ar[u] = cur[i * L + r];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          const double v = (i == r) ? rowv : fma(beta, ar[u], alpha * aa[u]);
+          if (i < M) nxt[i * L + j] = v;
+        }
       }
     }
     __syncthreads();
@@ -914,6 +927,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     for (int t = lane; t < MM; t += 64, w.next(M)) {
       const int i = w.i, j = w.j;
       double e = 0.0;
+#pragma unroll 8
       for (int q = 0; q < M; ++q) e += C2s[q * L + i] * Ci[j * L + q];
       Hr[i * L + j] = e;
       Zr[i * L + j] = (i == j) ? 1.0 : 0.0;
@@ -936,35 +950,62 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     const double beta = 2.0 / vv;
     if (lane < M) v[lane] = vi;
     __syncthreads();
-    if (lane < M) {   // left: column lane, rows k+1..
-      double w0 = 0.0, w1 = 0.0;
-      int i = k + 1;
-      for (; i + 1 < M; i += 2) {
-        w0 += v[i] * Hr[i * L + lane];
-        w1 += v[i + 1] * Hr[(i + 1) * L + lane];
+    if (lane < M) {   // left: column lane, rows k+1.. in batches of 8 (clamped rows weigh 0)
+      double wsum = 0.0;
+      for (int i0 = k + 1; i0 < M; i0 += 8) {
+        double hv[8], vv8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = min(i0 + u, M - 1);
+          hv[u] = Hr[i * L + lane];
+          vv8[u] = (i0 + u < M) ? v[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wsum += vv8[u] * hv[u];
       }
-      if (i < M) w0 += v[i] * Hr[i * L + lane];
-      const double bw = beta * (w0 + w1);
-      for (i = k + 1; i < M; ++i) Hr[i * L + lane] -= v[i] * bw;
+      const double bw = beta * wsum;
+      for (int i0 = k + 1; i0 < M; i0 += 8) {
+        double hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = Hr[min(i0 + u, M - 1) * L + lane];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (i0 + u < M) Hr[(i0 + u) * L + lane] = hv[u] - v[i0 + u] * bw;
+      }
     }
     __syncthreads();
-    if (lane < M) {   // right: row lane, columns k+1.. (Hr and Zr)
-      double u0 = 0.0, u1 = 0.0, z0 = 0.0, z1 = 0.0;
-      int j = k + 1;
-      for (; j + 1 < M; j += 2) {
-        u0 += Hr[lane * L + j] * v[j];
-        z0 += Zr[lane * L + j] * v[j];
-        u1 += Hr[lane * L + j + 1] * v[j + 1];
-        z1 += Zr[lane * L + j + 1] * v[j + 1];
+    if (lane < M) {   // right: row lane, columns k+1.. (Hr and Zr) in batches of 8
+      double us = 0.0, zs = 0.0;
+      for (int j0 = k + 1; j0 < M; j0 += 8) {
+        double hv[8], zv[8], vv8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = min(j0 + u, M - 1);
+          hv[u] = Hr[lane * L + j];
+          zv[u] = Zr[lane * L + j];
+          vv8[u] = (j0 + u < M) ? v[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          us += hv[u] * vv8[u];
+          zs += zv[u] * vv8[u];
+        }
       }
-      if (j < M) {
-        u0 += Hr[lane * L + j] * v[j];
-        z0 += Zr[lane * L + j] * v[j];
-      }
-      const double bu = beta * (u0 + u1), buz = beta * (z0 + z1);
-      for (j = k + 1; j < M; ++j) {
-        Hr[lane * L + j] -= bu * v[j];
-        Zr[lane * L + j] -= buz * v[j];
+      const double bu = beta * us, buz = beta * zs;
+      for (int j0 = k + 1; j0 < M; j0 += 8) {
+        double hv[8], zv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = min(j0 + u, M - 1);
+          hv[u] = Hr[lane * L + j];
+          zv[u] = Zr[lane * L + j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < M) {
+            Hr[lane * L + j0 + u] = hv[u] - bu * v[j0 + u];
+            Zr[lane * L + j0 + u] = zv[u] - buz * v[j0 + u];
+          }
       }
     }
     __syncthreads();
@@ -976,8 +1017,9 @@ __device__ void fd_eig_body(const SolveArgs& A) {
   // lanes.  A deflated 2 x 2 block with real eigenvalues is rotated to upper
   // triangular form; one with complex eigenvalues stays.
   // reflector (I - tau u u^T), u = (1, u1, u2), applied to rows k.. of Hr
-  // (columns c0..M-1) and to columns k.. of Hr (rows 0..r1) and of Zr
-  auto reflect = [&](int k, int len, double tau, double u1, double u2, int c0, int r1) {
+  // (columns c0..M-1) and to columns k.. of Hr (rows 0..r1) and of Zr;
+  // returns this lane's new Hr[lane][k] (rows <= r1)
+  auto reflect = [&](int k, int len, double tau, double u1, double u2, int c0, int r1) -> double {
     if (lane >= c0 && lane < M) {
       const double h0 = Hr[k * L + lane], h1 = Hr[(k + 1) * L + lane];
       const double h2 = len == 3 ? Hr[(k + 2) * L + lane] : 0.0;
@@ -987,11 +1029,13 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       if (len == 3) Hr[(k + 2) * L + lane] = h2 - w * u2;
     }
     __syncthreads();
+    double col = 0.0;
     if (lane <= r1) {
       const double h0 = Hr[lane * L + k], h1 = Hr[lane * L + k + 1];
       const double h2 = len == 3 ? Hr[lane * L + k + 2] : 0.0;
       const double w = tau * (h0 + u1 * h1 + u2 * h2);
-      Hr[lane * L + k] = h0 - w;
+      col = h0 - w;
+      Hr[lane * L + k] = col;
       Hr[lane * L + k + 1] = h1 - w * u1;
       if (len == 3) Hr[lane * L + k + 2] = h2 - w * u2;
     }
@@ -1004,8 +1048,10 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       if (len == 3) Zr[lane * L + k + 2] = z2 - w * u2;
     }
     __syncthreads();
+    return col;
   };
-  // Householder vector of (x, y, z): (I - tau u u^T)(x, y, z)^T = (beta, 0, 0)^T
+  // Householder vector of (x, y, z): (I - tau u u^T)(x, y, z)^T = (beta, 0, 0)^T,
+  // tau = (beta - x) / beta and u = (1, y, z) / (x - beta) from one reciprocal
   auto house = [](double x, double y, double z, double& tau, double& u1, double& u2) {
     const double nrm = sqrt(x * x + y * y + z * z);
     if (y == 0.0 && z == 0.0) {
@@ -1014,10 +1060,18 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       return;
     }
     const double beta = x >= 0.0 ? -nrm : nrm;
-    tau = (beta - x) / beta;
-    const double sc = 1.0 / (x - beta);
+    const double xb = x - beta;
+    const double inv = 1.0 / (beta * xb);
+    tau = -xb * xb * inv;
+    const double sc = beta * inv;
     u1 = y * sc;
     u2 = z * sc;
+  };
+  // a double held by lane l, to every lane (l wave-uniform)
+  auto from_lane = [](double x, int l) -> double {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane(int(b), l), hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
   };
   int hi = M - 1, it = 0, total = 0;
   const int limit = 40 * M;
@@ -1102,21 +1156,24 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     double x = a00 * a00 + a01 * a10 - s * a00 + t;
     double y = a10 * (a00 + a11 - s);
     double z = a10 * a21;
+    // after the reflector at k, the next bulge column (rows k+1..k+3 of
+    // column k) sits in registers of lanes k+1..k+3
     for (int k = lo; k + 1 < hi; ++k) {
-      if (k > lo) {
-        x = Hr[k * L + k - 1];
-        y = Hr[(k + 1) * L + k - 1];
-        z = (k + 2 <= hi) ? Hr[(k + 2) * L + k - 1] : 0.0;
-      }
       double tau, u1, u2;
       house(x, y, z, tau, u1, u2);
-      __syncthreads();
-      if (tau != 0.0) reflect(k, 3, tau, u1, u2, max(lo, k - 1), min(k + 3, hi));
+      if (tau != 0.0) {
+        const double col = reflect(k, 3, tau, u1, u2, max(lo, k - 1), min(k + 3, hi));
+        x = from_lane(col, k + 1);
+        y = from_lane(col, k + 2);
+        z = (k + 3 <= hi) ? from_lane(col, k + 3) : 0.0;
+      } else {
+        x = Hr[(k + 1) * L + k];
+        y = Hr[(k + 2) * L + k];
+        z = (k + 3 <= hi) ? Hr[(k + 3) * L + k] : 0.0;
+      }
     }
     {
       const int k = hi - 1;
-      x = Hr[k * L + k - 1];
-      y = Hr[(k + 1) * L + k - 1];
       double tau, u1, u2;
       house(x, y, 0.0, tau, u1, u2);
       __syncthreads();

@@ -33,7 +33,7 @@ __global__ void k_residual_final(ResFinal A, double* __restrict__ out) {
 
 using taps::dev::BalanceArgs;
 
-__global__ void k_balance(BalanceArgs A) { taps::dev::balance(blockIdx.x, A); }
+__global__ __launch_bounds__(256) void k_balance(BalanceArgs A) { taps::dev::balance(A); }
 
 __global__ void k_first_info(int D, const int* __restrict__ infos, int* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -113,7 +113,7 @@ taps_status balance_impl(taps_handle* h, const taps_problem_t* p, double* const*
     ba.n[d] = p->n[d];
     ba.U[d] = d_U[d];
   }
-  k_balance<<<p->M, 256, 0, stream>>>(ba);
+  k_balance<<<1, 256, 0, stream>>>(ba);
   TAPS_LAUNCHED(h, "k_balance");
   h->gc.valid = 0;  // every Gram changes scale
   return TAPS_OK;
@@ -154,7 +154,7 @@ taps_status balance_launch(taps_handle* h, const taps_problem_t* p, double* cons
     ba.n[d] = p->n[d];
     ba.U[d] = d_U[d];
   }
-  k_balance<<<p->M, 256, 0, stream>>>(ba);
+  k_balance<<<1, 256, 0, stream>>>(ba);
   TAPS_LAUNCHED(h, "k_balance");
   return TAPS_OK;
 }

@@ -235,7 +235,7 @@ def restart_plain(rho1, rho2, plain_median_rho1):
 # ------------------------------------------------------------- streaming
 
 
-def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, on_done=None):
+def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, on_done=None, on_done_batch=None):
     """Continuous batching of Algorithm 1: up to ``slots`` slabs in flight,
     one batched sweep (taps_als_batched) per round; a slab leaves as soon as
     its projected residual reaches tol or it has run ``cap`` sweeps, and the
@@ -246,6 +246,8 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     rule is applied after sweep 2: a slab whose warm start lost (sweep-1
     residual above median_rho1, or growing from sweep 1 to 2) restarts from
     its U_plain factors with a fresh sweep count.
+    on_done(i) is called for every slab as it leaves; on_done_batch(list)
+    once per round with all slabs that left in it.
     Returns (sweeps run per slab, final residual per slab, number of restarts)."""
     from collections import deque
     n = len(probs)
@@ -260,7 +262,7 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
         while len(active) < slots and waiting:
             active.append(waiting.popleft())
         _, r = capi.taps_als_batched(h, [probs[i].struct for i in active], [U[i] for i in active], 0.0, 1)
-        keep = []
+        keep, done = [], []
         for i, ri in zip(active, r):
             count[i] += 1
             total[i] += 1
@@ -276,9 +278,12 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
                     keep.append(i)
                     continue
             if ri <= tol or count[i] >= cap:
+                done.append(i)
                 if on_done is not None:
                     on_done(i)
             else:
                 keep.append(i)
+        if done and on_done_batch is not None:
+            on_done_batch(done)
         active = keep
     return total, rho, len(restarted)

@@ -151,3 +151,29 @@ def test_reduced_precision_rejects_oversized_plane(env):
     out = torch.empty((1, 4), dtype=torch.float64, device="cuda")
     with pytest.raises(RuntimeError):
         capi.taps_reconstruct(h, P, 4, out, prec=capi.BF16, mode=capi.REDUCE)
+
+
+@pytest.mark.parametrize("prec,mode", [("bf16", "reduce"), ("bf16", "store"), ("fp32", "reduce"), ("fp64", "reduce")])
+def test_batched_fields_equal_single_calls(env, prec, mode):
+    # several fields of one shape in one call: each output bit-identical to
+    # its own single-field call (ragged plane sizes, one field without weights)
+    torch, capi, h = env
+    shape, M, B = (70, 45, 9), 40, 5
+    P = {"bf16": capi.BF16, "fp32": capi.FP32, "fp64": capi.FP64}[prec]
+    md = capi.REDUCE if mode == "reduce" else capi.STORE
+    dt = torch.float64 if (md == capi.REDUCE or P == capi.FP64) else torch.float32
+    size = (shape[2], 4) if md == capi.REDUCE else (shape[0] * shape[1] * shape[2],)
+    fields, ws, outs, refs = [], [], [], []
+    for b in range(B):
+        Phis, w = factors(shape, M, 100 + b)
+        fields.append([torch.tensor(Q, device="cuda") for Q in Phis])
+        ws.append(None if b == 2 else torch.tensor(w, device="cuda"))
+        outs.append(torch.full(size, float("nan"), dtype=dt, device="cuda"))
+        refs.append(torch.full(size, float("nan"), dtype=dt, device="cuda"))
+    _say(f"batched {prec} {mode}: {B} fields {shape} M={M}")
+    capi.taps_reconstruct_batched(h, fields, M, outs, prec=P, mode=md, mode_ws=ws, thr=0.5)
+    for b in range(B):
+        capi.taps_reconstruct(h, fields[b], M, refs[b], prec=P, mode=md, mode_w=ws[b], thr=0.5)
+    torch.cuda.synchronize()
+    for b in range(B):
+        assert torch.equal(outs[b], refs[b]), b
