@@ -321,6 +321,16 @@ taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* prob
  *                      wa = min(w, n-1-k) (pivot factorisation, row panel,
  *                      trailing update, right-hand side, back substitution);
  *                      bytes = band + couplings + Q read, X written.
+ *                      Fast diagonalisation (solver 1), its banded stage:
+ *                      flops = 8 n M^2 (the two complex transforms) +
+ *                      8 n M (w+1)(w+2) (elimination and back substitution);
+ *                      bytes = bands + Q read, X written, complex right-hand
+ *                      sides and U rows written and read back.
+ *   TAPS_PROF_EIG      fast diagonalisation, its eigen stage: flops = 44 M^3
+ *                      per system (inverse 2, E 2, Schur form with Schur
+ *                      vectors 25, triangular eigenvectors and their inverse
+ *                      2 x 4/3, H3 4, Z Wv 4, H2 4, in units of M^3); bytes =
+ *                      couplings read, transforms and inverse written.
  *   TAPS_PROF_CONTRACT Grams, load Grams, couplings and force: flops of the
  *                      products, bytes = U, bands, F read once + outputs.
  *   TAPS_PROF_RECON    FP32/BF16 reconstruction on the matrix cores: flops =
@@ -329,7 +339,12 @@ taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* prob
  * taps_profile_enable(h, 1) clears the counters and starts recording,
  * (h, 0) stops.  taps_profile_read synchronises on the recorded events and
  * returns launches, summed kernel milliseconds, flops and bytes of one family. */
-typedef enum { TAPS_PROF_SOLVE = 0, TAPS_PROF_CONTRACT = 1, TAPS_PROF_RECON = 2 } taps_prof_family;
+typedef enum {
+  TAPS_PROF_SOLVE = 0,
+  TAPS_PROF_CONTRACT = 1,
+  TAPS_PROF_RECON = 2,
+  TAPS_PROF_EIG = 3
+} taps_prof_family;
 taps_status taps_profile_enable(taps_handle_t h, int32_t enable);
 taps_status taps_profile_read(taps_handle_t h, taps_prof_family family, int32_t* launches,
                               double* total_ms, double* flops, double* bytes);

@@ -128,7 +128,7 @@ taps_status taps_profile_enable(taps_handle_t h, int32_t enable) {
   if (!h) return TAPS_ERR_INVALID;
   if (enable) {
     h->prof.used = 0;
-    for (int f = 0; f < 3; ++f) h->prof.flops[f] = h->prof.bytes[f] = 0.0;
+    for (int f = 0; f < 4; ++f) h->prof.flops[f] = h->prof.bytes[f] = 0.0;
   }
   h->prof.on = enable != 0;
   return TAPS_OK;
@@ -137,7 +137,8 @@ taps_status taps_profile_enable(taps_handle_t h, int32_t enable) {
 taps_status taps_profile_read(taps_handle_t h, taps_prof_family family, int32_t* launches, double* total_ms,
                               double* flops, double* bytes) {
   if (!h) return TAPS_ERR_INVALID;
-  if (family != TAPS_PROF_SOLVE && family != TAPS_PROF_CONTRACT && family != TAPS_PROF_RECON)
+  if (family != TAPS_PROF_SOLVE && family != TAPS_PROF_CONTRACT && family != TAPS_PROF_RECON &&
+      family != TAPS_PROF_EIG)
     return taps::fail(h, TAPS_ERR_INVALID, "unknown family %d", int(family));
   auto& P = h->prof;
   int cnt = 0;

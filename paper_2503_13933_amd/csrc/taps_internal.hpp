@@ -52,7 +52,7 @@ struct taps_handle {
     std::vector<hipEvent_t> ev;    // start/stop pairs, reused
     std::vector<int> fam;          // family of each recorded pair
     size_t used = 0;               // pairs recorded since enable
-    double flops[3] = {0, 0, 0}, bytes[3] = {0, 0, 0};
+    double flops[4] = {0, 0, 0, 0}, bytes[4] = {0, 0, 0, 0};
     bool on = false;
   } prof;
 };

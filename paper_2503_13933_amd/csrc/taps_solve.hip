@@ -1463,15 +1463,27 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   __syncthreads();
   cplx* Y = reinterpret_cast<cplx*>(f.Y);      // n x M
   cplx* U = reinterpret_cast<cplx*>(f.U);      // M x n x (w+1)
-  // ---- R = Q H2 (fixed rows zero)
-  {
-    IjWalk wk(tid, M, nt);
-    for (long t = tid; t < long(n) * M; t += nt, wk.next(M)) {
-      const int i = wk.i, m = wk.j;
-      cplx sacc = cmk(0.0, 0.0);
-      if (!is_fixed(A, i))
-        for (int q = 0; q < M; ++q) sacc = cadd(sacc, cscale(sH2[q * M + m], A.Q[long(i) * M + q]));
-      Y[t] = sacc;
+  // ---- R = Q H2 (fixed rows zero) on the matrix cores: 16 x 16 tiles of
+  // (rows, modes) dealt to the waves, real and imaginary parts in two
+  // accumulators sharing the Q operand (lane l: row l%16, q = 4kk + l/16)
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nrt = (n + 15) / 16, nct = (M + 15) / 16, ksteps = (M + 3) / 4;
+  for (int tile = wave; tile < nrt * nct; tile += nt >> 6) {
+    const int tr = tile / nct, tc = tile - (tile / nct) * nct;
+    const int ia = tr * 16 + (lane & 15), mb = tc * 16 + (lane & 15);
+    const bool row_ok = ia < n && !is_fixed(A, ia);
+    v4d are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < ksteps; ++kk) {
+      const int q = 4 * kk + (lane >> 4);
+      const double a = (row_ok && q < M) ? A.Q[long(ia) * M + q] : 0.0;
+      const cplx hb = (q < M && mb < M) ? sH2[q * M + mb] : cmk(0.0, 0.0);
+      are = mfma16x16x4(a, hb.r, are);
+      aim = mfma16x16x4(a, hb.i, aim);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = tr * 16 + (lane >> 4) + 4 * j;
+      if (i < n && mb < M) Y[long(i) * M + mb] = cmk(are[j], aim[j]);
     }
   }
   __syncthreads();
@@ -1527,17 +1539,25 @@ __device__ void fd_solve_body(const SolveArgs& A) {
     }
   }
   __syncthreads();
-  // ---- X = Re(Y H3), fixed rows zero
-  IjWalk wk(tid, M, nt);
-  for (long t = tid; t < long(n) * M; t += nt, wk.next(M)) {
-    const int i = wk.i, q = wk.j;
-    double x = 0.0;
-    if (!is_fixed(A, i))
-      for (int m = 0; m < M; ++m) {
-        const cplx y = Y[long(i) * M + m], h = sH3[m * M + q];
-        x += y.r * h.r - y.i * h.i;
-      }
-    A.X[t] = x;
+  // ---- X = Re(Y H3) = Yr H3r - Yi H3i (fixed rows zero) on the matrix
+  // cores, tiles of (rows, modes) as above
+  for (int tile = wave; tile < nrt * nct; tile += nt >> 6) {
+    const int tr = tile / nct, tc = tile - (tile / nct) * nct;
+    const int ia = tr * 16 + (lane & 15), qb = tc * 16 + (lane & 15);
+    const bool row_ok = ia < n && !is_fixed(A, ia);
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < ksteps; ++kk) {
+      const int m = 4 * kk + (lane >> 4);
+      const cplx ya = (row_ok && m < M) ? Y[long(ia) * M + m] : cmk(0.0, 0.0);
+      const cplx hb = (m < M && qb < M) ? sH3[m * M + qb] : cmk(0.0, 0.0);
+      acc = mfma16x16x4(ya.r, hb.r, acc);
+      acc = mfma16x16x4(-ya.i, hb.i, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = tr * 16 + (lane >> 4) + 4 * j;
+      if (i < n && qb < M) A.X[long(i) * M + qb] = acc[j];
+    }
   }
   if (tid == 0 && s_info) A.info[0] = s_info;
 }
@@ -1567,18 +1587,23 @@ bool fd_supported(int M, int s, int K) {
   return K == 2 && M <= kFdMaxM && fd_eig_lds(M) <= 160 * 1024 - 2048 && fd_solve_lds(M, s) <= 160 * 1024 - 2048;
 }
 
-// Algorithmic flops of one fast-diagonalisation solve: the eigen stage
-// (nominal 30 M^3: inverse, E, Hessenberg form, QR, eigenvectors, H2, H3), the
-// two complex transforms (4 n M^2 each) and the M banded complex solves
-// (8 n w (w + 2) each).
+// Algorithmic work of the fast diagonalisation's two stages.  Eigen stage
+// per system, in units of M^3 real flops: C1^{-1} 2, E 2, Schur form with
+// Schur vectors 25 (the usual Hessenberg + QR count), triangular eigenvectors
+// and their inverse 4/3 each, H3 4, Z Wv 4, H2 4.  Banded stage: the two
+// complex transforms (4 n M^2 each) and M banded complex eliminations with
+// back substitution, 8 n (w+1)(w+2) each.
+double fd_eig_flops(int M) { return 44.0 * M * double(M) * M; }
+double fd_eig_bytes(int M) { return 8.0 * (2.0 * M * M) + 16.0 * (2.0 * M * M + M) + 8.0 * M * M; }
 double fd_flops(int n, int M, int w) {
-  return 30.0 * M * double(M) * M + 8.0 * n * double(M) * M + 8.0 * M * double(n) * w * (w + 2);
+  return 8.0 * n * double(M) * M + 8.0 * M * double(n) * (w + 1) * (w + 2);
 }
 
-// Algorithmic bytes: the two bands, Q and X once each, the couplings, and the
-// complex right-hand sides written and read back plus the U rows.
+// Algorithmic bytes of the banded stage: the two bands, Q and X once each,
+// the transforms, and the complex right-hand sides written and read back plus
+// the U rows.
 double fd_bytes(int n, int M, int w) {
-  return 8.0 * (2.0 * n * (2 * w + 1) + 2.0 * n * M + 2.0 * M * M) + 16.0 * (2.0 * n * M + 2.0 * n * M * (w + 1));
+  return 8.0 * (2.0 * n * (2 * w + 1) + 2.0 * n * M) + 16.0 * (2.0 * M * M + 2.0 * n * M + 2.0 * n * M * (w + 1));
 }
 
 }  // namespace
@@ -1681,9 +1706,11 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
   if (use_fd) {
     TAPS_TRY(allow_lds(h, k_fd_eig_one, fd_eig_lds(M), &fd_eig1_allowed));
     TAPS_TRY(allow_lds(h, k_fd_solve_one, fd_solve_lds(M, s), &fd_solve1_allowed));
-    TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+    TAPS_TRY(prof_begin(h, TAPS_PROF_EIG, stream, &slot));
     k_fd_eig_one<<<1, 64, fd_eig_lds(M), stream>>>(A);
     TAPS_LAUNCHED(h, "k_fd_eig");
+    TAPS_TRY(prof_end(h, slot, fd_eig_flops(M), fd_eig_bytes(M), stream));
+    TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
     k_fd_solve_one<<<1, kFdThreads, fd_solve_lds(M, s), stream>>>(A);
     TAPS_LAUNCHED(h, "k_fd_solve");
     TAPS_TRY(prof_end(h, slot, fd_flops(n, M, w), fd_bytes(n, M, w), stream));
@@ -1767,10 +1794,12 @@ taps_status fd_prepare(taps_handle* h, int M, int s) {
 taps_status fd_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active, int M, int s,
                               double flops, double bytes, hipStream_t stream) {
   size_t slot;
-  TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+  TAPS_TRY(prof_begin(h, TAPS_PROF_EIG, stream, &slot));
   const SolveArgs* args = static_cast<const SolveArgs*>(d_args);
   k_fd_eig<<<n_active, 64, fd_eig_lds(M), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_eig");
+  TAPS_TRY(prof_end(h, slot, n_active * fd_eig_flops(M), n_active * fd_eig_bytes(M), stream));
+  TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
   k_fd_solve<<<n_active, kFdThreads, fd_solve_lds(M, s), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_solve");
   TAPS_TRY(prof_end(h, slot, flops, bytes, stream));
