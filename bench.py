@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--M", type=int, default=40)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=3, help="plain sweep budget that sets the target residual")
-    ap.add_argument("--batch", type=int, default=512, help="slabs in flight, one workgroup each")
+    ap.add_argument("--batch", type=int, default=1024, help="slabs in flight, one workgroup each")
     ap.add_argument("--slabs", type=int, default=1024, help="slabs solved per step")
     ap.add_argument("--train-chains", type=int, default=512)
     ap.add_argument("--train-steps", type=int, default=3000)
@@ -141,7 +141,7 @@ def main():
     U_plain_big = [torch.tensor(np.stack([u[d] for u in U0_host]), dtype=torch.float64, device="cuda")
                    for d in range(4)]
     del U0_host
-    U_plain = [[t[b] for t in U_plain_big] for b in range(N)]
+    U_plain = ws.FactorBatch(U_plain_big)
     layout = ws.Layout(h, cases[0], M)
     n_tr = args.train_chains
     tr_a = family(n_tr, args.seed + 101, **grid)
@@ -164,10 +164,15 @@ def main():
 
     stats = torch.empty((N, args.nz, 4), dtype=torch.float64, device="cuda")
 
+    n_pts, nt, s_row = [ax.n for ax in cases[0].axes[:3]], cases[0].axes[3].n, args.nz * 4 * 8
+
     def reconstruct(U, done):
-        # end-time fields of the slabs that left this round, in one call
-        capi.taps_reconstruct_batched(h, [U[b][:3] for b in done], M, [stats[b] for b in done], prec=capi.BF16,
-                                      mode=capi.REDUCE, mode_ws=[U[b][3][-1] for b in done], thr=1000.0)
+        # end-time fields (time factor's last row as mode weights) of the
+        # slabs that left this round, in one call, by address
+        capi.taps_reconstruct_batched(h, [[U.ptr(b, 0), U.ptr(b, 1), U.ptr(b, 2)] for b in done], M,
+                                      [stats.data_ptr() + b * s_row for b in done], prec=capi.BF16,
+                                      mode=capi.REDUCE, mode_ws=[U.ptr(b, 3, nt - 1) for b in done], thr=1000.0,
+                                      n_pts=n_pts)
 
     def step_warm():
         Y = net.forward(X_bench)
@@ -176,8 +181,7 @@ def main():
                                on_done_batch=lambda done: reconstruct(U, done))
 
     def step_random_batched():
-        big = [t.clone() for t in U_plain_big]
-        U = [[t[b] for t in big] for b in range(N)]
+        U = U_plain.clone()
         return ws.solve_stream(h, probs, U, rho_star, cap, B, on_done_batch=lambda done: reconstruct(U, done))
 
     def timed(fn, label, prof=False):
@@ -209,7 +213,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        U = [u.clone() for u in U_plain[0]]
+        U = [u.clone() for u in U_plain[0]]   # (views of slab 0, cloned)
         torch.cuda.synchronize()
         tp = time.perf_counter()
         sw, rho, _ = capi.taps_als(h, probs[0].struct, U, rho_star, cap)

@@ -120,9 +120,12 @@ def lib():
 
 
 def _ptr(t):
-    """Device (or host) address of a tensor, None for None."""
+    """Device (or host) address of a tensor (or a raw address given as an
+    int), None for None."""
     if t is None:
         return None
+    if isinstance(t, int):
+        return t
     if not t.is_contiguous():
         raise TapsError("tensor must be contiguous")
     return t.data_ptr()
@@ -330,11 +333,12 @@ def taps_reconstruct(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int =
 
 
 def taps_reconstruct_batched(h: Handle, Phis, M: int, outs, prec: int = BF16, mode: int = REDUCE, mode_ws=None,
-                             thr: float = 0.0, stream=None):
-    """Phis: B lists of 3 factor tensors (one grid shape); outs: B outputs;
-    mode_ws: B weight tensors (entries may be None) or None."""
+                             thr: float = 0.0, stream=None, n_pts=None):
+    """Phis: B lists of 3 factor tensors (one grid shape) or raw addresses
+    (then n_pts gives the three lengths); outs: B outputs; mode_ws: B weight
+    tensors or addresses (entries may be None) or None."""
     B = len(Phis)
-    n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis[0]])
+    n = (C.c_int32 * 3)(*(n_pts if n_pts is not None else [int(P.shape[0]) for P in Phis[0]]))
     mw = _ptr_array(mode_ws) if mode_ws is not None else None
     h.check(lib().taps_reconstruct_batched(h.h, B, n, _ptr_array([P for F in Phis for P in F]), M, mw, prec, mode,
                                            _ptr_array(outs), thr, _stream(stream)), "taps_reconstruct_batched")
@@ -360,8 +364,8 @@ def taps_als_batched(h: Handle, probs, Us, tol: float, iter_max: int, stream=Non
     """Algorithm 1 over a batch.  probs: list of Problem; Us: list (per problem)
     of factor tensor lists.  Returns (sweeps list, rho list)."""
     B = len(probs)
-    arr = (Problem * B)(*probs)
-    ptrs = _ptr_array([u for U in Us for u in U])
+    arr = probs if isinstance(probs, C.Array) else (Problem * B)(*probs)
+    ptrs = Us if isinstance(Us, C.Array) else _ptr_array([u for U in Us for u in U])
     sw = (C.c_int32 * B)()
     rh = (C.c_double * B)()
     h.check(lib().taps_als_batched(h.h, B, arr, ptrs, tol, iter_max, sw, rh, _stream(stream)), "taps_als_batched")

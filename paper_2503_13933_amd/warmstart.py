@@ -27,6 +27,43 @@ F32, F64 = torch.float32, torch.float64
 PARAM_RANGES = {"power": (100.0, 300.0), "radius": (0.030, 0.080), "k": (0.010, 0.030), "y0": (0.3, 0.7)}
 
 
+class FactorBatch:
+    """Factors of N slabs on one grid: one contiguous (N, n_d, M) FP64 tensor
+    per dim.  Slab b's factor of dim d starts at a computed address, so a
+    round of the batched driver needs no per-slab tensor objects; ``fb[b]``
+    gives tensor views when they are wanted."""
+
+    def __init__(self, dims):
+        self.dims = [t.contiguous() for t in dims]
+        self.N, self.M = self.dims[0].shape[0], self.dims[0].shape[2]
+        self.n = [int(t.shape[1]) for t in self.dims]
+        self.base = [t.data_ptr() for t in self.dims]
+        self.stride = [int(t.shape[1] * t.shape[2]) * 8 for t in self.dims]
+
+    def __len__(self):
+        return self.N
+
+    def __getitem__(self, b):
+        return [t[b] for t in self.dims]
+
+    def ptr(self, b, d, row=0):
+        """Address of row ``row`` of slab b's factor of dim d."""
+        return self.base[d] + b * self.stride[d] + row * self.M * 8
+
+    def ptrs(self, idx):
+        """Factor pointers of the slabs idx, problem-major (driver order)."""
+        D = len(self.dims)
+        import ctypes as C
+        arr = (C.c_void_p * (len(idx) * D))()
+        for j, b in enumerate(idx):
+            for d in range(D):
+                arr[j * D + d] = self.base[d] + b * self.stride[d]
+        return arr
+
+    def clone(self):
+        return FactorBatch([t.clone() for t in self.dims])
+
+
 def ldw(w: int) -> int:
     return (w + 31) // 32 * 32
 
@@ -155,10 +192,9 @@ class Layout:
         return self.initial_batch(y.unsqueeze(0), fixed)[0]
 
     def initial_batch(self, Y, fixed):
-        """Network outputs (N, n_out) -> per slab [0, U_y, U_z, U_t], the
-        slabs' factors being contiguous (n_d x M) slices of one (N, n_d, M)
-        tensor per dim: one prolongation call per dim for the whole batch
-        (the N coarse factors side by side as N*M columns)."""
+        """Network outputs (N, n_out) -> FactorBatch of [0, U_y, U_z, U_t]
+        per slab: one prolongation call per dim for the whole batch (the N
+        coarse factors side by side as N*M columns)."""
         N, M = Y.shape[0], self.M
         dims, off = [], 0
         for d, (c, s, size) in enumerate(zip(self.coarse, self.scale, self.sizes)):
@@ -169,7 +205,7 @@ class Layout:
                 Uf[:, torch.tensor(sorted(fixed[d + 1]), device=Y.device)] = 0.0
             dims.append(Uf)
         U0 = torch.zeros((N, self.axes[0].n, M), dtype=F64, device=Y.device)
-        return [[U0[b]] + [Ud[b] for Ud in dims] for b in range(N)]
+        return FactorBatch([U0] + dims)
 
     def features(self, case, V):
         f = torch.tensor(param_features(case), dtype=F64, device=self.coarse[0].keep[0].device)
@@ -248,9 +284,23 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     its U_plain factors with a fresh sweep count.
     on_done(i) is called for every slab as it leaves; on_done_batch(list)
     once per round with all slabs that left in it.
+    U (and U_plain) may be FactorBatch objects (addresses computed per
+    round) or lists of per-slab factor lists.
     Returns (sweeps run per slab, final residual per slab, number of restarts)."""
+    import ctypes as C
     from collections import deque
     n = len(probs)
+    allp = (capi.Problem * n)(*[p.struct for p in probs])
+    psize = C.sizeof(capi.Problem)
+
+    def prob_array(idx):
+        if len(idx) == n and idx == list(range(n)):
+            return allp
+        sub = (capi.Problem * len(idx))()
+        for j, i in enumerate(idx):
+            C.memmove(C.addressof(sub) + j * psize, C.addressof(allp) + i * psize, psize)
+        return sub
+
     waiting = deque(range(n))
     active = []
     count = [0] * n          # sweeps since the (re)start
@@ -261,7 +311,8 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     while waiting or active:
         while len(active) < slots and waiting:
             active.append(waiting.popleft())
-        _, r = capi.taps_als_batched(h, [probs[i].struct for i in active], [U[i] for i in active], 0.0, 1)
+        Ua = U.ptrs(active) if isinstance(U, FactorBatch) else [U[i] for i in active]
+        _, r = capi.taps_als_batched(h, prob_array(active), Ua, 0.0, 1)
         keep, done = [], []
         for i, ri in zip(active, r):
             count[i] += 1
