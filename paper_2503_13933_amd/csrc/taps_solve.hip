@@ -1301,7 +1301,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
   if (lane == 0) A.info[0] = s_fail ? -s_fail : 0;
 }
 
-constexpr int kFdThreads = 256;
+constexpr int kFdThreads = 64;   // one wave: transforms, staging and elimination
 
 // Banded complex solves (A1 + lambda_m A2) y_m = r_m of the fast
 // diagonalisation with the elimination window in registers: lane m of wave 0
@@ -1314,36 +1314,52 @@ constexpr int kFdThreads = 256;
 // reciprocal pivot and the w upper entries of row k (the U row, layout
 // [row][entry][system] so stores and loads are coalesced over systems) and
 // the reduced right-hand side; back substitution walks the rows upwards with
-// the U rows loaded w+1 rows ahead.  Rows beyond n are identity rows, so the
-// last steps need no guards.  No pivoting: a zero pivot sets the info word.
+// the U rows loaded a few rows ahead.  Rows beyond n are identity rows, so
+// the last steps need no guards.  No pivoting: a zero pivot sets the info word.
+// One 64-lane wave per system set: the elimination is bound by its own
+// instruction stream, so one wave per SIMD is the useful occupancy; the wave
+// stages the band itself, loading chunk c+2 into registers before
+// eliminating chunk c and storing it to LDS after.
 template <int W>
 __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLam, double2* ring, int* s_info) {
   constexpr int W1 = W + 1, BW = 2 * W + 1, CH = W1 * (32 / W1);
-  const int n = A.n, M = A.M, tid = threadIdx.x, wave = tid >> 6, m = tid & 63;
+  constexpr int SPL = (CH * BW + 63) / 64;   // staged entries per lane and chunk
+  const int n = A.n, M = A.M, tid = threadIdx.x, m = tid;
   const double* b1 = A.band;
   const double* b2 = A.band + long(n) * BW;
   cplx* Yg = reinterpret_cast<cplx*>(f.Y);
   cplx* Ug = reinterpret_cast<cplx*>(f.U);
   // staged (a1, a2) of band row i, offset o (column i - W + o), with fixed
   // rows (identity), fixed and out-of-range columns (zero) applied
-  auto stage = [&](int c, int t0, int nt) {
-    double2* dst = ring + (c % 3) * CH * BW;
-    for (int t = t0; t < CH * BW; t += nt) {
-      const int i = c * CH + t / BW, o = t % BW, j = i - W + o;
-      double2 v = make_double2(0.0, 0.0);
-      if (i >= n || is_fixed(A, i)) {
-        v.x = (o == W) ? 1.0 : 0.0;
-      } else if (j >= 0 && j < n && !is_fixed(A, j)) {
-        v = make_double2(b1[long(i) * BW + o], b2[long(i) * BW + o]);
-      }
-      dst[t] = v;
+  auto band_pair = [&](int c, int t) -> double2 {
+    const int i = c * CH + t / BW, o = t % BW, j = i - W + o;
+    double2 v = make_double2(0.0, 0.0);
+    if (t >= CH * BW) return v;
+    if (i >= n || is_fixed(A, i)) {
+      v.x = (o == W) ? 1.0 : 0.0;
+    } else if (j >= 0 && j < n && !is_fixed(A, j)) {
+      v = make_double2(b1[long(i) * BW + o], b2[long(i) * BW + o]);
     }
+    return v;
+  };
+  auto stage_store = [&](int c, const double2* v) {
+    double2* dst = ring + (c % 3) * CH * BW;
+#pragma unroll
+    for (int u = 0; u < SPL; ++u)
+      if (tid + 64 * u < CH * BW) dst[tid + 64 * u] = v[u];
   };
   const int nchunks = (n + W) / CH + 1;   // rows up to n + W are read
-  stage(0, tid, blockDim.x);
-  if (nchunks > 1) stage(1, tid, blockDim.x);
+  double2 sv[SPL];
+#pragma unroll
+  for (int u = 0; u < SPL; ++u) sv[u] = band_pair(0, tid + 64 * u);
+  stage_store(0, sv);
+  if (nchunks > 1) {
+#pragma unroll
+    for (int u = 0; u < SPL; ++u) sv[u] = band_pair(1, tid + 64 * u);
+    stage_store(1, sv);
+  }
   __syncthreads();
-  const bool act = wave == 0 && m < M;
+  const bool act = m < M;
   const cplx lam = act ? sLam[m] : cmk(0.0, 0.0);
   auto E = [&](int i, int o) -> cplx {
     const double2 v = ring[((i / CH) % 3 * CH + i % CH) * BW + o];
@@ -1363,6 +1379,11 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
   int info = 0;
   // ---- forward elimination, one chunk of CH rows per barrier
   for (int c = 0; c * CH < n; ++c) {
+    const bool more = c + 2 < nchunks;
+    if (more) {   // loads of chunk c+2, consumed after this chunk's steps
+#pragma unroll
+      for (int u = 0; u < SPL; ++u) sv[u] = band_pair(c + 2, tid + 64 * u);
+    }
     if (act) {
       for (int k0 = c * CH; k0 < (c + 1) * CH && k0 < n; k0 += W1) {
 #pragma unroll
@@ -1401,41 +1422,51 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
           }
         }
       }
-    } else if (wave > 0) {
-      if (c + 2 < nchunks) stage(c + 2, tid - 64, blockDim.x - 64);
     }
+    if (more) stage_store(c + 2, sv);
     __syncthreads();
   }
   if (act && info) atomicCAS(s_info, 0, info);
-  // ---- back substitution: y_k = inv_k (yhat_k - sum_c U[k][c] y_{k+c})
+  // ---- back substitution: y_k = inv_k (yhat_k - sum_c U[k][c] y_{k+c});
+  // the U rows and reduced right-hand sides are loaded PF rows ahead (a ring
+  // of PF row buffers, PF dividing w+1, so slots stay static in the unrolled
+  // groups)
   if (act) {
-    cplx ub[W1][W1], yh[W1], yw[W1];
-    const int gtop = (n - 1) / W1;
+    constexpr int PF = W1 / 2 > 0 ? W1 / 2 : 1;
+    static_assert(W1 % PF == 0, "prefetch ring must divide the group");
+    cplx ub[PF][W1], yh[PF], yw[W1];
 #pragma unroll
-    for (int p = 0; p < W1; ++p) {   // slot p: the highest row below n with k % W1 == p
-      yw[p] = cmk(0.0, 0.0);
-      const int k = gtop * W1 + p < n ? gtop * W1 + p : (gtop - 1) * W1 + p;
+    for (int p = 0; p < W1; ++p) yw[p] = cmk(0.0, 0.0);
+#pragma unroll
+    for (int j = 1; j <= PF; ++j) {   // rows n-1 .. n-PF into slots k % PF
+      const int k = n - j;
       if (k >= 0) {
 #pragma unroll
-        for (int cc = 0; cc < W1; ++cc) ub[p][cc] = Ug[(long(k) * W1 + cc) * M + m];
-        yh[p] = Yg[long(k) * M + m];
+        for (int q = 0; q < PF; ++q)
+          if (k % PF == q) {
+#pragma unroll
+            for (int cc = 0; cc < W1; ++cc) ub[q][cc] = Ug[(long(k) * W1 + cc) * M + m];
+            yh[q] = Yg[long(k) * M + m];
+          }
       }
     }
+    const int gtop = (n - 1) / W1;
     for (int g = gtop; g >= 0; --g) {
 #pragma unroll
       for (int p = W1 - 1; p >= 0; --p) {
         const int k = g * W1 + p;
         if (k < n) {
-          cplx acc = yh[p];
+          const int q = p % PF;
+          cplx acc = yh[q];
 #pragma unroll
-          for (int cc = 1; cc < W1; ++cc) acc = csub(acc, cmul(ub[p][cc], yw[(p + cc) % W1]));
-          const cplx y = cmul(acc, ub[p][0]);
+          for (int cc = 1; cc < W1; ++cc) acc = csub(acc, cmul(ub[q][cc], yw[(p + cc) % W1]));
+          const cplx y = cmul(acc, ub[q][0]);
           yw[p] = y;
           Yg[long(k) * M + m] = y;
-          if (k - W1 >= 0) {
+          if (k - PF >= 0) {
 #pragma unroll
-            for (int cc = 0; cc < W1; ++cc) ub[p][cc] = Ug[(long(k - W1) * W1 + cc) * M + m];
-            yh[p] = Yg[long(k - W1) * M + m];
+            for (int cc = 0; cc < W1; ++cc) ub[q][cc] = Ug[(long(k - PF) * W1 + cc) * M + m];
+            yh[q] = Yg[long(k - PF) * M + m];
           }
         }
       }
@@ -1447,19 +1478,18 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, n = A.n, w = 2 * A.s + 1, BW = 2 * w + 1, W1 = w + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
-  cplx* sH2 = reinterpret_cast<cplx*>(lds);    // M x M
-  cplx* sH3 = sH2 + MM;                          // M x M
-  cplx* sLam = sH3 + MM;                         // M
-  cplx* win = sLam + M;                          // M systems x (w+1) rows x (2w+1)
+  // LDS: the eigenvalues, then one region used in turn by H2 (transform
+  // in), the staged band chunks (register window) or per-system row rings
+  // (other patch sizes), and H3 (transform out)
+  cplx* sLam = reinterpret_cast<cplx*>(lds);    // M
+  cplx* win = sLam + M;
+  cplx* sH = win;                                // M x M, H2 then H3
   const FdWs f = fd_ws(A);
   __shared__ int s_info;
   if (tid == 0) s_info = 0;
   if (A.info[0] != 0) return;   // the eigen stage failed: leave its code
-  for (int t = tid; t < MM; t += nt) {
-    sH2[t] = cmk(f.H2[2 * t], f.H2[2 * t + 1]);
-    sH3[t] = cmk(f.H3[2 * t], f.H3[2 * t + 1]);
-  }
   for (int m = tid; m < M; m += nt) sLam[m] = cmk(f.lam[2 * m], f.lam[2 * m + 1]);
+  for (int t = tid; t < MM; t += nt) sH[t] = cmk(f.H2[2 * t], f.H2[2 * t + 1]);
   __syncthreads();
   cplx* Y = reinterpret_cast<cplx*>(f.Y);      // n x M
   cplx* U = reinterpret_cast<cplx*>(f.U);      // M x n x (w+1)
@@ -1473,12 +1503,20 @@ __device__ void fd_solve_body(const SolveArgs& A) {
     const int ia = tr * 16 + (lane & 15), mb = tc * 16 + (lane & 15);
     const bool row_ok = ia < n && !is_fixed(A, ia);
     v4d are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
-    for (int kk = 0; kk < ksteps; ++kk) {
-      const int q = 4 * kk + (lane >> 4);
-      const double a = (row_ok && q < M) ? A.Q[long(ia) * M + q] : 0.0;
-      const cplx hb = (q < M && mb < M) ? sH2[q * M + mb] : cmk(0.0, 0.0);
-      are = mfma16x16x4(a, hb.r, are);
-      aim = mfma16x16x4(a, hb.i, aim);
+    for (int k0 = 0; k0 < ksteps; k0 += 4) {   // Q operands of 4 steps loaded together
+      double av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = 4 * (k0 + u) + (lane >> 4);
+        av[u] = (row_ok && q < M) ? A.Q[long(ia) * M + q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = 4 * (k0 + u) + (lane >> 4);
+        const cplx hb = (q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
+        are = mfma16x16x4(av[u], hb.r, are);
+        aim = mfma16x16x4(av[u], hb.i, aim);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1541,17 +1579,27 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   __syncthreads();
   // ---- X = Re(Y H3) = Yr H3r - Yi H3i (fixed rows zero) on the matrix
   // cores, tiles of (rows, modes) as above
+  for (int t = tid; t < MM; t += nt) sH[t] = cmk(f.H3[2 * t], f.H3[2 * t + 1]);
+  __syncthreads();
   for (int tile = wave; tile < nrt * nct; tile += nt >> 6) {
     const int tr = tile / nct, tc = tile - (tile / nct) * nct;
     const int ia = tr * 16 + (lane & 15), qb = tc * 16 + (lane & 15);
     const bool row_ok = ia < n && !is_fixed(A, ia);
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kk = 0; kk < ksteps; ++kk) {
-      const int m = 4 * kk + (lane >> 4);
-      const cplx ya = (row_ok && m < M) ? Y[long(ia) * M + m] : cmk(0.0, 0.0);
-      const cplx hb = (m < M && qb < M) ? sH3[m * M + qb] : cmk(0.0, 0.0);
-      acc = mfma16x16x4(ya.r, hb.r, acc);
-      acc = mfma16x16x4(-ya.i, hb.i, acc);
+    for (int k0 = 0; k0 < ksteps; k0 += 4) {   // Y operands of 4 steps loaded together
+      cplx yv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int m = 4 * (k0 + u) + (lane >> 4);
+        yv[u] = (row_ok && m < M) ? Y[long(ia) * M + m] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int m = 4 * (k0 + u) + (lane >> 4);
+        const cplx hb = (m < M && qb < M) ? sH[m * M + qb] : cmk(0.0, 0.0);
+        acc = mfma16x16x4(yv[u].r, hb.r, acc);
+        acc = mfma16x16x4(-yv[u].i, hb.i, acc);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1566,20 +1614,21 @@ __global__ __launch_bounds__(64) void k_fd_eig(const SolveArgs* __restrict__ arg
   const SolveArgs A = args[active[blockIdx.x]];
   fd_eig_body(A);
 }
-__global__ __launch_bounds__(kFdThreads) void k_fd_solve(const SolveArgs* __restrict__ args,
+__global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve(const SolveArgs* __restrict__ args,
                                                          const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
   fd_solve_body(A);
 }
 __global__ __launch_bounds__(64) void k_fd_eig_one(SolveArgs A) { fd_eig_body(A); }
-__global__ __launch_bounds__(kFdThreads) void k_fd_solve_one(SolveArgs A) { fd_solve_body(A); }
+__global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { fd_solve_body(A); }
 
 size_t fd_eig_lds(int M) { return size_t(6) * M * (M | 1) * 8; }
 size_t fd_solve_lds(int M, int s) {
   const int w = 2 * s + 1;
-  const size_t rows = size_t(M) * (w + 1) * (2 * w + 1);          // per-system row rings (any w)
+  const bool reg = (w == 1 || w == 3 || w == 5);
+  const size_t rows = size_t(M) * (w + 1) * (2 * w + 1);                      // per-system row rings
   const size_t ring = size_t(3) * ((w + 1) * (32 / (w + 1))) * (2 * w + 1);   // staged band chunks
-  return (size_t(2) * M * M + M + std::max(rows, ring)) * 16;
+  return (size_t(M) + std::max(size_t(M) * M, reg ? ring : rows)) * 16;
 }
 size_t fd_eig_allowed = 0, fd_solve_allowed = 0, fd_eig1_allowed = 0, fd_solve1_allowed = 0;
 
