@@ -46,12 +46,11 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix)
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
-# Memory traffic of the batched dim solve per algorithmic flop, from two
-# rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a
-# 1 GiB copy), valid for the solve source with this SHA-256 prefix only.
-SOLVE_TRAFFIC = {"bytes_per_flop": 0.2813, "source_sha256": "c9a856e7e0610480"}
-# Same for the eigen stage of the fast diagonalisation (none taken yet for this source).
-EIG_TRAFFIC = {"bytes_per_flop": 0.0, "source_sha256": ""}
+# Memory traffic of the eigen stage (k_fd_eig) per algorithmic flop, from two
+# rocprofv3 counter runs of paper_2503_13933_amd/prof_solve.py (FETCH_SIZE x
+# 2.0 + WRITE_SIZE x 1.0, the factors read off its 1 GiB device copy), valid
+# for the solve source with this SHA-256 prefix only.
+EIG_TRAFFIC = {"bytes_per_flop": 0.03683, "source_sha256": "4eedcf6bc3a1756d"}
 
 
 def log(msg):
@@ -229,9 +228,8 @@ def main():
     fd = args.solver == "fastdiag"
     # dominant kernel: the eigen stage for the fast diagonalisation, the block LU otherwise
     n_dom, ms_dom, fl_dom = (n_eig, ms_eig, fl_eig) if fd else (n_solve, ms_solve, fl_solve)
-    tr = EIG_TRAFFIC if fd else SOLVE_TRAFFIC
-    same_kernel = digest == tr["source_sha256"]
-    traffic = tr["bytes_per_flop"] * fl_dom / n_dom if (same_kernel and n_dom) else None
+    same_kernel = fd and digest == EIG_TRAFFIC["source_sha256"]
+    traffic = EIG_TRAFFIC["bytes_per_flop"] * fl_dom / n_dom if (same_kernel and n_dom) else None
     achieved = (fl_dom / n_dom) / (ms_dom / n_dom * 1e-3) / 1e12 if n_dom else 0.0
     rec_tf = (fl_rec / n_rec) / (ms_rec / n_rec * 1e-3) / 1e12 if n_rec else 0.0
     out = {

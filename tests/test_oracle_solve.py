@@ -247,3 +247,48 @@ def test_heat_operator_rank_one_reproduced_exactly():
     u = fulltensor.td_tensor(U)
     ref = np.einsum("i,j,k,l->ijkl", np.ones(9), np.ones(8), z * (2 * H - z), t)
     assert np.abs(u - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_dim_system_by_complex_schur_route():
+    # the fast-diagonalisation reading of a two-kind dim system (Sec. 2.6):
+    # A1 X C1^T + A2 X C2^T = Q with (A1, C1) the mass kind; E = C2^T C1^{-T}
+    # = Z T Z^H (complex Schur), P = Z Wv (eigenvectors), M banded systems
+    # (A1 + lambda_m A2) y_m = (Q C1^{-T} P)_m, X = Re(Y P^{-1}) -- must equal
+    # the plain solve of the dim system, non-symmetric time dim included
+    from scipy.linalg import schur, solve_triangular
+    case = W.heat_slab(10, 9, 8, 9, M=5, seed=3)
+    prob = problems.heat_slab(case)
+    rng = np.random.Generator(np.random.PCG64(8))
+    U = []
+    for d in range(prob.D):
+        u = rng.standard_normal((prob.n[d], 5))
+        u[list(prob.fixed[d])] = 0.0
+        U.append(u)
+    for d in range(prob.D):
+        C = separated.couplings(prob, U, d)
+        Q = separated.force(prob, U, d)
+        ref = separated.solve_dim(prob, d, C, Q)
+        k1 = "mass"
+        k2 = [k for k in prob.kinds(d) if k != "mass"][0]
+        A1, A2 = prob.mats[d][k1].toarray(), prob.mats[d][k2].toarray()
+        fx = list(prob.fixed[d])
+        A1[fx, :] = 0.0
+        A1[:, fx] = 0.0
+        A1[fx, fx] = 1.0
+        A2[fx, :] = 0.0
+        A2[:, fx] = 0.0
+        C1inv = np.linalg.inv(C[k1])
+        E = C[k2].T @ C1inv.T
+        T, Z = schur(E.astype(complex), output="complex")
+        M = E.shape[0]
+        Wv = np.eye(M, dtype=complex)
+        for k in range(M):
+            for i in range(k - 1, -1, -1):
+                Wv[i, k] = -(T[i, i + 1:k + 1] @ Wv[i + 1:k + 1, k]) / (T[i, i] - T[k, k])
+        P = Z @ Wv
+        R = Q.copy()
+        R[fx] = 0.0
+        R = R @ C1inv.T @ P
+        Y = np.column_stack([np.linalg.solve(A1 + T[m, m] * A2, R[:, m]) for m in range(M)])
+        X = (Y @ solve_triangular(Wv, np.eye(M), lower=False) @ Z.conj().T).real
+        assert np.abs(X - ref).max() <= 1e-10 * np.abs(ref).max(), d
