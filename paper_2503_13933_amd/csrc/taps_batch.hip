@@ -129,8 +129,9 @@ __global__ void kb_residual_final(const BProb* __restrict__ P, const int* __rest
   q.outs[q.D + 1] = qs > 0.0 ? sqrt(rs / qs) : sqrt(rs);
 }
 
-__global__ __launch_bounds__(256) void kb_balance(const BalanceArgs* __restrict__ BA, const int* __restrict__ act) {
-  balance(BA[act[blockIdx.x]]);
+__global__ __launch_bounds__(256) void kb_balance(const BalanceArgs* __restrict__ BA, const int* __restrict__ act,
+                                                   unsigned scale_mask) {
+  balance(BA[act[blockIdx.x]], scale_mask);
 }
 
 size_t gram_lds_allowed = 0, res_lds_allowed = 0;
@@ -296,6 +297,10 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     for (int d = 0; d < D; ++d) {
       bal[b].n[d] = p.n[d];
       bal[b].U[d] = q.U[d];
+      bal[b].K[d] = p.n_kinds[d];
+      bal[b].Rc[d] = p.R_cols[d];
+      bal[b].gram[d] = q.gram[d];
+      bal[b].lgram[d] = q.lgram[d];
     }
   }
   std::vector<int> active(B), next;
@@ -392,9 +397,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       kb_berr_final<<<cdiv(nact, 64), 64, 0, st>>>(d_prob, d_active, nact, d);
       TAPS_LAUNCHED(h, "kb_berr_final");
     }
-    kb_balance<<<nact, 256, 0, st>>>(d_bal, d_active);
+    // the Grams still valid (every dim but the last solved) are rescaled with
+    // the factors inside the balancing kernel; only the stale ones are recomputed
+    kb_balance<<<nact, 256, 0, st>>>(d_bal, d_active, valid);
     TAPS_LAUNCHED(h, "kb_balance");
-    for (int e = 0; e < D; ++e) TAPS_TRY(refresh(e, nact, st));
+    for (int e = 0; e < D; ++e)
+      if (!(valid & (1u << e))) TAPS_TRY(refresh(e, nact, st));
     for (int d = 0; d < D; ++d) {
       TAPS_TRY(system(d, nact, st));
       TAPS_TRY(residual_parts(d, nact, st));

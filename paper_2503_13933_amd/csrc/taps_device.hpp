@@ -344,14 +344,21 @@ struct BalanceArgs {
   int D, M;
   int n[TAPS_MAX_DIMS];
   double* U[TAPS_MAX_DIMS];
+  // cached Grams of each dim (K x M x M) and load Grams (Rc x M), rescaled
+  // with the factors for the dims of the scale mask (batched driver)
+  int K[TAPS_MAX_DIMS], Rc[TAPS_MAX_DIMS];
+  double* gram[TAPS_MAX_DIMS];
+  double* lgram[TAPS_MAX_DIMS];
 };
 
 // Every mode m of one problem: column norms of every dim, their geometric
 // mean g, U_e[:, m] *= g / ||U_e[:, m]|| (skipped for a mode with a norm below
 // 1e-300).  Block of 256 threads as 4 row phases x 64 mode lanes, so each row
 // of a factor is read and written as one contiguous segment; the row phases
-// are summed in a fixed order.
-__device__ inline void balance(const BalanceArgs& A) {
+// are summed in a fixed order.  For the dims in scale_mask the cached Grams
+// follow the factors without being recomputed: G^k[m][n] *= f_m f_n and
+// L[c][m] *= f_m (f = the factor applied to column m).
+__device__ inline void balance(const BalanceArgs& A, unsigned scale_mask = 0) {
   __shared__ double part[4][64];
   __shared__ double fac[TAPS_MAX_DIMS][64];
   const int m = threadIdx.x & 63, ph = threadIdx.x >> 6, M = A.M;
@@ -383,6 +390,15 @@ __device__ inline void balance(const BalanceArgs& A) {
       const double f = fac[e][m];
       for (int i = ph; i < A.n[e]; i += 4) A.U[e][long(i) * M + m] *= f;
     }
+  for (int e = 0; e < A.D; ++e) {
+    if (!(scale_mask & (1u << e))) continue;
+    const int MM = M * M;
+    for (int t = threadIdx.x; t < A.K[e] * MM; t += blockDim.x) {
+      const int r = t - (t / MM) * MM, mm = r / M, nn = r - (r / M) * M;
+      A.gram[e][t] *= fac[e][mm] * fac[e][nn];
+    }
+    for (int t = threadIdx.x; t < A.Rc[e] * M; t += blockDim.x) A.lgram[e][t] *= fac[e][t - (t / M) * M];
+  }
 }
 
 }  // namespace dev
