@@ -27,10 +27,12 @@ separately from the benchmark slabs.  The plain form (one slab at a time,
 random start) and the batched form with random starts are timed under the
 same rule.
 
-The JSON line carries the roofline of the dominant kernel (the eigen stage
-of the fast diagonalisation, FP64 and latency-bound: algorithmic flops over
-its event-timed kernel time, against the FP64 peak) and the CPU oracle timed
-on a bounded sample.
+The JSON line carries the roofline of the dominant kernel (the banded stage
+of the fast diagonalisation, k_fd_solve, whose complex right-hand sides and
+U rows stream through HBM: algorithmic bytes over its event-timed kernel
+time, against the HBM peak; with the block LU, that kernel's FP64 flops
+against the FP64 peak) and the CPU oracle timed on a bounded sample.  The
+eigen stage (three latency-bound one-wave kernels) is reported beside it.
 """
 import argparse
 import json
@@ -46,11 +48,13 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix)
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
-# Memory traffic of the eigen stage (k_fd_eig) per algorithmic flop, from two
-# rocprofv3 counter runs of paper_2503_13933_amd/prof_solve.py (FETCH_SIZE x
-# 2.0 + WRITE_SIZE x 1.0, the factors read off its 1 GiB device copy), valid
-# for the solve source with this SHA-256 prefix only.
-EIG_TRAFFIC = {"bytes_per_flop": 0.03683, "source_sha256": "4eedcf6bc3a1756d"}
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+# Memory traffic of the banded stage (k_fd_solve) per algorithmic byte, from
+# two rocprofv3 counter runs of paper_2503_13933_amd/prof_solve.py
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off its 1 GiB device
+# copy, over the algorithmic bytes it prints), valid for the solve source with
+# this SHA-256 prefix only (None: not measured for the current source).
+SOLVE_TRAFFIC = {"bytes_per_alg_byte": None, "source_sha256": None}
 
 
 def log(msg):
@@ -204,7 +208,7 @@ def main():
         return el, tot_sw / (N * args.steps), last
 
     el_w, sw_w, last_w = timed(step_warm, "warm+batched", prof=True)
-    n_solve, ms_solve, fl_solve, _ = capi.taps_profile_read(h, capi.PROF_SOLVE)
+    n_solve, ms_solve, fl_solve, by_solve = capi.taps_profile_read(h, capi.PROF_SOLVE)
     n_eig, ms_eig, fl_eig, _ = capi.taps_profile_read(h, capi.PROF_EIG)
     n_con, ms_con, _, _ = capi.taps_profile_read(h, capi.PROF_CONTRACT)
     n_rec, ms_rec, fl_rec, _ = capi.taps_profile_read(h, capi.PROF_RECON)
@@ -226,11 +230,23 @@ def main():
     src = os.path.join(ROOT, "paper_2503_13933_amd", "csrc", "taps_solve.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     fd = args.solver == "fastdiag"
-    # dominant kernel: the eigen stage for the fast diagonalisation, the block LU otherwise
-    n_dom, ms_dom, fl_dom = (n_eig, ms_eig, fl_eig) if fd else (n_solve, ms_solve, fl_solve)
-    same_kernel = fd and digest == EIG_TRAFFIC["source_sha256"]
-    traffic = EIG_TRAFFIC["bytes_per_flop"] * fl_dom / n_dom if (same_kernel and n_dom) else None
-    achieved = (fl_dom / n_dom) / (ms_dom / n_dom * 1e-3) / 1e12 if n_dom else 0.0
+    # dominant kernel: the banded stage k_fd_solve (HBM) for the fast
+    # diagonalisation, the block LU (FP64) otherwise; both in the solve family
+    same_kernel = fd and SOLVE_TRAFFIC["bytes_per_alg_byte"] and digest == SOLVE_TRAFFIC["source_sha256"]
+    traffic = SOLVE_TRAFFIC["bytes_per_alg_byte"] * by_solve / n_solve if (same_kernel and n_solve) else None
+    sec = ms_solve * 1e-3 if n_solve else float("inf")
+    if fd:
+        roof = {"bound": "hbm", "kernel": "k_fd_solve (banded stage of the fast diagonalisation, one 64-lane wave "
+                                          "per system)",
+                "achieved": by_solve / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "kernel": "k_block_lu_mfma_batched (block-banded FP64 dim solve)",
+                "achieved": fl_solve / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": traffic,
+                 "traffic_unit": "bytes per launch (HBM/MALL counters, calibrated)", "launches": n_solve,
+                 "avg_launch_ms": ms_solve / max(1, n_solve),
+                 "bytes_per_launch": by_solve / max(1, n_solve), "flops_per_launch": fl_solve / max(1, n_solve)})
+    eig_tf = fl_eig / (ms_eig * 1e-3) / 1e12 if n_eig else 0.0
     rec_tf = (fl_rec / n_rec) / (ms_rec / n_rec * 1e-3) / 1e12 if n_rec else 0.0
     out = {
         "metric": "TAPS slab solves/s at rel. residual 1e-8; warm-start+batched vs plain",
@@ -262,6 +278,9 @@ def main():
             "setup_s": setup_s,
             "solve_kernel_ms_per_step": ms_solve / args.steps,
             "eig_kernel_ms_per_step": ms_eig / args.steps,
+            "eig_stage": {"kernels": "k_fd_inverse + k_fd_schur + k_fd_vectors", "launch_groups": n_eig,
+                          "avg_group_ms": ms_eig / max(1, n_eig), "fp64_tflops": eig_tf,
+                          "fp64_frac": eig_tf / FP64_PEAK_TFLOPS} if fd else None,
             "contract_kernel_ms_per_step": ms_con / args.steps,
             "recon_kernel_ms_per_step": ms_rec / args.steps,
             "recon_bf16_tflops": rec_tf,
@@ -271,20 +290,7 @@ def main():
             "plain": plain,
             "warm_batched_over_plain": (value / plain["value"]) if plain else None,
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": ("k_fd_eig (eigen stage of the fast diagonalisation, one 64-lane wave per system)" if fd
-                       else "k_block_lu_mfma_batched (block-banded FP64 dim solve)"),
-            "achieved": achieved,
-            "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": traffic,
-            "traffic_unit": "bytes per launch (HBM/MALL counters, calibrated)",
-            "launches": n_dom,
-            "avg_launch_ms": ms_dom / max(1, n_dom),
-            "flops_per_launch": fl_dom / max(1, n_dom),
-        },
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

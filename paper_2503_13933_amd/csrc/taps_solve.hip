@@ -693,18 +693,19 @@ size_t res_lds_allowed = 0;
 // Wv unit upper triangular), P = Z Wv diagonalises E, and Y = X P decouples
 // into M banded systems (A1 + l_m A2) y_m = (Q C1^{-T} P)_m; X = Re(Y P^{-1})
 // with P^{-1} = Wv^{-1} Z^H.
-//   k_fd_eig   (one wave per system): C1^{-1} by Gauss-Jordan with partial
-//              pivoting, E, Householder Hessenberg form, complex single-shift
-//              QR with Wilkinson shifts (Givens bulge chase, Z accumulated),
-//              Wv and Wv^{-1} by substitution; writes H2 = C1^{-T} Z Wv,
-//              H3 = Wv^{-1} Z^H and l to the workspace.
+//   k_fd_inverse, k_fd_schur, k_fd_vectors (one wave per system each):
+//              C1^{-1} by Gauss-Jordan with partial pivoting and E; Householder
+//              Hessenberg form and Francis double-shift QR to the real Schur
+//              form (Z accumulated); complex Schur form, Wv and Wv^{-1} by
+//              substitution; writes H2 = C1^{-T} Z Wv, H3 = Wv^{-1} Z^H and l
+//              to the workspace.
 //   k_fd_solve (one workgroup per system): R = Q H2, the M banded complex
 //              systems (one lane each; elimination without pivoting over a
 //              (w+1)-row window in LDS, U rows kept for back substitution),
 //              X = Re(Y H3).  Fixed rows are identity rows with zero right-hand
 //              side and zero columns.
 // Workspace (doubles, from A.Zst): H2 2M^2 | H3 2M^2 | l 2M | C1inv M^2 |
-// Y 2nM | U store 2 M n (w+1).
+// T M^2 | Z M^2 | Y 2nM | U store 2 M n (w+1).
 struct cplx {
   double r, i;
 };
@@ -715,6 +716,10 @@ __device__ inline cplx cmul(cplx a, cplx b) { return cplx{a.r * b.r - a.i * b.i,
 __device__ inline cplx cconj(cplx a) { return cplx{a.r, -a.i}; }
 __device__ inline cplx cscale(cplx a, double s) { return cplx{a.r * s, a.i * s}; }
 __device__ inline double cabs2(cplx a) { return hypot(a.r, a.i); }
+// a - l b in four fused multiply-adds
+__device__ inline cplx cfms(cplx a, cplx l, cplx b) {
+  return cplx{fma(-l.r, b.r, fma(l.i, b.i, a.r)), fma(-l.r, b.i, fma(-l.i, b.r, a.i))};
+}
 __device__ inline cplx cdivz(cplx a, cplx b) {
   // Smith's algorithm
   if (fabs(b.r) >= fabs(b.i)) {
@@ -736,11 +741,12 @@ constexpr int kFdMaxM = 48;
 
 // Workspace of one fast-diagonalisation solve (inside the first workspace
 // region): H2 = C1^{-T} P and H3 = P^{-1} (M x M complex), the eigenvalues
-// (M complex), C1^{-1} (M x M), the right-hand sides / solutions of the
+// (M complex), C1^{-1}, E (then the real Schur form T) and the Schur
+// vectors Z (M x M each), the right-hand sides / solutions of the
 // banded systems (n x M complex, row-major) and their U rows
 // (n x (w+1) x M complex).
 struct FdWs {
-  double *H2, *H3, *lam, *C1inv, *Y, *U;
+  double *H2, *H3, *lam, *C1inv, *T, *Zq, *Y, *U;
 };
 __device__ inline FdWs fd_ws(const SolveArgs& A) {
   const int M = A.M, MM = M * M;
@@ -749,7 +755,9 @@ __device__ inline FdWs fd_ws(const SolveArgs& A) {
   f.H3 = f.H2 + 2 * MM;
   f.lam = f.H3 + 2 * MM;
   f.C1inv = f.lam + 2 * M;
-  f.Y = f.C1inv + MM;
+  f.T = f.C1inv + MM;
+  f.Zq = f.T + MM;
+  f.Y = f.Zq + MM;
   f.U = f.Y + 2 * long(A.n) * M;
   return f;
 }
@@ -806,37 +814,59 @@ struct IjWalk {
   }
 };
 
-// Eigen stage of the fast diagonalisation for one dim system with two kinds
-// (one 64-wide wave):
-//   C1^{-1} by Gauss-Jordan with partial pivoting,
-//   E = C2^T C1^{-T} (the system becomes A1 X + A2 X E = Q C1^{-T}),
-//   Householder reduction of E to Hessenberg form, Francis double-shift QR
-//   in real arithmetic to the real Schur form (at most 40 M iterations), and
-//   unitary 2 x 2 rotations of its complex-pair blocks to the complex Schur
-//   form E = Z T Z^H,
-//   eigenvectors Wv of T (unit upper triangular), so P = Z Wv,
-//   H2 = C1^{-T} P and H3 = P^{-1} = Wv^{-1} Z^H to the workspace, with the
-//   eigenvalues.
-// LDS: six M x L real units (L = M rounded up to odd, so that column walks
-// over the lanes hit distinct banks), reused by phase:
-//   units 0-1: C2 (unit 0) | complex H (T, then Wv^{-1}, then Z Wv)
-//   units 2-3: real Hessenberg / Schur Hr, Zr | complex Wv | C1^{-1} (unit 2)
-//   units 4-5: Gauss-Jordan buffers | complex Z
-// so that two workgroups share a compute unit at M = 40; C1^{-1} waits in
-// the workspace between its two uses.
-// info word: 0, -1 (C1 singular) or -2 (no convergence).
-__device__ void fd_eig_body(const SolveArgs& A) {
+// Eigen stage of the fast diagonalisation for one dim system with two kinds,
+// in three kernels of one 64-lane wave per system (split so that the long
+// real phases hold little LDS and four systems share a compute unit):
+//   inverse: C1^{-1} by Gauss-Jordan with partial pivoting, E = C2^T C1^{-T}
+//     (the system becomes A1 X + A2 X E = Q C1^{-T}) to the workspace;
+//   schur: Householder reduction of E to Hessenberg form and Francis
+//     double-shift QR in real arithmetic to the real Schur form (at most
+//     40 M iterations), T and Z to the workspace;
+//   vectors: unitary 2 x 2 rotations of the complex-pair blocks to the
+//     complex Schur form E = Z T Z^H, eigenvectors Wv of T (unit upper
+//     triangular), so P = Z Wv; H2 = C1^{-T} P and H3 = P^{-1} = Wv^{-1} Z^H
+//     to the workspace, with the eigenvalues.
+// LDS in M x L real units (L = M rounded up to odd, so that column walks over
+// the lanes hit distinct banks): inverse 3 (two Gauss-Jordan buffers, C2),
+// schur 2 (Hr, Zr), vectors 6 (complex H, Wv, Z; C1^{-1} at the end).
+// info word: 0, -1 (C1 singular) or -2 (no convergence); a later kernel
+// skips a system whose info is set.
+// Orders the LDS accesses of one wave for the compiler.  A workgroup of one
+// wave needs no hardware barrier: its LDS accesses complete in issue order.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// sqrt(q), q > 0 and normal: the hardware reciprocal square root estimate,
+// one Goldschmidt step for sqrt(q) and 1/(2 sqrt(q)) together, then two
+// Newton corrections of the square root.
+__device__ inline double nr_sqrt(double q) {
+  const double r = __builtin_amdgcn_rsq(q);
+  double g = q * r, hh = 0.5 * r;
+  const double e = fma(-hh, g, 0.5);
+  g = fma(g, e, g);
+  hh = fma(hh, e, hh);
+  double d = fma(-g, g, q);
+  g = fma(d, hh, g);
+  d = fma(-g, g, q);
+  return fma(d, hh, g);
+}
+// 1/d, d normal: the hardware reciprocal estimate and two Newton steps.
+__device__ inline double nr_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ void fd_eig_inverse(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
-  cplx* H = reinterpret_cast<cplx*>(lds);            // units 0-1
-  double* C2s = lds;                                  // unit 0
-  double* Hr = lds + 2 * LL;                          // unit 2
-  double* Zr = lds + 3 * LL;                          // unit 3
-  cplx* Wv = reinterpret_cast<cplx*>(lds + 2 * LL);   // units 2-3
-  double* S0 = lds + 4 * LL;                          // unit 4
-  double* S1 = lds + 5 * LL;                          // unit 5
-  cplx* Z = reinterpret_cast<cplx*>(S0);              // units 4-5
-  __shared__ double v[64];                            // Householder vector
+  double* S0 = lds;                                   // unit 0
+  double* S1 = lds + LL;                              // unit 1
+  double* C2s = lds + 2 * LL;                         // unit 2
   __shared__ int perm[64];
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
@@ -848,7 +878,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       C2s[w.i * L + w.j] = A.C[MM + t];
     }
   }
-  __syncthreads();
+  wave_sync();
   // ---- C1^{-1}: Gauss-Jordan with partial pivoting (row swaps, undone as
   // column swaps at the end)
   double* cur = S0;
@@ -875,7 +905,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       cur[r * L + lane] = cur[p * L + lane];
       cur[p * L + lane] = t;
     }
-    __syncthreads();
+    wave_sync();
     if (lane < M) {   // column lane of the next iterate, rows in batches of 8
       const int j = lane;
       const double ip = 1.0 / cur[r * L + r];
@@ -902,7 +932,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
         }
       }
     }
-    __syncthreads();
+    wave_sync();
     double* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -914,14 +944,14 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       cur[lane * L + r] = cur[lane * L + p];
       cur[lane * L + p] = t;
     }
-    __syncthreads();
+    wave_sync();
   }
   const double* Ci = cur;   // C1^{-1}, kept for E and saved for H2
   {
     IjWalk w(lane, M);
     for (int t = lane; t < MM; t += 64, w.next(M)) f.C1inv[t] = Ci[w.i * L + w.j];
   }
-  // ---- E[i][j] = sum_q C2[q][i] C1inv[j][q] into Hr; Zr = I
+  // ---- E[i][j] = sum_q C2[q][i] C1inv[j][q] to the workspace
   {
     IjWalk w(lane, M);
     for (int t = lane; t < MM; t += 64, w.next(M)) {
@@ -929,11 +959,31 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       double e = 0.0;
 #pragma unroll 8
       for (int q = 0; q < M; ++q) e += C2s[q * L + i] * Ci[j * L + q];
-      Hr[i * L + j] = e;
-      Zr[i * L + j] = (i == j) ? 1.0 : 0.0;
+      f.T[t] = e;
     }
   }
-  __syncthreads();
+  if (lane == 0) A.info[0] = s_fail ? -1 : 0;
+}
+
+__device__ void fd_eig_schur(const SolveArgs& A) {
+  extern __shared__ double lds[];
+  const int M = A.M, MM = M * M, L = M | 1, lane = threadIdx.x;
+  const int LL = M * L;
+  double* Hr = lds;                                   // unit 0
+  double* Zr = lds + LL;                              // unit 1
+  __shared__ double v[64];                            // Householder vector
+  __shared__ int s_fail;
+  const FdWs f = fd_ws(A);
+  if (A.info[0] != 0) return;
+  if (lane == 0) s_fail = 0;
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      Hr[w.i * L + w.j] = f.T[t];
+      Zr[w.i * L + w.j] = (w.i == w.j) ? 1.0 : 0.0;
+    }
+  }
+  wave_sync();
   // ---- Householder Hessenberg form, Zr accumulated
   for (int k = 0; k + 2 < M; ++k) {
     const double x = (lane > k && lane < M) ? Hr[lane * L + k] : 0.0;
@@ -949,7 +999,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
     if (lane < M) v[lane] = vi;
-    __syncthreads();
+    wave_sync();
     if (lane < M) {   // left: column lane, rows k+1.. in batches of 8 (clamped rows weigh 0)
       double wsum = 0.0;
       for (int i0 = k + 1; i0 < M; i0 += 8) {
@@ -973,7 +1023,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
           if (i0 + u < M) Hr[(i0 + u) * L + lane] = hv[u] - v[i0 + u] * bw;
       }
     }
-    __syncthreads();
+    wave_sync();
     if (lane < M) {   // right: row lane, columns k+1.. (Hr and Zr) in batches of 8
       double us = 0.0, zs = 0.0;
       for (int j0 = k + 1; j0 < M; j0 += 8) {
@@ -1008,7 +1058,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
           }
       }
     }
-    __syncthreads();
+    wave_sync();
   }
   // ---- real Schur form by Francis double-shift QR (two shifts per sweep,
   // the eigenvalues of the trailing 2 x 2 block, or an exceptional pair every
@@ -1028,7 +1078,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       Hr[(k + 1) * L + lane] = h1 - w * u1;
       if (len == 3) Hr[(k + 2) * L + lane] = h2 - w * u2;
     }
-    __syncthreads();
+    wave_sync();
     double col = 0.0;
     if (lane <= r1) {
       const double h0 = Hr[lane * L + k], h1 = Hr[lane * L + k + 1];
@@ -1047,21 +1097,24 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       Zr[lane * L + k + 1] = z1 - w * u1;
       if (len == 3) Zr[lane * L + k + 2] = z2 - w * u2;
     }
-    __syncthreads();
+    wave_sync();
     return col;
   };
   // Householder vector of (x, y, z): (I - tau u u^T)(x, y, z)^T = (beta, 0, 0)^T,
   // tau = (beta - x) / beta and u = (1, y, z) / (x - beta) from one reciprocal
+  // (norm and reciprocal by Newton iterations from the hardware estimates:
+  // no range scaling, the entries are far from under- and overflow)
   auto house = [](double x, double y, double z, double& tau, double& u1, double& u2) {
-    const double nrm = sqrt(x * x + y * y + z * z);
     if (y == 0.0 && z == 0.0) {
       tau = 0.0;
       u1 = u2 = 0.0;
       return;
     }
+    const double q = x * x + y * y + z * z;
+    const double nrm = nr_sqrt(q);
     const double beta = x >= 0.0 ? -nrm : nrm;
     const double xb = x - beta;
-    const double inv = 1.0 / (beta * xb);
+    const double inv = nr_rcp(beta * xb);
     tau = -xb * xb * inv;
     const double sc = beta * inv;
     u1 = y * sc;
@@ -1083,12 +1136,12 @@ __device__ void fd_eig_body(const SolveArgs& A) {
             2.220446049250313e-16 * (fabs(Hr[lane * L + lane]) + fabs(Hr[(lane - 1) * L + lane - 1]));
     const unsigned long long bal = __ballot(neg);
     const int lo = bal ? 63 - __clzll(bal) : 0;
-    __syncthreads();
+    wave_sync();
     if (lo > 0 && lane == 0) Hr[lo * L + lo - 1] = 0.0;
     if (lo == hi) {
       --hi;
       it = 0;
-      __syncthreads();
+      wave_sync();
       continue;
     }
     if (lo == hi - 1) {
@@ -1096,7 +1149,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       const double a = Hr[(hi - 1) * L + hi - 1], b = Hr[(hi - 1) * L + hi], c = Hr[hi * L + hi - 1],
                    d = Hr[hi * L + hi];
       const double p = 0.5 * (a - d), disc = p * p + b * c;
-      __syncthreads();
+      wave_sync();
       if (disc >= 0.0) {
         const double sq = sqrt(disc);
         const double lam = 0.5 * (a + d) + (p >= 0.0 ? sq : -sq);
@@ -1115,7 +1168,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
             Hr[k * L + lane] = cs * h0 + sn * h1;
             Hr[(k + 1) * L + lane] = cs * h1 - sn * h0;
           }
-          __syncthreads();
+          wave_sync();
           if (lane <= hi) {
             const double h0 = Hr[lane * L + k], h1 = Hr[lane * L + k + 1];
             Hr[lane * L + k] = cs * h0 + sn * h1;
@@ -1126,13 +1179,13 @@ __device__ void fd_eig_body(const SolveArgs& A) {
             Zr[lane * L + k] = cs * z0 + sn * z1;
             Zr[lane * L + k + 1] = cs * z1 - sn * z0;
           }
-          __syncthreads();
+          wave_sync();
           if (lane == 0) Hr[hi * L + hi - 1] = 0.0;
         }
       }
       hi -= 2;
       it = 0;
-      __syncthreads();
+      wave_sync();
       continue;
     }
     ++it;
@@ -1159,10 +1212,45 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     // after the reflector at k, the next bulge column (rows k+1..k+3 of
     // column k) sits in registers of lanes k+1..k+3
     for (int k = lo; k + 1 < hi; ++k) {
+      // One step of the chase: the reflector acts on rows k..k+2 (one column
+      // per lane) and then on columns k..k+2 (rows 0..r1 of Hr and all rows
+      // of Zr, one row per lane).  The row operands and Zr are read before
+      // the reflector is known, so those loads overlap its computation; the
+      // column operands are read after the row pass has stored (one wave:
+      // its LDS accesses complete in issue order), and the Zr pass fills that
+      // wait.  Loads run on every lane (lanes past M on row / column M - 1);
+      // only stores are masked (row pass: columns c0..M-1).
+      const int c0 = max(lo, k - 1), r1 = min(k + 3, hi);
+      const int lm = min(lane, M - 1);
+      const double a0 = Hr[k * L + lm], a1 = Hr[(k + 1) * L + lm], a2 = Hr[(k + 2) * L + lm];
+      const double z0 = Zr[lm * L + k], z1 = Zr[lm * L + k + 1], z2 = Zr[lm * L + k + 2];
       double tau, u1, u2;
       house(x, y, z, tau, u1, u2);
       if (tau != 0.0) {
-        const double col = reflect(k, 3, tau, u1, u2, max(lo, k - 1), min(k + 3, hi));
+        {
+          const double w = tau * (a0 + u1 * a1 + u2 * a2);
+          if (lane >= c0 && lane < M) {
+            Hr[k * L + lane] = a0 - w;
+            Hr[(k + 1) * L + lane] = a1 - w * u1;
+            Hr[(k + 2) * L + lane] = a2 - w * u2;
+          }
+        }
+        const double h0 = Hr[lm * L + k], h1 = Hr[lm * L + k + 1], h2 = Hr[lm * L + k + 2];
+        {
+          const double w = tau * (z0 + u1 * z1 + u2 * z2);
+          if (lane < M) {
+            Zr[lane * L + k] = z0 - w;
+            Zr[lane * L + k + 1] = z1 - w * u1;
+            Zr[lane * L + k + 2] = z2 - w * u2;
+          }
+        }
+        const double w = tau * (h0 + u1 * h1 + u2 * h2);
+        const double col = h0 - w;
+        if (lane <= r1) {
+          Hr[lane * L + k] = col;
+          Hr[lane * L + k + 1] = h1 - w * u1;
+          Hr[lane * L + k + 2] = h2 - w * u2;
+        }
         x = from_lane(col, k + 1);
         y = from_lane(col, k + 2);
         z = (k + 3 <= hi) ? from_lane(col, k + 3) : 0.0;
@@ -1171,28 +1259,47 @@ __device__ void fd_eig_body(const SolveArgs& A) {
         y = Hr[(k + 2) * L + k];
         z = (k + 3 <= hi) ? Hr[(k + 3) * L + k] : 0.0;
       }
+      wave_sync();
     }
     {
       const int k = hi - 1;
       double tau, u1, u2;
       house(x, y, 0.0, tau, u1, u2);
-      __syncthreads();
+      wave_sync();
       if (tau != 0.0) reflect(k, 2, tau, u1, 0.0, max(lo, k - 1), hi);
     }
   }
   if (hi >= 0 && lane == 0) s_fail = 2;
-  __syncthreads();
+  wave_sync();
+  {
+    IjWalk w(lane, M);
+    for (int t = lane; t < MM; t += 64, w.next(M)) {
+      f.T[t] = (w.i > w.j + 1) ? 0.0 : Hr[w.i * L + w.j];   // rounding residue below the subdiagonal dropped
+      f.Zq[t] = Zr[w.i * L + w.j];
+    }
+  }
+  if (lane == 0 && s_fail) A.info[0] = -2;
+}
+
+__device__ void fd_eig_vectors(const SolveArgs& A) {
+  extern __shared__ double lds[];
+  const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
+  cplx* H = reinterpret_cast<cplx*>(lds);            // units 0-1
+  cplx* Wv = reinterpret_cast<cplx*>(lds + 2 * LL);   // units 2-3
+  cplx* Z = reinterpret_cast<cplx*>(lds + 4 * LL);    // units 4-5
+  const FdWs f = fd_ws(A);
+  if (A.info[0] != 0) return;
   // ---- complex Schur form: H = Hr, Z = Zr, then each remaining 2 x 2 block
   // (complex eigenvalue pair) is triangularised by a unitary rotation whose
   // first column is the block's eigenvector for mu
   {
     IjWalk w(lane, M);
     for (int t = lane; t < MM; t += 64, w.next(M)) {
-      H[w.i * L + w.j] = cmk(Hr[w.i * L + w.j], 0.0);
-      Z[w.i * L + w.j] = cmk(Zr[w.i * L + w.j], 0.0);
+      H[w.i * L + w.j] = cmk(f.T[t], 0.0);
+      Z[w.i * L + w.j] = cmk(f.Zq[t], 0.0);
     }
   }
-  __syncthreads();
+  wave_sync();
   for (int k = 0; k + 1 < M; ++k) {
     const cplx c = H[(k + 1) * L + k];
     if (c.r == 0.0 && c.i == 0.0) continue;
@@ -1207,13 +1314,13 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     }
     const double en = rsqrt(e0.r * e0.r + e0.i * e0.i + e1.r * e1.r + e1.i * e1.i);
     const cplx g0 = cscale(e0, en), g1 = cscale(e1, en);   // G = [g0 -conj(g1); g1 conj(g0)]
-    __syncthreads();
+    wave_sync();
     if (lane >= k && lane < M) {   // rows k, k+1 <- G^H rows
       const cplx h0 = H[k * L + lane], h1 = H[(k + 1) * L + lane];
       H[k * L + lane] = cadd(cmul(cconj(g0), h0), cmul(cconj(g1), h1));
       H[(k + 1) * L + lane] = csub(cmul(g0, h1), cmul(g1, h0));
     }
-    __syncthreads();
+    wave_sync();
     if (lane <= k + 1) {           // columns k, k+1 <- columns G
       const cplx h0 = H[lane * L + k], h1 = H[lane * L + k + 1];
       H[lane * L + k] = cadd(cmul(h0, g0), cmul(h1, g1));
@@ -1224,9 +1331,9 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       Z[lane * L + k] = cadd(cmul(z0, g0), cmul(z1, g1));
       Z[lane * L + k + 1] = csub(cmul(z1, cconj(g0)), cmul(z0, cconj(g1)));
     }
-    __syncthreads();
+    wave_sync();
     if (lane == 0) H[(k + 1) * L + k] = cmk(0.0, 0.0);
-    __syncthreads();
+    wave_sync();
     ++k;   // the next subdiagonal entry is zero
   }
   // ---- eigenvectors Wv of T (unit upper triangular), one column per lane
@@ -1247,7 +1354,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
     f.lam[2 * k] = tk.r;
     f.lam[2 * k + 1] = tk.i;
   }
-  __syncthreads();
+  wave_sync();
   // ---- Winv = Wv^{-1} (unit upper triangular) into H (T no longer needed)
   if (lane < M) {
     const int j = lane;
@@ -1258,7 +1365,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       H[i * L + j] = cscale(sacc, -1.0);
     }
   }
-  __syncthreads();
+  wave_sync();
   // ---- H3 = Winv Z^H  (H3[m][q] = sum_j Winv[m][j] conj(Z[q][j]))
   {
     IjWalk w(lane, M);
@@ -1270,7 +1377,7 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       f.H3[2 * t + 1] = sacc.i;
     }
   }
-  __syncthreads();
+  wave_sync();
   // ---- ZW = Z Wv into H, then H2 = C1inv^T ZW (H2[q][m] = sum_j C1inv[j][q] ZW[j][m])
   {
     IjWalk w(lane, M);
@@ -1281,13 +1388,13 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       H[i * L + m] = sacc;
     }
   }
-  __syncthreads();
+  wave_sync();
   double* Ci2 = lds + 2 * LL;   // C1^{-1} back from the workspace (Wv is dead)
   {
     IjWalk w(lane, M);
     for (int t = lane; t < MM; t += 64, w.next(M)) Ci2[w.i * L + w.j] = f.C1inv[t];
   }
-  __syncthreads();
+  wave_sync();
   {
     IjWalk w(lane, M);
     for (int t = lane; t < MM; t += 64, w.next(M)) {
@@ -1298,28 +1405,26 @@ __device__ void fd_eig_body(const SolveArgs& A) {
       f.H2[2 * t + 1] = sacc.i;
     }
   }
-  if (lane == 0) A.info[0] = s_fail ? -s_fail : 0;
 }
 
 constexpr int kFdThreads = 64;   // one wave: transforms, staging and elimination
 
 // Banded complex solves (A1 + lambda_m A2) y_m = r_m of the fast
-// diagonalisation with the elimination window in registers: lane m of wave 0
-// owns system m and keeps rows k..k+w, columns k..k+w of its partly reduced
-// matrix (a (w+1)^2 ring indexed by row and column modulo w+1, so the
-// unrolled steps address it statically) plus the right-hand sides of those
-// rows.  Band rows (A1, A2 pairs, shared by the M systems) are staged into a
-// three-chunk LDS ring by waves 1..3 while wave 0 eliminates; the right-hand
-// side entering at step k is loaded w+1 steps ahead.  Each step stores the
-// reciprocal pivot and the w upper entries of row k (the U row, layout
-// [row][entry][system] so stores and loads are coalesced over systems) and
-// the reduced right-hand side; back substitution walks the rows upwards with
-// the U rows loaded a few rows ahead.  Rows beyond n are identity rows, so
-// the last steps need no guards.  No pivoting: a zero pivot sets the info word.
-// One 64-lane wave per system set: the elimination is bound by its own
-// instruction stream, so one wave per SIMD is the useful occupancy; the wave
-// stages the band itself, loading chunk c+2 into registers before
-// eliminating chunk c and storing it to LDS after.
+// diagonalisation with the elimination window in registers: lane m owns
+// system m and keeps rows k..k+w, columns k..k+w of its partly reduced matrix
+// (a (w+1)^2 ring indexed by row and column modulo w+1, so the unrolled steps
+// address it statically) plus the right-hand sides of those rows.  Band rows
+// (A1, A2 pairs, shared by the M systems) go through a three-chunk LDS ring:
+// the wave loads chunk c+2 into registers before eliminating chunk c and
+// stores it to LDS after.  The right-hand side entering at step k is loaded
+// w+1 steps ahead.  Each step stores row k divided by its pivot: the w upper
+// entries (the U row, layout [row][entry][system] so stores and loads are
+// coalesced over systems) and the reduced right-hand side; back substitution
+// walks the rows upwards with the U rows loaded a few rows ahead and needs no
+// division.  Rows beyond n are identity rows, so the last steps need no
+// guards.  No pivoting: a zero pivot sets the info word.  One 64-lane wave
+// per system set: the elimination is bound by its own instruction stream and
+// the U stores, so one wave per SIMD is the useful occupancy.
 template <int W>
 __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLam, double2* ring, int* s_info) {
   constexpr int W1 = W + 1, BW = 2 * W + 1, CH = W1 * (32 / W1);
@@ -1393,7 +1498,7 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
             const cplx piv = win[p][p];
             const double d = piv.r * piv.r + piv.i * piv.i;
             if (!(d > 0.0) || !(d < INFINITY)) info = info ? info : k + 1;
-            const cplx inv = cscale(cconj(piv), 1.0 / d);
+            const cplx inv = cscale(cconj(piv), nr_rcp(d));
 #pragma unroll
             for (int r = 1; r < W1; ++r) {
               const int rs = (p + r) % W1;
@@ -1401,15 +1506,16 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
 #pragma unroll
               for (int cc = 1; cc < W1; ++cc) {
                 const int cs = (p + cc) % W1;
-                win[rs][cs] = csub(win[rs][cs], cmul(l, win[p][cs]));
+                win[rs][cs] = cfms(win[rs][cs], l, win[p][cs]);
               }
-              rhs[rs] = csub(rhs[rs], cmul(l, rhs[p]));
+              rhs[rs] = cfms(rhs[rs], l, rhs[p]);
             }
-            cplx* u = Ug + long(k) * W1 * M + m;
-            u[0] = inv;
+            // row k divided by its pivot: the w upper entries and the
+            // reduced right-hand side
+            cplx* u = Ug + long(k) * W * M + m;
 #pragma unroll
-            for (int cc = 1; cc < W1; ++cc) u[long(cc) * M] = win[p][(p + cc) % W1];
-            Yg[long(k) * M + m] = rhs[p];
+            for (int cc = 1; cc < W1; ++cc) u[long(cc - 1) * M] = cmul(inv, win[p][(p + cc) % W1]);
+            Yg[long(k) * M + m] = cmul(inv, rhs[p]);
             // slot p now takes row k + W1 (columns k+1 .. k+W1) and column
             // k + W1 (rows k+1 .. k+W)
             const int i = k + W1;
@@ -1427,14 +1533,15 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
     __syncthreads();
   }
   if (act && info) atomicCAS(s_info, 0, info);
-  // ---- back substitution: y_k = inv_k (yhat_k - sum_c U[k][c] y_{k+c});
+  // ---- back substitution: y_k = yhat_k - sum_c U[k][c] y_{k+c} (row k
+  // already divided by its pivot);
   // the U rows and reduced right-hand sides are loaded PF rows ahead (a ring
   // of PF row buffers, PF dividing w+1, so slots stay static in the unrolled
   // groups)
   if (act) {
     constexpr int PF = W1 / 2 > 0 ? W1 / 2 : 1;
     static_assert(W1 % PF == 0, "prefetch ring must divide the group");
-    cplx ub[PF][W1], yh[PF], yw[W1];
+    cplx ub[PF][W], yh[PF], yw[W1];
 #pragma unroll
     for (int p = 0; p < W1; ++p) yw[p] = cmk(0.0, 0.0);
 #pragma unroll
@@ -1445,7 +1552,7 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
         for (int q = 0; q < PF; ++q)
           if (k % PF == q) {
 #pragma unroll
-            for (int cc = 0; cc < W1; ++cc) ub[q][cc] = Ug[(long(k) * W1 + cc) * M + m];
+            for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k) * W + cc) * M + m];
             yh[q] = Yg[long(k) * M + m];
           }
       }
@@ -1459,13 +1566,13 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
           const int q = p % PF;
           cplx acc = yh[q];
 #pragma unroll
-          for (int cc = 1; cc < W1; ++cc) acc = csub(acc, cmul(ub[q][cc], yw[(p + cc) % W1]));
-          const cplx y = cmul(acc, ub[q][0]);
+          for (int cc = 1; cc < W1; ++cc) acc = cfms(acc, ub[q][cc - 1], yw[(p + cc) % W1]);
+          const cplx y = acc;
           yw[p] = y;
           Yg[long(k) * M + m] = y;
           if (k - PF >= 0) {
 #pragma unroll
-            for (int cc = 0; cc < W1; ++cc) ub[q][cc] = Ug[(long(k - PF) * W1 + cc) * M + m];
+            for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k - PF) * W + cc) * M + m];
             yh[q] = Yg[long(k - PF) * M + m];
           }
         }
@@ -1610,19 +1717,34 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   if (tid == 0 && s_info) A.info[0] = s_info;
 }
 
-__global__ __launch_bounds__(64) void k_fd_eig(const SolveArgs* __restrict__ args, const int* __restrict__ active) {
+__global__ __launch_bounds__(64) void k_fd_inverse(const SolveArgs* __restrict__ args,
+                                                   const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
-  fd_eig_body(A);
+  fd_eig_inverse(A);
+}
+__global__ __launch_bounds__(64) void k_fd_schur(const SolveArgs* __restrict__ args, const int* __restrict__ active) {
+  const SolveArgs A = args[active[blockIdx.x]];
+  fd_eig_schur(A);
+}
+__global__ __launch_bounds__(64) void k_fd_vectors(const SolveArgs* __restrict__ args,
+                                                   const int* __restrict__ active) {
+  const SolveArgs A = args[active[blockIdx.x]];
+  fd_eig_vectors(A);
 }
 __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve(const SolveArgs* __restrict__ args,
                                                          const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
   fd_solve_body(A);
 }
-__global__ __launch_bounds__(64) void k_fd_eig_one(SolveArgs A) { fd_eig_body(A); }
+__global__ __launch_bounds__(64) void k_fd_inverse_one(SolveArgs A) { fd_eig_inverse(A); }
+__global__ __launch_bounds__(64) void k_fd_schur_one(SolveArgs A) { fd_eig_schur(A); }
+__global__ __launch_bounds__(64) void k_fd_vectors_one(SolveArgs A) { fd_eig_vectors(A); }
 __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { fd_solve_body(A); }
 
-size_t fd_eig_lds(int M) { return size_t(6) * M * (M | 1) * 8; }
+// dynamic LDS of the three eigen-stage kernels, in M x L real units
+size_t fd_inverse_lds(int M) { return size_t(3) * M * (M | 1) * 8; }
+size_t fd_schur_lds(int M) { return size_t(2) * M * (M | 1) * 8; }
+size_t fd_vectors_lds(int M) { return size_t(6) * M * (M | 1) * 8; }
 size_t fd_solve_lds(int M, int s) {
   const int w = 2 * s + 1;
   const bool reg = (w == 1 || w == 3 || w == 5);
@@ -1630,10 +1752,12 @@ size_t fd_solve_lds(int M, int s) {
   const size_t ring = size_t(3) * ((w + 1) * (32 / (w + 1))) * (2 * w + 1);   // staged band chunks
   return (size_t(M) + std::max(size_t(M) * M, reg ? ring : rows)) * 16;
 }
-size_t fd_eig_allowed = 0, fd_solve_allowed = 0, fd_eig1_allowed = 0, fd_solve1_allowed = 0;
+size_t fd_inverse_allowed = 0, fd_schur_allowed = 0, fd_vectors_allowed = 0, fd_solve_allowed = 0;
+size_t fd_inverse1_allowed = 0, fd_schur1_allowed = 0, fd_vectors1_allowed = 0, fd_solve1_allowed = 0;
 
 bool fd_supported(int M, int s, int K) {
-  return K == 2 && M <= kFdMaxM && fd_eig_lds(M) <= 160 * 1024 - 2048 && fd_solve_lds(M, s) <= 160 * 1024 - 2048;
+  return K == 2 && M <= kFdMaxM && fd_vectors_lds(M) <= 160 * 1024 - 2048 &&
+         fd_solve_lds(M, s) <= 160 * 1024 - 2048;
 }
 
 // Algorithmic work of the fast diagonalisation's two stages.  Eigen stage
@@ -1652,7 +1776,7 @@ double fd_flops(int n, int M, int w) {
 // the transforms, and the complex right-hand sides written and read back plus
 // the U rows.
 double fd_bytes(int n, int M, int w) {
-  return 8.0 * (2.0 * n * (2 * w + 1) + 2.0 * n * M) + 16.0 * (2.0 * M * M + 2.0 * n * M + 2.0 * n * M * (w + 1));
+  return 8.0 * (2.0 * n * (2 * w + 1) + 2.0 * n * M) + 16.0 * (2.0 * M * M + 2.0 * n * M + 2.0 * n * M * w);
 }
 
 }  // namespace
@@ -1711,7 +1835,7 @@ size_t solve_lds_bytes(int M, int s) {
 // the fast diagonalisation's transforms, eigenvalues, C1^{-1}, complex
 // right-hand sides and banded U rows, whichever is larger.
 size_t fd_doubles(int n, int M, int s) {
-  return size_t(5) * M * M + 2 * size_t(M) + 2 * size_t(n) * M * (2 * s + 3);
+  return size_t(7) * M * M + 2 * size_t(M) + 2 * size_t(n) * M * (2 * s + 3);
 }
 
 size_t zst_doubles(int n, int M, int s) {
@@ -1753,11 +1877,17 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
   A.info = d_info;
   size_t slot;
   if (use_fd) {
-    TAPS_TRY(allow_lds(h, k_fd_eig_one, fd_eig_lds(M), &fd_eig1_allowed));
+    TAPS_TRY(allow_lds(h, k_fd_inverse_one, fd_inverse_lds(M), &fd_inverse1_allowed));
+    TAPS_TRY(allow_lds(h, k_fd_schur_one, fd_schur_lds(M), &fd_schur1_allowed));
+    TAPS_TRY(allow_lds(h, k_fd_vectors_one, fd_vectors_lds(M), &fd_vectors1_allowed));
     TAPS_TRY(allow_lds(h, k_fd_solve_one, fd_solve_lds(M, s), &fd_solve1_allowed));
     TAPS_TRY(prof_begin(h, TAPS_PROF_EIG, stream, &slot));
-    k_fd_eig_one<<<1, 64, fd_eig_lds(M), stream>>>(A);
-    TAPS_LAUNCHED(h, "k_fd_eig");
+    k_fd_inverse_one<<<1, 64, fd_inverse_lds(M), stream>>>(A);
+    TAPS_LAUNCHED(h, "k_fd_inverse");
+    k_fd_schur_one<<<1, 64, fd_schur_lds(M), stream>>>(A);
+    TAPS_LAUNCHED(h, "k_fd_schur");
+    k_fd_vectors_one<<<1, 64, fd_vectors_lds(M), stream>>>(A);
+    TAPS_LAUNCHED(h, "k_fd_vectors");
     TAPS_TRY(prof_end(h, slot, fd_eig_flops(M), fd_eig_bytes(M), stream));
     TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
     k_fd_solve_one<<<1, kFdThreads, fd_solve_lds(M, s), stream>>>(A);
@@ -1836,7 +1966,9 @@ double solve_fd_flops(int n, int M, int s) { return fd_flops(n, M, 2 * s + 1); }
 double solve_fd_bytes(int n, int M, int s) { return fd_bytes(n, M, 2 * s + 1); }
 
 taps_status fd_prepare(taps_handle* h, int M, int s) {
-  TAPS_TRY(allow_lds(h, k_fd_eig, fd_eig_lds(M), &fd_eig_allowed));
+  TAPS_TRY(allow_lds(h, k_fd_inverse, fd_inverse_lds(M), &fd_inverse_allowed));
+  TAPS_TRY(allow_lds(h, k_fd_schur, fd_schur_lds(M), &fd_schur_allowed));
+  TAPS_TRY(allow_lds(h, k_fd_vectors, fd_vectors_lds(M), &fd_vectors_allowed));
   return allow_lds(h, k_fd_solve, fd_solve_lds(M, s), &fd_solve_allowed);
 }
 
@@ -1845,8 +1977,12 @@ taps_status fd_batched_launch(taps_handle* h, int n_active, const void* d_args, 
   size_t slot;
   TAPS_TRY(prof_begin(h, TAPS_PROF_EIG, stream, &slot));
   const SolveArgs* args = static_cast<const SolveArgs*>(d_args);
-  k_fd_eig<<<n_active, 64, fd_eig_lds(M), stream>>>(args, d_active);
-  TAPS_LAUNCHED(h, "k_fd_eig");
+  k_fd_inverse<<<n_active, 64, fd_inverse_lds(M), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_inverse");
+  k_fd_schur<<<n_active, 64, fd_schur_lds(M), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_schur");
+  k_fd_vectors<<<n_active, 64, fd_vectors_lds(M), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_vectors");
   TAPS_TRY(prof_end(h, slot, n_active * fd_eig_flops(M), n_active * fd_eig_bytes(M), stream));
   TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
   k_fd_solve<<<n_active, kFdThreads, fd_solve_lds(M, s), stream>>>(args, d_active);

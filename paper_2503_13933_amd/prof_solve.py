@@ -2,7 +2,9 @@
 --slabs heat slabs (512 x 512 x 128 x 257, M = 40 by default) with the fast
 diagonalisation (--solver fastdiag, the default) or the block LU, followed by
 a plain device copy of --copy-mib MiB (torch's copy kernel) whose known size
-calibrates the memory counters.  Meant to run under rocprofv3:
+calibrates the memory counters.  Prints the launches, event-timed kernel time
+and algorithmic flops and bytes of the solve, eigen and contraction kernel
+families over the sweep.  Meant to run under rocprofv3:
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- \\
         python3 paper_2503_13933_amd/prof_solve.py
@@ -36,8 +38,14 @@ def main():
     U = [p.factors(W.initial_factors(c.axes, args.M, c.seed)) for p, c in zip(probs, cases)]
     torch.cuda.synchronize()
     print(f"batched sweep ({args.solver}): {args.slabs} slabs {[a.n for a in cases[0].axes]} M={args.M}", flush=True)
+    capi.taps_profile_enable(h, True)
     sw, rho = capi.taps_als_batched(h, [p.struct for p in probs], U, 0.0, args.sweeps)
     torch.cuda.synchronize()
+    capi.taps_profile_enable(h, False)
+    for name, fam in (("solve", capi.PROF_SOLVE), ("eig", capi.PROF_EIG), ("contract", capi.PROF_CONTRACT)):
+        n_l, ms, fl, by = capi.taps_profile_read(h, fam)
+        print(f"family {name}: launches {n_l} kernel ms {ms:.3f} algorithmic flops {fl:.6e} bytes {by:.6e}",
+              flush=True)
     n = args.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
