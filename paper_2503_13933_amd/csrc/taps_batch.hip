@@ -136,9 +136,17 @@ __global__ __launch_bounds__(256) void kb_balance(const BalanceArgs* __restrict_
 
 size_t gram_lds_allowed = 0, res_lds_allowed = 0;
 
+// grid sizes per dim (maxima over the batch; blocks past a problem's own
+// extent return at once)
 struct Sizes {
-  int max_chunks = 1, max_ctiles = 1, max_splits = 1, max_gram = 1, max_lgram = 1, max_rblocks = 1;
-  int max_cpl = 1, max_wt = 1, max_rchunks = 1, max_terms = 1;
+  int chunks[TAPS_MAX_DIMS], ctiles[TAPS_MAX_DIMS], splits[TAPS_MAX_DIMS], gram[TAPS_MAX_DIMS];
+  int lgram[TAPS_MAX_DIMS], rblocks[TAPS_MAX_DIMS], cpl[TAPS_MAX_DIMS], wt[TAPS_MAX_DIMS];
+  int rchunks[TAPS_MAX_DIMS];
+  int max_terms = 1;
+  Sizes() {
+    for (int d = 0; d < TAPS_MAX_DIMS; ++d)
+      chunks[d] = ctiles[d] = splits[d] = gram[d] = lgram[d] = rblocks[d] = cpl[d] = wt[d] = rchunks[d] = 1;
+  }
 };
 
 }  // namespace
@@ -201,15 +209,15 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       Z.max_terms = std::max(Z.max_terms, cdiv(long(p.R) * M, 256));
       bp[b].roff[d] = tot;
       tot += cdiv(p.n[d], kResRows);
-      Z.max_chunks = std::max(Z.max_chunks, ch);
-      Z.max_ctiles = std::max(Z.max_ctiles, ct);
-      Z.max_splits = std::max(Z.max_splits, sp);
-      Z.max_gram = std::max(Z.max_gram, cdiv(long(p.n_kinds[d]) * MM, 256));
-      Z.max_lgram = std::max(Z.max_lgram, cdiv(long(p.R_cols[d]) * M, 256));
-      Z.max_rblocks = std::max(Z.max_rblocks, cdiv(p.n[d], kQRows));
-      Z.max_cpl = std::max(Z.max_cpl, cdiv(long(p.n_kinds[d]) * MM, 256));
-      Z.max_wt = std::max(Z.max_wt, cdiv(long(p.R_cols[d]) * M, 256));
-      Z.max_rchunks = std::max(Z.max_rchunks, cdiv(p.n[d], kResRows));
+      Z.chunks[d] = std::max(Z.chunks[d], ch);
+      Z.ctiles[d] = std::max(Z.ctiles[d], ct);
+      Z.splits[d] = std::max(Z.splits[d], sp);
+      Z.gram[d] = std::max(Z.gram[d], cdiv(long(p.n_kinds[d]) * MM, 256));
+      Z.lgram[d] = std::max(Z.lgram[d], cdiv(long(p.R_cols[d]) * M, 256));
+      Z.rblocks[d] = std::max(Z.rblocks[d], cdiv(p.n[d], kQRows));
+      Z.cpl[d] = std::max(Z.cpl[d], cdiv(long(p.n_kinds[d]) * MM, 256));
+      Z.wt[d] = std::max(Z.wt[d], cdiv(long(p.R_cols[d]) * M, 256));
+      Z.rchunks[d] = std::max(Z.rchunks[d], cdiv(p.n[d], kResRows));
     }
     o_cache[b] = bump.take(cache_total(&p));
     o_C[b] = bump.take(size_t(Kmax) * MM * 8);
@@ -330,13 +338,13 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto refresh = [&](int e, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_gram_partial<<<dim3(Z.max_chunks, nact), 256, glds, st>>>(d_prob, d_active, e);
+    kb_gram_partial<<<dim3(Z.chunks[e], nact), 256, glds, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_partial");
-    kb_gram_sum<<<dim3(Z.max_gram, nact), 256, 0, st>>>(d_prob, d_active, e);
+    kb_gram_sum<<<dim3(Z.gram[e], nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_sum");
-    kb_lgram_partial<<<dim3(Z.max_ctiles, Z.max_splits, nact), 256, 0, st>>>(d_prob, d_active, e);
+    kb_lgram_partial<<<dim3(Z.ctiles[e], Z.splits[e], nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_lgram_partial");
-    kb_lgram_sum<<<dim3(Z.max_lgram, nact), 256, 0, st>>>(d_prob, d_active, e);
+    kb_lgram_sum<<<dim3(Z.lgram[e], nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_lgram_sum");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -350,13 +358,13 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto system = [&](int d, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_couple<<<dim3(Z.max_cpl, nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
+    kb_couple<<<dim3(Z.cpl[d], nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_couple");
     kb_load_terms<<<dim3(Z.max_terms, nact), 256, 0, st>>>(d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_terms");
-    kb_load_weights<<<dim3(Z.max_wt, nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
+    kb_load_weights<<<dim3(Z.wt[d], nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_weights");
-    kb_force<<<dim3(Z.max_rblocks, nact), 256, 0, st>>>(d_prob, d_active, d);
+    kb_force<<<dim3(Z.rblocks[d], nact), 256, 0, st>>>(d_prob, d_active, d);
     TAPS_LAUNCHED(h, "kb_force");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -368,7 +376,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return prof_end(h, slot, fl, by, st);
   };
   auto residual_parts = [&](int d, int nact, hipStream_t st) -> taps_status {
-    kb_residual_part<<<dim3(Z.max_rchunks, nact), 256, rlds, st>>>(d_prob, d_active, d);
+    kb_residual_part<<<dim3(Z.rchunks[d], nact), 256, rlds, st>>>(d_prob, d_active, d);
     TAPS_LAUNCHED(h, "kb_residual_part");
     return TAPS_OK;
   };
@@ -423,9 +431,13 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   }
   auto graph_for = [&](int nact, int k) -> taps_status {
     std::vector<int64_t> sig = {int64_t(reinterpret_cast<intptr_t>(base)), B, D, M, nact, k, int64_t(glds),
-                                int64_t(rlds), Z.max_chunks, Z.max_ctiles, Z.max_splits, Z.max_gram, Z.max_lgram,
-                                Z.max_rblocks, Z.max_cpl, Z.max_wt, Z.max_rchunks};
-    for (int d = 0; d < D; ++d) sig.push_back(p0.s[d] * 2 + use_fd[d]);
+                                int64_t(rlds), Z.max_terms};
+    for (int d = 0; d < D; ++d) {
+      sig.push_back(p0.s[d] * 2 + use_fd[d]);
+      for (int v : {Z.chunks[d], Z.ctiles[d], Z.splits[d], Z.gram[d], Z.lgram[d], Z.rblocks[d], Z.cpl[d], Z.wt[d],
+                    Z.rchunks[d]})
+        sig.push_back(v);
+    }
     if (h->graph_exec && sig == h->graph_sig) return TAPS_OK;
     if (h->graph_exec) {
       TAPS_HIP(h, hipGraphExecDestroy(h->graph_exec));

@@ -15,7 +15,9 @@ constexpr int kLgRows = 256;    // rows per load-Gram split
 constexpr int kQRows = 64;      // rows of Q per force block
 constexpr int kResRows = 64;    // rows per residual partial block
 
-inline int gram_lds_doubles(int M, int s) { return (2 * kGramRows + 2 * (2 * s + 1)) * (M | 1); }
+inline int gram_lds_doubles(int M, int s) {
+  return (2 * kGramRows + 2 * (2 * s + 1)) * (M | 1) + kGramRows * (2 * (2 * s + 1) + 1);
+}
 
 // v_mfma_f64_16x16x4f64 operands of lane l: A[l%16][l/16], B[l/16][l%16];
 // result D[l/16 + 4j][l%16], j = 0..3.
@@ -25,50 +27,86 @@ __device__ inline rv4d mfma_f64(double a, double b, rv4d c) {
 }
 inline int residual_lds_doubles(int M, int s) { return (kResRows + 2 * (2 * s + 1) + M) * (M | 1); }
 
+// V = A^k U on 16 chunk rows i0.. (i0 wave-uniform), one column per lane:
+// the column's 15 + BW halo values sit in registers and each output takes
+// BW of them (a sliding window); the band coefficients (sB, the chunk's band
+// rows) are the same for every lane.  Rows past the chunk's end give zero.
+template <int BW>
+__device__ inline void band_rows16(const double* sB, int i0, int rows, const double* sU, double* sV, int L, int M,
+                                   int lane) {
+  constexpr int R = 16;
+  for (int c = lane; c < M; c += 64) {
+    double u[R + BW - 1];
+#pragma unroll
+    for (int t = 0; t < R + BW - 1; ++t) u[t] = sU[(i0 + t) * L + c];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double v = 0.0;
+      if (i0 + i < rows) {
+#pragma unroll
+        for (int o = 0; o < BW; ++o) v = fma(sB[(i0 + i) * BW + o], u[i + o], v);
+      }
+      sV[(i0 + i) * L + c] = v;
+    }
+  }
+}
+
 // Partial of G^k = U^T A^k U over rows [chunk*kGramRows, +kGramRows): the
-// chunk of U plus a halo of w rows goes to LDS, V = A^k U on the chunk rows
-// (vector FMAs), then U_chunk^T V on the matrix cores, the rows of the chunk
-// being the contracted index (16 steps of 4); the 16 x 16 tiles of the M x M
-// result are dealt to the 4 waves.  part: K x M x M for this chunk.
-__device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const double* __restrict__ band,
-                                    const double* __restrict__ U, double* __restrict__ part) {
+// chunk of U plus a halo of w rows goes to LDS (rows over the waves, columns
+// over the lanes) and the chunk's band rows of kind k after it, V = A^k U on
+// the chunk rows (16 rows per wave, see band_rows16), then U_chunk^T V on the
+// matrix cores, the rows of the chunk
+// being the contracted index (16 steps of 4, operands of four steps loaded
+// together); the 16 x 16 tiles of the M x M result are dealt to the 4 waves.
+// Operand rows and columns past M read neighbouring LDS entries and only
+// reach result entries past M, which are not stored.
+// part: K x M x M for this chunk.
+__device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const double* __restrict__ band_,
+                                    const double* __restrict__ U_, double* __restrict__ part_) {
+  const auto band = gp(band_);
+  const auto U = gp(U_);
+  const auto part = gp(part_);
   extern __shared__ double lds[];
   const int w = 2 * s + 1, BW = 2 * w + 1, L = M | 1, MM = M * M;
   const int r0 = chunk * kGramRows;
   const int rows = min(kGramRows, n - r0);
-  double* sU = lds;                            // (kGramRows + 2w) x L
-  double* sV = lds + (kGramRows + 2 * w) * L;  // kGramRows x L
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int halo_rows = kGramRows + 2 * w;
-  for (int t = tid; t < halo_rows * M; t += blockDim.x) {
-    const int rr = t / M, m = t - (t / M) * M;
+  double* sU = lds;                  // halo_rows x L
+  double* sV = sU + halo_rows * L;   // kGramRows x L
+  double* sB = sV + kGramRows * L;   // rows x BW
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int rr = wv; rr < halo_rows; rr += 4) {
     const int g = r0 - w + rr;
-    sU[rr * L + m] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
+    for (int c = lane; c < M; c += 64) sU[rr * L + c] = (g >= 0 && g < n) ? U[long(g) * M + c] : 0.0;
   }
   const int nt = (M + 15) / 16;
   for (int k = 0; k < K; ++k) {
+    __syncthreads();   // sB and sV free
+    const auto brows = band + (long(k) * n + r0) * BW;
+    for (int t = tid; t < rows * BW; t += blockDim.x) sB[t] = brows[t];
     __syncthreads();
-    const double* bk = band + long(k) * n * BW;
-    for (int t = tid; t < kGramRows * M; t += blockDim.x) {
-      const int i = t / M, m = t - (t / M) * M;
-      double v = 0.0;
-      if (i < rows) {
-        const double* brow = bk + long(r0 + i) * BW;
-        for (int o = 0; o < BW; ++o) v += brow[o] * sU[(i + o) * L + m];
-      }
-      sV[i * L + m] = v;
+    switch (s) {
+      case 0: band_rows16<3>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
+      case 1: band_rows16<7>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
+      case 2: band_rows16<11>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
+      default: band_rows16<15>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
     }
     __syncthreads();
     for (int tile = wv; tile < nt * nt; tile += 4) {
       const int tr = tile / nt, tc = tile - (tile / nt) * nt;
       const int ma = tr * 16 + (lane & 15), nb = tc * 16 + (lane & 15);
       rv4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-      for (int kk = 0; kk < kGramRows / 4; ++kk) {
-        const int i = 4 * kk + (lane >> 4);
-        const double a = ma < M ? sU[(i + w) * L + ma] : 0.0;
-        const double b = nb < M ? sV[i * L + nb] : 0.0;
-        acc = mfma_f64(a, b, acc);
+      for (int kk0 = 0; kk0 < kGramRows / 4; kk0 += 4) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = 4 * (kk0 + u) + (lane >> 4);
+          a[u] = sU[(i + w) * L + ma];
+          b[u] = sV[i * L + nb];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = mfma_f64(a[u], b[u], acc);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -80,8 +118,10 @@ __device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const
 }
 
 // out[t] = sum_b part[b][t] in block order, for t in this block's range.
-__device__ inline void sum_parts(int tblock, int nparts, long len, const double* __restrict__ part,
-                                 double* __restrict__ out) {
+__device__ inline void sum_parts(int tblock, int nparts, long len, const double* __restrict__ part_,
+                                 double* __restrict__ out_) {
+  const auto part = gp(part_);
+  const auto out = gp(out_);
   const long t = tblock * long(blockDim.x) + threadIdx.x;
   if (t >= len) return;
   double acc = 0.0;
@@ -95,8 +135,11 @@ __device__ inline void sum_parts(int tblock, int nparts, long len, const double*
 // M columns of U are covered in passes of up to four 16-wide tiles.  Operands
 // are read from global memory (16 consecutive doubles per row and step).
 // part layout: [split][Rc][M].
-__device__ inline void lgram_partial(int ctile, int split, int n, int Rc, int M, const double* __restrict__ F,
-                                     const double* __restrict__ U, double* __restrict__ part) {
+__device__ inline void lgram_partial(int ctile, int split, int n, int Rc, int M, const double* __restrict__ F_,
+                                     const double* __restrict__ U_, double* __restrict__ part_) {
+  const auto F = gp(F_);
+  const auto U = gp(U_);
+  const auto part = gp(part_);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int cw = ctile * kLgCols + wv * 16;
   if (cw >= Rc) return;
@@ -211,8 +254,11 @@ __device__ inline void load_weights(int tblock, const WeightArgs& A, double* __r
 // owns rows [16v, 16v+16) of the block, the load columns are the contracted
 // index (steps of 4), and the M columns are covered in passes of up to four
 // 16-wide tiles.
-__device__ inline void force(int rblock, int n, int Rc, int M, const double* __restrict__ F,
-                             const double* __restrict__ Wt, double* __restrict__ Q) {
+__device__ inline void force(int rblock, int n, int Rc, int M, const double* __restrict__ F_,
+                             const double* __restrict__ Wt_, double* __restrict__ Q_) {
+  const auto F = gp(F_);
+  const auto Wt = gp(Wt_);
+  const auto Q = gp(Q_);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int rw = rblock * kQRows + wv * 16;
   if (rw >= n) return;
@@ -255,10 +301,16 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
 // is formed directly as the A operands of v_mfma_f64_16x16x4f64 (lane l:
 // row l%16, column 4kk + l/16) and multiplied by (C^k)^T on the matrix cores,
 // up to four 16-column tiles of R per pass.
-__device__ inline void residual_part(int chunk, int n, int M, int s, int K, const double* __restrict__ band,
-                                     const double* __restrict__ C, const double* __restrict__ U,
-                                     const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
-                                     double* __restrict__ part) {
+__device__ inline void residual_part(int chunk, int n, int M, int s, int K, const double* __restrict__ band_,
+                                     const double* __restrict__ C_, const double* __restrict__ U_,
+                                     const double* __restrict__ Q_, const uint8_t* __restrict__ fixed_,
+                                     double* __restrict__ part_) {
+  const auto band = gp(band_);
+  const auto C = gp(C_);
+  const auto U = gp(U_);
+  const auto Q = gp(Q_);
+  const auto fixed = gp(fixed_);
+  const auto part = gp(part_);
   extern __shared__ double lds[];
   constexpr int kMaxBW = 2 * (2 * TAPS_MAX_S + 1) + 1;
   const int w = 2 * s + 1, BW = 2 * w + 1, L = M | 1;
@@ -269,10 +321,9 @@ __device__ inline void residual_part(int chunk, int n, int M, int s, int K, cons
   double* sC = sU + hr * L;    // M x L
   __shared__ double red[4][2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int t = tid; t < hr * M; t += blockDim.x) {
-    const int rr = t / M, m = t - (t / M) * M;
+  for (int rr = wv; rr < hr; rr += 4) {   // rows over the waves, columns over the lanes
     const int g = r0 - w + rr;
-    sU[rr * L + m] = (g >= 0 && g < n) ? U[long(g) * M + m] : 0.0;
+    for (int c = lane; c < M; c += 64) sU[rr * L + c] = (g >= 0 && g < n) ? U[long(g) * M + c] : 0.0;
   }
   const int i_a = wv * 16 + (lane & 15);    // chunk row of this lane's A operands
   const int ksteps = (M + 3) / 4, nct = (M + 15) / 16;
@@ -283,12 +334,10 @@ __device__ inline void residual_part(int chunk, int n, int M, int s, int K, cons
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < K; ++k) {
       __syncthreads();   // sU staged / sC free
-      for (int t = tid; t < M * M; t += blockDim.x) {
-        const int r = t / M, c = t - (t / M) * M;
-        sC[r * L + c] = C[long(k) * M * M + t];
-      }
+      for (int r = wv; r < M; r += 4)
+        for (int c = lane; c < M; c += 64) sC[r * L + c] = C[(long(k) * M + r) * M + c];
       double bc[kMaxBW];
-      const double* brow = band + (long(k) * n + r0 + i_a) * BW;
+      const auto brow = band + (long(k) * n + r0 + i_a) * BW;
 #pragma unroll
       for (int o = 0; o < kMaxBW; ++o) bc[o] = (o < BW && i_a < rows) ? brow[o] : 0.0;
       __syncthreads();

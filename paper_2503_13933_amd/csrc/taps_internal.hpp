@@ -142,6 +142,18 @@ inline int half_band(int s) { return 2 * s + 1; }
 
 inline int cdiv(long a, long b) { return static_cast<int>((a + b - 1) / b); }
 
+// Global-memory view of a pointer.  Pointers read from argument records in
+// memory are generic to the compiler, and generic (flat) accesses count
+// against the LDS wait counter as well, so a kernel waiting on its LDS reads
+// would also wait for every outstanding flat load and store.  Device bodies
+// rebind their record pointers through gp() to get global accesses.
+template <class T>
+using gmem = T __attribute__((address_space(1)));
+template <class T>
+__device__ inline gmem<T>* gp(T* p) {
+  return (gmem<T>*)p;
+}
+
 // ---- shared argument checks ------------------------------------------------
 taps_status check_basis(taps_handle* h, const taps_basis1d_t* b);
 taps_status check_problem(taps_handle* h, const taps_problem_t* p);

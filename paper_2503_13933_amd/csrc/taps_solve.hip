@@ -22,6 +22,9 @@
 
 namespace {
 
+using taps::gmem;
+using taps::gp;
+
 constexpr int kThreads = 256;
 constexpr int kTI = 4;  // register tile of the trailing update (rows)
 constexpr int kTJ = 4;  // (cols)
@@ -40,7 +43,7 @@ struct SolveArgs {
   int* info;
 };
 
-__device__ inline bool is_fixed(const SolveArgs& A, int i) { return A.fixed && A.fixed[i]; }
+__device__ inline bool is_fixed(const SolveArgs& A, int i) { return A.fixed && gp(A.fixed)[i]; }
 
 // Write the original block B_ij (|i-j| <= w) into the window ring.
 __device__ void build_block(const SolveArgs& A, int i, int j, double* dst) {
@@ -716,6 +719,23 @@ __device__ inline cplx cmul(cplx a, cplx b) { return cplx{a.r * b.r - a.i * b.i,
 __device__ inline cplx cconj(cplx a) { return cplx{a.r, -a.i}; }
 __device__ inline cplx cscale(cplx a, double s) { return cplx{a.r * s, a.i * s}; }
 __device__ inline double cabs2(cplx a) { return hypot(a.r, a.i); }
+// Complex array in global memory (real and imaginary parts adjacent):
+// entries read as cplx and assigned from cplx through global accesses.
+struct GCplx {
+  gmem<double>* p;
+  struct Ref {
+    gmem<double>* q;
+    __device__ operator cplx() const { return cplx{q[0], q[1]}; }
+    __device__ const Ref& operator=(cplx v) const {
+      q[0] = v.r;
+      q[1] = v.i;
+      return *this;
+    }
+  };
+  __device__ Ref operator[](long i) const { return Ref{p + 2 * i}; }
+  __device__ GCplx operator+(long i) const { return GCplx{p + 2 * i}; }
+};
+
 // a - l b in four fused multiply-adds
 __device__ inline cplx cfms(cplx a, cplx l, cplx b) {
   return cplx{fma(-l.r, b.r, fma(l.i, b.i, a.r)), fma(-l.r, b.i, fma(-l.i, b.r, a.i))};
@@ -746,12 +766,12 @@ constexpr int kFdMaxM = 48;
 // banded systems (n x M complex, row-major) and their U rows
 // (n x (w+1) x M complex).
 struct FdWs {
-  double *H2, *H3, *lam, *C1inv, *T, *Zq, *Y, *U;
+  gmem<double> *H2, *H3, *lam, *C1inv, *T, *Zq, *Y, *U;
 };
 __device__ inline FdWs fd_ws(const SolveArgs& A) {
   const int M = A.M, MM = M * M;
   FdWs f;
-  f.H2 = A.Zst;
+  f.H2 = gp(A.Zst);
   f.H3 = f.H2 + 2 * MM;
   f.lam = f.H3 + 2 * MM;
   f.C1inv = f.lam + 2 * M;
@@ -1430,10 +1450,9 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
   constexpr int W1 = W + 1, BW = 2 * W + 1, CH = W1 * (32 / W1);
   constexpr int SPL = (CH * BW + 63) / 64;   // staged entries per lane and chunk
   const int n = A.n, M = A.M, tid = threadIdx.x, m = tid;
-  const double* b1 = A.band;
-  const double* b2 = A.band + long(n) * BW;
-  cplx* Yg = reinterpret_cast<cplx*>(f.Y);
-  cplx* Ug = reinterpret_cast<cplx*>(f.U);
+  const auto b1 = gp(A.band);
+  const auto b2 = b1 + long(n) * BW;
+  const GCplx Yg{f.Y}, Ug{f.U};
   // staged (a1, a2) of band row i, offset o (column i - W + o), with fixed
   // rows (identity), fixed and out-of-range columns (zero) applied
   auto band_pair = [&](int c, int t) -> double2 {
@@ -1512,7 +1531,7 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
             }
             // row k divided by its pivot: the w upper entries and the
             // reduced right-hand side
-            cplx* u = Ug + long(k) * W * M + m;
+            const GCplx u = Ug + (long(k) * W * M + m);
 #pragma unroll
             for (int cc = 1; cc < W1; ++cc) u[long(cc - 1) * M] = cmul(inv, win[p][(p + cc) % W1]);
             Yg[long(k) * M + m] = cmul(inv, rhs[p]);
@@ -1598,8 +1617,10 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   for (int m = tid; m < M; m += nt) sLam[m] = cmk(f.lam[2 * m], f.lam[2 * m + 1]);
   for (int t = tid; t < MM; t += nt) sH[t] = cmk(f.H2[2 * t], f.H2[2 * t + 1]);
   __syncthreads();
-  cplx* Y = reinterpret_cast<cplx*>(f.Y);      // n x M
-  cplx* U = reinterpret_cast<cplx*>(f.U);      // M x n x (w+1)
+  const GCplx Y{f.Y};   // n x M
+  const GCplx U{f.U};   // M x n x (w+1)
+  const auto Qg = gp(A.Q);
+  const auto Xg = gp(A.X);
   // ---- R = Q H2 (fixed rows zero) on the matrix cores: 16 x 16 tiles of
   // (rows, modes) dealt to the waves, real and imaginary parts in two
   // accumulators sharing the Q operand (lane l: row l%16, q = 4kk + l/16)
@@ -1615,7 +1636,7 @@ __device__ void fd_solve_body(const SolveArgs& A) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int q = 4 * (k0 + u) + (lane >> 4);
-        av[u] = (row_ok && q < M) ? A.Q[long(ia) * M + q] : 0.0;
+        av[u] = (row_ok && q < M) ? Qg[long(ia) * M + q] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -1639,8 +1660,8 @@ __device__ void fd_solve_body(const SolveArgs& A) {
     if (w == 3) fd_banded_reg<3>(A, f, sLam, ring, &s_info);
     if (w == 1) fd_banded_reg<1>(A, f, sLam, ring, &s_info);
   } else if (tid < M) {   // any patch size: one lane per system, ring of rows in LDS
-    const double* b1 = A.band;
-    const double* b2 = A.band + long(n) * BW;
+    const auto b1 = gp(A.band);
+    const auto b2 = b1 + long(n) * BW;
     const int m = tid;
     const cplx lam = sLam[m];
     cplx* wr = win + long(m) * W1 * BW;   // ring of w+1 rows, entry c <-> column (row - w + c)
@@ -1677,7 +1698,7 @@ __device__ void fd_solve_body(const SolveArgs& A) {
       if (k + W1 < n) load_row(k + W1);
     }
     for (int k = n - 1; k >= 0; --k) {
-      const cplx* uk = U + (long(m) * n + k) * W1;
+      const GCplx uk = U + (long(m) * n + k) * W1;
       cplx sacc = Y[long(k) * M + m];
       for (int c = 1; c <= w && k + c < n; ++c) sacc = csub(sacc, cmul(uk[c], Y[long(k + c) * M + m]));
       Y[long(k) * M + m] = cdivz(sacc, uk[0]);
@@ -1711,7 +1732,7 @@ __device__ void fd_solve_body(const SolveArgs& A) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = tr * 16 + (lane >> 4) + 4 * j;
-      if (i < n && qb < M) A.X[long(i) * M + qb] = acc[j];
+      if (i < n && qb < M) Xg[long(i) * M + qb] = acc[j];
     }
   }
   if (tid == 0 && s_info) A.info[0] = s_info;
