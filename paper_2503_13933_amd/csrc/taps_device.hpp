@@ -25,6 +25,28 @@ typedef double rv4d __attribute__((ext_vector_type(4)));
 __device__ inline rv4d mfma_f64(double a, double b, rv4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// Rows g0 .. g0+nrows-1 of a row-major matrix with M columns into LDS rows
+// 0 .. nrows-1 (row stride L), zero outside rows [0, n): rows over the 4
+// waves of the block, columns over the lanes, eight rows per wave loaded
+// before any is stored so their memory latencies overlap.
+template <class P>
+__device__ inline void stage_rows(double* dst, int L, P src, int M, int g0, int n, int nrows) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = lane; c < M; c += 64) {
+    for (int r = wv; r < nrows; r += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int rr = r + 4 * u, g = g0 + rr;
+        v[u] = (rr < nrows && g >= 0 && g < n) ? src[long(g) * M + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (r + 4 * u < nrows) dst[(r + 4 * u) * L + c] = v[u];
+    }
+  }
+}
+
 inline int residual_lds_doubles(int M, int s) { return (kResRows + 2 * (2 * s + 1) + M) * (M | 1); }
 
 // V = A^k U on 16 chunk rows i0.. (i0 wave-uniform), one column per lane:
@@ -76,10 +98,7 @@ __device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const
   double* sB = sV + kGramRows * L;   // rows x BW
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (int rr = wv; rr < halo_rows; rr += 4) {
-    const int g = r0 - w + rr;
-    for (int c = lane; c < M; c += 64) sU[rr * L + c] = (g >= 0 && g < n) ? U[long(g) * M + c] : 0.0;
-  }
+  stage_rows(sU, L, U, M, r0 - w, n, halo_rows);
   const int nt = (M + 15) / 16;
   for (int k = 0; k < K; ++k) {
     __syncthreads();   // sB and sV free
@@ -150,17 +169,28 @@ __device__ inline void lgram_partial(int ctile, int split, int n, int Rc, int M,
     rv4d acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+    // 16 rows per pass, all operands loaded before the four steps
 #pragma unroll 2
-    for (int i0 = rbeg; i0 < rend; i0 += 4) {
-      const int i = i0 + (lane >> 4);
-      const bool ok = i < rend;
-      const double a = (ok && ca < Rc) ? F[long(i) * Rc + ca] : 0.0;
+    for (int i0 = rbeg; i0 < rend; i0 += 16) {
+      double a[4], b[4][4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (ct0 + c >= nct) break;
-        const int m = (ct0 + c) * 16 + (lane & 15);
-        const double b = (ok && m < M) ? U[long(i) * M + m] : 0.0;
-        acc[c] = mfma_f64(a, b, acc[c]);
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 4 * u + (lane >> 4);
+        const bool ok = i < rend;
+        a[u] = (ok && ca < Rc) ? F[long(i) * Rc + ca] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int m = (ct0 + c) * 16 + (lane & 15);
+          b[u][c] = (ok && ct0 + c < nct && m < M) ? U[long(i) * M + m] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (ct0 + c >= nct) break;
+          acc[c] = mfma_f64(a[u], b[u][c], acc[c]);
+        }
       }
     }
 #pragma unroll
@@ -252,8 +282,8 @@ __device__ inline void load_weights(int tblock, const WeightArgs& A, double* __r
 
 // Q = F_d Wt for rows [rblock*kQRows, +kQRows) on the matrix cores: wave v
 // owns rows [16v, 16v+16) of the block, the load columns are the contracted
-// index (steps of 4), and the M columns are covered in passes of up to four
-// 16-wide tiles.
+// index (passes of 16 columns in four steps, operands loaded together), and
+// the M columns are covered in passes of up to four 16-wide tiles.
 __device__ inline void force(int rblock, int n, int Rc, int M, const double* __restrict__ F_,
                              const double* __restrict__ Wt_, double* __restrict__ Q_) {
   const auto F = gp(F_);
@@ -268,17 +298,28 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
     rv4d acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+    // 16 load columns per pass, all operands loaded before the four steps
 #pragma unroll 2
-    for (int c0 = 0; c0 < Rc; c0 += 4) {
-      const int kc = c0 + (lane >> 4);
-      const bool ok = kc < Rc;
-      const double a = (ok && ia < n) ? F[long(ia) * Rc + kc] : 0.0;
+    for (int c0 = 0; c0 < Rc; c0 += 16) {
+      double a[4], b[4][4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (ct0 + c >= nct) break;
-        const int m = (ct0 + c) * 16 + (lane & 15);
-        const double b = (ok && m < M) ? Wt[long(kc) * M + m] : 0.0;
-        acc[c] = mfma_f64(a, b, acc[c]);
+      for (int u = 0; u < 4; ++u) {
+        const int kc = c0 + 4 * u + (lane >> 4);
+        const bool ok = kc < Rc;
+        a[u] = (ok && ia < n) ? F[long(ia) * Rc + kc] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int m = (ct0 + c) * 16 + (lane & 15);
+          b[u][c] = (ok && ct0 + c < nct && m < M) ? Wt[long(kc) * M + m] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (ct0 + c >= nct) break;
+          acc[c] = mfma_f64(a[u], b[u][c], acc[c]);
+        }
       }
     }
 #pragma unroll
@@ -321,10 +362,7 @@ __device__ inline void residual_part(int chunk, int n, int M, int s, int K, cons
   double* sC = sU + hr * L;    // M x L
   __shared__ double red[4][2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int rr = wv; rr < hr; rr += 4) {   // rows over the waves, columns over the lanes
-    const int g = r0 - w + rr;
-    for (int c = lane; c < M; c += 64) sU[rr * L + c] = (g >= 0 && g < n) ? U[long(g) * M + c] : 0.0;
-  }
+  stage_rows(sU, L, U, M, r0 - w, n, hr);
   const int i_a = wv * 16 + (lane & 15);    // chunk row of this lane's A operands
   const int ksteps = (M + 3) / 4, nct = (M + 15) / 16;
   double rr2 = 0.0, qq2 = 0.0;
