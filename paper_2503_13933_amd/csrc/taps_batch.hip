@@ -45,10 +45,18 @@ __global__ void kb_gram_partial(const BProb* __restrict__ P, const int* __restri
                q.gpart + long(blockIdx.x) * q.K[e] * q.M * q.M);
 }
 
+// The elementwise kernels (sums of partials, couplings, load terms and
+// weights) run kVB slices of 256 items per block: a grid with one slice per
+// block has tens of thousands of tiny blocks, and their dispatch, not their
+// work, then sets the time.
+constexpr int kVB = 8;
+
 __global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
   const BProb& q = P[act[blockIdx.y]];
   const int chunks = (q.n[e] + kGramRows - 1) / kGramRows;
-  sum_parts(blockIdx.x, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
+#pragma unroll
+  for (int u = 0; u < kVB; ++u)
+    sum_parts(blockIdx.x * kVB + u, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
 }
 
 __global__ void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
@@ -60,23 +68,28 @@ __global__ void kb_lgram_partial(const BProb* __restrict__ P, const int* __restr
 __global__ void kb_lgram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
   const BProb& q = P[act[blockIdx.y]];
   const int splits = (q.n[e] + kLgRows - 1) / kLgRows;
-  sum_parts(blockIdx.x, splits, long(q.Rc[e]) * q.M, q.lpart, q.lgram[e]);
+#pragma unroll
+  for (int u = 0; u < kVB; ++u) sum_parts(blockIdx.x * kVB + u, splits, long(q.Rc[e]) * q.M, q.lpart, q.lgram[e]);
 }
 
 __global__ void kb_couple(const BProb* __restrict__ P, const CoupleArgs* __restrict__ CA,
                           const int* __restrict__ act, int d, int D) {
   const int b = act[blockIdx.y];
-  couple(blockIdx.x, CA[long(b) * D + d], P[b].C);
+#pragma unroll
+  for (int u = 0; u < kVB; ++u) couple(blockIdx.x * kVB + u, CA[long(b) * D + d], P[b].C);
 }
 
 __global__ void kb_load_terms(const WeightArgs* __restrict__ WA, const int* __restrict__ act, int d, int D) {
-  load_terms(blockIdx.x, WA[long(act[blockIdx.y]) * D + d]);
+  const WeightArgs& A = WA[long(act[blockIdx.y]) * D + d];
+#pragma unroll
+  for (int u = 0; u < kVB; ++u) load_terms(blockIdx.x * kVB + u, A);
 }
 
 __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* __restrict__ WA,
                                 const int* __restrict__ act, int d, int D) {
   const int b = act[blockIdx.y];
-  load_weights(blockIdx.x, WA[long(b) * D + d], P[b].Wt);
+#pragma unroll
+  for (int u = 0; u < kVB; ++u) load_weights(blockIdx.x * kVB + u, WA[long(b) * D + d], P[b].Wt);
 }
 
 __global__ void kb_force(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
@@ -340,11 +353,11 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
     kb_gram_partial<<<dim3(Z.chunks[e], nact), 256, glds, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_partial");
-    kb_gram_sum<<<dim3(Z.gram[e], nact), 256, 0, st>>>(d_prob, d_active, e);
+    kb_gram_sum<<<dim3(cdiv(Z.gram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_sum");
     kb_lgram_partial<<<dim3(Z.ctiles[e], Z.splits[e], nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_lgram_partial");
-    kb_lgram_sum<<<dim3(Z.lgram[e], nact), 256, 0, st>>>(d_prob, d_active, e);
+    kb_lgram_sum<<<dim3(cdiv(Z.lgram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_lgram_sum");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -358,11 +371,11 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto system = [&](int d, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_couple<<<dim3(Z.cpl[d], nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
+    kb_couple<<<dim3(cdiv(Z.cpl[d], kVB), nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_couple");
-    kb_load_terms<<<dim3(Z.max_terms, nact), 256, 0, st>>>(d_wa, d_active, d, D);
+    kb_load_terms<<<dim3(cdiv(Z.max_terms, kVB), nact), 256, 0, st>>>(d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_terms");
-    kb_load_weights<<<dim3(Z.wt[d], nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
+    kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_weights");
     kb_force<<<dim3(Z.rblocks[d], nact), 256, 0, st>>>(d_prob, d_active, d);
     TAPS_LAUNCHED(h, "kb_force");

@@ -226,11 +226,11 @@ __device__ inline void couple(int tblock, const CoupleArgs& A, double* __restric
     double prod = A.gamma[tau];
     for (int e = 0; e < A.D; ++e) {
       if (e == A.d) continue;
-      prod *= A.gram[e][long(A.tk[tau][e]) * MM + mn];
+      prod *= gp(A.gram[e])[long(A.tk[tau][e]) * MM + mn];
     }
     acc += prod;
   }
-  C[t] = acc;
+  gp(C)[t] = acc;
 }
 
 struct WeightArgs {
@@ -247,37 +247,38 @@ struct WeightArgs {
 // thread's loads depend only on its own term, so the whole table fills in a
 // few memory latencies.
 __device__ inline void load_terms(int tblock, const WeightArgs& A) {
-  const long t = tblock * long(blockDim.x) + threadIdx.x;
-  if (t >= long(A.R) * A.M) return;
-  const int q = int(t / A.M), m = int(t - (t / A.M) * A.M);
-  const int r = A.ptr ? A.idx[q] : q;
+  const int t = tblock * blockDim.x + threadIdx.x;   // R M < 2^31
+  const int M = A.M;
+  if (t >= A.R * M) return;
+  const int q = t / M, m = t - q * M;
+  const int r = A.ptr ? gp(A.idx)[q] : q;
   double prod = 1.0;
   for (int e = 0; e < A.D; ++e) {
     if (e == A.d) continue;
-    const int ce = A.col[e] ? A.col[e][r] : r;
-    prod *= A.lgram[e][long(ce) * A.M + m];
+    const int ce = A.col[e] ? gp(A.col[e])[r] : r;
+    prod *= gp(A.lgram[e])[long(ce) * M + m];
   }
-  A.P[t] = prod;
+  gp(A.P)[t] = prod;
 }
 
 // Wt[c][m] = sum of P[q][m] over the terms q of group c (ptr[c] .. ptr[c+1]),
 // in term order; independent contiguous loads.
 __device__ inline void load_weights(int tblock, const WeightArgs& A, double* __restrict__ Wt) {
-  const long t = tblock * long(blockDim.x) + threadIdx.x;
-  if (t >= long(A.Rc) * A.M) return;
-  const int c = int(t / A.M), m = int(t - (t / A.M) * A.M);
-  const int rb = A.ptr ? A.ptr[c] : c;
-  const int re = A.ptr ? A.ptr[c + 1] : c + 1;
-  const double* P = A.P + m;
+  const int t = tblock * blockDim.x + threadIdx.x;   // Rc M < 2^31
+  const int M = A.M;
+  if (t >= A.Rc * M) return;
+  const int c = t / M, m = t - c * M;
+  const int rb = A.ptr ? gp(A.ptr)[c] : c;
+  const int re = A.ptr ? gp(A.ptr)[c + 1] : c + 1;
+  const auto P = gp(A.P) + m;
   double acc = 0.0;
   int q = rb;
   for (; q + 4 <= re; q += 4) {
-    const double p0 = P[long(q) * A.M], p1 = P[long(q + 1) * A.M], p2 = P[long(q + 2) * A.M],
-                 p3 = P[long(q + 3) * A.M];
+    const double p0 = P[long(q) * M], p1 = P[long(q + 1) * M], p2 = P[long(q + 2) * M], p3 = P[long(q + 3) * M];
     acc = (((acc + p0) + p1) + p2) + p3;
   }
-  for (; q < re; ++q) acc += P[long(q) * A.M];
-  Wt[t] = acc;
+  for (; q < re; ++q) acc += P[long(q) * M];
+  gp(Wt)[t] = acc;
 }
 
 // Q = F_d Wt for rows [rblock*kQRows, +kQRows) on the matrix cores: wave v

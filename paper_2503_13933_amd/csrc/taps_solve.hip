@@ -1621,35 +1621,50 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   const GCplx U{f.U};   // M x n x (w+1)
   const auto Qg = gp(A.Q);
   const auto Xg = gp(A.X);
-  // ---- R = Q H2 (fixed rows zero) on the matrix cores: 16 x 16 tiles of
-  // (rows, modes) dealt to the waves, real and imaginary parts in two
-  // accumulators sharing the Q operand (lane l: row l%16, q = 4kk + l/16)
-  const int wave = tid >> 6, lane = tid & 63;
+  // ---- R = Q H2 (fixed rows zero) on the matrix cores: per 16-row tile
+  // (tiles dealt to the waves) the Q operands of every step are loaded once
+  // for all mode tiles, and the next tile's operands are loaded before this
+  // tile's products; real and imaginary parts in two accumulators sharing
+  // the Q operand (lane l: row l%16, q = 4kk + l/16)
+  constexpr int kKS = kFdMaxM / 4;
+  const int wave = tid >> 6, lane = tid & 63, nwv = nt >> 6;
   const int nrt = (n + 15) / 16, nct = (M + 15) / 16, ksteps = (M + 3) / 4;
-  for (int tile = wave; tile < nrt * nct; tile += nt >> 6) {
-    const int tr = tile / nct, tc = tile - (tile / nct) * nct;
-    const int ia = tr * 16 + (lane & 15), mb = tc * 16 + (lane & 15);
-    const bool row_ok = ia < n && !is_fixed(A, ia);
-    v4d are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < ksteps; k0 += 4) {   // Q operands of 4 steps loaded together
-      double av[4];
+  {
+    double an[kKS];
+    auto load_q = [&](int tr, double* dst) {
+      const int ia = tr * 16 + (lane & 15);
+      const int ic = min(ia, n - 1);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int q = 4 * (k0 + u) + (lane >> 4);
-        av[u] = (row_ok && q < M) ? Qg[long(ia) * M + q] : 0.0;
+      for (int u = 0; u < kKS; ++u) {
+        const int q = 4 * u + (lane >> 4);
+        dst[u] = (u < ksteps && q < M) ? Qg[long(ic) * M + q] : 0.0;
       }
+    };
+    if (wave < nrt) load_q(wave, an);
+    for (int tr = wave; tr < nrt; tr += nwv) {
+      double av[kKS];
+      const int ia = tr * 16 + (lane & 15);
+      const bool row_ok = ia < n && !is_fixed(A, ia);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int q = 4 * (k0 + u) + (lane >> 4);
-        const cplx hb = (q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
-        are = mfma16x16x4(av[u], hb.r, are);
-        aim = mfma16x16x4(av[u], hb.i, aim);
+      for (int u = 0; u < kKS; ++u) av[u] = row_ok ? an[u] : 0.0;
+      if (tr + nwv < nrt) load_q(tr + nwv, an);
+      for (int tc = 0; tc < nct; ++tc) {
+        const int mb = tc * 16 + (lane & 15);
+        v4d are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < kKS; ++u) {
+          if (u >= ksteps) break;
+          const int q = 4 * u + (lane >> 4);
+          const cplx hb = (q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
+          are = mfma16x16x4(av[u], hb.r, are);
+          aim = mfma16x16x4(av[u], hb.i, aim);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = tr * 16 + (lane >> 4) + 4 * j;
+          if (i < n && mb < M) Y[long(i) * M + mb] = cmk(are[j], aim[j]);
+        }
       }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int i = tr * 16 + (lane >> 4) + 4 * j;
-      if (i < n && mb < M) Y[long(i) * M + mb] = cmk(are[j], aim[j]);
     }
   }
   __syncthreads();
@@ -1706,33 +1721,50 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   }
   __syncthreads();
   // ---- X = Re(Y H3) = Yr H3r - Yi H3i (fixed rows zero) on the matrix
-  // cores, tiles of (rows, modes) as above
+  // cores, row tiles as above (Y operands of every step loaded once per row
+  // tile, the next tile's before this tile's products)
   for (int t = tid; t < MM; t += nt) sH[t] = cmk(f.H3[2 * t], f.H3[2 * t + 1]);
   __syncthreads();
-  for (int tile = wave; tile < nrt * nct; tile += nt >> 6) {
-    const int tr = tile / nct, tc = tile - (tile / nct) * nct;
-    const int ia = tr * 16 + (lane & 15), qb = tc * 16 + (lane & 15);
-    const bool row_ok = ia < n && !is_fixed(A, ia);
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < ksteps; k0 += 4) {   // Y operands of 4 steps loaded together
-      cplx yv[4];
+  {
+    double anr[kKS], ani[kKS];
+    auto load_y = [&](int tr, double* dr, double* di) {
+      const int ic = min(tr * 16 + (lane & 15), n - 1);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int m = 4 * (k0 + u) + (lane >> 4);
-        yv[u] = (row_ok && m < M) ? Y[long(ia) * M + m] : cmk(0.0, 0.0);
+      for (int u = 0; u < kKS; ++u) {
+        const int m = 4 * u + (lane >> 4);
+        const cplx v = (u < ksteps && m < M) ? cplx(Y[long(ic) * M + m]) : cmk(0.0, 0.0);
+        dr[u] = v.r;
+        di[u] = v.i;
       }
+    };
+    if (wave < nrt) load_y(wave, anr, ani);
+    for (int tr = wave; tr < nrt; tr += nwv) {
+      double yr[kKS], yi[kKS];
+      const int ia = tr * 16 + (lane & 15);
+      const bool row_ok = ia < n && !is_fixed(A, ia);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int m = 4 * (k0 + u) + (lane >> 4);
-        const cplx hb = (m < M && qb < M) ? sH[m * M + qb] : cmk(0.0, 0.0);
-        acc = mfma16x16x4(yv[u].r, hb.r, acc);
-        acc = mfma16x16x4(-yv[u].i, hb.i, acc);
+      for (int u = 0; u < kKS; ++u) {
+        yr[u] = row_ok ? anr[u] : 0.0;
+        yi[u] = row_ok ? -ani[u] : 0.0;
       }
-    }
+      if (tr + nwv < nrt) load_y(tr + nwv, anr, ani);
+      for (int tc = 0; tc < nct; ++tc) {
+        const int qb = tc * 16 + (lane & 15);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int i = tr * 16 + (lane >> 4) + 4 * j;
-      if (i < n && qb < M) Xg[long(i) * M + qb] = acc[j];
+        for (int u = 0; u < kKS; ++u) {
+          if (u >= ksteps) break;
+          const int m = 4 * u + (lane >> 4);
+          const cplx hb = (m < M && qb < M) ? sH[m * M + qb] : cmk(0.0, 0.0);
+          acc = mfma16x16x4(yr[u], hb.r, acc);
+          acc = mfma16x16x4(yi[u], hb.i, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = tr * 16 + (lane >> 4) + 4 * j;
+          if (i < n && qb < M) Xg[long(i) * M + qb] = acc[j];
+        }
+      }
     }
   }
   if (tid == 0 && s_info) A.info[0] = s_info;
