@@ -27,12 +27,15 @@ separately from the benchmark slabs.  The plain form (one slab at a time,
 random start) and the batched form with random starts are timed under the
 same rule.
 
-The JSON line carries the roofline of the dominant kernel (the banded stage
-of the fast diagonalisation, k_fd_solve, whose complex right-hand sides and
-U rows stream through HBM: algorithmic bytes over its event-timed kernel
-time, against the HBM peak; with the block LU, that kernel's FP64 flops
-against the FP64 peak) and the CPU oracle timed on a bounded sample.  The
-eigen stage (three latency-bound one-wave kernels) is reported beside it.
+The JSON line carries the roofline of the dominant kernel, the one of the
+two largest kernels of the fast diagonalisation with more event-timed time
+in the timed region: the banded stage k_fd_solve (its complex right-hand
+sides and U rows stream through HBM: algorithmic bytes over kernel time,
+against the HBM peak) or the real Schur kernel k_fd_schur (a one-wave FP64
+latency chain: algorithmic flops over kernel time, against the FP64 peak);
+with the block LU, that kernel's FP64 flops against the FP64 peak.  The
+other one and the whole eigen stage are reported beside it, with the CPU
+oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -49,12 +52,13 @@ if ROOT not in sys.path:
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix)
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-# Memory traffic of the banded stage (k_fd_solve) per algorithmic byte, from
-# two rocprofv3 counter runs of paper_2503_13933_amd/prof_solve.py
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off its 1 GiB device
-# copy, over the algorithmic bytes it prints), valid for the solve source with
-# this SHA-256 prefix only (None: not measured for the current source).
-SOLVE_TRAFFIC = {"bytes_per_alg_byte": None, "source_sha256": None}
+# Memory traffic per algorithmic byte of the banded stage (k_fd_solve) and of
+# the real Schur kernel (k_fd_schur), from two rocprofv3 counter runs of
+# paper_2503_13933_amd/prof_solve.py (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
+# the factors read off its 1 GiB device copy, over the algorithmic bytes the
+# library counts for the same launches), valid for the solve source with this
+# SHA-256 prefix only (None: not measured for the current source).
+TRAFFIC = {"k_fd_solve": 1.2970, "k_fd_schur": 1.0207, "source_sha256": "e1bb694a7435562d"}
 
 
 def log(msg):
@@ -210,6 +214,7 @@ def main():
     el_w, sw_w, last_w = timed(step_warm, "warm+batched", prof=True)
     n_solve, ms_solve, fl_solve, by_solve = capi.taps_profile_read(h, capi.PROF_SOLVE)
     n_eig, ms_eig, fl_eig, _ = capi.taps_profile_read(h, capi.PROF_EIG)
+    n_sch, ms_sch, fl_sch, by_sch = capi.taps_profile_read(h, capi.PROF_SCHUR)
     n_con, ms_con, _, _ = capi.taps_profile_read(h, capi.PROF_CONTRACT)
     n_rec, ms_rec, fl_rec, _ = capi.taps_profile_read(h, capi.PROF_RECON)
     el_b, sw_b, last_b = timed(step_random_batched, "random+batched")
@@ -230,22 +235,39 @@ def main():
     src = os.path.join(ROOT, "paper_2503_13933_amd", "csrc", "taps_solve.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     fd = args.solver == "fastdiag"
-    # dominant kernel: the banded stage k_fd_solve (HBM) for the fast
-    # diagonalisation, the block LU (FP64) otherwise; both in the solve family
-    same_kernel = fd and SOLVE_TRAFFIC["bytes_per_alg_byte"] and digest == SOLVE_TRAFFIC["source_sha256"]
-    traffic = SOLVE_TRAFFIC["bytes_per_alg_byte"] * by_solve / n_solve if (same_kernel and n_solve) else None
-    sec = ms_solve * 1e-3 if n_solve else float("inf")
+    # dominant kernel: with the fast diagonalisation the banded stage
+    # k_fd_solve (HBM) or the real Schur kernel k_fd_schur (FP64 latency
+    # chain), whichever has more kernel time in the timed region; the block
+    # LU (FP64) otherwise
+    measured = fd and digest == TRAFFIC["source_sha256"]
+
+    def roofline(name, n_l, ms_l, fl_l, by_l):
+        sec = ms_l * 1e-3 if n_l else float("inf")
+        if name == "k_fd_solve":
+            r = {"bound": "hbm", "kernel": "k_fd_solve (banded stage of the fast diagonalisation, one 64-lane "
+                                          "wave per system)",
+                 "achieved": by_l / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        elif name == "k_fd_schur":
+            r = {"bound": "alu", "kernel": "k_fd_schur (real Schur form: Hessenberg reduction and Francis QR, "
+                                          "one 64-lane wave per system)",
+                 "achieved": fl_l / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        else:
+            r = {"bound": "alu", "kernel": "k_block_lu_mfma_batched (block-banded FP64 dim solve)",
+                 "achieved": fl_l / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        ratio = TRAFFIC.get(name) if measured else None
+        r.update({"frac": r["achieved"] / r["peak"],
+                  "traffic": ratio * by_l / n_l if (ratio and n_l) else None,
+                  "traffic_unit": "bytes per launch (HBM/MALL counters, calibrated)", "launches": n_l,
+                  "avg_launch_ms": ms_l / max(1, n_l), "bytes_per_launch": by_l / max(1, n_l),
+                  "flops_per_launch": fl_l / max(1, n_l)})
+        return r
+
     if fd:
-        roof = {"bound": "hbm", "kernel": "k_fd_solve (banded stage of the fast diagonalisation, one 64-lane wave "
-                                          "per system)",
-                "achieved": by_solve / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        r_solve = roofline("k_fd_solve", n_solve, ms_solve, fl_solve, by_solve)
+        r_schur = roofline("k_fd_schur", n_sch, ms_sch, fl_sch, by_sch)
+        roof, other = (r_solve, r_schur) if ms_solve >= ms_sch else (r_schur, r_solve)
     else:
-        roof = {"bound": "alu", "kernel": "k_block_lu_mfma_batched (block-banded FP64 dim solve)",
-                "achieved": fl_solve / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": traffic,
-                 "traffic_unit": "bytes per launch (HBM/MALL counters, calibrated)", "launches": n_solve,
-                 "avg_launch_ms": ms_solve / max(1, n_solve),
-                 "bytes_per_launch": by_solve / max(1, n_solve), "flops_per_launch": fl_solve / max(1, n_solve)})
+        roof, other = roofline("k_block_lu", n_solve, ms_solve, fl_solve, by_solve), None
     eig_tf = fl_eig / (ms_eig * 1e-3) / 1e12 if n_eig else 0.0
     rec_tf = (fl_rec / n_rec) / (ms_rec / n_rec * 1e-3) / 1e12 if n_rec else 0.0
     out = {
@@ -281,6 +303,8 @@ def main():
             "eig_stage": {"kernels": "k_fd_inverse + k_fd_schur + k_fd_vectors", "launch_groups": n_eig,
                           "avg_group_ms": ms_eig / max(1, n_eig), "fp64_tflops": eig_tf,
                           "fp64_frac": eig_tf / FP64_PEAK_TFLOPS} if fd else None,
+            "schur_kernel_ms_per_step": ms_sch / args.steps,
+            "second_kernel_roofline": other,
             "contract_kernel_ms_per_step": ms_con / args.steps,
             "recon_kernel_ms_per_step": ms_rec / args.steps,
             "recon_bf16_tflops": rec_tf,

@@ -331,6 +331,11 @@ taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* prob
  *                      vectors 25, triangular eigenvectors and their inverse
  *                      2 x 4/3, H3 4, Z Wv 4, H2 4, in units of M^3); bytes =
  *                      couplings read, transforms and inverse written.
+ *   TAPS_PROF_SCHUR    the same stage's real Schur kernel alone (timed inside
+ *                      the eigen-stage bracket): flops = 25 M^3 per system
+ *                      (Hessenberg reduction and Francis QR with the Schur
+ *                      vectors accumulated); bytes = 24 M^2 (E read, the
+ *                      Schur form and its vectors written).
  *   TAPS_PROF_CONTRACT Grams, load Grams, couplings and force: flops of the
  *                      products, bytes = U, bands, F read once + outputs.
  *   TAPS_PROF_RECON    FP32/BF16 reconstruction on the matrix cores: flops =
@@ -343,7 +348,8 @@ typedef enum {
   TAPS_PROF_SOLVE = 0,
   TAPS_PROF_CONTRACT = 1,
   TAPS_PROF_RECON = 2,
-  TAPS_PROF_EIG = 3
+  TAPS_PROF_EIG = 3,
+  TAPS_PROF_SCHUR = 4
 } taps_prof_family;
 taps_status taps_profile_enable(taps_handle_t h, int32_t enable);
 taps_status taps_profile_read(taps_handle_t h, taps_prof_family family, int32_t* launches,

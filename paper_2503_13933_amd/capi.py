@@ -30,7 +30,7 @@ FUNCTIONS = (
     "taps_adam_step", "taps_set_tuning", "taps_get_tuning", "taps_autotune",
 )
 MLP_MAX_LAYERS = 8
-PROF_SOLVE, PROF_CONTRACT, PROF_RECON, PROF_EIG = 0, 1, 2, 3
+PROF_SOLVE, PROF_CONTRACT, PROF_RECON, PROF_EIG, PROF_SCHUR = 0, 1, 2, 3, 4
 
 
 class TapsError(RuntimeError):

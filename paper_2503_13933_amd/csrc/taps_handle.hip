@@ -128,7 +128,7 @@ taps_status taps_profile_enable(taps_handle_t h, int32_t enable) {
   if (!h) return TAPS_ERR_INVALID;
   if (enable) {
     h->prof.used = 0;
-    for (int f = 0; f < 4; ++f) h->prof.flops[f] = h->prof.bytes[f] = 0.0;
+    for (int f = 0; f < kProfFamilies; ++f) h->prof.flops[f] = h->prof.bytes[f] = 0.0;
   }
   h->prof.on = enable != 0;
   return TAPS_OK;
@@ -138,7 +138,7 @@ taps_status taps_profile_read(taps_handle_t h, taps_prof_family family, int32_t*
                               double* flops, double* bytes) {
   if (!h) return TAPS_ERR_INVALID;
   if (family != TAPS_PROF_SOLVE && family != TAPS_PROF_CONTRACT && family != TAPS_PROF_RECON &&
-      family != TAPS_PROF_EIG)
+      family != TAPS_PROF_EIG && family != TAPS_PROF_SCHUR)
     return taps::fail(h, TAPS_ERR_INVALID, "unknown family %d", int(family));
   auto& P = h->prof;
   int cnt = 0;

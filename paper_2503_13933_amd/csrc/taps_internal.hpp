@@ -20,6 +20,8 @@ struct taps_gram_cache {
   uint32_t valid = 0;
 };
 
+constexpr int kProfFamilies = 5;   // taps_prof_family values
+
 struct taps_handle {
   // scratch: reused by every call (partial sums, solve factors, C/Q buffers)
   void* ws = nullptr;
@@ -52,7 +54,7 @@ struct taps_handle {
     std::vector<hipEvent_t> ev;    // start/stop pairs, reused
     std::vector<int> fam;          // family of each recorded pair
     size_t used = 0;               // pairs recorded since enable
-    double flops[4] = {0, 0, 0, 0}, bytes[4] = {0, 0, 0, 0};
+    double flops[kProfFamilies] = {}, bytes[kProfFamilies] = {};
     bool on = false;
   } prof;
 };

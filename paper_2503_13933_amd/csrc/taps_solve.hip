@@ -1004,7 +1004,11 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
     }
   }
   wave_sync();
-  // ---- Householder Hessenberg form, Zr accumulated
+  // ---- Householder Hessenberg form, Zr accumulated.  The rows (left) and
+  // columns (right) past k are read once into registers in batches of 8
+  // (static, at most kFdMaxM / 8 batches; clamped entries weigh 0), all
+  // loads before the first use, and updated from there.
+  constexpr int kHB = kFdMaxM / 8;
   for (int k = 0; k + 2 < M; ++k) {
     const double x = (lane > k && lane < M) ? Hr[lane * L + k] : 0.0;
     double ss = x * x;
@@ -1014,68 +1018,87 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
     if (nx == 0.0) continue;
     const double alpha = x0 >= 0.0 ? -nx : nx;
     const double vi = (lane == k + 1) ? x - alpha : x;
-    double vv = vi * vi;
-    for (int o = 32; o > 0; o >>= 1) vv += __shfl_xor(vv, o);
-    if (vv == 0.0) continue;
-    const double beta = 2.0 / vv;
+    const double beta = 1.0 / (nx * (nx + fabs(x0)));   // 2 / |v|^2, |v|^2 = 2 nx (nx + |x0|)
     if (lane < M) v[lane] = vi;
     wave_sync();
-    if (lane < M) {   // left: column lane, rows k+1.. in batches of 8 (clamped rows weigh 0)
-      double wsum = 0.0;
-      for (int i0 = k + 1; i0 < M; i0 += 8) {
-        double hv[8], vv8[8];
+    if (lane < M) {   // left: column lane, rows k+1..
+      double hv[kHB][8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int i = min(i0 + u, M - 1);
-          hv[u] = Hr[i * L + lane];
-          vv8[u] = (i0 + u < M) ? v[i] : 0.0;
+      for (int b = 0; b < kHB; ++b) {
+        const int i0 = k + 1 + 8 * b;
+        if (i0 < M) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) hv[b][u] = Hr[min(i0 + u, M - 1) * L + lane];
         }
+      }
+      double wsum = 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) wsum += vv8[u] * hv[u];
+      for (int b = 0; b < kHB; ++b) {
+        const int i0 = k + 1 + 8 * b;
+        if (i0 < M) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double vr = v[min(i0 + u, M - 1)];
+            wsum += ((i0 + u < M) ? vr : 0.0) * hv[b][u];
+          }
+        }
       }
       const double bw = beta * wsum;
-      for (int i0 = k + 1; i0 < M; i0 += 8) {
-        double hv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = Hr[min(i0 + u, M - 1) * L + lane];
+      for (int b = 0; b < kHB; ++b) {
+        const int i0 = k + 1 + 8 * b;
+        if (i0 < M) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (i0 + u < M) Hr[(i0 + u) * L + lane] = hv[u] - v[i0 + u] * bw;
+          for (int u = 0; u < 8; ++u) {
+            const double vr = v[min(i0 + u, M - 1)];
+            if (i0 + u < M) Hr[(i0 + u) * L + lane] = hv[b][u] - vr * bw;
+          }
+        }
       }
     }
     wave_sync();
-    if (lane < M) {   // right: row lane, columns k+1.. (Hr and Zr) in batches of 8
-      double us = 0.0, zs = 0.0;
-      for (int j0 = k + 1; j0 < M; j0 += 8) {
-        double hv[8], zv[8], vv8[8];
+    if (lane < M) {   // right: row lane, columns k+1.. (Hr and Zr)
+      double hv[kHB][8], zv[kHB][8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = min(j0 + u, M - 1);
-          hv[u] = Hr[lane * L + j];
-          zv[u] = Zr[lane * L + j];
-          vv8[u] = (j0 + u < M) ? v[j] : 0.0;
+      for (int b = 0; b < kHB; ++b) {
+        const int j0 = k + 1 + 8 * b;
+        if (j0 < M) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = min(j0 + u, M - 1);
+            hv[b][u] = Hr[lane * L + j];
+            zv[b][u] = Zr[lane * L + j];
+          }
         }
+      }
+      double us = 0.0, zs = 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          us += hv[u] * vv8[u];
-          zs += zv[u] * vv8[u];
+      for (int b = 0; b < kHB; ++b) {
+        const int j0 = k + 1 + 8 * b;
+        if (j0 < M) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double vr = v[min(j0 + u, M - 1)];
+            const double vj = (j0 + u < M) ? vr : 0.0;
+            us += hv[b][u] * vj;
+            zs += zv[b][u] * vj;
+          }
         }
       }
       const double bu = beta * us, buz = beta * zs;
-      for (int j0 = k + 1; j0 < M; j0 += 8) {
-        double hv[8], zv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = min(j0 + u, M - 1);
-          hv[u] = Hr[lane * L + j];
-          zv[u] = Zr[lane * L + j];
-        }
+      for (int b = 0; b < kHB; ++b) {
+        const int j0 = k + 1 + 8 * b;
+        if (j0 < M) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (j0 + u < M) {
-            Hr[lane * L + j0 + u] = hv[u] - bu * v[j0 + u];
-            Zr[lane * L + j0 + u] = zv[u] - buz * v[j0 + u];
+          for (int u = 0; u < 8; ++u) {
+            const double vr = v[min(j0 + u, M - 1)];
+            if (j0 + u < M) {
+              Hr[lane * L + j0 + u] = hv[b][u] - bu * vr;
+              Zr[lane * L + j0 + u] = zv[b][u] - buz * vr;
+            }
           }
+        }
       }
     }
     wave_sync();
@@ -1820,6 +1843,10 @@ bool fd_supported(int M, int s, int K) {
 // complex transforms (4 n M^2 each) and M banded complex eliminations with
 // back substitution, 8 n (w+1)(w+2) each.
 double fd_eig_flops(int M) { return 44.0 * M * double(M) * M; }
+// the real Schur kernel alone: Hessenberg reduction and Francis QR with the
+// Schur vectors accumulated; E read, T and Z written
+double fd_schur_flops(int M) { return 25.0 * M * double(M) * M; }
+double fd_schur_bytes(int M) { return 24.0 * M * double(M); }
 double fd_eig_bytes(int M) { return 8.0 * (2.0 * M * M) + 16.0 * (2.0 * M * M + M) + 8.0 * M * M; }
 double fd_flops(int n, int M, int w) {
   return 8.0 * n * double(M) * M + 8.0 * M * double(n) * (w + 1) * (w + 2);
@@ -1937,8 +1964,11 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
     TAPS_TRY(prof_begin(h, TAPS_PROF_EIG, stream, &slot));
     k_fd_inverse_one<<<1, 64, fd_inverse_lds(M), stream>>>(A);
     TAPS_LAUNCHED(h, "k_fd_inverse");
+    size_t sslot;
+    TAPS_TRY(prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
     k_fd_schur_one<<<1, 64, fd_schur_lds(M), stream>>>(A);
     TAPS_LAUNCHED(h, "k_fd_schur");
+    TAPS_TRY(prof_end(h, sslot, fd_schur_flops(M), fd_schur_bytes(M), stream));
     k_fd_vectors_one<<<1, 64, fd_vectors_lds(M), stream>>>(A);
     TAPS_LAUNCHED(h, "k_fd_vectors");
     TAPS_TRY(prof_end(h, slot, fd_eig_flops(M), fd_eig_bytes(M), stream));
@@ -2032,8 +2062,11 @@ taps_status fd_batched_launch(taps_handle* h, int n_active, const void* d_args, 
   const SolveArgs* args = static_cast<const SolveArgs*>(d_args);
   k_fd_inverse<<<n_active, 64, fd_inverse_lds(M), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_inverse");
+  size_t sslot;
+  TAPS_TRY(prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
   k_fd_schur<<<n_active, 64, fd_schur_lds(M), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_schur");
+  TAPS_TRY(prof_end(h, sslot, n_active * fd_schur_flops(M), n_active * fd_schur_bytes(M), stream));
   k_fd_vectors<<<n_active, 64, fd_vectors_lds(M), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_vectors");
   TAPS_TRY(prof_end(h, slot, n_active * fd_eig_flops(M), n_active * fd_eig_bytes(M), stream));

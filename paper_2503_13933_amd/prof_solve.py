@@ -3,8 +3,8 @@
 diagonalisation (--solver fastdiag, the default) or the block LU, followed by
 a plain device copy of --copy-mib MiB (torch's copy kernel) whose known size
 calibrates the memory counters.  Prints the launches, event-timed kernel time
-and algorithmic flops and bytes of the solve, eigen and contraction kernel
-families over the sweep.  Meant to run under rocprofv3:
+and algorithmic flops and bytes of the solve, eigen, real Schur and
+contraction kernel families over the sweep.  Meant to run under rocprofv3:
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- \\
         python3 paper_2503_13933_amd/prof_solve.py
@@ -42,7 +42,8 @@ def main():
     sw, rho = capi.taps_als_batched(h, [p.struct for p in probs], U, 0.0, args.sweeps)
     torch.cuda.synchronize()
     capi.taps_profile_enable(h, False)
-    for name, fam in (("solve", capi.PROF_SOLVE), ("eig", capi.PROF_EIG), ("contract", capi.PROF_CONTRACT)):
+    for name, fam in (("solve", capi.PROF_SOLVE), ("eig", capi.PROF_EIG), ("schur", capi.PROF_SCHUR),
+                      ("contract", capi.PROF_CONTRACT)):
         n_l, ms, fl, by = capi.taps_profile_read(h, fam)
         print(f"family {name}: launches {n_l} kernel ms {ms:.3f} algorithmic flops {fl:.6e} bytes {by:.6e}",
               flush=True)
