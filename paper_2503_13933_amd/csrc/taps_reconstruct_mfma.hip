@@ -83,7 +83,7 @@ __global__ void k_recon_convert(int n, int M, int Mp, const double* __restrict__
 struct Reduce {
   float mx;
   double ss;
-  unsigned long long cnt;  // wave-uniform: counted with ballots
+  unsigned int cnt;  // this lane's count, summed over the wave at the end
 };
 
 // Epilogue of one j tile.  The products are formed transposed (streamed
@@ -118,7 +118,7 @@ __device__ inline void epilogue(const f32x4 (&acc)[4], int ibase, int c16, int j
         for (int q = 0; q < 4; ++q) {
           r.mx = fmaxf(r.mx, v[q]);
           ss = fmaf(v[q], v[q], ss);
-          r.cnt += __popcll(__ballot(v[q] > thrf));
+          r.cnt += (v[q] > thrf) ? 1u : 0u;
         }
       } else {
 #pragma unroll
@@ -126,7 +126,7 @@ __device__ inline void epilogue(const f32x4 (&acc)[4], int ibase, int c16, int j
           const bool ok = i < n0 && j0 + q < n1;
           r.mx = ok ? fmaxf(r.mx, v[q]) : r.mx;
           ss = ok ? fmaf(v[q], v[q], ss) : ss;
-          r.cnt += __popcll(__ballot(ok && v[q] > thrf));
+          r.cnt += (ok && v[q] > thrf) ? 1u : 0u;
         }
       }
       r.ss += double(ss);
@@ -140,6 +140,7 @@ __device__ void reduce_store(Reduce r, double* rec) {
   for (int off = 32; off > 0; off >>= 1) {
     r.mx = fmaxf(r.mx, __shfl_xor(r.mx, off));
     r.ss += __shfl_xor(r.ss, off);
+    r.cnt += __shfl_xor(r.cnt, off);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int 
       b[ks] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb1, off, 0, 0));
     }
   };
-  Reduce red{-INFINITY, 0.0, 0ull};
+  Reduce red{-INFINITY, 0.0, 0u};
   const bool rows_full = ibase + kRowsWave <= n0;
   auto tile = [&](int jt, const bf16x8* b) {
     f32x4 acc[4];
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int 
       b[4 * q4 + 3] = v.w;
     }
   };
-  Reduce red{-INFINITY, 0.0, 0ull};
+  Reduce red{-INFINITY, 0.0, 0u};
   const bool rows_full = ibase + kRowsWave <= n0;
   auto tile = [&](int jt, const float* b) {
     f32x4 acc[4];

@@ -100,3 +100,34 @@ def test_batch_rejects_mismatched_modes(env):
     Ub = b.factors(W.initial_factors([x.ax for x in b.axes], 4, 1))
     with pytest.raises(capi.TapsError):
         capi.taps_als_batched(h, [a.struct, b.struct], [Ua, Ub], 0.0, 1)
+
+
+def test_profile_families_of_the_fast_diagonalisation(env):
+    """Kernel timing: one batched sweep with the fast diagonalisation records
+    one launch per dim in the banded-stage (solve), eigen-stage and real-Schur
+    families, with the algorithmic work the C-ABI documents; the Schur kernel
+    is timed inside the eigen-stage bracket, so its time is the smaller."""
+    torch, capi, problem, h = env
+    capi.taps_set_tuning(h, solver=capi.SOLVER_FAST_DIAG)
+    try:
+        cases = [W.heat_slab(40, 33, 10, 21, M=6, seed=21 + i) for i in range(3)]
+        devs = [problem.heat_slab(h, c) for c in cases]
+        Ub = [d.factors(W.initial_factors(c.axes, c.M, c.seed)) for c, d in zip(cases, devs)]
+        torch.cuda.synchronize()
+        capi.taps_profile_enable(h, True)
+        capi.taps_als_batched(h, [d.struct for d in devs], Ub, 0.0, 1)
+        torch.cuda.synchronize()
+        capi.taps_profile_enable(h, False)
+        D, M, B = 4, 6, len(cases)
+        n_s, ms_s, fl_s, by_s = capi.taps_profile_read(h, capi.PROF_SOLVE)
+        n_e, ms_e, fl_e, by_e = capi.taps_profile_read(h, capi.PROF_EIG)
+        n_c, ms_c, fl_c, by_c = capi.taps_profile_read(h, capi.PROF_SCHUR)
+        _say(f"profile: solve {n_s} x {ms_s:.3f} ms, eig {n_e} x {ms_e:.3f} ms, schur {n_c} x {ms_c:.3f} ms")
+        assert n_s == n_e == n_c == D
+        assert 0.0 < ms_c < ms_e
+        assert fl_c == pytest.approx(D * B * 25.0 * M ** 3, rel=1e-12)
+        assert by_c == pytest.approx(D * B * 24.0 * M ** 2, rel=1e-12)
+        assert fl_e == pytest.approx(D * B * 44.0 * M ** 3, rel=1e-12)
+        assert fl_s > 0.0 and by_s > 0.0
+    finally:
+        capi.taps_set_tuning(h, solver=capi.SOLVER_BLOCK_LU)
