@@ -848,7 +848,8 @@ struct IjWalk {
 //     to the workspace, with the eigenvalues.
 // LDS in M x L real units (L = M rounded up to odd, so that column walks over
 // the lanes hit distinct banks): inverse 3 (two Gauss-Jordan buffers, C2),
-// schur 2 (Hr, Zr), vectors 6 (complex H, Wv, Z; C1^{-1} at the end).
+// schur 2 (Hr, Zr; there at the largest M, L = kFdMaxM + 1), vectors 6
+// (complex H, Wv, Z; C1^{-1} at the end).
 // info word: 0, -1 (C1 singular) or -2 (no convergence); a later kernel
 // skips a system whose info is set.
 // Orders the LDS accesses of one wave for the compiler.  A workgroup of one
@@ -985,12 +986,16 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
   if (lane == 0) A.info[0] = s_fail ? -1 : 0;
 }
 
+// (the Schur kernel's LDS layout is fixed at the largest M, row stride
+// kFdMaxM + 1 (odd) and Zr at a fixed offset, so that every row and column
+// offset of the bulge chase is an immediate of the LDS instructions)
+constexpr int kSchurL = kFdMaxM | 1;
 __device__ void fd_eig_schur(const SolveArgs& A) {
   extern __shared__ double lds[];
-  const int M = A.M, MM = M * M, L = M | 1, lane = threadIdx.x;
-  const int LL = M * L;
-  double* Hr = lds;                                   // unit 0
-  double* Zr = lds + LL;                              // unit 1
+  const int M = A.M, MM = M * M, lane = threadIdx.x;
+  constexpr int L = kSchurL;
+  double* Hr = lds;                                   // kFdMaxM x L
+  double* Zr = lds + kFdMaxM * L;                     // kFdMaxM x L
   __shared__ double v[64];                            // Householder vector
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
@@ -1819,7 +1824,7 @@ __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { f
 
 // dynamic LDS of the three eigen-stage kernels, in M x L real units
 size_t fd_inverse_lds(int M) { return size_t(3) * M * (M | 1) * 8; }
-size_t fd_schur_lds(int M) { return size_t(2) * M * (M | 1) * 8; }
+size_t fd_schur_lds(int) { return size_t(2) * kFdMaxM * kSchurL * 8; }
 size_t fd_vectors_lds(int M) { return size_t(6) * M * (M | 1) * 8; }
 size_t fd_solve_lds(int M, int s) {
   const int w = 2 * s + 1;
