@@ -170,7 +170,6 @@ __device__ inline void lgram_partial(int ctile, int split, int n, int Rc, int M,
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     // 16 rows per pass, all operands loaded before the four steps
-#pragma unroll 2
     for (int i0 = rbeg; i0 < rend; i0 += 16) {
       double a[4], b[4][4];
 #pragma unroll
@@ -187,10 +186,8 @@ __device__ inline void lgram_partial(int ctile, int split, int n, int Rc, int M,
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (ct0 + c >= nct) break;
-          acc[c] = mfma_f64(a[u], b[u][c], acc[c]);
-        }
+        for (int c = 0; c < 4; ++c)
+          if (ct0 + c < nct) acc[c] = mfma_f64(a[u], b[u][c], acc[c]);   // guard, not exit: stays unrolled
       }
     }
 #pragma unroll
@@ -300,7 +297,6 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     // 16 load columns per pass, all operands loaded before the four steps
-#pragma unroll 2
     for (int c0 = 0; c0 < Rc; c0 += 16) {
       double a[4], b[4][4];
 #pragma unroll
@@ -317,10 +313,8 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (ct0 + c >= nct) break;
-          acc[c] = mfma_f64(a[u], b[u][c], acc[c]);
-        }
+        for (int c = 0; c < 4; ++c)
+          if (ct0 + c < nct) acc[c] = mfma_f64(a[u], b[u][c], acc[c]);   // guard, not exit: stays unrolled
       }
     }
 #pragma unroll
@@ -390,10 +384,11 @@ __device__ inline void residual_part(int chunk, int n, int M, int s, int K, cons
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          if (ct0 + c >= nct) break;
-          const int m = (ct0 + c) * 16 + (lane & 15);
-          const double b = (m < M && q < M) ? sC[m * L + q] : 0.0;
-          acc[c] = mfma_f64(a, b, acc[c]);
+          if (ct0 + c < nct) {
+            const int m = (ct0 + c) * 16 + (lane & 15);
+            const double b = (m < M && q < M) ? sC[m * L + q] : 0.0;
+            acc[c] = mfma_f64(a, b, acc[c]);
+          }
         }
       }
     }

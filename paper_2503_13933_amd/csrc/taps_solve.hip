@@ -1681,11 +1681,12 @@ __device__ void fd_solve_body(const SolveArgs& A) {
         v4d are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < kKS; ++u) {
-          if (u >= ksteps) break;
-          const int q = 4 * u + (lane >> 4);
-          const cplx hb = (q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
-          are = mfma16x16x4(av[u], hb.r, are);
-          aim = mfma16x16x4(av[u], hb.i, aim);
+          if (u < ksteps) {   // (a guard, not a loop exit: the loop stays fully unrolled)
+            const int q = 4 * u + (lane >> 4);
+            const cplx hb = (q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
+            are = mfma16x16x4(av[u], hb.r, are);
+            aim = mfma16x16x4(av[u], hb.i, aim);
+          }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1781,11 +1782,12 @@ __device__ void fd_solve_body(const SolveArgs& A) {
         v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < kKS; ++u) {
-          if (u >= ksteps) break;
-          const int m = 4 * u + (lane >> 4);
-          const cplx hb = (m < M && qb < M) ? sH[m * M + qb] : cmk(0.0, 0.0);
-          acc = mfma16x16x4(yr[u], hb.r, acc);
-          acc = mfma16x16x4(yi[u], hb.i, acc);
+          if (u < ksteps) {
+            const int m = 4 * u + (lane >> 4);
+            const cplx hb = (m < M && qb < M) ? sH[m * M + qb] : cmk(0.0, 0.0);
+            acc = mfma16x16x4(yr[u], hb.r, acc);
+            acc = mfma16x16x4(yi[u], hb.i, acc);
+          }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
