@@ -337,10 +337,13 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
 // is formed directly as the A operands of v_mfma_f64_16x16x4f64 (lane l:
 // row l%16, column 4kk + l/16) and multiplied by (C^k)^T on the matrix cores,
 // up to four 16-column tiles of R per pass.
-__device__ inline void residual_part(int chunk, int n, int M, int s, int K, const double* __restrict__ band_,
-                                     const double* __restrict__ C_, const double* __restrict__ U_,
-                                     const double* __restrict__ Q_, const uint8_t* __restrict__ fixed_,
-                                     double* __restrict__ part_) {
+// (BW = 2(2s+1)+1 band entries per row, a template argument so that the
+// band coefficients and the A-operand sums are exactly BW long)
+template <int BW>
+__device__ inline void residual_part_bw(int chunk, int n, int M, int K, const double* __restrict__ band_,
+                                        const double* __restrict__ C_, const double* __restrict__ U_,
+                                        const double* __restrict__ Q_, const uint8_t* __restrict__ fixed_,
+                                        double* __restrict__ part_) {
   const auto band = gp(band_);
   const auto C = gp(C_);
   const auto U = gp(U_);
@@ -348,8 +351,8 @@ __device__ inline void residual_part(int chunk, int n, int M, int s, int K, cons
   const auto fixed = gp(fixed_);
   const auto part = gp(part_);
   extern __shared__ double lds[];
-  constexpr int kMaxBW = 2 * (2 * TAPS_MAX_S + 1) + 1;
-  const int w = 2 * s + 1, BW = 2 * w + 1, L = M | 1;
+  constexpr int w = (BW - 1) / 2;
+  const int L = M | 1;
   const int r0 = chunk * kResRows;
   const int rows = min(kResRows, n - r0);
   const int hr = kResRows + 2 * w;
@@ -369,18 +372,20 @@ __device__ inline void residual_part(int chunk, int n, int M, int s, int K, cons
       __syncthreads();   // sU staged / sC free
       for (int r = wv; r < M; r += 4)
         for (int c = lane; c < M; c += 64) sC[r * L + c] = C[(long(k) * M + r) * M + c];
-      double bc[kMaxBW];
-      const auto brow = band + (long(k) * n + r0 + i_a) * BW;
+      double bc[BW];
+      const auto brow = band + (long(k) * n + r0 + min(i_a, rows - 1)) * BW;
 #pragma unroll
-      for (int o = 0; o < kMaxBW; ++o) bc[o] = (o < BW && i_a < rows) ? brow[o] : 0.0;
+      for (int o = 0; o < BW; ++o) {
+        const double bv = brow[o];
+        bc[o] = (i_a < rows) ? bv : 0.0;
+      }
       __syncthreads();
       for (int kk = 0; kk < ksteps; ++kk) {
         const int q = 4 * kk + (lane >> 4);
         double a = 0.0;
         if (q < M) {
 #pragma unroll
-          for (int o = 0; o < kMaxBW; ++o)
-            if (o < BW) a += bc[o] * sU[(i_a + o) * L + q];
+          for (int o = 0; o < BW; ++o) a += bc[o] * sU[(i_a + o) * L + q];
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -420,6 +425,18 @@ __device__ inline void residual_part(int chunk, int n, int M, int s, int K, cons
   if (tid == 0) {
     part[0] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
     part[1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+  }
+}
+
+__device__ inline void residual_part(int chunk, int n, int M, int s, int K, const double* __restrict__ band,
+                                     const double* __restrict__ C, const double* __restrict__ U,
+                                     const double* __restrict__ Q, const uint8_t* __restrict__ fixed,
+                                     double* __restrict__ part) {
+  switch (s) {
+    case 0: residual_part_bw<3>(chunk, n, M, K, band, C, U, Q, fixed, part); break;
+    case 1: residual_part_bw<7>(chunk, n, M, K, band, C, U, Q, fixed, part); break;
+    case 2: residual_part_bw<11>(chunk, n, M, K, band, C, U, Q, fixed, part); break;
+    default: residual_part_bw<15>(chunk, n, M, K, band, C, U, Q, fixed, part); break;
   }
 }
 
