@@ -37,7 +37,7 @@ struct BProb {
   double* outs;  // res (D+2), then backward error per dim (D)
 };
 
-__global__ void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
+__global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
   const BProb& q = P[act[blockIdx.y]];
   const int n = q.n[e];
   if (int(blockIdx.x) * kGramRows >= n) return;
@@ -59,7 +59,7 @@ __global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__
     sum_parts(blockIdx.x * kVB + u, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
 }
 
-__global__ void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
+__global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
   const BProb& q = P[act[blockIdx.z]];
   if (int(blockIdx.x) * kLgCols >= q.Rc[e] || int(blockIdx.y) * kLgRows >= q.n[e]) return;
   lgram_partial(blockIdx.x, blockIdx.y, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
@@ -92,7 +92,7 @@ __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* _
   for (int u = 0; u < kVB; ++u) load_weights(blockIdx.x * kVB + u, WA[long(b) * D + d], P[b].Wt);
 }
 
-__global__ void kb_force(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
+__global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
   const BProb& q = P[act[blockIdx.y]];
   if (int(blockIdx.x) * kQRows >= q.n[d]) return;
   force(blockIdx.x, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);

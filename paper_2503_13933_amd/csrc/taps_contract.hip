@@ -9,7 +9,7 @@ namespace {
 
 using namespace taps::dev;
 
-__global__ void k_gram_partial(int n, int M, int s, int K, const double* __restrict__ band,
+__global__ __launch_bounds__(256) void k_gram_partial(int n, int M, int s, int K, const double* __restrict__ band,
                                const double* __restrict__ U, double* __restrict__ part) {
   gram_partial(blockIdx.x, n, M, s, K, band, U, part + long(blockIdx.x) * K * M * M);
 }
@@ -18,7 +18,7 @@ __global__ void k_sum_parts(int nparts, long len, const double* __restrict__ par
   sum_parts(blockIdx.x, nparts, len, part, out);
 }
 
-__global__ void k_lgram_partial(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ U,
+__global__ __launch_bounds__(256) void k_lgram_partial(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ U,
                                 double* __restrict__ part) {
   lgram_partial(blockIdx.x, blockIdx.y, n, Rc, M, F, U, part);
 }
@@ -28,7 +28,7 @@ __global__ void k_couple(CoupleArgs A, double* __restrict__ C) { couple(blockIdx
 __global__ void k_load_terms(WeightArgs A) { load_terms(blockIdx.x, A); }
 __global__ void k_load_weights(WeightArgs A, double* __restrict__ Wt) { load_weights(blockIdx.x, A, Wt); }
 
-__global__ void k_force(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ Wt,
+__global__ __launch_bounds__(256) void k_force(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ Wt,
                         double* __restrict__ Q) {
   force(blockIdx.x, n, Rc, M, F, Wt, Q);
 }

@@ -296,9 +296,9 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
     rv4d acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
-    // 16 load columns per pass, all operands loaded before the four steps
-    for (int c0 = 0; c0 < Rc; c0 += 16) {
-      double a[4], b[4][4];
+    // 16 load columns per pass, all operands of a pass loaded together and
+    // the next pass's requested before this pass's products
+    auto load = [&](int c0, double (&a)[4], double (&b)[4][4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kc = c0 + 4 * u + (lane >> 4);
@@ -310,6 +310,18 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
           b[u][c] = (ok && ct0 + c < nct && m < M) ? Wt[long(kc) * M + m] : 0.0;
         }
       }
+    };
+    double an[4], bn[4][4];
+    load(0, an, bn);
+    for (int c0 = 0; c0 < Rc; c0 += 16) {
+      double a[4], b[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = an[u];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[u][c] = bn[u][c];
+      }
+      if (c0 + 16 < Rc) load(c0 + 16, an, bn);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
