@@ -80,9 +80,7 @@ __global__ void kb_couple(const BProb* __restrict__ P, const CoupleArgs* __restr
 }
 
 __global__ void kb_load_terms(const WeightArgs* __restrict__ WA, const int* __restrict__ act, int d, int D) {
-  const WeightArgs& A = WA[long(act[blockIdx.y]) * D + d];
-#pragma unroll
-  for (int u = 0; u < kVB; ++u) load_terms(blockIdx.x * kVB + u, A);
+  load_terms_n<kVB>(blockIdx.x * kVB, WA[long(act[blockIdx.y]) * D + d]);
 }
 
 __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* __restrict__ WA,

@@ -243,20 +243,44 @@ struct WeightArgs {
 // of dim d: P[q][m] = prod_{e != d} L_e[col_e(r)][m], r = idx[q].  Every
 // thread's loads depend only on its own term, so the whole table fills in a
 // few memory latencies.
-__device__ inline void load_terms(int tblock, const WeightArgs& A) {
-  const int t = tblock * blockDim.x + threadIdx.x;   // R M < 2^31
-  const int M = A.M;
-  if (t >= A.R * M) return;
-  const int q = t / M, m = t - q * M;
-  const int r = A.ptr ? gp(A.idx)[q] : q;
-  double prod = 1.0;
+// NS consecutive slices of blockDim.x items from slice s0 on, every load of
+// a kind issued for all slices before any is used (the index, column-map and
+// load-Gram reads form a dependent chain per item), the products stored last.
+template <int NS>
+__device__ inline void load_terms_n(int s0, const WeightArgs& A) {
+  const int M = A.M, RM = A.R * M;   // R M < 2^31
+  if (RM <= 0 || s0 * int(blockDim.x) >= RM) return;
+  int t[NS], m[NS], r[NS];
+  double prod[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    t[u] = (s0 + u) * blockDim.x + threadIdx.x;
+    const int tc = min(t[u], RM - 1);
+    const int q = tc / M;
+    m[u] = tc - q * M;
+    r[u] = q;
+    prod[u] = 1.0;
+  }
+  if (A.ptr) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) r[u] = gp(A.idx)[r[u]];
+  }
   for (int e = 0; e < A.D; ++e) {
     if (e == A.d) continue;
-    const int ce = A.col[e] ? gp(A.col[e])[r] : r;
-    prod *= gp(A.lgram[e])[long(ce) * M + m];
+    int ce[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) ce[u] = A.col[e] ? gp(A.col[e])[r[u]] : r[u];
+    double lv[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) lv[u] = gp(A.lgram[e])[long(ce[u]) * M + m[u]];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) prod[u] *= lv[u];
   }
-  gp(A.P)[t] = prod;
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+    if (t[u] < RM) gp(A.P)[t[u]] = prod[u];
 }
+__device__ inline void load_terms(int tblock, const WeightArgs& A) { load_terms_n<1>(tblock, A); }
 
 // Wt[c][m] = sum of P[q][m] over the terms q of group c (ptr[c] .. ptr[c+1]),
 // in term order; independent contiguous loads.
