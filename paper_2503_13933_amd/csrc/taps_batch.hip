@@ -54,9 +54,7 @@ constexpr int kVB = 8;
 __global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
   const BProb& q = P[act[blockIdx.y]];
   const int chunks = (q.n[e] + kGramRows - 1) / kGramRows;
-#pragma unroll
-  for (int u = 0; u < kVB; ++u)
-    sum_parts(blockIdx.x * kVB + u, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
+  sum_parts_n<kVB>(blockIdx.x * kVB, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
 }
 
 __global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
@@ -68,15 +66,13 @@ __global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict_
 __global__ void kb_lgram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
   const BProb& q = P[act[blockIdx.y]];
   const int splits = (q.n[e] + kLgRows - 1) / kLgRows;
-#pragma unroll
-  for (int u = 0; u < kVB; ++u) sum_parts(blockIdx.x * kVB + u, splits, long(q.Rc[e]) * q.M, q.lpart, q.lgram[e]);
+  sum_parts_n<kVB>(blockIdx.x * kVB, splits, long(q.Rc[e]) * q.M, q.lpart, q.lgram[e]);
 }
 
 __global__ void kb_couple(const BProb* __restrict__ P, const CoupleArgs* __restrict__ CA,
                           const int* __restrict__ act, int d, int D) {
   const int b = act[blockIdx.y];
-#pragma unroll
-  for (int u = 0; u < kVB; ++u) couple(blockIdx.x * kVB + u, CA[long(b) * D + d], P[b].C);
+  couple_n<kVB>(blockIdx.x * kVB, CA[long(b) * D + d], P[b].C);
 }
 
 __global__ void kb_load_terms(const WeightArgs* __restrict__ WA, const int* __restrict__ act, int d, int D) {

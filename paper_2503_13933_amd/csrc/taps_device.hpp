@@ -137,15 +137,30 @@ __device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const
 }
 
 // out[t] = sum_b part[b][t] in block order, for t in this block's range.
-__device__ inline void sum_parts(int tblock, int nparts, long len, const double* __restrict__ part_,
-                                 double* __restrict__ out_) {
+template <int NS>
+__device__ inline void sum_parts_n(int s0, int nparts, long len, const double* __restrict__ part_,
+                                   double* __restrict__ out_) {
   const auto part = gp(part_);
   const auto out = gp(out_);
-  const long t = tblock * long(blockDim.x) + threadIdx.x;
-  if (t >= len) return;
-  double acc = 0.0;
-  for (int b = 0; b < nparts; ++b) acc += part[long(b) * len + t];
-  out[t] = acc;
+  if (s0 * long(blockDim.x) >= len) return;
+  long t[NS];
+  double acc[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    t[u] = (s0 + u) * long(blockDim.x) + threadIdx.x;
+    acc[u] = 0.0;
+  }
+  for (int b = 0; b < nparts; ++b) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) acc[u] += part[long(b) * len + min(t[u], len - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+    if (t[u] < len) out[t[u]] = acc[u];
+}
+__device__ inline void sum_parts(int tblock, int nparts, long len, const double* __restrict__ part,
+                                 double* __restrict__ out) {
+  sum_parts_n<1>(tblock, nparts, len, part, out);
 }
 
 // Partial of L = F^T U for load columns [ctile*kLgCols, +kLgCols) over rows of
@@ -212,23 +227,43 @@ struct CoupleArgs {
 
 // C^k_d[m][n] = sum over terms whose dim-d matrix is k of
 // gamma * prod_{e != d} G_e^{kind(term, e)}[m][n]  (Hadamard product).
-__device__ inline void couple(int tblock, const CoupleArgs& A, double* __restrict__ C) {
-  const int t = tblock * blockDim.x + threadIdx.x;
-  const int MM = A.M * A.M;
-  if (t >= A.Kd * MM) return;
-  const int k = t / MM, mn = t % MM;
-  double acc = 0.0;
+// NS consecutive slices of blockDim.x entries from slice s0 on, stored after
+// all their loads (one store per slice would otherwise order the next
+// slice's loads behind it).
+template <int NS>
+__device__ inline void couple_n(int s0, const CoupleArgs& A, double* __restrict__ C) {
+  const int MM = A.M * A.M, len = A.Kd * MM;
+  if (s0 * int(blockDim.x) >= len) return;
+  int t[NS], k[NS], mn[NS];
+  double acc[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    t[u] = (s0 + u) * blockDim.x + threadIdx.x;
+    const int tc = min(t[u], len - 1);
+    k[u] = tc / MM;
+    mn[u] = tc - k[u] * MM;
+    acc[u] = 0.0;
+  }
   for (int tau = 0; tau < A.T; ++tau) {
-    if (A.tk[tau][A.d] != k) continue;
-    double prod = A.gamma[tau];
+    const int kt = A.tk[tau][A.d];
+    double prod[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) prod[u] = A.gamma[tau];
     for (int e = 0; e < A.D; ++e) {
       if (e == A.d) continue;
-      prod *= gp(A.gram[e])[long(A.tk[tau][e]) * MM + mn];
+      const auto g = gp(A.gram[e]) + long(A.tk[tau][e]) * MM;
+#pragma unroll
+      for (int u = 0; u < NS; ++u) prod[u] *= g[mn[u]];
     }
-    acc += prod;
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      if (k[u] == kt) acc[u] += prod[u];
   }
-  gp(C)[t] = acc;
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+    if (t[u] < len) gp(C)[t[u]] = acc[u];
 }
+__device__ inline void couple(int tblock, const CoupleArgs& A, double* __restrict__ C) { couple_n<1>(tblock, A, C); }
 
 struct WeightArgs {
   int D, M, R, d, Rc;
