@@ -534,12 +534,26 @@ __device__ inline void balance(const BalanceArgs& A, unsigned scale_mask = 0) {
   __shared__ double fac[TAPS_MAX_DIMS][64];
   const int m = threadIdx.x & 63, ph = threadIdx.x >> 6, M = A.M;
   for (int e = 0; e < A.D; ++e) {
+    // rows ph, ph+4, ... of column m, eight rows loaded before they are used
+    const auto Ue = gp(A.U[e]);
+    const int n = A.n[e];
     double acc = 0.0;
-    if (m < M)
-      for (int i = ph; i < A.n[e]; i += 4) {
-        const double v = A.U[e][long(i) * M + m];
-        acc += v * v;
+    if (m < M) {
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
+      int i = ph;
+      for (; i + 28 < n; i += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Ue[long(i + 4 * u) * M + m];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a4[u & 3] += v[u] * v[u];
       }
+      for (; i < n; i += 4) {
+        const double v = Ue[long(i) * M + m];
+        a4[0] += v * v;
+      }
+      acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    }
     part[ph][m] = acc;
     __syncthreads();
     if (ph == 0) fac[e][m] = sqrt(((part[0][m] + part[1][m]) + part[2][m]) + part[3][m]);
@@ -559,16 +573,27 @@ __device__ inline void balance(const BalanceArgs& A, unsigned scale_mask = 0) {
   if (m < M)
     for (int e = 0; e < A.D; ++e) {
       const double f = fac[e][m];
-      for (int i = ph; i < A.n[e]; i += 4) A.U[e][long(i) * M + m] *= f;
+      const auto Ue = gp(A.U[e]);
+      const int n = A.n[e];
+      int i = ph;
+      for (; i + 28 < n; i += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Ue[long(i + 4 * u) * M + m];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Ue[long(i + 4 * u) * M + m] = v[u] * f;
+      }
+      for (; i < n; i += 4) Ue[long(i) * M + m] *= f;
     }
   for (int e = 0; e < A.D; ++e) {
     if (!(scale_mask & (1u << e))) continue;
     const int MM = M * M;
+    const auto G = gp(A.gram[e]), LG = gp(A.lgram[e]);
     for (int t = threadIdx.x; t < A.K[e] * MM; t += blockDim.x) {
       const int r = t - (t / MM) * MM, mm = r / M, nn = r - (r / M) * M;
-      A.gram[e][t] *= fac[e][mm] * fac[e][nn];
+      G[t] *= fac[e][mm] * fac[e][nn];
     }
-    for (int t = threadIdx.x; t < A.Rc[e] * M; t += blockDim.x) A.lgram[e][t] *= fac[e][t - (t / M) * M];
+    for (int t = threadIdx.x; t < A.Rc[e] * M; t += blockDim.x) LG[t] *= fac[e][t - (t / M) * M];
   }
 }
 
