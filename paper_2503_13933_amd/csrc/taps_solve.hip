@@ -990,12 +990,16 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
 // kFdMaxM + 1 (odd) and Zr at a fixed offset, so that every row and column
 // offset of the bulge chase is an immediate of the LDS instructions)
 constexpr int kSchurL = kFdMaxM | 1;
+// the sink takes the three stores of each lane a pass leaves alone: row pass
+// at lane + {0, L, 2L}, column passes at 3 lane + {0, 1, 2}
+constexpr int kSchurSink = 2 * kSchurL + 64 > 3 * 64 ? 2 * kSchurL + 64 : 3 * 64;
 __device__ void fd_eig_schur(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, lane = threadIdx.x;
   constexpr int L = kSchurL;
   double* Hr = lds;                                   // kFdMaxM x L
   double* Zr = lds + kFdMaxM * L;                     // kFdMaxM x L
+  double* Dm = lds + 2 * kFdMaxM * L;                 // kSchurSink: stores of lanes a chase step leaves alone
   __shared__ double v[64];                            // Householder vector
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
@@ -1151,22 +1155,20 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   // Householder vector of (x, y, z): (I - tau u u^T)(x, y, z)^T = (beta, 0, 0)^T,
   // tau = (beta - x) / beta and u = (1, y, z) / (x - beta) from one reciprocal
   // (norm and reciprocal by Newton iterations from the hardware estimates:
-  // no range scaling, the entries are far from under- and overflow)
+  // no range scaling, the entries are far from under- and overflow).  With
+  // y = z = 0 the reflector is the identity (tau = 0); that case is a select
+  // on a harmless stand-in norm, not a branch.
   auto house = [](double x, double y, double z, double& tau, double& u1, double& u2) {
-    if (y == 0.0 && z == 0.0) {
-      tau = 0.0;
-      u1 = u2 = 0.0;
-      return;
-    }
-    const double q = x * x + y * y + z * z;
+    const bool ident = y == 0.0 && z == 0.0;
+    const double q = ident ? 1.0 : x * x + y * y + z * z;
     const double nrm = nr_sqrt(q);
     const double beta = x >= 0.0 ? -nrm : nrm;
-    const double xb = x - beta;
+    const double xb = x - beta;   // |xb| >= nrm > 0
     const double inv = nr_rcp(beta * xb);
-    tau = -xb * xb * inv;
     const double sc = beta * inv;
-    u1 = y * sc;
-    u2 = z * sc;
+    tau = ident ? 0.0 : -xb * xb * inv;
+    u1 = ident ? 0.0 : y * sc;
+    u2 = ident ? 0.0 : z * sc;
   };
   // a double held by lane l, to every lane (l wave-uniform)
   auto from_lane = [](double x, int l) -> double {
@@ -1266,47 +1268,45 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
       // the reflector is known, so those loads overlap its computation; the
       // column operands are read after the row pass has stored (one wave:
       // its LDS accesses complete in issue order), and the Zr pass fills that
-      // wait.  Loads run on every lane (lanes past M on row / column M - 1);
-      // only stores are masked (row pass: columns c0..M-1).
+      // wait.  Loads run on every lane (lanes past M on row / column M - 1).
+      // Every lane stores too: a lane outside a pass (row pass: columns
+      // c0..M-1; column pass: rows 0..r1; Zr: rows 0..M-1) stores into the
+      // sink, so the step has no branch, and a reflector that is the identity
+      // (tau = 0) stores the values it read.
       const int c0 = max(lo, k - 1), r1 = min(k + 3, hi);
       const int lm = min(lane, M - 1);
       const double a0 = Hr[k * L + lm], a1 = Hr[(k + 1) * L + lm], a2 = Hr[(k + 2) * L + lm];
       const double z0 = Zr[lm * L + k], z1 = Zr[lm * L + k + 1], z2 = Zr[lm * L + k + 2];
       double tau, u1, u2;
       house(x, y, z, tau, u1, u2);
-      if (tau != 0.0) {
-        {
-          const double w = tau * (a0 + u1 * a1 + u2 * a2);
-          if (lane >= c0 && lane < M) {
-            Hr[k * L + lane] = a0 - w;
-            Hr[(k + 1) * L + lane] = a1 - w * u1;
-            Hr[(k + 2) * L + lane] = a2 - w * u2;
-          }
-        }
-        const double h0 = Hr[lm * L + k], h1 = Hr[lm * L + k + 1], h2 = Hr[lm * L + k + 2];
-        {
-          const double w = tau * (z0 + u1 * z1 + u2 * z2);
-          if (lane < M) {
-            Zr[lane * L + k] = z0 - w;
-            Zr[lane * L + k + 1] = z1 - w * u1;
-            Zr[lane * L + k + 2] = z2 - w * u2;
-          }
-        }
-        const double w = tau * (h0 + u1 * h1 + u2 * h2);
-        const double col = h0 - w;
-        if (lane <= r1) {
-          Hr[lane * L + k] = col;
-          Hr[lane * L + k + 1] = h1 - w * u1;
-          Hr[lane * L + k + 2] = h2 - w * u2;
-        }
-        x = from_lane(col, k + 1);
-        y = from_lane(col, k + 2);
-        z = (k + 3 <= hi) ? from_lane(col, k + 3) : 0.0;
-      } else {
-        x = Hr[(k + 1) * L + k];
-        y = Hr[(k + 2) * L + k];
-        z = (k + 3 <= hi) ? Hr[(k + 3) * L + k] : 0.0;
+      {
+        const double w = tau * (a0 + u1 * a1 + u2 * a2);
+        double* const p = (lane >= c0 && lane < M) ? Hr + k * L + lane : Dm + lane;
+        p[0] = a0 - w;
+        p[L] = a1 - w * u1;
+        p[2 * L] = a2 - w * u2;
       }
+      const double h0 = Hr[lm * L + k], h1 = Hr[lm * L + k + 1], h2 = Hr[lm * L + k + 2];
+      {
+        const double w = tau * (z0 + u1 * z1 + u2 * z2);
+        double* const p = lane < M ? Zr + lane * L + k : Dm + 3 * lane;
+        p[0] = z0 - w;
+        p[1] = z1 - w * u1;
+        p[2] = z2 - w * u2;
+      }
+      const double w = tau * (h0 + u1 * h1 + u2 * h2);
+      const double col = h0 - w;
+      {
+        double* const p = lane <= r1 ? Hr + lane * L + k : Dm + 3 * lane;
+        p[0] = col;
+        p[1] = h1 - w * u1;
+        p[2] = h2 - w * u2;
+      }
+      // the next bulge column: rows k+1..k+3 of column k (k + 3 <= hi + 1 <= M)
+      x = from_lane(col, k + 1);
+      y = from_lane(col, k + 2);
+      const double z3 = from_lane(col, k + 3);
+      z = (k + 3 <= hi) ? z3 : 0.0;
       wave_sync();
     }
     {
@@ -1826,7 +1826,7 @@ __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { f
 
 // dynamic LDS of the three eigen-stage kernels, in M x L real units
 size_t fd_inverse_lds(int M) { return size_t(3) * M * (M | 1) * 8; }
-size_t fd_schur_lds(int) { return size_t(2) * kFdMaxM * kSchurL * 8; }
+size_t fd_schur_lds(int) { return (size_t(2) * kFdMaxM * kSchurL + kSchurSink) * 8; }
 size_t fd_vectors_lds(int M) { return size_t(6) * M * (M | 1) * 8; }
 size_t fd_solve_lds(int M, int s) {
   const int w = 2 * s + 1;
