@@ -1546,23 +1546,28 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
             const double d = piv.r * piv.r + piv.i * piv.i;
             if (!(d > 0.0) || !(d < INFINITY)) info = info ? info : k + 1;
             const cplx inv = cscale(cconj(piv), nr_rcp(d));
+            // row k divided by its pivot (the w upper entries and the reduced
+            // right-hand side); the rows below subtract their column-k entry
+            // times it, which needs no multiplier per row
+            cplx urow[W1];
+#pragma unroll
+            for (int cc = 1; cc < W1; ++cc) urow[cc] = cmul(inv, win[p][(p + cc) % W1]);
+            const cplx yk = cmul(inv, rhs[p]);
 #pragma unroll
             for (int r = 1; r < W1; ++r) {
               const int rs = (p + r) % W1;
-              const cplx l = cmul(win[rs][p], inv);
+              const cplx l = win[rs][p];
 #pragma unroll
               for (int cc = 1; cc < W1; ++cc) {
                 const int cs = (p + cc) % W1;
-                win[rs][cs] = cfms(win[rs][cs], l, win[p][cs]);
+                win[rs][cs] = cfms(win[rs][cs], l, urow[cc]);
               }
-              rhs[rs] = cfms(rhs[rs], l, rhs[p]);
+              rhs[rs] = cfms(rhs[rs], l, yk);
             }
-            // row k divided by its pivot: the w upper entries and the
-            // reduced right-hand side
             const GCplx u = Ug + (long(k) * W * M + m);
 #pragma unroll
-            for (int cc = 1; cc < W1; ++cc) u[long(cc - 1) * M] = cmul(inv, win[p][(p + cc) % W1]);
-            Yg[long(k) * M + m] = cmul(inv, rhs[p]);
+            for (int cc = 1; cc < W1; ++cc) u[long(cc - 1) * M] = urow[cc];
+            Yg[long(k) * M + m] = yk;
             // slot p now takes row k + W1 (columns k+1 .. k+W1) and column
             // k + W1 (rows k+1 .. k+W)
             const int i = k + W1;
