@@ -1633,7 +1633,7 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
   }
 }
 
-__device__ void fd_solve_body(const SolveArgs& A) {
+__device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, n = A.n, w = 2 * A.s + 1, BW = 2 * w + 1, W1 = w + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1658,10 +1658,28 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   // (tiles dealt to the waves) the Q operands of every step are loaded once
   // for all mode tiles, and the next tile's operands are loaded before this
   // tile's products; real and imaginary parts in two accumulators sharing
-  // the Q operand (lane l: row l%16, q = 4kk + l/16)
-  constexpr int kKS = kFdMaxM / 4;
+  // the Q operand (lane l: row l%16, q = 4kk + l/16).  The H2 operands are
+  // the same for every row tile: they sit in registers for the whole
+  // transform, and each mode tile has its own accumulators, so the products
+  // of one step are independent of each other.
+  constexpr int kKS = kFdMaxM / 4, kCT = (kFdMaxM + 15) / 16;
   const int wave = tid >> 6, lane = tid & 63, nwv = nt >> 6;
   const int nrt = (n + 15) / 16, nct = (M + 15) / 16, ksteps = (M + 3) / 4;
+  // operand u of mode tile c (lane l: mode 16 c + l%16, q = 4 u + l/16) of an
+  // M x M complex matrix in LDS; zero outside
+  auto b_operands = [&](double (*br)[kKS], double (*bi)[kKS]) {
+#pragma unroll
+    for (int c = 0; c < kCT; ++c) {
+      const int mb = c * 16 + (lane & 15);
+#pragma unroll
+      for (int u = 0; u < kKS; ++u) {
+        const int q = 4 * u + (lane >> 4);
+        const cplx hb = (u < ksteps && c < nct && q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
+        br[c][u] = hb.r;
+        bi[c][u] = hb.i;
+      }
+    }
+  };
   {
     double an[kKS];
     auto load_q = [&](int tr, double* dst) {
@@ -1674,6 +1692,8 @@ __device__ void fd_solve_body(const SolveArgs& A) {
       }
     };
     if (wave < nrt) load_q(wave, an);
+    double hr[kCT][kKS], hi[kCT][kKS];
+    b_operands(hr, hi);
     for (int tr = wave; tr < nrt; tr += nwv) {
       double av[kKS];
       const int ia = tr * 16 + (lane & 15);
@@ -1681,22 +1701,26 @@ __device__ void fd_solve_body(const SolveArgs& A) {
 #pragma unroll
       for (int u = 0; u < kKS; ++u) av[u] = row_ok ? an[u] : 0.0;
       if (tr + nwv < nrt) load_q(tr + nwv, an);
-      for (int tc = 0; tc < nct; ++tc) {
-        const int mb = tc * 16 + (lane & 15);
-        v4d are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
+      v4d are[kCT], aim[kCT];
 #pragma unroll
-        for (int u = 0; u < kKS; ++u) {
-          if (u < ksteps) {   // (a guard, not a loop exit: the loop stays fully unrolled)
-            const int q = 4 * u + (lane >> 4);
-            const cplx hb = (q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
-            are = mfma16x16x4(av[u], hb.r, are);
-            aim = mfma16x16x4(av[u], hb.i, aim);
+      for (int c = 0; c < kCT; ++c) are[c] = aim[c] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < kKS; ++u) {
+#pragma unroll
+        for (int c = 0; c < kCT; ++c) {
+          if (u < ksteps && c < nct) {   // (guards, not loop exits: the loops stay fully unrolled)
+            are[c] = mfma16x16x4(av[u], hr[c][u], are[c]);
+            aim[c] = mfma16x16x4(av[u], hi[c][u], aim[c]);
           }
         }
+      }
+#pragma unroll
+      for (int c = 0; c < kCT; ++c) {
+        const int mb = c * 16 + (lane & 15);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int i = tr * 16 + (lane >> 4) + 4 * j;
-          if (i < n && mb < M) Y[long(i) * M + mb] = cmk(are[j], aim[j]);
+          if (c < nct && i < n && mb < M) Y[long(i) * M + mb] = cmk(are[c][j], aim[c][j]);
         }
       }
     }
@@ -1756,7 +1780,9 @@ __device__ void fd_solve_body(const SolveArgs& A) {
   __syncthreads();
   // ---- X = Re(Y H3) = Yr H3r - Yi H3i (fixed rows zero) on the matrix
   // cores, row tiles as above (Y operands of every step loaded once per row
-  // tile, the next tile's before this tile's products)
+  // tile, the next tile's before this tile's products; H3 operands in
+  // registers; the two products of a step go to two accumulators per mode
+  // tile, summed at the store)
   for (int t = tid; t < MM; t += nt) sH[t] = cmk(f.H3[2 * t], f.H3[2 * t + 1]);
   __syncthreads();
   {
@@ -1772,6 +1798,8 @@ __device__ void fd_solve_body(const SolveArgs& A) {
       }
     };
     if (wave < nrt) load_y(wave, anr, ani);
+    double hr[kCT][kKS], hi[kCT][kKS];
+    b_operands(hr, hi);
     for (int tr = wave; tr < nrt; tr += nwv) {
       double yr[kKS], yi[kKS];
       const int ia = tr * 16 + (lane & 15);
@@ -1782,22 +1810,27 @@ __device__ void fd_solve_body(const SolveArgs& A) {
         yi[u] = row_ok ? -ani[u] : 0.0;
       }
       if (tr + nwv < nrt) load_y(tr + nwv, anr, ani);
-      for (int tc = 0; tc < nct; ++tc) {
-        const int qb = tc * 16 + (lane & 15);
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
+      v4d ar[kCT], ai[kCT];
 #pragma unroll
-        for (int u = 0; u < kKS; ++u) {
-          if (u < ksteps) {
-            const int m = 4 * u + (lane >> 4);
-            const cplx hb = (m < M && qb < M) ? sH[m * M + qb] : cmk(0.0, 0.0);
-            acc = mfma16x16x4(yr[u], hb.r, acc);
-            acc = mfma16x16x4(yi[u], hb.i, acc);
+      for (int c = 0; c < kCT; ++c) ar[c] = ai[c] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < kKS; ++u) {
+#pragma unroll
+        for (int c = 0; c < kCT; ++c) {
+          if (u < ksteps && c < nct) {
+            ar[c] = mfma16x16x4(yr[u], hr[c][u], ar[c]);
+            ai[c] = mfma16x16x4(yi[u], hi[c][u], ai[c]);
           }
         }
+      }
+#pragma unroll
+      for (int c = 0; c < kCT; ++c) {
+        const int qb = c * 16 + (lane & 15);
+        const v4d x = ar[c] + ai[c];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int i = tr * 16 + (lane >> 4) + 4 * j;
-          if (i < n && qb < M) Xg[long(i) * M + qb] = acc[j];
+          if (c < nct && i < n && qb < M) Xg[long(i) * M + qb] = x[j];
         }
       }
     }
