@@ -1000,7 +1000,6 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   double* Hr = lds;                                   // kFdMaxM x L
   double* Zr = lds + kFdMaxM * L;                     // kFdMaxM x L
   double* Dm = lds + 2 * kFdMaxM * L;                 // kSchurSink: stores of lanes a chase step leaves alone
-  __shared__ double v[64];                            // Householder vector
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
   if (A.info[0] != 0) return;
@@ -1019,17 +1018,28 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   // loads before the first use, and updated from there.
   constexpr int kHB = kFdMaxM / 8;
   for (int k = 0; k + 2 < M; ++k) {
-    const double x = (lane > k && lane < M) ? Hr[lane * L + k] : 0.0;
-    double ss = x * x;
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
-    const double x0 = __shfl(x, k + 1);
+    // the Householder vector, in registers of every lane: column k below the
+    // diagonal read by all lanes (one address per load, a broadcast), rows
+    // past M - 1 zero; its norm from four partial sums
+    double vv[kHB][8];
+    double sq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < kHB; ++b) {
+      const int i0 = k + 1 + 8 * b;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double xv = (i0 < M) ? Hr[min(i0 + u, M - 1) * L + k] : 0.0;
+        vv[b][u] = (i0 + u < M) ? xv : 0.0;
+        sq[u & 3] = fma(vv[b][u], vv[b][u], sq[u & 3]);
+      }
+    }
+    const double ss = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+    if (ss == 0.0) continue;
+    const double x0 = vv[0][0];
     const double nx = sqrt(ss);
-    if (nx == 0.0) continue;
     const double alpha = x0 >= 0.0 ? -nx : nx;
-    const double vi = (lane == k + 1) ? x - alpha : x;
+    vv[0][0] = x0 - alpha;
     const double beta = 1.0 / (nx * (nx + fabs(x0)));   // 2 / |v|^2, |v|^2 = 2 nx (nx + |x0|)
-    if (lane < M) v[lane] = vi;
-    wave_sync();
     if (lane < M) {   // left: column lane, rows k+1..
       double hv[kHB][8];
 #pragma unroll
@@ -1040,28 +1050,23 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
           for (int u = 0; u < 8; ++u) hv[b][u] = Hr[min(i0 + u, M - 1) * L + lane];
         }
       }
-      double wsum = 0.0;
+      double ws[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int b = 0; b < kHB; ++b) {
         const int i0 = k + 1 + 8 * b;
         if (i0 < M) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const double vr = v[min(i0 + u, M - 1)];
-            wsum += ((i0 + u < M) ? vr : 0.0) * hv[b][u];
-          }
+          for (int u = 0; u < 8; ++u) ws[u & 3] = fma(vv[b][u], hv[b][u], ws[u & 3]);
         }
       }
-      const double bw = beta * wsum;
+      const double bw = beta * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
 #pragma unroll
       for (int b = 0; b < kHB; ++b) {
         const int i0 = k + 1 + 8 * b;
         if (i0 < M) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const double vr = v[min(i0 + u, M - 1)];
-            if (i0 + u < M) Hr[(i0 + u) * L + lane] = hv[b][u] - vr * bw;
-          }
+          for (int u = 0; u < 8; ++u)
+            if (i0 + u < M) Hr[(i0 + u) * L + lane] = hv[b][u] - vv[b][u] * bw;
         }
       }
     }
@@ -1080,31 +1085,28 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
           }
         }
       }
-      double us = 0.0, zs = 0.0;
+      double us[2] = {0.0, 0.0}, zs[2] = {0.0, 0.0};
 #pragma unroll
       for (int b = 0; b < kHB; ++b) {
         const int j0 = k + 1 + 8 * b;
         if (j0 < M) {
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const double vr = v[min(j0 + u, M - 1)];
-            const double vj = (j0 + u < M) ? vr : 0.0;
-            us += hv[b][u] * vj;
-            zs += zv[b][u] * vj;
+            us[u & 1] = fma(hv[b][u], vv[b][u], us[u & 1]);
+            zs[u & 1] = fma(zv[b][u], vv[b][u], zs[u & 1]);
           }
         }
       }
-      const double bu = beta * us, buz = beta * zs;
+      const double bu = beta * (us[0] + us[1]), buz = beta * (zs[0] + zs[1]);
 #pragma unroll
       for (int b = 0; b < kHB; ++b) {
         const int j0 = k + 1 + 8 * b;
         if (j0 < M) {
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const double vr = v[min(j0 + u, M - 1)];
             if (j0 + u < M) {
-              Hr[lane * L + j0 + u] = hv[b][u] - bu * vr;
-              Zr[lane * L + j0 + u] = zv[b][u] - buz * vr;
+              Hr[lane * L + j0 + u] = hv[b][u] - bu * vv[b][u];
+              Zr[lane * L + j0 + u] = zv[b][u] - buz * vv[b][u];
             }
           }
         }
