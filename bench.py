@@ -12,7 +12,9 @@ prolongation of its coarse factors), then Algorithm 1 in batched form (Grams,
 couplings, dim solves by fast diagonalisation -- the complex Schur route the
 paper names -- balancing, projected residual) with continuous batching --
 --batch slabs in flight, one workgroup each per kernel; a slab leaves when its
-residual reaches the target or the sweep cap and the next takes its slot --
+residual reaches the target or the sweep cap and the next takes its slot, so
+with more slabs than slots (by default 4096 through 1024) only the last
+rounds of a step run part-empty --
 the fallback rule after sweep 2, and a BF16 reconstruction of the end-time
 field of every slab that leaves (per-plane max, sum of squares and hot-point
 count), one batched call per round.
@@ -112,7 +114,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=3, help="plain sweep budget that sets the target residual")
     ap.add_argument("--batch", type=int, default=1024, help="slabs in flight, one workgroup each")
-    ap.add_argument("--slabs", type=int, default=1024, help="slabs solved per step")
+    ap.add_argument("--slabs", type=int, default=4096,
+                    help="slabs solved per step (streamed through --batch slots)")
     ap.add_argument("--train-chains", type=int, default=512)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--Kc", type=int, default=8, help="modes of the carried initial condition")
@@ -285,7 +288,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{N} x heat_slab {args.nx}x{args.nx}x{args.nz}x{args.nt} M={M}, learned warm start, "
-                         f"{B} in flight, to the plain {args.sweeps}-sweep median residual (cap {cap} sweeps), "
+                         f"{B} in flight (continuous batching), to the plain {args.sweeps}-sweep median residual "
+                         f"(cap {cap} sweeps), "
                          f"BF16 end-time reconstruction"),
             "variant": "warm-start+batched",
             "solver": args.solver,
