@@ -52,13 +52,11 @@ class FactorBatch:
 
     def ptrs(self, idx):
         """Factor pointers of the slabs idx, problem-major (driver order)."""
-        D = len(self.dims)
         import ctypes as C
-        arr = (C.c_void_p * (len(idx) * D))()
-        for j, b in enumerate(idx):
-            for d in range(D):
-                arr[j * D + d] = self.base[d] + b * self.stride[d]
-        return arr
+        D = len(self.dims)
+        b = np.asarray(idx, dtype=np.uint64)[:, None]
+        a = np.asarray(self.base, dtype=np.uint64)[None, :] + b * np.asarray(self.stride, dtype=np.uint64)[None, :]
+        return (C.c_void_p * (len(idx) * D)).from_buffer_copy(np.ascontiguousarray(a).tobytes())
 
     def clone(self):
         return FactorBatch([t.clone() for t in self.dims])
@@ -292,14 +290,12 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     n = len(probs)
     allp = (capi.Problem * n)(*[p.struct for p in probs])
     psize = C.sizeof(capi.Problem)
+    allp_bytes = np.frombuffer(allp, dtype=np.uint8).reshape(n, psize)   # a view; allp outlives the rounds
 
     def prob_array(idx):
         if len(idx) == n and idx == list(range(n)):
             return allp
-        sub = (capi.Problem * len(idx))()
-        for j, i in enumerate(idx):
-            C.memmove(C.addressof(sub) + j * psize, C.addressof(allp) + i * psize, psize)
-        return sub
+        return (capi.Problem * len(idx)).from_buffer_copy(allp_bytes[np.asarray(idx)].tobytes())
 
     waiting = deque(range(n))
     active = []
