@@ -441,8 +441,15 @@ __device__ inline void residual_part_bw(int chunk, int n, int M, int K, const do
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < K; ++k) {
       __syncthreads();   // sU staged / sC free
-      for (int r = wv; r < M; r += 4)
-        for (int c = lane; c < M; c += 64) sC[r * L + c] = C[(long(k) * M + r) * M + c];
+      for (int c = lane; c < M; c += 64)   // rows wv, wv+4, ..: eight loads in flight, then eight stores
+        for (int rb = wv; rb < M; rb += 32) {
+          double cv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) cv[u] = C[(long(k) * M + min(rb + 4 * u, M - 1)) * M + c];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (rb + 4 * u < M) sC[(rb + 4 * u) * L + c] = cv[u];
+        }
       double bc[BW];
       const auto brow = band + (long(k) * n + r0 + min(i_a, rows - 1)) * BW;
 #pragma unroll
