@@ -833,6 +833,27 @@ struct IjWalk {
     }
   }
 };
+// One wave reads the row-major M x M matrices srcs[0..N) (element t = i M + j)
+// and hands entry (i, j) of each to put(i, j, values); sixteen entries per lane
+// are loaded before the first is handed on, so the loads' latencies overlap.
+template <int N, class Src, class Put>
+__device__ inline void stage_square(int M, int lane, const Src* const (&srcs)[N], Put put) {
+  constexpr int kU = 16;
+  const int MM = M * M;
+  IjWalk w(lane, M);
+  for (int t0 = lane; t0 < MM; t0 += 64 * kU) {
+    double v[kU][N];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int a = 0; a < N; ++a) v[u][a] = srcs[a][min(t0 + 64 * u, MM - 1)];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (t0 + 64 * u < MM) put(w.i, w.j, v[u]);
+      w.next(M);
+    }
+  }
+}
 
 // Eigen stage of the fast diagonalisation for one dim system with two kinds,
 // in three kernels of one 64-lane wave per system (split so that the long
@@ -893,11 +914,12 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
   const FdWs f = fd_ws(A);
   if (lane == 0) s_fail = 0;
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) {
-      S0[w.i * L + w.j] = A.C[t];
-      C2s[w.i * L + w.j] = A.C[MM + t];
-    }
+    const auto Cg = gp(A.C);
+    const gmem<double>* const src[2] = {Cg, Cg + MM};
+    stage_square(M, lane, src, [&](int i, int j, const double* v) {
+      S0[i * L + j] = v[0];
+      C2s[i * L + j] = v[1];
+    });
   }
   wave_sync();
   // ---- C1^{-1}: Gauss-Jordan with partial pivoting (row swaps, undone as
@@ -1005,11 +1027,11 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   if (A.info[0] != 0) return;
   if (lane == 0) s_fail = 0;
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) {
-      Hr[w.i * L + w.j] = f.T[t];
-      Zr[w.i * L + w.j] = (w.i == w.j) ? 1.0 : 0.0;
-    }
+    const gmem<double>* const src[1] = {f.T};
+    stage_square(M, lane, src, [&](int i, int j, const double* v) {
+      Hr[i * L + j] = v[0];
+      Zr[i * L + j] = (i == j) ? 1.0 : 0.0;
+    });
   }
   wave_sync();
   // ---- Householder Hessenberg form, Zr accumulated.  The rows (left) and
@@ -1343,11 +1365,11 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
   // (complex eigenvalue pair) is triangularised by a unitary rotation whose
   // first column is the block's eigenvector for mu
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) {
-      H[w.i * L + w.j] = cmk(f.T[t], 0.0);
-      Z[w.i * L + w.j] = cmk(f.Zq[t], 0.0);
-    }
+    const gmem<double>* const src[2] = {f.T, f.Zq};
+    stage_square(M, lane, src, [&](int i, int j, const double* v) {
+      H[i * L + j] = cmk(v[0], 0.0);
+      Z[i * L + j] = cmk(v[1], 0.0);
+    });
   }
   wave_sync();
   for (int k = 0; k + 1 < M; ++k) {
@@ -1441,8 +1463,8 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
   wave_sync();
   double* Ci2 = lds + 2 * LL;   // C1^{-1} back from the workspace (Wv is dead)
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) Ci2[w.i * L + w.j] = f.C1inv[t];
+    const gmem<double>* const src[1] = {f.C1inv};
+    stage_square(M, lane, src, [&](int i, int j, const double* v) { Ci2[i * L + j] = v[0]; });
   }
   wave_sync();
   {
@@ -1635,6 +1657,22 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
   }
 }
 
+// dst[t] = (src[2t], src[2t+1]) for t < n, by nt threads with sixteen loads in flight each
+__device__ inline void stage_cplx(cplx* dst, const gmem<double>* src, int n, int tid, int nt) {
+  constexpr int kU = 16;
+  for (int t0 = tid; t0 < n; t0 += nt * kU) {
+    double re[kU], im[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = min(t0 + nt * u, n - 1);
+      re[u] = src[2 * t];
+      im[u] = src[2 * t + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (t0 + nt * u < n) dst[t0 + nt * u] = cmk(re[u], im[u]);
+  }
+}
 __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, n = A.n, w = 2 * A.s + 1, BW = 2 * w + 1, W1 = w + 1;
@@ -1650,7 +1688,7 @@ __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A)
   if (tid == 0) s_info = 0;
   if (A.info[0] != 0) return;   // the eigen stage failed: leave its code
   for (int m = tid; m < M; m += nt) sLam[m] = cmk(f.lam[2 * m], f.lam[2 * m + 1]);
-  for (int t = tid; t < MM; t += nt) sH[t] = cmk(f.H2[2 * t], f.H2[2 * t + 1]);
+  stage_cplx(sH, f.H2, MM, tid, nt);
   __syncthreads();
   const GCplx Y{f.Y};   // n x M
   const GCplx U{f.U};   // M x n x (w+1)
@@ -1785,7 +1823,7 @@ __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A)
   // tile, the next tile's before this tile's products; H3 operands in
   // registers; the two products of a step go to two accumulators per mode
   // tile, summed at the store)
-  for (int t = tid; t < MM; t += nt) sH[t] = cmk(f.H3[2 * t], f.H3[2 * t + 1]);
+  stage_cplx(sH, f.H3, MM, tid, nt);
   __syncthreads();
   {
     double anr[kKS], ani[kKS];
