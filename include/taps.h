@@ -243,29 +243,42 @@ taps_status taps_balance(taps_handle_t h, const taps_problem_t* prob,
 taps_status taps_sweep(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
                        int32_t* d_info, double* d_berr, hipStream_t stream);
 
-/* Algorithm 1 to tolerance: sweeps until rho <= tol or iter_max sweeps.
- * Synchronises the stream once per sweep to read rho.  Host outputs:
- * *sweeps, *rho (last), history[k] = rho after sweep k (nullable, iter_max
- * entries).  Returns TAPS_OK even if not converged (compare *rho with tol);
- * a breakdown in a dim solve (zero pivot, or backward error above
- * TAPS_BERR_LIMIT) ends the loop with *rho = NaN and taps_last_error()
- * naming the dim. */
+/* Algorithm 1 to tolerance (Sec. 2.6).  Stops after the first sweep whose
+ * projected residual rho <= tol, or -- the paper's own rule -- whose relative
+ * change of all factors
+ *   change = sqrt(sum_d ||U_d - U_d^prev||_F^2 / sum_d ||U_d||_F^2)
+ * (balanced factors after the sweep against those at its start) is at or
+ * below change_tol > 0 (0 disables that rule), or after iter_max sweeps.
+ * Synchronises the stream once per sweep to read rho and the change.  Host
+ * outputs: *sweeps, *rho (last), *change (last; nullable), history[k] = rho
+ * and change_history[k] = change after sweep k (nullable, iter_max entries
+ * each).  Returns TAPS_OK even if not converged (compare *rho with tol); a
+ * breakdown in a dim solve (zero pivot, or backward error above
+ * TAPS_BERR_LIMIT) ends the loop with *rho = *change = NaN and
+ * taps_last_error() naming the dim.  Workspace: the handle keeps a copy of
+ * the factors (sum_d n_d M doubles) for the change. */
 taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
-                     double tol, int32_t iter_max, int32_t* sweeps, double* rho,
-                     double* history, hipStream_t stream);
+                     double tol, double change_tol, int32_t iter_max, int32_t* sweeps, double* rho,
+                     double* change, double* history, double* change_history, hipStream_t stream);
 
 /* Algorithm 1 over a batch of B independent problems (slabs, parameter
- * queries) sharing D, M and the patch size of each dim; grid sizes may
- * differ.  d_U holds B*D factor pointers, problem-major (d_U[b*D + d]).
- * Each dim step solves every active system in one launch (one workgroup
- * per system, block LU on the matrix cores); after each sweep the host reads
- * every problem's residual and backward errors and drops the problems that
- * reached tol or broke down.  Host outputs: sweeps[b], rho[b] (NaN after a
- * breakdown).  Synchronises the stream once per sweep.  Needs the matrix-core
- * solve to fit LDS (TAPS_ERR_UNSUPPORTED otherwise). */
+ * queries) sharing D, M and the patch size of each dim; grid sizes, term
+ * tables and loads may differ.  d_U holds B*D factor pointers,
+ * problem-major (d_U[b*D + d]).  Each step of a sweep is one launch over
+ * every active problem: Gram and load-Gram refreshes, couplings, forces, the
+ * dim solves (the solver of taps_set_tuning: fast diagonalisation for dims
+ * with two matrix kinds and M <= 48, block LU on the matrix cores otherwise;
+ * one workgroup per system), backward errors, balancing with the relative
+ * change, and the residual.  After each sweep (or each replay of a captured
+ * graph of sweeps, taps_set_tuning) the host reads every problem's residual,
+ * change and backward errors and drops the problems that reached tol or
+ * change_tol (same rules as taps_als) or broke down.  Host outputs:
+ * sweeps[b], rho[b] and change[b] (nullable) after the last sweep run, NaN
+ * after a breakdown.  Synchronises the stream once per sweep (or replay).
+ * TAPS_ERR_UNSUPPORTED when a block-LU dim does not fit LDS (M, s). */
 taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* probs,
-                             double* const* d_U, double tol, int32_t iter_max, int32_t* sweeps,
-                             double* rho, hipStream_t stream);
+                             double* const* d_U, double tol, double change_tol, int32_t iter_max,
+                             int32_t* sweeps, double* rho, double* change, hipStream_t stream);
 
 /* Tuning of the dim solves and of the batched driver.
  *
@@ -324,8 +337,11 @@ taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* prob
  *                      Fast diagonalisation (solver 1), its banded stage:
  *                      flops = 8 n M^2 (the two complex transforms) +
  *                      8 n M (w+1)(w+2) (elimination and back substitution);
- *                      bytes = bands + Q read, X written, complex right-hand
- *                      sides and U rows written and read back.
+ *                      bytes = what the method moves: bands and Q read, X
+ *                      written, the two complex M x M transforms read (the
+ *                      kernel's own scratch -- complex right-hand sides and
+ *                      pivot-scaled U rows written and read back -- is not
+ *                      counted).
  *   TAPS_PROF_EIG      fast diagonalisation, its eigen stage: flops = 44 M^3
  *                      per system (inverse 2, E 2, Schur form with Schur
  *                      vectors 25, triangular eigenvectors and their inverse
@@ -337,10 +353,15 @@ taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* prob
  *                      vectors accumulated); bytes = 24 M^2 (E read, the
  *                      Schur form and its vectors written).
  *   TAPS_PROF_CONTRACT Grams, load Grams, couplings and force: flops of the
- *                      products, bytes = U, bands, F read once + outputs.
+ *                      products; bytes = what the method moves: U read once
+ *                      for all kinds of a dim and the Grams written, F and U
+ *                      read and the load Grams written, F read and Q written
+ *                      for the force (the banded 1D matrices are not counted:
+ *                      they are Toeplitz inside a uniform grid).
  *   TAPS_PROF_RECON    FP32/BF16 reconstruction on the matrix cores: flops =
- *                      2 n0 n1 n2 Mp (Mp = M padded to the MFMA inner size),
- *                      bytes = field written (STORE) + factors read once.
+ *                      2 n0 n1 n2 M (the method's modes; the matrix cores
+ *                      execute M padded to their inner size), bytes = field
+ *                      written (STORE) + factors read once.
  * taps_profile_enable(h, 1) clears the counters and starts recording,
  * (h, 0) stops.  taps_profile_read synchronises on the recorded events and
  * returns launches, summed kernel milliseconds, flops and bytes of one family. */

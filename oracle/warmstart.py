@@ -77,4 +77,7 @@ def ic_features(axes, V, nc=4):
 
 
 def restart_plain(rho1, rho2, plain_median_rho1):
-    return bool(rho1 > plain_median_rho1 or rho2 > rho1)
+    """True when the warm start lost: its sweep-1 residual is above the plain
+    start's median, it grew from sweep 1 to 2, or either residual is not a
+    number (a breakdown counts as a loss)."""
+    return not (rho1 <= plain_median_rho1) or not (rho2 <= rho1)

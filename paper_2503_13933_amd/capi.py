@@ -90,12 +90,12 @@ def lib():
             "taps_residual": (i32, [vp, P(Problem), P(vp), vp, vp]),
             "taps_balance": (i32, [vp, P(Problem), P(vp), vp]),
             "taps_sweep": (i32, [vp, P(Problem), P(vp), vp, vp, vp]),
-            "taps_als": (i32, [vp, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), P(dbl), vp]),
+            "taps_als": (i32, [vp, P(Problem), P(vp), dbl, dbl, i32, P(i32), P(dbl), P(dbl), P(dbl), P(dbl), vp]),
             "taps_interp1d": (i32, [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]),
             "taps_reconstruct": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
             "taps_reconstruct_batched": (i32, [vp, i32, P(i32), P(vp), i32, P(vp), i32, i32, P(vp), dbl, vp]),
             "taps_profile_enable": (i32, [vp, i32]),
-            "taps_als_batched": (i32, [vp, i32, P(Problem), P(vp), dbl, i32, P(i32), P(dbl), vp]),
+            "taps_als_batched": (i32, [vp, i32, P(Problem), P(vp), dbl, dbl, i32, P(i32), P(dbl), P(dbl), vp]),
             "taps_profile_read": (i32, [vp, i32, P(i32), P(dbl), P(dbl), P(dbl)]),
             "taps_band_apply": (i32, [vp, i32, i32, vp, i32, vp, i32, vp, dbl, vp, i32, vp]),
             "taps_canonicalize": (i32, [vp, i32, P(i32), i32, P(vp), P(vp), vp]),
@@ -222,14 +222,20 @@ def taps_sweep(h: Handle, prob: Problem, U, info=None, berr=None, stream=None):
             "taps_sweep")
 
 
-def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, stream=None):
+def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, change_tol: float = 0.0, stream=None,
+             change_hist=None):
     """Returns (sweeps, rho, history list); rho is NaN after a breakdown
-    (the reason is in last_error(h))."""
+    (the reason is in last_error(h)).  change_hist, a list, receives the
+    relative change of the factors after every sweep."""
     sweeps = C.c_int32()
     rho = C.c_double()
+    chg = C.c_double()
     hist = (C.c_double * iter_max)()
-    h.check(lib().taps_als(h.h, C.byref(prob), _ptr_array(U), tol, iter_max, C.byref(sweeps), C.byref(rho), hist,
-                           _stream(stream)), "taps_als")
+    chist = (C.c_double * iter_max)()
+    h.check(lib().taps_als(h.h, C.byref(prob), _ptr_array(U), tol, change_tol, iter_max, C.byref(sweeps),
+                           C.byref(rho), C.byref(chg), hist, chist, _stream(stream)), "taps_als")
+    if change_hist is not None:
+        change_hist.extend(chist[: sweeps.value])
     return sweeps.value, rho.value, list(hist[: sweeps.value])
 
 
@@ -360,13 +366,20 @@ def last_error(h: Handle) -> str:
     return lib().taps_last_error(h.h).decode()
 
 
-def taps_als_batched(h: Handle, probs, Us, tol: float, iter_max: int, stream=None):
+def taps_als_batched(h: Handle, probs, Us, tol: float, iter_max: int, change_tol: float = 0.0, stream=None,
+                     change=None):
     """Algorithm 1 over a batch.  probs: list of Problem; Us: list (per problem)
-    of factor tensor lists.  Returns (sweeps list, rho list)."""
+    of factor tensor lists, or a ctypes array of factor pointers.  Returns
+    (sweeps list, rho list); change, a list, receives every problem's
+    relative change of the factors over its last sweep."""
     B = len(probs)
     arr = probs if isinstance(probs, C.Array) else (Problem * B)(*probs)
     ptrs = Us if isinstance(Us, C.Array) else _ptr_array([u for U in Us for u in U])
     sw = (C.c_int32 * B)()
     rh = (C.c_double * B)()
-    h.check(lib().taps_als_batched(h.h, B, arr, ptrs, tol, iter_max, sw, rh, _stream(stream)), "taps_als_batched")
+    ch = (C.c_double * B)()
+    h.check(lib().taps_als_batched(h.h, B, arr, ptrs, tol, change_tol, iter_max, sw, rh, ch, _stream(stream)),
+            "taps_als_batched")
+    if change is not None:
+        change.extend(ch)
     return list(sw), list(rh)

@@ -34,7 +34,7 @@ struct BProb {
   double* gpart;
   double* lpart;
   double* rparts;
-  double* outs;  // res (D+2), then backward error per dim (D)
+  double* outs;  // res (D+2), backward error per dim (D), relative change of the sweep (1)
 };
 
 __global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
@@ -141,6 +141,10 @@ __global__ __launch_bounds__(256) void kb_balance(const BalanceArgs* __restrict_
   balance(BA[act[blockIdx.x]], scale_mask);
 }
 
+__global__ __launch_bounds__(256) void kb_snapshot(const BalanceArgs* __restrict__ BA, const int* __restrict__ act) {
+  snapshot(BA[act[blockIdx.x]]);
+}
+
 size_t gram_lds_allowed = 0, res_lds_allowed = 0;
 
 // grid sizes per dim (maxima over the batch; blocks past a problem's own
@@ -159,8 +163,8 @@ struct Sizes {
 }  // namespace
 
 extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* probs,
-                                        double* const* d_U, double tol, int32_t iter_max, int32_t* sweeps,
-                                        double* rho, hipStream_t stream) {
+                                        double* const* d_U, double tol, double change_tol, int32_t iter_max,
+                                        int32_t* sweeps, double* rho, double* change, hipStream_t stream) {
   if (!h) return TAPS_ERR_INVALID;
   if (B < 1 || !probs || !d_U || !sweeps || !rho) return fail(h, TAPS_ERR_INVALID, "bad batch arguments");
   if (iter_max < 1) return fail(h, TAPS_ERR_INVALID, "iter_max < 1");
@@ -197,14 +201,16 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const size_t o_wa = bump.take(sizeof(WeightArgs) * size_t(B) * D);
   const size_t o_bal = bump.take(sizeof(BalanceArgs) * size_t(B));
   const size_t o_active = bump.take(size_t(B) * 4);
-  const size_t o_outs = bump.take(size_t(B) * (2 * D + 2) * 8);
+  const int NO = 2 * D + 3;  // outputs per problem
+  const size_t o_outs = bump.take(size_t(B) * NO * 8);
   const size_t o_infos = bump.take(size_t(B) * D * 4);
   std::vector<BProb> bp(B);
   std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B), wt_doubles(B);
+  std::vector<size_t> o_snap(B);
   for (int b = 0; b < B; ++b) {
     const taps_problem_t& p = probs[b];
     int Kmax = 1, nmax = 1, tot = 0;
-    size_t ws = 0, gp = 0, lp = 0, wt = 0;
+    size_t ws = 0, gp = 0, lp = 0, wt = 0, nsum = 0;
     for (int d = 0; d < D; ++d) {
       const int ch = cdiv(p.n[d], kGramRows), ct = cdiv(p.R_cols[d], kLgCols), sp = cdiv(p.n[d], kLgRows);
       Kmax = std::max(Kmax, p.n_kinds[d]);
@@ -215,6 +221,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       wt = std::max(wt, size_t(p.R_cols[d]) * M * 8);
       Z.max_terms = std::max(Z.max_terms, cdiv(long(p.R) * M, 256));
       bp[b].roff[d] = tot;
+      nsum += size_t(p.n[d]);
       tot += cdiv(p.n[d], kResRows);
       Z.chunks[d] = std::max(Z.chunks[d], ch);
       Z.ctiles[d] = std::max(Z.ctiles[d], ct);
@@ -235,6 +242,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     o_lp[b] = bump.take(lp);
     o_rp[b] = bump.take(size_t(tot) * 2 * 8);
     o_ws[b] = bump.take(ws);
+    o_snap[b] = bump.take(nsum * M * 8);
   }
   TAPS_TRY(grow(h, &h->batch, &h->batch_bytes, bump.off, stream));
   char* base = static_cast<char*>(h->batch);
@@ -275,7 +283,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     q.gpart = reinterpret_cast<double*>(base + o_gp[b]);
     q.lpart = reinterpret_cast<double*>(base + o_lp[b]);
     q.rparts = reinterpret_cast<double*>(base + o_rp[b]);
-    q.outs = outs + size_t(b) * (2 * D + 2);
+    q.outs = outs + size_t(b) * NO;
     for (int d = 0; d < D; ++d) {
       CoupleArgs& ca = cpl[size_t(b) * D + d];
       ca = CoupleArgs{};
@@ -309,6 +317,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     bal[b] = BalanceArgs{};
     bal[b].D = D;
     bal[b].M = M;
+    double* snap = reinterpret_cast<double*>(base + o_snap[b]);
     for (int d = 0; d < D; ++d) {
       bal[b].n[d] = p.n[d];
       bal[b].U[d] = q.U[d];
@@ -316,13 +325,17 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       bal[b].Rc[d] = p.R_cols[d];
       bal[b].gram[d] = q.gram[d];
       bal[b].lgram[d] = q.lgram[d];
+      bal[b].snap[d] = snap;
+      snap += size_t(p.n[d]) * M;
     }
+    bal[b].change = q.outs + 2 * D + 2;
   }
   std::vector<int> active(B), next;
   for (int b = 0; b < B; ++b) {
     active[b] = b;
     sweeps[b] = 0;
     rho[b] = NAN;
+    if (change) change[b] = NAN;
   }
   TAPS_HIP(h, hipMemcpyAsync(base + o_args, args.data(), args.size(), hipMemcpyHostToDevice, stream));
   TAPS_HIP(h, hipMemcpyAsync(base + o_prob, bp.data(), sizeof(BProb) * B, hipMemcpyHostToDevice, stream));
@@ -353,12 +366,15 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_LAUNCHED(h, "kb_lgram_partial");
     kb_lgram_sum<<<dim3(cdiv(Z.lgram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_lgram_sum");
+    // work of the method: Grams (U read once for all kinds, K M^2 written;
+    // flops K (2 bw n M + 2 n M^2)) and load Gram (F and U read, R M written;
+    // 2 n R M flops)
     double fl = 0.0, by = 0.0;
     for (int b : active) {
       const taps_problem_t& p = probs[b];
       const double n = p.n[e], K = p.n_kinds[e], Rc = p.R_cols[e], bw = 4 * p.s[e] + 3;
       fl += K * (2.0 * bw * n * M + 2.0 * n * M * M) + 2.0 * n * Rc * M;
-      by += 8.0 * (n * M + K * n * bw + n * Rc + K * MM + Rc * M);
+      by += 8.0 * (n * M + K * MM + n * Rc + Rc * M);
     }
     return prof_end(h, slot, fl, by, st);
   };
@@ -392,6 +408,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const uint32_t all = (1u << D) - 1u;
   auto one_sweep = [&](int nact, hipStream_t st) -> taps_status {
     uint32_t valid = 0;
+    kb_snapshot<<<nact, 256, 0, st>>>(d_bal, d_active);
+    TAPS_LAUNCHED(h, "kb_snapshot");
     for (int d = 0; d < D; ++d) {
       const uint32_t stale = (all & ~(1u << d)) & ~valid;
       for (int e = 0; e < D; ++e)
@@ -474,7 +492,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return TAPS_OK;
   };
 
-  std::vector<double> h_outs(size_t(B) * (2 * D + 2));
+  std::vector<double> h_outs(size_t(B) * NO);
   std::vector<int> h_infos(size_t(B) * D);
   for (int it = 0; it < iter_max && !active.empty();) {
     const int nact = int(active.size());
@@ -492,13 +510,15 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_HIP(h, hipStreamSynchronize(run));
     next.clear();
     for (int b : active) {
-      const double* o = h_outs.data() + size_t(b) * (2 * D + 2);
+      const double* o = h_outs.data() + size_t(b) * NO;
       bool broke = false;
       for (int d = 0; d < D; ++d)
         broke = broke || h_infos[size_t(b) * D + d] != 0 || !(o[D + 2 + d] <= TAPS_BERR_LIMIT);
       sweeps[b] = it;
       rho[b] = broke ? NAN : o[D + 1];
-      if (!broke && rho[b] > tol) next.push_back(b);
+      const double chg = broke ? NAN : o[2 * D + 2];
+      if (change) change[b] = chg;
+      if (!broke && rho[b] > tol && !(change_tol > 0.0 && chg <= change_tol)) next.push_back(b);
     }
     if (next.size() != active.size() && !next.empty()) {
       TAPS_HIP(h, hipMemcpyAsync(d_active, next.data(), next.size() * 4, hipMemcpyHostToDevice, run));

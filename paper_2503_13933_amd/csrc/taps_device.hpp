@@ -527,11 +527,37 @@ struct BalanceArgs {
   int K[TAPS_MAX_DIMS], Rc[TAPS_MAX_DIMS];
   double* gram[TAPS_MAX_DIMS];
   double* lgram[TAPS_MAX_DIMS];
+  // factors at the start of the sweep (same layout as U; null: no change
+  // measured) and where the relative change of the sweep goes (one double)
+  const double* snap[TAPS_MAX_DIMS];
+  double* change;
 };
+
+// Copy of every factor of one problem (the start of a sweep), one block of
+// 256 threads walking the contiguous n_d x M arrays.
+__device__ inline void snapshot(const BalanceArgs& A) {
+  if (!A.change) return;
+  for (int e = 0; e < A.D; ++e) {
+    const auto src = gp(A.U[e]);
+    const auto dst = gp(const_cast<double*>(A.snap[e]));
+    const long len = long(A.n[e]) * A.M;
+    long i = threadIdx.x;
+    for (; i + 3 * 256 < len; i += 4 * 256) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = src[i + u * 256];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) dst[i + u * 256] = v[u];
+    }
+    for (; i < len; i += 256) dst[i] = src[i];
+  }
+}
 
 // Every mode m of one problem: column norms of every dim, their geometric
 // mean g, U_e[:, m] *= g / ||U_e[:, m]|| (skipped for a mode with a norm below
-// 1e-300).  Block of 256 threads as 4 row phases x 64 mode lanes, so each row
+// 1e-300).  With a snapshot, the relative change of the sweep,
+// sqrt(sum_e ||U_e - snap_e||_F^2 / sum_e ||U_e||_F^2) of the balanced
+// factors, is written to *change (the paper's stop rule, Sec. 2.6).  Block of 256 threads as 4 row phases x 64 mode lanes, so each row
 // of a factor is read and written as one contiguous segment; the row phases
 // are summed in a fixed order.  For the dims in scale_mask the cached Grams
 // follow the factors without being recomputed: G^k[m][n] *= f_m f_n and
@@ -577,12 +603,38 @@ __device__ inline void balance(const BalanceArgs& A, unsigned scale_mask = 0) {
     for (int e = 0; e < A.D; ++e) fac[e][m] = tiny ? 1.0 : g / fac[e][m];
   }
   __syncthreads();
+  double dsum = 0.0, nsum = 0.0;
   if (m < M)
     for (int e = 0; e < A.D; ++e) {
       const double f = fac[e][m];
       const auto Ue = gp(A.U[e]);
       const int n = A.n[e];
       int i = ph;
+      if (A.change) {
+        const auto Se = gp(A.snap[e]);
+        for (; i + 28 < n; i += 32) {
+          double v[8], o[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            v[u] = Ue[long(i + 4 * u) * M + m];
+            o[u] = Se[long(i + 4 * u) * M + m];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double x = v[u] * f, dx = x - o[u];
+            Ue[long(i + 4 * u) * M + m] = x;
+            dsum += dx * dx;
+            nsum += x * x;
+          }
+        }
+        for (; i < n; i += 4) {
+          const double x = Ue[long(i) * M + m] * f, dx = x - Se[long(i) * M + m];
+          Ue[long(i) * M + m] = x;
+          dsum += dx * dx;
+          nsum += x * x;
+        }
+        continue;
+      }
       for (; i + 28 < n; i += 32) {
         double v[8];
 #pragma unroll
@@ -592,6 +644,24 @@ __device__ inline void balance(const BalanceArgs& A, unsigned scale_mask = 0) {
       }
       for (; i < n; i += 4) Ue[long(i) * M + m] *= f;
     }
+  if (A.change) {
+    // block sum in a fixed order: lanes of a wave by shuffles, then the waves
+    for (int o = 32; o > 0; o >>= 1) {
+      dsum += __shfl_xor(dsum, o);
+      nsum += __shfl_xor(nsum, o);
+    }
+    __syncthreads();
+    if (m == 0) {
+      part[ph][0] = dsum;
+      part[ph][1] = nsum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double dd = (part[0][0] + part[1][0]) + (part[2][0] + part[3][0]);
+      const double nn = (part[0][1] + part[1][1]) + (part[2][1] + part[3][1]);
+      *A.change = nn > 0.0 ? sqrt(dd / nn) : (dd > 0.0 ? INFINITY : 0.0);
+    }
+  }
   for (int e = 0; e < A.D; ++e) {
     if (!(scale_mask & (1u << e))) continue;
     const int MM = M * M;

@@ -391,9 +391,10 @@ void launch_fp32(dim3 grid, hipStream_t st, int n0, int n1, int nrb, int M, cons
 namespace taps {
 
 // Accounting of one reconstruction call for the profiler family RECON:
-// flops = 2 n0 n1 n2 Mp (padded modes, as executed); bytes = stored field
+// flops = 2 n0 n1 n2 M (the method's modes, not the padded ones the
+// matrix cores execute); bytes = stored field
 // (STORE) + factors read once.
-double recon_flops(int n0, int n1, int n2, int Mp) { return 2.0 * n0 * double(n1) * n2 * Mp; }
+double recon_flops(int n0, int n1, int n2, int M) { return 2.0 * n0 * double(n1) * n2 * M; }
 
 // B fields of one shape: d_Phi holds 3 factor pointers per field, d_mode_w
 // one pointer per field (or is null), d_out one output per field.  B = 1
@@ -480,7 +481,7 @@ taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts,
   fn(grid, stream, n0, n1, nrb, M, P0f(0), P1(0), d_Phi[2], d_mode_w ? d_mode_w[0] : nullptr, thrf, out0, rec(0),
      t_r);
   TAPS_LAUNCHED(h, bf ? "k_recon_bf16" : "k_recon_fp32");
-  TAPS_TRY(prof_end(h, slot, B * recon_flops(n0, n1, n2, Mp),
+  TAPS_TRY(prof_end(h, slot, B * recon_flops(n0, n1, n2, M),
                     B * ((st ? 4.0 * n0 * double(n1) * n2 : 0.0) + 4.0 * (double(n0) + n1) * Mp), stream));
   if (!st) {
     k_recon_plane_mfma<<<dim3(cdiv(n2, 64), B), 64, 0, stream>>>(nrb, n2, rec(0), static_cast<double*>(d_out[0]),

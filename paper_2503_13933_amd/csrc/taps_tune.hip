@@ -126,10 +126,10 @@ extern "C" taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_prob
     h->tune.graph_sweeps = kCandidates[c];
     // untimed run (captures the graph), then the timed one from the same factors
     st = copy_all(false);
-    if (st == TAPS_OK) st = taps_als_batched(h, B, probs, d_U, 0.0, kTimedSweeps, sw.data(), rho.data(), stream);
+    if (st == TAPS_OK) st = taps_als_batched(h, B, probs, d_U, 0.0, 0.0, kTimedSweeps, sw.data(), rho.data(), nullptr, stream);
     if (st == TAPS_OK) st = copy_all(false);
     if (st == TAPS_OK && hipEventRecord(e0, stream) != hipSuccess) st = fail(h, TAPS_ERR_HIP, "event record failed");
-    if (st == TAPS_OK) st = taps_als_batched(h, B, probs, d_U, 0.0, kTimedSweeps, sw.data(), rho.data(), stream);
+    if (st == TAPS_OK) st = taps_als_batched(h, B, probs, d_U, 0.0, 0.0, kTimedSweeps, sw.data(), rho.data(), nullptr, stream);
     if (st == TAPS_OK && hipEventRecord(e1, stream) != hipSuccess) st = fail(h, TAPS_ERR_HIP, "event record failed");
     float t = 0.0f;
     if (st == TAPS_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))

@@ -263,7 +263,10 @@ def train(h, net, X, T, steps, lr, batch, seed):
 
 
 def restart_plain(rho1, rho2, plain_median_rho1):
-    return bool(rho1 > plain_median_rho1 or rho2 > rho1)
+    """True when the warm start lost: its sweep-1 residual is above the plain
+    start's median, it grew from sweep 1 to 2, or either residual is not a
+    number (a breakdown counts as a loss)."""
+    return not (rho1 <= plain_median_rho1) or not (rho2 <= rho1)
 
 
 # ------------------------------------------------------------- streaming
@@ -272,19 +275,21 @@ def restart_plain(rho1, rho2, plain_median_rho1):
 def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, on_done=None, on_done_batch=None):
     """Continuous batching of Algorithm 1: up to ``slots`` slabs in flight,
     one batched sweep (taps_als_batched) per round; a slab leaves as soon as
-    its projected residual reaches tol or it has run ``cap`` sweeps, and the
-    next waiting slab takes its place, so the matrix cores stay busy while
-    slabs converge at different speeds.
+    its projected residual reaches tol, it has run ``cap`` sweeps, or its
+    solve broke down (NaN residual), and the next waiting slab takes its
+    place, so the kernels stay busy while slabs converge at different speeds.
 
     With U_plain and median_rho1 given, U holds warm starts and the fallback
-    rule is applied after sweep 2: a slab whose warm start lost (sweep-1
-    residual above median_rho1, or growing from sweep 1 to 2) restarts from
-    its U_plain factors with a fresh sweep count.
+    rule is applied: a slab whose warm start lost (sweep-1 residual above
+    median_rho1, or growing from sweep 1 to 2, or a breakdown in either
+    sweep) restarts from its U_plain factors with a fresh sweep count.
     on_done(i) is called for every slab as it leaves; on_done_batch(list)
     once per round with all slabs that left in it.
     U (and U_plain) may be FactorBatch objects (addresses computed per
     round) or lists of per-slab factor lists.
-    Returns (sweeps run per slab, final residual per slab, number of restarts)."""
+    Returns (sweeps run per slab, final residual per slab, number of
+    restarts, outcome per slab: 0 reached tol, 1 stopped at the cap,
+    2 broke down)."""
     import ctypes as C
     from collections import deque
     n = len(probs)
@@ -303,6 +308,7 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     total = [0] * n          # sweeps run
     rho = [float("nan")] * n
     rho1 = [float("nan")] * n
+    outcome = [1] * n
     restarted = set()
     while waiting or active:
         while len(active) < slots and waiting:
@@ -317,14 +323,16 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
             if U_plain is not None and i not in restarted:
                 if count[i] == 1:
                     rho1[i] = ri
-                elif count[i] == 2 and restart_plain(rho1[i], ri, median_rho1):
+                lost = (count[i] == 1 and ri != ri) or (count[i] == 2 and restart_plain(rho1[i], ri, median_rho1))
+                if lost:
                     restarted.add(i)
                     for u, u0 in zip(U[i], U_plain[i]):
                         u.copy_(u0)
                     count[i] = 0
                     keep.append(i)
                     continue
-            if ri <= tol or count[i] >= cap:
+            if ri <= tol or ri != ri or count[i] >= cap:
+                outcome[i] = 0 if ri <= tol else (2 if ri != ri else 1)
                 done.append(i)
                 if on_done is not None:
                     on_done(i)
@@ -333,4 +341,4 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
         if done and on_done_batch is not None:
             on_done_batch(done)
         active = keep
-    return total, rho, len(restarted)
+    return total, rho, len(restarted), outcome

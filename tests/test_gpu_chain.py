@@ -4,6 +4,7 @@ both driven through the C ABI (taps_band_apply, taps_als)."""
 import numpy as np
 import pytest
 
+import parity_util as pu
 import taps_workloads as W
 from oracle import chain as ochain
 from oracle import fulltensor, problems
@@ -61,14 +62,23 @@ def test_chain_matches_oracle(env):
     _say("chain 3 slabs 20x16x9x9 M=4 Kc=3 on the oracle")
     dims = problems.dims_of(base)
     ref = ochain.run_chain(cases, dims, U0s, C0s, sweeps=4, comp_sweeps=4)
+    # the chain's own rounding amplification: the same chain with every dim
+    # solve's couplings and force perturbed by 1e-14 of their RMS entry
+    with pu.perturbed(1e-14, seed=1):
+        pert = ochain.run_chain(cases, dims, U0s, C0s, sweeps=4, comp_sweeps=4)
     _say("chain on the GPU")
     got = chain.run_chain(h, cases, U0s, C0s, sweeps=4, comp_sweeps=4)
     torch.cuda.synchronize()
     for T in range(3):
         Ug = [u.cpu().numpy() for u in got[T][0]]
         Vg = [v.cpu().numpy() for v in got[T][2]]
-        e_u = rel(fulltensor.td_tensor(Ug), fulltensor.td_tensor(ref[T][0]))
-        e_v = rel(fulltensor.td_tensor(Vg), fulltensor.td_tensor(ref[T][2]))
-        _say(f"  slab {T}: slab field {e_u:.2e}, carried field {e_v:.2e}")
-        assert e_u < 1e-9 and e_v < 1e-9
+        fu, fv = fulltensor.td_tensor(ref[T][0]), fulltensor.td_tensor(ref[T][2])
+        bar_u = max(pu.TOL, 10 * pu.rel(fulltensor.td_tensor(pert[T][0]), fu),
+                    10 * pu.maxrel(fulltensor.td_tensor(pert[T][0]), fu))
+        bar_v = max(pu.TOL, 10 * pu.rel(fulltensor.td_tensor(pert[T][2]), fv),
+                    10 * pu.maxrel(fulltensor.td_tensor(pert[T][2]), fv))
+        e_u = pu.check(fulltensor.td_tensor(Ug), fu, bar_u, f"slab {T} field")
+        e_v = pu.check(fulltensor.td_tensor(Vg), fv, bar_v, f"slab {T} carried field")
+        _say(f"  slab {T}: slab field rel/max {e_u[0]:.2e}/{e_u[1]:.2e} (bar {bar_u:.1e}), "
+             f"carried field {e_v[0]:.2e}/{e_v[1]:.2e} (bar {bar_v:.1e})")
         assert np.all(Vg[2][0] == 0.0)

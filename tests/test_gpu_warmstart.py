@@ -75,11 +75,20 @@ def test_trained_network_beats_plain_initialisation(env):
         _say(f"  sweep {s + 1}: median rho warm {np.nanmedian(warm[s]):.3e}  plain {np.nanmedian(plain[s]):.3e}")
     # fallback rule: keep the warm start unless it loses to the plain median at sweep 1 or grows
     keep = np.array([not ws.restart_plain(warm[0, j], warm[1, j], med1) for j in range(len(te))])
-    final = np.where(keep, warm[-1], plain[-1])
-    _say(f"warm start kept for {keep.sum()}/{len(te)} slabs; median final rho {np.nanmedian(final):.3e} "
-         f"vs plain {np.nanmedian(plain[-1]):.3e}")
+    # what the network gains: sweeps to reach the plain start's median residual
+    # after 3 sweeps (the target the benchmark uses), a slab that falls back
+    # paying its two warm sweeps plus the plain start's count; never reached
+    # within the sweeps run counts as sweeps + 1
+    target = float(np.nanmedian(hist[2, tr]))
+
+    def to_target(h_col):
+        hit = np.nonzero(h_col <= target)[0]
+        return int(hit[0]) + 1 if hit.size else sweeps + 1
+
+    n_plain = np.array([to_target(plain[:, j]) for j in range(len(te))])
+    n_warm = np.array([to_target(warm[:, j]) if keep[j] else 2 + n_plain[j] for j in range(len(te))])
+    _say(f"warm start kept for {keep.sum()}/{len(te)} slabs; sweeps to the plain 3-sweep median {target:.3e}: "
+         f"warm {n_warm.mean():.2f} (with fallbacks) vs plain {n_plain.mean():.2f}")
+    assert np.nanmedian(warm[0]) < np.nanmedian(plain[0])
     assert np.nanmedian(warm[1]) < np.nanmedian(plain[1])
-    # after the last sweep both starts sit at Algorithm 1's stagnation level
-    # (rho ~ 1.8e-2 here); the warm start must not end above it beyond the
-    # spread that rounding of the contractions moves it by (a few percent)
-    assert np.nanmedian(final) <= 1.05 * np.nanmedian(plain[-1])
+    assert n_warm.mean() < n_plain.mean()

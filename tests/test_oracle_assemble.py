@@ -81,3 +81,26 @@ def test_gaussian_load_total():
     s2 = np.sqrt(2.0) / r
     exact = np.sqrt(np.pi) / (2 * s2) * (erf(s2 * (1 - c)) - erf(s2 * (0 - c)))
     assert abs(F.sum() - exact) < 1e-9 * exact
+
+
+@pytest.mark.parametrize("s,p", [(2, 2), (1, 1), (3, 3)])
+def test_weighted_mass_moments_with_linear_coefficient(s, p):
+    # for a coefficient c(x) = alpha + beta x and q, r <= p the reproducing
+    # property makes (x^q)^T W^c x^r the exact integral of c(x) x^(q+r) over the
+    # domain: a dropped, squared or misplaced coefficient changes these values
+    D = _dim(n=13, s=s, p=p, L=1.3, seed=3)
+    a0, b0 = D.nodes[0], D.nodes[-1]
+    alpha, beta = 0.7, -1.9
+    W = D.matrix("wmass", coef=lambda x: alpha + beta * x).toarray()
+    x = D.nodes
+    for q in range(p + 1):
+        for r in range(p + 1):
+            k = q + r
+            exact = alpha * (b0 ** (k + 1) - a0 ** (k + 1)) / (k + 1) + beta * (b0 ** (k + 2) - a0 ** (k + 2)) / (k + 2)
+            assert abs(x ** q @ W @ x ** r - exact) < 1e-12 * max(1.0, abs(exact))
+    # a constant coefficient gives c times the mass matrix, entry by entry
+    Wc = D.matrix("wmass", coef=lambda x: 2.5 * np.ones_like(x)).toarray()
+    assert np.abs(Wc - 2.5 * D.matrix("mass").toarray()).max() < 1e-15
+    # coefficient values given at the Gauss points are the callable's values there
+    Wv = D.matrix("wmass", coef=alpha + beta * D.xg).toarray()
+    assert np.abs(Wv - W).max() == 0.0

@@ -108,3 +108,21 @@ def test_derivative_matches_finite_difference():
     Nm = basis.shape_matrices(x, 2, 20.0, 2, pts - h)[0].toarray()
     # points chosen away from nodes, where Ntilde is smooth
     assert np.abs((Np - Nm) / (2 * h) - B.toarray()).max() < 1e-5
+
+
+def test_abs_term_sum_of_reconstruction():
+    # sum_m |w_m prod_d Phi_d[i_d, m]| written out by hand on a tiny case; it
+    # bounds the reconstructed value and equals it when every term is positive
+    from oracle import reconstruct
+    P0 = np.array([[1.0, -2.0], [0.5, 3.0]])
+    P1 = np.array([[2.0, 1.0], [-1.0, 4.0], [0.25, -0.5]])
+    P2 = np.array([[3.0, -1.0]])
+    w = np.array([0.5, -2.0])
+    idx = np.array([[i, j, 0] for i in range(2) for j in range(3)])
+    got = reconstruct.abs_term_sum([P0, P1, P2], idx, w)
+    want = [abs(0.5 * P0[i, 0] * P1[j, 0] * 3.0) + abs(-2.0 * P0[i, 1] * P1[j, 1] * -1.0) for i, j, _ in idx]
+    assert np.array_equal(got, np.array(want))
+    val = reconstruct.reconstruct_points([P0, P1, P2], idx, w)
+    assert np.all(np.abs(val) <= got * (1 + 1e-15))
+    pos = [np.abs(P0), np.abs(P1), np.abs(P2)]
+    assert np.allclose(reconstruct.abs_term_sum(pos, idx), reconstruct.reconstruct_points(pos, idx), rtol=1e-15)

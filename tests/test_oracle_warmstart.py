@@ -77,3 +77,8 @@ def test_param_features_and_fallback_rule():
     assert warmstart.restart_plain(2.0, 1.0, 1.5)          # worse than the plain median
     assert warmstart.restart_plain(1.0, 1.2, 1.5)          # grows from sweep 1 to 2
     assert not warmstart.restart_plain(1.0, 0.9, 1.5)
+    # a breakdown (NaN residual) after either sweep is a loss, never a keep
+    nan = float("nan")
+    assert warmstart.restart_plain(nan, 0.9, 1.5)
+    assert warmstart.restart_plain(1.0, nan, 1.5)
+    assert warmstart.restart_plain(nan, nan, 1.5)
