@@ -180,16 +180,16 @@ def test_batched_sweep_of_1024_problems(env):
         Ub = [d.factors(u) for d, u in zip(devs, U0)]
         sweeps, rhos = capi.taps_als_batched(h, [d.struct for d in devs], Ub, 0.0, 1)
         torch.cuda.synchronize()
-        worst = 0.0
+        worst, raised = 0.0, 0
         for b, (c, u0, ub, rb) in enumerate(zip(cases, U0, Ub, rhos)):
             ora = problems.heat_slab(c)
             Uo, rho_o, ch_o = pu.oracle_sweeps(ora, u0, 1)
-            kappa = max(pu.cond_estimate(ora, d, separated.couplings(ora, Uo, d)) for d in range(ora.D))
-            bar = max(TOL, 10 * kappa * pu.EPS)
+            fbar, rbar, cbar, kappa = pu.sweep_bars(ora, u0, Uo, 1, rho_o[-1], ch_o[-1])
             for d, (a, o) in enumerate(zip(ub, Uo)):
-                r, m = pu.check(a.cpu().numpy(), o, bar, f"problem {b} factor {d}")
+                r, m = pu.check(a.cpu().numpy(), o, fbar[d], f"problem {b} factor {d}")
                 worst = max(worst, r, m)
-            assert abs(rb - rho_o[-1]) <= max(TOL * rho_o[-1], 10 * kappa * pu.EPS)
-        _say(f"  worst factor difference over 1024 problems {worst:.2e}")
+                raised += fbar[d] > TOL
+            assert abs(rb - rho_o[-1]) <= rbar
+        _say(f"  worst factor difference over 1024 problems {worst:.2e}; bars above 1e-10: {raised} of {4 * 1024}")
     finally:
         capi.taps_set_tuning(h, solver=capi.SOLVER_BLOCK_LU)
