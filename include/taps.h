@@ -412,6 +412,26 @@ taps_status taps_reconstruct_batched(taps_handle_t h, int32_t B, const int32_t* 
                                      taps_prec prec, taps_recon_mode mode, void* const* d_out, double thr,
                                      hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * reconstruction as taps_reconstruct (same kernels, bit-identical outputs,
+ * every precision and mode), with its scratch -- the staged reduced-precision
+ * factors and the per-block partial records -- in a static device array of
+ * TAPS_NOALLOC_SCRATCH_BYTES per GPU instead of the handle's workspace.  It
+ * calls no allocation routine and times no kernel.  The array is looked up
+ * by taps_create on the handle's GPU, which must be current; every call on a
+ * GPU shares that GPU's array and overwrites it (nothing in it needs to
+ * start at zero), so calls that overlap on one GPU -- on concurrent streams
+ * or from several host threads -- race.  Sizes whose scratch exceeds the
+ * array return TAPS_ERR_UNSUPPORTED before anything is enqueued: FP32/BF16
+ * need 4 n0 Mp + (2 or 4) n1 Mp bytes (Mp = M padded to 32 for BF16, 16 for
+ * FP32) plus 32 n2 ceil(n0/256) for REDUCE; FP64 REDUCE needs
+ * 32 n2 ceil(n0/16) ceil(n1/16); FP64 STORE needs none. */
+#define TAPS_NOALLOC_SCRATCH_BYTES (8u << 20)
+taps_status taps_reconstruct_noalloc(taps_handle_t h, const int32_t* n_pts, const double* const* d_Phi,
+                                     int32_t M, const double* d_mode_w, taps_prec prec, taps_recon_mode mode,
+                                     void* d_out, double thr, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Learned warm start.  A slab's converged factors are stored in a canonical
  * form before a network learns them, and the network's coarse factors are

@@ -27,7 +27,7 @@ FUNCTIONS = (
     "taps_solve_dim", "taps_residual", "taps_balance", "taps_sweep", "taps_als", "taps_interp1d",
     "taps_reconstruct", "taps_reconstruct_batched", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
     "taps_canonicalize", "taps_mlp_cache_bytes", "taps_mlp_forward", "taps_mlp_backward", "taps_mlp_mse",
-    "taps_adam_step", "taps_set_tuning", "taps_get_tuning", "taps_autotune",
+    "taps_adam_step", "taps_set_tuning", "taps_get_tuning", "taps_autotune", "taps_reconstruct_noalloc",
 )
 MLP_MAX_LAYERS = 8
 PROF_SOLVE, PROF_CONTRACT, PROF_RECON, PROF_EIG, PROF_SCHUR = 0, 1, 2, 3, 4
@@ -107,6 +107,7 @@ def lib():
             "taps_set_tuning": (i32, [vp, P(Tuning)]),
             "taps_get_tuning": (i32, [vp, P(Tuning)]),
             "taps_autotune": (i32, [vp, i32, P(Problem), P(vp), C.c_char_p, P(Tuning), P(dbl), vp]),
+            "taps_reconstruct_noalloc": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -336,6 +337,13 @@ def taps_reconstruct(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int =
     n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis])
     h.check(lib().taps_reconstruct(h.h, n, _ptr_array(Phis), M, _ptr(mode_w), prec, mode, _ptr(out), thr,
                                    _stream(stream)), "taps_reconstruct")
+
+
+def taps_reconstruct_noalloc(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int = STORE, mode_w=None,
+                             thr: float = 0.0, stream=None):
+    n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis])
+    h.check(lib().taps_reconstruct_noalloc(h.h, n, _ptr_array(Phis), M, _ptr(mode_w), prec, mode, _ptr(out), thr,
+                                           _stream(stream)), "taps_reconstruct_noalloc")
 
 
 def taps_reconstruct_batched(h: Handle, Phis, M: int, outs, prec: int = BF16, mode: int = REDUCE, mode_ws=None,

@@ -171,6 +171,12 @@ taps_status taps_create(taps_handle_t* out) {
     delete h;
     return TAPS_ERR_ALLOC;
   }
+  const taps_status st = taps::recon_scratch_attach(h);
+  if (st != TAPS_OK) {
+    (void)hipFree(h->d_small);
+    delete h;
+    return st;
+  }
   *out = h;
   return TAPS_OK;
 }

@@ -208,6 +208,9 @@ taps_status berr_final_launch(taps_handle* h, int nparts, const double* parts, d
 double solve_flops(int n, int M, int w);
 double solve_bytes(int n, int M, int w, int K);
 
+// Device address of the allocation-free reconstruction's scratch on the
+// handle's GPU (looked up once per GPU by taps_create).
+taps_status recon_scratch_attach(taps_handle* h);
 taps_status balance_launch(taps_handle* h, const taps_problem_t* p, double* const* d_U, hipStream_t stream);
 taps_status residual_final_launch(taps_handle* h, int D, const int* nparts, double* const* parts, double* out,
                                   hipStream_t stream);

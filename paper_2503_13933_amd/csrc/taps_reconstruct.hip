@@ -13,7 +13,14 @@ taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double*
                              double thr, hipStream_t stream);
 taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts, const double* const* d_Phi,
                                     int32_t M, const double* const* d_mode_w, taps_prec prec, taps_recon_mode mode,
-                                    void* const* d_out, double thr, hipStream_t stream);
+                                    void* const* d_out, double thr, hipStream_t stream, char* ext = nullptr,
+                                    size_t ext_cap = 0);
+char* recon_scratch(taps_handle* h);
+}
+
+namespace {
+taps_status fp64_reduce(taps_handle* h, const int32_t* n_pts, const double* const* d_Phi, int32_t M,
+                        const double* d_mode_w, double* out, double thr, double* t, hipStream_t stream);
 }
 
 namespace {
@@ -114,14 +121,69 @@ extern "C" taps_status taps_reconstruct(taps_handle_t h, const int32_t* n_pts, c
   }
   const long tiles = long(grid.x) * grid.y * n2;
   TAPS_TRY(need_ws(h, size_t(tiles) * 4 * 8, stream));
-  double* t = static_cast<double*>(h->ws);
+  return fp64_reduce(h, n_pts, d_Phi, M, d_mode_w, static_cast<double*>(d_out), thr, static_cast<double*>(h->ws),
+                     stream);
+}
+
+extern "C" taps_status taps_reconstruct_noalloc(taps_handle_t h, const int32_t* n_pts, const double* const* d_Phi,
+                                                int32_t M, const double* d_mode_w, taps_prec prec,
+                                                taps_recon_mode mode, void* d_out, double thr, hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (!n_pts || !d_Phi || !d_out) return fail(h, TAPS_ERR_INVALID, "null pointer");
+  if (M < 1 || M > TAPS_MAX_M) return fail(h, TAPS_ERR_UNSUPPORTED, "M=%d", M);
+  for (int d = 0; d < 3; ++d) {
+    if (n_pts[d] < 1) return fail(h, TAPS_ERR_INVALID, "n_pts[%d]=%d", d, n_pts[d]);
+    if (!d_Phi[d]) return fail(h, TAPS_ERR_INVALID, "Phi[%d] is null", d);
+  }
+  if (mode != TAPS_STORE && mode != TAPS_REDUCE) return fail(h, TAPS_ERR_INVALID, "mode %d", int(mode));
+  if (prec != TAPS_FP64 && prec != TAPS_FP32 && prec != TAPS_BF16)
+    return fail(h, TAPS_ERR_INVALID, "precision %d", int(prec));
+  int dev = -1;
+  TAPS_HIP(h, hipGetDevice(&dev));
+  if (dev != h->device)
+    return fail(h, TAPS_ERR_INVALID, "handle belongs to device %d, device %d is current", h->device, dev);
+  char* ext = recon_scratch(h);
+  if (!ext) return fail(h, TAPS_ERR_HIP, "reconstruction scratch not attached on device %d", dev);
+  if (prec == TAPS_FP32 || prec == TAPS_BF16) {
+    const double* const mw[1] = {d_mode_w};
+    void* const out[1] = {d_out};
+    return reconstruct_mfma_fields(h, 1, n_pts, d_Phi, M, d_mode_w ? mw : nullptr, prec, mode, out, thr, stream, ext,
+                                   TAPS_NOALLOC_SCRATCH_BYTES);
+  }
+  const int n0 = n_pts[0], n1 = n_pts[1], n2 = n_pts[2];
+  if (mode == TAPS_STORE) {
+    dim3 grid(cdiv(n0, kTile), cdiv(n1, kTile), n2);
+    k_recon_fp64<<<grid, kTile * kTile, 0, stream>>>(n0, n1, n2, M, d_Phi[0], d_Phi[1], d_Phi[2], d_mode_w,
+                                                     mode, thr, static_cast<double*>(d_out));
+    TAPS_LAUNCHED(h, "k_recon_fp64");
+    return TAPS_OK;
+  }
+  const size_t need = size_t(cdiv(n0, kTile)) * cdiv(n1, kTile) * n2 * 4 * 8;
+  if (need > TAPS_NOALLOC_SCRATCH_BYTES)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "this reconstruction needs %zu bytes of scratch; the allocation-free entry "
+                "point has %zu", need, size_t(TAPS_NOALLOC_SCRATCH_BYTES));
+  return fp64_reduce(h, n_pts, d_Phi, M, d_mode_w, static_cast<double*>(d_out), thr, reinterpret_cast<double*>(ext),
+                     stream);
+}
+
+namespace {
+
+// FP64 REDUCE: per-tile records into t (one record of 4 doubles per 2D tile
+// and plane), then one record per plane into out.
+taps_status fp64_reduce(taps_handle* h, const int32_t* n_pts, const double* const* d_Phi, int32_t M,
+                        const double* d_mode_w, double* out, double thr, double* t, hipStream_t stream) {
+  const int n0 = n_pts[0], n1 = n_pts[1], n2 = n_pts[2];
+  dim3 grid(cdiv(n0, kTile), cdiv(n1, kTile), n2);
+  const taps_recon_mode mode = TAPS_REDUCE;
   k_recon_fp64<<<grid, kTile * kTile, 0, stream>>>(n0, n1, n2, M, d_Phi[0], d_Phi[1], d_Phi[2], d_mode_w, mode,
                                                    thr, t);
   TAPS_LAUNCHED(h, "k_recon_fp64");
-  k_recon_plane<<<cdiv(n2, 64), 64, 0, stream>>>(int(grid.x * grid.y), n2, t, static_cast<double*>(d_out));
+  k_recon_plane<<<cdiv(n2, 64), 64, 0, stream>>>(int(grid.x * grid.y), n2, t, out);
   TAPS_LAUNCHED(h, "k_recon_plane");
   return TAPS_OK;
 }
+
+}  // namespace
 
 extern "C" taps_status taps_reconstruct_batched(taps_handle_t h, int32_t B, const int32_t* n_pts,
                                                 const double* const* d_Phi, int32_t M,

@@ -29,7 +29,14 @@
 #include "taps_internal.hpp"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
+
+// Scratch of taps_reconstruct_noalloc (staged factors and per-block partial
+// records of one call), for callers that cannot allocate.  One copy per GPU,
+// held until the process ends; host code reaches it only through the device
+// address recon_scratch_attach() looked up for that GPU.
+static __device__ __align__(256) char scratch[TAPS_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -400,9 +407,12 @@ double recon_flops(int n0, int n1, int n2, int M) { return 2.0 * n0 * double(n1)
 // one pointer per field (or is null), d_out one output per field.  B = 1
 // passes the pointers to the kernels directly; B > 1 uploads per-field tables
 // (grid.y = field) into the workspace behind the staged factors.
+// ext (with ext_cap bytes) replaces the handle workspace when given: then
+// nothing is allocated and no kernel is timed.
 taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts, const double* const* d_Phi,
                                     int32_t M, const double* const* d_mode_w, taps_prec prec, taps_recon_mode mode,
-                                    void* const* d_out, double thr, hipStream_t stream) {
+                                    void* const* d_out, double thr, hipStream_t stream, char* ext = nullptr,
+                                    size_t ext_cap = 0) {
   const int n0 = n_pts[0], n1 = n_pts[1], n2 = n_pts[2];
   const bool bf = (prec == TAPS_BF16);
   const int Mp = bf ? 32 * cdiv(M, 32) : 16 * cdiv(M, 16);
@@ -422,8 +432,12 @@ taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts,
     o_R[b] = bump.take(s_R);
   }
   const size_t o_tab = bump.take(B > 1 ? size_t(B) * (2 * sizeof(ConvJob) + sizeof(ReconJob) + sizeof(PlaneJob)) : 0);
-  TAPS_TRY(need_ws(h, bump.off, stream));
-  char* ws = static_cast<char*>(h->ws);
+  if (ext && bump.off > ext_cap)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "this reconstruction needs %zu bytes of scratch; the allocation-free entry "
+                "point has %zu", bump.off, ext_cap);
+  if (ext && B > 1) return fail(h, TAPS_ERR_INVALID, "allocation-free reconstruction takes one field");
+  if (!ext) TAPS_TRY(need_ws(h, bump.off, stream));
+  char* ws = ext ? ext : static_cast<char*>(h->ws);
   auto P0f = [&](int b) { return reinterpret_cast<float*>(ws + o_P0[b]); };
   auto P1 = [&](int b) { return static_cast<void*>(ws + o_P1[b]); };
   auto rec = [&](int b) { return reinterpret_cast<double*>(ws + o_R[b]); };
@@ -473,16 +487,17 @@ taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts,
       default: fn = st ? launch_fp32<16, TAPS_STORE> : launch_fp32<16, TAPS_REDUCE>; break;
     }
   }
-  size_t slot;
-  TAPS_TRY(prof_begin(h, TAPS_PROF_RECON, stream, &slot));
+  size_t slot = 0;
+  if (!ext) TAPS_TRY(prof_begin(h, TAPS_PROF_RECON, stream, &slot));
   // largest float <= thr (for u > thr decided in FP32 exactly as in FP64)
   float thrf = float(thr);
   if (double(thrf) > thr) thrf = std::nextafter(thrf, -INFINITY);
   fn(grid, stream, n0, n1, nrb, M, P0f(0), P1(0), d_Phi[2], d_mode_w ? d_mode_w[0] : nullptr, thrf, out0, rec(0),
      t_r);
   TAPS_LAUNCHED(h, bf ? "k_recon_bf16" : "k_recon_fp32");
-  TAPS_TRY(prof_end(h, slot, B * recon_flops(n0, n1, n2, M),
-                    B * ((st ? 4.0 * n0 * double(n1) * n2 : 0.0) + 4.0 * (double(n0) + n1) * Mp), stream));
+  if (!ext)
+    TAPS_TRY(prof_end(h, slot, B * recon_flops(n0, n1, n2, M),
+                      B * ((st ? 4.0 * n0 * double(n1) * n2 : 0.0) + 4.0 * (double(n0) + n1) * Mp), stream));
   if (!st) {
     k_recon_plane_mfma<<<dim3(cdiv(n2, 64), B), 64, 0, stream>>>(nrb, n2, rec(0), static_cast<double*>(d_out[0]),
                                                                t_p);
@@ -496,7 +511,33 @@ taps_status reconstruct_mfma(taps_handle* h, const int32_t* n_pts, const double*
                              hipStream_t stream) {
   const double* const mw[1] = {d_mode_w};
   void* const out[1] = {d_out};
-  return reconstruct_mfma_fields(h, 1, n_pts, d_Phi, M, d_mode_w ? mw : nullptr, prec, mode, out, thr, stream);
+  return reconstruct_mfma_fields(h, 1, n_pts, d_Phi, M, d_mode_w ? mw : nullptr, prec, mode, out, thr, stream,
+                                 nullptr, 0);
+}
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+char* scratch_ptr[kScratchDevices] = {};  // device address of `scratch` on each GPU
+}  // namespace
+
+// Looks up the device address of the no-alloc scratch on the handle's GPU
+// (which must be current), once per GPU; taps_create calls it.
+taps_status recon_scratch_attach(taps_handle* h) {
+  if (h->device < 0 || h->device >= kScratchDevices)
+    return fail(h, TAPS_ERR_UNSUPPORTED, "device %d beyond the %d the library tracks", h->device, kScratchDevices);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[h->device]) return TAPS_OK;
+  void* ptr = nullptr;
+  TAPS_HIP(h, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(h, TAPS_ERR_HIP, "no device address for the reconstruction scratch");
+  scratch_ptr[h->device] = static_cast<char*>(ptr);
+  return TAPS_OK;
+}
+
+char* recon_scratch(taps_handle* h) {
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return (h->device >= 0 && h->device < kScratchDevices) ? scratch_ptr[h->device] : nullptr;
 }
 
 }  // namespace taps
