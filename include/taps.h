@@ -122,9 +122,15 @@ taps_status taps_shape1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_pts
  *   TAPS_SRC_SIN:      params[0]*sin(params[1]*x)      (n_cols must be 1)
  *   TAPS_SRC_NODAL:    Ntilde_c(x) of `basis` (time interpolation of a
  *                      non-separable source; n_cols = basis->n_nodes)
- * d_centers is used by GAUSS only; basis by NODAL only. */
+ *   TAPS_SRC_EXPQUAD:  (p0 + p1 xi + p2 xi^2) exp(-beta xi^2 + lambda x)
+ *                      + q0 + q1 x with xi = x - s, per column c from
+ *                      d_centers[8c .. 8c+7] = {s, beta, lambda, p0, p1, p2,
+ *                      q0, q1} (factors of closed-form test fields and
+ *                      their sources: Gaussians and exponentials times
+ *                      quadratics)
+ * d_centers is used by GAUSS and EXPQUAD only; basis by NODAL only. */
 typedef enum { TAPS_SRC_GAUSS = 0, TAPS_SRC_TOPLAYER = 1, TAPS_SRC_POLY = 2,
-               TAPS_SRC_SIN = 3, TAPS_SRC_NODAL = 4 } taps_source_kind;
+               TAPS_SRC_SIN = 3, TAPS_SRC_NODAL = 4, TAPS_SRC_EXPQUAD = 5 } taps_source_kind;
 taps_status taps_source1d(taps_handle_t h, taps_source_kind kind, int32_t n_pts,
                           const double* d_pts, int32_t n_cols, int32_t n_params,
                           const double* params, const double* d_centers,
@@ -282,6 +288,12 @@ taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* p
 
 /* Tuning of the dim solves and of the batched driver.
  *
+ * lgram_rows is the row split of the batched load-Gram kernel: each work
+ * item contracts 64 load columns over lgram_rows rows (a multiple of 16,
+ * 16..4096; 0 = 256), and the partials of the ceil(n/lgram_rows) splits are
+ * summed afterwards -- fewer, longer items stream F with less partial
+ * traffic, more, shorter ones spread a small problem over more workgroups.
+ *
  * graph_sweeps = 0 launches every kernel of a sweep from the host; K > 0
  * captures K consecutive sweeps (every launch, no host work in between) into
  * one HIP graph, replays it, and checks the residuals after each replay, so a
@@ -307,20 +319,24 @@ taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* p
 typedef struct {
   int32_t graph_sweeps;
   int32_t solver;
+  int32_t lgram_rows;   /* rows per partial of the batched load Gram (0 = 256) */
 } taps_tuning_t;
 taps_status taps_set_tuning(taps_handle_t h, const taps_tuning_t* t);
 taps_status taps_get_tuning(taps_handle_t h, taps_tuning_t* t);
 
-/* Timing autotuner of the batched driver.  For the candidates graph_sweeps =
- * 0, 1, 2, 4 it times taps_als_batched on this batch (4 sweeps after one
- * untimed run that also captures the graph; HIP events on `stream`), keeps the
- * smallest K whose time per sweep is within 3 % of the fastest, applies it to
- * the handle and returns it in *chosen; ms_per_sweep (nullable, 4 doubles)
- * receives the measured times.  The factors d_U are saved first and restored
- * before returning (device copies, allocated here).  With cache_path non-NULL
- * the choice is looked up in, or appended to, a JSON file keyed by the batch
- * shape (B, D, M, s, and per dim the largest n, R_cols and n_kinds); a key
- * already there is applied without timing (ms_per_sweep then all -1). */
+/* Timing autotuner of the batched driver (coordinate search).  First the
+ * load-Gram row split lgram_rows in {128, 256, 512, 1024} with host launches
+ * (the fastest is kept), then graph_sweeps in {0, 1, 2, 4} with that split
+ * (the smallest K within 3 % of the fastest is kept); each candidate is
+ * timed on this batch (4 sweeps after one untimed run that also captures the
+ * graph; HIP events on `stream`).  The choice is applied to the handle and
+ * returned in *chosen; ms_per_sweep (nullable, 8 doubles) receives the
+ * measured times, row splits first.  The factors d_U are saved first and
+ * restored before returning (device copies, allocated here).  With
+ * cache_path non-NULL the choice is looked up in, or appended to, a JSON
+ * file keyed by the batch shape (B, D, M, solver, s, and per dim the largest
+ * n, R_cols and n_kinds); a key already there is applied without timing
+ * (ms_per_sweep then all -1). */
 taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* probs, double* const* d_U,
                           const char* cache_path, taps_tuning_t* chosen, double* ms_per_sweep,
                           hipStream_t stream);

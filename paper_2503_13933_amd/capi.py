@@ -17,7 +17,7 @@ MAX_DIMS, MAX_TERMS, MAX_KINDS, MAX_M, MAX_S, MAX_GAUSS = 8, 16, 4, 64, 3, 8
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = 0, -1, -2, -3, -4
 MASS, STIFF, DDT, WMASS, BMASS = 0, 1, 2, 3, 4
-SRC_GAUSS, SRC_TOPLAYER, SRC_POLY, SRC_SIN, SRC_NODAL = 0, 1, 2, 3, 4
+SRC_GAUSS, SRC_TOPLAYER, SRC_POLY, SRC_SIN, SRC_NODAL, SRC_EXPQUAD = 0, 1, 2, 3, 4, 5
 FP64, FP32, BF16 = 0, 1, 2
 STORE, REDUCE = 0, 1
 
@@ -55,7 +55,7 @@ class Problem(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("graph_sweeps", C.c_int32), ("solver", C.c_int32)]
+    _fields_ = [("graph_sweeps", C.c_int32), ("solver", C.c_int32), ("lgram_rows", C.c_int32)]
 
 
 class MLP(C.Structure):
@@ -249,26 +249,29 @@ def taps_get_tuning(h: Handle) -> Tuning:
     return t
 
 
-def taps_set_tuning(h: Handle, graph_sweeps: int = None, solver: int = None):
+def taps_set_tuning(h: Handle, graph_sweeps: int = None, solver: int = None, lgram_rows: int = None):
     """Fields left as None keep the handle's current value."""
     t = taps_get_tuning(h)
     if graph_sweeps is not None:
         t.graph_sweeps = graph_sweeps
     if solver is not None:
         t.solver = solver
+    if lgram_rows is not None:
+        t.lgram_rows = lgram_rows
     h.check(lib().taps_set_tuning(h.h, C.byref(t)), "taps_set_tuning")
 
 
 def taps_autotune(h: Handle, probs, Us, cache_path=None, stream=None):
-    """Returns (chosen graph_sweeps, ms per sweep of candidates 0, 1, 2, 4)."""
+    """Returns (chosen Tuning, ms per sweep of the 8 candidates: row splits
+    128, 256, 512, 1024 with host launches, then graph lengths 0, 1, 2, 4)."""
     B = len(probs)
-    arr = (Problem * B)(*probs)
+    arr = probs if isinstance(probs, C.Array) else (Problem * B)(*probs)
+    ptrs = Us if isinstance(Us, C.Array) else _ptr_array([u for U in Us for u in U])
     t = Tuning()
-    ms = (C.c_double * 4)()
+    ms = (C.c_double * 8)()
     path = cache_path.encode() if cache_path else None
-    h.check(lib().taps_autotune(h.h, B, arr, _ptr_array([u for U in Us for u in U]), path, C.byref(t), ms,
-                                _stream(stream)), "taps_autotune")
-    return t.graph_sweeps, list(ms)
+    h.check(lib().taps_autotune(h.h, B, arr, ptrs, path, C.byref(t), ms, _stream(stream)), "taps_autotune")
+    return t, list(ms)
 
 
 def taps_band_apply(h: Handle, s: int, band, X, Y, alpha: float = 1.0, scale=None, stream=None):

@@ -226,6 +226,12 @@ __global__ void k_source(SourceArgs S, const double* __restrict__ pts, const dou
       v = (l >= 0 && l < 2 * B.s + 2) ? n_[l] : 0.0;
       break;
     }
+    case TAPS_SRC_EXPQUAD: {
+      const double* r = centers + 8L * c;   // s, beta, lambda, p0, p1, p2, q0, q1
+      const double xi = x - r[0];
+      v = ((r[5] * xi + r[4]) * xi + r[3]) * exp(-r[1] * xi * xi + r[2] * x) + (r[6] + r[7] * x);
+      break;
+    }
   }
   out[idx] = v;
 }
@@ -392,6 +398,9 @@ taps_status taps_source1d(taps_handle_t h, taps_source_kind kind, int32_t n_pts,
     case TAPS_SRC_SIN:
       if (n_cols != 1) return fail(h, TAPS_ERR_INVALID, "POLY/SIN take one column");
       if (kind == TAPS_SRC_SIN && n_params < 2) return fail(h, TAPS_ERR_INVALID, "SIN needs amp, omega");
+      break;
+    case TAPS_SRC_EXPQUAD:
+      if (!d_centers) return fail(h, TAPS_ERR_INVALID, "EXPQUAD needs 8 coefficients per column");
       break;
     case TAPS_SRC_NODAL:
       TAPS_TRY(check_basis(h, basis));

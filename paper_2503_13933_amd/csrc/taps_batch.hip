@@ -1,11 +1,16 @@
 // Batched Algorithm 1 (paper Sec. 2.6) over many independent problems --
 // slabs, parameter queries -- that share D, M and the patch size of each dim
 // (grid sizes may differ).  Every step of a sweep is one launch over all
-// active problems (the problem is the last grid coordinate): Gram refreshes,
-// couplings, forces, the block-LU solves (one workgroup per system), the
-// backward-error check, balancing and the residual.  Problems that reach the
-// tolerance or break down are predicated off on the host after each sweep by
-// shrinking the active list.
+// active problems: Gram refreshes, couplings, forces, the dim solves (one
+// workgroup per system), the backward-error check, balancing and the
+// residual.  The row-chunked contraction kernels (Gram, load Gram, force,
+// residual) are persistent: a fixed grid of workgroups strides over a list of
+// work items -- one per (problem, row chunk), or (problem, column tile, row
+// split) for the load Gram -- that holds exactly the chunks of the active
+// problems however uneven their sizes, with the item count read from device
+// memory so a captured graph stays valid.  Problems that reach the tolerance
+// or break down are predicated off on the host after each sweep by shrinking
+// the active list (and its work items).
 #include "taps_device.hpp"
 
 #include <algorithm>
@@ -37,12 +42,25 @@ struct BProb {
   double* outs;  // res (D+2), backward error per dim (D), relative change of the sweep (1)
 };
 
-__global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
-  const BProb& q = P[act[blockIdx.y]];
-  const int n = q.n[e];
-  if (int(blockIdx.x) * kGramRows >= n) return;
-  gram_partial(blockIdx.x, n, q.M, q.s[e], q.K[e], q.band[e], q.U[e],
-               q.gpart + long(blockIdx.x) * q.K[e] * q.M * q.M);
+// Work item of the persistent kernels: problem b, chunk or column tile i,
+// row split j.
+struct Item {
+  int b, i, j, pad;
+};
+enum { kItGram = 0, kItLgram = 1, kItForce = 2, kItRes = 3, kItKinds = 4 };
+// persistent grid sizes: LDS-heavy bodies (Gram, residual) hold a few
+// workgroups per compute unit, the streaming ones (load Gram, force) more
+constexpr int kPersistLds = 1024, kPersistStream = 2048;
+
+__global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const Item* __restrict__ it,
+                                                       const int* __restrict__ cnt, int e) {
+  const int nit = *cnt;
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item x = it[w];
+    const BProb& q = P[x.b];
+    gram_partial(x.i, q.n[e], q.M, q.s[e], q.K[e], q.band[e], q.U[e], q.gpart + long(x.i) * q.K[e] * q.M * q.M);
+    __syncthreads();   // LDS free for the next item
+  }
 }
 
 // The elementwise kernels (sums of partials, couplings, load terms and
@@ -57,15 +75,19 @@ __global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__
   sum_parts_n<kVB>(blockIdx.x * kVB, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
 }
 
-__global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
-  const BProb& q = P[act[blockIdx.z]];
-  if (int(blockIdx.x) * kLgCols >= q.Rc[e] || int(blockIdx.y) * kLgRows >= q.n[e]) return;
-  lgram_partial(blockIdx.x, blockIdx.y, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
+__global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const Item* __restrict__ it,
+                                                        const int* __restrict__ cnt, int e, int rows) {
+  const int nit = *cnt;
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item x = it[w];
+    const BProb& q = P[x.b];
+    lgram_partial(x.i, x.j, rows, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
+  }
 }
 
-__global__ void kb_lgram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e) {
+__global__ void kb_lgram_sum(const BProb* __restrict__ P, const int* __restrict__ act, int e, int rows) {
   const BProb& q = P[act[blockIdx.y]];
-  const int splits = (q.n[e] + kLgRows - 1) / kLgRows;
+  const int splits = (q.n[e] + rows - 1) / rows;
   sum_parts_n<kVB>(blockIdx.x * kVB, splits, long(q.Rc[e]) * q.M, q.lpart, q.lgram[e]);
 }
 
@@ -86,17 +108,26 @@ __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* _
   for (int u = 0; u < kVB; ++u) load_weights(blockIdx.x * kVB + u, WA[long(b) * D + d], P[b].Wt);
 }
 
-__global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
-  const BProb& q = P[act[blockIdx.y]];
-  if (int(blockIdx.x) * kQRows >= q.n[d]) return;
-  force(blockIdx.x, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
+__global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const Item* __restrict__ it,
+                                                const int* __restrict__ cnt, int d) {
+  const int nit = *cnt;
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item x = it[w];
+    const BProb& q = P[x.b];
+    force(x.i, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
+  }
 }
 
-__global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
-  const BProb& q = P[act[blockIdx.y]];
-  if (int(blockIdx.x) * kResRows >= q.n[d]) return;
-  residual_part(blockIdx.x, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
-                q.rparts + 2 * (q.roff[d] + blockIdx.x));
+__global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const Item* __restrict__ it,
+                                                        const int* __restrict__ cnt, int d) {
+  const int nit = *cnt;
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+    const Item x = it[w];
+    const BProb& q = P[x.b];
+    residual_part(x.i, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
+                  q.rparts + 2 * (q.roff[d] + x.i));
+    __syncthreads();   // LDS free for the next item
+  }
 }
 
 // One thread per active problem: backward error of dim d from its partials.
@@ -193,6 +224,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
 
   // ---- layout of the batch buffer
   const size_t args_sz = solve_args_bytes();
+  const int lg_rows = h->tune.lgram_rows > 0 ? h->tune.lgram_rows : kLgRows;
   Sizes Z;
   Bump bump;
   const size_t o_args = bump.take(args_sz * size_t(D) * B);
@@ -204,6 +236,19 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const int NO = 2 * D + 3;  // outputs per problem
   const size_t o_outs = bump.take(size_t(B) * NO * 8);
   const size_t o_infos = bump.take(size_t(B) * D * 4);
+  // work items of every (kind, dim) for the whole batch, and their counts
+  std::vector<size_t> it_off(kItKinds * D);
+  std::vector<long> it_full(kItKinds * D, 0);
+  for (int b = 0; b < B; ++b)
+    for (int d = 0; d < D; ++d) {
+      const taps_problem_t& p = probs[b];
+      it_full[kItGram * D + d] += cdiv(p.n[d], kGramRows);
+      it_full[kItLgram * D + d] += long(cdiv(p.R_cols[d], kLgCols)) * cdiv(p.n[d], lg_rows);
+      it_full[kItForce * D + d] += cdiv(p.n[d], kQRows);
+      it_full[kItRes * D + d] += cdiv(p.n[d], kResRows);
+    }
+  for (int k = 0; k < kItKinds * D; ++k) it_off[k] = bump.take(size_t(it_full[k]) * sizeof(Item));
+  const size_t o_itcnt = bump.take(size_t(kItKinds) * D * 4);
   std::vector<BProb> bp(B);
   std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B), wt_doubles(B);
   std::vector<size_t> o_snap(B);
@@ -212,7 +257,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     int Kmax = 1, nmax = 1, tot = 0;
     size_t ws = 0, gp = 0, lp = 0, wt = 0, nsum = 0;
     for (int d = 0; d < D; ++d) {
-      const int ch = cdiv(p.n[d], kGramRows), ct = cdiv(p.R_cols[d], kLgCols), sp = cdiv(p.n[d], kLgRows);
+      const int ch = cdiv(p.n[d], kGramRows), ct = cdiv(p.R_cols[d], kLgCols), sp = cdiv(p.n[d], lg_rows);
       Kmax = std::max(Kmax, p.n_kinds[d]);
       nmax = std::max(nmax, p.n[d]);
       ws = std::max(ws, solve_ws_bytes(p.n[d], M, p.s[d], use_fd[d]));
@@ -253,6 +298,41 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const CoupleArgs* d_cpl = reinterpret_cast<const CoupleArgs*>(base + o_cpl);
   const WeightArgs* d_wa = reinterpret_cast<const WeightArgs*>(base + o_wa);
   const BalanceArgs* d_bal = reinterpret_cast<const BalanceArgs*>(base + o_bal);
+  const int* d_itcnt = reinterpret_cast<const int*>(base + o_itcnt);
+  auto items = [&](int kind, int d) { return reinterpret_cast<const Item*>(base + it_off[kind * D + d]); };
+  auto count = [&](int kind, int d) { return d_itcnt + kind * D + d; };
+  // persistent grid of one kernel: its items over the whole batch, capped
+  auto pgrid = [&](int kind, int d, int cap) { return unsigned(std::max(1L, std::min(long(cap), it_full[kind * D + d]))); };
+  // work items of the active problems, in problem order (host staging kept
+  // alive until the uploads are synchronised)
+  std::vector<Item> h_items;
+  std::vector<int> h_itcnt(kItKinds * D);
+  std::vector<size_t> h_itpos(kItKinds * D);
+  auto upload_items = [&](const std::vector<int>& act_list, hipStream_t st) -> taps_status {
+    size_t total = 0;
+    for (int k = 0; k < kItKinds * D; ++k) {
+      h_itpos[k] = total;
+      total += size_t(it_full[k]);
+    }
+    h_items.assign(total, Item{0, 0, 0, 0});
+    std::fill(h_itcnt.begin(), h_itcnt.end(), 0);
+    for (int d = 0; d < D; ++d)
+      for (int b : act_list) {
+        const taps_problem_t& p = probs[b];
+        auto put = [&](int kind, int i, int j) { h_items[h_itpos[kind * D + d] + h_itcnt[kind * D + d]++] = Item{b, i, j, 0}; };
+        for (int c = 0; c < cdiv(p.n[d], kGramRows); ++c) put(kItGram, c, 0);
+        for (int c = 0; c < cdiv(p.R_cols[d], kLgCols); ++c)
+          for (int sp = 0; sp < cdiv(p.n[d], lg_rows); ++sp) put(kItLgram, c, sp);
+        for (int c = 0; c < cdiv(p.n[d], kQRows); ++c) put(kItForce, c, 0);
+        for (int c = 0; c < cdiv(p.n[d], kResRows); ++c) put(kItRes, c, 0);
+      }
+    for (int k = 0; k < kItKinds * D; ++k)
+      if (h_itcnt[k])
+        TAPS_HIP(h, hipMemcpyAsync(base + it_off[k], h_items.data() + h_itpos[k], size_t(h_itcnt[k]) * sizeof(Item),
+                                   hipMemcpyHostToDevice, st));
+    TAPS_HIP(h, hipMemcpyAsync(base + o_itcnt, h_itcnt.data(), h_itcnt.size() * 4, hipMemcpyHostToDevice, st));
+    return TAPS_OK;
+  };
 
   // ---- device records (host staging kept alive until the copies are synchronised)
   std::vector<char> args(args_sz * size_t(D) * B);
@@ -345,6 +425,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
                              stream));
   TAPS_HIP(h, hipMemcpyAsync(base + o_bal, bal.data(), sizeof(BalanceArgs) * B, hipMemcpyHostToDevice, stream));
   TAPS_HIP(h, hipMemcpyAsync(d_active, active.data(), size_t(B) * 4, hipMemcpyHostToDevice, stream));
+  TAPS_TRY(upload_items(active, stream));
   TAPS_HIP(h, hipStreamSynchronize(stream));
 
   const size_t glds = size_t(gram_lds_doubles(M, *std::max_element(p0.s, p0.s + D))) * 8;
@@ -358,13 +439,14 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto refresh = [&](int e, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_gram_partial<<<dim3(Z.chunks[e], nact), 256, glds, st>>>(d_prob, d_active, e);
+    kb_gram_partial<<<pgrid(kItGram, e, kPersistLds), 256, glds, st>>>(d_prob, items(kItGram, e), count(kItGram, e), e);
     TAPS_LAUNCHED(h, "kb_gram_partial");
     kb_gram_sum<<<dim3(cdiv(Z.gram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_sum");
-    kb_lgram_partial<<<dim3(Z.ctiles[e], Z.splits[e], nact), 256, 0, st>>>(d_prob, d_active, e);
+    kb_lgram_partial<<<pgrid(kItLgram, e, kPersistStream), 256, 0, st>>>(d_prob, items(kItLgram, e),
+                                                                        count(kItLgram, e), e, lg_rows);
     TAPS_LAUNCHED(h, "kb_lgram_partial");
-    kb_lgram_sum<<<dim3(cdiv(Z.lgram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
+    kb_lgram_sum<<<dim3(cdiv(Z.lgram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e, lg_rows);
     TAPS_LAUNCHED(h, "kb_lgram_sum");
     // work of the method: Grams (U read once for all kinds, K M^2 written;
     // flops K (2 bw n M + 2 n M^2)) and load Gram (F and U read, R M written;
@@ -387,7 +469,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_LAUNCHED(h, "kb_load_terms");
     kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_weights");
-    kb_force<<<dim3(Z.rblocks[d], nact), 256, 0, st>>>(d_prob, d_active, d);
+    kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, items(kItForce, d), count(kItForce, d), d);
     TAPS_LAUNCHED(h, "kb_force");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -399,7 +481,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return prof_end(h, slot, fl, by, st);
   };
   auto residual_parts = [&](int d, int nact, hipStream_t st) -> taps_status {
-    kb_residual_part<<<dim3(Z.rchunks[d], nact), 256, rlds, st>>>(d_prob, d_active, d);
+    kb_residual_part<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, items(kItRes, d), count(kItRes, d), d);
     TAPS_LAUNCHED(h, "kb_residual_part");
     return TAPS_OK;
   };
@@ -456,7 +538,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   }
   auto graph_for = [&](int nact, int k) -> taps_status {
     std::vector<int64_t> sig = {int64_t(reinterpret_cast<intptr_t>(base)), B, D, M, nact, k, int64_t(glds),
-                                int64_t(rlds), Z.max_terms};
+                                int64_t(rlds), Z.max_terms, lg_rows};
+    for (long v : it_full) sig.push_back(v);
     for (int d = 0; d < D; ++d) {
       sig.push_back(p0.s[d] * 2 + use_fd[d]);
       for (int v : {Z.chunks[d], Z.ctiles[d], Z.splits[d], Z.gram[d], Z.lgram[d], Z.rblocks[d], Z.cpl[d], Z.wt[d],
@@ -522,6 +605,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     }
     if (next.size() != active.size() && !next.empty()) {
       TAPS_HIP(h, hipMemcpyAsync(d_active, next.data(), next.size() * 4, hipMemcpyHostToDevice, run));
+      TAPS_TRY(upload_items(next, run));
       TAPS_HIP(h, hipStreamSynchronize(run));
     }
     active.swap(next);

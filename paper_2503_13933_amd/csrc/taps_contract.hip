@@ -20,7 +20,7 @@ __global__ void k_sum_parts(int nparts, long len, const double* __restrict__ par
 
 __global__ __launch_bounds__(256) void k_lgram_partial(int n, int Rc, int M, const double* __restrict__ F, const double* __restrict__ U,
                                 double* __restrict__ part) {
-  lgram_partial(blockIdx.x, blockIdx.y, n, Rc, M, F, U, part);
+  lgram_partial(blockIdx.x, blockIdx.y, kLgRows, n, Rc, M, F, U, part);
 }
 
 __global__ void k_couple(CoupleArgs A, double* __restrict__ C) { couple(blockIdx.x, A, C); }

@@ -163,21 +163,22 @@ __device__ inline void sum_parts(int tblock, int nparts, long len, const double*
   sum_parts_n<1>(tblock, nparts, len, part, out);
 }
 
-// Partial of L = F^T U for load columns [ctile*kLgCols, +kLgCols) over rows of
-// split `split`, on the matrix cores: wave v owns load columns
+// Partial of L = F^T U for load columns [ctile*kLgCols, +kLgCols) over rows
+// [split*rows, +rows) (rows a multiple of 16), on the matrix cores: wave v owns load columns
 // [16v, 16v+16) of the tile, the rows are the contracted index, and the
 // M columns of U are covered in passes of up to four 16-wide tiles.  Operands
 // are read from global memory (16 consecutive doubles per row and step).
 // part layout: [split][Rc][M].
-__device__ inline void lgram_partial(int ctile, int split, int n, int Rc, int M, const double* __restrict__ F_,
-                                     const double* __restrict__ U_, double* __restrict__ part_) {
+__device__ inline void lgram_partial(int ctile, int split, int rows, int n, int Rc, int M,
+                                     const double* __restrict__ F_, const double* __restrict__ U_,
+                                     double* __restrict__ part_) {
   const auto F = gp(F_);
   const auto U = gp(U_);
   const auto part = gp(part_);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int cw = ctile * kLgCols + wv * 16;
   if (cw >= Rc) return;
-  const int rbeg = split * kLgRows, rend = min(n, rbeg + kLgRows);
+  const int rbeg = split * rows, rend = min(n, rbeg + rows);
   const int ca = cw + (lane & 15);
   const int nct = (M + 15) / 16;
   for (int ct0 = 0; ct0 < nct; ct0 += 4) {

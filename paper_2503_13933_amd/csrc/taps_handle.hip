@@ -201,6 +201,8 @@ taps_status taps_set_tuning(taps_handle_t h, const taps_tuning_t* t) {
   if (!t || t->graph_sweeps < 0 || t->graph_sweeps > 16)
     return taps::fail(h, TAPS_ERR_INVALID, "graph_sweeps must be 0..16");
   if (t->solver != 0 && t->solver != 1) return taps::fail(h, TAPS_ERR_INVALID, "solver must be 0 or 1");
+  if (t->lgram_rows != 0 && (t->lgram_rows < 16 || t->lgram_rows > 4096 || t->lgram_rows % 16))
+    return taps::fail(h, TAPS_ERR_INVALID, "lgram_rows must be 0 or a multiple of 16 in 16..4096");
   h->tune = *t;
   return TAPS_OK;
 }

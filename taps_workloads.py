@@ -139,6 +139,139 @@ def heat_slab_family(batch: int = 64, seed: int = 4, **grid):
     return out
 
 
+@dataclass(frozen=True)
+class SPTSlab:
+    """One space-parameter-time slab (x, y, z, P, r, k, t): the heat slab with
+    laser power P, beam radius r and conductivity k as extra tensor
+    dimensions of uniform nodes over their ranges (paper Sec. 2.3, the
+    space-parameter-time variables)."""
+
+    axes: Tuple[Axis, Axis, Axis, Axis, Axis, Axis, Axis]
+    M: int
+    seed: int
+    rho_cp: float = 4.0e-3
+    eta: float = 0.4
+    depth: float = 0.050
+    speed: float = 1.0
+    x_start: float = 0.1
+    y0: float = 0.5
+    kind: str = "spt_slab"
+
+    @property
+    def rho_cp_per_ms(self) -> float:
+        return self.rho_cp * 1.0e3
+
+    @property
+    def height(self) -> float:
+        return self.axes[2].hi
+
+
+PARAM_BOUNDS = {"P": (100.0, 300.0), "r": (0.030, 0.080), "k": (0.010, 0.030)}
+
+
+def spt_slab(nx: int, ny: int, nz: int, nt: int, n_param: int = 32, M: int = 30, seed: int = 3,
+             s: int = 2, p: int = 2, duration_ms: float = 0.8, **phys) -> SPTSlab:
+    """Space-parameter-time slab: x, y in [0, 1 mm], z in [0, 0.2 mm], P, r, k
+    on n_param uniform nodes of their ranges, t in [0, duration]; z = 0 and
+    t = 0 fixed."""
+    ax = [
+        Axis("x", 0.0, 1.0, nx, s, 20.0, p),
+        Axis("y", 0.0, 1.0, ny, s, 20.0, p),
+        Axis("z", 0.0, 0.2, nz, s, 20.0, p, fixed=(0,)),
+        Axis("P", *PARAM_BOUNDS["P"], n_param, s, 20.0, p),
+        Axis("r", *PARAM_BOUNDS["r"], n_param, s, 20.0, p),
+        Axis("k", *PARAM_BOUNDS["k"], n_param, s, 20.0, p),
+        Axis("t", 0.0, duration_ms, nt, s, 20.0, p, fixed=(0,)),
+    ]
+    return SPTSlab(tuple(ax), M, seed, **phys)
+
+
+def spt_batch(batch: int = 64, n_lo: int = 64, n_hi: int = 1024, n_param: int = 32, M: int = 30,
+              seed: int = 3):
+    """Uneven batch of space-parameter-time slabs: n_x, n_y, n_z, n_t drawn
+    from U{n_lo..n_hi}, the track offset y0 from U[0.3, 0.7] mm per problem."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(batch):
+        nx, ny, nz, nt = (int(v) for v in rng.integers(n_lo, n_hi + 1, size=4))
+        y0 = float(rng.uniform(0.3, 0.7))
+        out.append(spt_slab(nx, ny, nz, nt, n_param=n_param, M=M, seed=seed * 100003 + b, y0=y0))
+    return out
+
+
+@dataclass(frozen=True)
+class STConvergence:
+    """The space-time convergence problem of the paper's first results
+    section: du/dt - lap u = f with rho c_p = k = 1 and the exact field
+    u = (1 - exp(-decay t)) exp(-y^2 - (x - speed t - x0)^2) (independent of
+    z), u = 0 at t = 0 and u = u^ex on every spatial face.  Readings (the
+    paper gives neither): x in [0, 10], y in [-5, 5], z in [0, 1], t in
+    [0, 0.05], so the Gaussian travels from x = 5 onto the x = 10 face (the
+    faces carry O(1) data there and on both z faces)."""
+
+    axes: Tuple[Axis, Axis, Axis, Axis]
+    M: int
+    seed: int
+    speed: float = 100.0
+    x0: float = 5.0
+    decay: float = 15.0
+    kind: str = "st_convergence"
+
+
+def st_convergence(n: int = 100, nt: int = 100, M: int = 25, s: int = 1, p: int = 1, seed: int = 5,
+                   n_y: int | None = None, n_z: int | None = None, T: float = 0.05) -> STConvergence:
+    """n nodes along x (and y, z unless given), nt along t; every spatial face
+    Dirichlet (fixed rows of the homogeneous part), t = 0 fixed."""
+    ny = n if n_y is None else n_y
+    nz = n if n_z is None else n_z
+    ends = lambda m: (0, m - 1)
+    ax = [
+        Axis("x", 0.0, 10.0, n, s, 20.0, p, fixed=ends(n)),
+        Axis("y", -5.0, 5.0, ny, s, 20.0, p, fixed=ends(ny)),
+        Axis("z", 0.0, 1.0, nz, s, 20.0, p, fixed=ends(nz)),
+        Axis("t", 0.0, T, nt, s, 20.0, p, fixed=(0,)),
+    ]
+    return STConvergence(tuple(ax), M, seed)
+
+
+@dataclass(frozen=True)
+class SPT8Convergence:
+    """The space-parameter-time convergence problem of the paper's second
+    results section on eight dimensions (x, y, z, k, P, rho, c_p, t):
+    rho c_p du/dt - k lap u = f with the exact field
+    u = rho c_p P (1 - exp(-decay k t)) exp(-width (x^2 + y^2)) (independent
+    of z), u = 0 at t = 0, u = u^ex on every spatial face.  Readings (the
+    paper states neither domain nor ranges): x, y in [-1, 1], z in [0, 1],
+    k, P, rho, c_p in [1, 2], t in [0, 0.2]."""
+
+    axes: Tuple[Axis, ...]
+    M: int
+    seed: int
+    decay: float = 15.0
+    width: float = 25.0
+    kind: str = "spt8_convergence"
+
+
+def spt8_convergence(n: int = 20, M: int = 20, s: int = 1, p: int = 1, seed: int = 8,
+                     n_param: int | None = None, nt: int | None = None) -> SPT8Convergence:
+    """n nodes along every dim (n_param along k, P, rho, c_p and nt along t
+    when given); every spatial face Dirichlet, t = 0 fixed."""
+    npar = n if n_param is None else n_param
+    ntt = n if nt is None else nt
+    ends = lambda m: (0, m - 1)
+    ax = [
+        Axis("x", -1.0, 1.0, n, s, 20.0, p, fixed=ends(n)),
+        Axis("y", -1.0, 1.0, n, s, 20.0, p, fixed=ends(n)),
+        Axis("z", 0.0, 1.0, n, s, 20.0, p, fixed=ends(n)),
+        Axis("k", 1.0, 2.0, npar, s, 20.0, p),
+        Axis("P", 1.0, 2.0, npar, s, 20.0, p),
+        Axis("rho", 1.0, 2.0, npar, s, 20.0, p),
+        Axis("cp", 1.0, 2.0, npar, s, 20.0, p),
+        Axis("t", 0.0, 0.2, ntt, s, 20.0, p, fixed=(0,)),
+    ]
+    return SPT8Convergence(tuple(ax), M, seed)
+
+
 def initial_factors(axes, M: int, seed: int):
     """Random initial mode factors U_d ~ N(0,1) (n_d x M, float64, row-major),
     one PCG64 stream per problem, dims drawn in order; rows of fixed nodes are 0."""

@@ -74,17 +74,40 @@ def test_autotune_restores_factors_and_uses_cache(env, tmp_path):
     U = [d.factors(u) for d, u in zip(devs, U0)]
     before = [[u.clone() for u in Ub] for Ub in U]
     path = str(tmp_path / "tune.json")
-    K, ms = capi.taps_autotune(h, [d.struct for d in devs], U, path)
+    t, ms = capi.taps_autotune(h, [d.struct for d in devs], U, path)
     torch.cuda.synchronize()
-    _say(f"autotune: ms per sweep for graph_sweeps 0/1/2/4 = {[round(m, 3) for m in ms]} -> {K}")
-    assert K in (0, 1, 2, 4) and all(m > 0 for m in ms)
-    assert capi.taps_get_tuning(h).graph_sweeps == K
+    _say(f"autotune: ms per sweep for lgram_rows 128/256/512/1024 = {[round(m, 3) for m in ms[:4]]}, "
+         f"graph_sweeps 0/1/2/4 = {[round(m, 3) for m in ms[4:]]} -> K={t.graph_sweeps} rows={t.lgram_rows}")
+    assert t.graph_sweeps in (0, 1, 2, 4) and t.lgram_rows in (128, 256, 512, 1024) and all(m > 0 for m in ms)
+    got = capi.taps_get_tuning(h)
+    assert got.graph_sweeps == t.graph_sweeps and got.lgram_rows == t.lgram_rows
     for a, b in zip(U, before):
         for u, v in zip(a, b):
             assert torch.equal(u, v)
-    assert os.path.exists(path) and "graph_sweeps" in open(path).read()
-    K2, ms2 = capi.taps_autotune(h, [d.struct for d in devs], U, path)
-    assert K2 == K and all(m == -1.0 for m in ms2)
-    capi.taps_set_tuning(h, 0)
+    assert os.path.exists(path) and "lgram_rows" in open(path).read()
+    t2, ms2 = capi.taps_autotune(h, [d.struct for d in devs], U, path)
+    assert (t2.graph_sweeps, t2.lgram_rows) == (t.graph_sweeps, t.lgram_rows) and all(m == -1.0 for m in ms2)
+    capi.taps_set_tuning(h, 0, lgram_rows=0)
     with pytest.raises(RuntimeError):
         capi.taps_set_tuning(h, 17)
+    with pytest.raises(RuntimeError):
+        capi.taps_set_tuning(h, lgram_rows=24)
+
+
+def test_row_splits_give_the_same_result(env):
+    # the load-Gram row split only regroups the sums over rows: every split
+    # gives the same sweep to rounding
+    torch, capi, problem, h = env
+    cases, devs, U0 = batch(env, n=6, seed=35)
+    out = {}
+    for rows in (16, 128, 1024):
+        capi.taps_set_tuning(h, lgram_rows=rows)
+        U = [d.factors(u) for d, u in zip(devs, U0)]
+        capi.taps_als_batched(h, [d.struct for d in devs], U, 0.0, 2)
+        torch.cuda.synchronize()
+        out[rows] = [[u.cpu().numpy() for u in Ub] for Ub in U]
+    capi.taps_set_tuning(h, lgram_rows=0)
+    for rows in (16, 1024):
+        for a, b in zip(out[rows], out[128]):
+            for u, v in zip(a, b):
+                assert np.linalg.norm(u - v) <= 1e-11 * np.linalg.norm(v)
