@@ -167,6 +167,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the space-parameter-time batch")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--c3-only", action="store_true", help="run only the space-parameter-time batch")
     ap.add_argument("--c3-sweeps", type=int, default=3)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="end with a plain device copy of this many MiB (counter calibration)")
@@ -183,6 +184,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.c3_only:
+        # the space-parameter-time batch alone (for kernel traces of it)
+        print(json.dumps({"spt_batch": c3_batch(capi, torch, args)}), flush=True)
+        return
     grid = dict(nx=args.nx, ny=args.nx, nz=args.nz, nt=args.nt, M=args.M)
     h = capi.Handle()
     capi.taps_set_tuning(h, solver=capi.SOLVER_FAST_DIAG if args.solver == "fastdiag" else capi.SOLVER_BLOCK_LU)

@@ -60,8 +60,8 @@ typedef enum {
 typedef struct taps_handle* taps_handle_t;
 
 #define TAPS_MAX_DIMS 8
-#define TAPS_MAX_TERMS 16
-#define TAPS_MAX_KINDS 4
+#define TAPS_MAX_TERMS 32
+#define TAPS_MAX_KINDS 8
 #define TAPS_MAX_M 64
 #define TAPS_MAX_S 3
 #define TAPS_MAX_GAUSS 8
@@ -137,17 +137,22 @@ taps_status taps_source1d(taps_handle_t h, taps_source_kind kind, int32_t n_pts,
                           const taps_basis1d_t* basis, double* d_out, hipStream_t stream);
 
 /* 1D matrices and load vectors by Gauss quadrature (Sec. 2.5, the 1D
- * integrals of the spatial, parametric and temporal terms):
+ * integrals of the spatial, parametric and temporal terms; Appendix A, the
+ * solution-dependent coefficients):
  *   TAPS_MASS   int Ntilde_i Ntilde_j        TAPS_STIFF int Btilde_i Btilde_j
  *   TAPS_DDT    int Ntilde_i Btilde_j        TAPS_WMASS int c(x) Ntilde_i Ntilde_j
  *   TAPS_BMASS  e_b e_b^T (boundary point mass of node bnode[k])
+ *   TAPS_WSTIFF int c(x) Btilde_i Btilde_j
+ *   TAPS_WDDT   int Ntilde_i d/dx (c(x) Ntilde_j) = int Ntilde_i (c' Ntilde_j + c Btilde_j)
  * d_band: n_kinds (<= 8) bands of n_nodes*(4s+3) doubles, in the order of kinds[].
- * d_coef_g: c at the Gauss points ((n_nodes-1)*n_gauss), WMASS only.
+ * d_coef_g: c at the Gauss points ((n_nodes-1)*n_gauss) for WMASS and WSTIFF;
+ * for WDDT c followed by c' (2 (n_nodes-1) n_gauss).  The weighted kinds of
+ * one call share d_coef_g.
  * Loads: d_F[i*n_loads + r] = int Ntilde_i f_r with f_r given at the Gauss
  * points as d_f_g[r*n_gpts + g] (n_gpts = (n_nodes-1)*n_gauss).
  * n_loads = 0 skips the loads. */
 typedef enum { TAPS_MASS = 0, TAPS_STIFF = 1, TAPS_DDT = 2, TAPS_WMASS = 3,
-               TAPS_BMASS = 4 } taps_kind;
+               TAPS_BMASS = 4, TAPS_WSTIFF = 5, TAPS_WDDT = 6 } taps_kind;
 taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_kinds,
                             const int32_t* kinds, const double* d_coef_g,
                             const int32_t* bnode, double* d_band, int32_t n_loads,
@@ -165,6 +170,18 @@ taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_
 taps_status taps_band_apply(taps_handle_t h, int32_t n, int32_t s, const double* d_band,
                             int32_t n_cols, const double* d_X, int32_t ldx, const double* d_scale,
                             double alpha, double* d_Y, int32_t ldy, hipStream_t stream);
+
+/* Inner product of two TD fields a = sum_m prod_d A_d[:, m] and
+ * b = sum_m prod_d B_d[:, m] in the metric of one banded 1D matrix per dim
+ * (the mass matrices give the L2 inner product of the interpolated fields,
+ * Sec. 2.3): d_out[m*Mb + m'] = prod_d A_d[:, m]^T S_d B_d[:, m'] and
+ * d_out[Ma*Mb] = the sum of those entries, (a, b).  A_d: n[d] x Ma, B_d:
+ * n[d] x Mb row-major, S_d = d_band[d], one band of taps_assemble1d with
+ * patch size s[d].  Used for the change of a field between iterations
+ * (||a - b||^2 = (a,a) + (b,b) - 2 (a,b)).  d_out holds Ma*Mb + 1 doubles. */
+taps_status taps_td_inner(taps_handle_t h, int32_t D, const int32_t* n, const int32_t* s,
+                          const double* const* d_band, int32_t Ma, const double* const* d_A, int32_t Mb,
+                          const double* const* d_B, double* d_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Separated problem (Sec. 2.5): operator sum_tau gamma_tau (x)_d A^{tau}_d

@@ -16,7 +16,7 @@ import scipy.sparse as sp
 
 from . import basis, quadrature
 
-KINDS = ("mass", "stiff", "ddt", "wmass", "bmass")
+KINDS = ("mass", "stiff", "ddt", "wmass", "bmass", "wstiff", "wddt")
 
 
 class Dim1D:
@@ -30,12 +30,16 @@ class Dim1D:
         self.xg, self.wg, self.elem = quadrature.gauss_points(self.nodes, n_gauss)
         self.Ng, self.Bg = basis.shape_matrices(self.nodes, s, a, p, self.xg)
 
-    def matrix(self, kind, coef=None, bnode=None):
+    def matrix(self, kind, coef=None, bnode=None, dcoef=None):
         """Sparse n x n matrix of one kind.
 
-        kind 'wmass' takes coef = callable c(x) (or values at the Gauss points);
-        kind 'bmass' takes bnode = the boundary node index."""
+        Kinds 'wmass' (int c N_i N_j), 'wstiff' (int c B_i B_j) and 'wddt'
+        (int N_i d/dx (c N_j) = int N_i (c' N_j + c B_j), the time derivative
+        of a product with a solution-dependent coefficient, Appendix A) take
+        coef = callable c(x) or values at the Gauss points; 'wddt' also takes
+        dcoef = c' likewise.  Kind 'bmass' takes bnode = the boundary node."""
         W = sp.diags(self.wg)
+        val = lambda f: f(self.xg) if callable(f) else np.asarray(f, dtype=np.float64)
         if kind == "mass":
             A = self.Ng.T @ W @ self.Ng
         elif kind == "stiff":
@@ -43,8 +47,11 @@ class Dim1D:
         elif kind == "ddt":
             A = self.Ng.T @ W @ self.Bg
         elif kind == "wmass":
-            c = coef(self.xg) if callable(coef) else np.asarray(coef, dtype=np.float64)
-            A = self.Ng.T @ sp.diags(self.wg * c) @ self.Ng
+            A = self.Ng.T @ sp.diags(self.wg * val(coef)) @ self.Ng
+        elif kind == "wstiff":
+            A = self.Bg.T @ sp.diags(self.wg * val(coef)) @ self.Bg
+        elif kind == "wddt":
+            A = self.Ng.T @ sp.diags(self.wg * val(dcoef)) @ self.Ng + self.Ng.T @ sp.diags(self.wg * val(coef)) @ self.Bg
         elif kind == "bmass":
             A = sp.csr_matrix(([1.0], ([bnode], [bnode])), shape=(self.n, self.n))
         else:

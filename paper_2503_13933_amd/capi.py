@@ -13,10 +13,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtaps.so")
 
-MAX_DIMS, MAX_TERMS, MAX_KINDS, MAX_M, MAX_S, MAX_GAUSS = 8, 16, 4, 64, 3, 8
+MAX_DIMS, MAX_TERMS, MAX_KINDS, MAX_M, MAX_S, MAX_GAUSS = 8, 32, 8, 64, 3, 8
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = 0, -1, -2, -3, -4
-MASS, STIFF, DDT, WMASS, BMASS = 0, 1, 2, 3, 4
+MASS, STIFF, DDT, WMASS, BMASS, WSTIFF, WDDT = 0, 1, 2, 3, 4, 5, 6
 SRC_GAUSS, SRC_TOPLAYER, SRC_POLY, SRC_SIN, SRC_NODAL, SRC_EXPQUAD = 0, 1, 2, 3, 4, 5
 FP64, FP32, BF16 = 0, 1, 2
 STORE, REDUCE = 0, 1
@@ -28,6 +28,7 @@ FUNCTIONS = (
     "taps_reconstruct", "taps_reconstruct_batched", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
     "taps_canonicalize", "taps_mlp_cache_bytes", "taps_mlp_forward", "taps_mlp_backward", "taps_mlp_mse",
     "taps_adam_step", "taps_set_tuning", "taps_get_tuning", "taps_autotune", "taps_reconstruct_noalloc",
+    "taps_td_inner",
 )
 MLP_MAX_LAYERS = 8
 PROF_SOLVE, PROF_CONTRACT, PROF_RECON, PROF_EIG, PROF_SCHUR = 0, 1, 2, 3, 4
@@ -108,6 +109,7 @@ def lib():
             "taps_get_tuning": (i32, [vp, P(Tuning)]),
             "taps_autotune": (i32, [vp, i32, P(Problem), P(vp), C.c_char_p, P(Tuning), P(dbl), vp]),
             "taps_reconstruct_noalloc": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
+            "taps_td_inner": (i32, [vp, i32, P(i32), P(i32), P(vp), i32, P(vp), i32, P(vp), vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -340,6 +342,16 @@ def taps_reconstruct(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int =
     n = (C.c_int32 * 3)(*[int(P.shape[0]) for P in Phis])
     h.check(lib().taps_reconstruct(h.h, n, _ptr_array(Phis), M, _ptr(mode_w), prec, mode, _ptr(out), thr,
                                    _stream(stream)), "taps_reconstruct")
+
+
+def taps_td_inner(h: Handle, s, bands, A, B, out, stream=None):
+    """out (Ma*Mb + 1 doubles): entrywise prod_d A_d^T S_d B_d, then the sum
+    (the inner product of the two TD fields in the metric of the bands)."""
+    D = len(A)
+    n = (C.c_int32 * D)(*[int(a.shape[0]) for a in A])
+    ss = (C.c_int32 * D)(*s)
+    h.check(lib().taps_td_inner(h.h, D, n, ss, _ptr_array(bands), int(A[0].shape[1]), _ptr_array(A),
+                                int(B[0].shape[1]), _ptr_array(B), _ptr(out), _stream(stream)), "taps_td_inner")
 
 
 def taps_reconstruct_noalloc(h: Handle, Phis, M: int, out, prec: int = FP64, mode: int = STORE, mode_w=None,

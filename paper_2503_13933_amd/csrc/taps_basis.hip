@@ -250,6 +250,7 @@ __global__ void k_band(BandArgs A, const double* __restrict__ Ng, const double* 
                        const int* __restrict__ firstg, const double* __restrict__ wg,
                        const double* __restrict__ coef, double* __restrict__ band) {
   const int w = 2 * A.s + 1, BW = 2 * w + 1, Lw = 2 * A.s + 2;
+  const long ngp = long(A.n - 1) * A.ng;
   const long idx = blockIdx.x * long(blockDim.x) + threadIdx.x;
   if (idx >= long(A.K) * A.n * BW) return;
   const int kk = int(idx / (long(A.n) * BW));
@@ -267,11 +268,15 @@ __global__ void k_band(BandArgs A, const double* __restrict__ Ng, const double* 
         for (int g = 0; g < A.ng; ++g) {
           const long P = long(e) * A.ng + g;
           const int f = firstg[P];
-          const double ai = (kind == TAPS_STIFF) ? dNg[P * Lw + (i - f)] : Ng[P * Lw + (i - f)];
-          const double bj = (kind == TAPS_MASS || kind == TAPS_WMASS) ? Ng[P * Lw + (j - f)]
-                                                                      : dNg[P * Lw + (j - f)];
-          const double c = (kind == TAPS_WMASS) ? wg[P] * coef[P] : wg[P];
+          const bool dtest = kind == TAPS_STIFF || kind == TAPS_WSTIFF;
+          const bool dtrial = kind == TAPS_STIFF || kind == TAPS_WSTIFF || kind == TAPS_DDT || kind == TAPS_WDDT;
+          const double ai = dtest ? dNg[P * Lw + (i - f)] : Ng[P * Lw + (i - f)];
+          const double bj = dtrial ? dNg[P * Lw + (j - f)] : Ng[P * Lw + (j - f)];
+          const bool weighted = kind == TAPS_WMASS || kind == TAPS_WSTIFF || kind == TAPS_WDDT;
+          const double c = weighted ? wg[P] * coef[P] : wg[P];
           val += c * ai * bj;
+          if (kind == TAPS_WDDT)   // + int Ntilde_i c' Ntilde_j
+            val += wg[P] * coef[ngp + P] * ai * Ng[P * Lw + (j - f)];
         }
       }
     }
@@ -325,6 +330,51 @@ __global__ void k_band_apply(int n, int w, const double* __restrict__ band, int 
   double v = 0.0;
   for (int j = j0; j <= j1; ++j) v += band[long(i) * BW + (j - i + w)] * X[long(j) * ldx + c];
   Y[long(i) * ldy + c] = alpha * (scale ? scale[c] : 1.0) * v;
+}
+
+struct TdInnerArgs {
+  int D, Ma, Mb;
+  int n[TAPS_MAX_DIMS], w[TAPS_MAX_DIMS];
+  const double* band[TAPS_MAX_DIMS];
+  const double* A[TAPS_MAX_DIMS];
+  const double* B[TAPS_MAX_DIMS];
+};
+
+// G[m][m'] = prod_d A_d[:, m]^T S_d B_d[:, m'] (S_d banded): block (m, m'),
+// rows strided over the threads, one block-wide sum per dim in a fixed order.
+__global__ __launch_bounds__(256) void k_td_gram(TdInnerArgs T, double* __restrict__ G) {
+  __shared__ double red[256];
+  const int m = blockIdx.x, mp = blockIdx.y, tid = threadIdx.x;
+  double prod = 1.0;
+  for (int d = 0; d < T.D; ++d) {
+    const int n = T.n[d], w = T.w[d], BW = 2 * w + 1;
+    const double* A = T.A[d];
+    const double* B = T.B[d];
+    const double* band = T.band[d];
+    double acc = 0.0;
+    for (int i = tid; i < n; i += 256) {
+      double sb = 0.0;
+      for (int j = max(0, i - w); j <= min(n - 1, i + w); ++j) sb += band[long(i) * BW + (j - i + w)] * B[long(j) * T.Mb + mp];
+      acc += A[long(i) * T.Ma + m] * sb;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    prod *= red[0];
+    __syncthreads();
+  }
+  if (tid == 0) G[long(m) * T.Mb + mp] = prod;
+}
+
+// out[Ma*Mb] = sum of every entry of G, in row order.
+__global__ void k_td_total(int len, double* __restrict__ G) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int t = 0; t < len; ++t) s += G[t];
+  G[len] = s;
 }
 
 BasisArgs basis_args(const taps_basis1d_t* b) {
@@ -432,8 +482,9 @@ taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_
   A.ng = b->n_gauss;
   A.K = n_kinds;
   for (int k = 0; k < n_kinds; ++k) {
-    if (kinds[k] < TAPS_MASS || kinds[k] > TAPS_BMASS) return fail(h, TAPS_ERR_INVALID, "kind %d", kinds[k]);
-    if (kinds[k] == TAPS_WMASS && !d_coef_g) return fail(h, TAPS_ERR_INVALID, "WMASS needs coefficients");
+    if (kinds[k] < TAPS_MASS || kinds[k] > TAPS_WDDT) return fail(h, TAPS_ERR_INVALID, "kind %d", kinds[k]);
+    if ((kinds[k] == TAPS_WMASS || kinds[k] == TAPS_WSTIFF || kinds[k] == TAPS_WDDT) && !d_coef_g)
+      return fail(h, TAPS_ERR_INVALID, "weighted kind %d needs coefficients", kinds[k]);
     A.kinds[k] = kinds[k];
     A.bnode[k] = -1;
     if (kinds[k] == TAPS_BMASS) {
@@ -482,6 +533,33 @@ taps_status taps_band_apply(taps_handle_t h, int32_t n, int32_t s, const double*
   k_band_apply<<<grid_for(long(n) * n_cols, 256), 256, 0, stream>>>(n, 2 * s + 1, d_band, n_cols, d_X, ldx, d_scale,
                                                                      alpha, d_Y, ldy);
   TAPS_LAUNCHED(h, "k_band_apply");
+  return TAPS_OK;
+}
+
+taps_status taps_td_inner(taps_handle_t h, int32_t D, const int32_t* n, const int32_t* s,
+                          const double* const* d_band, int32_t Ma, const double* const* d_A, int32_t Mb,
+                          const double* const* d_B, double* d_out, hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (D < 1 || D > TAPS_MAX_DIMS || Ma < 1 || Mb < 1 || Ma > 1024 || Mb > 1024)
+    return fail(h, TAPS_ERR_INVALID, "D=%d Ma=%d Mb=%d", D, Ma, Mb);
+  if (!n || !s || !d_band || !d_A || !d_B || !d_out) return fail(h, TAPS_ERR_INVALID, "null pointer");
+  TdInnerArgs T{};
+  T.D = D;
+  T.Ma = Ma;
+  T.Mb = Mb;
+  for (int d = 0; d < D; ++d) {
+    if (n[d] < 1 || s[d] < 0 || s[d] > TAPS_MAX_S) return fail(h, TAPS_ERR_INVALID, "dim %d: n=%d s=%d", d, n[d], s[d]);
+    if (!d_band[d] || !d_A[d] || !d_B[d]) return fail(h, TAPS_ERR_INVALID, "dim %d: null pointer", d);
+    T.n[d] = n[d];
+    T.w[d] = 2 * s[d] + 1;
+    T.band[d] = d_band[d];
+    T.A[d] = d_A[d];
+    T.B[d] = d_B[d];
+  }
+  k_td_gram<<<dim3(Ma, Mb), 256, 0, stream>>>(T, d_out);
+  TAPS_LAUNCHED(h, "k_td_gram");
+  k_td_total<<<1, 64, 0, stream>>>(Ma * Mb, d_out);
+  TAPS_LAUNCHED(h, "k_td_total");
   return TAPS_OK;
 }
 

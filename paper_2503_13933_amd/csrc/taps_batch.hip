@@ -4,13 +4,15 @@
 // active problems: Gram refreshes, couplings, forces, the dim solves (one
 // workgroup per system), the backward-error check, balancing and the
 // residual.  The row-chunked contraction kernels (Gram, load Gram, force,
-// residual) are persistent: a fixed grid of workgroups strides over a list of
-// work items -- one per (problem, row chunk), or (problem, column tile, row
-// split) for the load Gram -- that holds exactly the chunks of the active
-// problems however uneven their sizes, with the item count read from device
-// memory so a captured graph stays valid.  Problems that reach the tolerance
-// or break down are predicated off on the host after each sweep by shrinking
-// the active list (and its work items).
+// residual) are persistent: a fixed grid of workgroups strides over the work
+// items -- one per (problem, row chunk), or (problem, column tile, row split)
+// for the load Gram -- of exactly the active problems however uneven their
+// sizes.  Item w belongs to the active problem a with pref[a] <= w <
+// pref[a+1] (a binary search in a per-kind prefix table of the active
+// problems' item counts, read from device memory, so a captured graph stays
+// valid while the table changes).  Problems that reach the tolerance or break
+// down are predicated off on the host after each sweep by shrinking the
+// active list and its prefix tables.
 #include "taps_device.hpp"
 
 #include <algorithm>
@@ -42,23 +44,33 @@ struct BProb {
   double* outs;  // res (D+2), backward error per dim (D), relative change of the sweep (1)
 };
 
-// Work item of the persistent kernels: problem b, chunk or column tile i,
-// row split j.
-struct Item {
-  int b, i, j, pad;
-};
 enum { kItGram = 0, kItLgram = 1, kItForce = 2, kItRes = 3, kItKinds = 4 };
-// persistent grid sizes: LDS-heavy bodies (Gram, residual) hold a few
-// workgroups per compute unit, the streaming ones (load Gram, force) more
-constexpr int kPersistLds = 1024, kPersistStream = 2048;
+// persistent grid sizes (a few items per workgroup at full batches)
+constexpr int kPersistLds = 4096, kPersistStream = 8192;
 
-__global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const Item* __restrict__ it,
-                                                       const int* __restrict__ cnt, int e) {
-  const int nit = *cnt;
+// Work item w -> (active problem index in P, item index within the problem):
+// the largest a with pref[a] <= w (pref has nact + 1 entries, pref[nact] the
+// item count).
+struct Item {
+  int b, c;
+};
+__device__ inline Item locate(const int* __restrict__ act, const int* __restrict__ pref, int nact, int w) {
+  int lo = 0, hi = nact;   // pref[lo] <= w < pref[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pref[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  return Item{act[lo], w - pref[lo]};
+}
+
+__global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
+                                                       const int* __restrict__ pref, int nact, int e) {
+  const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = it[w];
+    const Item x = locate(act, pref, nact, w);
     const BProb& q = P[x.b];
-    gram_partial(x.i, q.n[e], q.M, q.s[e], q.K[e], q.band[e], q.U[e], q.gpart + long(x.i) * q.K[e] * q.M * q.M);
+    gram_partial(x.c, q.n[e], q.M, q.s[e], q.K[e], q.band[e], q.U[e], q.gpart + long(x.c) * q.K[e] * q.M * q.M);
     __syncthreads();   // LDS free for the next item
   }
 }
@@ -75,13 +87,15 @@ __global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__
   sum_parts_n<kVB>(blockIdx.x * kVB, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
 }
 
-__global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const Item* __restrict__ it,
-                                                        const int* __restrict__ cnt, int e, int rows) {
-  const int nit = *cnt;
+__global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
+                                                        const int* __restrict__ pref, int nact, int e, int rows) {
+  const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = it[w];
+    const Item x = locate(act, pref, nact, w);
     const BProb& q = P[x.b];
-    lgram_partial(x.i, x.j, rows, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
+    const int splits = (q.n[e] + rows - 1) / rows;
+    const int ct = x.c / splits;
+    lgram_partial(ct, x.c - ct * splits, rows, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
   }
 }
 
@@ -108,24 +122,24 @@ __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* _
   for (int u = 0; u < kVB; ++u) load_weights(blockIdx.x * kVB + u, WA[long(b) * D + d], P[b].Wt);
 }
 
-__global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const Item* __restrict__ it,
-                                                const int* __restrict__ cnt, int d) {
-  const int nit = *cnt;
+__global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act,
+                                                const int* __restrict__ pref, int nact, int d) {
+  const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = it[w];
+    const Item x = locate(act, pref, nact, w);
     const BProb& q = P[x.b];
-    force(x.i, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
+    force(x.c, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
   }
 }
 
-__global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const Item* __restrict__ it,
-                                                        const int* __restrict__ cnt, int d) {
-  const int nit = *cnt;
+__global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act,
+                                                        const int* __restrict__ pref, int nact, int d) {
+  const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = it[w];
+    const Item x = locate(act, pref, nact, w);
     const BProb& q = P[x.b];
-    residual_part(x.i, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
-                  q.rparts + 2 * (q.roff[d] + x.i));
+    residual_part(x.c, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
+                  q.rparts + 2 * (q.roff[d] + x.c));
     __syncthreads();   // LDS free for the next item
   }
 }
@@ -218,8 +232,11 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     bool fd = h->tune.solver == 1;
     for (int b = 0; b < B && fd; ++b) fd = solve_fd_supported(M, p0.s[d], probs[b].n_kinds[d]);
     use_fd[d] = fd;
-    if (!fd && !solve_batched_supported(M, p0.s[d]))
-      return fail(h, TAPS_ERR_UNSUPPORTED, "batched solve needs M=%d, s=%d to fit LDS", M, p0.s[d]);
+    int kmax = 1;
+    for (int b = 0; b < B; ++b) kmax = std::max(kmax, probs[b].n_kinds[d]);
+    if (!fd && !solve_batched_supported(M, p0.s[d], kmax))
+      return fail(h, TAPS_ERR_UNSUPPORTED, "batched block LU needs M=%d, s=%d to fit LDS and at most 4 kinds (%d)", M,
+                  p0.s[d], kmax);
   }
 
   // ---- layout of the batch buffer
@@ -236,19 +253,22 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const int NO = 2 * D + 3;  // outputs per problem
   const size_t o_outs = bump.take(size_t(B) * NO * 8);
   const size_t o_infos = bump.take(size_t(B) * D * 4);
-  // work items of every (kind, dim) for the whole batch, and their counts
-  std::vector<size_t> it_off(kItKinds * D);
+  // work items of every (kind, dim) per problem, their totals over the batch,
+  // and the prefix tables over the active problems (B + 1 entries each)
+  auto items_of = [&](int kind, int b, int d) -> int {
+    const taps_problem_t& p = probs[b];
+    switch (kind) {
+      case kItGram: return cdiv(p.n[d], kGramRows);
+      case kItLgram: return cdiv(p.R_cols[d], kLgCols) * cdiv(p.n[d], lg_rows);
+      case kItForce: return cdiv(p.n[d], kQRows);
+      default: return cdiv(p.n[d], kResRows);
+    }
+  };
   std::vector<long> it_full(kItKinds * D, 0);
   for (int b = 0; b < B; ++b)
-    for (int d = 0; d < D; ++d) {
-      const taps_problem_t& p = probs[b];
-      it_full[kItGram * D + d] += cdiv(p.n[d], kGramRows);
-      it_full[kItLgram * D + d] += long(cdiv(p.R_cols[d], kLgCols)) * cdiv(p.n[d], lg_rows);
-      it_full[kItForce * D + d] += cdiv(p.n[d], kQRows);
-      it_full[kItRes * D + d] += cdiv(p.n[d], kResRows);
-    }
-  for (int k = 0; k < kItKinds * D; ++k) it_off[k] = bump.take(size_t(it_full[k]) * sizeof(Item));
-  const size_t o_itcnt = bump.take(size_t(kItKinds) * D * 4);
+    for (int k = 0; k < kItKinds; ++k)
+      for (int d = 0; d < D; ++d) it_full[k * D + d] += items_of(k, b, d);
+  const size_t o_pref = bump.take(size_t(kItKinds) * D * (B + 1) * 4);
   std::vector<BProb> bp(B);
   std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B), wt_doubles(B);
   std::vector<size_t> o_snap(B);
@@ -298,39 +318,21 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const CoupleArgs* d_cpl = reinterpret_cast<const CoupleArgs*>(base + o_cpl);
   const WeightArgs* d_wa = reinterpret_cast<const WeightArgs*>(base + o_wa);
   const BalanceArgs* d_bal = reinterpret_cast<const BalanceArgs*>(base + o_bal);
-  const int* d_itcnt = reinterpret_cast<const int*>(base + o_itcnt);
-  auto items = [&](int kind, int d) { return reinterpret_cast<const Item*>(base + it_off[kind * D + d]); };
-  auto count = [&](int kind, int d) { return d_itcnt + kind * D + d; };
+  const int* d_pref = reinterpret_cast<const int*>(base + o_pref);
+  auto pref = [&](int kind, int d) { return d_pref + size_t(kind * D + d) * (B + 1); };
   // persistent grid of one kernel: its items over the whole batch, capped
   auto pgrid = [&](int kind, int d, int cap) { return unsigned(std::max(1L, std::min(long(cap), it_full[kind * D + d]))); };
-  // work items of the active problems, in problem order (host staging kept
-  // alive until the uploads are synchronised)
-  std::vector<Item> h_items;
-  std::vector<int> h_itcnt(kItKinds * D);
-  std::vector<size_t> h_itpos(kItKinds * D);
+  // prefix tables of the active problems' item counts (host staging kept
+  // alive until the upload is synchronised)
+  std::vector<int> h_pref(size_t(kItKinds) * D * (B + 1));
   auto upload_items = [&](const std::vector<int>& act_list, hipStream_t st) -> taps_status {
-    size_t total = 0;
-    for (int k = 0; k < kItKinds * D; ++k) {
-      h_itpos[k] = total;
-      total += size_t(it_full[k]);
-    }
-    h_items.assign(total, Item{0, 0, 0, 0});
-    std::fill(h_itcnt.begin(), h_itcnt.end(), 0);
-    for (int d = 0; d < D; ++d)
-      for (int b : act_list) {
-        const taps_problem_t& p = probs[b];
-        auto put = [&](int kind, int i, int j) { h_items[h_itpos[kind * D + d] + h_itcnt[kind * D + d]++] = Item{b, i, j, 0}; };
-        for (int c = 0; c < cdiv(p.n[d], kGramRows); ++c) put(kItGram, c, 0);
-        for (int c = 0; c < cdiv(p.R_cols[d], kLgCols); ++c)
-          for (int sp = 0; sp < cdiv(p.n[d], lg_rows); ++sp) put(kItLgram, c, sp);
-        for (int c = 0; c < cdiv(p.n[d], kQRows); ++c) put(kItForce, c, 0);
-        for (int c = 0; c < cdiv(p.n[d], kResRows); ++c) put(kItRes, c, 0);
+    for (int k = 0; k < kItKinds; ++k)
+      for (int d = 0; d < D; ++d) {
+        int* pr = h_pref.data() + size_t(k * D + d) * (B + 1);
+        pr[0] = 0;
+        for (size_t a = 0; a < act_list.size(); ++a) pr[a + 1] = pr[a] + items_of(k, act_list[a], d);
       }
-    for (int k = 0; k < kItKinds * D; ++k)
-      if (h_itcnt[k])
-        TAPS_HIP(h, hipMemcpyAsync(base + it_off[k], h_items.data() + h_itpos[k], size_t(h_itcnt[k]) * sizeof(Item),
-                                   hipMemcpyHostToDevice, st));
-    TAPS_HIP(h, hipMemcpyAsync(base + o_itcnt, h_itcnt.data(), h_itcnt.size() * 4, hipMemcpyHostToDevice, st));
+    TAPS_HIP(h, hipMemcpyAsync(base + o_pref, h_pref.data(), h_pref.size() * 4, hipMemcpyHostToDevice, st));
     return TAPS_OK;
   };
 
@@ -439,12 +441,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto refresh = [&](int e, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_gram_partial<<<pgrid(kItGram, e, kPersistLds), 256, glds, st>>>(d_prob, items(kItGram, e), count(kItGram, e), e);
+    kb_gram_partial<<<pgrid(kItGram, e, kPersistLds), 256, glds, st>>>(d_prob, d_active, pref(kItGram, e), nact, e);
     TAPS_LAUNCHED(h, "kb_gram_partial");
     kb_gram_sum<<<dim3(cdiv(Z.gram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_sum");
-    kb_lgram_partial<<<pgrid(kItLgram, e, kPersistStream), 256, 0, st>>>(d_prob, items(kItLgram, e),
-                                                                        count(kItLgram, e), e, lg_rows);
+    kb_lgram_partial<<<pgrid(kItLgram, e, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItLgram, e), nact,
+                                                                        e, lg_rows);
     TAPS_LAUNCHED(h, "kb_lgram_partial");
     kb_lgram_sum<<<dim3(cdiv(Z.lgram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e, lg_rows);
     TAPS_LAUNCHED(h, "kb_lgram_sum");
@@ -469,7 +471,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_LAUNCHED(h, "kb_load_terms");
     kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_weights");
-    kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, items(kItForce, d), count(kItForce, d), d);
+    kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItForce, d), nact, d);
     TAPS_LAUNCHED(h, "kb_force");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -481,7 +483,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return prof_end(h, slot, fl, by, st);
   };
   auto residual_parts = [&](int d, int nact, hipStream_t st) -> taps_status {
-    kb_residual_part<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, items(kItRes, d), count(kItRes, d), d);
+    kb_residual_part<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, d_active, pref(kItRes, d), nact, d);
     TAPS_LAUNCHED(h, "kb_residual_part");
     return TAPS_OK;
   };

@@ -190,7 +190,7 @@ size_t solve_args_bytes();
 size_t solve_ws_bytes(int n, int M, int s, bool fd);
 void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_C, const double* d_Q,
                      double* d_X, int* d_info, void* ws, bool fd);
-bool solve_batched_supported(int M, int s);
+bool solve_batched_supported(int M, int s, int K);
 // raises the kernel's LDS limit ahead of any launch (not allowed inside a capture)
 taps_status solve_batched_prepare(taps_handle* h, int M, int s);
 // Fast diagonalisation of two-kind dim systems (solver 1 of the tuning):

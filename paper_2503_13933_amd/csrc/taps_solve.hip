@@ -241,6 +241,9 @@ size_t lu_lds_allowed = 0;
 // layout: A[l%16][l/16], B[l/16][l%16], D[l/16 + 4i][l%16] (i = 0..3).
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kThreadsMfma = 512;
+// kinds the matrix-core block LU holds couplings for in registers; systems
+// with more kinds go to the vector kernel
+constexpr int kLuKinds = 4;
 constexpr int kMaxBlk = 2 * (2 * TAPS_MAX_S + 1) + 1;  // entering blocks per row
 
 __device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
@@ -328,7 +331,7 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
   double* sG0 = Zp + M4 * P16;    // M x M  Gauss-Jordan buffers
   double* sG1 = sG0 + MM;         // M x M
   const double* sPinv = (M % 2 == 0) ? sG0 : sG1;  // where M pivots leave the inverse
-  __shared__ double sCoef[kMaxBlk * TAPS_MAX_KINDS];
+  __shared__ double sCoef[kMaxBlk * kLuKinds];
   __shared__ double sQ[TAPS_MAX_M];
   __shared__ int sFixRow[2 * TAPS_MAX_S + 2];
   __shared__ int s_info;
@@ -357,11 +360,11 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
   // couplings at this thread's entries of an M x M block, zero for kinds
   // k >= K; loaded where blocks are built rather than held for the whole
   // kernel (the registers are needed by the update)
-  auto load_couplings = [&](double (&cr)[TAPS_MAX_KINDS][kEnt]) {
+  auto load_couplings = [&](double (&cr)[kLuKinds][kEnt]) {
 #pragma unroll
     for (int u = 0; u < kEnt; ++u) {
 #pragma unroll
-      for (int k = 0; k < TAPS_MAX_KINDS; ++k) {
+      for (int k = 0; k < kLuKinds; ++k) {
         const double c = A.C[long(min(k, K - 1)) * MM + ej[u] * M + ei[u]];
         cr[k][u] = (k < K) ? c : 0.0;
       }
@@ -373,16 +376,16 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
   for (int t = tid; t < (M4 - M) * P16; t += nt) Zp[M * P16 + t] = 0.0;
   // block (i, j) of the original matrix, from coefficients cf[K] and the fixed
   // flags (bit 0: row i fixed -> identity or zero block, bit 1: column j fixed)
-  // (cf holds TAPS_MAX_KINDS values, zero beyond K, read once per block)
-  auto build = [&](const double (&creg)[TAPS_MAX_KINDS][kEnt], const double* cf, int fix, bool diag, int off) {
-    double c[TAPS_MAX_KINDS];
+  // (cf holds kLuKinds values, zero beyond K, read once per block)
+  auto build = [&](const double (&creg)[kLuKinds][kEnt], const double* cf, int fix, bool diag, int off) {
+    double c[kLuKinds];
 #pragma unroll
-    for (int k = 0; k < TAPS_MAX_KINDS; ++k) c[k] = cf[k];
+    for (int k = 0; k < kLuKinds; ++k) c[k] = cf[k];
 #pragma unroll
     for (int u = 0; u < kEnt; ++u) {
       double v = 0.0;
 #pragma unroll
-      for (int k = 0; k < TAPS_MAX_KINDS; ++k) v += c[k] * creg[k][u];
+      for (int k = 0; k < kLuKinds; ++k) v += c[k] * creg[k][u];
       v = (fix & 2) ? 0.0 : v;
       v = (fix & 1) ? ((diag && ei[u] == ej[u]) ? 1.0 : 0.0) : v;
       const int t = tid + u * nt;
@@ -391,14 +394,14 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
   };
   // initial window rows/cols 0..min(w, n-1)
   {
-    double creg[TAPS_MAX_KINDS][kEnt];
+    double creg[kLuKinds][kEnt];
     load_couplings(creg);
     const int hi = min(w, n - 1);
     for (int i = 0; i <= hi; ++i) {
       for (int j = 0; j <= hi; ++j) {
-        double cf[TAPS_MAX_KINDS];
+        double cf[kLuKinds];
 #pragma unroll
-        for (int k = 0; k < TAPS_MAX_KINDS; ++k)
+        for (int k = 0; k < kLuKinds; ++k)
           cf[k] = (k < K) ? A.band[(long(k) * n + i) * BW + (j - i + w)] : 0.0;
         build(creg, cf, (fixed_at(i) ? 1 : 0) | (fixed_at(j) ? 2 : 0), i == j, woff(i, j));
       }
@@ -409,14 +412,14 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
   // band coefficients, fixed flags of rows kn..kn+w and the load row of the
   // blocks entering at block row kn (row t = kn + w, columns kn..t, and column
   // t, rows kn..t-1): loaded early into registers, stored to LDS late
-  // (thread tid loads coefficient kk = tid % TAPS_MAX_KINDS of block
-  // b = tid / TAPS_MAX_KINDS, zero for kk >= K)
+  // (thread tid loads coefficient kk = tid % kLuKinds of block
+  // b = tid / kLuKinds, zero for kk >= K)
   struct Pre { double cf, q; int fx; };
   auto pre_issue = [&](int kn) {
     Pre pr{0.0, 0.0, 0};
     const int t = kn + w;
     if (t >= n || kn < 1) return pr;
-    const int b = min(tid / TAPS_MAX_KINDS, 2 * w), kk = tid % TAPS_MAX_KINDS;
+    const int b = min(tid / kLuKinds, 2 * w), kk = tid % kLuKinds;
     const int i = (b <= w) ? t : kn + (b - w - 1);
     const int j = (b <= w) ? kn + b : t;
     const double cf = A.band[(long(min(kk, K - 1)) * n + i) * BW + (j - i + w)];
@@ -427,7 +430,7 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
   };
   auto pre_commit = [&](int kn, const Pre& pr) {
     if (kn + w >= n || kn < 1) return;
-    if (tid < (2 * w + 1) * TAPS_MAX_KINDS) sCoef[tid] = pr.cf;
+    if (tid < (2 * w + 1) * kLuKinds) sCoef[tid] = pr.cf;
     if (tid < M) sQ[tid] = pr.q;
     if (tid <= w) sFixRow[tid] = pr.fx;
   };
@@ -440,12 +443,12 @@ __device__ void block_lu_mfma_body(const SolveArgs& A) {
     // (A) entering blocks: row t = k + w (cols k..t) and column t (rows k..t-1)
     if (k > 0 && k + w < n) {
       const int t = k + w;
-      double creg[TAPS_MAX_KINDS][kEnt];
+      double creg[kLuKinds][kEnt];
       load_couplings(creg);
       for (int b = 0; b < 2 * w + 1; ++b) {
         const int i = (b <= w) ? t : k + (b - w - 1);
         const int j = (b <= w) ? k + b : t;
-        build(creg, sCoef + b * TAPS_MAX_KINDS, (sFixRow[i - k] ? 1 : 0) | (sFixRow[j - k] ? 2 : 0), i == j,
+        build(creg, sCoef + b * kLuKinds, (sFixRow[i - k] ? 1 : 0) | (sFixRow[j - k] ? 2 : 0), i == j,
               woff(i, j));
       }
       bstore(rw, tid < M ? roff(t) + tid * 8 : kOOB, sFixRow[w] ? 0.0 : sQ[min(tid, M - 1)]);
@@ -2014,7 +2017,7 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
                            const double* d_Q, double* d_X, int* d_info, double* d_berr, hipStream_t stream) {
   const int n = p->n[d], M = p->M, s = p->s[d], w = 2 * s + 1;
   const size_t lds_mfma = solve_mfma_lds_bytes(M, s);
-  const bool use_mfma = lds_mfma <= 160 * 1024 - 64 && !getenv("TAPS_SOLVE_VECTOR");
+  const bool use_mfma = lds_mfma <= 160 * 1024 - 64 && p->n_kinds[d] <= kLuKinds && !getenv("TAPS_SOLVE_VECTOR");
   const size_t lds = use_mfma ? lds_mfma : solve_lds_bytes(M, s);
   const bool use_fd = h->tune.solver == 1 && fd_supported(M, s, p->n_kinds[d]);
   if (!use_fd && lds > 160 * 1024 - 64)
@@ -2129,7 +2132,9 @@ void solve_args_fill(void* dst, const taps_problem_t* p, int d, const double* d_
   memcpy(dst, &A, sizeof(A));
 }
 
-bool solve_batched_supported(int M, int s) { return solve_mfma_lds_bytes(M, s) <= 160 * 1024 - 64; }
+bool solve_batched_supported(int M, int s, int K) {
+  return solve_mfma_lds_bytes(M, s) <= 160 * 1024 - 64 && K <= kLuKinds;
+}
 
 bool solve_fd_supported(int M, int s, int K) { return fd_supported(M, s, K); }
 double solve_fd_flops(int n, int M, int s) { return fd_flops(n, M, 2 * s + 1); }

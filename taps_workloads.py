@@ -272,6 +272,52 @@ def spt8_convergence(n: int = 20, M: int = 20, s: int = 1, p: int = 1, seed: int
     return SPT8Convergence(tuple(ax), M, seed)
 
 
+@dataclass(frozen=True)
+class NonlinearHeat:
+    """Space-time heat problem with temperature-dependent material (paper's
+    third results section and the appendix on solution-dependent
+    coefficients): d/dt (rho c_p(u) u) - div (k(u) grad u) = f with the linear
+    fits k(u) = m_k u + n_k and rho c_p(u) = m_c u + n_c the paper gives
+    (Inconel 718; u read as the temperature rise above ambient, mm, s, W, J).
+    u = 0 on the left and right faces (x = 0, x = L_x) and at t = 0, zero flux
+    elsewhere.  Source: the moving Gaussian beam of radius r at speed v,
+    volumetric through the plate thickness (2 eta P / (pi r^2 H)
+    exp(-2 ((x - x0 - v t)^2 + (y - y0)^2) / r^2)), or, with
+    source="poly", the load of the exact field u = a x (L_x - x) t."""
+
+    axes: Tuple[Axis, Axis, Axis, Axis]
+    M: int
+    seed: int
+    m_k: float = 1.52e-5
+    n_k: float = 5.29e-3
+    m_c: float = 6.11e-7
+    n_c: float = 3.25e-3
+    power: float = 100.0
+    eta: float = 0.4
+    radius: float = 0.5
+    speed: float = 500.0
+    x_start: float = 1.0
+    y0: float = 5.0
+    amp: float = 1.0
+    source: str = "gauss"
+    kind: str = "nonlinear_heat"
+
+
+def nonlinear_heat(nx: int = 101, ny: int = 101, nz: int = 11, nt: int = 126, M: int = 10, seed: int = 9,
+                   Lx: float = 10.0, Ly: float = 10.0, H: float = 1.0, T: float = 0.02, s: int = 2, p: int = 2,
+                   **phys) -> NonlinearHeat:
+    """The paper's nonlinear set-up by default: 10 mm x 10 mm x 1 mm, beam
+    radius 0.5 mm at 500 mm/s, 10 elements per beam diameter in x and y, time
+    increment 1.6e-4 s over 0.02 s."""
+    ax = [
+        Axis("x", 0.0, Lx, nx, s, 20.0, p, fixed=(0, nx - 1)),
+        Axis("y", 0.0, Ly, ny, s, 20.0, p),
+        Axis("z", 0.0, H, nz, s, 20.0, p),
+        Axis("t", 0.0, T, nt, s, 20.0, p, fixed=(0,)),
+    ]
+    return NonlinearHeat(tuple(ax), M, seed, **phys)
+
+
 def initial_factors(axes, M: int, seed: int):
     """Random initial mode factors U_d ~ N(0,1) (n_d x M, float64, row-major),
     one PCG64 stream per problem, dims drawn in order; rows of fixed nodes are 0."""

@@ -104,3 +104,35 @@ def test_weighted_mass_moments_with_linear_coefficient(s, p):
     # coefficient values given at the Gauss points are the callable's values there
     Wv = D.matrix("wmass", coef=alpha + beta * D.xg).toarray()
     assert np.abs(Wv - W).max() == 0.0
+
+
+@pytest.mark.parametrize("s,p", [(2, 2), (1, 1), (3, 3)])
+def test_weighted_stiffness_and_product_derivative_moments(s, p):
+    # c(x) = alpha + beta x: (x^q)^T W_K x^r = q r int c x^(q+r-2), and
+    # (x^q)^T W_G x^r = int x^q (c x^r)' exactly for q, r <= p; with q = 0 the
+    # latter is c x^r between the domain ends (integration by parts pins the
+    # product rule, not only the sum of its two parts)
+    D = _dim(n=13, s=s, p=p, L=1.3, seed=5)
+    a0, b0 = D.nodes[0], D.nodes[-1]
+    alpha, beta = 0.7, -1.9
+    c = lambda x: alpha + beta * x
+    WK = D.matrix("wstiff", coef=c).toarray()
+    WG = D.matrix("wddt", coef=c, dcoef=lambda x: beta * np.ones_like(x)).toarray()
+    x = D.nodes
+    P = lambda k: (b0 ** k - a0 ** k) / k   # int x^(k-1)
+    for q in range(p + 1):
+        for r in range(p + 1):
+            if q > 0 and r > 0:
+                k = q + r - 2
+                exact = q * r * (alpha * P(k + 1) + beta * P(k + 2))
+                assert abs(x ** q @ WK @ x ** r - exact) < 1e-10 * max(1.0, abs(exact))
+            # int x^q (alpha x^r + beta x^(r+1))' = int x^q (alpha r x^(r-1) + beta (r+1) x^r)
+            exact = (alpha * r * P(q + r) if r > 0 else 0.0) + beta * (r + 1) * P(q + r + 1)
+            assert abs(x ** q @ WG @ x ** r - exact) < 1e-11 * max(1.0, abs(exact))
+        ends = c(b0) * b0 ** q - c(a0) * a0 ** q
+        assert abs(np.ones_like(x) @ WG @ x ** q - ends) < 1e-11 * max(1.0, abs(ends))
+    # a constant coefficient gives c times the plain kinds
+    Kc = D.matrix("wstiff", coef=lambda x: 2.5 * np.ones_like(x)).toarray()
+    Gc = D.matrix("wddt", coef=lambda x: 2.5 * np.ones_like(x), dcoef=lambda x: np.zeros_like(x)).toarray()
+    assert np.abs(Kc - 2.5 * D.matrix("stiff").toarray()).max() < 1e-12
+    assert np.abs(Gc - 2.5 * D.matrix("ddt").toarray()).max() < 1e-14
