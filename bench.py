@@ -458,10 +458,11 @@ def main():
 def c3_batch(capi, torch, args):
     """64 space-parameter-time slabs (x, y, z, P, r, k, t; n_x..n_t drawn from
     64..1024, 32 nodes for P, r, k; M = 30; R = 32 n_t load terms): the
-    autotuner picks the load-Gram row split and the graph length on the
-    batch, then --c3-sweeps sweeps of Algorithm 1 run through the batched
-    driver (captured graphs when the tuner chose them), timed; a second,
-    profiled run gives the contraction kernels' time against their bytes."""
+    autotuner picks the load-Gram row split (and reports its graph-length
+    choice) on the batch, then --c3-sweeps sweeps of Algorithm 1 run through
+    the batched driver as one captured HIP graph, timed; a second, profiled
+    run (host launches) gives the contraction kernels' time against their
+    bytes."""
     import taps_workloads as W
     from paper_2503_13933_amd import problem
     h = capi.Handle()
@@ -479,8 +480,11 @@ def c3_batch(capi, torch, args):
     log(f"c3: 64 space-parameter-time slabs set up in {setup:.1f} s ({f_bytes / 1e9:.2f} GB of load columns); "
         f"autotune lgram_rows {tune.lgram_rows}, graph_sweeps {tune.graph_sweeps} "
         f"(ms per sweep {[round(m, 2) for m in tms]})")
+    # the timed sweeps replay one captured graph holding all of them (the
+    # tuner's row split kept)
+    capi.taps_set_tuning(h, graph_sweeps=args.c3_sweeps)
     U = [[u.clone() for u in Ub] for Ub in U0]
-    capi.taps_als_batched(h, structs, U, 0.0, 1)        # warm-up (and graph capture)
+    capi.taps_als_batched(h, structs, U, 0.0, args.c3_sweeps)   # warm-up and graph capture
     U = [[u.clone() for u in Ub] for Ub in U0]
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -505,6 +509,7 @@ def c3_batch(capi, torch, args):
                         "R = 32 n_t load terms, fast diagonalisation (block LU for P and r)",
             "setup_s": setup, "load_column_gb": f_bytes / 1e9,
             "tuning": {"lgram_rows": tune.lgram_rows, "graph_sweeps": tune.graph_sweeps, "candidates_ms": tms},
+            "graph_sweeps_timed": args.c3_sweeps,
             "sweeps": args.c3_sweeps, "ms_per_sweep": el / args.c3_sweeps * 1e3,
             "problem_sweeps_per_s": 64 * args.c3_sweeps / el, "median_rho": float(np.nanmedian(rho)),
             "median_change": float(np.nanmedian(chg)),

@@ -122,6 +122,16 @@ __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* _
   for (int u = 0; u < kVB; ++u) load_weights(blockIdx.x * kVB + u, WA[long(b) * D + d], P[b].Wt);
 }
 
+// Long groups: block x = group (blocks past a problem's group count return).
+__global__ __launch_bounds__(256) void kb_load_weights_long(const BProb* __restrict__ P,
+                                                            const WeightArgs* __restrict__ WA,
+                                                            const int* __restrict__ act, int d, int D) {
+  const int b = act[blockIdx.y];
+  const WeightArgs& A = WA[long(b) * D + d];
+  if (int(blockIdx.x) >= A.Rc) return;
+  load_weights_long(blockIdx.x, A, P[b].Wt);
+}
+
 __global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act,
                                                 const int* __restrict__ pref, int nact, int d) {
   const int nit = pref[nact];
@@ -197,11 +207,11 @@ size_t gram_lds_allowed = 0, res_lds_allowed = 0;
 struct Sizes {
   int chunks[TAPS_MAX_DIMS], ctiles[TAPS_MAX_DIMS], splits[TAPS_MAX_DIMS], gram[TAPS_MAX_DIMS];
   int lgram[TAPS_MAX_DIMS], rblocks[TAPS_MAX_DIMS], cpl[TAPS_MAX_DIMS], wt[TAPS_MAX_DIMS];
-  int rchunks[TAPS_MAX_DIMS];
+  int rchunks[TAPS_MAX_DIMS], rc[TAPS_MAX_DIMS];
   int max_terms = 1;
   Sizes() {
     for (int d = 0; d < TAPS_MAX_DIMS; ++d)
-      chunks[d] = ctiles[d] = splits[d] = gram[d] = lgram[d] = rblocks[d] = cpl[d] = wt[d] = rchunks[d] = 1;
+      chunks[d] = ctiles[d] = splits[d] = gram[d] = lgram[d] = rblocks[d] = cpl[d] = wt[d] = rchunks[d] = rc[d] = 1;
   }
 };
 
@@ -297,6 +307,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       Z.cpl[d] = std::max(Z.cpl[d], cdiv(long(p.n_kinds[d]) * MM, 256));
       Z.wt[d] = std::max(Z.wt[d], cdiv(long(p.R_cols[d]) * M, 256));
       Z.rchunks[d] = std::max(Z.rchunks[d], cdiv(p.n[d], kResRows));
+      Z.rc[d] = std::max(Z.rc[d], p.R_cols[d]);
     }
     o_cache[b] = bump.take(cache_total(&p));
     o_C[b] = bump.take(size_t(Kmax) * MM * 8);
@@ -318,6 +329,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const CoupleArgs* d_cpl = reinterpret_cast<const CoupleArgs*>(base + o_cpl);
   const WeightArgs* d_wa = reinterpret_cast<const WeightArgs*>(base + o_wa);
   const BalanceArgs* d_bal = reinterpret_cast<const BalanceArgs*>(base + o_bal);
+  // group sums of the load weights: a block per group where the groups are
+  // long (on average 64 terms or more per load column in every problem)
+  std::vector<char> long_groups(D, 1);
+  for (int d = 0; d < D; ++d)
+    for (int b = 0; b < B; ++b)
+      if (long(probs[b].R) < 64L * probs[b].R_cols[d]) long_groups[d] = 0;
   const int* d_pref = reinterpret_cast<const int*>(base + o_pref);
   auto pref = [&](int kind, int d) { return d_pref + size_t(kind * D + d) * (B + 1); };
   // persistent grid of one kernel: its items over the whole batch, capped
@@ -469,8 +486,13 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_LAUNCHED(h, "kb_couple");
     kb_load_terms<<<dim3(cdiv(Z.max_terms, kVB), nact), 256, 0, st>>>(d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_terms");
-    kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
-    TAPS_LAUNCHED(h, "kb_load_weights");
+    if (long_groups[d]) {
+      kb_load_weights_long<<<dim3(Z.rc[d], nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
+      TAPS_LAUNCHED(h, "kb_load_weights_long");
+    } else {
+      kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
+      TAPS_LAUNCHED(h, "kb_load_weights");
+    }
     kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItForce, d), nact, d);
     TAPS_LAUNCHED(h, "kb_force");
     double fl = 0.0, by = 0.0;
@@ -545,7 +567,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     for (int d = 0; d < D; ++d) {
       sig.push_back(p0.s[d] * 2 + use_fd[d]);
       for (int v : {Z.chunks[d], Z.ctiles[d], Z.splits[d], Z.gram[d], Z.lgram[d], Z.rblocks[d], Z.cpl[d], Z.wt[d],
-                    Z.rchunks[d]})
+                    Z.rchunks[d], Z.rc[d], int(long_groups[d])})
         sig.push_back(v);
     }
     if (h->graph_exec && sig == h->graph_sig) return TAPS_OK;

@@ -338,6 +338,38 @@ __device__ inline void load_weights(int tblock, const WeightArgs& A, double* __r
   gp(Wt)[t] = acc;
 }
 
+// The same group sums for long groups (a few groups of many terms each, e.g.
+// a dim whose every load term uses its one column): one block of 256
+// threads per group, as 256/L row lanes x L mode lanes (L = M rounded up to
+// 32 or 64), each row lane summing every (256/L)-th term of the group with
+// eight loads in flight, the row lanes then summed in a fixed order.
+__device__ inline void load_weights_long(int c, const WeightArgs& A, double* __restrict__ Wt) {
+  __shared__ double red[256];
+  const int M = A.M, L = M <= 32 ? 32 : 64, lanes = 256 / L;
+  const int m = threadIdx.x % L, lr = threadIdx.x / L;
+  const int rb = A.ptr ? gp(A.ptr)[c] : c;
+  const int re = A.ptr ? gp(A.ptr)[c + 1] : c + 1;
+  const auto P = gp(A.P) + min(m, M - 1);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int q = rb + lr;
+  for (; q + 7 * lanes < re; q += 8 * lanes) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[long(q + u * lanes) * M];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u & 3] += v[u];
+  }
+  for (; q < re; q += lanes) acc[0] += P[long(q) * M];
+  red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (lr == 0 && m < M) {
+    double s = 0.0;
+    for (int k = 0; k < lanes; ++k) s += red[k * L + m];
+    gp(Wt)[long(c) * M + m] = s;
+  }
+  __syncthreads();
+}
+
 // Q = F_d Wt for rows [rblock*kQRows, +kQRows) on the matrix cores: wave v
 // owns rows [16v, 16v+16) of the block, the load columns are the contracted
 // index (passes of 16 columns in four steps, operands loaded together), and
