@@ -238,6 +238,26 @@ __global__ void k_source(SourceArgs S, const double* __restrict__ pts, const dou
 
 constexpr int kMaxAssembleKinds = 8;
 
+// NODAL source columns: one thread per point computes the point's shape
+// values once and writes every column (nonzero only in its window), column
+// by column so that neighbouring points' stores are adjacent.
+__global__ void k_source_nodal(int npts, int ncols, const double* __restrict__ pts, BasisArgs B,
+                               double* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  double n_[kMaxL], d_[kMaxL];
+  int f;
+  shape_point(B, pts[p], &f, n_, d_);
+  const int L = 2 * B.s + 2;
+  for (int c = 0; c < ncols; ++c) {
+    const int l = c - f;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k) v = (k == l && k < L) ? n_[k] : v;
+    out[long(c) * npts + p] = v;
+  }
+}
+
 struct BandArgs {
   int n, s, ng, K;
   int kinds[kMaxAssembleKinds];
@@ -459,6 +479,11 @@ taps_status taps_source1d(taps_handle_t h, taps_source_kind kind, int32_t n_pts,
       break;
     default:
       return fail(h, TAPS_ERR_INVALID, "unknown source kind %d", int(kind));
+  }
+  if (kind == TAPS_SRC_NODAL) {
+    k_source_nodal<<<grid_for(n_pts, 128), 128, 0, stream>>>(n_pts, n_cols, d_pts, B, d_out);
+    TAPS_LAUNCHED(h, "k_source_nodal");
+    return TAPS_OK;
   }
   k_source<<<grid_for(long(n_pts) * n_cols, 256), 256, 0, stream>>>(S, d_pts, d_centers, B, d_out);
   TAPS_LAUNCHED(h, "k_source");

@@ -318,6 +318,42 @@ def nonlinear_heat(nx: int = 101, ny: int = 101, nz: int = 11, nt: int = 126, M:
     return NonlinearHeat(tuple(ax), M, seed, **phys)
 
 
+def multitrack_slabs(steps_per_slab: int, n_slabs: int, n: int = 301, M: int | None = None, seed: int = 11,
+                     hatch: float = 0.05, tracks: int = 1, L: float = 1.5, H: float = 1.5, h_mesh: float = 0.005,
+                     s: int = 2, p: int = 2, x_margin: float = 0.1):
+    """Space-time slabs of the multi-track LPBF set-up (paper table of
+    multi-track parameters; Ti-6Al-4V table): 1.5 mm cube, 5 um mesh (301
+    nodes per spatial dim), P = 200 W, r = 50 um, v = 500 mm/s, eta = 0.25,
+    penetration depth 50 um, hatch 50 um, k = 22 W/(m K), rho c_p = 4270 kg/m^3
+    x 745 J/(kg K).  Reading (not stated): one time step moves the beam one
+    mesh cell (dt = h / v = 10 us), and M = 5 x time steps per slab (the
+    paper's single-track rule) capped at 48.  Tracks run in alternating
+    directions along x, y0 = L/2 - (tracks - 1) hatch / 2 + j hatch; slab T
+    starts where slab T-1 ended.  Returns the slab cases in order."""
+    dt = h_mesh / 0.5              # ms (v = 0.5 mm/ms)
+    T_slab = steps_per_slab * dt
+    nt = steps_per_slab + 1
+    M = min(48, 5 * steps_per_slab) if M is None else M
+    track_len = L - 2 * x_margin
+    slabs_per_track = max(1, int(round(track_len / (0.5 * T_slab))))
+    out = []
+    for T in range(n_slabs):
+        j, k = divmod(T, slabs_per_track)
+        j = j % tracks
+        y0 = L / 2 - (tracks - 1) * hatch / 2 + j * hatch
+        fwd = j % 2 == 0
+        x0 = x_margin + 0.5 * T_slab * k if fwd else L - x_margin - 0.5 * T_slab * k
+        ax = [
+            Axis("x", 0.0, L, n, s, 20.0, p),
+            Axis("y", 0.0, L, n, s, 20.0, p),
+            Axis("z", 0.0, H, n, s, 20.0, p, fixed=(0,)),
+            Axis("t", 0.0, T_slab, nt, s, 20.0, p, fixed=(0,)),
+        ]
+        out.append(HeatSlab(tuple(ax), M, seed * 1009 + T, k=0.022, rho_cp=4.27e-6 * 745.0, eta=0.25,
+                            power=200.0, radius=0.05, depth=0.05, speed=0.5 if fwd else -0.5, x_start=x0, y0=y0))
+    return out
+
+
 def initial_factors(axes, M: int, seed: int):
     """Random initial mode factors U_d ~ N(0,1) (n_d x M, float64, row-major),
     one PCG64 stream per problem, dims drawn in order; rows of fixed nodes are 0."""
