@@ -297,7 +297,9 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
  * change and backward errors and drops the problems that reached tol or
  * change_tol (same rules as taps_als) or broke down.  Host outputs:
  * sweeps[b], rho[b] and change[b] (nullable) after the last sweep run, NaN
- * after a breakdown.  Synchronises the stream once per sweep (or replay).
+ * after a breakdown.  The change is measured (one copy of the factors per
+ * sweep) only when change is non-null or change_tol > 0.  Synchronises the
+ * stream once per sweep (or replay).
  * TAPS_ERR_UNSUPPORTED when a block-LU dim does not fit LDS (M, s). */
 taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* probs,
                              double* const* d_U, double tol, double change_tol, int32_t iter_max,

@@ -8,7 +8,8 @@ k = m_k u + n_k, rho c_p = m_c u + n_c are themselves in TD form whenever u
 is.  Global stage: with the coefficients frozen the problem is linear and is
 solved by Algorithm 1.  Local stage: the coefficients are updated from the
 new u (for linear fits exactly, at every Gauss point, through the TD form).
-The loop stops when the coefficients change by less than a tolerance.
+The loop stops when the coefficients change by at most a positive tolerance
+(tol = 0: every one of the given outer stages runs).
 
 Readings:
   * the coefficient field is the TD of u compressed to R_c modes by the
@@ -128,6 +129,6 @@ def global_local(case, dims, U0, Rc, outer, sweeps, comp_sweeps=4, tol=0.0, seed
             change = np.sqrt(max(nn + td_inner(dims, V, V) - 2 * td_inner(dims, Vn, V), 0.0) / nn)
         changes.append(change)
         V = Vn
-        if change <= tol:
+        if tol > 0.0 and change <= tol:
             break
     return U, V, changes

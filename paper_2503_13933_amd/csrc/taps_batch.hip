@@ -235,6 +235,9 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     }
   }
   const int D = p0.D, M = p0.M, MM = M * M;
+  // the relative change of a sweep needs the factors of its start (one copy
+  // per sweep); measured only when asked for or used by the stop rule
+  const bool want_change = change != nullptr || change_tol > 0.0;
   // per dim: fast diagonalisation when selected and every system of the
   // batch has two kinds, block LU otherwise
   std::vector<char> use_fd(D, 0);
@@ -427,7 +430,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       bal[b].snap[d] = snap;
       snap += size_t(p.n[d]) * M;
     }
-    bal[b].change = q.outs + 2 * D + 2;
+    bal[b].change = want_change ? q.outs + 2 * D + 2 : nullptr;
   }
   std::vector<int> active(B), next;
   for (int b = 0; b < B; ++b) {
@@ -514,8 +517,10 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const uint32_t all = (1u << D) - 1u;
   auto one_sweep = [&](int nact, hipStream_t st) -> taps_status {
     uint32_t valid = 0;
-    kb_snapshot<<<nact, 256, 0, st>>>(d_bal, d_active);
-    TAPS_LAUNCHED(h, "kb_snapshot");
+    if (want_change) {
+      kb_snapshot<<<nact, 256, 0, st>>>(d_bal, d_active);
+      TAPS_LAUNCHED(h, "kb_snapshot");
+    }
     for (int d = 0; d < D; ++d) {
       const uint32_t stale = (all & ~(1u << d)) & ~valid;
       for (int e = 0; e < D; ++e)
@@ -562,7 +567,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   }
   auto graph_for = [&](int nact, int k) -> taps_status {
     std::vector<int64_t> sig = {int64_t(reinterpret_cast<intptr_t>(base)), B, D, M, nact, k, int64_t(glds),
-                                int64_t(rlds), Z.max_terms, lg_rows};
+                                int64_t(rlds), Z.max_terms, lg_rows, int64_t(want_change)};
     for (long v : it_full) sig.push_back(v);
     for (int d = 0; d < D; ++d) {
       sig.push_back(p0.s[d] * 2 + use_fd[d]);
@@ -623,7 +628,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
         broke = broke || h_infos[size_t(b) * D + d] != 0 || !(o[D + 2 + d] <= TAPS_BERR_LIMIT);
       sweeps[b] = it;
       rho[b] = broke ? NAN : o[D + 1];
-      const double chg = broke ? NAN : o[2 * D + 2];
+      const double chg = broke || !want_change ? NAN : o[2 * D + 2];
       if (change) change[b] = chg;
       if (!broke && rho[b] > tol && !(change_tol > 0.0 && chg <= change_tol)) next.push_back(b);
     }

@@ -16,8 +16,9 @@ from taps_shape1d and taps_interp1d).  Operator terms per global stage:
     n_c (M, M, M, G),  m_c (W[v_x], W[v_y], W[v_z], W_G[v_t])  per mode v,
     n_k (K, M, M, M) + (M, K, M, M) + (M, M, K, M),
     m_k (W_K[v_x], W[v_y], W[v_z], W[v_t]) and its y, z analogues per mode.
-The loop stops when the compressed field changes by at most tol in the
-mass norm between global stages (taps_td_inner).
+The loop stops when the compressed field changes by at most tol > 0 in the
+mass norm between global stages (taps_td_inner); tol = 0 runs every outer
+stage (the change has a rounding floor near 1e-8 and can read exactly 0).
 """
 from __future__ import annotations
 
@@ -149,6 +150,6 @@ def global_local(h, case, U0, Rc, outer, sweeps, comp_sweeps=4, tol=0.0, V_init=
         capi.taps_als(h, comp.struct, Vn, 0.0, comp_sweeps)
         changes.append(1.0 if V is None else change(h, prob, Vn, V))
         V = Vn
-        if changes[-1] <= tol:
+        if tol > 0.0 and changes[-1] <= tol:
             break
     return U, V, changes
