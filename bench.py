@@ -186,7 +186,9 @@ def main():
     torch.cuda.set_device(0)
     if args.c3_only:
         # the space-parameter-time batch alone (for kernel traces of it)
-        print(json.dumps({"spt_batch": c3_batch(capi, torch, args)}), flush=True)
+        res = c3_batch(capi, torch, args)
+        calibration_copy(args, torch)
+        print(json.dumps({"spt_batch": res}), flush=True)
         return
     grid = dict(nx=args.nx, ny=args.nx, nz=args.nz, nt=args.nt, M=args.M)
     h = capi.Handle()
@@ -442,17 +444,24 @@ def main():
         log("cpu baseline: oracle on the host")
         spb = rand["sweeps_per_slab"] if rand else warm["sweeps_per_slab"]
         out["cpu_baseline"] = cpu_baseline(cases[:args.cpu_slabs], spb)
-    if args.calibration_copy_mib:
-        n = args.calibration_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy: {args.calibration_copy_mib} MiB")
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(args, torch)
     h.close()
     print(json.dumps(out), flush=True)
+
+
+def calibration_copy(args, torch):
+    """A plain device copy of --calibration-copy-mib MiB (its source filled
+    first): the known byte counts that scale the memory counters."""
+    if not args.calibration_copy_mib:
+        return
+    n = args.calibration_copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {args.calibration_copy_mib} MiB")
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def c3_batch(capi, torch, args):

@@ -398,7 +398,9 @@ taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* prob
  *                      execute M padded to their inner size), bytes = field
  *                      written (STORE) + factors read once.
  * taps_profile_enable(h, 1) clears the counters and starts recording,
- * (h, 0) stops.  taps_profile_read synchronises on the recorded events and
+ * (h, 0) stops; each call also launches one empty kernel (k_prof_mark) on
+ * the null stream, so that a kernel trace or counter run of the process can
+ * find the profiled region between the two dispatches.  taps_profile_read synchronises on the recorded events and
  * returns launches, summed kernel milliseconds, flops and bytes of one family. */
 typedef enum {
   TAPS_PROF_SOLVE = 0,
