@@ -166,9 +166,13 @@ def main():
     ap.add_argument("--cpu-slabs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the space-parameter-time batch")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="no tuner and no captured graphs (host launches; rocprofv3 counter runs abort on graph "
+                         "launches); --lgram-rows sets the row split instead")
+    ap.add_argument("--lgram-rows", type=int, default=0, help="load-Gram row split without the tuner (0: default)")
     ap.add_argument("--c3-only", action="store_true", help="run only the space-parameter-time batch")
     ap.add_argument("--c3-sweeps", type=int, default=3)
+    ap.add_argument("--no-large", action="store_true", help="skip the large single slab (15000^2 x 15 x 513, M=60)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="end with a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -254,7 +258,9 @@ def main():
     # ---- tuning of the batched driver on the first round's slabs (untimed):
     # load-Gram row split and graph length, applied to the stream's handle
     tune = None
-    if not args.no_autotune:
+    if args.no_autotune:
+        capi.taps_set_tuning(h, lgram_rows=args.lgram_rows)
+    else:
         nb = min(B, N)
         Ut = ws.FactorBatch([t[:nb].clone() for t in U_plain_big])
         tb = (capi.Problem * nb)(*[p.struct for p in probs[:nb]])
@@ -351,6 +357,9 @@ def main():
     # 2048 x 2048 planes, M = 60 (256 planes of the 2048^3 subvolume)
     rec = recon_large(h, capi, torch)
 
+    # ---- the large single slab: sweeps and its 2048^3 subvolume
+    large = None if args.no_large else large_slab(capi, torch)
+
     # ---- the uneven space-parameter-time batch: autotuned, graph-replayed
     c3 = None if args.no_c3 else c3_batch(capi, torch, args)
 
@@ -435,6 +444,7 @@ def main():
             "recon_in_step": {"launches": n_r, "ms_per_step": ms_r, "bf16_tflops_at_M": rec_tf,
                               "bf16_frac": rec_tf / BF16_PEAK_TFLOPS},
             "recon_2048_planes_M60": rec,
+            "large_slab": large,
             "spt_batch": c3,
             "traffic_sources_sha256": digest,
         },
@@ -484,14 +494,20 @@ def c3_batch(capi, torch, args):
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     f_bytes = sum(8.0 * p.axes[d].F.numel() for p in probs for d in range(7))
-    tune, tms = capi.taps_autotune(h, structs, U0)
+    if args.no_autotune:
+        capi.taps_set_tuning(h, lgram_rows=args.lgram_rows)
+        tune, tms = capi.taps_get_tuning(h), []
+        graph = 0
+    else:
+        tune, tms = capi.taps_autotune(h, structs, U0)
+        graph = args.c3_sweeps
     torch.cuda.synchronize()
     log(f"c3: 64 space-parameter-time slabs set up in {setup:.1f} s ({f_bytes / 1e9:.2f} GB of load columns); "
-        f"autotune lgram_rows {tune.lgram_rows}, graph_sweeps {tune.graph_sweeps} "
+        f"lgram_rows {tune.lgram_rows}, tuner's graph_sweeps {tune.graph_sweeps} "
         f"(ms per sweep {[round(m, 2) for m in tms]})")
     # the timed sweeps replay one captured graph holding all of them (the
-    # tuner's row split kept)
-    capi.taps_set_tuning(h, graph_sweeps=args.c3_sweeps)
+    # tuner's row split kept); host launches without the tuner
+    capi.taps_set_tuning(h, graph_sweeps=graph)
     U = [[u.clone() for u in Ub] for Ub in U0]
     capi.taps_als_batched(h, structs, U, 0.0, args.c3_sweeps)   # warm-up and graph capture
     U = [[u.clone() for u in Ub] for Ub in U0]
@@ -518,7 +534,7 @@ def c3_batch(capi, torch, args):
                         "R = 32 n_t load terms, fast diagonalisation (block LU for P and r)",
             "setup_s": setup, "load_column_gb": f_bytes / 1e9,
             "tuning": {"lgram_rows": tune.lgram_rows, "graph_sweeps": tune.graph_sweeps, "candidates_ms": tms},
-            "graph_sweeps_timed": args.c3_sweeps,
+            "graph_sweeps_timed": graph,
             "sweeps": args.c3_sweeps, "ms_per_sweep": el / args.c3_sweeps * 1e3,
             "problem_sweeps_per_s": 64 * args.c3_sweeps / el, "median_rho": float(np.nanmedian(rho)),
             "median_change": float(np.nanmedian(chg)),
@@ -528,6 +544,73 @@ def c3_batch(capi, torch, args):
                                   "fp64_tflops": fl_c / (ms_c * 1e-3) / 1e12 if n_c else 0.0},
             "profiled_ms_per_sweep": {"contract": ms_c / args.c3_sweeps, "solve": ms_s / args.c3_sweeps,
                                       "eig": ms_e / args.c3_sweeps}}
+
+
+def large_slab(capi, torch, sweeps=3):
+    """The large single slab (x, y: 15000 nodes over 15 mm, z: 15, t: 513,
+    M = 60): Algorithm 1 sweeps from the random start with the fast
+    diagonalisation, timed (wall clock and the library's kernel events), and
+    the BF16 / FP32 / FP64 reductions of the 2048^3 subvolume around the melt
+    pool at the slab's end time, timed by the library's kernel events."""
+    import taps_workloads as W
+    from paper_2503_13933_amd import problem
+    h = capi.Handle()
+    capi.taps_set_tuning(h, solver=capi.SOLVER_FAST_DIAG)
+    case = W.large_slab()
+    t0 = time.perf_counter()
+    dev = problem.heat_slab(h, case)
+    U0 = W.initial_factors(case.axes, case.M, case.seed)
+    U = dev.factors(U0)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    capi.taps_als(h, dev.struct, [u.clone() for u in U], 0.0, 1)      # workspace growth, untimed
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, rho, hist = capi.taps_als(h, dev.struct, U, 0.0, sweeps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    U = dev.factors(U0)
+    capi.taps_profile_enable(h, True)
+    capi.taps_als(h, dev.struct, U, 0.0, sweeps)
+    torch.cuda.synchronize()
+    capi.taps_profile_enable(h, False)
+    fam = {nm: capi.taps_profile_read(h, f) for nm, f in (("solve", capi.PROF_SOLVE), ("eig", capi.PROF_EIG),
+                                                         ("contract", capi.PROF_CONTRACT))}
+    # 2048^3 points about the beam's last position (x, y 2.048 mm wide, all of z)
+    n, M = 2048, case.M
+    xe = case.x_start + case.speed * case.axes[3].hi
+    spans = [(xe - 1.024, xe + 1.024), (case.y0 - 1.024, case.y0 + 1.024), (0.0, case.axes[2].hi)]
+    Phis = []
+    for d, (lo, hi) in enumerate(spans):
+        pts = torch.tensor(lo + (hi - lo) * (np.arange(n) + 0.5) / n, device="cuda")
+        N = torch.empty((n, 2 * case.axes[d].s + 2), dtype=torch.float64, device="cuda")
+        first = torch.empty(n, dtype=torch.int32, device="cuda")
+        capi.taps_shape1d(h, dev.axes[d].basis, pts, N, None, first)
+        P = torch.empty((n, M), dtype=torch.float64, device="cuda")
+        capi.taps_interp1d(h, N, first, case.axes[d].n, U[d], P)
+        Phis.append(P)
+    w = U[3][-1].contiguous()
+    rec = {}
+    for prec, pn, peak in ((capi.BF16, "bf16", BF16_PEAK_TFLOPS), (capi.FP32, "fp32", 157.3),
+                           (capi.FP64, "fp64", FP64_PEAK_TFLOPS)):
+        out = torch.empty((n, 4), dtype=torch.float64, device="cuda")
+        capi.taps_reconstruct(h, Phis, M, out, prec=prec, mode=capi.REDUCE, mode_w=w, thr=100.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        capi.taps_reconstruct(h, Phis, M, out, prec=prec, mode=capi.REDUCE, mode_w=w, thr=100.0)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3
+        rec[pn] = {"ms": ms, "points": n ** 3, "tflops_at_M": 2.0 * M * n ** 3 / (ms * 1e-3) / 1e12,
+                   "frac_of_peak": 2.0 * M * n ** 3 / (ms * 1e-3) / 1e12 / peak,
+                   "hottest_plane_max": float(out[:, 0].max().item())}
+    h.close()
+    log(f"large slab: {sweeps} sweeps in {el * 1e3:.1f} ms, rho {hist}; 2048^3 reductions "
+        f"{[(k, round(v['ms'], 2)) for k, v in rec.items()]} ms")
+    return {"workload": "heat slab x, y 15000 nodes over 15 mm, z 15 nodes over 0.2 mm, t 513 nodes over 1 ms, "
+                        "M=60, fast diagonalisation, random start",
+            "setup_s": setup, "sweeps": sweeps, "ms_per_sweep": el / sweeps * 1e3, "rho_by_sweep": hist,
+            "profiled_ms_per_sweep": {k: v[1] / sweeps for k, v in fam.items()},
+            "subvolume_2048_cubed_reduce": rec}
 
 
 def recon_large(h, capi, torch, n=2048, M=60, planes=256):

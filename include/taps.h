@@ -290,7 +290,7 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
  * problem-major (d_U[b*D + d]).  Each step of a sweep is one launch over
  * every active problem: Gram and load-Gram refreshes, couplings, forces, the
  * dim solves (the solver of taps_set_tuning: fast diagonalisation for dims
- * with two matrix kinds and M <= 48, block LU on the matrix cores otherwise;
+ * with two matrix kinds and M <= 64, block LU on the matrix cores otherwise;
  * one workgroup per system), backward errors, balancing with the relative
  * change, and the residual.  After each sweep (or each replay of a captured
  * graph of sweeps, taps_set_tuning) the host reads every problem's residual,
@@ -329,8 +329,10 @@ taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* p
  *      E = C^(1)T C^(0)-T is brought to complex Schur form and its
  *      eigenvectors P, and the system decouples into M banded complex
  *      systems (A^0 + lambda_m A^1) y_m = (Q C^(0)-T P)_m, X = Re(Y P^-1).
- *      Needs M <= 48; dims with another number of kinds, or larger M, use
- *      the block LU.  Failure codes in the info word: -1 C^(0) singular,
+ *      Needs M <= 64 (kernels laid out for M <= 48 and for M <= 64; above
+ *      56 the complex Schur vectors of the last eigen kernel go through the
+ *      workspace instead of LDS); dims with another number of kinds, or
+ *      larger M, use the block LU.  Failure codes in the info word: -1 C^(0) singular,
  *      -2 the QR iteration did not converge (40 M iterations), k > 0 a zero
  *      pivot in row k-1 of a banded system.  Same backward-error check as
  *      the block LU.

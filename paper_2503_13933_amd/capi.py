@@ -394,13 +394,14 @@ def taps_als_batched(h: Handle, probs, Us, tol: float, iter_max: int, change_tol
     """Algorithm 1 over a batch.  probs: list of Problem; Us: list (per problem)
     of factor tensor lists, or a ctypes array of factor pointers.  Returns
     (sweeps list, rho list); change, a list, receives every problem's
-    relative change of the factors over its last sweep."""
+    relative change of the factors over its last sweep (measured only when
+    change is given or change_tol > 0)."""
     B = len(probs)
     arr = probs if isinstance(probs, C.Array) else (Problem * B)(*probs)
     ptrs = Us if isinstance(Us, C.Array) else _ptr_array([u for U in Us for u in U])
     sw = (C.c_int32 * B)()
     rh = (C.c_double * B)()
-    ch = (C.c_double * B)()
+    ch = (C.c_double * B)() if change is not None else None   # measured only when asked for
     h.check(lib().taps_als_batched(h.h, B, arr, ptrs, tol, change_tol, iter_max, sw, rh, ch, _stream(stream)),
             "taps_als_batched")
     if change is not None:

@@ -760,7 +760,11 @@ __device__ inline cplx csqrtz(cplx z) {
   return cplx{fabs(z.i) / (2.0 * r), z.i >= 0.0 ? r : -r};
 }
 
-constexpr int kFdMaxM = 48;
+// largest M of the fast diagonalisation; kernels are instantiated for
+// M <= kFdSmallM (the layouts and register tiles of the common sizes) and
+// for M <= kFdMaxM
+constexpr int kFdSmallM = 48;
+constexpr int kFdMaxM = 64;
 
 // Workspace of one fast-diagonalisation solve (inside the first workspace
 // region): H2 = C1^{-T} P and H3 = P^{-1} (M x M complex), the eigenvalues
@@ -1011,20 +1015,22 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
   if (lane == 0) A.info[0] = s_fail ? -1 : 0;
 }
 
-// (the Schur kernel's LDS layout is fixed at the largest M, row stride
-// kFdMaxM + 1 (odd) and Zr at a fixed offset, so that every row and column
-// offset of the bulge chase is an immediate of the LDS instructions)
-constexpr int kSchurL = kFdMaxM | 1;
+// (the Schur kernel's LDS layout is fixed at the largest M of its
+// instantiation, MAXM: row stride MAXM + 1 (odd) and Zr at a fixed offset,
+// so that every row and column offset of the bulge chase is an immediate of
+// the LDS instructions)
+constexpr int schur_l(int maxm) { return maxm | 1; }
 // the sink takes the three stores of each lane a pass leaves alone: row pass
 // at lane + {0, L, 2L}, column passes at 3 lane + {0, 1, 2}
-constexpr int kSchurSink = 2 * kSchurL + 64 > 3 * 64 ? 2 * kSchurL + 64 : 3 * 64;
+constexpr int schur_sink(int maxm) { return 2 * schur_l(maxm) + 64 > 3 * 64 ? 2 * schur_l(maxm) + 64 : 3 * 64; }
+template <int MAXM>
 __device__ void fd_eig_schur(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, lane = threadIdx.x;
-  constexpr int L = kSchurL;
-  double* Hr = lds;                                   // kFdMaxM x L
-  double* Zr = lds + kFdMaxM * L;                     // kFdMaxM x L
-  double* Dm = lds + 2 * kFdMaxM * L;                 // kSchurSink: stores of lanes a chase step leaves alone
+  constexpr int L = schur_l(MAXM);
+  double* Hr = lds;                                   // MAXM x L
+  double* Zr = lds + MAXM * L;                        // MAXM x L
+  double* Dm = lds + 2 * MAXM * L;                    // schur_sink: stores of lanes a chase step leaves alone
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
   if (A.info[0] != 0) return;
@@ -1039,9 +1045,9 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   wave_sync();
   // ---- Householder Hessenberg form, Zr accumulated.  The rows (left) and
   // columns (right) past k are read once into registers in batches of 8
-  // (static, at most kFdMaxM / 8 batches; clamped entries weigh 0), all
+  // (static, at most MAXM / 8 batches; clamped entries weigh 0), all
   // loads before the first use, and updated from there.
-  constexpr int kHB = kFdMaxM / 8;
+  constexpr int kHB = MAXM / 8;
   for (int k = 0; k + 2 < M; ++k) {
     // the Householder vector, in registers of every lane: column k below the
     // diagonal read by all lanes (one address per load, a broadcast), rows
@@ -1356,13 +1362,22 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   if (lane == 0 && s_fail) A.info[0] = -2;
 }
 
+// ZG: Z lives in the workspace (the right-hand-side region, free until the
+// banded stage) instead of LDS, for M whose six LDS units do not fit; the
+// lanes of one wave see each other's global stores in issue order.
+template <bool ZG>
 __device__ void fd_eig_vectors(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
   cplx* H = reinterpret_cast<cplx*>(lds);            // units 0-1
   cplx* Wv = reinterpret_cast<cplx*>(lds + 2 * LL);   // units 2-3
-  cplx* Z = reinterpret_cast<cplx*>(lds + 4 * LL);    // units 4-5
   const FdWs f = fd_ws(A);
+  using ZPtr = typename std::conditional<ZG, GCplx, cplx*>::type;
+  ZPtr Z;                                             // units 4-5, or the workspace
+  if constexpr (ZG)
+    Z = GCplx{f.Y};
+  else
+    Z = reinterpret_cast<cplx*>(lds + 4 * LL);
   if (A.info[0] != 0) return;
   // ---- complex Schur form: H = Hr, Z = Zr, then each remaining 2 x 2 block
   // (complex eigenvalue pair) is triangularised by a unitary rotation whose
@@ -1676,6 +1691,7 @@ __device__ inline void stage_cplx(cplx* dst, const gmem<double>* src, int n, int
       if (t0 + nt * u < n) dst[t0 + nt * u] = cmk(re[u], im[u]);
   }
 }
+template <int MAXM>
 __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, n = A.n, w = 2 * A.s + 1, BW = 2 * w + 1, W1 = w + 1;
@@ -1705,7 +1721,7 @@ __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A)
   // the same for every row tile: they sit in registers for the whole
   // transform, and each mode tile has its own accumulators, so the products
   // of one step are independent of each other.
-  constexpr int kKS = kFdMaxM / 4, kCT = (kFdMaxM + 15) / 16;
+  constexpr int kKS = MAXM / 4, kCT = (MAXM + 15) / 16;
   const int wave = tid >> 6, lane = tid & 63, nwv = nt >> 6;
   const int nrt = (n + 15) / 16, nct = (M + 15) / 16, ksteps = (M + 3) / 4;
   // operand u of mode tile c (lane l: mode 16 c + l%16, q = 4 u + l/16) of an
@@ -1886,29 +1902,42 @@ __global__ __launch_bounds__(64) void k_fd_inverse(const SolveArgs* __restrict__
   const SolveArgs A = args[active[blockIdx.x]];
   fd_eig_inverse(A);
 }
+template <int MAXM>
 __global__ __launch_bounds__(64) void k_fd_schur(const SolveArgs* __restrict__ args, const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
-  fd_eig_schur(A);
+  fd_eig_schur<MAXM>(A);
 }
+template <bool ZG>
 __global__ __launch_bounds__(64) void k_fd_vectors(const SolveArgs* __restrict__ args,
                                                    const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
-  fd_eig_vectors(A);
+  fd_eig_vectors<ZG>(A);
 }
+template <int MAXM>
 __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve(const SolveArgs* __restrict__ args,
                                                          const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
-  fd_solve_body(A);
+  fd_solve_body<MAXM>(A);
 }
 __global__ __launch_bounds__(64) void k_fd_inverse_one(SolveArgs A) { fd_eig_inverse(A); }
-__global__ __launch_bounds__(64) void k_fd_schur_one(SolveArgs A) { fd_eig_schur(A); }
-__global__ __launch_bounds__(64) void k_fd_vectors_one(SolveArgs A) { fd_eig_vectors(A); }
-__global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { fd_solve_body(A); }
+template <int MAXM>
+__global__ __launch_bounds__(64) void k_fd_schur_one(SolveArgs A) { fd_eig_schur<MAXM>(A); }
+template <bool ZG>
+__global__ __launch_bounds__(64) void k_fd_vectors_one(SolveArgs A) { fd_eig_vectors<ZG>(A); }
+template <int MAXM>
+__global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { fd_solve_body<MAXM>(A); }
 
 // dynamic LDS of the three eigen-stage kernels, in M x L real units
+constexpr size_t kFdLdsCap = 160 * 1024 - 2048;
 size_t fd_inverse_lds(int M) { return size_t(3) * M * (M | 1) * 8; }
-size_t fd_schur_lds(int) { return (size_t(2) * kFdMaxM * kSchurL + kSchurSink) * 8; }
-size_t fd_vectors_lds(int M) { return size_t(6) * M * (M | 1) * 8; }
+int fd_maxm(int M) { return M <= kFdSmallM ? kFdSmallM : kFdMaxM; }
+size_t fd_schur_lds(int M) {
+  const int mx = fd_maxm(M);
+  return (size_t(2) * mx * schur_l(mx) + schur_sink(mx)) * 8;
+}
+// Z goes to the workspace when the six units do not fit
+bool fd_vectors_zg(int M) { return size_t(6) * M * (M | 1) * 8 > kFdLdsCap; }
+size_t fd_vectors_lds(int M) { return size_t(fd_vectors_zg(M) ? 4 : 6) * M * (M | 1) * 8; }
 size_t fd_solve_lds(int M, int s) {
   const int w = 2 * s + 1;
   const bool reg = (w == 1 || w == 3 || w == 5);
@@ -1916,12 +1945,79 @@ size_t fd_solve_lds(int M, int s) {
   const size_t ring = size_t(3) * ((w + 1) * (32 / (w + 1))) * (2 * w + 1);   // staged band chunks
   return (size_t(M) + std::max(size_t(M) * M, reg ? ring : rows)) * 16;
 }
-size_t fd_inverse_allowed = 0, fd_schur_allowed = 0, fd_vectors_allowed = 0, fd_solve_allowed = 0;
-size_t fd_inverse1_allowed = 0, fd_schur1_allowed = 0, fd_vectors1_allowed = 0, fd_solve1_allowed = 0;
+size_t fd_inverse_allowed = 0, fd_inverse1_allowed = 0;
 
 bool fd_supported(int M, int s, int K) {
-  return K == 2 && M <= kFdMaxM && fd_vectors_lds(M) <= 160 * 1024 - 2048 &&
-         fd_solve_lds(M, s) <= 160 * 1024 - 2048;
+  return K == 2 && M <= kFdMaxM && fd_vectors_lds(M) <= kFdLdsCap && fd_inverse_lds(M) <= kFdLdsCap &&
+         fd_solve_lds(M, s) <= kFdLdsCap;
+}
+
+// Launches of one instantiation: MAXM the layout and register-tile size
+// (kFdSmallM or kFdMaxM), ZG whether the vectors kernel keeps Z in the
+// workspace.  Flops and bytes as the library counts them (fd_eig_*, fd_*).
+template <int MAXM> size_t fd_schur_lds_ok = 0;
+template <int MAXM> size_t fd_schur1_lds_ok = 0;
+template <bool ZG> size_t fd_vectors_lds_ok = 0;
+template <bool ZG> size_t fd_vectors1_lds_ok = 0;
+template <int MAXM> size_t fd_solve_lds_ok = 0;
+template <int MAXM> size_t fd_solve1_lds_ok = 0;
+double fd_schur_flops(int M);
+double fd_schur_bytes(int M);
+double fd_eig_flops(int M);
+double fd_eig_bytes(int M);
+double fd_flops(int n, int M, int w);
+double fd_bytes(int n, int M, int w);
+
+template <int MAXM, bool ZG>
+taps_status fd_single_t(taps_handle* h, const SolveArgs& A, int n, int M, int s, hipStream_t stream) {
+  const int w = 2 * s + 1;
+  TAPS_TRY(taps::allow_lds(h, k_fd_inverse_one, fd_inverse_lds(M), &fd_inverse1_allowed));
+  TAPS_TRY(taps::allow_lds(h, k_fd_schur_one<MAXM>, fd_schur_lds(M), &fd_schur1_lds_ok<MAXM>));
+  TAPS_TRY(taps::allow_lds(h, k_fd_vectors_one<ZG>, fd_vectors_lds(M), &fd_vectors1_lds_ok<ZG>));
+  TAPS_TRY(taps::allow_lds(h, k_fd_solve_one<MAXM>, fd_solve_lds(M, s), &fd_solve1_lds_ok<MAXM>));
+  size_t slot, sslot;
+  TAPS_TRY(taps::prof_begin(h, TAPS_PROF_EIG, stream, &slot));
+  k_fd_inverse_one<<<1, 64, fd_inverse_lds(M), stream>>>(A);
+  TAPS_LAUNCHED(h, "k_fd_inverse");
+  TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
+  k_fd_schur_one<MAXM><<<1, 64, fd_schur_lds(M), stream>>>(A);
+  TAPS_LAUNCHED(h, "k_fd_schur");
+  TAPS_TRY(taps::prof_end(h, sslot, fd_schur_flops(M), fd_schur_bytes(M), stream));
+  k_fd_vectors_one<ZG><<<1, 64, fd_vectors_lds(M), stream>>>(A);
+  TAPS_LAUNCHED(h, "k_fd_vectors");
+  TAPS_TRY(taps::prof_end(h, slot, fd_eig_flops(M), fd_eig_bytes(M), stream));
+  TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+  k_fd_solve_one<MAXM><<<1, kFdThreads, fd_solve_lds(M, s), stream>>>(A);
+  TAPS_LAUNCHED(h, "k_fd_solve");
+  return taps::prof_end(h, slot, fd_flops(n, M, w), fd_bytes(n, M, w), stream);
+}
+
+template <int MAXM, bool ZG>
+taps_status fd_prepare_t(taps_handle* h, int M, int s) {
+  TAPS_TRY(taps::allow_lds(h, k_fd_inverse, fd_inverse_lds(M), &fd_inverse_allowed));
+  TAPS_TRY(taps::allow_lds(h, k_fd_schur<MAXM>, fd_schur_lds(M), &fd_schur_lds_ok<MAXM>));
+  TAPS_TRY(taps::allow_lds(h, k_fd_vectors<ZG>, fd_vectors_lds(M), &fd_vectors_lds_ok<ZG>));
+  return taps::allow_lds(h, k_fd_solve<MAXM>, fd_solve_lds(M, s), &fd_solve_lds_ok<MAXM>);
+}
+
+template <int MAXM, bool ZG>
+taps_status fd_batched_t(taps_handle* h, int n_active, const SolveArgs* args, const int* d_active, int M, int s,
+                         double flops, double bytes, hipStream_t stream) {
+  size_t slot, sslot;
+  TAPS_TRY(taps::prof_begin(h, TAPS_PROF_EIG, stream, &slot));
+  k_fd_inverse<<<n_active, 64, fd_inverse_lds(M), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_inverse");
+  TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
+  k_fd_schur<MAXM><<<n_active, 64, fd_schur_lds(M), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_schur");
+  TAPS_TRY(taps::prof_end(h, sslot, n_active * fd_schur_flops(M), n_active * fd_schur_bytes(M), stream));
+  k_fd_vectors<ZG><<<n_active, 64, fd_vectors_lds(M), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_vectors");
+  TAPS_TRY(taps::prof_end(h, slot, n_active * fd_eig_flops(M), n_active * fd_eig_bytes(M), stream));
+  TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
+  k_fd_solve<MAXM><<<n_active, kFdThreads, fd_solve_lds(M, s), stream>>>(args, d_active);
+  TAPS_LAUNCHED(h, "k_fd_solve");
+  return taps::prof_end(h, slot, flops, bytes, stream);
 }
 
 // Algorithmic work of the fast diagonalisation's two stages.  Eigen stage
@@ -2005,7 +2101,9 @@ size_t solve_lds_bytes(int M, int s) {
 // the fast diagonalisation's transforms, eigenvalues, C1^{-1}, complex
 // right-hand sides and banded U rows, whichever is larger.
 size_t fd_doubles(int n, int M, int s) {
-  return size_t(7) * M * M + 2 * size_t(M) + 2 * size_t(n) * M * (2 * s + 3);
+  // the right-hand-side region also holds the vectors kernel's complex Z
+  // (M x (M | 1)) when that does not fit LDS
+  return size_t(7) * M * M + 2 * size_t(M) + std::max(2 * size_t(n) * M * (2 * s + 3), 2 * size_t(M) * (M | 1));
 }
 
 size_t zst_doubles(int n, int M, int s) {
@@ -2047,25 +2145,12 @@ taps_status solve_dim_impl(taps_handle* h, const taps_problem_t* p, int d, const
   A.info = d_info;
   size_t slot;
   if (use_fd) {
-    TAPS_TRY(allow_lds(h, k_fd_inverse_one, fd_inverse_lds(M), &fd_inverse1_allowed));
-    TAPS_TRY(allow_lds(h, k_fd_schur_one, fd_schur_lds(M), &fd_schur1_allowed));
-    TAPS_TRY(allow_lds(h, k_fd_vectors_one, fd_vectors_lds(M), &fd_vectors1_allowed));
-    TAPS_TRY(allow_lds(h, k_fd_solve_one, fd_solve_lds(M, s), &fd_solve1_allowed));
-    TAPS_TRY(prof_begin(h, TAPS_PROF_EIG, stream, &slot));
-    k_fd_inverse_one<<<1, 64, fd_inverse_lds(M), stream>>>(A);
-    TAPS_LAUNCHED(h, "k_fd_inverse");
-    size_t sslot;
-    TAPS_TRY(prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
-    k_fd_schur_one<<<1, 64, fd_schur_lds(M), stream>>>(A);
-    TAPS_LAUNCHED(h, "k_fd_schur");
-    TAPS_TRY(prof_end(h, sslot, fd_schur_flops(M), fd_schur_bytes(M), stream));
-    k_fd_vectors_one<<<1, 64, fd_vectors_lds(M), stream>>>(A);
-    TAPS_LAUNCHED(h, "k_fd_vectors");
-    TAPS_TRY(prof_end(h, slot, fd_eig_flops(M), fd_eig_bytes(M), stream));
-    TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
-    k_fd_solve_one<<<1, kFdThreads, fd_solve_lds(M, s), stream>>>(A);
-    TAPS_LAUNCHED(h, "k_fd_solve");
-    TAPS_TRY(prof_end(h, slot, fd_flops(n, M, w), fd_bytes(n, M, w), stream));
+    if (M <= kFdSmallM)
+      TAPS_TRY((fd_single_t<kFdSmallM, false>(h, A, n, M, s, stream)));
+    else if (fd_vectors_zg(M))
+      TAPS_TRY((fd_single_t<kFdMaxM, true>(h, A, n, M, s, stream)));
+    else
+      TAPS_TRY((fd_single_t<kFdMaxM, false>(h, A, n, M, s, stream)));
   } else if (use_mfma) {
     lu_single_fn fn = lu_single_for(M);
     TAPS_TRY(allow_lds(h, fn, lds, &lu_mfma_lds_allowed[mp_of(M) / 8]));
@@ -2141,32 +2226,17 @@ double solve_fd_flops(int n, int M, int s) { return fd_flops(n, M, 2 * s + 1); }
 double solve_fd_bytes(int n, int M, int s) { return fd_bytes(n, M, 2 * s + 1); }
 
 taps_status fd_prepare(taps_handle* h, int M, int s) {
-  TAPS_TRY(allow_lds(h, k_fd_inverse, fd_inverse_lds(M), &fd_inverse_allowed));
-  TAPS_TRY(allow_lds(h, k_fd_schur, fd_schur_lds(M), &fd_schur_allowed));
-  TAPS_TRY(allow_lds(h, k_fd_vectors, fd_vectors_lds(M), &fd_vectors_allowed));
-  return allow_lds(h, k_fd_solve, fd_solve_lds(M, s), &fd_solve_allowed);
+  if (M <= kFdSmallM) return fd_prepare_t<kFdSmallM, false>(h, M, s);
+  return fd_vectors_zg(M) ? fd_prepare_t<kFdMaxM, true>(h, M, s) : fd_prepare_t<kFdMaxM, false>(h, M, s);
 }
 
 taps_status fd_batched_launch(taps_handle* h, int n_active, const void* d_args, const int* d_active, int M, int s,
                               double flops, double bytes, hipStream_t stream) {
-  size_t slot;
-  TAPS_TRY(prof_begin(h, TAPS_PROF_EIG, stream, &slot));
   const SolveArgs* args = static_cast<const SolveArgs*>(d_args);
-  k_fd_inverse<<<n_active, 64, fd_inverse_lds(M), stream>>>(args, d_active);
-  TAPS_LAUNCHED(h, "k_fd_inverse");
-  size_t sslot;
-  TAPS_TRY(prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
-  k_fd_schur<<<n_active, 64, fd_schur_lds(M), stream>>>(args, d_active);
-  TAPS_LAUNCHED(h, "k_fd_schur");
-  TAPS_TRY(prof_end(h, sslot, n_active * fd_schur_flops(M), n_active * fd_schur_bytes(M), stream));
-  k_fd_vectors<<<n_active, 64, fd_vectors_lds(M), stream>>>(args, d_active);
-  TAPS_LAUNCHED(h, "k_fd_vectors");
-  TAPS_TRY(prof_end(h, slot, n_active * fd_eig_flops(M), n_active * fd_eig_bytes(M), stream));
-  TAPS_TRY(prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
-  k_fd_solve<<<n_active, kFdThreads, fd_solve_lds(M, s), stream>>>(args, d_active);
-  TAPS_LAUNCHED(h, "k_fd_solve");
-  TAPS_TRY(prof_end(h, slot, flops, bytes, stream));
-  return TAPS_OK;
+  if (M <= kFdSmallM)
+    return fd_batched_t<kFdSmallM, false>(h, n_active, args, d_active, M, s, flops, bytes, stream);
+  if (fd_vectors_zg(M)) return fd_batched_t<kFdMaxM, true>(h, n_active, args, d_active, M, s, flops, bytes, stream);
+  return fd_batched_t<kFdMaxM, false>(h, n_active, args, d_active, M, s, flops, bytes, stream);
 }
 
 taps_status solve_batched_prepare(taps_handle* h, int M, int s) {

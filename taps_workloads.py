@@ -390,3 +390,20 @@ def mlp_init(widths, seed: int = 0):
     Ws = [rng.standard_normal((o, i)) * np.sqrt(2.0 / i) for i, o in zip(widths[:-1], widths[1:])]
     bs = [np.zeros(o) for o in widths[1:]]
     return Ws, bs
+
+
+def large_slab(n: int = 15000, nz: int = 15, nt: int = 513, M: int = 60, seed: int = 5,
+               width_mm: float = 15.0, duration_ms: float = 1.0, s: int = 2, a: float = 20.0, p: int = 2,
+               n_gauss: int = 5, **phys) -> HeatSlab:
+    """The large single slab: x, y in [0, 15 mm] with 15000 nodes each (about
+    1 um spacing), z in [0, 0.2 mm] with 15 nodes, t in [0, 1 ms] with 513
+    nodes (512 steps), M = 60; the moving source and material of the heat
+    slab, the track centred in y."""
+    ax = [
+        Axis("x", 0.0, width_mm, n, s, a, p, n_gauss),
+        Axis("y", 0.0, width_mm, n, s, a, p, n_gauss),
+        Axis("z", 0.0, 0.2, nz, s, a, p, n_gauss, fixed=(0,)),
+        Axis("t", 0.0, duration_ms, nt, s, a, p, n_gauss, fixed=(0,)),
+    ]
+    phys.setdefault("y0", 0.5 * width_mm)
+    return HeatSlab(tuple(ax), M, seed, **phys)

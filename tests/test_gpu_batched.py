@@ -132,3 +132,32 @@ def test_profile_families_of_the_fast_diagonalisation(env):
         assert fl_s > 0.0 and by_s > 0.0
     finally:
         capi.taps_set_tuning(h, solver=capi.SOLVER_BLOCK_LU)
+
+
+@pytest.mark.parametrize("M", [56, 60])
+def test_batched_fast_diag_large_modes(env, M):
+    """Fast diagonalisation at M above the common kernel layout (M <= 64
+    layout; at M = 60 the complex Schur vectors go through the workspace),
+    batched over two uneven slabs whose z and t dims have fewer rows than
+    modes, one sweep against the oracle's."""
+    torch, capi, problem, h = env
+    cases = [W.heat_slab(70, 40, 15, 21, M=M, seed=21), W.heat_slab(52, 61, 9, 13, M=M, seed=22, k=0.015)]
+    _say(f"batched fast diagonalisation, M={M}, slabs {[[a.n for a in c.axes] for c in cases]}")
+    capi.taps_set_tuning(h, solver=capi.SOLVER_FAST_DIAG)
+    try:
+        devs = [problem.heat_slab(h, c) for c in cases]
+        U0 = [W.initial_factors(c.axes, c.M, c.seed) for c in cases]
+        Ub = [d.factors(u) for d, u in zip(devs, U0)]
+        sweeps, rhos = capi.taps_als_batched(h, [d.struct for d in devs], Ub, 0.0, 1)
+        torch.cuda.synchronize()
+        assert sweeps == [1, 1]
+        for c, u0, ub, rb in zip(cases, U0, Ub, rhos):
+            ora = problems.heat_slab(c)
+            Uo, rho_o, ch_o = pu.oracle_sweeps(ora, u0, 1)
+            fbar, rbar, cbar, kappa = pu.sweep_bars(ora, u0, Uo, 1, rho_o[-1], ch_o[-1])
+            diffs = [pu.check(a.cpu().numpy(), o, bar, f"factor {d}") for d, (a, o, bar) in enumerate(zip(ub, Uo, fbar))]
+            assert abs(rb - rho_o[-1]) <= rbar
+            _say(f"  kappa {kappa:.1e} factor diffs {[f'{x:.1e}/{y:.1e}' for x, y in diffs]} "
+                 f"(bars {[f'{b:.0e}' for b in fbar]}); rho {rb:.8e} vs {rho_o[-1]:.8e}")
+    finally:
+        capi.taps_set_tuning(h, solver=capi.SOLVER_BLOCK_LU)

@@ -236,10 +236,12 @@ def _check_solve_dim(env, case, dev, ora, seed):
         _say(f"  dim {d}: kappa {kappa:.2e} bar {bar:.1e} backward {back:.1e} rel {r:.2e} max entry {m:.2e}")
 
 
-@pytest.mark.parametrize("M", [40, 48])
+@pytest.mark.parametrize("M", [40, 48, 49, 56, 60, 64])
 def test_solve_dim_fast_diag_wide(env, M, solver):
-    # bench-sized mode counts (the eigen stage's largest M) on grids spanning
-    # several hundred rows with ragged ends
+    # bench-sized mode counts on grids spanning several hundred rows with
+    # ragged ends, through both kernel layouts (M <= 48, M <= 64) and both
+    # homes of the complex Schur vectors (LDS up to M = 56, workspace above);
+    # the z and t dims have fewer rows than modes at M = 60, 64
     torch, capi, problem, h = env
     _say(f"solve_dim fast diagonalisation, heat slab 130 x 70 x 20 x 33, M={M}")
     solver(capi.SOLVER_FAST_DIAG)
