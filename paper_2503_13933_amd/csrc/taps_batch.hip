@@ -48,27 +48,39 @@ enum { kItGram = 0, kItLgram = 1, kItForce = 2, kItRes = 3, kItKinds = 4 };
 // persistent grid sizes (a few items per workgroup at full batches)
 constexpr int kPersistLds = 4096, kPersistStream = 8192;
 
-// Work item w -> (active problem index in P, item index within the problem):
-// the largest a with pref[a] <= w (pref has nact + 1 entries, pref[nact] the
-// item count).
+// Work item w -> (active problem index in P, item index within the problem).
+// pref has nact + 1 entries (pref[nact] the item count); owner[w] is the
+// active index a with pref[a] <= w < pref[a + 1], written by kb_owner_fill
+// whenever the active set changes, so an item is located by one load.
 struct Item {
   int b, c;
 };
-__device__ inline Item locate(const int* __restrict__ act, const int* __restrict__ pref, int nact, int w) {
-  int lo = 0, hi = nact;   // pref[lo] <= w < pref[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pref[mid] <= w) lo = mid;
-    else hi = mid;
-  }
-  return Item{act[lo], w - pref[lo]};
+__device__ inline Item locate(const int* __restrict__ act, const int* __restrict__ pref,
+                              const int* __restrict__ owner, int w) {
+  const int a = owner[w];
+  return Item{act[a], w - pref[a]};
+}
+
+// owner tables of every (kind, dim): one thread per active problem fills
+// its items' entries (grid.y = kind * D + dim)
+struct OwnerOffsets {
+  int off[kItKinds * TAPS_MAX_DIMS];
+};
+__global__ void kb_owner_fill(const int* __restrict__ pref, int* __restrict__ owner, OwnerOffsets oo, int nact,
+                              int B) {
+  const int kd = blockIdx.y;
+  const int* pr = pref + size_t(kd) * (B + 1);
+  int* ow = owner + oo.off[kd];
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < nact; a += gridDim.x * blockDim.x)
+    for (int w = pr[a]; w < pr[a + 1]; ++w) ow[w] = a;
 }
 
 __global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                       const int* __restrict__ pref, int nact, int e) {
+                                                       const int* __restrict__ pref, const int* __restrict__ owner,
+                                                       int nact, int e) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = locate(act, pref, nact, w);
+    const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     gram_partial(x.c, q.n[e], q.M, q.s[e], q.K[e], q.band[e], q.U[e], q.gpart + long(x.c) * q.K[e] * q.M * q.M);
     __syncthreads();   // LDS free for the next item
@@ -88,10 +100,11 @@ __global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__
 }
 
 __global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                        const int* __restrict__ pref, int nact, int e, int rows) {
+                                                        const int* __restrict__ pref, const int* __restrict__ owner,
+                                                        int nact, int e, int rows) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = locate(act, pref, nact, w);
+    const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     const int splits = (q.n[e] + rows - 1) / rows;
     const int ct = x.c / splits;
@@ -133,20 +146,22 @@ __global__ __launch_bounds__(256) void kb_load_weights_long(const BProb* __restr
 }
 
 __global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                const int* __restrict__ pref, int nact, int d) {
+                                                const int* __restrict__ pref, const int* __restrict__ owner,
+                                                int nact, int d) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = locate(act, pref, nact, w);
+    const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     force(x.c, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
   }
 }
 
 __global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                        const int* __restrict__ pref, int nact, int d) {
+                                                        const int* __restrict__ pref, const int* __restrict__ owner,
+                                                        int nact, int d) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
-    const Item x = locate(act, pref, nact, w);
+    const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     residual_part(x.c, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
                   q.rparts + 2 * (q.roff[d] + x.c));
@@ -282,6 +297,14 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     for (int k = 0; k < kItKinds; ++k)
       for (int d = 0; d < D; ++d) it_full[k * D + d] += items_of(k, b, d);
   const size_t o_pref = bump.take(size_t(kItKinds) * D * (B + 1) * 4);
+  OwnerOffsets own_off{};
+  long own_total = 0;
+  for (int kd = 0; kd < kItKinds * D; ++kd) {
+    own_off.off[kd] = int(own_total);
+    own_total += it_full[kd];
+  }
+  if (own_total >= (1L << 31)) return fail(h, TAPS_ERR_UNSUPPORTED, "too many work items in one batch");
+  const size_t o_owner = bump.take(size_t(std::max(1L, own_total)) * 4);
   std::vector<BProb> bp(B);
   std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B), wt_doubles(B);
   std::vector<size_t> o_snap(B);
@@ -340,6 +363,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       if (long(probs[b].R) < 64L * probs[b].R_cols[d]) long_groups[d] = 0;
   const int* d_pref = reinterpret_cast<const int*>(base + o_pref);
   auto pref = [&](int kind, int d) { return d_pref + size_t(kind * D + d) * (B + 1); };
+  int* d_owner = reinterpret_cast<int*>(base + o_owner);
+  auto owner = [&](int kind, int d) { return d_owner + own_off.off[kind * D + d]; };
   // persistent grid of one kernel: its items over the whole batch, capped
   auto pgrid = [&](int kind, int d, int cap) { return unsigned(std::max(1L, std::min(long(cap), it_full[kind * D + d]))); };
   // prefix tables of the active problems' item counts (host staging kept
@@ -353,6 +378,9 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
         for (size_t a = 0; a < act_list.size(); ++a) pr[a + 1] = pr[a] + items_of(k, act_list[a], d);
       }
     TAPS_HIP(h, hipMemcpyAsync(base + o_pref, h_pref.data(), h_pref.size() * 4, hipMemcpyHostToDevice, st));
+    const int na = int(act_list.size());
+    kb_owner_fill<<<dim3(cdiv(na, 256), kItKinds * D), 256, 0, st>>>(d_pref, d_owner, own_off, na, B);
+    TAPS_LAUNCHED(h, "kb_owner_fill");
     return TAPS_OK;
   };
 
@@ -461,12 +489,13 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto refresh = [&](int e, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_gram_partial<<<pgrid(kItGram, e, kPersistLds), 256, glds, st>>>(d_prob, d_active, pref(kItGram, e), nact, e);
+    kb_gram_partial<<<pgrid(kItGram, e, kPersistLds), 256, glds, st>>>(d_prob, d_active, pref(kItGram, e),
+                                                                       owner(kItGram, e), nact, e);
     TAPS_LAUNCHED(h, "kb_gram_partial");
     kb_gram_sum<<<dim3(cdiv(Z.gram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_sum");
-    kb_lgram_partial<<<pgrid(kItLgram, e, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItLgram, e), nact,
-                                                                        e, lg_rows);
+    kb_lgram_partial<<<pgrid(kItLgram, e, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItLgram, e),
+                                                                        owner(kItLgram, e), nact, e, lg_rows);
     TAPS_LAUNCHED(h, "kb_lgram_partial");
     kb_lgram_sum<<<dim3(cdiv(Z.lgram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e, lg_rows);
     TAPS_LAUNCHED(h, "kb_lgram_sum");
@@ -496,7 +525,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
       TAPS_LAUNCHED(h, "kb_load_weights");
     }
-    kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItForce, d), nact, d);
+    kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItForce, d),
+                                                                 owner(kItForce, d), nact, d);
     TAPS_LAUNCHED(h, "kb_force");
     double fl = 0.0, by = 0.0;
     for (int b : active) {
@@ -508,7 +538,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return prof_end(h, slot, fl, by, st);
   };
   auto residual_parts = [&](int d, int nact, hipStream_t st) -> taps_status {
-    kb_residual_part<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, d_active, pref(kItRes, d), nact, d);
+    kb_residual_part<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, d_active, pref(kItRes, d),
+                                                                       owner(kItRes, d), nact, d);
     TAPS_LAUNCHED(h, "kb_residual_part");
     return TAPS_OK;
   };
