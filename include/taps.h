@@ -10,6 +10,7 @@
  *   taps_gauss_points / taps_shape1d     1D C-HiDeNN basis at points      (Sec. 2.1)
  *   taps_source1d                        separable source factors           (Sec. 2.4)
  *   taps_assemble1d                      1D quadrature matrices and loads  (Sec. 2.5)
+ *   taps_load1d                          loads from shape values held by the caller
  *   taps_band_apply                      banded 1D matrix x factor columns
  *   taps_contract                        Grams, Hadamard couplings, force  (Sec. 2.5)
  *   taps_solve_dim                       block-banded (n_d M) dim solve    (Sec. 2.6)
@@ -157,6 +158,17 @@ taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_
                             const int32_t* kinds, const double* d_coef_g,
                             const int32_t* bnode, double* d_band, int32_t n_loads,
                             const double* d_f_g, double* d_F, hipStream_t stream);
+
+/* The loads of taps_assemble1d from shape values the caller already holds,
+ * for many load sets on one grid (the shape functions are then computed
+ * once): d_N (n_gpts x (2s+2)) and d_first (n_gpts) are taps_shape1d at the
+ * Gauss points of taps_gauss_points (whose weights are d_wg, n_gpts =
+ * (n_nodes-1)*n_gauss); d_f_g and d_F as for taps_assemble1d:
+ *   d_F[i*n_loads + r] = sum_g d_wg[g] Ntilde_i(x_g) d_f_g[r*n_gpts + g]
+ * (Sec. 2.5, the forcing integrals).  Needs n_nodes >= max(2, 2s+2). */
+taps_status taps_load1d(taps_handle_t h, int32_t n_nodes, int32_t s, int32_t n_gauss, const double* d_N,
+                        const int32_t* d_first, const double* d_wg, int32_t n_loads, const double* d_f_g,
+                        double* d_F, hipStream_t stream);
 
 /* Banded 1D matrix times a block of columns (Sec. 2.5: the 1D matrices act on
  * factor columns; the slab chain builds its carried-field loads A_d V_d and the
@@ -394,7 +406,9 @@ taps_status taps_autotune(taps_handle_t h, int32_t B, const taps_problem_t* prob
  *                      for all kinds of a dim and the Grams written, F and U
  *                      read and the load Grams written, F read and Q written
  *                      for the force (the banded 1D matrices are not counted:
- *                      they are Toeplitz inside a uniform grid).
+ *                      they are Toeplitz inside a uniform grid; a load matrix
+ *                      that several problems of one batched launch share is
+ *                      counted once).
  *   TAPS_PROF_RECON    FP32/BF16 reconstruction on the matrix cores: flops =
  *                      2 n0 n1 n2 M (the method's modes; the matrix cores
  *                      execute M padded to their inner size), bytes = field

@@ -28,7 +28,7 @@ FUNCTIONS = (
     "taps_reconstruct", "taps_reconstruct_batched", "taps_profile_enable", "taps_profile_read", "taps_als_batched", "taps_band_apply",
     "taps_canonicalize", "taps_mlp_cache_bytes", "taps_mlp_forward", "taps_mlp_backward", "taps_mlp_mse",
     "taps_adam_step", "taps_set_tuning", "taps_get_tuning", "taps_autotune", "taps_reconstruct_noalloc",
-    "taps_td_inner",
+    "taps_td_inner", "taps_load1d",
 )
 MLP_MAX_LAYERS = 8
 PROF_SOLVE, PROF_CONTRACT, PROF_RECON, PROF_EIG, PROF_SCHUR = 0, 1, 2, 3, 4
@@ -152,6 +152,7 @@ class Handle:
         self.h = h
 
     def close(self):
+        self.__dict__.pop("_grids", None)      # device data cached per grid (problem.py)
         if self.h:
             lib().taps_destroy(self.h)
             self.h = None
@@ -200,6 +201,13 @@ def taps_assemble1d(h: Handle, basis: Basis1D, kinds, band, coef_g=None, bnode=N
     bn = (C.c_int32 * max(1, len(kinds)))(*(bnode or [-1] * len(kinds)))
     h.check(lib().taps_assemble1d(h.h, C.byref(basis), len(kinds), k, _ptr(coef_g), bn, _ptr(band), n_loads,
                                   _ptr(f_g), _ptr(F), _stream(stream)), "taps_assemble1d")
+
+
+def taps_load1d(h: Handle, n_nodes: int, s: int, n_gauss: int, Ng, first, wg, f_g, F, stream=None):
+    """Loads of f_g ((R, n_gpts) at the Gauss points) from shape values at
+    the Gauss points (Ng, first from taps_shape1d; wg the Gauss weights)."""
+    h.check(lib().taps_load1d(h.h, n_nodes, s, n_gauss, _ptr(Ng), _ptr(first), _ptr(wg), int(f_g.shape[0]),
+                              _ptr(f_g), _ptr(F), _stream(stream)), "taps_load1d")
 
 
 def taps_contract(h: Handle, prob: Problem, d: int, stale_mask: int, U, Cout, Q, stream=None):

@@ -46,10 +46,12 @@ def slab_problem(h, case, V=None, device="cuda", M=None):
     ax, ay, az, at = case.axes
     Kc = 0 if V is None else V[0].shape[1]
     nc = 3 * Kc
-    X = DeviceAxis(h, ax, [capi.MASS, capi.STIFF], device)
-    Y = DeviceAxis(h, ay, [capi.MASS, capi.STIFF], device)
-    Z = DeviceAxis(h, az, [capi.MASS, capi.STIFF], device)
-    T = DeviceAxis(h, at, [capi.MASS, capi.DDT], device)
+    # grid-only data shared by every slab on the grid (the loads are per slab,
+    # apart from the time loads, which depend on the grid and K_c alone)
+    X = DeviceAxis(h, ax, [capi.MASS, capi.STIFF], device, shared=True)
+    Y = DeviceAxis(h, ay, [capi.MASS, capi.STIFF], device, shared=True)
+    Z = DeviceAxis(h, az, [capi.MASS, capi.STIFF], device, shared=True)
+    T = DeviceAxis(h, at, [capi.MASS, capi.DDT], device, shared=True)
     pad = lambda A, f: torch.cat([f, torch.zeros((nc, A.ngp), dtype=F64, device=device)]) if nc else f
     amp = 2.0 * case.eta * case.power / (math.pi * case.radius ** 2 * case.depth)
     centers = torch.tensor(case.x_start + case.speed * at.nodes(), dtype=F64, device=device)
@@ -57,10 +59,11 @@ def slab_problem(h, case, V=None, device="cuda", M=None):
     X.assemble(pad(X, X.source(capi.SRC_GAUSS, [amp, case.radius], n_cols=at.n, centers=centers)))
     Y.assemble(pad(Y, Y.source(capi.SRC_GAUSS, [1.0, case.radius], n_cols=1, centers=yc)))
     Z.assemble(pad(Z, Z.source(capi.SRC_TOPLAYER, [case.height, case.depth])))
-    ft = T.source(capi.SRC_NODAL, [], n_cols=at.n)
-    if Kc:
-        ft = torch.cat([ft, T.source(capi.SRC_POLY, [1.0])])       # w_t = int Ntilde dt
-    T.assemble(ft)
+    def time_loads():
+        ft = T.source(capi.SRC_NODAL, [], n_cols=at.n)
+        return torch.cat([ft, T.source(capi.SRC_POLY, [1.0])]) if Kc else ft   # w_t = int Ntilde dt
+
+    T.assemble_shared(("nodal", bool(Kc)), time_loads)
     nt = at.n
     if Kc:
         # carried terms j = 0, 1, 2 (stiffness in spatial dim j), column j*Kc + r

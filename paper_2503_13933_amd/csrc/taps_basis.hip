@@ -547,6 +547,21 @@ taps_status taps_assemble1d(taps_handle_t h, const taps_basis1d_t* b, int32_t n_
   return TAPS_OK;
 }
 
+taps_status taps_load1d(taps_handle_t h, int32_t n_nodes, int32_t s, int32_t n_gauss, const double* d_N,
+                        const int32_t* d_first, const double* d_wg, int32_t n_loads, const double* d_f_g,
+                        double* d_F, hipStream_t stream) {
+  if (!h) return TAPS_ERR_INVALID;
+  if (n_nodes < 2 * s + 2 || n_nodes < 2 || s < 0 || s > TAPS_MAX_S || n_gauss < 1 || n_gauss > TAPS_MAX_GAUSS ||
+      n_loads < 0)
+    return fail(h, TAPS_ERR_INVALID, "n_nodes=%d s=%d n_gauss=%d n_loads=%d", n_nodes, s, n_gauss, n_loads);
+  if (n_loads == 0) return TAPS_OK;
+  if (!d_N || !d_first || !d_wg || !d_f_g || !d_F) return fail(h, TAPS_ERR_INVALID, "null pointer");
+  const long work = long(n_nodes) * n_loads;
+  k_load<<<grid_for(work, 256), 256, 0, stream>>>(n_nodes, s, n_gauss, n_loads, d_N, d_first, d_wg, d_f_g, d_F);
+  TAPS_LAUNCHED(h, "k_load");
+  return TAPS_OK;
+}
+
 taps_status taps_band_apply(taps_handle_t h, int32_t n, int32_t s, const double* d_band, int32_t n_cols,
                             const double* d_X, int32_t ldx, const double* d_scale, double alpha, double* d_Y,
                             int32_t ldy, hipStream_t stream) {

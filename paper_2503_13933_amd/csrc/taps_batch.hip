@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <unordered_set>
 #include <vector>
 
 using namespace taps;
@@ -501,13 +502,16 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_LAUNCHED(h, "kb_lgram_sum");
     // work of the method: Grams (U read once for all kinds, K M^2 written;
     // flops K (2 bw n M + 2 n M^2)) and load Gram (F and U read, R M written;
-    // 2 n R M flops)
+    // 2 n R M flops); a load matrix shared by several problems (one grid's
+    // time loads) is read once per launch
     double fl = 0.0, by = 0.0;
+    std::unordered_set<const double*> seen;
     for (int b : active) {
       const taps_problem_t& p = probs[b];
       const double n = p.n[e], K = p.n_kinds[e], Rc = p.R_cols[e], bw = 4 * p.s[e] + 3;
+      const bool first = seen.insert(p.d_F[e]).second;
       fl += K * (2.0 * bw * n * M + 2.0 * n * M * M) + 2.0 * n * Rc * M;
-      by += 8.0 * (n * M + K * MM + n * Rc + Rc * M);
+      by += 8.0 * (n * M + K * MM + (first ? n * Rc : 0.0) + Rc * M);
     }
     return prof_end(h, slot, fl, by, st);
   };
@@ -529,11 +533,13 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
                                                                  owner(kItForce, d), nact, d);
     TAPS_LAUNCHED(h, "kb_force");
     double fl = 0.0, by = 0.0;
+    std::unordered_set<const double*> seen;
     for (int b : active) {
       const taps_problem_t& p = probs[b];
       const double n = p.n[d], Rc = p.R_cols[d];
+      const bool first = seen.insert(p.d_F[d]).second;
       fl += 2.0 * n * Rc * M;
-      by += 8.0 * (n * Rc + Rc * M + n * M);
+      by += 8.0 * ((first ? n * Rc : 0.0) + Rc * M + n * M);
     }
     return prof_end(h, slot, fl, by, st);
   };

@@ -25,26 +25,69 @@ from .capi import Basis1D, Problem
 F64 = torch.float64
 
 
-class DeviceAxis:
-    """Nodes, basis descriptor, Gauss rule and bands of one dimension."""
+class _Grid:
+    """Grid-only data of one axis, shared by every problem built on that grid
+    with the same matrix kinds: nodes, Gauss rule, shape values at the Gauss
+    points, the 1D bands, the fixed-row mask, and load matrices that depend
+    on the grid alone (keyed by the caller).  Read-only once built."""
 
     def __init__(self, h, ax, kinds, device):
-        self.ax = ax
-        self.n = ax.n
         self.x = torch.tensor(ax.nodes(), dtype=F64, device=device)
         self.basis = Basis1D(ax.n, self.x.data_ptr(), ax.s, float(ax.a), ax.p, ax.n_gauss)
+        ngp = (ax.n - 1) * ax.n_gauss
+        self.xg = torch.empty(ngp, dtype=F64, device=device)
+        self.wg = torch.empty(ngp, dtype=F64, device=device)
+        capi.taps_gauss_points(h, self.basis, self.xg, self.wg)
+        self.Ng = torch.empty((ngp, 2 * ax.s + 2), dtype=F64, device=device)
+        self.firstg = torch.empty(ngp, dtype=torch.int32, device=device)
+        capi.taps_shape1d(h, self.basis, self.xg, self.Ng, None, self.firstg)
+        self.band = torch.empty((len(kinds), ax.n, 4 * ax.s + 3), dtype=F64, device=device)
+        capi.taps_assemble1d(h, self.basis, list(kinds), self.band)
+        self.fixed = torch.zeros(ax.n, dtype=torch.uint8, device=device)
+        if ax.fixed:
+            self.fixed[list(ax.fixed)] = 1
+        self.loads = {}
+
+
+def _grid(h, ax, kinds, device):
+    cache = h.__dict__.setdefault("_grids", {})
+    key = (ax.lo, ax.hi, ax.n, ax.s, float(ax.a), ax.p, ax.n_gauss, tuple(ax.fixed), tuple(kinds), str(device))
+    g = cache.get(key)
+    if g is None:
+        g = cache[key] = _Grid(h, ax, kinds, device)
+    return g
+
+
+class DeviceAxis:
+    """Nodes, basis descriptor, Gauss rule and bands of one dimension.
+
+    shared=True takes the grid-only data from the handle's cache (computed
+    once per grid and kinds, never written afterwards), so only the loads are
+    assembled per problem (taps_load1d); problems whose bands are rewritten
+    later (the coefficient problems of Algorithm 2) use their own."""
+
+    def __init__(self, h, ax, kinds, device, shared=False):
+        self.ax = ax
+        self.n = ax.n
+        self.kinds = list(kinds)
+        self.F = None
+        self.h = h
+        self.device = device
         self.ngp = (ax.n - 1) * ax.n_gauss
+        self.grid = _grid(h, ax, kinds, device) if shared else None
+        if self.grid is not None:
+            g = self.grid
+            self.x, self.basis, self.xg, self.wg, self.band, self.fixed = g.x, g.basis, g.xg, g.wg, g.band, g.fixed
+            return
+        self.x = torch.tensor(ax.nodes(), dtype=F64, device=device)
+        self.basis = Basis1D(ax.n, self.x.data_ptr(), ax.s, float(ax.a), ax.p, ax.n_gauss)
         self.xg = torch.empty(self.ngp, dtype=F64, device=device)
         self.wg = torch.empty(self.ngp, dtype=F64, device=device)
         capi.taps_gauss_points(h, self.basis, self.xg, self.wg)
-        self.kinds = list(kinds)
         self.band = torch.empty((len(kinds), ax.n, 4 * ax.s + 3), dtype=F64, device=device)
         self.fixed = torch.zeros(ax.n, dtype=torch.uint8, device=device)
         if ax.fixed:
             self.fixed[list(ax.fixed)] = 1
-        self.F = None
-        self.h = h
-        self.device = device
 
     def source(self, kind, params, n_cols=1, centers=None):
         """Source factor(s) at the Gauss points, (n_cols, ngp)."""
@@ -55,11 +98,31 @@ class DeviceAxis:
 
     def assemble(self, f_g, coef_g=None):
         """Bands of self.kinds and load columns of f_g ((R, ngp) at the Gauss
-        points); coef_g: the weighted-mass coefficient at the Gauss points."""
+        points); coef_g: the weighted-mass coefficient at the Gauss points.
+        On a shared grid only the loads are assembled."""
         f_g = f_g.contiguous()
         R = f_g.shape[0]
         self.F = torch.empty((self.n, R), dtype=F64, device=self.device)
+        if self.grid is not None:
+            assert coef_g is None, "a shared grid's bands are fixed"
+            g, ax = self.grid, self.ax
+            capi.taps_load1d(self.h, ax.n, ax.s, ax.n_gauss, g.Ng, g.firstg, g.wg, f_g, self.F)
+            return self
         capi.taps_assemble1d(self.h, self.basis, self.kinds, self.band, coef_g=coef_g, f_g=f_g, F=self.F, n_loads=R)
+        return self
+
+    def assemble_shared(self, key, make_f_g):
+        """Loads that depend on the grid alone (e.g. the nodal time loads):
+        assembled once per shared grid and key, then the same tensor for every
+        problem on it (read-only)."""
+        if self.grid is None:
+            return self.assemble(make_f_g())
+        F = self.grid.loads.get(key)
+        if F is None:
+            self.assemble(make_f_g())
+            self.grid.loads[key] = self.F
+        else:
+            self.F = F
         return self
 
 
@@ -112,17 +175,19 @@ def heat_slab(h, case, device="cuda", M=None):
     """Device problem of one heat slab (workload taps_workloads.HeatSlab)."""
     M = case.M if M is None else M
     ax, ay, az, at = case.axes
-    X = DeviceAxis(h, ax, [capi.MASS, capi.STIFF], device)
-    Y = DeviceAxis(h, ay, [capi.MASS, capi.STIFF], device)
-    Z = DeviceAxis(h, az, [capi.MASS, capi.STIFF], device)
-    T = DeviceAxis(h, at, [capi.MASS, capi.DDT], device)
+    # grid-only data (shape values, bands, the nodal time loads) computed once
+    # per grid on the handle and shared by every slab on it
+    X = DeviceAxis(h, ax, [capi.MASS, capi.STIFF], device, shared=True)
+    Y = DeviceAxis(h, ay, [capi.MASS, capi.STIFF], device, shared=True)
+    Z = DeviceAxis(h, az, [capi.MASS, capi.STIFF], device, shared=True)
+    T = DeviceAxis(h, at, [capi.MASS, capi.DDT], device, shared=True)
     amp = 2.0 * case.eta * case.power / (math.pi * case.radius ** 2 * case.depth)
     centers = torch.tensor(case.x_start + case.speed * at.nodes(), dtype=F64, device=device)
     X.assemble(X.source(capi.SRC_GAUSS, [amp, case.radius], n_cols=at.n, centers=centers))
     yc = torch.tensor([case.y0], dtype=F64, device=device)
     Y.assemble(Y.source(capi.SRC_GAUSS, [1.0, case.radius], n_cols=1, centers=yc))
     Z.assemble(Z.source(capi.SRC_TOPLAYER, [case.height, case.depth]))
-    T.assemble(T.source(capi.SRC_NODAL, [], n_cols=at.n))
+    T.assemble_shared(("nodal",), lambda: T.source(capi.SRC_NODAL, [], n_cols=at.n))
     rc, k = case.rho_cp_per_ms, case.k
     terms = [(rc, (0, 0, 0, 1)), (k, (1, 0, 0, 0)), (k, (0, 1, 0, 0)), (k, (0, 0, 1, 0))]
     zeros = np.zeros(at.n, dtype=np.int32)

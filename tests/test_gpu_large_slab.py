@@ -76,8 +76,11 @@ def test_residual_of_the_sweeps(large):
     Rs, Qs = separated.residuals(ora, Uh)
     ro = separated.residual_norm(ora, Uh)
     for d in range(ora.D):
-        ref = float(np.sum(Rs[d] ** 2))
-        assert abs(o[d] - ref) <= pu.TOL * ref, (d, o[d], ref)
+        # the last-solved dim's residual is rounding noise of its own solve:
+        # compared at the rounding scale of its force, not relative to itself
+        ref, qd = float(np.sum(Rs[d] ** 2)), float(np.sum(Qs[d] ** 2))
+        _say(f"dim {d}: ||R||/||Q|| gpu {np.sqrt(o[d] / qd):.3e} oracle {np.sqrt(ref / qd):.3e}")
+        assert abs(o[d] - ref) <= pu.TOL * ref + (1e4 * pu.EPS) ** 2 * qd, (d, o[d], ref, qd)
     _say(f"rho gpu {o[-1]:.12e} (Algorithm 1's last {rho:.12e}) oracle {ro:.12e}")
     assert abs(o[-1] - ro) <= pu.TOL * ro
     assert abs(rho - ro) <= pu.TOL * ro

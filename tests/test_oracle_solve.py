@@ -292,3 +292,14 @@ def test_dim_system_by_complex_schur_route():
         Y = np.column_stack([np.linalg.solve(A1 + T[m, m] * A2, R[:, m]) for m in range(M)])
         X = (Y @ solve_triangular(Wv, np.eye(M), lower=False) @ Z.conj().T).real
         assert np.abs(X - ref).max() <= 1e-10 * np.abs(ref).max(), d
+
+
+def test_relative_change_by_hand():
+    # the stop rule of Sec. 2.6: change of all solution matrices relative to
+    # the new ones, sqrt(sum_d ||U_d - U_d^prev||^2 / sum_d ||U_d||^2)
+    old = [np.array([[3.0, 0.0]]), np.array([[0.0], [0.0]])]
+    new = [np.array([[3.0, 0.0]]), np.array([[4.0], [0.0]])]
+    assert als.relative_change(old, new) == pytest.approx(0.8, rel=0, abs=1e-15)
+    assert als.relative_change(new, new) == 0.0
+    # a swapped argument order is not the same rule
+    assert als.relative_change(new, old) == pytest.approx(4.0 / 3.0, abs=1e-15)
