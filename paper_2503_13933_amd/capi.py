@@ -110,7 +110,11 @@ def lib():
             "taps_autotune": (i32, [vp, i32, P(Problem), P(vp), C.c_char_p, P(Tuning), P(dbl), vp]),
             "taps_reconstruct_noalloc": (i32, [vp, P(i32), P(vp), i32, vp, i32, i32, vp, dbl, vp]),
             "taps_td_inner": (i32, [vp, i32, P(i32), P(i32), P(vp), i32, P(vp), i32, P(vp), vp, vp]),
+            "taps_load1d": (i32, [vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp]),
         }
+        missing = set(FUNCTIONS) - set(sig)
+        if missing:
+            raise TapsError(f"no ctypes signature for {sorted(missing)}")
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
             fn.restype = res

@@ -35,3 +35,13 @@ def test_library_exports_every_declared_symbol():
 def test_binding_covers_every_declared_symbol():
     from paper_2503_13933_amd import capi
     assert set(declared_functions()) == set(capi.FUNCTIONS)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_gives_every_function_a_signature():
+    # the loader refuses a function without argument types (ctypes would
+    # otherwise pass 64-bit pointers as C ints)
+    from paper_2503_13933_amd import capi
+    L = capi.lib()
+    for name in capi.FUNCTIONS:
+        assert getattr(L, name).argtypes is not None, name
