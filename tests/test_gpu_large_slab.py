@@ -110,7 +110,14 @@ def test_contractions_and_dim_solves(large):
         free = np.ones(n, bool)
         free[list(ora.fixed[d])] = False
         back = pu.rel(separated.apply_dim(ora, d, Co, X)[free], Qo[free])
-        msg = f"dim {d} (n={n}): backward error {back:.2e} (library's own {float(berr.item()):.2e})"
+        # a fast-diagonalisation solve is backward stable up to the condition
+        # of the eigenvector matrix P of E = C2^T C1^-T (the oracle's couplings)
+        C1, C2 = Co["mass"], Co["stiff" if "stiff" in Co else "ddt"]
+        E = C2.T @ np.linalg.inv(C1.T)
+        condP = float(np.linalg.cond(np.linalg.eig(E)[1]))
+        back_bar = max(1e-12, 100 * condP * pu.EPS)
+        msg = (f"dim {d} (n={n}): backward error {back:.2e} (library's own {float(berr.item()):.2e}; "
+               f"cond(P) {condP:.1e}, bar {back_bar:.1e})")
         if n <= 1000:
             Xo = separated.solve_dim(ora, d, Co, Qo)
             kappa = pu.cond_estimate(ora, d, Co)
@@ -118,7 +125,7 @@ def test_contractions_and_dim_solves(large):
             r, m = pu.check(X, Xo, bar, f"X dim {d}")
             msg += f"; against the oracle's solve rel {r:.2e} max entry {m:.2e} (kappa {kappa:.1e}, bar {bar:.1e})"
         _say(msg)
-        assert back < 1e-11
+        assert back <= back_bar
         assert np.all(X[~free] == 0.0)
 
 
