@@ -41,11 +41,16 @@ struct BProb {
   double* Wt;
   double* gpart;
   double* lpart;
+  double* qpart;  // partial forces of split load rows ([split][n M])
   double* rparts;
   double* outs;  // res (D+2), backward error per dim (D), relative change of the sweep (1)
 };
 
 enum { kItGram = 0, kItLgram = 1, kItForce = 2, kItRes = 3, kItKinds = 4 };
+// load columns per force work item where a dim's loads are split (long load
+// rows: the force of a few problems with tens of thousands of load terms
+// would otherwise run on a few waves per SIMD with its loads exposed)
+constexpr int kForceCols = 1024;
 // persistent grid sizes (a few items per workgroup at full batches)
 constexpr int kPersistLds = 4096, kPersistStream = 8192;
 
@@ -146,15 +151,30 @@ __global__ __launch_bounds__(256) void kb_load_weights_long(const BProb* __restr
   load_weights_long(blockIdx.x, A, P[b].Wt);
 }
 
+// split = 0: item = row block, Q written directly; split = 1: item = (row
+// block, column range of kForceCols), partial Q per range, summed by
+// kb_force_sum
 __global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act,
                                                 const int* __restrict__ pref, const int* __restrict__ owner,
-                                                int nact, int d) {
+                                                int nact, int d, int split) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
-    force(x.c, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
+    if (!split) {
+      force(x.c, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
+    } else {
+      const int ns = (q.Rc[d] + kForceCols - 1) / kForceCols, rb = x.c / ns, sp = x.c - rb * ns;
+      force(rb, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.qpart + long(sp) * q.n[d] * q.M, sp * kForceCols,
+            (sp + 1) * kForceCols);
+    }
   }
+}
+
+__global__ void kb_force_sum(const BProb* __restrict__ P, const int* __restrict__ act, int d) {
+  const BProb& q = P[act[blockIdx.y]];
+  const int ns = (q.Rc[d] + kForceCols - 1) / kForceCols;
+  sum_parts_n<kVB>(blockIdx.x * kVB, ns, long(q.n[d]) * q.M, q.qpart, q.Q);
 }
 
 __global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act,
@@ -212,6 +232,15 @@ __global__ __launch_bounds__(256) void kb_balance(const BalanceArgs* __restrict_
   balance(BA[act[blockIdx.x]], scale_mask);
 }
 
+// the Gram rescaling of the balance over many blocks per problem (a large
+// load Gram rescaled by the one balancing block took milliseconds)
+__global__ __launch_bounds__(256) void kb_rescale_grams(const BalanceArgs* __restrict__ BA,
+                                                        const int* __restrict__ act, unsigned scale_mask) {
+  const BalanceArgs& A = BA[act[blockIdx.y]];
+#pragma unroll
+  for (int u = 0; u < kVB; ++u) rescale_grams(A, scale_mask, (long(blockIdx.x) * kVB + u) * blockDim.x);
+}
+
 __global__ __launch_bounds__(256) void kb_snapshot(const BalanceArgs* __restrict__ BA, const int* __restrict__ act) {
   snapshot(BA[act[blockIdx.x]]);
 }
@@ -223,11 +252,14 @@ size_t gram_lds_allowed = 0, res_lds_allowed = 0;
 struct Sizes {
   int chunks[TAPS_MAX_DIMS], ctiles[TAPS_MAX_DIMS], splits[TAPS_MAX_DIMS], gram[TAPS_MAX_DIMS];
   int lgram[TAPS_MAX_DIMS], rblocks[TAPS_MAX_DIMS], cpl[TAPS_MAX_DIMS], wt[TAPS_MAX_DIMS];
-  int rchunks[TAPS_MAX_DIMS], rc[TAPS_MAX_DIMS];
+  int rchunks[TAPS_MAX_DIMS], rc[TAPS_MAX_DIMS], qlen[TAPS_MAX_DIMS], fsplit[TAPS_MAX_DIMS];
   int max_terms = 1;
   Sizes() {
-    for (int d = 0; d < TAPS_MAX_DIMS; ++d)
+    for (int d = 0; d < TAPS_MAX_DIMS; ++d) {
       chunks[d] = ctiles[d] = splits[d] = gram[d] = lgram[d] = rblocks[d] = cpl[d] = wt[d] = rchunks[d] = rc[d] = 1;
+      qlen[d] = 1;
+      fsplit[d] = 0;
+    }
   }
 };
 
@@ -272,6 +304,15 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const size_t args_sz = solve_args_bytes();
   const int lg_rows = h->tune.lgram_rows > 0 ? h->tune.lgram_rows : kLgRows;
   Sizes Z;
+  for (int d = 0; d < D; ++d)
+    for (int b = 0; b < B; ++b)
+      if (probs[b].R_cols[d] > kForceCols) Z.fsplit[d] = 1;
+  // dims whose load map is the identity in every problem: the per-term
+  // products are the load weights themselves, written straight into Wt
+  std::vector<char> ident(D, 1);
+  for (int d = 0; d < D; ++d)
+    for (int b = 0; b < B; ++b)
+      if (probs[b].d_load_col[d]) ident[d] = 0;
   Bump bump;
   const size_t o_args = bump.take(args_sz * size_t(D) * B);
   const size_t o_prob = bump.take(sizeof(BProb) * size_t(B));
@@ -289,7 +330,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     switch (kind) {
       case kItGram: return cdiv(p.n[d], kGramRows);
       case kItLgram: return cdiv(p.R_cols[d], kLgCols) * cdiv(p.n[d], lg_rows);
-      case kItForce: return cdiv(p.n[d], kQRows);
+      case kItForce: return cdiv(p.n[d], kQRows) * (Z.fsplit[d] ? cdiv(p.R_cols[d], kForceCols) : 1);
       default: return cdiv(p.n[d], kResRows);
     }
   };
@@ -308,11 +349,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const size_t o_owner = bump.take(size_t(std::max(1L, own_total)) * 4);
   std::vector<BProb> bp(B);
   std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B), wt_doubles(B);
-  std::vector<size_t> o_snap(B);
+  std::vector<size_t> o_snap(B), o_qp(B), o_fac(B);
+  long rescale_len = 1;   // Gram and load-Gram entries of all dims, largest problem
   for (int b = 0; b < B; ++b) {
     const taps_problem_t& p = probs[b];
     int Kmax = 1, nmax = 1, tot = 0;
-    size_t ws = 0, gp = 0, lp = 0, wt = 0, nsum = 0;
+    size_t ws = 0, gp = 0, lp = 0, wt = 0, nsum = 0, qp = 0;
     for (int d = 0; d < D; ++d) {
       const int ch = cdiv(p.n[d], kGramRows), ct = cdiv(p.R_cols[d], kLgCols), sp = cdiv(p.n[d], lg_rows);
       Kmax = std::max(Kmax, p.n_kinds[d]);
@@ -335,6 +377,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       Z.wt[d] = std::max(Z.wt[d], cdiv(long(p.R_cols[d]) * M, 256));
       Z.rchunks[d] = std::max(Z.rchunks[d], cdiv(p.n[d], kResRows));
       Z.rc[d] = std::max(Z.rc[d], p.R_cols[d]);
+      Z.qlen[d] = std::max(Z.qlen[d], cdiv(long(p.n[d]) * M, 256));
+      if (Z.fsplit[d]) qp = std::max(qp, size_t(cdiv(p.R_cols[d], kForceCols)) * p.n[d] * M * 8);
     }
     o_cache[b] = bump.take(cache_total(&p));
     o_C[b] = bump.take(size_t(Kmax) * MM * 8);
@@ -346,6 +390,11 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     o_rp[b] = bump.take(size_t(tot) * 2 * 8);
     o_ws[b] = bump.take(ws);
     o_snap[b] = bump.take(nsum * M * 8);
+    o_fac[b] = bump.take(size_t(D) * M * 8);
+    long rl = 0;
+    for (int d = 0; d < D; ++d) rl += long(p.n_kinds[d]) * MM + long(p.R_cols[d]) * M;
+    rescale_len = std::max(rescale_len, rl);
+    o_qp[b] = bump.take(qp);
   }
   TAPS_TRY(grow(h, &h->batch, &h->batch_bytes, bump.off, stream));
   char* base = static_cast<char*>(h->batch);
@@ -413,6 +462,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     q.Wt = reinterpret_cast<double*>(base + o_Wt[b]);
     q.gpart = reinterpret_cast<double*>(base + o_gp[b]);
     q.lpart = reinterpret_cast<double*>(base + o_lp[b]);
+    q.qpart = reinterpret_cast<double*>(base + o_qp[b]);
     q.rparts = reinterpret_cast<double*>(base + o_rp[b]);
     q.outs = outs + size_t(b) * NO;
     for (int d = 0; d < D; ++d) {
@@ -441,7 +491,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       }
       w.ptr = p.d_load_ptr[d];
       w.idx = p.d_load_idx[d];
-      w.P = q.Wt + wt_doubles[b];
+      w.P = ident[d] ? q.Wt : q.Wt + wt_doubles[b];
       solve_args_fill(args.data() + (size_t(d) * B + b) * args_sz, &p, d, q.C, q.Q, q.U[d],
                       infos + size_t(b) * D + d, base + o_ws[b], use_fd[d]);
     }
@@ -460,6 +510,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       snap += size_t(p.n[d]) * M;
     }
     bal[b].change = want_change ? q.outs + 2 * D + 2 : nullptr;
+    bal[b].fac = reinterpret_cast<double*>(base + o_fac[b]);
   }
   std::vector<int> active(B), next;
   for (int b = 0; b < B; ++b) {
@@ -522,7 +573,9 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_LAUNCHED(h, "kb_couple");
     kb_load_terms<<<dim3(cdiv(Z.max_terms, kVB), nact), 256, 0, st>>>(d_wa, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_load_terms");
-    if (long_groups[d]) {
+    if (ident[d]) {
+      // the products are the weights (one term per load column)
+    } else if (long_groups[d]) {
       kb_load_weights_long<<<dim3(Z.rc[d], nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
       TAPS_LAUNCHED(h, "kb_load_weights_long");
     } else {
@@ -530,8 +583,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       TAPS_LAUNCHED(h, "kb_load_weights");
     }
     kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItForce, d),
-                                                                 owner(kItForce, d), nact, d);
+                                                                 owner(kItForce, d), nact, d, Z.fsplit[d]);
     TAPS_LAUNCHED(h, "kb_force");
+    if (Z.fsplit[d]) {
+      kb_force_sum<<<dim3(cdiv(Z.qlen[d], kVB), nact), 256, 0, st>>>(d_prob, d_active, d);
+      TAPS_LAUNCHED(h, "kb_force_sum");
+    }
     double fl = 0.0, by = 0.0;
     std::unordered_set<const double*> seen;
     for (int b : active) {
@@ -582,6 +639,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     // the factors inside the balancing kernel; only the stale ones are recomputed
     kb_balance<<<nact, 256, 0, st>>>(d_bal, d_active, valid);
     TAPS_LAUNCHED(h, "kb_balance");
+    kb_rescale_grams<<<dim3(unsigned(cdiv(rescale_len, 256L * kVB)), nact), 256, 0, st>>>(d_bal, d_active, valid);
+    TAPS_LAUNCHED(h, "kb_rescale_grams");
     for (int e = 0; e < D; ++e)
       if (!(valid & (1u << e))) TAPS_TRY(refresh(e, nact, st));
     for (int d = 0; d < D; ++d) {
@@ -609,7 +668,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     for (int d = 0; d < D; ++d) {
       sig.push_back(p0.s[d] * 2 + use_fd[d]);
       for (int v : {Z.chunks[d], Z.ctiles[d], Z.splits[d], Z.gram[d], Z.lgram[d], Z.rblocks[d], Z.cpl[d], Z.wt[d],
-                    Z.rchunks[d], Z.rc[d], int(long_groups[d])})
+                    Z.rchunks[d], Z.rc[d], int(long_groups[d]), Z.qlen[d], Z.fsplit[d], int(ident[d])})
         sig.push_back(v);
     }
     if (h->graph_exec && sig == h->graph_sig) return TAPS_OK;

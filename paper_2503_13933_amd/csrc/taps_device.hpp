@@ -374,8 +374,11 @@ __device__ inline void load_weights_long(int c, const WeightArgs& A, double* __r
 // owns rows [16v, 16v+16) of the block, the load columns are the contracted
 // index (passes of 16 columns in four steps, operands loaded together), and
 // the M columns are covered in passes of up to four 16-wide tiles.
+// (load columns [c_lo, c_hi) only: the batched driver splits long load
+// rows over several work items and sums their partial Q afterwards)
 __device__ inline void force(int rblock, int n, int Rc, int M, const double* __restrict__ F_,
-                             const double* __restrict__ Wt_, double* __restrict__ Q_) {
+                             const double* __restrict__ Wt_, double* __restrict__ Q_, int c_lo = 0,
+                             int c_hi = 0x7fffffff) {
   const auto F = gp(F_);
   const auto Wt = gp(Wt_);
   const auto Q = gp(Q_);
@@ -390,11 +393,12 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     // 16 load columns per pass, all operands of a pass loaded together and
     // the next pass's requested before this pass's products
+    const int c_end = min(Rc, c_hi);
     auto load = [&](int c0, double (&a)[4], double (&b)[4][4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kc = c0 + 4 * u + (lane >> 4);
-        const bool ok = kc < Rc;
+        const bool ok = kc < c_end;
         a[u] = (ok && ia < n) ? F[long(ia) * Rc + kc] : 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -404,8 +408,8 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
       }
     };
     double an[4], bn[4][4];
-    load(0, an, bn);
-    for (int c0 = 0; c0 < Rc; c0 += 16) {
+    load(c_lo, an, bn);
+    for (int c0 = c_lo; c0 < c_end; c0 += 16) {
       double a[4], b[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -413,7 +417,7 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
 #pragma unroll
         for (int c = 0; c < 4; ++c) b[u][c] = bn[u][c];
       }
-      if (c0 + 16 < Rc) load(c0 + 16, an, bn);
+      if (c0 + 16 < c_end) load(c0 + 16, an, bn);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
@@ -564,6 +568,9 @@ struct BalanceArgs {
   // measured) and where the relative change of the sweep goes (one double)
   const double* snap[TAPS_MAX_DIMS];
   double* change;
+  // where the per-dim mode factors go (D x M; null: the Grams of the scale
+  // mask are rescaled inside the balancing block itself)
+  double* fac;
 };
 
 // Copy of every factor of one problem (the start of a sweep), one block of
@@ -695,6 +702,11 @@ __device__ inline void balance(const BalanceArgs& A, unsigned scale_mask = 0) {
       *A.change = nn > 0.0 ? sqrt(dd / nn) : (dd > 0.0 ? INFINITY : 0.0);
     }
   }
+  if (A.fac) {
+    if (ph == 0 && m < M)
+      for (int e = 0; e < A.D; ++e) gp(A.fac)[e * M + m] = fac[e][m];
+    return;
+  }
   for (int e = 0; e < A.D; ++e) {
     if (!(scale_mask & (1u << e))) continue;
     const int MM = M * M;
@@ -704,6 +716,30 @@ __device__ inline void balance(const BalanceArgs& A, unsigned scale_mask = 0) {
       G[t] *= fac[e][mm] * fac[e][nn];
     }
     for (int t = threadIdx.x; t < A.Rc[e] * M; t += blockDim.x) LG[t] *= fac[e][t - (t / M) * M];
+  }
+}
+
+// The Grams and load Grams of the dims in scale_mask follow the factors
+// balance() applied (A.fac): G^k[m][n] *= f_m f_n, L[c][m] *= f_m, for the
+// entries [t0, t0 + blockDim.x) of the mask's dims laid end to end.
+__device__ inline void rescale_grams(const BalanceArgs& A, unsigned scale_mask, long t0) {
+  const int M = A.M, MM = M * M;
+  long t = t0 + threadIdx.x;
+  for (int e = 0; e < A.D; ++e) {
+    if (!(scale_mask & (1u << e))) continue;
+    const long g = long(A.K[e]) * MM, l = long(A.Rc[e]) * M;
+    const auto f = gp(A.fac) + e * M;
+    if (t < g) {
+      const int r = int(t % MM), mm = r / M, nn = r - mm * M;
+      gp(A.gram[e])[t] *= f[mm] * f[nn];
+      return;
+    }
+    t -= g;
+    if (t < l) {
+      gp(A.lgram[e])[t] *= f[int(t % M)];
+      return;
+    }
+    t -= l;
   }
 }
 

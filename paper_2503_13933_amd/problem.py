@@ -149,6 +149,8 @@ class DeviceProblem:
             p.d_F[d] = a.F.data_ptr()
             p.d_fixed[d] = a.fixed.data_ptr()
             cols = load_cols[d]
+            if cols is not None and len(cols) == a.F.shape[1] and np.array_equal(cols, np.arange(len(cols))):
+                cols = None     # the identity map: one load column per term, no grouping
             if cols is None:
                 assert a.F.shape[1] == R
                 continue

@@ -76,3 +76,38 @@ def test_uneven_batch_against_oracle(env, solver):
              f"rho {rb:.8e} vs {rho_o[-1]:.8e}; change {cb:.8e} vs {ch_o[-1]:.8e}")
         assert abs(rb - rho_o[-1]) <= rbar
         assert abs(cb - ch_o[-1]) <= cbar * ch_o[-1]
+
+
+def test_long_load_rows_split_over_force_items(env):
+    """Load rows longer than one force work item's column range (32 n_t load
+    terms above 1024 in x): the force is summed from per-range partials.
+    Against the oracle, and a captured graph of the same two sweeps equal
+    to host launches bit for bit."""
+    torch, capi, problem, h = env
+    cases = [W.spt_slab(14, 11, 9, nt, n_param=32, M=5, seed=31 + i, y0=0.4 + 0.1 * i)
+             for i, nt in enumerate((41, 12, 36))]
+    _say(f"long load rows: R = {[32 * c.axes[6].n for c in cases]}, M=5")
+    capi.taps_set_tuning(h, solver=capi.SOLVER_FAST_DIAG)
+    try:
+        devs = [problem.spt_slab(h, c) for c in cases]
+        U0 = [W.initial_factors(c.axes, c.M, c.seed) for c in cases]
+        Ub = [d.factors(u) for d, u in zip(devs, U0)]
+        sweeps, rhos = capi.taps_als_batched(h, [d.struct for d in devs], Ub, 0.0, 2)
+        torch.cuda.synchronize()
+        for c, u0, ub, rb in zip(cases, U0, Ub, rhos):
+            ora = problems.spt_slab(c)
+            Uo, rho_o, ch_o = pu.oracle_sweeps(ora, u0, 2)
+            fbar, rbar, cbar, kappa = pu.sweep_bars(ora, u0, Uo, 2, rho_o[-1], ch_o[-1])
+            diffs = [pu.check(a.cpu().numpy(), o, bar, f"factor {d}") for d, (a, o, bar) in enumerate(zip(ub, Uo, fbar))]
+            _say(f"  R={32 * c.axes[6].n} kappa {kappa:.1e} factor diffs {[f'{x:.0e}/{y:.0e}' for x, y in diffs]} "
+                 f"(bars {[f'{b:.0e}' for b in fbar]}); rho {rb:.8e} vs {rho_o[-1]:.8e}")
+            assert abs(rb - rho_o[-1]) <= rbar
+        capi.taps_set_tuning(h, graph_sweeps=2)
+        Ug = [d.factors(u) for d, u in zip(devs, U0)]
+        capi.taps_als_batched(h, [d.struct for d in devs], Ug, 0.0, 2)
+        torch.cuda.synchronize()
+        for ub, ug in zip(Ub, Ug):
+            for a, b in zip(ub, ug):
+                assert torch.equal(a, b)
+    finally:
+        capi.taps_set_tuning(h, solver=capi.SOLVER_BLOCK_LU, graph_sweeps=0)
