@@ -42,6 +42,7 @@ struct BProb {
   double* gpart;
   double* lpart;
   double* qpart;  // partial forces of split load rows ([split][n M])
+  double* wpart;  // partial load weights of sliced long groups ([group][slice][M])
   double* rparts;
   double* outs;  // res (D+2), backward error per dim (D), relative change of the sweep (1)
 };
@@ -51,6 +52,8 @@ enum { kItGram = 0, kItLgram = 1, kItForce = 2, kItRes = 3, kItKinds = 4 };
 // rows: the force of a few problems with tens of thousands of load terms
 // would otherwise run on a few waves per SIMD with its loads exposed)
 constexpr int kForceCols = 1024;
+// terms per slice of a long load group (load weights formed in place)
+constexpr int kWSlice = 512;
 // persistent grid sizes (a few items per workgroup at full batches)
 constexpr int kPersistLds = 4096, kPersistStream = 8192;
 
@@ -65,6 +68,22 @@ __device__ inline Item locate(const int* __restrict__ act, const int* __restrict
                               const int* __restrict__ owner, int w) {
   const int a = owner[w];
   return Item{act[a], w - pref[a]};
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (block b runs on XCD b % 8),
+// and each XCD has its own L2.  A persistent grid therefore renumbers its
+// blocks so that XCD x's blocks take the x-th contiguous eighth of the work
+// items, and each block a contiguous run of items: the items of one problem
+// (row blocks sharing its U, Wt, C, Q and bands) then stay on one XCD and
+// read those operands from HBM once instead of once per XCD.
+struct ItemRange {
+  int lo, hi;
+};
+__device__ inline ItemRange xcd_items(int nit) {
+  const int G = gridDim.x, b = blockIdx.x, G8 = G & ~7;
+  const int L = b < G8 ? (b & 7) * (G8 >> 3) + (b >> 3) : b;
+  const int per = (nit + G - 1) / G;
+  return ItemRange{min(nit, L * per), min(nit, (L + 1) * per)};
 }
 
 // owner tables of every (kind, dim): one thread per active problem fills
@@ -85,7 +104,8 @@ __global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__
                                                        const int* __restrict__ pref, const int* __restrict__ owner,
                                                        int nact, int e) {
   const int nit = pref[nact];
-  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+  const ItemRange ir = xcd_items(nit);
+  for (int w = ir.lo; w < ir.hi; ++w) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     gram_partial(x.c, q.n[e], q.M, q.s[e], q.K[e], q.band[e], q.U[e], q.gpart + long(x.c) * q.K[e] * q.M * q.M);
@@ -109,7 +129,8 @@ __global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict_
                                                         const int* __restrict__ pref, const int* __restrict__ owner,
                                                         int nact, int e, int rows) {
   const int nit = pref[nact];
-  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+  const ItemRange ir = xcd_items(nit);
+  for (int w = ir.lo; w < ir.hi; ++w) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     const int splits = (q.n[e] + rows - 1) / rows;
@@ -141,14 +162,31 @@ __global__ void kb_load_weights(const BProb* __restrict__ P, const WeightArgs* _
   for (int u = 0; u < kVB; ++u) load_weights(blockIdx.x * kVB + u, WA[long(b) * D + d], P[b].Wt);
 }
 
-// Long groups: block x = group (blocks past a problem's group count return).
-__global__ __launch_bounds__(256) void kb_load_weights_long(const BProb* __restrict__ P,
-                                                            const WeightArgs* __restrict__ WA,
-                                                            const int* __restrict__ act, int d, int D) {
+// Long groups, products formed in place: block x = group * wsl + slice
+// (blocks past a problem's group count return); wsl = 1 writes the load
+// weights directly, otherwise per-slice partials summed by kb_wsum.
+__global__ __launch_bounds__(256) void kb_load_weights_fused(const BProb* __restrict__ P,
+                                                             const WeightArgs* __restrict__ WA,
+                                                             const int* __restrict__ act, int d, int D, int wsl) {
   const int b = act[blockIdx.y];
   const WeightArgs& A = WA[long(b) * D + d];
-  if (int(blockIdx.x) >= A.Rc) return;
-  load_weights_long(blockIdx.x, A, P[b].Wt);
+  const int c = blockIdx.x / wsl, sl = blockIdx.x - c * wsl;
+  if (c >= A.Rc) return;
+  load_weights_fused(c, sl, wsl, A, wsl == 1 ? P[b].Wt : P[b].wpart);
+}
+
+__global__ void kb_wsum(const BProb* __restrict__ P, const WeightArgs* __restrict__ WA, const int* __restrict__ act,
+                        int d, int D, int wsl) {
+  const int b = act[blockIdx.y];
+  const BProb& q = P[b];
+  const int M = q.M, Rc = WA[long(b) * D + d].Rc;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Rc * M) return;
+  const int c = t / M, m = t - c * M;
+  const auto part = gp(q.wpart) + long(c) * wsl * M + m;
+  double acc = 0.0;
+  for (int sl = 0; sl < wsl; ++sl) acc += part[long(sl) * M];
+  gp(q.Wt)[t] = acc;
 }
 
 // split = 0: item = row block, Q written directly; split = 1: item = (row
@@ -158,7 +196,8 @@ __global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, con
                                                 const int* __restrict__ pref, const int* __restrict__ owner,
                                                 int nact, int d, int split) {
   const int nit = pref[nact];
-  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+  const ItemRange ir = xcd_items(nit);
+  for (int w = ir.lo; w < ir.hi; ++w) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     if (!split) {
@@ -181,7 +220,8 @@ __global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict_
                                                         const int* __restrict__ pref, const int* __restrict__ owner,
                                                         int nact, int d) {
   const int nit = pref[nact];
-  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
+  const ItemRange ir = xcd_items(nit);
+  for (int w = ir.lo; w < ir.hi; ++w) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     residual_part(x.c, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
@@ -252,13 +292,14 @@ size_t gram_lds_allowed = 0, res_lds_allowed = 0;
 struct Sizes {
   int chunks[TAPS_MAX_DIMS], ctiles[TAPS_MAX_DIMS], splits[TAPS_MAX_DIMS], gram[TAPS_MAX_DIMS];
   int lgram[TAPS_MAX_DIMS], rblocks[TAPS_MAX_DIMS], cpl[TAPS_MAX_DIMS], wt[TAPS_MAX_DIMS];
-  int rchunks[TAPS_MAX_DIMS], rc[TAPS_MAX_DIMS], qlen[TAPS_MAX_DIMS], fsplit[TAPS_MAX_DIMS];
+  int rchunks[TAPS_MAX_DIMS], rc[TAPS_MAX_DIMS], qlen[TAPS_MAX_DIMS], fsplit[TAPS_MAX_DIMS], wsl[TAPS_MAX_DIMS];
   int max_terms = 1;
   Sizes() {
     for (int d = 0; d < TAPS_MAX_DIMS; ++d) {
       chunks[d] = ctiles[d] = splits[d] = gram[d] = lgram[d] = rblocks[d] = cpl[d] = wt[d] = rchunks[d] = rc[d] = 1;
       qlen[d] = 1;
       fsplit[d] = 0;
+      wsl[d] = 1;
     }
   }
 };
@@ -313,6 +354,18 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   for (int d = 0; d < D; ++d)
     for (int b = 0; b < B; ++b)
       if (probs[b].d_load_col[d]) ident[d] = 0;
+  // long groups (on average 64 terms or more per load column in every
+  // problem): the products formed in place, each group cut into Z.wsl slices
+  // of at most about kWSlice terms on average
+  std::vector<char> long_groups(D, 1);
+  for (int d = 0; d < D; ++d) {
+    for (int b = 0; b < B; ++b) {
+      const taps_problem_t& p = probs[b];
+      if (long(p.R) < 64L * p.R_cols[d]) long_groups[d] = 0;
+      Z.wsl[d] = std::max(Z.wsl[d], cdiv(cdiv(p.R, p.R_cols[d]), kWSlice));
+    }
+    if (!long_groups[d] || ident[d]) Z.wsl[d] = 1;
+  }
   Bump bump;
   const size_t o_args = bump.take(args_sz * size_t(D) * B);
   const size_t o_prob = bump.take(sizeof(BProb) * size_t(B));
@@ -349,12 +402,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const size_t o_owner = bump.take(size_t(std::max(1L, own_total)) * 4);
   std::vector<BProb> bp(B);
   std::vector<size_t> o_cache(B), o_C(B), o_Q(B), o_Wt(B), o_gp(B), o_lp(B), o_rp(B), o_ws(B), wt_doubles(B);
-  std::vector<size_t> o_snap(B), o_qp(B), o_fac(B);
+  std::vector<size_t> o_snap(B), o_qp(B), o_fac(B), o_wp(B);
   long rescale_len = 1;   // Gram and load-Gram entries of all dims, largest problem
   for (int b = 0; b < B; ++b) {
     const taps_problem_t& p = probs[b];
     int Kmax = 1, nmax = 1, tot = 0;
-    size_t ws = 0, gp = 0, lp = 0, wt = 0, nsum = 0, qp = 0;
+    size_t ws = 0, gp = 0, lp = 0, wt = 0, nsum = 0, qp = 0, wp = 0;
     for (int d = 0; d < D; ++d) {
       const int ch = cdiv(p.n[d], kGramRows), ct = cdiv(p.R_cols[d], kLgCols), sp = cdiv(p.n[d], lg_rows);
       Kmax = std::max(Kmax, p.n_kinds[d]);
@@ -379,6 +432,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       Z.rc[d] = std::max(Z.rc[d], p.R_cols[d]);
       Z.qlen[d] = std::max(Z.qlen[d], cdiv(long(p.n[d]) * M, 256));
       if (Z.fsplit[d]) qp = std::max(qp, size_t(cdiv(p.R_cols[d], kForceCols)) * p.n[d] * M * 8);
+      if (Z.wsl[d] > 1) wp = std::max(wp, size_t(p.R_cols[d]) * Z.wsl[d] * M * 8);
     }
     o_cache[b] = bump.take(cache_total(&p));
     o_C[b] = bump.take(size_t(Kmax) * MM * 8);
@@ -391,6 +445,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     o_ws[b] = bump.take(ws);
     o_snap[b] = bump.take(nsum * M * 8);
     o_fac[b] = bump.take(size_t(D) * M * 8);
+    o_wp[b] = bump.take(wp);
     long rl = 0;
     for (int d = 0; d < D; ++d) rl += long(p.n_kinds[d]) * MM + long(p.R_cols[d]) * M;
     rescale_len = std::max(rescale_len, rl);
@@ -405,12 +460,6 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const CoupleArgs* d_cpl = reinterpret_cast<const CoupleArgs*>(base + o_cpl);
   const WeightArgs* d_wa = reinterpret_cast<const WeightArgs*>(base + o_wa);
   const BalanceArgs* d_bal = reinterpret_cast<const BalanceArgs*>(base + o_bal);
-  // group sums of the load weights: a block per group where the groups are
-  // long (on average 64 terms or more per load column in every problem)
-  std::vector<char> long_groups(D, 1);
-  for (int d = 0; d < D; ++d)
-    for (int b = 0; b < B; ++b)
-      if (long(probs[b].R) < 64L * probs[b].R_cols[d]) long_groups[d] = 0;
   const int* d_pref = reinterpret_cast<const int*>(base + o_pref);
   auto pref = [&](int kind, int d) { return d_pref + size_t(kind * D + d) * (B + 1); };
   int* d_owner = reinterpret_cast<int*>(base + o_owner);
@@ -463,6 +512,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     q.gpart = reinterpret_cast<double*>(base + o_gp[b]);
     q.lpart = reinterpret_cast<double*>(base + o_lp[b]);
     q.qpart = reinterpret_cast<double*>(base + o_qp[b]);
+    q.wpart = reinterpret_cast<double*>(base + o_wp[b]);
     q.rparts = reinterpret_cast<double*>(base + o_rp[b]);
     q.outs = outs + size_t(b) * NO;
     for (int d = 0; d < D; ++d) {
@@ -571,13 +621,22 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
     kb_couple<<<dim3(cdiv(Z.cpl[d], kVB), nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
     TAPS_LAUNCHED(h, "kb_couple");
-    kb_load_terms<<<dim3(cdiv(Z.max_terms, kVB), nact), 256, 0, st>>>(d_wa, d_active, d, D);
-    TAPS_LAUNCHED(h, "kb_load_terms");
-    if (ident[d]) {
-      // the products are the weights (one term per load column)
-    } else if (long_groups[d]) {
-      kb_load_weights_long<<<dim3(Z.rc[d], nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
-      TAPS_LAUNCHED(h, "kb_load_weights_long");
+    if (long_groups[d] && !ident[d]) {
+      // products formed in place, group slices summed afterwards
+      kb_load_weights_fused<<<dim3(Z.rc[d] * Z.wsl[d], nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D,
+                                                                           Z.wsl[d]);
+      TAPS_LAUNCHED(h, "kb_load_weights_fused");
+      if (Z.wsl[d] > 1) {
+        kb_wsum<<<dim3(cdiv(Z.wt[d], 1), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D, Z.wsl[d]);
+        TAPS_LAUNCHED(h, "kb_wsum");
+      }
+    } else {
+      kb_load_terms<<<dim3(cdiv(Z.max_terms, kVB), nact), 256, 0, st>>>(d_wa, d_active, d, D);
+      TAPS_LAUNCHED(h, "kb_load_terms");
+    }
+    if (ident[d] || long_groups[d]) {
+      // the products are the weights (one term per load column), or the
+      // weights were formed in place above
     } else {
       kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
       TAPS_LAUNCHED(h, "kb_load_weights");
@@ -668,7 +727,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     for (int d = 0; d < D; ++d) {
       sig.push_back(p0.s[d] * 2 + use_fd[d]);
       for (int v : {Z.chunks[d], Z.ctiles[d], Z.splits[d], Z.gram[d], Z.lgram[d], Z.rblocks[d], Z.cpl[d], Z.wt[d],
-                    Z.rchunks[d], Z.rc[d], int(long_groups[d]), Z.qlen[d], Z.fsplit[d], int(ident[d])})
+                    Z.rchunks[d], Z.rc[d], int(long_groups[d]), Z.qlen[d], Z.fsplit[d], int(ident[d]), Z.wsl[d]})
         sig.push_back(v);
     }
     if (h->graph_exec && sig == h->graph_sig) return TAPS_OK;

@@ -338,34 +338,53 @@ __device__ inline void load_weights(int tblock, const WeightArgs& A, double* __r
   gp(Wt)[t] = acc;
 }
 
-// The same group sums for long groups (a few groups of many terms each, e.g.
-// a dim whose every load term uses its one column): one block of 256
-// threads per group, as 256/L row lanes x L mode lanes (L = M rounded up to
-// 32 or 64), each row lane summing every (256/L)-th term of the group with
-// eight loads in flight, the row lanes then summed in a fixed order.
-__device__ inline void load_weights_long(int c, const WeightArgs& A, double* __restrict__ Wt) {
+// Long groups with the per-term products formed in place (no product
+// table): block (c, s) takes slice s of wsl equal slices of group c's terms
+// and sums prod_{e != d} L_e[col_e(r)][m] over them, as 256/L row lanes x L
+// mode lanes (L = M rounded up to 32 or 64); the row lanes are summed in a
+// fixed order and the slice's sum goes to out[(c wsl + s) M + m] (the load
+// weights themselves when wsl = 1).
+__device__ inline void load_weights_fused(int c, int s, int wsl, const WeightArgs& A, double* __restrict__ out) {
   __shared__ double red[256];
   const int M = A.M, L = M <= 32 ? 32 : 64, lanes = 256 / L;
-  const int m = threadIdx.x % L, lr = threadIdx.x / L;
+  const int m = threadIdx.x % L, lr = threadIdx.x / L, mc = min(m, M - 1);
   const int rb = A.ptr ? gp(A.ptr)[c] : c;
   const int re = A.ptr ? gp(A.ptr)[c + 1] : c + 1;
-  const auto P = gp(A.P) + min(m, M - 1);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  int q = rb + lr;
-  for (; q + 7 * lanes < re; q += 8 * lanes) {
-    double v[8];
+  const int len = (re - rb + wsl - 1) / wsl;
+  const int q0 = rb + s * len, q1 = min(re, q0 + len);
+  // four terms per step, every load of a kind issued for all four before
+  // any is used (index -> column map -> load Gram is a dependent chain)
+  constexpr int NT = 4;
+  double acc[NT] = {0.0, 0.0, 0.0, 0.0};
+  for (int q = q0 + lr; q < q1; q += NT * lanes) {
+    int r[NT];
+    double prod[NT];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = P[long(q + u * lanes) * M];
+    for (int t = 0; t < NT; ++t) {
+      const int qt = min(q + t * lanes, q1 - 1);
+      r[t] = A.ptr ? gp(A.idx)[qt] : qt;
+      prod[t] = (q + t * lanes < q1) ? 1.0 : 0.0;
+    }
+    for (int e = 0; e < A.D; ++e) {
+      if (e == A.d) continue;
+      int ce[NT];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u & 3] += v[u];
+      for (int t = 0; t < NT; ++t) ce[t] = A.col[e] ? gp(A.col[e])[r[t]] : r[t];
+      double lv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) lv[t] = gp(A.lgram[e])[long(ce[t]) * M + mc];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) prod[t] *= lv[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] += prod[t];
   }
-  for (; q < re; q += lanes) acc[0] += P[long(q) * M];
   red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   if (lr == 0 && m < M) {
-    double s = 0.0;
-    for (int k = 0; k < lanes; ++k) s += red[k * L + m];
-    gp(Wt)[long(c) * M + m] = s;
+    double t = 0.0;
+    for (int k = 0; k < lanes; ++k) t += red[k * L + m];
+    gp(out)[(long(c) * wsl + s) * M + m] = t;
   }
   __syncthreads();
 }
