@@ -290,8 +290,9 @@ taps_status taps_sweep(taps_handle_t h, const taps_problem_t* prob, double* cons
  * each).  Returns TAPS_OK even if not converged (compare *rho with tol); a
  * breakdown in a dim solve (zero pivot, or backward error above
  * TAPS_BERR_LIMIT) ends the loop with *rho = *change = NaN and
- * taps_last_error() naming the dim.  Workspace: the handle keeps a copy of
- * the factors (sum_d n_d M doubles) for the change. */
+ * taps_last_error() naming the dim.  The change is measured (a copy of the
+ * factors, sum_d n_d M doubles of workspace, per sweep) only when change or
+ * change_history is non-null or change_tol > 0. */
 taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const* d_U,
                      double tol, double change_tol, int32_t iter_max, int32_t* sweeps, double* rho,
                      double* change, double* history, double* change_history, hipStream_t stream);

@@ -244,11 +244,10 @@ def taps_als(h: Handle, prob: Problem, U, tol: float, iter_max: int, change_tol:
     relative change of the factors after every sweep."""
     sweeps = C.c_int32()
     rho = C.c_double()
-    chg = C.c_double()
     hist = (C.c_double * iter_max)()
-    chist = (C.c_double * iter_max)()
+    chist = (C.c_double * iter_max)() if change_hist is not None else None   # measured only when asked for
     h.check(lib().taps_als(h.h, C.byref(prob), _ptr_array(U), tol, change_tol, iter_max, C.byref(sweeps),
-                           C.byref(rho), C.byref(chg), hist, chist, _stream(stream)), "taps_als")
+                           C.byref(rho), None, hist, chist, _stream(stream)), "taps_als")
     if change_hist is not None:
         change_hist.extend(chist[: sweeps.value])
     return sweeps.value, rho.value, list(hist[: sweeps.value])

@@ -70,22 +70,6 @@ __device__ inline Item locate(const int* __restrict__ act, const int* __restrict
   return Item{act[a], w - pref[a]};
 }
 
-// Workgroups are dealt to the 8 XCDs in turn (block b runs on XCD b % 8),
-// and each XCD has its own L2.  A persistent grid therefore renumbers its
-// blocks so that XCD x's blocks take the x-th contiguous eighth of the work
-// items, and each block a contiguous run of items: the items of one problem
-// (row blocks sharing its U, Wt, C, Q and bands) then stay on one XCD and
-// read those operands from HBM once instead of once per XCD.
-struct ItemRange {
-  int lo, hi;
-};
-__device__ inline ItemRange xcd_items(int nit) {
-  const int G = gridDim.x, b = blockIdx.x, G8 = G & ~7;
-  const int L = b < G8 ? (b & 7) * (G8 >> 3) + (b >> 3) : b;
-  const int per = (nit + G - 1) / G;
-  return ItemRange{min(nit, L * per), min(nit, (L + 1) * per)};
-}
-
 // owner tables of every (kind, dim): one thread per active problem fills
 // its items' entries (grid.y = kind * D + dim)
 struct OwnerOffsets {
@@ -104,8 +88,7 @@ __global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__
                                                        const int* __restrict__ pref, const int* __restrict__ owner,
                                                        int nact, int e) {
   const int nit = pref[nact];
-  const ItemRange ir = xcd_items(nit);
-  for (int w = ir.lo; w < ir.hi; ++w) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     gram_partial(x.c, q.n[e], q.M, q.s[e], q.K[e], q.band[e], q.U[e], q.gpart + long(x.c) * q.K[e] * q.M * q.M);
@@ -129,8 +112,7 @@ __global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict_
                                                         const int* __restrict__ pref, const int* __restrict__ owner,
                                                         int nact, int e, int rows) {
   const int nit = pref[nact];
-  const ItemRange ir = xcd_items(nit);
-  for (int w = ir.lo; w < ir.hi; ++w) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     const int splits = (q.n[e] + rows - 1) / rows;
@@ -196,8 +178,7 @@ __global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, con
                                                 const int* __restrict__ pref, const int* __restrict__ owner,
                                                 int nact, int d, int split) {
   const int nit = pref[nact];
-  const ItemRange ir = xcd_items(nit);
-  for (int w = ir.lo; w < ir.hi; ++w) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     if (!split) {
@@ -220,8 +201,7 @@ __global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict_
                                                         const int* __restrict__ pref, const int* __restrict__ owner,
                                                         int nact, int d) {
   const int nit = pref[nact];
-  const ItemRange ir = xcd_items(nit);
-  for (int w = ir.lo; w < ir.hi; ++w) {
+  for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     residual_part(x.c, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],

@@ -253,13 +253,15 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
   *sweeps = 0;
   *rho = NAN;
   if (change) *change = NAN;
+  // the change needs a copy of the factors per sweep: only when asked for
+  const bool want_change = change || change_history || change_tol > 0.0;
   for (int it = 0; it < iter_max; ++it) {
-    TAPS_TRY(sweep_impl(h, prob, d_U, d_inf, d_be, stream, d_chg));
+    TAPS_TRY(sweep_impl(h, prob, d_U, d_inf, d_be, stream, want_change ? d_chg : nullptr));
     TAPS_TRY(residual_impl(h, prob, d_U, d_res, stream));
     TAPS_HIP(h, hipMemcpyAsync(res, d_res, size_t(D + 2) * 8, hipMemcpyDeviceToHost, stream));
     TAPS_HIP(h, hipMemcpyAsync(be, d_be, size_t(D) * 8, hipMemcpyDeviceToHost, stream));
     TAPS_HIP(h, hipMemcpyAsync(&info, d_inf, 4, hipMemcpyDeviceToHost, stream));
-    TAPS_HIP(h, hipMemcpyAsync(&chg, d_chg, 8, hipMemcpyDeviceToHost, stream));
+    if (want_change) TAPS_HIP(h, hipMemcpyAsync(&chg, d_chg, 8, hipMemcpyDeviceToHost, stream));
     TAPS_HIP(h, hipStreamSynchronize(stream));
     *sweeps = it + 1;
     int bad = -1;
