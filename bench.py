@@ -153,9 +153,10 @@ def main():
     ap.add_argument("--batch", type=int, default=1024, help="slabs in flight, one workgroup each")
     ap.add_argument("--slabs", type=int, default=4096,
                     help="slabs solved per step (streamed through --batch slots)")
-    ap.add_argument("--train-chains", type=int, default=512)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-chains", type=int, default=4096)
+    ap.add_argument("--train-steps", type=int, default=12000)
     ap.add_argument("--Kc", type=int, default=8, help="modes of the carried initial condition")
+    ap.add_argument("--coarse", default="32,16,32", help="coarse nodes of the predicted y, z, t factors")
     ap.add_argument("--solver", choices=["fastdiag", "blocklu"], default="fastdiag",
                     help="dim solver: fast diagonalisation (complex Schur) or block LU")
     ap.add_argument("--floor-slabs", type=int, default=64)
@@ -209,7 +210,7 @@ def main():
                    for d in range(4)]
     del U0_host
     U_plain = ws.FactorBatch(U_plain_big)
-    layout = ws.Layout(h, cases[0], M)
+    layout = ws.Layout(h, cases[0], M, coarse=tuple(int(v) for v in args.coarse.split(",")))
     n_tr = args.train_chains
     tr_a = family(n_tr, args.seed + 101, **grid)
     tr_b = [W.replace(c, x_start=0.9) for c in family(n_tr, args.seed + 202, **grid)]
@@ -391,7 +392,7 @@ def main():
     n_c, ms_c, fl_c, by_c = prof["contract"]
     ratio_c = TRAFFIC.get("contract") if measured else None
     contract = {"bound": "hbm", "kernels": "kb_gram_partial/sum, kb_lgram_partial/sum, kb_couple, kb_load_terms, "
-                                            "kb_load_weights, kb_force",
+                                            "kb_load_weights(_fused)/kb_wsum, kb_force(/sum)",
                 "achieved": by_c / (ms_c * 1e-3) / 1e9 if n_c else 0.0, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "launch_groups": n_c, "ms_per_step": ms_c, "method_bytes_per_step": by_c,
                 "fp64_tflops": fl_c / (ms_c * 1e-3) / 1e12 if n_c else 0.0,
