@@ -23,6 +23,10 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# per source: the reconstruction's matrix-core accumulators in ordinary
+# vector registers (each AGPR result would otherwise be copied out by one
+# vector instruction per value before the epilogue uses it)
+EXTRA = {"taps_reconstruct_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -31,7 +35,8 @@ def build(verbose: bool = False) -> str:
     objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmds.append([hipcc, *[f for f in FLAGS if f != "-shared"], "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([hipcc, *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), "-c", os.path.join(CSRC, src),
+                     "-o", obj])
         objs.append(obj)
 
     def run(cmd):

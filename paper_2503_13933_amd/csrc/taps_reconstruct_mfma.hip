@@ -26,6 +26,7 @@
 // first element for every q, and indexing the 128-bit load result of a
 // generic vector type element by element made it load one word for all four;
 // whole-vector bit casts and named components avoid both.
+#include <type_traits>
 #include "taps_internal.hpp"
 
 #include <cmath>
@@ -90,19 +91,23 @@ __global__ void k_recon_convert(int n, int M, int Mp, const double* __restrict__
 struct Reduce {
   float mx;
   double ss;
-  unsigned int cnt;  // this lane's count, summed over the wave at the end
+  unsigned int cnt;  // the wave's count (the same in every lane: ballots counted on the scalar unit)
 };
 
 // Epilogue of one j tile.  The products are formed transposed (streamed
 // Phi_1 rows as the MFMA's first operand), so lane l holds, for row
 // i = ibase + 16 rt + l%16, the four consecutive columns j0 .. j0+3 with
 // j0 = 16 jt + 4 (l/16): one 16-byte store per lane and 16-row tile.  Store
-// the values, or fold them into the lane's {max, sum of squares,
-// count(u > thr)}; thrf is thr rounded down to FP32, so v > thrf exactly when
-// v > thr.  Tiles wholly inside the plane take the unpredicated path.
-template <int MODE>
+// the values, or fold them into {max, sum of squares, count(u > thr)}: the
+// maximum and the squares per lane (the squares of a tile's 16 values summed
+// in FP32, then added in FP64), the count per wave from ballots of the
+// compares, popcounted on the scalar unit; thrf is thr rounded down to FP32,
+// so v > thrf exactly when v > thr.  FULL (wave-uniform: a tile wholly inside
+// the plane) takes the unpredicated path.
+template <int MODE, bool FULL>
 __device__ inline void epilogue(const f32x4 (&acc)[4], int ibase, int c16, int j0, int n0, int n1, bool jfull,
-                                bool full, float thrf, Reduce& r, __amdgpu_buffer_rsrc_t ro) {
+                                float thrf, Reduce& r, __amdgpu_buffer_rsrc_t ro) {
+  float ss = 0.0f;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
     const float v[4] = {acc[rt].x, acc[rt].y, acc[rt].z, acc[rt].w};
@@ -119,26 +124,24 @@ __device__ inline void epilogue(const f32x4 (&acc)[4], int ibase, int c16, int j
         }
       }
     } else {
-      float ss = 0.0f;
-      if (full) {
+      // the same compare (and ballot) on both paths, so it is formed once
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 4; ++q) {
+        const unsigned long long gt = __ballot(v[q] > thrf);
+        if (FULL) {
           r.mx = fmaxf(r.mx, v[q]);
           ss = fmaf(v[q], v[q], ss);
-          r.cnt += (v[q] > thrf) ? 1u : 0u;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
+          r.cnt += __builtin_popcountll(gt);
+        } else {
           const bool ok = i < n0 && j0 + q < n1;
           r.mx = ok ? fmaxf(r.mx, v[q]) : r.mx;
           ss = ok ? fmaf(v[q], v[q], ss) : ss;
-          r.cnt += (ok && v[q] > thrf) ? 1u : 0u;
+          r.cnt += __builtin_popcountll(gt & __ballot(ok));
         }
       }
-      r.ss += double(ss);
     }
   }
+  if (MODE == TAPS_REDUCE) r.ss += double(ss);
 }
 
 // Workgroup reduction of {max, sum of squares, count} into one record.
@@ -147,7 +150,6 @@ __device__ void reduce_store(Reduce r, double* rec) {
   for (int off = 32; off > 0; off >>= 1) {
     r.mx = fmaxf(r.mx, __shfl_xor(r.mx, off));
     r.ss += __shfl_xor(r.ss, off);
-    r.cnt += __shfl_xor(r.cnt, off);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
@@ -239,7 +241,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int 
   };
   Reduce red{-INFINITY, 0.0, 0u};
   const bool rows_full = ibase + kRowsWave <= n0;
-  auto tile = [&](int jt, const bf16x8* b) {
+  // ALL: every tile of this wave lies inside the plane (its rows, and a
+  // multiple of 16 columns), so no tile needs the per-tile test
+  auto tile = [&](int jt, const bf16x8* b, auto all) {
     f32x4 acc[4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
@@ -249,28 +253,37 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int 
         acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks], __builtin_bit_cast(bf16x8, a[rt][ks]), acc[rt], 0, 0, 0);
     }
     const bool jfull = 16 * jt + 16 <= n1;
-    epilogue<MODE>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, rows_full && jfull, thrf, red, ro);
+    if (decltype(all)::value || (rows_full && jfull))
+      epilogue<MODE, true>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
+    else
+      epilogue<MODE, false>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
   };
   // four register sets in rotation: tile jt's operands were requested three
   // tiles earlier (an L2 round trip outlasts one tile's MFMA chain)
   const int ntj = (n1 + 15) / 16;
-  bf16x8 b0[KS], b1[KS], b2[KS], b3[KS];
-  bload(0, b0);
-  bload(1, b1);
-  bload(2, b2);
-  for (int jt = 0; jt < ntj; jt += 4) {
-    bload(jt + 3, b3);
-    tile(jt, b0);
-    if (jt + 1 >= ntj) break;
-    bload(jt + 4, b0);
-    tile(jt + 1, b1);
-    if (jt + 2 >= ntj) break;
-    bload(jt + 5, b1);
-    tile(jt + 2, b2);
-    if (jt + 3 >= ntj) break;
-    bload(jt + 6, b2);
-    tile(jt + 3, b3);
-  }
+  auto run = [&](auto all) {
+    bf16x8 b0[KS], b1[KS], b2[KS], b3[KS];
+    bload(0, b0);
+    bload(1, b1);
+    bload(2, b2);
+    for (int jt = 0; jt < ntj; jt += 4) {
+      bload(jt + 3, b3);
+      tile(jt, b0, all);
+      if (jt + 1 >= ntj) break;
+      bload(jt + 4, b0);
+      tile(jt + 1, b1, all);
+      if (jt + 2 >= ntj) break;
+      bload(jt + 5, b1);
+      tile(jt + 2, b2, all);
+      if (jt + 3 >= ntj) break;
+      bload(jt + 6, b2);
+      tile(jt + 3, b3, all);
+    }
+  };
+  if (rows_full && n1 % 16 == 0)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
   if (MODE == TAPS_REDUCE) reduce_store(red, rec + (long(k) * nrb + rb) * 4);
 }
 
@@ -331,7 +344,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int 
   };
   Reduce red{-INFINITY, 0.0, 0u};
   const bool rows_full = ibase + kRowsWave <= n0;
-  auto tile = [&](int jt, const float* b) {
+  // ALL: every tile of this wave inside the plane (as in the BF16 kernel)
+  auto tile = [&](int jt, const float* b, auto all) {
     f32x4 acc[4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
@@ -340,18 +354,27 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int 
       for (int q = 0; q < S; ++q) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[q], a[rt][q], acc[rt], 0, 0, 0);
     }
     const bool jfull = 16 * jt + 16 <= n1;
-    epilogue<MODE>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, rows_full && jfull, thrf, red, ro);
+    if (decltype(all)::value || (rows_full && jfull))
+      epilogue<MODE, true>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
+    else
+      epilogue<MODE, false>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
   };
   const int ntj = (n1 + 15) / 16;
-  float bA[S], bB[S];
-  bload(0, bA);
-  for (int jt = 0; jt < ntj; jt += 2) {
-    bload(jt + 1, bB);
-    tile(jt, bA);
-    if (jt + 1 >= ntj) break;
-    bload(jt + 2, bA);
-    tile(jt + 1, bB);
-  }
+  auto run = [&](auto all) {
+    float bA[S], bB[S];
+    bload(0, bA);
+    for (int jt = 0; jt < ntj; jt += 2) {
+      bload(jt + 1, bB);
+      tile(jt, bA, all);
+      if (jt + 1 >= ntj) break;
+      bload(jt + 2, bA);
+      tile(jt + 1, bB, all);
+    }
+  };
+  if (rows_full && n1 % 16 == 0)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
   if (MODE == TAPS_REDUCE) reduce_store(red, rec + (long(k) * nrb + rb) * 4);
 }
 
