@@ -13,9 +13,15 @@
 //         accumulated in FP32 by v_mfma_f32_16x16x32_bf16.
 //   FP32: the same in FP32 throughout (v_mfma_f32_16x16x4_f32).
 //
-// Workgroup = 4 waves = 256 rows of i for one plane; each wave owns 64 rows
-// (four 16-row tiles, scaled Phi_0 operands in registers) and walks the j
-// tiles of 16 columns, Phi_1 operands loaded one tile ahead.  Lanes with no row or
+// Workgroup = 4 waves for one plane.  BF16: 512 rows of i, each wave owning
+// 128 rows (eight 16-row tiles, scaled Phi_0 operands in registers); FP32: 256
+// rows, four tiles per wave.  Each wave walks the j tiles of 16 columns, Phi_1
+// operands loaded three tiles ahead.  The BF16 Phi_1 is staged tile-ordered:
+// for each 16-column tile and 32-mode step, the 64 lanes' 16-byte operands lie
+// contiguously, so one load instruction reads 1 KB in 8 whole cache lines (the
+// row-major layout touches 16 lines, half of each, and its loads bounded the
+// kernel well below the matrix cores' rate); eight row tiles per wave halve
+// the operand bytes per product against four.  Lanes with no row or
 // column load and store through buffer resources with out-of-range offsets,
 // which the address unit turns into zeros and dropped stores.
 //
@@ -46,9 +52,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((__vector_size__(16)));
 
 constexpr int kWaves = 4;
-constexpr int kRowsWave = 64;
-constexpr int kRowsWG = kWaves * kRowsWave;
+constexpr int kTilesF32 = 4;   // 16-row tiles per wave, FP32 kernel
+constexpr int kTilesBF16 = 8;  // 16-row tiles per wave, BF16 kernel
 constexpr int kOOB = 0x7ffffff0;
+
+// rows of i per workgroup
+constexpr int rows_wg(bool bf) { return kWaves * 16 * (bf ? kTilesBF16 : kTilesF32); }
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, long bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
@@ -88,60 +97,75 @@ __global__ void k_recon_convert(int n, int M, int Mp, const double* __restrict__
   out[idx] = T(v);
 }
 
+// FP64 factor (n x M) -> BF16 in the tile order of k_recon_bf16's streamed
+// operand: element e of lane l of (tile jt, step ks) at ((jt KS + ks) 64 + l) 8 + e
+// holds row 16 jt + l%16, mode 32 ks + 8 (l/16) + e; rows past n and modes
+// past M are zero.  ntj = ceil(n / 16) tiles, KS = Mp / 32 steps.
+__global__ void k_recon_convert_tiled(int n, int M, int KS, const double* __restrict__ P, __bf16* __restrict__ out,
+                                      const ConvJob* __restrict__ tab) {
+  if (tab) {
+    P = tab[blockIdx.y].P;
+    out = static_cast<__bf16*>(tab[blockIdx.y].out);
+  }
+  const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long ntj = (n + 15) / 16;
+  if (idx >= ntj * KS * 512) return;
+  const int e = int(idx & 7), l = int((idx >> 3) & 63);
+  const long t = idx >> 9;  // jt KS + ks
+  const int ks = int(t % KS), jt = int(t / KS);
+  const int j = 16 * jt + (l & 15), m = 32 * ks + 8 * (l >> 4) + e;
+  const float v = (j < n && m < M) ? float(P[long(j) * M + m]) : 0.0f;
+  out[idx] = __bf16(v);
+}
+
 struct Reduce {
   float mx;
   double ss;
   unsigned int cnt;  // the wave's count (the same in every lane: ballots counted on the scalar unit)
 };
 
-// Epilogue of one j tile.  The products are formed transposed (streamed
-// Phi_1 rows as the MFMA's first operand), so lane l holds, for row
-// i = ibase + 16 rt + l%16, the four consecutive columns j0 .. j0+3 with
-// j0 = 16 jt + 4 (l/16): one 16-byte store per lane and 16-row tile.  Store
-// the values, or fold them into {max, sum of squares, count(u > thr)}: the
-// maximum and the squares per lane (the squares of a tile's 16 values summed
-// in FP32, then added in FP64), the count per wave from ballots of the
-// compares, popcounted on the scalar unit; thrf is thr rounded down to FP32,
-// so v > thrf exactly when v > thr.  FULL (wave-uniform: a tile wholly inside
-// the plane) takes the unpredicated path.
+// Epilogue of one 16 x 16 tile of the products.  They are formed transposed
+// (streamed Phi_1 rows as the MFMA's first operand), so lane l holds, for row
+// i = (tile's first row) + l%16, the four consecutive columns j0 .. j0+3 with
+// j0 = 16 jt + 4 (l/16): one 16-byte store per lane.  Store the values, or
+// fold them into {max, sum of squares, count(u > thr)}: the maximum and the
+// squares per lane (ss: the squares of a j tile's values summed in FP32,
+// added to r.ss in FP64 by the caller), the count per wave from ballots of
+// the compares, popcounted on the scalar unit; thrf is thr rounded down to
+// FP32, so v > thrf exactly when v > thr.  FULL (wave-uniform: a tile wholly
+// inside the plane) takes the unpredicated path.
 template <int MODE, bool FULL>
-__device__ inline void epilogue(const f32x4 (&acc)[4], int ibase, int c16, int j0, int n0, int n1, bool jfull,
-                                float thrf, Reduce& r, __amdgpu_buffer_rsrc_t ro) {
-  float ss = 0.0f;
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
-    const float v[4] = {acc[rt].x, acc[rt].y, acc[rt].z, acc[rt].w};
-    const int i = ibase + 16 * rt + c16;
-    if (MODE == TAPS_STORE) {
-      if (jfull) {
-        const int off = (i < n0) ? (i * n1 + j0) * 4 : kOOB;
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[rt]), ro, off, 0, 0);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int off = (i < n0 && j0 + q < n1) ? (i * n1 + j0 + q) * 4 : kOOB;
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), ro, off, 0, 0);
-        }
-      }
+__device__ inline void epilogue(const f32x4& acc, int i, int j0, int n0, int n1, bool jfull, float thrf, Reduce& r,
+                                float& ss, __amdgpu_buffer_rsrc_t ro) {
+  const float v[4] = {acc.x, acc.y, acc.z, acc.w};
+  if (MODE == TAPS_STORE) {
+    if (jfull) {
+      const int off = (i < n0) ? (i * n1 + j0) * 4 : kOOB;
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc), ro, off, 0, 0);
     } else {
-      // the same compare (and ballot) on both paths, so it is formed once
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const unsigned long long gt = __ballot(v[q] > thrf);
-        if (FULL) {
-          r.mx = fmaxf(r.mx, v[q]);
-          ss = fmaf(v[q], v[q], ss);
-          r.cnt += __builtin_popcountll(gt);
-        } else {
-          const bool ok = i < n0 && j0 + q < n1;
-          r.mx = ok ? fmaxf(r.mx, v[q]) : r.mx;
-          ss = ok ? fmaf(v[q], v[q], ss) : ss;
-          r.cnt += __builtin_popcountll(gt & __ballot(ok));
-        }
+        const int off = (i < n0 && j0 + q < n1) ? (i * n1 + j0 + q) * 4 : kOOB;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), ro, off, 0, 0);
+      }
+    }
+  } else {
+    // the same compare (and ballot) on both paths, so it is formed once
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const unsigned long long gt = __ballot(v[q] > thrf);
+      if (FULL) {
+        r.mx = fmaxf(r.mx, v[q]);
+        ss = fmaf(v[q], v[q], ss);
+        r.cnt += __builtin_popcountll(gt);
+      } else {
+        const bool ok = i < n0 && j0 + q < n1;
+        r.mx = ok ? fmaxf(r.mx, v[q]) : r.mx;
+        ss = ok ? fmaf(v[q], v[q], ss) : ss;
+        r.cnt += __builtin_popcountll(gt & __ballot(ok));
       }
     }
   }
-  if (MODE == TAPS_REDUCE) r.ss += double(ss);
 }
 
 // Workgroup reduction of {max, sum of squares, count} into one record.
@@ -180,34 +204,35 @@ __device__ void plane_scale(float* s, int k, int M, int Mp, const double* P2, co
 }
 
 // BF16 x BF16 -> FP32.  KS = Mp / 32 inner steps of 32 modes; lane group
-// g = l/16 of step ks covers modes 32 ks + 8 g + (0..7).
+// g = l/16 of step ks covers modes 32 ks + 8 g + (0..7).  P1t is Phi_1 in
+// the tile order of k_recon_convert_tiled.
 template <int KS, int MODE>
 __global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int nrb, int M, const float* __restrict__ P0f,
-                                                            const __bf16* __restrict__ P1b, const double* __restrict__ P2,
+                                                            const __bf16* __restrict__ P1t, const double* __restrict__ P2,
                                                             const double* __restrict__ mw, float thrf, float* __restrict__ out,
                                                             double* __restrict__ rec, const ReconJob* __restrict__ tab) {
   if (tab) {
     const ReconJob& J = tab[blockIdx.y];
     P0f = J.P0f;
-    P1b = static_cast<const __bf16*>(J.P1);
+    P1t = static_cast<const __bf16*>(J.P1);
     P2 = J.P2;
     mw = J.mw;
     out = J.out;
     rec = J.rec;
   }
-  constexpr int Mp = 32 * KS;
+  constexpr int Mp = 32 * KS, RT = kTilesBF16;
   __shared__ __align__(16) float s[Mp];
   const int k = blockIdx.x / nrb, rb = blockIdx.x - k * nrb;
   const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile tests branch on the scalar unit
   plane_scale(s, k, M, Mp, P2, mw);
-  const int ibase = rb * kRowsWG + wave * kRowsWave;
+  const int ibase = rb * rows_wg(true) + wave * 16 * RT;
   // scaled operands a'[i][m] = bf16(P0f[i][m] * s[m]), kept as packed words
   // (held as eight separate halves they were re-packed at every use)
   // (rows past n0 read row n0-1 and are zeroed: no load is predicated)
-  u32x4 a[4][KS];
+  u32x4 a[RT][KS];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
+  for (int rt = 0; rt < RT; ++rt) {
     const int i = ibase + 16 * rt + c16;
     const f32x4* row = reinterpret_cast<const f32x4*>(P0f + long(min(i, n0 - 1)) * Mp);
     const float keep = (i < n0) ? 1.0f : 0.0f;
@@ -228,39 +253,41 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int 
       a[rt][ks] = __builtin_bit_cast(u32x4, v);
     }
   }
-  const __amdgpu_buffer_rsrc_t rb1 = make_rsrc(P1b, long(n1) * Mp * 2);
+  const int ntj = (n1 + 15) / 16;
+  const __amdgpu_buffer_rsrc_t rb1 = make_rsrc(P1t, long(ntj) * 16 * Mp * 2);
   const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + (MODE == TAPS_STORE ? long(k) * n0 * n1 : 0),
                                               MODE == TAPS_STORE ? long(n0) * n1 * 4 : 0);
   auto bload = [&](int jt, bf16x8* b) {
-    const int j = 16 * jt + c16;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int off = (j < n1) ? (j * Mp + 32 * ks + 8 * g) * 2 : kOOB;
+      const int off = (jt < ntj) ? ((jt * KS + ks) * 64 + lane) * 16 : kOOB;
       b[ks] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb1, off, 0, 0));
     }
   };
   Reduce red{-INFINITY, 0.0, 0u};
-  const bool rows_full = ibase + kRowsWave <= n0;
+  const bool rows_full = ibase + 16 * RT <= n0;
   // ALL: every tile of this wave lies inside the plane (its rows, and a
   // multiple of 16 columns), so no tile needs the per-tile test
   auto tile = [&](int jt, const bf16x8* b, auto all) {
-    f32x4 acc[4];
+    const bool jfull = 16 * jt + 16 <= n1;
+    const bool full = decltype(all)::value || (rows_full && jfull);
+    float ss = 0.0f;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      acc[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int rt = 0; rt < RT; ++rt) {
+      f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
-        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks], __builtin_bit_cast(bf16x8, a[rt][ks]), acc[rt], 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks], __builtin_bit_cast(bf16x8, a[rt][ks]), acc, 0, 0, 0);
+      const int i = ibase + 16 * rt + c16;
+      if (full)
+        epilogue<MODE, true>(acc, i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
+      else
+        epilogue<MODE, false>(acc, i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
     }
-    const bool jfull = 16 * jt + 16 <= n1;
-    if (decltype(all)::value || (rows_full && jfull))
-      epilogue<MODE, true>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
-    else
-      epilogue<MODE, false>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
+    if (MODE == TAPS_REDUCE) red.ss += double(ss);
   };
   // four register sets in rotation: tile jt's operands were requested three
   // tiles earlier (an L2 round trip outlasts one tile's MFMA chain)
-  const int ntj = (n1 + 15) / 16;
   auto run = [&](auto all) {
     bf16x8 b0[KS], b1[KS], b2[KS], b3[KS];
     bload(0, b0);
@@ -309,7 +336,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int 
   const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile tests branch on the scalar unit
   plane_scale(s, k, M, Mp, P2, mw);
-  const int ibase = rb * kRowsWG + wave * kRowsWave;
+  const int ibase = rb * rows_wg(false) + wave * 16 * kTilesF32;
   // (rows past n0 read row n0-1 and are zeroed: no load is predicated)
   float a[4][S];
 #pragma unroll
@@ -343,7 +370,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int 
     }
   };
   Reduce red{-INFINITY, 0.0, 0u};
-  const bool rows_full = ibase + kRowsWave <= n0;
+  const bool rows_full = ibase + 16 * kTilesF32 <= n0;
   // ALL: every tile of this wave inside the plane (as in the BF16 kernel)
   auto tile = [&](int jt, const float* b, auto all) {
     f32x4 acc[4];
@@ -354,10 +381,17 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_fp32(int n0, int n1, int 
       for (int q = 0; q < S; ++q) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[q], a[rt][q], acc[rt], 0, 0, 0);
     }
     const bool jfull = 16 * jt + 16 <= n1;
-    if (decltype(all)::value || (rows_full && jfull))
-      epilogue<MODE, true>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
-    else
-      epilogue<MODE, false>(acc, ibase, c16, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ro);
+    const bool full = decltype(all)::value || (rows_full && jfull);
+    float ss = 0.0f;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int i = ibase + 16 * rt + c16;
+      if (full)
+        epilogue<MODE, true>(acc[rt], i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
+      else
+        epilogue<MODE, false>(acc[rt], i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
+    }
+    if (MODE == TAPS_REDUCE) red.ss += double(ss);
   };
   const int ntj = (n1 + 15) / 16;
   auto run = [&](auto all) {
@@ -441,12 +475,12 @@ taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts,
   const int Mp = bf ? 32 * cdiv(M, 32) : 16 * cdiv(M, 16);
   if (long(n0) * n1 * 4 >= (1L << 31) || long(n1) * Mp * 4 >= (1L << 31))
     return fail(h, TAPS_ERR_UNSUPPORTED, "plane %d x %d too large for 32-bit offsets", n0, n1);
-  const int nrb = cdiv(n0, kRowsWG);
+  const int nrb = cdiv(n0, rows_wg(bf));
   if (long(nrb) * n2 >= (1L << 31)) return fail(h, TAPS_ERR_UNSUPPORTED, "grid too large");
   if (B > 65535) return fail(h, TAPS_ERR_UNSUPPORTED, "%d fields in one call (max 65535)", B);
   const bool st = (mode == TAPS_STORE);
   Bump bump;
-  const size_t s_P0 = size_t(n0) * Mp * 4, s_P1 = size_t(n1) * Mp * (bf ? 2 : 4);
+  const size_t s_P0 = size_t(n0) * Mp * 4, s_P1 = bf ? size_t(cdiv(n1, 16)) * 16 * Mp * 2 : size_t(n1) * Mp * 4;
   const size_t s_R = st ? 0 : size_t(n2) * nrb * 4 * 8;
   std::vector<size_t> o_P0(B), o_P1(B), o_R(B);
   for (int b = 0; b < B; ++b) {
@@ -492,7 +526,8 @@ taps_status reconstruct_mfma_fields(taps_handle* h, int B, const int32_t* n_pts,
   k_recon_convert<float><<<g0, 256, 0, stream>>>(n0, M, Mp, d_Phi[0], P0f(0), t_c0);
   TAPS_LAUNCHED(h, "k_recon_convert");
   if (bf)
-    k_recon_convert<__bf16><<<g1, 256, 0, stream>>>(n1, M, Mp, d_Phi[1], static_cast<__bf16*>(P1(0)), t_c1);
+    k_recon_convert_tiled<<<dim3(cdiv(long(cdiv(n1, 16)) * 16 * Mp, 256), B), 256, 0, stream>>>(
+        n1, M, Mp / 32, d_Phi[1], static_cast<__bf16*>(P1(0)), t_c1);
   else
     k_recon_convert<float><<<g1, 256, 0, stream>>>(n1, M, Mp, d_Phi[1], static_cast<float*>(P1(0)), t_c1);
   TAPS_LAUNCHED(h, "k_recon_convert");

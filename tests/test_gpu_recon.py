@@ -77,6 +77,7 @@ CASES = [  # (n0, n1, n2, M): ragged row blocks and column tiles, all paddings
     (5, 3, 4, 1),
     (1, 1, 1, 7),
     (512, 130, 2, 33),
+    (1030, 64, 2, 60),
 ]
 
 
