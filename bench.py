@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--M", type=int, default=40)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=3, help="plain sweep budget that sets the target residual")
+    ap.add_argument("--target-sweeps", type=int, default=3,
+                    help="plain sweeps behind the warm-start network's training targets (at least --sweeps)")
     ap.add_argument("--batch", type=int, default=1024, help="slabs in flight, one workgroup each")
     ap.add_argument("--slabs", type=int, default=4096,
                     help="slabs solved per step (streamed through --batch slots)")
@@ -214,7 +216,8 @@ def main():
     n_tr = args.train_chains
     tr_a = family(n_tr, args.seed + 101, **grid)
     tr_b = [W.replace(c, x_start=0.9) for c in family(n_tr, args.seed + 202, **grid)]
-    data = ws.make_chains(h, tr_a, tr_b, M, args.Kc, args.sweeps, 4, 1000 + args.seed, layout)
+    data = ws.make_chains(h, tr_a, tr_b, M, args.Kc, max(args.sweeps, args.target_sweeps), 4, 1000 + args.seed,
+                          layout)
     hist = data["hist"][:, :n_tr]          # first slabs of the chains: zero initial condition, like the batch
     rho_star = float(np.nanmedian(hist[args.sweeps - 1]))
     med1 = float(np.nanmedian(hist[0]))

@@ -22,6 +22,8 @@ inline int gram_lds_doubles(int M, int s) {
 // v_mfma_f64_16x16x4f64 operands of lane l: A[l%16][l/16], B[l/16][l%16];
 // result D[l/16 + 4j][l%16], j = 0..3.
 typedef double rv4d __attribute__((ext_vector_type(4)));
+// two doubles at an 8-byte-aligned address (one 16-byte load)
+typedef double f64x2u __attribute__((ext_vector_type(2), aligned(8)));
 __device__ inline rv4d mfma_f64(double a, double b, rv4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -392,7 +394,11 @@ __device__ inline void load_weights_fused(int c, int s, int wsl, const WeightArg
 // Q = F_d Wt for rows [rblock*kQRows, +kQRows) on the matrix cores: wave v
 // owns rows [16v, 16v+16) of the block, the load columns are the contracted
 // index (passes of 16 columns in four steps, operands loaded together), and
-// the M columns are covered in passes of up to four 16-wide tiles.
+// the M columns are covered in passes of up to four 16-wide tiles.  In a pass
+// from column c0, lane group g = l/16 takes columns c0 + 4g .. c0 + 4g + 3, one
+// per step (the Wt rows follow the same assignment), so each lane reads its
+// four F entries as two 16-byte loads: 64 contiguous bytes of four rows' lines
+// per instruction pair instead of four loads of 8 bytes per row.
 // (load columns [c_lo, c_hi) only: the batched driver splits long load
 // rows over several work items and sums their partial Q afterwards)
 __device__ inline void force(int rblock, int n, int Rc, int M, const double* __restrict__ F_,
@@ -414,15 +420,25 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
     // the next pass's requested before this pass's products
     const int c_end = min(Rc, c_hi);
     auto load = [&](int c0, double (&a)[4], double (&b)[4][4]) {
+      const int kb = c0 + 4 * (lane >> 4);
+      if (ia < n && kb + 3 < c_end) {
+        const gmem<f64x2u>* p = reinterpret_cast<const gmem<f64x2u>*>(F + long(ia) * Rc + kb);
+        const f64x2u lo = p[0], hi = p[1];
+        a[0] = lo.x;
+        a[1] = lo.y;
+        a[2] = hi.x;
+        a[3] = hi.y;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = (ia < n && kb + u < c_end) ? F[long(ia) * Rc + kb + u] : 0.0;
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int kc = c0 + 4 * u + (lane >> 4);
-        const bool ok = kc < c_end;
-        a[u] = (ok && ia < n) ? F[long(ia) * Rc + kc] : 0.0;
+        const bool ok = kb + u < c_end;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int m = (ct0 + c) * 16 + (lane & 15);
-          b[u][c] = (ok && ct0 + c < nct && m < M) ? Wt[long(kc) * M + m] : 0.0;
+          b[u][c] = (ok && ct0 + c < nct && m < M) ? Wt[long(kb + u) * M + m] : 0.0;
         }
       }
     };
