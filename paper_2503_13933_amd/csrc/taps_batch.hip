@@ -84,7 +84,8 @@ __global__ void kb_owner_fill(const int* __restrict__ pref, int* __restrict__ ow
     for (int w = pr[a]; w < pr[a + 1]; ++w) ow[w] = a;
 }
 
-__global__ __launch_bounds__(256) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
+// (at most 168 registers: three workgroups per CU, as many as its LDS allows)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
                                                        const int* __restrict__ pref, const int* __restrict__ owner,
                                                        int nact, int e) {
   const int nit = pref[nact];
@@ -174,7 +175,7 @@ __global__ void kb_wsum(const BProb* __restrict__ P, const WeightArgs* __restric
 // split = 0: item = row block, Q written directly; split = 1: item = (row
 // block, column range of kForceCols), partial Q per range, summed by
 // kb_force_sum
-__global__ __launch_bounds__(256) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act,
                                                 const int* __restrict__ pref, const int* __restrict__ owner,
                                                 int nact, int d, int split) {
   const int nit = pref[nact];

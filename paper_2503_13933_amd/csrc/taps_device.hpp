@@ -187,9 +187,9 @@ __device__ inline void lgram_partial(int ctile, int split, int rows, int n, int 
     rv4d acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
-    // 16 rows per pass, all operands loaded before the four steps
-    for (int i0 = rbeg; i0 < rend; i0 += 16) {
-      double a[4], b[4][4];
+    // 16 rows per pass, all operands of a pass loaded together and the next
+    // pass's requested before this pass's products
+    auto load = [&](int i0, double (&a)[4], double (&b)[4][4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int i = i0 + 4 * u + (lane >> 4);
@@ -201,6 +201,18 @@ __device__ inline void lgram_partial(int ctile, int split, int rows, int n, int 
           b[u][c] = (ok && ct0 + c < nct && m < M) ? U[long(i) * M + m] : 0.0;
         }
       }
+    };
+    double an[4], bn[4][4];
+    if (rbeg < rend) load(rbeg, an, bn);
+    for (int i0 = rbeg; i0 < rend; i0 += 16) {
+      double a[4], b[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = an[u];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[u][c] = bn[u][c];
+      }
+      if (i0 + 16 < rend) load(i0 + 16, an, bn);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
@@ -442,23 +454,38 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
         }
       }
     };
-    double an[4], bn[4][4];
-    load(c_lo, an, bn);
-    for (int c0 = c_lo; c0 < c_end; c0 += 16) {
-      double a[4], b[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = an[u];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[u][c] = bn[u][c];
-      }
-      if (c0 + 16 < c_end) load(c0 + 16, an, bn);
+    // two passes in flight: pass p's products are formed after pass p+2's
+    // loads were issued (buffers A and B in turn)
+    auto mma = [&](const double (&a)[4], const double (&b)[4][4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           if (ct0 + c < nct) acc[c] = mfma_f64(a[u], b[u][c], acc[c]);   // guard, not exit: stays unrolled
       }
+    };
+    double aA[4], bA[4][4], aB[4], bB[4][4];
+    load(c_lo, aA, bA);
+    if (c_lo + 16 < c_end) load(c_lo + 16, aB, bB);
+    for (int c0 = c_lo; c0 < c_end; c0 += 32) {
+      double a[4], b[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = aA[u];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[u][c] = bA[u][c];
+      }
+      if (c0 + 32 < c_end) load(c0 + 32, aA, bA);
+      mma(a, b);
+      if (c0 + 16 >= c_end) break;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = aB[u];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[u][c] = bB[u][c];
+      }
+      if (c0 + 48 < c_end) load(c0 + 48, aB, bB);
+      mma(a, b);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
