@@ -1497,7 +1497,26 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
   }
 }
 
+// dst[t] = (src[2t], src[2t+1]) for t < n, by nt threads with sixteen loads in flight each
+__device__ inline void stage_cplx(cplx* dst, const gmem<double>* src, int n, int tid, int nt) {
+  constexpr int kU = 16;
+  for (int t0 = tid; t0 < n; t0 += nt * kU) {
+    double re[kU], im[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = min(t0 + nt * u, n - 1);
+      re[u] = src[2 * t];
+      im[u] = src[2 * t + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (t0 + nt * u < n) dst[t0 + nt * u] = cmk(re[u], im[u]);
+  }
+}
 constexpr int kFdThreads = 64;   // one wave: transforms, staging and elimination
+// the register-window back substitution forms X itself (its H3 operands held
+// in registers) up to the 48-mode layout
+template <int MAXM> constexpr bool kFuseOut = MAXM <= 48;
 
 // Banded complex solves (A1 + lambda_m A2) y_m = r_m of the fast
 // diagonalisation with the elimination window in registers: lane m owns
@@ -1515,7 +1534,7 @@ constexpr int kFdThreads = 64;   // one wave: transforms, staging and eliminatio
 // guards.  No pivoting: a zero pivot sets the info word.  One 64-lane wave
 // per system set: the elimination is bound by its own instruction stream and
 // the U stores, so one wave per SIMD is the useful occupancy.
-template <int W>
+template <int MAXM, int W>
 __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLam, double2* ring, int* s_info) {
   constexpr int W1 = W + 1, BW = 2 * W + 1, CH = W1 * (32 / W1);
   constexpr int SPL = (CH * BW + 63) / 64;   // staged entries per lane and chunk
@@ -1627,12 +1646,74 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
     __syncthreads();
   }
   if (act && info) atomicCAS(s_info, 0, info);
+  if constexpr (kFuseOut<MAXM>) {
   // ---- back substitution: y_k = yhat_k - sum_c U[k][c] y_{k+c} (row k
-  // already divided by its pivot);
-  // the U rows and reduced right-hand sides are loaded PF rows ahead (a ring
-  // of PF row buffers, PF dividing w+1, so slots stay static in the unrolled
-  // groups)
-  if (act) {
+  // already divided by its pivot), fused with the transform out: the rows of
+  // y go to a ring of two 16-row tiles in LDS (the band ring is dead by now)
+  // and each completed tile becomes 16 rows of X = Re(Y H3) on the matrix
+  // cores, so y never returns to global memory.  The U rows and reduced
+  // right-hand sides are loaded PF rows ahead (a ring of PF row buffers, PF
+  // dividing w+1, so slots stay static in the unrolled groups).  Lanes past M
+  // follow mode M-1 without storing: the tile products need the whole wave.
+  const int MM = M * M;
+  cplx* sH = reinterpret_cast<cplx*>(ring);
+  stage_cplx(sH, f.H3, MM, tid, 64);
+  __syncthreads();
+  constexpr int kKS = MAXM / 4, kCT = (MAXM + 15) / 16;
+  const int lane = tid, nct = (M + 15) / 16, ksteps = (M + 3) / 4;
+  double hr[kCT][kKS], hi[kCT][kKS];
+#pragma unroll
+  for (int c = 0; c < kCT; ++c) {
+    const int mb = c * 16 + (lane & 15);
+#pragma unroll
+    for (int u = 0; u < kKS; ++u) {
+      const int q = 4 * u + (lane >> 4);
+      const cplx hb = (u < ksteps && c < nct && q < M && mb < M) ? sH[q * M + mb] : cmk(0.0, 0.0);
+      hr[c][u] = hb.r;
+      hi[c][u] = hb.i;
+    }
+  }
+  __syncthreads();
+  cplx* ytile = sH;   // [2][16][M]
+  const auto Xg = gp(A.X);
+  auto flush = [&](int t) {   // rows 16t .. 16t+15 of X from tile slot t & 1
+    const cplx* yt = ytile + (t & 1) * 16 * M;
+    const int ia = t * 16 + (lane & 15);
+    const bool row_ok = ia < n && !is_fixed(A, ia);
+    double yr[kKS], yi[kKS];
+#pragma unroll
+    for (int u = 0; u < kKS; ++u) {
+      const int mm = 4 * u + (lane >> 4);
+      const cplx v = (row_ok && u < ksteps && mm < M) ? yt[(lane & 15) * M + mm] : cmk(0.0, 0.0);
+      yr[u] = v.r;
+      yi[u] = -v.i;
+    }
+    v4d ar[kCT], ai[kCT];
+#pragma unroll
+    for (int c = 0; c < kCT; ++c) ar[c] = ai[c] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < kKS; ++u) {
+#pragma unroll
+      for (int c = 0; c < kCT; ++c) {
+        if (u < ksteps && c < nct) {   // (guards, not loop exits: the loops stay fully unrolled)
+          ar[c] = mfma16x16x4(yr[u], hr[c][u], ar[c]);
+          ai[c] = mfma16x16x4(yi[u], hi[c][u], ai[c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kCT; ++c) {
+      const int qb = c * 16 + (lane & 15);
+      const v4d x = ar[c] + ai[c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = t * 16 + (lane >> 4) + 4 * j;
+        if (c < nct && i < n && qb < M) Xg[long(i) * M + qb] = x[j];
+      }
+    }
+  };
+  {
+    const int me = act ? m : M - 1;
     constexpr int PF = W1 / 2 > 0 ? W1 / 2 : 1;
     static_assert(W1 % PF == 0, "prefetch ring must divide the group");
     cplx ub[PF][W], yh[PF], yw[W1];
@@ -1646,12 +1727,13 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
         for (int q = 0; q < PF; ++q)
           if (k % PF == q) {
 #pragma unroll
-            for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k) * W + cc) * M + m];
-            yh[q] = Yg[long(k) * M + m];
+            for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k) * W + cc) * M + me];
+            yh[q] = Yg[long(k) * M + me];
           }
       }
     }
     const int gtop = (n - 1) / W1;
+    int tp = (n - 1) >> 4;   // the highest tile not yet turned into X
     for (int g = gtop; g >= 0; --g) {
 #pragma unroll
       for (int p = W1 - 1; p >= 0; --p) {
@@ -1663,11 +1745,61 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
           for (int cc = 1; cc < W1; ++cc) acc = cfms(acc, ub[q][cc - 1], yw[(p + cc) % W1]);
           const cplx y = acc;
           yw[p] = y;
-          Yg[long(k) * M + m] = y;
+          if (act) ytile[(((k >> 4) & 1) * 16 + (k & 15)) * M + m] = y;
           if (k - PF >= 0) {
 #pragma unroll
-            for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k - PF) * W + cc) * M + m];
-            yh[q] = Yg[long(k - PF) * M + m];
+            for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k - PF) * W + cc) * M + me];
+            yh[q] = Yg[long(k - PF) * M + me];
+          }
+        }
+      }
+      // every row from g W1 up is done: tiles starting at or above it are complete
+      while (tp >= 0 && 16 * tp >= g * W1) {
+        wave_sync();
+        flush(tp);
+        --tp;
+      }
+    }
+  }
+  } else {
+    // (64-mode layout: y back to global memory, transformed afterwards)
+    if (act) {
+      constexpr int PF = W1 / 2 > 0 ? W1 / 2 : 1;
+      static_assert(W1 % PF == 0, "prefetch ring must divide the group");
+      cplx ub[PF][W], yh[PF], yw[W1];
+#pragma unroll
+      for (int p = 0; p < W1; ++p) yw[p] = cmk(0.0, 0.0);
+#pragma unroll
+      for (int j = 1; j <= PF; ++j) {
+        const int k = n - j;
+        if (k >= 0) {
+#pragma unroll
+          for (int q = 0; q < PF; ++q)
+            if (k % PF == q) {
+#pragma unroll
+              for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k) * W + cc) * M + m];
+              yh[q] = Yg[long(k) * M + m];
+            }
+        }
+      }
+      const int gtop = (n - 1) / W1;
+      for (int g = gtop; g >= 0; --g) {
+#pragma unroll
+        for (int p = W1 - 1; p >= 0; --p) {
+          const int k = g * W1 + p;
+          if (k < n) {
+            const int q = p % PF;
+            cplx acc = yh[q];
+#pragma unroll
+            for (int cc = 1; cc < W1; ++cc) acc = cfms(acc, ub[q][cc - 1], yw[(p + cc) % W1]);
+            const cplx y = acc;
+            yw[p] = y;
+            Yg[long(k) * M + m] = y;
+            if (k - PF >= 0) {
+#pragma unroll
+              for (int cc = 0; cc < W; ++cc) ub[q][cc] = Ug[(long(k - PF) * W + cc) * M + m];
+              yh[q] = Yg[long(k - PF) * M + m];
+            }
           }
         }
       }
@@ -1675,22 +1807,6 @@ __device__ void fd_banded_reg(const SolveArgs& A, const FdWs& f, const cplx* sLa
   }
 }
 
-// dst[t] = (src[2t], src[2t+1]) for t < n, by nt threads with sixteen loads in flight each
-__device__ inline void stage_cplx(cplx* dst, const gmem<double>* src, int n, int tid, int nt) {
-  constexpr int kU = 16;
-  for (int t0 = tid; t0 < n; t0 += nt * kU) {
-    double re[kU], im[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int t = min(t0 + nt * u, n - 1);
-      re[u] = src[2 * t];
-      im[u] = src[2 * t + 1];
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (t0 + nt * u < n) dst[t0 + nt * u] = cmk(re[u], im[u]);
-  }
-}
 template <int MAXM>
 __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A) {
   extern __shared__ double lds[];
@@ -1788,9 +1904,9 @@ __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A)
   // ---- banded systems (A1 + l_m A2) y = r
   if (w == 5 || w == 3 || w == 1) {
     double2* ring = reinterpret_cast<double2*>(win);
-    if (w == 5) fd_banded_reg<5>(A, f, sLam, ring, &s_info);
-    if (w == 3) fd_banded_reg<3>(A, f, sLam, ring, &s_info);
-    if (w == 1) fd_banded_reg<1>(A, f, sLam, ring, &s_info);
+    if (w == 5) fd_banded_reg<MAXM, 5>(A, f, sLam, ring, &s_info);
+    if (w == 3) fd_banded_reg<MAXM, 3>(A, f, sLam, ring, &s_info);
+    if (w == 1) fd_banded_reg<MAXM, 1>(A, f, sLam, ring, &s_info);
   } else if (tid < M) {   // any patch size: one lane per system, ring of rows in LDS
     const auto b1 = gp(A.band);
     const auto b2 = b1 + long(n) * BW;
@@ -1841,10 +1957,12 @@ __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A)
   // cores, row tiles as above (Y operands of every step loaded once per row
   // tile, the next tile's before this tile's products; H3 operands in
   // registers; the two products of a step go to two accumulators per mode
-  // tile, summed at the store)
-  stage_cplx(sH, f.H3, MM, tid, nt);
+  // tile, summed at the store).  The register-window solves formed X
+  // during their back substitution already.
+  const bool x_done = kFuseOut<MAXM> && (w == 5 || w == 3 || w == 1);
+  if (!x_done) stage_cplx(sH, f.H3, MM, tid, nt);
   __syncthreads();
-  {
+  if (!x_done) {
     double anr[kKS], ani[kKS];
     auto load_y = [&](int tr, double* dr, double* di) {
       const int ic = min(tr * 16 + (lane & 15), n - 1);
@@ -1943,7 +2061,8 @@ size_t fd_solve_lds(int M, int s) {
   const bool reg = (w == 1 || w == 3 || w == 5);
   const size_t rows = size_t(M) * (w + 1) * (2 * w + 1);                      // per-system row rings
   const size_t ring = size_t(3) * ((w + 1) * (32 / (w + 1))) * (2 * w + 1);   // staged band chunks
-  return (size_t(M) + std::max(size_t(M) * M, reg ? ring : rows)) * 16;
+  // (register-window solves: also two 16-row tiles of y for the fused transform out)
+  return (size_t(M) + std::max(std::max(size_t(M) * M, reg ? ring : rows), reg ? size_t(32) * M : size_t(0))) * 16;
 }
 size_t fd_inverse_allowed = 0, fd_inverse1_allowed = 0;
 
