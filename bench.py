@@ -67,7 +67,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # scaled by the same counter on a plain device copy of known size), valid
 # for the kernel sources with these SHA-256 prefixes only (None: not measured
 # for the current sources).
-TRAFFIC = {"k_fd_solve": None, "k_fd_schur": None, "contract": None, "sources": None}
+TRAFFIC = {"k_fd_solve": 10.228, "k_fd_schur": 1.024, "contract": 2.902, "contract_spt": 1.767,
+           "sources": "ccdde506080223ee"}
 TRAFFIC_SOURCES = ("taps_solve.hip", "taps_device.hpp", "taps_batch.hip")
 
 
@@ -545,6 +546,8 @@ def c3_batch(capi, torch, args):
             "contract_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": gbs / HBM_PEAK_GBS, "ms_per_sweep": ms_c / args.c3_sweeps,
                                   "method_bytes_per_sweep": by_c / args.c3_sweeps,
+                                  "traffic_per_sweep": (TRAFFIC["contract_spt"] * by_c / args.c3_sweeps
+                                                        if TRAFFIC["sources"] == sources_digest() else None),
                                   "fp64_tflops": fl_c / (ms_c * 1e-3) / 1e12 if n_c else 0.0},
             "profiled_ms_per_sweep": {"contract": ms_c / args.c3_sweeps, "solve": ms_s / args.c3_sweeps,
                                       "eig": ms_e / args.c3_sweeps}}
