@@ -84,15 +84,19 @@ __global__ void kb_owner_fill(const int* __restrict__ pref, int* __restrict__ ow
     for (int w = pr[a]; w < pr[a + 1]; ++w) ow[w] = a;
 }
 
-// (at most 168 registers: three workgroups per CU, as many as its LDS allows)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kb_gram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                       const int* __restrict__ pref, const int* __restrict__ owner,
-                                                       int nact, int e) {
+// One instantiation per band width BW = 4s + 3 (a launch's problems share
+// the patch size of each dim), so a kernel holds the registers of its own
+// band width only; at most 168 registers: three workgroups per CU, as many
+// as the LDS allows.
+template <int BW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kb_gram_partial(
+    const BProb* __restrict__ P, const int* __restrict__ act, const int* __restrict__ pref,
+    const int* __restrict__ owner, int nact, int e) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
-    gram_partial(x.c, q.n[e], q.M, q.s[e], q.K[e], q.band[e], q.U[e], q.gpart + long(x.c) * q.K[e] * q.M * q.M);
+    gram_partial_bw<BW>(x.c, q.n[e], q.M, q.K[e], q.band[e], q.U[e], q.gpart + long(x.c) * q.K[e] * q.M * q.M);
     __syncthreads();   // LDS free for the next item
   }
 }
@@ -198,16 +202,38 @@ __global__ void kb_force_sum(const BProb* __restrict__ P, const int* __restrict_
   sum_parts_n<kVB>(blockIdx.x * kVB, ns, long(q.n[d]) * q.M, q.qpart, q.Q);
 }
 
-__global__ __launch_bounds__(256) void kb_residual_part(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                        const int* __restrict__ pref, const int* __restrict__ owner,
-                                                        int nact, int d) {
+// (one instantiation per band width, as the Gram partials: three
+// workgroups per CU at the usual patch size)
+template <int BW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kb_residual_part(
+    const BProb* __restrict__ P, const int* __restrict__ act, const int* __restrict__ pref,
+    const int* __restrict__ owner, int nact, int d) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
-    residual_part(x.c, q.n[d], q.M, q.s[d], q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
-                  q.rparts + 2 * (q.roff[d] + x.c));
+    residual_part_bw<BW>(x.c, q.n[d], q.M, q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
+                         q.rparts + 2 * (q.roff[d] + x.c));
     __syncthreads();   // LDS free for the next item
+  }
+}
+
+// the instantiations of both, by patch size s (band width 4s + 3)
+typedef void (*persist_fn)(const BProb*, const int*, const int*, const int*, int, int);
+persist_fn gram_partial_for(int s) {
+  switch (s) {
+    case 0: return kb_gram_partial<3>;
+    case 1: return kb_gram_partial<7>;
+    case 2: return kb_gram_partial<11>;
+    default: return kb_gram_partial<15>;
+  }
+}
+persist_fn residual_part_for(int s) {
+  switch (s) {
+    case 0: return kb_residual_part<3>;
+    case 1: return kb_residual_part<7>;
+    case 2: return kb_residual_part<11>;
+    default: return kb_residual_part<15>;
   }
 }
 
@@ -266,7 +292,7 @@ __global__ __launch_bounds__(256) void kb_snapshot(const BalanceArgs* __restrict
   snapshot(BA[act[blockIdx.x]]);
 }
 
-size_t gram_lds_allowed = 0, res_lds_allowed = 0;
+size_t gram_lds_allowed[4] = {}, res_lds_allowed[4] = {};   // per patch size 0..3
 
 // grid sizes per dim (maxima over the batch; blocks past a problem's own
 // extent return at once)
@@ -564,15 +590,18 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   const size_t glds = size_t(gram_lds_doubles(M, *std::max_element(p0.s, p0.s + D))) * 8;
   const size_t rlds = size_t(residual_lds_doubles(M, *std::max_element(p0.s, p0.s + D))) * 8;
   if (rlds > 160 * 1024 - 4096) return fail(h, TAPS_ERR_UNSUPPORTED, "residual needs %zu bytes of LDS", rlds);
-  TAPS_TRY(allow_lds(h, kb_gram_partial, glds, &gram_lds_allowed));
-  TAPS_TRY(allow_lds(h, kb_residual_part, rlds, &res_lds_allowed));
+  for (int d = 0; d < D; ++d) {
+    const int si = std::min(p0.s[d], 3);
+    TAPS_TRY(allow_lds(h, gram_partial_for(p0.s[d]), glds, &gram_lds_allowed[si]));
+    TAPS_TRY(allow_lds(h, residual_part_for(p0.s[d]), rlds, &res_lds_allowed[si]));
+  }
   for (int d = 0; d < D; ++d)
     TAPS_TRY(use_fd[d] ? fd_prepare(h, M, p0.s[d]) : solve_batched_prepare(h, M, p0.s[d]));
 
   auto refresh = [&](int e, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_gram_partial<<<pgrid(kItGram, e, kPersistLds), 256, glds, st>>>(d_prob, d_active, pref(kItGram, e),
+    gram_partial_for(p0.s[e])<<<pgrid(kItGram, e, kPersistLds), 256, glds, st>>>(d_prob, d_active, pref(kItGram, e),
                                                                        owner(kItGram, e), nact, e);
     TAPS_LAUNCHED(h, "kb_gram_partial");
     kb_gram_sum<<<dim3(cdiv(Z.gram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
@@ -641,7 +670,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return prof_end(h, slot, fl, by, st);
   };
   auto residual_parts = [&](int d, int nact, hipStream_t st) -> taps_status {
-    kb_residual_part<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, d_active, pref(kItRes, d),
+    residual_part_for(p0.s[d])<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, d_active, pref(kItRes, d),
                                                                        owner(kItRes, d), nact, d);
     TAPS_LAUNCHED(h, "kb_residual_part");
     return TAPS_OK;

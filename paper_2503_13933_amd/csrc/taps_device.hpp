@@ -85,13 +85,15 @@ __device__ inline void band_rows16(const double* sB, int i0, int rows, const dou
 // Operand rows and columns past M read neighbouring LDS entries and only
 // reach result entries past M, which are not stored.
 // part: K x M x M for this chunk.
-__device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const double* __restrict__ band_,
-                                    const double* __restrict__ U_, double* __restrict__ part_) {
+template <int BW>
+__device__ inline void gram_partial_bw(int chunk, int n, int M, int K, const double* __restrict__ band_,
+                                       const double* __restrict__ U_, double* __restrict__ part_) {
   const auto band = gp(band_);
   const auto U = gp(U_);
   const auto part = gp(part_);
   extern __shared__ double lds[];
-  const int w = 2 * s + 1, BW = 2 * w + 1, L = M | 1, MM = M * M;
+  constexpr int w = (BW - 1) / 2;
+  const int L = M | 1, MM = M * M;
   const int r0 = chunk * kGramRows;
   const int rows = min(kGramRows, n - r0);
   const int halo_rows = kGramRows + 2 * w;
@@ -107,12 +109,7 @@ __device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const
     const auto brows = band + (long(k) * n + r0) * BW;
     for (int t = tid; t < rows * BW; t += blockDim.x) sB[t] = brows[t];
     __syncthreads();
-    switch (s) {
-      case 0: band_rows16<3>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
-      case 1: band_rows16<7>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
-      case 2: band_rows16<11>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
-      default: band_rows16<15>(sB, 16 * wv, rows, sU, sV, L, M, lane); break;
-    }
+    band_rows16<BW>(sB, 16 * wv, rows, sU, sV, L, M, lane);
     __syncthreads();
     for (int tile = wv; tile < nt * nt; tile += 4) {
       const int tr = tile / nt, tc = tile - (tile / nt) * nt;
@@ -135,6 +132,16 @@ __device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const
         if (m < M && nb < M) part[long(k) * MM + m * M + nb] = acc[j];
       }
     }
+  }
+}
+
+__device__ inline void gram_partial(int chunk, int n, int M, int s, int K, const double* __restrict__ band,
+                                    const double* __restrict__ U, double* __restrict__ part) {
+  switch (s) {
+    case 0: gram_partial_bw<3>(chunk, n, M, K, band, U, part); break;
+    case 1: gram_partial_bw<7>(chunk, n, M, K, band, U, part); break;
+    case 2: gram_partial_bw<11>(chunk, n, M, K, band, U, part); break;
+    default: gram_partial_bw<15>(chunk, n, M, K, band, U, part); break;
   }
 }
 
