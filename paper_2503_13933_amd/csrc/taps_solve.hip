@@ -875,8 +875,8 @@ __device__ inline void stage_square(int M, int lane, const Src* const (&srcs)[N]
 //     triangular), so P = Z Wv; H2 = C1^{-T} P and H3 = P^{-1} = Wv^{-1} Z^H
 //     to the workspace, with the eigenvalues.
 // LDS in M x L real units (L = M rounded up to odd, so that column walks over
-// the lanes hit distinct banks): inverse 3 (two Gauss-Jordan buffers, C2),
-// schur 2 (Hr, Zr; there at the largest M, L = kFdMaxM + 1), vectors 6
+// the lanes hit distinct banks): inverse 2 (the Gauss-Jordan iterate, in
+// place, and C2), schur 2 (Hr, Zr; at the largest M of the layout), vectors 6
 // (complex H, Wv, Z; C1^{-1} at the end).
 // info word: 0, -1 (C1 singular) or -2 (no convergence); a later kernel
 // skips a system whose info is set.
@@ -914,8 +914,7 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
   extern __shared__ double lds[];
   const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
   double* S0 = lds;                                   // unit 0
-  double* S1 = lds + LL;                              // unit 1
-  double* C2s = lds + 2 * LL;                         // unit 2
+  double* C2s = lds + LL;                             // unit 1
   __shared__ int perm[64];
   __shared__ int s_fail;
   const FdWs f = fd_ws(A);
@@ -930,9 +929,11 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
   }
   wave_sync();
   // ---- C1^{-1}: Gauss-Jordan with partial pivoting (row swaps, undone as
-  // column swaps at the end)
+  // column swaps at the end), in place: lane j rewrites its column j from
+  // its own entries and column r; every batch of rows is read by all lanes
+  // (one instruction for the wave) before any lane stores it, and lane r's
+  // stores to column r only reach rows the other lanes have read already
   double* cur = S0;
-  double* nxt = S1;
   for (int r = 0; r < M; ++r) {
     // pivot: largest |cur[i][r]|, i >= r (first on ties), by a wave reduction
     double bv = (lane >= r && lane < M) ? fabs(cur[lane * L + r]) : -1.0;
@@ -978,14 +979,11 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
         for (int u = 0; u < 8; ++u) {
           const int i = i0 + u;
           const double v = (i == r) ? rowv : fma(beta, ar[u], alpha * aa[u]);
-          if (i < M) nxt[i * L + j] = v;
+          if (i < M) cur[i * L + j] = v;
         }
       }
     }
     wave_sync();
-    double* tmp = cur;
-    cur = nxt;
-    nxt = tmp;
   }
   for (int r = M - 1; r >= 0; --r) {   // undo the row swaps as column swaps
     const int p = perm[r];
@@ -2047,7 +2045,7 @@ __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { f
 
 // dynamic LDS of the three eigen-stage kernels, in M x L real units
 constexpr size_t kFdLdsCap = 160 * 1024 - 2048;
-size_t fd_inverse_lds(int M) { return size_t(3) * M * (M | 1) * 8; }
+size_t fd_inverse_lds(int M) { return size_t(2) * M * (M | 1) * 8; }
 int fd_maxm(int M) { return M <= kFdSmallM ? kFdSmallM : kFdMaxM; }
 size_t fd_schur_lds(int M) {
   const int mx = fd_maxm(M);
