@@ -154,6 +154,9 @@ def main():
     ap.add_argument("--target-sweeps", type=int, default=3,
                     help="plain sweeps behind the warm-start network's training targets (at least --sweeps)")
     ap.add_argument("--batch", type=int, default=1024, help="slabs in flight, one workgroup each")
+    ap.add_argument("--stream-order", choices=["hardest-first", "input"], default="hardest-first",
+                    help="continuous batching: first sweep of every slab, then the unsolved ones by decreasing "
+                         "residual (hardest-first), or slabs strictly in input order")
     ap.add_argument("--slabs", type=int, default=4096,
                     help="slabs solved per step (streamed through --batch slots)")
     ap.add_argument("--train-chains", type=int, default=4096)
@@ -287,15 +290,18 @@ def main():
                                       mode=capi.REDUCE, mode_ws=[U.ptr(b, 3, nt - 1) for b in done], thr=1000.0,
                                       n_pts=n_pts)
 
+    hardest = args.stream_order == "hardest-first"
+
     def step_warm():
         Y = net.forward(X_bench)
         U = layout.initial_batch(Y, fixed)
         return ws.solve_stream(h, probs, U, rho_star, cap, B, U_plain=U_plain, median_rho1=med1,
-                               on_done_batch=lambda done: reconstruct(U, done))
+                               on_done_batch=lambda done: reconstruct(U, done), first_sweep_all=hardest)
 
     def step_random_batched():
         U = U_plain.clone()
-        return ws.solve_stream(h, probs, U, rho_star, cap, B, on_done_batch=lambda done: reconstruct(U, done))
+        return ws.solve_stream(h, probs, U, rho_star, cap, B, on_done_batch=lambda done: reconstruct(U, done),
+                               first_sweep_all=hardest)
 
     def timed(fn, label):
         for w in range(args.warmup):
@@ -422,11 +428,13 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{N} x heat_slab {args.nx}x{args.nx}x{args.nz}x{args.nt} M={M}, learned warm start, "
-                         f"{B} in flight (continuous batching), to the plain {args.sweeps}-sweep median projected "
+                         f"{B} in flight (continuous batching, {args.stream_order}), to the plain {args.sweeps}-sweep "
+                         f"median projected "
                          f"residual {rho_star:.3e} (cap {cap} sweeps), BF16 end-time reconstruction"),
             "variant": "warm-start+batched",
             "solver": args.solver,
             "batch": B,
+            "stream_order": args.stream_order,
             "slabs_per_step": N,
             "target_rho": rho_star,
             "target_note": "Algorithm 1 stalls far above 1e-8 on these slabs (see floor); value counts only "

@@ -272,12 +272,23 @@ def restart_plain(rho1, rho2, plain_median_rho1):
 # ------------------------------------------------------------- streaming
 
 
-def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, on_done=None, on_done_batch=None):
+def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, on_done=None, on_done_batch=None,
+                 first_sweep_all=False):
     """Continuous batching of Algorithm 1: up to ``slots`` slabs in flight,
     one batched sweep (taps_als_batched) per round; a slab leaves as soon as
     its projected residual reaches tol, it has run ``cap`` sweeps, or its
     solve broke down (NaN residual), and the next waiting slab takes its
     place, so the kernels stay busy while slabs converge at different speeds.
+
+    first_sweep_all: every slab runs its first sweep before any runs its
+    second (rounds of ``slots`` slabs in input order), and the slabs still
+    unsolved then wait in order of decreasing residual (a restarted slab
+    first), so the slabs that need the most sweeps start early and the last
+    rounds, which run part-empty at nearly a full round's cost, are few.
+    For slabs of one grid and load structure (the launch parameters then do
+    not depend on which slabs share a round) a slab's sweeps and residuals
+    do not depend on the schedule: the batched kernels treat every problem
+    of a launch alone.
 
     With U_plain and median_rho1 given, U holds warm starts and the fallback
     rule is applied: a slab whose warm start lost (sweep-1 residual above
@@ -310,9 +321,8 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     rho1 = [float("nan")] * n
     outcome = [1] * n
     restarted = set()
-    while waiting or active:
-        while len(active) < slots and waiting:
-            active.append(waiting.popleft())
+
+    def one_round(active):
         Ua = U.ptrs(active) if isinstance(U, FactorBatch) else [U[i] for i in active]
         _, r = capi.taps_als_batched(h, prob_array(active), Ua, 0.0, 1)
         keep, done = [], []
@@ -340,5 +350,17 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
                 keep.append(i)
         if done and on_done_batch is not None:
             on_done_batch(done)
-        active = keep
+        return keep
+
+    if first_sweep_all:
+        rest = []
+        while waiting:
+            rest += one_round([waiting.popleft() for _ in range(min(slots, len(waiting)))])
+        # hardest first: restarted slabs (count 0), then by decreasing residual
+        rest.sort(key=lambda i: (count[i] != 0, -rho[i]))
+        waiting = deque(rest)
+    while waiting or active:
+        while len(active) < slots and waiting:
+            active.append(waiting.popleft())
+        active = one_round(active)
     return total, rho, len(restarted), outcome
