@@ -202,23 +202,25 @@ __global__ void kb_force_sum(const BProb* __restrict__ P, const int* __restrict_
   sum_parts_n<kVB>(blockIdx.x * kVB, ns, long(q.n[d]) * q.M, q.qpart, q.Q);
 }
 
-// (one instantiation per band width, as the Gram partials: three
-// workgroups per CU at the usual patch size)
-template <int BW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kb_residual_part(
+// (one instantiation per band width, as the Gram partials, and per number
+// of 16-column tiles per pass, three up to 48 modes: 128 registers, four
+// workgroups per CU, as many as the LDS allows)
+template <int BW, int NCT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kb_residual_part(
     const BProb* __restrict__ P, const int* __restrict__ act, const int* __restrict__ pref,
     const int* __restrict__ owner, int nact, int d) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
-    residual_part_bw<BW>(x.c, q.n[d], q.M, q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
-                         q.rparts + 2 * (q.roff[d] + x.c));
+    residual_part_bw<BW, NCT>(x.c, q.n[d], q.M, q.K[d], q.band[d], q.C, q.U[d], q.Q, q.fixed[d],
+                              q.rparts + 2 * (q.roff[d] + x.c));
     __syncthreads();   // LDS free for the next item
   }
 }
 
-// the instantiations of both, by patch size s (band width 4s + 3)
+// the instantiations of both, by patch size s (band width 4s + 3) and, for
+// the residual, the number of modes
 typedef void (*persist_fn)(const BProb*, const int*, const int*, const int*, int, int);
 persist_fn gram_partial_for(int s) {
   switch (s) {
@@ -228,12 +230,20 @@ persist_fn gram_partial_for(int s) {
     default: return kb_gram_partial<15>;
   }
 }
-persist_fn residual_part_for(int s) {
+persist_fn residual_part_for(int s, int M) {
+  if (M <= 48) {
+    switch (s) {
+      case 0: return kb_residual_part<3, 3>;
+      case 1: return kb_residual_part<7, 3>;
+      case 2: return kb_residual_part<11, 3>;
+      default: return kb_residual_part<15, 3>;
+    }
+  }
   switch (s) {
-    case 0: return kb_residual_part<3>;
-    case 1: return kb_residual_part<7>;
-    case 2: return kb_residual_part<11>;
-    default: return kb_residual_part<15>;
+    case 0: return kb_residual_part<3, 4>;
+    case 1: return kb_residual_part<7, 4>;
+    case 2: return kb_residual_part<11, 4>;
+    default: return kb_residual_part<15, 4>;
   }
 }
 
@@ -593,7 +603,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   for (int d = 0; d < D; ++d) {
     const int si = std::min(p0.s[d], 3);
     TAPS_TRY(allow_lds(h, gram_partial_for(p0.s[d]), glds, &gram_lds_allowed[si]));
-    TAPS_TRY(allow_lds(h, residual_part_for(p0.s[d]), rlds, &res_lds_allowed[si]));
+    TAPS_TRY(allow_lds(h, residual_part_for(p0.s[d], M), rlds, &res_lds_allowed[si]));
   }
   for (int d = 0; d < D; ++d)
     TAPS_TRY(use_fd[d] ? fd_prepare(h, M, p0.s[d]) : solve_batched_prepare(h, M, p0.s[d]));
@@ -670,7 +680,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return prof_end(h, slot, fl, by, st);
   };
   auto residual_parts = [&](int d, int nact, hipStream_t st) -> taps_status {
-    residual_part_for(p0.s[d])<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, d_active, pref(kItRes, d),
+    residual_part_for(p0.s[d], M)<<<pgrid(kItRes, d, kPersistLds), 256, rlds, st>>>(d_prob, d_active, pref(kItRes, d),
                                                                        owner(kItRes, d), nact, d);
     TAPS_LAUNCHED(h, "kb_residual_part");
     return TAPS_OK;

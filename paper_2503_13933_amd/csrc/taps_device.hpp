@@ -516,7 +516,7 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
 // up to four 16-column tiles of R per pass.
 // (BW = 2(2s+1)+1 band entries per row, a template argument so that the
 // band coefficients and the A-operand sums are exactly BW long)
-template <int BW>
+template <int BW, int NCT = 4>
 __device__ inline void residual_part_bw(int chunk, int n, int M, int K, const double* __restrict__ band_,
                                         const double* __restrict__ C_, const double* __restrict__ U_,
                                         const double* __restrict__ Q_, const uint8_t* __restrict__ fixed_,
@@ -541,19 +541,19 @@ __device__ inline void residual_part_bw(int chunk, int n, int M, int K, const do
   const int i_a = wv * 16 + (lane & 15);    // chunk row of this lane's A operands
   const int ksteps = (M + 3) / 4, nct = (M + 15) / 16;
   double rr2 = 0.0, qq2 = 0.0;
-  for (int ct0 = 0; ct0 < nct; ct0 += 4) {
-    rv4d acc[4];
+  for (int ct0 = 0; ct0 < nct; ct0 += NCT) {
+    rv4d acc[NCT];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NCT; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < K; ++k) {
       __syncthreads();   // sU staged / sC free
-      for (int c = lane; c < M; c += 64)   // rows wv, wv+4, ..: eight loads in flight, then eight stores
-        for (int rb = wv; rb < M; rb += 32) {
-          double cv[8];
+      for (int c = lane; c < M; c += 64)   // rows wv, wv+4, ..: four loads in flight, then four stores
+        for (int rb = wv; rb < M; rb += 16) {
+          double cv[4];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) cv[u] = C[(long(k) * M + min(rb + 4 * u, M - 1)) * M + c];
+          for (int u = 0; u < 4; ++u) cv[u] = C[(long(k) * M + min(rb + 4 * u, M - 1)) * M + c];
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
+          for (int u = 0; u < 4; ++u)
             if (rb + 4 * u < M) sC[(rb + 4 * u) * L + c] = cv[u];
         }
       double bc[BW];
@@ -572,7 +572,7 @@ __device__ inline void residual_part_bw(int chunk, int n, int M, int K, const do
           for (int o = 0; o < BW; ++o) a += bc[o] * sU[(i_a + o) * L + q];
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NCT; ++c) {
           if (ct0 + c < nct) {
             const int m = (ct0 + c) * 16 + (lane & 15);
             const double b = (m < M && q < M) ? sC[m * L + q] : 0.0;
@@ -583,7 +583,7 @@ __device__ inline void residual_part_bw(int chunk, int n, int M, int K, const do
     }
     // R = acc - Q on this pass's tiles; lane holds rows l/16 + 4j, column l%16
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCT; ++c) {
       const int m = (ct0 + c) * 16 + (lane & 15);
       if (ct0 + c >= nct || m >= M) continue;
 #pragma unroll
