@@ -113,16 +113,19 @@ __global__ void kb_gram_sum(const BProb* __restrict__ P, const int* __restrict__
   sum_parts_n<kVB>(blockIdx.x * kVB, chunks, long(q.K[e]) * q.M * q.M, q.gpart, q.gram[e]);
 }
 
-__global__ __launch_bounds__(256) void kb_lgram_partial(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                        const int* __restrict__ pref, const int* __restrict__ owner,
-                                                        int nact, int e, int rows) {
+// (NCT 16-column tiles per pass, the fewest that cover M: three waves per
+// SIMD up to 48 modes)
+template <int NCT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kb_lgram_partial(
+    const BProb* __restrict__ P, const int* __restrict__ act, const int* __restrict__ pref,
+    const int* __restrict__ owner, int nact, int e, int rows) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     const int splits = (q.n[e] + rows - 1) / rows;
     const int ct = x.c / splits;
-    lgram_partial(ct, x.c - ct * splits, rows, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
+    lgram_partial<NCT>(ct, x.c - ct * splits, rows, q.n[e], q.Rc[e], q.M, q.F[e], q.U[e], q.lpart);
   }
 }
 
@@ -178,20 +181,22 @@ __global__ void kb_wsum(const BProb* __restrict__ P, const WeightArgs* __restric
 
 // split = 0: item = row block, Q written directly; split = 1: item = (row
 // block, column range of kForceCols), partial Q per range, summed by
-// kb_force_sum
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void kb_force(const BProb* __restrict__ P, const int* __restrict__ act,
-                                                const int* __restrict__ pref, const int* __restrict__ owner,
-                                                int nact, int d, int split) {
+// kb_force_sum.  (NCT as in the load Gram: 152 registers at NCT = 3, three
+// waves per SIMD.)
+template <int NCT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void kb_force(
+    const BProb* __restrict__ P, const int* __restrict__ act, const int* __restrict__ pref,
+    const int* __restrict__ owner, int nact, int d, int split) {
   const int nit = pref[nact];
   for (int w = blockIdx.x; w < nit; w += gridDim.x) {
     const Item x = locate(act, pref, owner, w);
     const BProb& q = P[x.b];
     if (!split) {
-      force(x.c, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
+      force<NCT>(x.c, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.Q);
     } else {
       const int ns = (q.Rc[d] + kForceCols - 1) / kForceCols, rb = x.c / ns, sp = x.c - rb * ns;
-      force(rb, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.qpart + long(sp) * q.n[d] * q.M, sp * kForceCols,
-            (sp + 1) * kForceCols);
+      force<NCT>(rb, q.n[d], q.Rc[d], q.M, q.F[d], q.Wt, q.qpart + long(sp) * q.n[d] * q.M, sp * kForceCols,
+                 (sp + 1) * kForceCols);
     }
   }
 }
@@ -203,10 +208,11 @@ __global__ void kb_force_sum(const BProb* __restrict__ P, const int* __restrict_
 }
 
 // (one instantiation per band width, as the Gram partials, and per number
-// of 16-column tiles per pass, three up to 48 modes: 128 registers, four
-// workgroups per CU, as many as the LDS allows)
+// of 16-column tiles per pass, three up to 48 modes: up to s = 1, 128
+// registers, four workgroups per CU, as many as the LDS allows; three for
+// the wider bands, whose windows would spill at 128)
 template <int BW, int NCT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kb_residual_part(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BW <= 7 ? 4 : 3))) void kb_residual_part(
     const BProb* __restrict__ P, const int* __restrict__ act, const int* __restrict__ pref,
     const int* __restrict__ owner, int nact, int d) {
   const int nit = pref[nact];
@@ -616,7 +622,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     TAPS_LAUNCHED(h, "kb_gram_partial");
     kb_gram_sum<<<dim3(cdiv(Z.gram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e);
     TAPS_LAUNCHED(h, "kb_gram_sum");
-    kb_lgram_partial<<<pgrid(kItLgram, e, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItLgram, e),
+    (M <= 32 ? kb_lgram_partial<2> : M <= 48 ? kb_lgram_partial<3> : kb_lgram_partial<4>)<<<pgrid(kItLgram, e, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItLgram, e),
                                                                         owner(kItLgram, e), nact, e, lg_rows);
     TAPS_LAUNCHED(h, "kb_lgram_partial");
     kb_lgram_sum<<<dim3(cdiv(Z.lgram[e], kVB), nact), 256, 0, st>>>(d_prob, d_active, e, lg_rows);
@@ -661,7 +667,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       kb_load_weights<<<dim3(cdiv(Z.wt[d], kVB), nact), 256, 0, st>>>(d_prob, d_wa, d_active, d, D);
       TAPS_LAUNCHED(h, "kb_load_weights");
     }
-    kb_force<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItForce, d),
+    (M <= 32 ? kb_force<2> : M <= 48 ? kb_force<3> : kb_force<4>)<<<pgrid(kItForce, d, kPersistStream), 256, 0, st>>>(d_prob, d_active, pref(kItForce, d),
                                                                  owner(kItForce, d), nact, d, Z.fsplit[d]);
     TAPS_LAUNCHED(h, "kb_force");
     if (Z.fsplit[d]) {

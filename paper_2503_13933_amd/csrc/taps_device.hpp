@@ -175,9 +175,11 @@ __device__ inline void sum_parts(int tblock, int nparts, long len, const double*
 // Partial of L = F^T U for load columns [ctile*kLgCols, +kLgCols) over rows
 // [split*rows, +rows) (rows a multiple of 16), on the matrix cores: wave v owns load columns
 // [16v, 16v+16) of the tile, the rows are the contracted index, and the
-// M columns of U are covered in passes of up to four 16-wide tiles.  Operands
+// M columns of U are covered in passes of up to NCT 16-wide tiles (as in
+// the force).  Operands
 // are read from global memory (16 consecutive doubles per row and step).
 // part layout: [split][Rc][M].
+template <int NCT = 4>
 __device__ inline void lgram_partial(int ctile, int split, int rows, int n, int Rc, int M,
                                      const double* __restrict__ F_, const double* __restrict__ U_,
                                      double* __restrict__ part_) {
@@ -190,45 +192,45 @@ __device__ inline void lgram_partial(int ctile, int split, int rows, int n, int 
   const int rbeg = split * rows, rend = min(n, rbeg + rows);
   const int ca = cw + (lane & 15);
   const int nct = (M + 15) / 16;
-  for (int ct0 = 0; ct0 < nct; ct0 += 4) {
-    rv4d acc[4];
+  for (int ct0 = 0; ct0 < nct; ct0 += NCT) {
+    rv4d acc[NCT];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NCT; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     // 16 rows per pass, all operands of a pass loaded together and the next
     // pass's requested before this pass's products
-    auto load = [&](int i0, double (&a)[4], double (&b)[4][4]) {
+    auto load = [&](int i0, double (&a)[4], double (&b)[4][NCT]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int i = i0 + 4 * u + (lane >> 4);
         const bool ok = i < rend;
         a[u] = (ok && ca < Rc) ? F[long(i) * Rc + ca] : 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NCT; ++c) {
           const int m = (ct0 + c) * 16 + (lane & 15);
           b[u][c] = (ok && ct0 + c < nct && m < M) ? U[long(i) * M + m] : 0.0;
         }
       }
     };
-    double an[4], bn[4][4];
+    double an[4], bn[4][NCT];
     if (rbeg < rend) load(rbeg, an, bn);
     for (int i0 = rbeg; i0 < rend; i0 += 16) {
-      double a[4], b[4][4];
+      double a[4], b[4][NCT];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         a[u] = an[u];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[u][c] = bn[u][c];
+        for (int c = 0; c < NCT; ++c) b[u][c] = bn[u][c];
       }
       if (i0 + 16 < rend) load(i0 + 16, an, bn);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NCT; ++c)
           if (ct0 + c < nct) acc[c] = mfma_f64(a[u], b[u][c], acc[c]);   // guard, not exit: stays unrolled
       }
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCT; ++c) {
       const int m = (ct0 + c) * 16 + (lane & 15);
       if (ct0 + c >= nct || m >= M) continue;
 #pragma unroll
@@ -413,13 +415,16 @@ __device__ inline void load_weights_fused(int c, int s, int wsl, const WeightArg
 // Q = F_d Wt for rows [rblock*kQRows, +kQRows) on the matrix cores: wave v
 // owns rows [16v, 16v+16) of the block, the load columns are the contracted
 // index (passes of 16 columns in four steps, operands loaded together), and
-// the M columns are covered in passes of up to four 16-wide tiles.  In a pass
+// the M columns are covered in passes of up to NCT 16-wide tiles (NCT = 4
+// covers any M; the batched kernels instantiate the smallest that covers
+// their M, which holds fewer operand registers).  In a pass
 // from column c0, lane group g = l/16 takes columns c0 + 4g .. c0 + 4g + 3, one
 // per step (the Wt rows follow the same assignment), so each lane reads its
 // four F entries as two 16-byte loads: 64 contiguous bytes of four rows' lines
 // per instruction pair instead of four loads of 8 bytes per row.
 // (load columns [c_lo, c_hi) only: the batched driver splits long load
 // rows over several work items and sums their partial Q afterwards)
+template <int NCT = 4>
 __device__ inline void force(int rblock, int n, int Rc, int M, const double* __restrict__ F_,
                              const double* __restrict__ Wt_, double* __restrict__ Q_, int c_lo = 0,
                              int c_hi = 0x7fffffff) {
@@ -431,14 +436,14 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
   if (rw >= n) return;
   const int ia = rw + (lane & 15);
   const int nct = (M + 15) / 16;
-  for (int ct0 = 0; ct0 < nct; ct0 += 4) {
-    rv4d acc[4];
+  for (int ct0 = 0; ct0 < nct; ct0 += NCT) {
+    rv4d acc[NCT];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NCT; ++c) acc[c] = rv4d{0.0, 0.0, 0.0, 0.0};
     // 16 load columns per pass, all operands of a pass loaded together and
     // the next pass's requested before this pass's products
     const int c_end = min(Rc, c_hi);
-    auto load = [&](int c0, double (&a)[4], double (&b)[4][4]) {
+    auto load = [&](int c0, double (&a)[4], double (&b)[4][NCT]) {
       const int kb = c0 + 4 * (lane >> 4);
       if (ia < n && kb + 3 < c_end) {
         const gmem<f64x2u>* p = reinterpret_cast<const gmem<f64x2u>*>(F + long(ia) * Rc + kb);
@@ -455,47 +460,36 @@ __device__ inline void force(int rblock, int n, int Rc, int M, const double* __r
       for (int u = 0; u < 4; ++u) {
         const bool ok = kb + u < c_end;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NCT; ++c) {
           const int m = (ct0 + c) * 16 + (lane & 15);
           b[u][c] = (ok && ct0 + c < nct && m < M) ? Wt[long(kb + u) * M + m] : 0.0;
         }
       }
     };
-    // two passes in flight: pass p's products are formed after pass p+2's
-    // loads were issued (buffers A and B in turn)
-    auto mma = [&](const double (&a)[4], const double (&b)[4][4]) {
+    // the next pass's operands requested before this pass's products
+    auto mma = [&](const double (&a)[4], const double (&b)[4][NCT]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NCT; ++c)
           if (ct0 + c < nct) acc[c] = mfma_f64(a[u], b[u][c], acc[c]);   // guard, not exit: stays unrolled
       }
     };
-    double aA[4], bA[4][4], aB[4], bB[4][4];
-    load(c_lo, aA, bA);
-    if (c_lo + 16 < c_end) load(c_lo + 16, aB, bB);
-    for (int c0 = c_lo; c0 < c_end; c0 += 32) {
-      double a[4], b[4][4];
+    double an[4], bn[4][NCT];
+    load(c_lo, an, bn);
+    for (int c0 = c_lo; c0 < c_end; c0 += 16) {
+      double a[4], b[4][NCT];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        a[u] = aA[u];
+        a[u] = an[u];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[u][c] = bA[u][c];
+        for (int c = 0; c < NCT; ++c) b[u][c] = bn[u][c];
       }
-      if (c0 + 32 < c_end) load(c0 + 32, aA, bA);
-      mma(a, b);
-      if (c0 + 16 >= c_end) break;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = aB[u];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[u][c] = bB[u][c];
-      }
-      if (c0 + 48 < c_end) load(c0 + 48, aB, bB);
+      if (c0 + 16 < c_end) load(c0 + 16, an, bn);
       mma(a, b);
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCT; ++c) {
       const int m = (ct0 + c) * 16 + (lane & 15);
       if (ct0 + c >= nct || m >= M) continue;
 #pragma unroll
