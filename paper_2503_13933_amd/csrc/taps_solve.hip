@@ -699,7 +699,8 @@ size_t res_lds_allowed = 0;
 // Wv unit upper triangular), P = Z Wv diagonalises E, and Y = X P decouples
 // into M banded systems (A1 + l_m A2) y_m = (Q C1^{-T} P)_m; X = Re(Y P^{-1})
 // with P^{-1} = Wv^{-1} Z^H.
-//   k_fd_inverse, k_fd_schur, k_fd_vectors (one wave per system each):
+//   k_fd_inverse, k_fd_schur, k_fd_vectors (one wave per system each, two
+//              for the vectors kernel):
 //              C1^{-1} by Gauss-Jordan with partial pivoting and E; Householder
 //              Hessenberg form and Francis double-shift QR to the real Schur
 //              form (Z accumulated); complex Schur form, Wv and Wv^{-1} by
@@ -840,23 +841,24 @@ struct IjWalk {
     }
   }
 };
-// One wave reads the row-major M x M matrices srcs[0..N) (element t = i M + j)
+// nthr threads (one wave by default) read the row-major M x M matrices
+// srcs[0..N) (element t = i M + j)
 // and hands entry (i, j) of each to put(i, j, values); sixteen entries per lane
 // are loaded before the first is handed on, so the loads' latencies overlap.
 template <int N, class Src, class Put>
-__device__ inline void stage_square(int M, int lane, const Src* const (&srcs)[N], Put put) {
+__device__ inline void stage_square(int M, int lane, const Src* const (&srcs)[N], Put put, int nthr = 64) {
   constexpr int kU = 16;
   const int MM = M * M;
-  IjWalk w(lane, M);
-  for (int t0 = lane; t0 < MM; t0 += 64 * kU) {
+  IjWalk w(lane, M, nthr);
+  for (int t0 = lane; t0 < MM; t0 += nthr * kU) {
     double v[kU][N];
 #pragma unroll
     for (int u = 0; u < kU; ++u)
 #pragma unroll
-      for (int a = 0; a < N; ++a) v[u][a] = srcs[a][min(t0 + 64 * u, MM - 1)];
+      for (int a = 0; a < N; ++a) v[u][a] = srcs[a][min(t0 + nthr * u, MM - 1)];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      if (t0 + 64 * u < MM) put(w.i, w.j, v[u]);
+      if (t0 + nthr * u < MM) put(w.i, w.j, v[u]);
       w.next(M);
     }
   }
@@ -864,7 +866,9 @@ __device__ inline void stage_square(int M, int lane, const Src* const (&srcs)[N]
 
 // Eigen stage of the fast diagonalisation for one dim system with two kinds,
 // in three kernels of one 64-lane wave per system (split so that the long
-// real phases hold little LDS and four systems share a compute unit):
+// real phases hold little LDS and four systems share a compute unit; the
+// vectors kernel, whose six LDS units leave room for two systems per compute
+// unit, runs two waves per system so that every SIMD has one):
 //   inverse: C1^{-1} by Gauss-Jordan with partial pivoting, E = C2^T C1^{-T}
 //     (the system becomes A1 X + A2 X E = Q C1^{-T}) to the workspace;
 //   schur: Householder reduction of E to Hessenberg form and Francis
@@ -1360,12 +1364,17 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   if (lane == 0 && s_fail) A.info[0] = -2;
 }
 
+constexpr int kVecThreads = 128;   // the eigenvector kernel: two waves per system
+
 // ZG: Z lives in the workspace (the right-hand-side region, free until the
 // banded stage) instead of LDS, for M whose six LDS units do not fit; the
 // lanes of one wave see each other's global stores in issue order.
 template <bool ZG>
 __device__ void fd_eig_vectors(const SolveArgs& A) {
   extern __shared__ double lds[];
+  // two waves per system: the lanes of the second take no row or column of
+  // their own (they reach the barriers) and share the dense products
+  constexpr int NT = kVecThreads;
   const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
   cplx* H = reinterpret_cast<cplx*>(lds);            // units 0-1
   cplx* Wv = reinterpret_cast<cplx*>(lds + 2 * LL);   // units 2-3
@@ -1385,9 +1394,9 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
     stage_square(M, lane, src, [&](int i, int j, const double* v) {
       H[i * L + j] = cmk(v[0], 0.0);
       Z[i * L + j] = cmk(v[1], 0.0);
-    });
+    }, NT);
   }
-  wave_sync();
+  __syncthreads();
   for (int k = 0; k + 1 < M; ++k) {
     const cplx c = H[(k + 1) * L + k];
     if (c.r == 0.0 && c.i == 0.0) continue;
@@ -1402,13 +1411,13 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
     }
     const double en = rsqrt(e0.r * e0.r + e0.i * e0.i + e1.r * e1.r + e1.i * e1.i);
     const cplx g0 = cscale(e0, en), g1 = cscale(e1, en);   // G = [g0 -conj(g1); g1 conj(g0)]
-    wave_sync();
+    __syncthreads();
     if (lane >= k && lane < M) {   // rows k, k+1 <- G^H rows
       const cplx h0 = H[k * L + lane], h1 = H[(k + 1) * L + lane];
       H[k * L + lane] = cadd(cmul(cconj(g0), h0), cmul(cconj(g1), h1));
       H[(k + 1) * L + lane] = csub(cmul(g0, h1), cmul(g1, h0));
     }
-    wave_sync();
+    __syncthreads();
     if (lane <= k + 1) {           // columns k, k+1 <- columns G
       const cplx h0 = H[lane * L + k], h1 = H[lane * L + k + 1];
       H[lane * L + k] = cadd(cmul(h0, g0), cmul(h1, g1));
@@ -1419,9 +1428,9 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
       Z[lane * L + k] = cadd(cmul(z0, g0), cmul(z1, g1));
       Z[lane * L + k + 1] = csub(cmul(z1, cconj(g0)), cmul(z0, cconj(g1)));
     }
-    wave_sync();
+    __syncthreads();
     if (lane == 0) H[(k + 1) * L + k] = cmk(0.0, 0.0);
-    wave_sync();
+    __syncthreads();
     ++k;   // the next subdiagonal entry is zero
   }
   // ---- eigenvectors Wv of T (unit upper triangular), one column per lane
@@ -1442,7 +1451,7 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
     f.lam[2 * k] = tk.r;
     f.lam[2 * k + 1] = tk.i;
   }
-  wave_sync();
+  __syncthreads();
   // ---- Winv = Wv^{-1} (unit upper triangular) into H (T no longer needed)
   if (lane < M) {
     const int j = lane;
@@ -1453,11 +1462,11 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
       H[i * L + j] = cscale(sacc, -1.0);
     }
   }
-  wave_sync();
+  __syncthreads();
   // ---- H3 = Winv Z^H  (H3[m][q] = sum_j Winv[m][j] conj(Z[q][j]))
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) {
+    IjWalk w(lane, M, NT);
+    for (int t = lane; t < MM; t += NT, w.next(M)) {
       const int m = w.i, q = w.j;
       cplx sacc = cmk(0.0, 0.0);
       for (int j = m; j < M; ++j) sacc = cadd(sacc, cmul(H[m * L + j], cconj(Z[q * L + j])));
@@ -1465,27 +1474,27 @@ __device__ void fd_eig_vectors(const SolveArgs& A) {
       f.H3[2 * t + 1] = sacc.i;
     }
   }
-  wave_sync();
+  __syncthreads();
   // ---- ZW = Z Wv into H, then H2 = C1inv^T ZW (H2[q][m] = sum_j C1inv[j][q] ZW[j][m])
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) {
+    IjWalk w(lane, M, NT);
+    for (int t = lane; t < MM; t += NT, w.next(M)) {
       const int i = w.i, m = w.j;
       cplx sacc = cmk(0.0, 0.0);
       for (int j = 0; j <= m; ++j) sacc = cadd(sacc, cmul(Z[i * L + j], Wv[j * L + m]));
       H[i * L + m] = sacc;
     }
   }
-  wave_sync();
+  __syncthreads();
   double* Ci2 = lds + 2 * LL;   // C1^{-1} back from the workspace (Wv is dead)
   {
     const gmem<double>* const src[1] = {f.C1inv};
-    stage_square(M, lane, src, [&](int i, int j, const double* v) { Ci2[i * L + j] = v[0]; });
+    stage_square(M, lane, src, [&](int i, int j, const double* v) { Ci2[i * L + j] = v[0]; }, NT);
   }
-  wave_sync();
+  __syncthreads();
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) {
+    IjWalk w(lane, M, NT);
+    for (int t = lane; t < MM; t += NT, w.next(M)) {
       const int q = w.i, m = w.j;
       cplx sacc = cmk(0.0, 0.0);
       for (int j = 0; j < M; ++j) sacc = cadd(sacc, cscale(H[j * L + m], Ci2[j * L + q]));
@@ -2024,7 +2033,7 @@ __global__ __launch_bounds__(64) void k_fd_schur(const SolveArgs* __restrict__ a
   fd_eig_schur<MAXM>(A);
 }
 template <bool ZG>
-__global__ __launch_bounds__(64) void k_fd_vectors(const SolveArgs* __restrict__ args,
+__global__ __launch_bounds__(kVecThreads) void k_fd_vectors(const SolveArgs* __restrict__ args,
                                                    const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
   fd_eig_vectors<ZG>(A);
@@ -2039,7 +2048,7 @@ __global__ __launch_bounds__(64) void k_fd_inverse_one(SolveArgs A) { fd_eig_inv
 template <int MAXM>
 __global__ __launch_bounds__(64) void k_fd_schur_one(SolveArgs A) { fd_eig_schur<MAXM>(A); }
 template <bool ZG>
-__global__ __launch_bounds__(64) void k_fd_vectors_one(SolveArgs A) { fd_eig_vectors<ZG>(A); }
+__global__ __launch_bounds__(kVecThreads) void k_fd_vectors_one(SolveArgs A) { fd_eig_vectors<ZG>(A); }
 template <int MAXM>
 __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve_one(SolveArgs A) { fd_solve_body<MAXM>(A); }
 
@@ -2100,7 +2109,7 @@ taps_status fd_single_t(taps_handle* h, const SolveArgs& A, int n, int M, int s,
   k_fd_schur_one<MAXM><<<1, 64, fd_schur_lds(M), stream>>>(A);
   TAPS_LAUNCHED(h, "k_fd_schur");
   TAPS_TRY(taps::prof_end(h, sslot, fd_schur_flops(M), fd_schur_bytes(M), stream));
-  k_fd_vectors_one<ZG><<<1, 64, fd_vectors_lds(M), stream>>>(A);
+  k_fd_vectors_one<ZG><<<1, kVecThreads, fd_vectors_lds(M), stream>>>(A);
   TAPS_LAUNCHED(h, "k_fd_vectors");
   TAPS_TRY(taps::prof_end(h, slot, fd_eig_flops(M), fd_eig_bytes(M), stream));
   TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
@@ -2128,7 +2137,7 @@ taps_status fd_batched_t(taps_handle* h, int n_active, const SolveArgs* args, co
   k_fd_schur<MAXM><<<n_active, 64, fd_schur_lds(M), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_schur");
   TAPS_TRY(taps::prof_end(h, sslot, n_active * fd_schur_flops(M), n_active * fd_schur_bytes(M), stream));
-  k_fd_vectors<ZG><<<n_active, 64, fd_vectors_lds(M), stream>>>(args, d_active);
+  k_fd_vectors<ZG><<<n_active, kVecThreads, fd_vectors_lds(M), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_vectors");
   TAPS_TRY(taps::prof_end(h, slot, n_active * fd_eig_flops(M), n_active * fd_eig_bytes(M), stream));
   TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SOLVE, stream, &slot));
