@@ -699,8 +699,8 @@ size_t res_lds_allowed = 0;
 // Wv unit upper triangular), P = Z Wv diagonalises E, and Y = X P decouples
 // into M banded systems (A1 + l_m A2) y_m = (Q C1^{-T} P)_m; X = Re(Y P^{-1})
 // with P^{-1} = Wv^{-1} Z^H.
-//   k_fd_inverse, k_fd_schur, k_fd_vectors (one wave per system each, two
-//              for the vectors kernel):
+//   k_fd_inverse, k_fd_schur, k_fd_vectors (one wave per system for the
+//              Schur kernel, four for the other two):
 //              C1^{-1} by Gauss-Jordan with partial pivoting and E; Householder
 //              Hessenberg form and Francis double-shift QR to the real Schur
 //              form (Z accumulated); complex Schur form, Wv and Wv^{-1} by
@@ -867,8 +867,8 @@ __device__ inline void stage_square(int M, int lane, const Src* const (&srcs)[N]
 // Eigen stage of the fast diagonalisation for one dim system with two kinds,
 // in three kernels of one 64-lane wave per system (split so that the long
 // real phases hold little LDS and four systems share a compute unit; the
-// vectors kernel, whose six LDS units leave room for two systems per compute
-// unit, runs two waves per system so that every SIMD has one):
+// inverse and vectors kernels run four waves per system, which share their
+// dense products while one wave takes the column-serial parts):
 //   inverse: C1^{-1} by Gauss-Jordan with partial pivoting, E = C2^T C1^{-T}
 //     (the system becomes A1 X + A2 X E = Q C1^{-T}) to the workspace;
 //   schur: Householder reduction of E to Hessenberg form and Francis
@@ -914,8 +914,13 @@ __device__ inline double nr_rcp(double d) {
   return fma(r, e, r);
 }
 
+constexpr int kVecThreads = 256;   // the inverse and eigenvector kernels: four waves per system
+
 __device__ void fd_eig_inverse(const SolveArgs& A) {
   extern __shared__ double lds[];
+  // four waves per system: Gauss-Jordan on the first (lane = column), the
+  // staging and the product E on all of them
+  constexpr int NT = kVecThreads;
   const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
   double* S0 = lds;                                   // unit 0
   double* C2s = lds + LL;                             // unit 1
@@ -929,9 +934,9 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
     stage_square(M, lane, src, [&](int i, int j, const double* v) {
       S0[i * L + j] = v[0];
       C2s[i * L + j] = v[1];
-    });
+    }, NT);
   }
-  wave_sync();
+  __syncthreads();
   // ---- C1^{-1}: Gauss-Jordan with partial pivoting (row swaps, undone as
   // column swaps at the end), in place: lane j rewrites its column j from
   // its own entries and column r; every batch of rows is read by all lanes
@@ -960,7 +965,7 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
       cur[r * L + lane] = cur[p * L + lane];
       cur[p * L + lane] = t;
     }
-    wave_sync();
+    __syncthreads();
     if (lane < M) {   // column lane of the next iterate, rows in batches of 8
       const int j = lane;
       const double ip = 1.0 / cur[r * L + r];
@@ -987,7 +992,7 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
         }
       }
     }
-    wave_sync();
+    __syncthreads();
   }
   for (int r = M - 1; r >= 0; --r) {   // undo the row swaps as column swaps
     const int p = perm[r];
@@ -996,17 +1001,17 @@ __device__ void fd_eig_inverse(const SolveArgs& A) {
       cur[lane * L + r] = cur[lane * L + p];
       cur[lane * L + p] = t;
     }
-    wave_sync();
+    __syncthreads();
   }
   const double* Ci = cur;   // C1^{-1}, kept for E and saved for H2
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) f.C1inv[t] = Ci[w.i * L + w.j];
+    IjWalk w(lane, M, NT);
+    for (int t = lane; t < MM; t += NT, w.next(M)) f.C1inv[t] = Ci[w.i * L + w.j];
   }
   // ---- E[i][j] = sum_q C2[q][i] C1inv[j][q] to the workspace
   {
-    IjWalk w(lane, M);
-    for (int t = lane; t < MM; t += 64, w.next(M)) {
+    IjWalk w(lane, M, NT);
+    for (int t = lane; t < MM; t += NT, w.next(M)) {
       const int i = w.i, j = w.j;
       double e = 0.0;
 #pragma unroll 8
@@ -1364,16 +1369,14 @@ __device__ void fd_eig_schur(const SolveArgs& A) {
   if (lane == 0 && s_fail) A.info[0] = -2;
 }
 
-constexpr int kVecThreads = 128;   // the eigenvector kernel: two waves per system
-
 // ZG: Z lives in the workspace (the right-hand-side region, free until the
 // banded stage) instead of LDS, for M whose six LDS units do not fit; the
 // lanes of one wave see each other's global stores in issue order.
 template <bool ZG>
 __device__ void fd_eig_vectors(const SolveArgs& A) {
   extern __shared__ double lds[];
-  // two waves per system: the lanes of the second take no row or column of
-  // their own (they reach the barriers) and share the dense products
+  // four waves per system: the lanes past the first wave take no row or
+  // column of their own (they reach the barriers) and share the dense products
   constexpr int NT = kVecThreads;
   const int M = A.M, MM = M * M, L = M | 1, LL = M * L, lane = threadIdx.x;
   cplx* H = reinterpret_cast<cplx*>(lds);            // units 0-1
@@ -2022,7 +2025,7 @@ __device__ __attribute__((always_inline)) void fd_solve_body(const SolveArgs& A)
   if (tid == 0 && s_info) A.info[0] = s_info;
 }
 
-__global__ __launch_bounds__(64) void k_fd_inverse(const SolveArgs* __restrict__ args,
+__global__ __launch_bounds__(kVecThreads) void k_fd_inverse(const SolveArgs* __restrict__ args,
                                                    const int* __restrict__ active) {
   const SolveArgs A = args[active[blockIdx.x]];
   fd_eig_inverse(A);
@@ -2044,7 +2047,7 @@ __global__ __launch_bounds__(kFdThreads, 1) void k_fd_solve(const SolveArgs* __r
   const SolveArgs A = args[active[blockIdx.x]];
   fd_solve_body<MAXM>(A);
 }
-__global__ __launch_bounds__(64) void k_fd_inverse_one(SolveArgs A) { fd_eig_inverse(A); }
+__global__ __launch_bounds__(kVecThreads) void k_fd_inverse_one(SolveArgs A) { fd_eig_inverse(A); }
 template <int MAXM>
 __global__ __launch_bounds__(64) void k_fd_schur_one(SolveArgs A) { fd_eig_schur<MAXM>(A); }
 template <bool ZG>
@@ -2103,7 +2106,7 @@ taps_status fd_single_t(taps_handle* h, const SolveArgs& A, int n, int M, int s,
   TAPS_TRY(taps::allow_lds(h, k_fd_solve_one<MAXM>, fd_solve_lds(M, s), &fd_solve1_lds_ok<MAXM>));
   size_t slot, sslot;
   TAPS_TRY(taps::prof_begin(h, TAPS_PROF_EIG, stream, &slot));
-  k_fd_inverse_one<<<1, 64, fd_inverse_lds(M), stream>>>(A);
+  k_fd_inverse_one<<<1, kVecThreads, fd_inverse_lds(M), stream>>>(A);
   TAPS_LAUNCHED(h, "k_fd_inverse");
   TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
   k_fd_schur_one<MAXM><<<1, 64, fd_schur_lds(M), stream>>>(A);
@@ -2131,7 +2134,7 @@ taps_status fd_batched_t(taps_handle* h, int n_active, const SolveArgs* args, co
                          double flops, double bytes, hipStream_t stream) {
   size_t slot, sslot;
   TAPS_TRY(taps::prof_begin(h, TAPS_PROF_EIG, stream, &slot));
-  k_fd_inverse<<<n_active, 64, fd_inverse_lds(M), stream>>>(args, d_active);
+  k_fd_inverse<<<n_active, kVecThreads, fd_inverse_lds(M), stream>>>(args, d_active);
   TAPS_LAUNCHED(h, "k_fd_inverse");
   TAPS_TRY(taps::prof_begin(h, TAPS_PROF_SCHUR, stream, &sslot));
   k_fd_schur<MAXM><<<n_active, 64, fd_schur_lds(M), stream>>>(args, d_active);
