@@ -315,52 +315,60 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
 
     waiting = deque(range(n))
     active = []
-    count = [0] * n          # sweeps since the (re)start
-    total = [0] * n          # sweeps run
-    rho = [float("nan")] * n
-    rho1 = [float("nan")] * n
-    outcome = [1] * n
-    restarted = set()
+    # per-slab state as arrays: a round's bookkeeping is a few vector
+    # operations, not a Python loop over the slabs in flight (the GPU waits
+    # for it between rounds)
+    count = np.zeros(n, dtype=np.int64)       # sweeps since the (re)start
+    total = np.zeros(n, dtype=np.int64)       # sweeps run
+    rho = np.full(n, np.nan)
+    rho1 = np.full(n, np.nan)
+    outcome = np.ones(n, dtype=np.int64)
+    restarted = np.zeros(n, dtype=bool)
 
     def one_round(active):
         Ua = U.ptrs(active) if isinstance(U, FactorBatch) else [U[i] for i in active]
         _, r = capi.taps_als_batched(h, prob_array(active), Ua, 0.0, 1)
-        keep, done = [], []
-        for i, ri in zip(active, r):
-            count[i] += 1
-            total[i] += 1
-            rho[i] = ri
-            if U_plain is not None and i not in restarted:
-                if count[i] == 1:
-                    rho1[i] = ri
-                lost = (count[i] == 1 and ri != ri) or (count[i] == 2 and restart_plain(rho1[i], ri, median_rho1))
-                if lost:
-                    restarted.add(i)
-                    for u, u0 in zip(U[i], U_plain[i]):
-                        u.copy_(u0)
-                    count[i] = 0
-                    keep.append(i)
-                    continue
-            if ri <= tol or ri != ri or count[i] >= cap:
-                outcome[i] = 0 if ri <= tol else (2 if ri != ri else 1)
-                done.append(i)
-                if on_done is not None:
-                    on_done(i)
-            else:
-                keep.append(i)
+        act = np.asarray(active, dtype=np.int64)
+        r = np.asarray(r, dtype=np.float64)
+        count[act] += 1
+        total[act] += 1
+        rho[act] = r
+        lost = np.zeros(len(act), dtype=bool)
+        if U_plain is not None:
+            fresh = ~restarted[act]
+            c = count[act]
+            first = fresh & (c == 1)
+            rho1[act[first]] = r[first]
+            # the fallback rule (restart_plain) on every slab of the round;
+            # a comparison with NaN is false, so a breakdown is a loss
+            r1 = rho1[act]
+            lost = (first & np.isnan(r)) | (fresh & (c == 2) & (~(r1 <= median_rho1) | ~(r <= r1)))
+            for i in act[lost].tolist():
+                for u, u0 in zip(U[i], U_plain[i]):
+                    u.copy_(u0)
+            restarted[act[lost]] = True
+            count[act[lost]] = 0
+        fin = ~lost & ((r <= tol) | np.isnan(r) | (count[act] >= cap))
+        fa, fr = act[fin], r[fin]
+        outcome[fa] = np.where(fr <= tol, 0, np.where(np.isnan(fr), 2, 1))
+        done = fa.tolist()
+        if on_done is not None:
+            for i in done:
+                on_done(i)
         if done and on_done_batch is not None:
             on_done_batch(done)
-        return keep
+        return act[~fin].tolist()
 
     if first_sweep_all:
         rest = []
         while waiting:
             rest += one_round([waiting.popleft() for _ in range(min(slots, len(waiting)))])
         # hardest first: restarted slabs (count 0), then by decreasing residual
-        rest.sort(key=lambda i: (count[i] != 0, -rho[i]))
-        waiting = deque(rest)
+        # (a stable sort, as the slabs' input order breaks ties)
+        ra = np.asarray(rest, dtype=np.int64)
+        waiting = deque(ra[np.lexsort((-rho[ra], count[ra] != 0))].tolist())
     while waiting or active:
         while len(active) < slots and waiting:
             active.append(waiting.popleft())
         active = one_round(active)
-    return total, rho, len(restarted), outcome
+    return total.tolist(), rho.tolist(), int(restarted.sum()), outcome.tolist()
