@@ -284,11 +284,13 @@ def main():
 
     def reconstruct(U, done):
         # end-time fields (time factor's last row as mode weights) of the
-        # slabs that left this round, in one call, by address
-        capi.taps_reconstruct_batched(h, [[U.ptr(b, 0), U.ptr(b, 1), U.ptr(b, 2)] for b in done], M,
-                                      [stats.data_ptr() + b * s_row for b in done], prec=capi.BF16,
-                                      mode=capi.REDUCE, mode_ws=[U.ptr(b, 3, nt - 1) for b in done], thr=1000.0,
-                                      n_pts=n_pts)
+        # slabs that left this round, in one call, by address (address
+        # arrays, no per-slab Python work)
+        idx = np.asarray(done, dtype=np.uint64)
+        phis = np.stack([U.addrs(idx, 0), U.addrs(idx, 1), U.addrs(idx, 2)], axis=1)
+        outs = np.uint64(stats.data_ptr()) + idx * np.uint64(s_row)
+        capi.taps_reconstruct_batched(h, phis, M, outs, prec=capi.BF16, mode=capi.REDUCE,
+                                      mode_ws=U.addrs(idx, 3, nt - 1), thr=1000.0, n_pts=n_pts)
 
     hardest = args.stream_order == "hardest-first"
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtaps.so")
@@ -174,6 +175,11 @@ class Handle:
 
 
 def _ptr_array(tensors):
+    """C array of addresses from a list of tensors / ints / None, or from an
+    integer numpy array of addresses (copied in one step)."""
+    if isinstance(tensors, np.ndarray):
+        a = np.ascontiguousarray(tensors, dtype=np.uint64).ravel()
+        return (C.c_void_p * len(a)).from_buffer_copy(a.tobytes())
     arr = (C.c_void_p * len(tensors))()
     for i, t in enumerate(tensors):
         arr[i] = _ptr(t)
@@ -375,12 +381,15 @@ def taps_reconstruct_noalloc(h: Handle, Phis, M: int, out, prec: int = FP64, mod
 def taps_reconstruct_batched(h: Handle, Phis, M: int, outs, prec: int = BF16, mode: int = REDUCE, mode_ws=None,
                              thr: float = 0.0, stream=None, n_pts=None):
     """Phis: B lists of 3 factor tensors (one grid shape) or raw addresses
-    (then n_pts gives the three lengths); outs: B outputs; mode_ws: B weight
-    tensors or addresses (entries may be None) or None."""
+    (then n_pts gives the three lengths), or a (B, 3) integer array of
+    addresses; outs: B outputs; mode_ws: B weight tensors or addresses
+    (entries may be None) or None; outs and mode_ws may be integer arrays of
+    addresses too."""
     B = len(Phis)
     n = (C.c_int32 * 3)(*(n_pts if n_pts is not None else [int(P.shape[0]) for P in Phis[0]]))
     mw = _ptr_array(mode_ws) if mode_ws is not None else None
-    h.check(lib().taps_reconstruct_batched(h.h, B, n, _ptr_array([P for F in Phis for P in F]), M, mw, prec, mode,
+    phis = Phis if isinstance(Phis, np.ndarray) else [P for F in Phis for P in F]
+    h.check(lib().taps_reconstruct_batched(h.h, B, n, _ptr_array(phis), M, mw, prec, mode,
                                            _ptr_array(outs), thr, _stream(stream)), "taps_reconstruct_batched")
 
 

@@ -631,14 +631,17 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     // flops K (2 bw n M + 2 n M^2)) and load Gram (F and U read, R M written;
     // 2 n R M flops); a load matrix shared by several problems (one grid's
     // time loads) is read once per launch
+    // (counted only while profiling: a loop over the problems per launch)
     double fl = 0.0, by = 0.0;
-    std::unordered_set<const double*> seen;
-    for (int b : active) {
-      const taps_problem_t& p = probs[b];
-      const double n = p.n[e], K = p.n_kinds[e], Rc = p.R_cols[e], bw = 4 * p.s[e] + 3;
-      const bool first = seen.insert(p.d_F[e]).second;
-      fl += K * (2.0 * bw * n * M + 2.0 * n * M * M) + 2.0 * n * Rc * M;
-      by += 8.0 * (n * M + K * MM + (first ? n * Rc : 0.0) + Rc * M);
+    if (slot != size_t(-1)) {
+      std::unordered_set<const double*> seen;
+      for (int b : active) {
+        const taps_problem_t& p = probs[b];
+        const double n = p.n[e], K = p.n_kinds[e], Rc = p.R_cols[e], bw = 4 * p.s[e] + 3;
+        const bool first = seen.insert(p.d_F[e]).second;
+        fl += K * (2.0 * bw * n * M + 2.0 * n * M * M) + 2.0 * n * Rc * M;
+        by += 8.0 * (n * M + K * MM + (first ? n * Rc : 0.0) + Rc * M);
+      }
     }
     return prof_end(h, slot, fl, by, st);
   };
@@ -675,13 +678,15 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       TAPS_LAUNCHED(h, "kb_force_sum");
     }
     double fl = 0.0, by = 0.0;
-    std::unordered_set<const double*> seen;
-    for (int b : active) {
-      const taps_problem_t& p = probs[b];
-      const double n = p.n[d], Rc = p.R_cols[d];
-      const bool first = seen.insert(p.d_F[d]).second;
-      fl += 2.0 * n * Rc * M;
-      by += 8.0 * ((first ? n * Rc : 0.0) + Rc * M + n * M);
+    if (slot != size_t(-1)) {
+      std::unordered_set<const double*> seen;
+      for (int b : active) {
+        const taps_problem_t& p = probs[b];
+        const double n = p.n[d], Rc = p.R_cols[d];
+        const bool first = seen.insert(p.d_F[d]).second;
+        fl += 2.0 * n * Rc * M;
+        by += 8.0 * ((first ? n * Rc : 0.0) + Rc * M + n * M);
+      }
     }
     return prof_end(h, slot, fl, by, st);
   };
@@ -707,10 +712,12 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       valid |= stale;
       TAPS_TRY(system(d, nact, st));
       double fl = 0.0, by = 0.0;
-      for (int b : active) {
-        const taps_problem_t& p = probs[b];
-        fl += use_fd[d] ? solve_fd_flops(p.n[d], M, p.s[d]) : solve_flops(p.n[d], M, 2 * p.s[d] + 1);
-        by += use_fd[d] ? solve_fd_bytes(p.n[d], M, p.s[d]) : solve_bytes(p.n[d], M, 2 * p.s[d] + 1, p.n_kinds[d]);
+      if (h->prof.on) {
+        for (int b : active) {
+          const taps_problem_t& p = probs[b];
+          fl += use_fd[d] ? solve_fd_flops(p.n[d], M, p.s[d]) : solve_flops(p.n[d], M, 2 * p.s[d] + 1);
+          by += use_fd[d] ? solve_fd_bytes(p.n[d], M, p.s[d]) : solve_bytes(p.n[d], M, 2 * p.s[d] + 1, p.n_kinds[d]);
+        }
       }
       const void* d_args = base + o_args + size_t(d) * B * args_sz;
       TAPS_TRY(use_fd[d] ? fd_batched_launch(h, nact, d_args, d_active, M, p0.s[d], fl, by, st)

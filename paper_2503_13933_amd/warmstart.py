@@ -50,6 +50,12 @@ class FactorBatch:
         """Address of row ``row`` of slab b's factor of dim d."""
         return self.base[d] + b * self.stride[d] + row * self.M * 8
 
+    def addrs(self, idx, d, row=0):
+        """Addresses of row ``row`` of the factors of dim d of the slabs idx
+        (a uint64 array)."""
+        b = np.asarray(idx, dtype=np.uint64)
+        return np.uint64(self.base[d] + row * self.M * 8) + b * np.uint64(self.stride[d])
+
     def ptrs(self, idx):
         """Factor pointers of the slabs idx, problem-major (driver order)."""
         import ctypes as C
