@@ -506,11 +506,16 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     return TAPS_OK;
   };
 
-  // ---- device records (host staging kept alive until the copies are synchronised)
-  std::vector<char> args(args_sz * size_t(D) * B);
-  std::vector<CoupleArgs> cpl(size_t(B) * D);
-  std::vector<WeightArgs> wa(size_t(B) * D);
-  std::vector<BalanceArgs> bal(B);
+  // ---- device records, written straight into the handle's pinned staging in
+  // the layout of [o_args, o_active + 4B) and sent in one copy
+  const size_t rec_bytes = o_active + size_t(B) * 4 - o_args;
+  TAPS_TRY(stage_reserve(h, rec_bytes));
+  char* const stg = static_cast<char*>(h->stage);
+  char* const args = stg;
+  CoupleArgs* const cpl = reinterpret_cast<CoupleArgs*>(stg + (o_cpl - o_args));
+  WeightArgs* const wa = reinterpret_cast<WeightArgs*>(stg + (o_wa - o_args));
+  BalanceArgs* const bal = reinterpret_cast<BalanceArgs*>(stg + (o_bal - o_args));
+  int* const act_h = reinterpret_cast<int*>(stg + (o_active - o_args));
   for (int b = 0; b < B; ++b) {
     const taps_problem_t& p = probs[b];
     BProb& q = bp[b];
@@ -539,8 +544,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     q.rparts = reinterpret_cast<double*>(base + o_rp[b]);
     q.outs = outs + size_t(b) * NO;
     for (int d = 0; d < D; ++d) {
+      // only the first T terms and D dims are read: the rest is left as it is
       CoupleArgs& ca = cpl[size_t(b) * D + d];
-      ca = CoupleArgs{};
       ca.D = D;
       ca.M = M;
       ca.T = p.T;
@@ -565,7 +570,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       w.ptr = p.d_load_ptr[d];
       w.idx = p.d_load_idx[d];
       w.P = ident[d] ? q.Wt : q.Wt + wt_doubles[b];
-      solve_args_fill(args.data() + (size_t(d) * B + b) * args_sz, &p, d, q.C, q.Q, q.U[d],
+      solve_args_fill(args + (size_t(d) * B + b) * args_sz, &p, d, q.C, q.Q, q.U[d],
                       infos + size_t(b) * D + d, base + o_ws[b], use_fd[d]);
     }
     bal[b] = BalanceArgs{};
@@ -588,18 +593,14 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   std::vector<int> active(B), next;
   for (int b = 0; b < B; ++b) {
     active[b] = b;
+    act_h[b] = b;
     sweeps[b] = 0;
     rho[b] = NAN;
     if (change) change[b] = NAN;
   }
-  TAPS_HIP(h, hipMemcpyAsync(base + o_args, args.data(), args.size(), hipMemcpyHostToDevice, stream));
-  TAPS_HIP(h, hipMemcpyAsync(base + o_prob, bp.data(), sizeof(BProb) * B, hipMemcpyHostToDevice, stream));
-  TAPS_HIP(h, hipMemcpyAsync(base + o_cpl, cpl.data(), sizeof(CoupleArgs) * cpl.size(), hipMemcpyHostToDevice,
-                             stream));
-  TAPS_HIP(h, hipMemcpyAsync(base + o_wa, wa.data(), sizeof(WeightArgs) * wa.size(), hipMemcpyHostToDevice,
-                             stream));
-  TAPS_HIP(h, hipMemcpyAsync(base + o_bal, bal.data(), sizeof(BalanceArgs) * B, hipMemcpyHostToDevice, stream));
-  TAPS_HIP(h, hipMemcpyAsync(d_active, active.data(), size_t(B) * 4, hipMemcpyHostToDevice, stream));
+  std::memcpy(stg + (o_prob - o_args), bp.data(), sizeof(BProb) * B);
+  TAPS_HIP(h, hipMemcpyAsync(base + o_args, stg, rec_bytes, hipMemcpyHostToDevice, stream));
+  TAPS_HIP(h, hipEventRecord(h->stage_ev, stream));
   TAPS_TRY(upload_items(active, stream));
   TAPS_HIP(h, hipStreamSynchronize(stream));
 

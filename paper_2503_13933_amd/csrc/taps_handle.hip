@@ -197,6 +197,8 @@ taps_status taps_destroy(taps_handle_t h) {
   for (auto e : h->prof.ev) (void)hipEventDestroy(e);
   if (h->side) (void)hipFree(h->side);
   if (h->batch) (void)hipFree(h->batch);
+  if (h->stage) (void)hipHostFree(h->stage);
+  if (h->stage_ev) (void)hipEventDestroy(h->stage_ev);
   if (h->d_small) (void)hipFree(h->d_small);
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->gstream) (void)hipStreamDestroy(h->gstream);

@@ -41,6 +41,11 @@ struct taps_handle {
   // batched driver region (per-problem caches, couplings, solve workspaces)
   void* batch = nullptr;
   size_t batch_bytes = 0;
+  // pinned host staging of the batched driver's per-call records, sent in one
+  // copy; stage_ev is recorded after that copy and waited on before reuse
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_ev = nullptr;
   std::string err;
   int device = 0;
   // tuning of the batched driver (taps_set_tuning / taps_autotune) and the
@@ -105,6 +110,25 @@ inline taps_status allow_lds(taps_handle* h, K kernel, size_t bytes, size_t* hav
   TAPS_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
   *have = bytes;
+  return TAPS_OK;
+}
+
+// Pinned host staging of at least `need` bytes, free to overwrite: the last
+// copy out of it has ended.
+inline taps_status stage_reserve(taps_handle* h, size_t need) {
+  if (!h->stage_ev) TAPS_HIP(h, hipEventCreateWithFlags(&h->stage_ev, hipEventDisableTiming));
+  else TAPS_HIP(h, hipEventSynchronize(h->stage_ev));
+  if (need <= h->stage_bytes) return TAPS_OK;
+  if (h->stage) TAPS_HIP(h, hipHostFree(h->stage));
+  h->stage = nullptr;
+  h->stage_bytes = 0;
+  const size_t bytes = align256(need + need / 4);
+  if (hipHostMalloc(&h->stage, bytes, hipHostMallocDefault) != hipSuccess) {
+    h->stage = nullptr;
+    (void)hipGetLastError();
+    return fail(h, TAPS_ERR_ALLOC, "hipHostMalloc of %zu bytes failed", bytes);
+  }
+  h->stage_bytes = bytes;
   return TAPS_OK;
 }
 
