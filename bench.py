@@ -210,6 +210,7 @@ def main():
     t0 = time.perf_counter()
     cases = family(N, args.seed, **grid)
     probs = [chain.slab_problem(h, c) for c in cases]
+    packed = ws.pack_problems(probs)     # the records of all slabs (probs keeps their buffers)
     # random starts of all slabs, one (N, n_d, M) tensor per dim (a slab's factors are slices)
     U0_host = [W.initial_factors(c.axes, M, c.seed) for c in cases]
     U_plain_big = [torch.tensor(np.stack([u[d] for u in U0_host]), dtype=torch.float64, device="cuda")
@@ -297,12 +298,12 @@ def main():
     def step_warm():
         Y = net.forward(X_bench)
         U = layout.initial_batch(Y, fixed)
-        return ws.solve_stream(h, probs, U, rho_star, cap, B, U_plain=U_plain, median_rho1=med1,
+        return ws.solve_stream(h, packed, U, rho_star, cap, B, U_plain=U_plain, median_rho1=med1,
                                on_done_batch=lambda done: reconstruct(U, done), first_sweep_all=hardest)
 
     def step_random_batched():
         U = U_plain.clone()
-        return ws.solve_stream(h, probs, U, rho_star, cap, B, on_done_batch=lambda done: reconstruct(U, done),
+        return ws.solve_stream(h, packed, U, rho_star, cap, B, on_done_batch=lambda done: reconstruct(U, done),
                                first_sweep_all=hardest)
 
     def timed(fn, label):

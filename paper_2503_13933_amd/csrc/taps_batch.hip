@@ -135,10 +135,11 @@ __global__ void kb_lgram_sum(const BProb* __restrict__ P, const int* __restrict_
   sum_parts_n<kVB>(blockIdx.x * kVB, splits, long(q.Rc[e]) * q.M, q.lpart, q.lgram[e]);
 }
 
+// one coupling record per problem (its term table), for every dim
 __global__ void kb_couple(const BProb* __restrict__ P, const CoupleArgs* __restrict__ CA,
-                          const int* __restrict__ act, int d, int D) {
+                          const int* __restrict__ act, int d) {
   const int b = act[blockIdx.y];
-  couple_n<kVB>(blockIdx.x * kVB, CA[long(b) * D + d], P[b].C);
+  couple_n<kVB>(blockIdx.x * kVB, CA[b], d, P[b].K[d], P[b].C);
 }
 
 __global__ void kb_load_terms(const WeightArgs* __restrict__ WA, const int* __restrict__ act, int d, int D) {
@@ -392,7 +393,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   Bump bump;
   const size_t o_args = bump.take(args_sz * size_t(D) * B);
   const size_t o_prob = bump.take(sizeof(BProb) * size_t(B));
-  const size_t o_cpl = bump.take(sizeof(CoupleArgs) * size_t(B) * D);
+  const size_t o_cpl = bump.take(sizeof(CoupleArgs) * size_t(B));
   const size_t o_wa = bump.take(sizeof(WeightArgs) * size_t(B) * D);
   const size_t o_bal = bump.take(sizeof(BalanceArgs) * size_t(B));
   const size_t o_active = bump.take(size_t(B) * 4);
@@ -489,17 +490,19 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto owner = [&](int kind, int d) { return d_owner + own_off.off[kind * D + d]; };
   // persistent grid of one kernel: its items over the whole batch, capped
   auto pgrid = [&](int kind, int d, int cap) { return unsigned(std::max(1L, std::min(long(cap), it_full[kind * D + d]))); };
-  // prefix tables of the active problems' item counts (host staging kept
-  // alive until the upload is synchronised)
-  std::vector<int> h_pref(size_t(kItKinds) * D * (B + 1));
+  // prefix tables of the active problems' item counts, staged in the
+  // handle's pinned staging behind the records (set below)
+  const size_t pref_len = size_t(kItKinds) * D * (B + 1);
+  int* h_pref = nullptr;
   auto upload_items = [&](const std::vector<int>& act_list, hipStream_t st) -> taps_status {
     for (int k = 0; k < kItKinds; ++k)
       for (int d = 0; d < D; ++d) {
-        int* pr = h_pref.data() + size_t(k * D + d) * (B + 1);
+        int* pr = h_pref + size_t(k * D + d) * (B + 1);
         pr[0] = 0;
         for (size_t a = 0; a < act_list.size(); ++a) pr[a + 1] = pr[a] + items_of(k, act_list[a], d);
       }
-    TAPS_HIP(h, hipMemcpyAsync(base + o_pref, h_pref.data(), h_pref.size() * 4, hipMemcpyHostToDevice, st));
+    TAPS_HIP(h, hipMemcpyAsync(base + o_pref, h_pref, pref_len * 4, hipMemcpyHostToDevice, st));
+    TAPS_HIP(h, hipEventRecord(h->stage_ev, st));
     const int na = int(act_list.size());
     kb_owner_fill<<<dim3(cdiv(na, 256), kItKinds * D), 256, 0, st>>>(d_pref, d_owner, own_off, na, B);
     TAPS_LAUNCHED(h, "kb_owner_fill");
@@ -507,10 +510,15 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   };
 
   // ---- device records, written straight into the handle's pinned staging in
-  // the layout of [o_args, o_active + 4B) and sent in one copy
+  // the layout of [o_args, o_active + 4B) and sent in one copy; the prefix
+  // tables follow them.  Every copy out of the staging is stream-ordered
+  // before the launches that read it, and the staging is rewritten only
+  // after the stream has drained (the readback of each sweep) or, in the
+  // next call, after the event recorded behind the last copy.
   const size_t rec_bytes = o_active + size_t(B) * 4 - o_args;
-  TAPS_TRY(stage_reserve(h, rec_bytes));
+  TAPS_TRY(stage_reserve(h, align256(rec_bytes) + pref_len * 4));
   char* const stg = static_cast<char*>(h->stage);
+  h_pref = reinterpret_cast<int*>(stg + align256(rec_bytes));
   char* const args = stg;
   CoupleArgs* const cpl = reinterpret_cast<CoupleArgs*>(stg + (o_cpl - o_args));
   WeightArgs* const wa = reinterpret_cast<WeightArgs*>(stg + (o_wa - o_args));
@@ -543,19 +551,19 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
     q.wpart = reinterpret_cast<double*>(base + o_wp[b]);
     q.rparts = reinterpret_cast<double*>(base + o_rp[b]);
     q.outs = outs + size_t(b) * NO;
+    // only the first T terms and D dims are read: the rest is left as it is
+    CoupleArgs& ca = cpl[b];
+    ca.D = D;
+    ca.M = M;
+    ca.T = p.T;
+    ca.d = 0;
+    ca.Kd = 0;
+    for (int t = 0; t < p.T; ++t) {
+      ca.gamma[t] = p.gamma[t];
+      for (int e = 0; e < D; ++e) ca.tk[t][e] = p.term_kind[t][e];
+    }
+    for (int e = 0; e < D; ++e) ca.gram[e] = q.gram[e];
     for (int d = 0; d < D; ++d) {
-      // only the first T terms and D dims are read: the rest is left as it is
-      CoupleArgs& ca = cpl[size_t(b) * D + d];
-      ca.D = D;
-      ca.M = M;
-      ca.T = p.T;
-      ca.d = d;
-      ca.Kd = p.n_kinds[d];
-      for (int t = 0; t < p.T; ++t) {
-        ca.gamma[t] = p.gamma[t];
-        for (int e = 0; e < D; ++e) ca.tk[t][e] = p.term_kind[t][e];
-      }
-      for (int e = 0; e < D; ++e) ca.gram[e] = q.gram[e];
       WeightArgs& w = wa[size_t(b) * D + d];
       w = WeightArgs{};
       w.D = D;
@@ -602,7 +610,8 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   TAPS_HIP(h, hipMemcpyAsync(base + o_args, stg, rec_bytes, hipMemcpyHostToDevice, stream));
   TAPS_HIP(h, hipEventRecord(h->stage_ev, stream));
   TAPS_TRY(upload_items(active, stream));
-  TAPS_HIP(h, hipStreamSynchronize(stream));
+  // captured sweeps run on the handle's own stream: the uploads must have landed
+  if (!h->prof.on && h->tune.graph_sweeps > 0) TAPS_HIP(h, hipStreamSynchronize(stream));
 
   const size_t glds = size_t(gram_lds_doubles(M, *std::max_element(p0.s, p0.s + D))) * 8;
   const size_t rlds = size_t(residual_lds_doubles(M, *std::max_element(p0.s, p0.s + D))) * 8;
@@ -649,7 +658,7 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
   auto system = [&](int d, int nact, hipStream_t st) -> taps_status {
     size_t slot;
     TAPS_TRY(prof_begin(h, TAPS_PROF_CONTRACT, st, &slot));
-    kb_couple<<<dim3(cdiv(Z.cpl[d], kVB), nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d, D);
+    kb_couple<<<dim3(cdiv(Z.cpl[d], kVB), nact), 256, 0, st>>>(d_prob, d_cpl, d_active, d);
     TAPS_LAUNCHED(h, "kb_couple");
     if (long_groups[d] && !ident[d]) {
       // products formed in place, group slices summed afterwards
@@ -822,9 +831,9 @@ extern "C" taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_p
       if (!broke && rho[b] > tol && !(change_tol > 0.0 && chg <= change_tol)) next.push_back(b);
     }
     if (next.size() != active.size() && !next.empty()) {
-      TAPS_HIP(h, hipMemcpyAsync(d_active, next.data(), next.size() * 4, hipMemcpyHostToDevice, run));
+      std::memcpy(act_h, next.data(), next.size() * 4);
+      TAPS_HIP(h, hipMemcpyAsync(d_active, act_h, next.size() * 4, hipMemcpyHostToDevice, run));
       TAPS_TRY(upload_items(next, run));
-      TAPS_HIP(h, hipStreamSynchronize(run));
     }
     active.swap(next);
   }

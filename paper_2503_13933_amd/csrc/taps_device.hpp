@@ -243,7 +243,7 @@ __device__ inline void lgram_partial(int ctile, int split, int rows, int n, int 
 }
 
 struct CoupleArgs {
-  int D, M, T, d, Kd;
+  int D, M, T, d, Kd;   // d and Kd: the dim and its kind count (single-problem launches)
   int tk[TAPS_MAX_TERMS][TAPS_MAX_DIMS];
   double gamma[TAPS_MAX_TERMS];
   const double* gram[TAPS_MAX_DIMS];  // dim e's Grams (n_kinds[e] x M x M)
@@ -255,8 +255,8 @@ struct CoupleArgs {
 // all their loads (one store per slice would otherwise order the next
 // slice's loads behind it).
 template <int NS>
-__device__ inline void couple_n(int s0, const CoupleArgs& A, double* __restrict__ C) {
-  const int MM = A.M * A.M, len = A.Kd * MM;
+__device__ inline void couple_n(int s0, const CoupleArgs& A, int d, int Kd, double* __restrict__ C) {
+  const int MM = A.M * A.M, len = Kd * MM;
   if (s0 * int(blockDim.x) >= len) return;
   int t[NS], k[NS], mn[NS];
   double acc[NS];
@@ -269,12 +269,12 @@ __device__ inline void couple_n(int s0, const CoupleArgs& A, double* __restrict_
     acc[u] = 0.0;
   }
   for (int tau = 0; tau < A.T; ++tau) {
-    const int kt = A.tk[tau][A.d];
+    const int kt = A.tk[tau][d];
     double prod[NS];
 #pragma unroll
     for (int u = 0; u < NS; ++u) prod[u] = A.gamma[tau];
     for (int e = 0; e < A.D; ++e) {
-      if (e == A.d) continue;
+      if (e == d) continue;
       const auto g = gp(A.gram[e]) + long(A.tk[tau][e]) * MM;
 #pragma unroll
       for (int u = 0; u < NS; ++u) prod[u] *= g[mn[u]];
@@ -287,7 +287,9 @@ __device__ inline void couple_n(int s0, const CoupleArgs& A, double* __restrict_
   for (int u = 0; u < NS; ++u)
     if (t[u] < len) gp(C)[t[u]] = acc[u];
 }
-__device__ inline void couple(int tblock, const CoupleArgs& A, double* __restrict__ C) { couple_n<1>(tblock, A, C); }
+__device__ inline void couple(int tblock, const CoupleArgs& A, double* __restrict__ C) {
+  couple_n<1>(tblock, A, A.d, A.Kd, C);
+}
 
 struct WeightArgs {
   int D, M, R, d, Rc;

@@ -278,6 +278,12 @@ def restart_plain(rho1, rho2, plain_median_rho1):
 # ------------------------------------------------------------- streaming
 
 
+def pack_problems(probs):
+    """The problem records of probs (objects with .struct) as one ctypes
+    array, in order."""
+    return (capi.Problem * len(probs))(*[p.struct for p in probs])
+
+
 def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, on_done=None, on_done_batch=None,
                  first_sweep_all=False):
     """Continuous batching of Algorithm 1: up to ``slots`` slabs in flight,
@@ -303,21 +309,28 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     on_done(i) is called for every slab as it leaves; on_done_batch(list)
     once per round with all slabs that left in it.
     U (and U_plain) may be FactorBatch objects (addresses computed per
-    round) or lists of per-slab factor lists.
+    round) or lists of per-slab factor lists.  probs is a list of problem
+    objects (with .struct) or their records packed once by pack_problems
+    (the objects must then outlive the call: the records point into their
+    device buffers).
     Returns (sweeps run per slab, final residual per slab, number of
     restarts, outcome per slab: 0 reached tol, 1 stopped at the cap,
     2 broke down)."""
     import ctypes as C
     from collections import deque
     n = len(probs)
-    allp = (capi.Problem * n)(*[p.struct for p in probs])
+    allp = probs if isinstance(probs, C.Array) else pack_problems(probs)
     psize = C.sizeof(capi.Problem)
-    allp_bytes = np.frombuffer(allp, dtype=np.uint8).reshape(n, psize)   # a view; allp outlives the rounds
+    # a view of the records as rows of 8-byte words (the struct holds
+    # pointers and doubles, so its size is a multiple of 8); allp outlives
+    # the rounds
+    allp_words = np.frombuffer(allp, dtype=np.uint64).reshape(n, psize // 8)
 
     def prob_array(idx):
         if len(idx) == n and idx == list(range(n)):
             return allp
-        return (capi.Problem * len(idx)).from_buffer_copy(allp_bytes[np.asarray(idx)].tobytes())
+        # one gather; the ctypes array keeps the gathered rows alive
+        return (capi.Problem * len(idx)).from_buffer(allp_words[np.asarray(idx, dtype=np.intp)])
 
     waiting = deque(range(n))
     active = []

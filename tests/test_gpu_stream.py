@@ -61,6 +61,16 @@ def test_schedules_give_identical_slab_results(env):
         torch.cuda.synchronize()
         res[first] = (total, rho, restarts, outcome, [t.clone() for t in U.dims])
         _say(f"first_sweep_all={first}: sweeps {sorted(total)}, restarts {restarts}, outcomes {sorted(outcome)}")
+    # the records packed once (as the benchmark passes them) give the same run
+    U = ws.FactorBatch([t.clone() for t in warm])
+    Up = ws.FactorBatch([t.clone() for t in plain])
+    packed = ws.pack_problems(probs)
+    c = ws.solve_stream(h, packed, U, tol, cap, slots, U_plain=Up, median_rho1=med1, first_sweep_all=True)
+    torch.cuda.synchronize()
+    assert c[0] == res[True][0] and c[3] == res[True][3]
+    assert np.array_equal(np.asarray(c[1]), np.asarray(res[True][1]), equal_nan=True)
+    for ta, tb in zip(U.dims, res[True][4]):
+        assert torch.equal(ta, tb)
     a, b = res[False], res[True]
     assert a[0] == b[0] and a[2] == b[2] and a[3] == b[3]
     assert np.array_equal(np.asarray(a[1]), np.asarray(b[1]), equal_nan=True)
