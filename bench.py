@@ -14,7 +14,7 @@ paper names -- balancing with the relative change, projected residual) with
 continuous batching: --batch slabs in flight, one workgroup each per kernel;
 a slab leaves when its residual reaches the target, at the sweep cap, or on a
 breakdown, and the next takes its slot, so with more slabs than slots (by
-default 4096 through 1024) only the last rounds of a step run part-empty.
+default 4096 through 2048) only the last rounds of a step run part-empty.
 The fallback rule runs after sweeps 1 and 2, and a BF16 reconstruction of
 the end-time field of every slab that leaves (per-plane max, sum of squares
 and hot-point count), one batched call per round, is part of the step.
@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=3, help="plain sweep budget that sets the target residual")
     ap.add_argument("--target-sweeps", type=int, default=3,
                     help="plain sweeps behind the warm-start network's training targets (at least --sweeps)")
-    ap.add_argument("--batch", type=int, default=1024, help="slabs in flight, one workgroup each")
+    ap.add_argument("--batch", type=int, default=2048, help="slabs in flight, one workgroup each")
     ap.add_argument("--stream-order", choices=["hardest-first", "input"], default="hardest-first",
                     help="continuous batching: first sweep of every slab, then the unsolved ones by decreasing "
                          "residual (hardest-first), or slabs strictly in input order")
