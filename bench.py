@@ -67,8 +67,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # scaled by the same counter on a plain device copy of known size), valid
 # for the kernel sources with these SHA-256 prefixes only (None: not measured
 # for the current sources).
-TRAFFIC = {"k_fd_solve": 10.230, "k_fd_schur": 1.024, "contract": 2.916, "contract_spt": 1.822,
-           "sources": "b651506a15270975"}
+TRAFFIC = {"k_fd_solve": 10.228, "k_fd_schur": 1.019, "contract": 2.976, "contract_spt": 1.821,
+           "sources": "13d91a1be39c9708"}
 TRAFFIC_SOURCES = ("taps_solve.hip", "taps_device.hpp", "taps_batch.hip")
 
 
