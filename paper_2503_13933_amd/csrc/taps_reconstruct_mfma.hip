@@ -268,21 +268,61 @@ __global__ __launch_bounds__(kWaves * 64) void k_recon_bf16(int n0, int n1, int 
   const bool rows_full = ibase + 16 * RT <= n0;
   // ALL: every tile of this wave lies inside the plane (its rows, and a
   // multiple of 16 columns), so no tile needs the per-tile test
+  bool hot = false;   // wave-uniform: the wave's previous tile held a value above thr
   auto tile = [&](int jt, const bf16x8* b, auto all) {
     const bool jfull = 16 * jt + 16 <= n1;
     const bool full = decltype(all)::value || (rows_full && jfull);
     float ss = 0.0f;
+    if (MODE == TAPS_REDUCE && full && !hot) {
+      // after a cold tile: the whole tile's products first, then the fold:
+      // the squares in the same order as the per-row-tile epilogue, the
+      // maximum, and the count only when some value of the tile exceeds thr
+      // (most of a field lies below it; otherwise every compare would be
+      // false), so a cold tile needs no compares and no ballots (a
+      // wave-uniform branch).  After a hot tile the per-row-tile epilogue,
+      // which overlaps the compares with the next row tile's products, folds
+      // the next one (the same values either way)
+      f32x4 acc[RT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int rt = 0; rt < RT; ++rt) {
+        acc[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks], __builtin_bit_cast(bf16x8, a[rt][ks]), acc, 0, 0, 0);
-      const int i = ibase + 16 * rt + c16;
-      if (full)
-        epilogue<MODE, true>(acc, i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
-      else
-        epilogue<MODE, false>(acc, i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
+        for (int ks = 0; ks < KS; ++ks)
+          acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks], __builtin_bit_cast(bf16x8, a[rt][ks]), acc[rt],
+                                                            0, 0, 0);
+      }
+      float t = -INFINITY;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        ss = fmaf(acc[rt].x, acc[rt].x, ss);
+        ss = fmaf(acc[rt].y, acc[rt].y, ss);
+        ss = fmaf(acc[rt].z, acc[rt].z, ss);
+        ss = fmaf(acc[rt].w, acc[rt].w, ss);
+        t = fmaxf(fmaxf(fmaxf(fmaxf(t, acc[rt].x), acc[rt].y), acc[rt].z), acc[rt].w);
+      }
+      red.mx = fmaxf(red.mx, t);
+      hot = __ballot(t > thrf) != 0;
+      if (hot) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          red.cnt += __builtin_popcountll(__ballot(acc[rt].x > thrf)) + __builtin_popcountll(__ballot(acc[rt].y > thrf)) +
+                     __builtin_popcountll(__ballot(acc[rt].z > thrf)) + __builtin_popcountll(__ballot(acc[rt].w > thrf));
+      }
+    } else {
+      const unsigned int cnt0 = red.cnt;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks], __builtin_bit_cast(bf16x8, a[rt][ks]), acc, 0, 0, 0);
+        const int i = ibase + 16 * rt + c16;
+        if (full)
+          epilogue<MODE, true>(acc, i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
+        else
+          epilogue<MODE, false>(acc, i, 16 * jt + 4 * g, n0, n1, jfull, thrf, red, ss, ro);
+      }
+      hot = red.cnt != cnt0;
     }
     if (MODE == TAPS_REDUCE) red.ss += double(ss);
   };
