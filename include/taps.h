@@ -33,8 +33,10 @@
  *     anything is enqueued: a bad argument returns TAPS_ERR_INVALID or
  *     TAPS_ERR_UNSUPPORTED and enqueues nothing; taps_last_error() tells why.
  *   - A handle owns a device workspace that grows on demand (hipMalloc after a
- *     stream synchronisation).  Call taps_reserve() up front to keep later calls
- *     allocation-free.  A handle is not thread-safe; use one per host thread.
+ *     stream synchronisation), and taps_als_batched a pinned host staging area
+ *     (hipHostMalloc).  Call taps_reserve() up front to keep later
+ *     single-problem calls allocation-free.  A handle is not thread-safe; use
+ *     one per host thread.
  *   - Numerical breakdown (zero or NaN pivot) never aborts: it is reported in a
  *     device info word (LAPACK style) and the outputs are then unspecified.
  *   - Everything is FP64 except the precision argument of taps_reconstruct.
@@ -312,7 +314,12 @@ taps_status taps_als(taps_handle_t h, const taps_problem_t* prob, double* const*
  * sweeps[b], rho[b] and change[b] (nullable) after the last sweep run, NaN
  * after a breakdown.  The change is measured (one copy of the factors per
  * sweep) only when change is non-null or change_tol > 0.  Synchronises the
- * stream once per sweep (or replay).
+ * stream once per sweep (or replay).  The per-call device records (problem
+ * layout, coupling term tables, solve arguments, the active list and its
+ * work-item prefix tables) are written into pinned host staging that the
+ * handle keeps (hipHostMalloc, grown on demand) and sent in stream-ordered
+ * copies; an event recorded behind the last copy guards the staging's reuse
+ * by the next call.  probs is read during the call only.
  * TAPS_ERR_UNSUPPORTED when a block-LU dim does not fit LDS (M, s). */
 taps_status taps_als_batched(taps_handle_t h, int32_t B, const taps_problem_t* probs,
                              double* const* d_U, double tol, double change_tol, int32_t iter_max,
