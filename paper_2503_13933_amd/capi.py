@@ -410,12 +410,13 @@ def last_error(h: Handle) -> str:
 
 
 def taps_als_batched(h: Handle, probs, Us, tol: float, iter_max: int, change_tol: float = 0.0, stream=None,
-                     change=None):
+                     change=None, arrays: bool = False):
     """Algorithm 1 over a batch.  probs: list of Problem; Us: list (per problem)
     of factor tensor lists, or a ctypes array of factor pointers.  Returns
-    (sweeps list, rho list); change, a list, receives every problem's
-    relative change of the factors over its last sweep (measured only when
-    change is given or change_tol > 0)."""
+    (sweeps list, rho list), or with arrays=True (sweeps, rho) as numpy
+    arrays over the call's own output buffers; change, a list, receives
+    every problem's relative change of the factors over its last sweep
+    (measured only when change is given or change_tol > 0)."""
     B = len(probs)
     arr = probs if isinstance(probs, C.Array) else (Problem * B)(*probs)
     ptrs = Us if isinstance(Us, C.Array) else _ptr_array([u for U in Us for u in U])
@@ -426,4 +427,6 @@ def taps_als_batched(h: Handle, probs, Us, tol: float, iter_max: int, change_tol
             "taps_als_batched")
     if change is not None:
         change.extend(ch)
+    if arrays:
+        return np.frombuffer(sw, dtype=np.int32), np.frombuffer(rh, dtype=np.float64)
     return list(sw), list(rh)

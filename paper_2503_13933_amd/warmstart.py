@@ -317,7 +317,6 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     restarts, outcome per slab: 0 reached tol, 1 stopped at the cap,
     2 broke down)."""
     import ctypes as C
-    from collections import deque
     n = len(probs)
     allp = probs if isinstance(probs, C.Array) else pack_problems(probs)
     psize = C.sizeof(capi.Problem)
@@ -327,13 +326,15 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     allp_words = np.frombuffer(allp, dtype=np.uint64).reshape(n, psize // 8)
 
     def prob_array(idx):
-        if len(idx) == n and idx == list(range(n)):
+        if len(idx) == n and np.array_equal(idx, np.arange(n)):
             return allp
         # one gather; the ctypes array keeps the gathered rows alive
-        return (capi.Problem * len(idx)).from_buffer(allp_words[np.asarray(idx, dtype=np.intp)])
+        return (capi.Problem * len(idx)).from_buffer(allp_words[idx])
 
-    waiting = deque(range(n))
-    active = []
+    # the waiting slabs in order (wait[w0:] still waits) and the slabs in
+    # flight, as integer arrays
+    wait, w0 = np.arange(n, dtype=np.intp), 0
+    active = np.zeros(0, dtype=np.intp)
     # per-slab state as arrays: a round's bookkeeping is a few vector
     # operations, not a Python loop over the slabs in flight (the GPU waits
     # for it between rounds)
@@ -344,11 +345,9 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
     outcome = np.ones(n, dtype=np.int64)
     restarted = np.zeros(n, dtype=bool)
 
-    def one_round(active):
-        Ua = U.ptrs(active) if isinstance(U, FactorBatch) else [U[i] for i in active]
-        _, r = capi.taps_als_batched(h, prob_array(active), Ua, 0.0, 1)
-        act = np.asarray(active, dtype=np.int64)
-        r = np.asarray(r, dtype=np.float64)
+    def one_round(act):
+        Ua = U.ptrs(act) if isinstance(U, FactorBatch) else [U[i] for i in act.tolist()]
+        _, r = capi.taps_als_batched(h, prob_array(act), Ua, 0.0, 1, arrays=True)
         count[act] += 1
         total[act] += 1
         rho[act] = r
@@ -376,18 +375,22 @@ def solve_stream(h, probs, U, tol, cap, slots, U_plain=None, median_rho1=None, o
                 on_done(i)
         if done and on_done_batch is not None:
             on_done_batch(done)
-        return act[~fin].tolist()
+        return act[~fin]
 
     if first_sweep_all:
         rest = []
-        while waiting:
-            rest += one_round([waiting.popleft() for _ in range(min(slots, len(waiting)))])
+        while w0 < n:
+            k = min(slots, n - w0)
+            rest.append(one_round(wait[w0:w0 + k]))
+            w0 += k
         # hardest first: restarted slabs (count 0), then by decreasing residual
         # (a stable sort, as the slabs' input order breaks ties)
-        ra = np.asarray(rest, dtype=np.int64)
-        waiting = deque(ra[np.lexsort((-rho[ra], count[ra] != 0))].tolist())
-    while waiting or active:
-        while len(active) < slots and waiting:
-            active.append(waiting.popleft())
+        ra = np.concatenate(rest)
+        wait, w0 = ra[np.lexsort((-rho[ra], count[ra] != 0))], 0
+    while w0 < len(wait) or len(active):
+        k = min(slots - len(active), len(wait) - w0)
+        if k > 0:
+            active = np.concatenate([active, wait[w0:w0 + k]])
+            w0 += k
         active = one_round(active)
     return total.tolist(), rho.tolist(), int(restarted.sum()), outcome.tolist()

@@ -56,7 +56,7 @@ def _script_call(monkeypatch, script, fb, seen):
     """The batched call as a script: slab i's residual after its j-th sweep
     of the run is script[i][j].  Checks that every round hands over the
     active slabs' own records and factor pointers, in the same order."""
-    def fake(h, probs, Us, tol, iter_max, change_tol=0.0, stream=None, change=None):
+    def fake(h, probs, Us, tol, iter_max, change_tol=0.0, stream=None, change=None, arrays=False):
         assert iter_max == 1
         idx = [probs[k].R for k in range(len(probs))]
         assert len(set(idx)) == len(idx)
@@ -66,6 +66,8 @@ def _script_call(monkeypatch, script, fb, seen):
         for i in idx:
             r.append(script[i][seen[i]])
             seen[i] += 1
+        if arrays:
+            return np.ones(len(idx), dtype=np.int32), np.asarray(r, dtype=np.float64)
         return [1] * len(idx), r
     monkeypatch.setattr(capi, "taps_als_batched", fake)
 
